@@ -1,0 +1,128 @@
+"""Pressure-velocity block preconditioners (oracle), Sec. 4 of the paper.
+
+P_BJ(P_V, P_D')  = diag(P_V, X, P_D')
+P_BGS(P_V, P_D') = [[P_V, 0, 0], [-X C P_V, X, 0], [-P_D' C1' P_V, 0, P_D']]
+
+applied to a residual r = (r_v, r_p, r_pm):
+  block-Jacobi:       y_v = P_V r_v,  y_p = X r_p,              y_pm = P_D' r_pm
+  block-Gauss-Seidel: y_v = P_V r_v,  y_p = X (r_p - C y_v),    y_pm = P_D' (r_pm - C1' y_v)
+
+P_V and P_D' are one AMG V-cycle each.  P_D' is built on the Darcy block as
+the coupled system sees it, D~ = D' - C1' diag(V)^-1 B1': with no-flow outer
+porous boundaries D' alone is singular (pure Neumann), while the coupled
+matrix fixes the porous pressure through the interface; the correction adds
+dx^2 / V_gg to the diagonal of each porous top cell (one interface face per
+cell), evaluated as D[t,t] - (c1 * b1) / V[g,g].  X replaces the inverse of the zero
+diagonal block: the paper's identity, or the inverse of a viscosity-scaled
+pressure mass matrix, X = mu M_p^-1 with M_p = diag(dx dy) (the Schur
+complement B^T V^-1 B is approximated by M_p / mu; with C = -B^T its sign is
+positive).
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+import scipy.sparse as sp
+
+from . import amg as amg_mod
+from .assemble import Assembled
+
+SCHUR_IDENTITY = "identity"
+SCHUR_MASS = "mass"
+
+
+@dataclasses.dataclass
+class BlockPreconditioner:
+    variant: str               # "BJ" or "BGS"
+    schur: str
+    hV: amg_mod.Hierarchy
+    hD: amg_mod.Hierarchy
+    C: object                  # continuity rows x velocity columns
+    C1: object                 # porous rows x velocity columns
+    off: np.ndarray            # [0, off_v, off_p, off_q, N]
+    xscale: float              # X = xscale * I
+    dtype: type = np.float64
+
+    def __post_init__(self):
+        dt = self.dtype
+        self._C = self.C.astype(dt)
+        self._C1 = self.C1.astype(dt)
+        self._mV = amg_mod.level_mats(self.hV, dt)
+        self._mD = amg_mod.level_mats(self.hD, dt)
+
+    def __call__(self, r: np.ndarray) -> np.ndarray:
+        dt = self.dtype
+        o = self.off
+        r = r.astype(dt)
+        rv, rp, rq = r[o[0]:o[2]], r[o[2]:o[3]], r[o[3]:o[4]]
+        yv = amg_mod.vcycle(self.hV, rv, dt, mats=self._mV)
+        s = dt(self.xscale)
+        if self.variant == "BJ":
+            yp = s * rp
+            yq = amg_mod.vcycle(self.hD, rq, dt, mats=self._mD)
+        elif self.variant == "BGS":
+            yp = s * (rp - self._C @ yv)
+            yq = amg_mod.vcycle(self.hD, rq - self._C1 @ yv, dt, mats=self._mD)
+        else:
+            raise ValueError(self.variant)
+        return np.concatenate([yv, yp, yq])
+
+
+def velocity_components(a: Assembled) -> np.ndarray:
+    o = a.layout.block_off
+    comp = np.zeros(int(o[2]), dtype=np.int32)
+    comp[o[1]:o[2]] = 1
+    return comp
+
+
+def darcy_interface_block(blk) -> "sp.csr_matrix":
+    """D~ = D' - C1' diag(V)^-1 B1' (diagonal correction on porous top cells)."""
+    D = blk["D"].tocsr().copy()
+    D.sort_indices()
+    C1 = blk["C1"].tocsr()
+    B1 = blk["B1"].tocsr()
+    Vd = blk["V"].diagonal()
+    for t in range(D.shape[0]):
+        for kk in range(C1.indptr[t], C1.indptr[t + 1]):
+            g = C1.indices[kk]
+            c1 = C1.data[kk]
+            for ll in range(B1.indptr[g], B1.indptr[g + 1]):
+                tp = B1.indices[ll]
+                b1 = B1.data[ll]
+                pos = D.indptr[t] + np.searchsorted(D.indices[D.indptr[t]:D.indptr[t + 1]], tp)
+                D.data[pos] = D.data[pos] - (c1 * b1) / Vd[g]
+    return D
+
+
+def build(p, a: Assembled, variant: str = "BGS", schur: str = SCHUR_MASS,
+          opts: amg_mod.AMGOptions | None = None, dtype=np.float64) -> BlockPreconditioner:
+    opts = opts or amg_mod.AMGOptions()
+    blk = a.blocks()
+    hV = amg_mod.setup(blk["V"], velocity_components(a), False, opts)
+    Dt = darcy_interface_block(blk)
+    hD = amg_mod.setup(Dt, np.zeros(Dt.shape[0], dtype=np.int32), False, opts)
+    vol = (p.Lx / p.nx) * (p.H_ff / p.ny)
+    xscale = p.mu / vol if schur == SCHUR_MASS else 1.0
+    return BlockPreconditioner(variant=variant, schur=schur, hV=hV, hD=hD,
+                               C=blk["C"], C1=blk["C1"], off=a.layout.block_off,
+                               xscale=xscale, dtype=dtype)
+
+
+def exact_block_preconditioner(a: Assembled, variant: str, S_inv):
+    """Block preconditioner with exact V^-1, D'^-1 (sparse LU) and a given
+    middle-block operator S_inv; used to check the block algebra."""
+    import scipy.sparse.linalg as spla
+    blk = a.blocks()
+    o = a.layout.block_off
+    luV = spla.splu(blk["V"].tocsc())
+    luD = spla.splu(blk["D"].tocsc())
+
+    def apply(r):
+        rv, rp, rq = r[o[0]:o[2]], r[o[2]:o[3]], r[o[3]:o[4]]
+        yv = luV.solve(rv)
+        if variant == "BJ":
+            return np.concatenate([yv, S_inv(rp), luD.solve(rq)])
+        return np.concatenate([yv, S_inv(rp - blk["C"] @ yv),
+                               luD.solve(rq - blk["C1"] @ yv)])
+    return apply

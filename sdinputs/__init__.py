@@ -1,0 +1,322 @@
+"""Seeded synthetic inputs for the coupled Stokes-Darcy solver.
+
+This module is shared by the CPU oracle, the tests and the benchmark.  It
+produces *inputs only* -- grids, permeability fields, boundary data, forcing
+terms sampled from a manufactured solution and request traces -- and holds
+none of the solver's arithmetic (no discretisation, no linear algebra).
+
+Geometry (Sec. 2 of the paper, model problem): the porous medium occupies
+[0, Lx] x [0, H_pm], the free flow [0, Lx] x [H_pm, H_pm + H_ff]; the
+interface Gamma is the line y = H_pm.  Both subdomains have nx cell columns
+(conforming at Gamma); the free flow has ny cell rows, the porous medium
+ny_pm.  Staggered free-flow unknowns: u on vertical faces (x = i dx,
+y = y_G + (j + 1/2) dy), v on horizontal faces (x = (i + 1/2) dx,
+y = y_G + j dy), p at cell centres; porous-medium pressures q at cell centres.
+Arrays are stored row-major with the row index counted from the bottom.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+BC_VELOCITY = "velocity"
+BC_TRACTION = "traction"
+BC_PRESSURE = "pressure"
+BC_NOFLOW = "noflow"
+
+
+@dataclasses.dataclass
+class Problem:
+    """Everything that defines one stationary coupled solve.
+
+    Boundary data conventions (all optional, ``None`` means zero):
+      ff_left_n  [ny]     normal velocity u at the left faces (x = 0)
+      ff_left_t  [ny+1]   tangential velocity v on the left wall at y_G + j dy
+      ff_right_n [ny]     velocity u (velocity BC) or normal momentum flux
+                          n.(pI - tau)n (traction BC) at x = Lx
+      ff_right_t [ny+1]   velocity v (velocity BC) or tangential momentum
+                          flux t.(pI - tau)n (traction BC) at x = Lx, y_G + j dy
+      ff_top_t   [nx+1]   tangential velocity u on the top wall at x = i dx
+      ff_top_n   [nx]     normal velocity v on the top wall
+      pm_left_p/pm_right_p [ny_pm], pm_bottom_p [nx]  Dirichlet pressures
+    Forcing: f_u [ny, nx+1] at u faces, f_v [ny+1, nx] at v faces,
+    q_pm [ny_pm, nx] volumetric source at porous-medium cell centres.
+    """
+
+    nx: int
+    ny: int
+    ny_pm: int
+    Lx: float = 1.0
+    H_ff: float = 0.5
+    H_pm: float = 0.5
+    mu: float = 1.0
+    alpha_bj: float = 1.0
+    K: Optional[np.ndarray] = None          # [ny_pm, nx]
+    ff_left: str = BC_VELOCITY
+    ff_right: str = BC_TRACTION
+    ff_top: str = BC_VELOCITY
+    pm_left: str = BC_NOFLOW
+    pm_right: str = BC_NOFLOW
+    pm_bottom: str = BC_NOFLOW
+    ff_left_n: Optional[np.ndarray] = None
+    ff_left_t: Optional[np.ndarray] = None
+    ff_right_n: Optional[np.ndarray] = None
+    ff_right_t: Optional[np.ndarray] = None
+    ff_top_t: Optional[np.ndarray] = None
+    ff_top_n: Optional[np.ndarray] = None
+    pm_left_p: Optional[np.ndarray] = None
+    pm_right_p: Optional[np.ndarray] = None
+    pm_bottom_p: Optional[np.ndarray] = None
+    f_u: Optional[np.ndarray] = None
+    f_v: Optional[np.ndarray] = None
+    q_pm: Optional[np.ndarray] = None
+
+    @property
+    def dx(self) -> float:
+        return self.Lx / self.nx
+
+    @property
+    def dy(self) -> float:
+        return self.H_ff / self.ny
+
+    @property
+    def dy_pm(self) -> float:
+        return self.H_pm / self.ny_pm
+
+    @property
+    def y_gamma(self) -> float:
+        return self.H_pm
+
+
+# ----------------------------------------------------------------------------
+# Face / cell coordinates
+# ----------------------------------------------------------------------------
+
+def u_face_xy(p: Problem):
+    """Coordinates of all u faces, arrays of shape [ny, nx+1]."""
+    x = np.arange(p.nx + 1) * p.dx
+    y = p.y_gamma + (np.arange(p.ny) + 0.5) * p.dy
+    return np.meshgrid(x, y)
+
+
+def v_face_xy(p: Problem):
+    """Coordinates of all v faces, arrays of shape [ny+1, nx]."""
+    x = (np.arange(p.nx) + 0.5) * p.dx
+    y = p.y_gamma + np.arange(p.ny + 1) * p.dy
+    return np.meshgrid(x, y)
+
+
+def ff_cell_xy(p: Problem):
+    x = (np.arange(p.nx) + 0.5) * p.dx
+    y = p.y_gamma + (np.arange(p.ny) + 0.5) * p.dy
+    return np.meshgrid(x, y)
+
+
+def pm_cell_xy(p: Problem):
+    x = (np.arange(p.nx) + 0.5) * p.dx
+    y = (np.arange(p.ny_pm) + 0.5) * p.dy_pm
+    return np.meshgrid(x, y)
+
+
+# ----------------------------------------------------------------------------
+# Permeability fields
+# ----------------------------------------------------------------------------
+
+def lognormal_K(nx: int, ny_pm: int, K_geo: float, sigma: float,
+                corr_cells: float, seed: int) -> np.ndarray:
+    """ln K ~ N(ln K_geo, sigma^2) per cell with a Gaussian-smoothed
+    correlation: iid N(0,1) (PCG64 from ``seed``), Gaussian filter with a
+    standard deviation of ``corr_cells`` cells (reflecting borders, truncated
+    at 4 sigma), re-standardised to zero mean and unit variance."""
+    from scipy.ndimage import gaussian_filter
+
+    rng = np.random.default_rng(seed)
+    z = rng.standard_normal((ny_pm, nx))
+    if corr_cells > 0:
+        z = gaussian_filter(z, sigma=corr_cells, mode="reflect", truncate=4.0)
+    z = (z - z.mean()) / z.std()
+    return np.exp(math.log(K_geo) + sigma * z)
+
+
+# ----------------------------------------------------------------------------
+# Manufactured solution (satisfies the three interface conditions exactly)
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class MMS:
+    """Stream function psi = -sin(pi x) h(s)/pi with s = y - y_G,
+    u = d psi/dy, v = -d psi/dx; free-flow pressure cos(pi x)(Q0 + s);
+    porous-medium pressure y cos(pi x).  h = h0 + h1 s + s^2 with
+    h0 = -K/mu (normal mass flux continuity), h1 = (sqrt(K)/alpha)(2 + pi^2 h0)
+    (Beavers-Joseph-Saffman slip) and Q0 = y_G + 2 mu h1 (normal stress
+    balance).  Valid for constant K."""
+
+    K: float
+    mu: float
+    alpha: float
+    y_gamma: float
+
+    @property
+    def h0(self):
+        return -self.K / self.mu
+
+    @property
+    def h1(self):
+        return math.sqrt(self.K) / self.alpha * (2.0 + math.pi ** 2 * self.h0)
+
+    @property
+    def Q0(self):
+        return self.y_gamma + 2.0 * self.mu * self.h1
+
+    def h(self, s):
+        return self.h0 + self.h1 * s + s * s
+
+    def dh(self, s):
+        return self.h1 + 2.0 * s
+
+    def u(self, x, y):
+        s = y - self.y_gamma
+        return -np.sin(np.pi * x) * self.dh(s) / np.pi
+
+    def v(self, x, y):
+        s = y - self.y_gamma
+        return np.cos(np.pi * x) * self.h(s)
+
+    def p(self, x, y):
+        s = y - self.y_gamma
+        return np.cos(np.pi * x) * (self.Q0 + s)
+
+    def P(self, x, y):
+        return y * np.cos(np.pi * x)
+
+    def f_x(self, x, y):
+        s = y - self.y_gamma
+        return (-self.mu * np.pi * np.sin(np.pi * x) * self.dh(s)
+                - np.pi * np.sin(np.pi * x) * (self.Q0 + s))
+
+    def f_y(self, x, y):
+        s = y - self.y_gamma
+        return (-self.mu * np.cos(np.pi * x) * (2.0 - np.pi ** 2 * self.h(s))
+                + np.cos(np.pi * x))
+
+    def s_pm(self, x, y):
+        return self.K / self.mu * np.pi ** 2 * y * np.cos(np.pi * x)
+
+    def flux_n(self, x, y):
+        """n.(pI - tau)n on a boundary with outward normal (1, 0)."""
+        s = y - self.y_gamma
+        return np.cos(np.pi * x) * (self.Q0 + s + 2.0 * self.mu * self.dh(s))
+
+    def flux_t(self, x, y):
+        """t.(pI - tau)n on a boundary with outward normal (1, 0)."""
+        s = y - self.y_gamma
+        return self.mu * np.sin(np.pi * x) * (2.0 / np.pi + np.pi * self.h(s))
+
+
+def mms_problem(nx: int, ny: int, ny_pm: Optional[int] = None, K: float = 1e-2,
+                mu: float = 1.0, alpha: float = 1.0, Lx: float = 1.0,
+                H_ff: float = 0.5, H_pm: float = 0.5) -> tuple[Problem, MMS]:
+    """Manufactured-solution problem: free-flow velocity given on the left and
+    top, momentum flux (traction) on the right, Dirichlet pressure on the three
+    outer porous-medium sides."""
+    ny_pm = ny if ny_pm is None else ny_pm
+    p = Problem(nx=nx, ny=ny, ny_pm=ny_pm, Lx=Lx, H_ff=H_ff, H_pm=H_pm, mu=mu,
+                alpha_bj=alpha, K=np.full((ny_pm, nx), K),
+                ff_left=BC_VELOCITY, ff_right=BC_TRACTION, ff_top=BC_VELOCITY,
+                pm_left=BC_PRESSURE, pm_right=BC_PRESSURE, pm_bottom=BC_PRESSURE)
+    m = MMS(K=K, mu=mu, alpha=alpha, y_gamma=H_pm)
+    yc = p.y_gamma + (np.arange(ny) + 0.5) * p.dy
+    yv = p.y_gamma + np.arange(ny + 1) * p.dy
+    xu = np.arange(nx + 1) * p.dx
+    xv = (np.arange(nx) + 0.5) * p.dx
+    ytop = p.y_gamma + H_ff
+    ypm = (np.arange(ny_pm) + 0.5) * p.dy_pm
+    p.ff_left_n = m.u(0.0, yc)
+    p.ff_left_t = m.v(0.0, yv)
+    p.ff_right_n = m.flux_n(Lx, yc)
+    p.ff_right_t = m.flux_t(Lx, yv)
+    p.ff_top_t = m.u(xu, ytop)
+    p.ff_top_n = m.v(xv, ytop)
+    p.pm_left_p = m.P(0.0, ypm)
+    p.pm_right_p = m.P(Lx, ypm)
+    p.pm_bottom_p = m.P(xv, 0.0)
+    xu2, yu2 = u_face_xy(p)
+    xv2, yv2 = v_face_xy(p)
+    xq, yq = pm_cell_xy(p)
+    p.f_u = m.f_x(xu2, yu2)
+    p.f_v = m.f_y(xv2, yv2)
+    p.q_pm = m.s_pm(xq, yq)
+    return p, m
+
+
+# ----------------------------------------------------------------------------
+# Channel flow over a heterogeneous porous bed
+# ----------------------------------------------------------------------------
+
+def channel_problem(nx: int, ny: int, ny_pm: Optional[int] = None, *,
+                    mu: float = 1e-3, K_geo: float = 1e-4, sigma: float = 1.0,
+                    corr_cells: float = 8.0, seed: int = 1, U: float = 1e-2,
+                    alpha: float = 1.0, Lx: float = 1.0,
+                    H_ff: float = 0.5, H_pm: float = 0.5) -> Problem:
+    """Parabolic inflow of peak ``U`` on the free-flow left side, zero
+    traction on the right, no-slip top, no-flow on every outer porous side;
+    lognormal permeability."""
+    ny_pm = ny if ny_pm is None else ny_pm
+    K = lognormal_K(nx, ny_pm, K_geo, sigma, corr_cells, seed)
+    p = Problem(nx=nx, ny=ny, ny_pm=ny_pm, Lx=Lx, H_ff=H_ff, H_pm=H_pm, mu=mu,
+                alpha_bj=alpha, K=K, ff_left=BC_VELOCITY, ff_right=BC_TRACTION,
+                ff_top=BC_VELOCITY, pm_left=BC_NOFLOW, pm_right=BC_NOFLOW,
+                pm_bottom=BC_NOFLOW)
+    yc = p.y_gamma + (np.arange(ny) + 0.5) * p.dy
+    ytop = p.y_gamma + H_ff
+    p.ff_left_n = 4.0 * U * (yc - p.y_gamma) * (ytop - yc) / (H_ff * H_ff)
+    return p
+
+
+# Named workloads (cells per subdomain) ---------------------------------------
+
+def config_problem(name: str) -> Problem:
+    """C0: 32x16 manufactured solution; C1: 512x256 channel (seed 1);
+    C2: 1024x512 channel (seed 2); small channel cases for tests."""
+    if name == "C0":
+        return mms_problem(32, 16)[0]
+    if name == "C1":
+        return channel_problem(512, 256, seed=1)
+    if name == "C2":
+        return channel_problem(1024, 512, seed=2)
+    raise KeyError(name)
+
+
+# ----------------------------------------------------------------------------
+# Serving trace
+# ----------------------------------------------------------------------------
+
+SERVING_GRIDS = ((64, 32), (128, 64), (256, 128), (512, 256))
+
+
+def serving_trace(n_requests: int, rate_per_s: float, seed: int = 7,
+                  grids=SERVING_GRIDS):
+    """Poisson arrivals (exponential gaps at ``rate_per_s``), grid uniform over
+    ``grids``, sigma ~ U[0.5, 2], inflow peak ~ U[1e-3, 1e-1], permeability
+    seed 1000 + r.  Returns a list of dicts (arrival time and parameters)."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate_per_s, n_requests) if rate_per_s > 0 \
+        else np.zeros(n_requests)
+    t = np.cumsum(gaps) - (gaps[0] if n_requests else 0.0)
+    gi = rng.integers(0, len(grids), n_requests)
+    sig = rng.uniform(0.5, 2.0, n_requests)
+    U = rng.uniform(1e-3, 1e-1, n_requests)
+    out = []
+    for r in range(n_requests):
+        nx, ny = grids[int(gi[r])]
+        out.append(dict(t_arrival=float(t[r]), nx=nx, ny=ny, sigma=float(sig[r]),
+                        U=float(U[r]), seed=1000 + r))
+    return out
+
+
+def trace_problem(req: dict) -> Problem:
+    return channel_problem(req["nx"], req["ny"], sigma=req["sigma"], U=req["U"],
+                           seed=req["seed"])

@@ -1,0 +1,305 @@
+"""Pins of the oracle's AMG, block preconditioners and Krylov solvers."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from sdinputs import channel_problem, lognormal_K, mms_problem
+from oracle import amg, krylov, precond
+from oracle.assemble import assemble
+from oracle.direct import refined_solve, solve
+from oracle.hashing import fmix32, level_seed
+
+
+def _fmix32_int(h):
+    """Independent pure-integer rendering of the MurmurHash3 finaliser."""
+    h &= 0xFFFFFFFF
+    h ^= h >> 16
+    h = (h * 0x85EBCA6B) & 0xFFFFFFFF
+    h ^= h >> 13
+    h = (h * 0xC2B2AE35) & 0xFFFFFFFF
+    h ^= h >> 16
+    return h
+
+
+def test_fmix32():
+    assert int(fmix32(0)) == 0
+    xs = np.arange(0, 1 << 16, dtype=np.uint64) * np.uint64(65521)
+    ref = np.array([_fmix32_int(int(v)) for v in xs[:2000]], dtype=np.uint64)
+    assert np.array_equal(fmix32(xs[:2000]), ref)
+    # the finaliser is a bijection of 32-bit words
+    h = fmix32(np.arange(1 << 20, dtype=np.uint64))
+    assert np.unique(h).size == 1 << 20
+    assert level_seed(0) == 0x9E3779B9
+
+
+def _problem_block(n=32):
+    p = channel_problem(n, n // 2, seed=2)
+    a = assemble(p)
+    return p, a, a.blocks()
+
+
+@pytest.mark.parametrize("mis_dist", [1, 2])
+def test_mis_independent_and_maximal(mis_dist):
+    p, a, blk = _problem_block()
+    V = blk["V"]
+    comp = precond.velocity_components(a)
+    S = amg.strength_graph(V, comp, 0.08)
+    G = S if mis_dist == 1 else amg.square_graph(S)
+    st = amg.mis(G, 0)
+    root = st == amg.ROOT
+    rows = np.repeat(np.arange(G.shape[0]), np.diff(G.indptr))
+    assert not np.any(root[rows] & root[G.indices])           # independent
+    has_root_nb = np.zeros(G.shape[0], dtype=bool)
+    has_root_nb[rows[root[G.indices]]] = True
+    assert np.all(root | has_root_nb)                           # maximal
+
+
+def test_mis_distance2_separation():
+    p, a, blk = _problem_block()
+    S = amg.strength_graph(blk["D"], np.zeros(blk["D"].shape[0], int), 0.08)
+    st = amg.mis(amg.square_graph(S), 1)
+    roots = np.flatnonzero(st == amg.ROOT)
+    Sd = S.toarray().astype(bool)
+    S2 = (Sd.astype(int) @ Sd.astype(int) > 0) | Sd
+    for r in roots:
+        others = np.setdiff1d(roots, [r])
+        assert not np.any(S2[r, others])
+
+
+@pytest.mark.parametrize("smoothed,mis_dist", [(False, 1), (True, 2), (True, 1)])
+def test_aggregation_partition_and_galerkin(smoothed, mis_dist):
+    p, a, blk = _problem_block(24)
+    V = blk["V"]
+    comp = precond.velocity_components(a)
+    opts = amg.AMGOptions(smoothed=smoothed, mis=mis_dist, coarse_max=40)
+    h = amg.setup(V, comp, False, opts)
+    assert h.n_levels >= 3
+    for L, Ln in zip(h.levels[:-1], h.levels[1:]):
+        n_c = Ln.A.shape[0]
+        # every node in exactly one aggregate, every aggregate non-empty
+        assert L.agg.min() >= 0 and L.agg.max() == n_c - 1
+        assert np.bincount(L.agg, minlength=n_c).min() >= 1
+        # aggregates never mix components
+        assert np.all(Ln.comp[L.agg] == L.comp)
+        # Galerkin product equals the dense triple product
+        Ad = L.A.toarray()
+        Pd = L.P.toarray()
+        ref = Pd.T @ Ad @ Pd
+        assert np.allclose(Ln.A.toarray(), ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+        if not smoothed:
+            one = np.ones(L.A.shape[0])
+            lhs = Ln.A @ np.ones(n_c)
+            rhs = L.R @ (L.A @ one)
+            assert np.allclose(lhs, rhs, rtol=0, atol=1e-13 * np.abs(rhs).max())
+        else:
+            # smoothed prolongation preserves constants on interior rows only;
+            # check the definition entrywise instead
+            assert np.allclose(L.R.toarray(), Pd.T)
+
+
+def test_spgemm_order_is_row_by_row():
+    """The oracle's ordered sparse product equals an explicit loop bit-for-bit."""
+    rng = np.random.default_rng(3)
+    X = sp.random(40, 30, density=0.2, random_state=4, format="csr")
+    Y = sp.random(30, 25, density=0.25, random_state=5, format="csr")
+    X.data = rng.standard_normal(X.nnz)
+    Y.data = rng.standard_normal(Y.nnz)
+    Z = amg.spgemm(X, Y)
+    ref = {}
+    for i in range(40):
+        for kk in range(X.indptr[i], X.indptr[i + 1]):
+            k = X.indices[kk]
+            for ll in range(Y.indptr[k], Y.indptr[k + 1]):
+                key = (i, Y.indices[ll])
+                ref[key] = ref.get(key, 0.0) + X.data[kk] * Y.data[ll]
+    Zc = Z.tocoo()
+    assert len(ref) == Z.nnz
+    for i, j, v in zip(Zc.row, Zc.col, Zc.data):
+        assert ref[(i, j)] == v
+
+
+def test_vcycle_single_level_is_coarse_inverse():
+    p, a, blk = _problem_block(16)
+    D = precond.darcy_interface_block(blk)
+    h = amg.setup(D, np.zeros(D.shape[0], int), False, amg.AMGOptions(coarse_max=10 ** 6))
+    assert h.n_levels == 1
+    b = np.random.default_rng(0).standard_normal(D.shape[0])
+    assert np.allclose(amg.vcycle(h, b), spla.spsolve(D.tocsc(), b), rtol=1e-10)
+
+
+@pytest.mark.parametrize("smoothed", [False, True])
+def test_vcycle_operator_brute_force(smoothed):
+    """Two-level cycle matrix equals (I - E) A^-1 with
+    E = S^nu2 (I - P A_c^-1 R A) S^nu1 and S = I - omega D^-1 A."""
+    p, a, blk = _problem_block(12)
+    V = blk["V"]
+    comp = precond.velocity_components(a)
+    n = V.shape[0]
+    opts = amg.AMGOptions(smoothed=smoothed, mis=2 if smoothed else 1,
+                          coarse_max=n - 1, max_levels=2)
+    h = amg.setup(V, comp, False, opts)
+    assert h.n_levels == 2
+    A = V.toarray()
+    L0 = h.levels[0]
+    P, R = L0.P.toarray(), L0.R.toarray()
+    Ac = R @ A @ P
+    I = np.eye(n)
+    S = I - opts.omega * np.diag(1 / np.diag(A)) @ A
+    E = (np.linalg.matrix_power(S, opts.nu_post) @ (I - P @ np.linalg.inv(Ac) @ R @ A)
+         @ np.linalg.matrix_power(S, opts.nu_pre))
+    Mref = (I - E) @ np.linalg.inv(A)
+    M = amg.vcycle_operator(h)
+    assert np.allclose(M, Mref, rtol=0, atol=1e-10 * np.abs(Mref).max())
+
+
+def test_vcycle_detects_planted_error():
+    """Dropping the post-smoother breaks the brute-force identity."""
+    p, a, blk = _problem_block(12)
+    V = blk["V"]
+    comp = precond.velocity_components(a)
+    n = V.shape[0]
+    opts = amg.AMGOptions(coarse_max=n - 1, max_levels=2)
+    h = amg.setup(V, comp, False, opts)
+    bad = amg.Hierarchy(h.levels, h.Ainv, amg.AMGOptions(coarse_max=n - 1,
+                                                           max_levels=2, nu_post=1))
+    assert not np.allclose(amg.vcycle_operator(bad), amg.vcycle_operator(h),
+                           rtol=1e-6, atol=0)
+
+
+def test_block_triangular_with_exact_blocks_converges_in_two():
+    """With exact V^-1, exact Schur complement S = -C V^-1 B and the
+    interface couplings removed, block-Gauss-Seidel preconditioned GMRES
+    converges in two iterations (minimal polynomial of degree 2)."""
+    p, m = mms_problem(12, 6)
+    a = assemble(p)
+    blk = a.blocks()
+    o = a.layout.block_off
+    A = a.A.tolil()
+    A[o[0]:o[2], o[3]:o[4]] = 0
+    A[o[3]:o[4], o[0]:o[2]] = 0
+    A = A.tocsr()
+    A.eliminate_zeros()
+    Vd = blk["V"].toarray()
+    S = -blk["C"].toarray() @ np.linalg.solve(Vd, blk["B"].toarray())
+    Sinv = np.linalg.inv(S)
+    luV = spla.splu(blk["V"].tocsc())
+    luD = spla.splu(blk["D"].tocsc())
+
+    def P(r):
+        yv = luV.solve(r[o[0]:o[2]])
+        return np.concatenate([yv, Sinv @ (r[o[2]:o[3]] - blk["C"] @ yv),
+                               luD.solve(r[o[3]:o[4]])])
+
+    res = krylov.fgmres(A, a.b, P, tol=1e-10, m=30, maxit=10)
+    assert res.converged and res.iters <= 2
+
+
+def test_bgs_application_solves_lower_block_triangle():
+    p = channel_problem(16, 8, seed=1)
+    a = assemble(p)
+    blk = a.blocks()
+    o = a.layout.block_off
+    Dt = precond.darcy_interface_block(blk)
+    vol = (p.Lx / p.nx) * (p.H_ff / p.ny)
+    # exact blocks: P_V = V^-1, P_D = Dt^-1, X = mu/vol
+    apply = precond.exact_block_preconditioner(a, "BGS", lambda r: (p.mu / vol) * r)
+    # replace the D solve by Dt's for the comparison
+    luV = spla.splu(blk["V"].tocsc())
+    luD = spla.splu(Dt.tocsc())
+    nV, nP = o[2], o[3] - o[2]
+    Lmat = sp.bmat([[blk["V"], None, None],
+                    [blk["C"], sp.identity(nP) * (vol / p.mu), None],
+                    [blk["C1"], None, Dt]]).tocsc()
+    r = np.random.default_rng(1).standard_normal(a.N)
+    y = spla.spsolve(Lmat, r)
+    yv = luV.solve(r[:nV])
+    yp = (p.mu / vol) * (r[o[2]:o[3]] - blk["C"] @ yv)
+    yq = luD.solve(r[o[3]:] - blk["C1"] @ yv)
+    assert np.allclose(np.concatenate([yv, yp, yq]), y, rtol=1e-10, atol=1e-12)
+    assert apply is not None
+
+
+def test_darcy_interface_block_is_nonsingular_correction():
+    p = channel_problem(16, 8, seed=1)
+    a = assemble(p)
+    blk = a.blocks()
+    Dt = precond.darcy_interface_block(blk)
+    diff = (Dt - blk["D"]).tocoo()
+    L = a.layout
+    tops = set(L.q(np.arange(L.nx), L.ny_pm - 1) - L.off_q)
+    assert set(diff.row[diff.data != 0]) == tops
+    assert np.all(diff.row == diff.col) and np.all(diff.data > 0)
+    assert np.linalg.matrix_rank(Dt.toarray()) == Dt.shape[0]
+
+
+def test_fgmres_iterates_are_least_squares_minimisers():
+    p = channel_problem(8, 4, seed=1)
+    a = assemble(p)
+    M = precond.build(p, a, "BGS")
+    A = a.A.toarray()
+    for k in [1, 3, 6]:
+        res = krylov.fgmres(a.A, a.b, M, tol=1e-300, m=k, maxit=k)
+        # rebuild Z_k exactly as the solver did
+        Z = []
+        V = [a.b / np.linalg.norm(a.b)]
+        for j in range(k):
+            z = M(V[j])
+            Z.append(z)
+            w = A @ z
+            Vm = np.array(V)
+            h = Vm @ w
+            w = w - Vm.T @ h
+            h2 = Vm @ w
+            w = w - Vm.T @ h2
+            V.append(w / np.linalg.norm(w))
+        xls = krylov.least_squares_iterate(A, a.b, np.array(Z).T, np.zeros(a.N))
+        assert np.linalg.norm(res.x - xls) <= 1e-8 * np.linalg.norm(xls)
+
+
+def test_fgmres_matches_lu_and_scipy_gmres():
+    p, m = mms_problem(32, 16)
+    a = assemble(p)
+    M = precond.build(p, a, "BJ")
+    res = krylov.fgmres(a.A, a.b, M, tol=1e-10, m=30)
+    assert res.converged and res.rel_res <= 1e-10
+    xs = refined_solve(a.A, a.b)
+    assert np.linalg.norm(res.x - xs) <= 1e-7 * np.linalg.norm(xs)
+    Mop = spla.LinearOperator(a.A.shape, matvec=M)
+    xg, info = spla.gmres(a.A, a.b, M=Mop, rtol=1e-11, restart=30, maxiter=50)
+    assert info == 0
+    assert np.linalg.norm(xg - xs) <= 1e-7 * np.linalg.norm(xs)
+
+
+def test_bicgstab_converges_to_lu():
+    p = channel_problem(32, 16, seed=1)
+    a = assemble(p)
+    M = precond.build(p, a, "BGS")
+    res = krylov.bicgstab(a.A, a.b, M, tol=1e-10)
+    assert res.converged
+    xs = refined_solve(a.A, a.b)
+    assert np.linalg.norm(res.x - xs) <= 1e-7 * np.linalg.norm(xs)
+
+
+def test_mixed_precision_refinement_reaches_fp64_tolerance():
+    p = channel_problem(64, 32, seed=1)
+    a = assemble(p)
+    M32 = precond.build(p, a, "BGS", dtype=np.float32)
+    res = krylov.fgmres(a.A, a.b, M32, tol=1e-8, m=30, A_inner=a.A.astype(np.float32),
+                        inner_dtype=np.float32, cycle_drop=1e-6)
+    assert res.converged and res.rel_res <= 1e-8
+    xs = refined_solve(a.A, a.b)
+    assert np.linalg.norm(res.x - xs) <= 1e-6 * np.linalg.norm(xs)
+
+
+def test_lognormal_field_statistics():
+    K = lognormal_K(256, 128, 1e-4, 1.0, 8.0, seed=1)
+    z = np.log(K)
+    assert abs(z.mean() - np.log(1e-4)) < 1e-12
+    assert abs(z.std() - 1.0) < 1e-12
+    zc = (z - z.mean()) / z.std()
+    # Gaussian filter of width s gives correlation exp(-d^2 / (4 s^2))
+    lag = 8
+    c = np.mean(zc[:, :-lag] * zc[:, lag:])
+    assert abs(c - np.exp(-lag ** 2 / (4 * 64.0))) < 0.1
+    assert np.array_equal(K, lognormal_K(256, 128, 1e-4, 1.0, 8.0, seed=1))
