@@ -1,0 +1,253 @@
+/*
+ * sd.h -- C ABI of the MI355X coupled Stokes-Darcy solver.
+ *
+ * The library assembles the monolithic system of the paper's Sec. 2 (free
+ * flow: stationary creeping Stokes in symmetric-gradient form on a staggered
+ * grid; porous medium: Darcy's law with two-point fluxes; interface Gamma:
+ * normal-stress balance, Beavers-Joseph-Saffman slip, normal mass-flux
+ * continuity) in the pressure-velocity block form
+ *
+ *       [ V    B   B1' ] [ v^ff ]   [ g ]
+ *       [ C    0   0   ] [ p^ff ] = [ 0 ]
+ *       [ C1'  0   D'  ] [ p^pm ]   [ 0 ]
+ *
+ * and solves it with flexible GMRES (or BiCGSTAB) right-preconditioned by the
+ * pressure-velocity block-Jacobi or block-Gauss-Seidel preconditioner of
+ * Sec. 4, whose velocity and Darcy sub-solves are one aggregation-AMG V-cycle
+ * each (Sec. 5 solver setup).  All iteration work runs in HIP kernels on one
+ * GPU; FP64 throughout, or mixed precision (FP32 preconditioner and inner
+ * products with an FP64 outer residual, orthogonalisation and coarse solve).
+ *
+ * Conventions.  Every function returns an sd_status (0 = success) unless its
+ * return type says otherwise; no C++ exception crosses this boundary.  On
+ * failure sd_last_error() returns a thread-local message.  Host inputs are
+ * copied during the call; the caller may free them on return.  Handles are
+ * owned by the caller and released by the matching *_destroy.  Device
+ * pointers must be allocated on the device that is current when the handle
+ * was created.  A problem/solver handle must not be used from two threads at
+ * once; a server handle is thread-safe.
+ *
+ * Grid.  The porous medium occupies [0,Lx] x [0,H_pm], the free flow
+ * [0,Lx] x [H_pm, H_pm+H_ff]; both have nx cell columns, the free flow ny
+ * rows and the porous medium ny_pm rows.  Unknown ordering (the pv blocks):
+ * u faces (free-flow row j major, face i = 1..nu_x minor, nu_x = nx with a
+ * traction right boundary, nx-1 with a velocity one), v faces (j = 0..ny-1,
+ * j = 0 on Gamma), free-flow cell pressures, porous cell pressures (row k = 0
+ * at the bottom).  Dirichlet velocity faces are eliminated and lifted into b.
+ */
+#ifndef SD_H
+#define SD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SD_OK = 0,
+  SD_E_INVALID = -1,    /* bad argument (sizes, NaN/Inf, K <= 0, unsupported BC) */
+  SD_E_NOMEM = -2,      /* device or host allocation failed / over budget      */
+  SD_E_DEVICE = -3,     /* HIP runtime error or no GPU                           */
+  SD_E_NOCONV = -4,     /* maxit reached: best iterate and stats still written   */
+  SD_E_BREAKDOWN = -5,  /* NaN/Inf in the iteration or a zero pivot              */
+  SD_E_BUSY = -6,       /* server: result not ready                              */
+  SD_E_NOTFOUND = -7    /* server: unknown ticket                                */
+} sd_status;
+
+typedef struct sd_problem sd_problem;
+typedef struct sd_solver sd_solver;
+typedef struct sd_server sd_server;
+
+/* Device-memory callbacks (e.g. a framework's caching allocator).  NULL for
+ * the library default (hipMalloc / hipFree).  alloc returns NULL on failure. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx, void* hip_stream);
+  void (*free)(void* ptr, void* ctx, void* hip_stream);
+  void* ctx;
+} sd_allocator;
+
+typedef struct {
+  int nx, ny, ny_pm;          /* cells: columns, free-flow rows, porous rows  */
+  double Lx, H_ff, H_pm;      /* extents; Gamma at y = H_pm                    */
+} sd_grid;
+
+typedef struct {
+  double mu;                  /* dynamic viscosity (rho = 1, nu = mu)          */
+  double alpha_bj;            /* Beavers-Joseph coefficient                    */
+} sd_physics;
+
+typedef enum { SD_BC_VELOCITY = 0, SD_BC_TRACTION = 1, SD_BC_PRESSURE = 2,
+               SD_BC_NOFLOW = 3 } sd_bc_type;
+
+/* Boundary conditions.  Free-flow left and top: SD_BC_VELOCITY; right:
+ * SD_BC_VELOCITY or SD_BC_TRACTION; porous left/right/bottom: SD_BC_PRESSURE
+ * or SD_BC_NOFLOW.  Data arrays may be NULL (zero):
+ *   ff_left_n [ny] u at x=0;  ff_left_t [ny+1] v on the left wall at y_G + j dy
+ *   ff_right_n [ny]  u (velocity) or n.(pI - tau)n (traction) at x = Lx
+ *   ff_right_t [ny+1] v (velocity) or t.(pI - tau)n (traction), y_G + j dy
+ *   ff_top_t [nx+1] u on the top wall at x = i dx; ff_top_n [nx] v on the top
+ *   pm_left_p, pm_right_p [ny_pm], pm_bottom_p [nx] Dirichlet pressures     */
+typedef struct {
+  int ff_left, ff_right, ff_top, pm_left, pm_right, pm_bottom;
+  const double *ff_left_n, *ff_left_t, *ff_right_n, *ff_right_t;
+  const double *ff_top_t, *ff_top_n;
+  const double *pm_left_p, *pm_right_p, *pm_bottom_p;
+} sd_bcs;
+
+/* Forcing sampled at DoF locations (NULL = 0): f_u [ny][nx+1] at all u faces,
+ * f_v [ny+1][nx] at all v faces, q_pm [ny_pm][nx] porous source. */
+typedef struct {
+  const double *f_u, *f_v, *q_pm;
+} sd_forcing;
+
+/* Assemble the coupled system (Sec. 2) on the host and upload it to the
+ * current device.  K: [ny_pm][nx] positive permeabilities (host).  The matrix
+ * is kept in FP64; its values are those of the documented stencil evaluated
+ * in IEEE double without contraction.  allocator may be NULL; hip_stream may
+ * be NULL (default stream). */
+int sd_assemble(const sd_grid* grid, const sd_physics* phys, const sd_bcs* bcs,
+                const double* K, const sd_forcing* forcing,
+                const sd_allocator* allocator, void* hip_stream, sd_problem** out);
+
+/* Same as sd_assemble without any device work (usable without a GPU); such
+ * a problem can be inspected and set up with sd_setup_host only. */
+int sd_assemble_host(const sd_grid* grid, const sd_physics* phys,
+                     const sd_bcs* bcs, const double* K,
+                     const sd_forcing* forcing, sd_problem** out);
+
+/* N, block offsets [0, off_v, off_p, off_q, N] and nnz of the assembled A. */
+int sd_problem_info(const sd_problem* pb, int64_t* N, int64_t block_off[5],
+                    int64_t* nnz);
+
+/* Read-only views of the host CSR (sorted columns) and the assembled b;
+ * valid until sd_problem_destroy. */
+int sd_problem_csr(const sd_problem* pb, const int64_t** rowptr,
+                   const int32_t** col, const double** val, const double** b);
+
+enum { SD_KRYLOV_FGMRES = 0, SD_KRYLOV_BICGSTAB = 1 };
+enum { SD_PREC_BJ = 0, SD_PREC_BGS = 1 };
+enum { SD_SCHUR_IDENTITY = 0, SD_SCHUR_MASS = 1 };
+enum { SD_PRECISION_FP64 = 0, SD_PRECISION_MIXED = 1 };
+enum { SD_AMG_PLAIN = 0, SD_AMG_SMOOTHED = 1 };
+
+typedef struct {
+  int krylov;        /* SD_KRYLOV_*                                            */
+  int restart;       /* FGMRES restart length m (1..64), default 30            */
+  int maxit;         /* total iteration cap, default 1000                      */
+  double tol;        /* relative true FP64 residual ||b-Ax||/||b||             */
+  int precond;       /* SD_PREC_BJ | SD_PREC_BGS                               */
+  int schur;         /* middle block: identity or mu * M_p^-1                  */
+  int precision;     /* SD_PRECISION_FP64 | SD_PRECISION_MIXED                 */
+  int amg;           /* SD_AMG_SMOOTHED (default) | SD_AMG_PLAIN               */
+  int mis;           /* root independent set distance: 1 or 2 (default 2)     */
+  double theta;      /* strength threshold, default 0.08                       */
+  double omega;      /* Jacobi damping, default 2/3                            */
+  int nu_pre, nu_post; /* Jacobi sweeps, default 2 / 2                         */
+  int coarse_max;    /* coarsest level size bound, default 256                 */
+  int max_levels;    /* default 20                                             */
+} sd_solver_opts;
+
+/* Fill opts with the defaults above. */
+void sd_solver_opts_default(sd_solver_opts* opts);
+
+/* Build the AMG hierarchies for V and for the Darcy block
+ * D~ = D' - C1' diag(V)^-1 B1' (host, deterministic) and upload them with the
+ * block preconditioner's operators and the Krylov workspace. */
+int sd_setup(sd_problem* pb, const sd_solver_opts* opts, sd_solver** out);
+
+/* Host-only setup (no device work), for inspection. */
+int sd_setup_host(sd_problem* pb, const sd_solver_opts* opts, sd_solver** out);
+
+/* Hierarchy inspection: block 0 = V, 1 = D~.  n_levels counts the coarsest. */
+int sd_solver_levels(const sd_solver* s, int block, int* n_levels);
+/* which: 0 = A_l, 1 = P_l (n_l x n_{l+1}), 2 = R_l.  Host CSR views. */
+int sd_solver_level_csr(const sd_solver* s, int block, int level, int which,
+                        int64_t* n_rows, int64_t* n_cols, const int64_t** rowptr,
+                        const int32_t** col, const double** val);
+int sd_solver_level_agg(const sd_solver* s, int block, int level,
+                        const int32_t** agg, int64_t* n);
+/* Dense row-major inverse of the coarsest operator of a block. */
+int sd_solver_coarse_inverse(const sd_solver* s, int block, const double** inv,
+                             int64_t* n);
+
+typedef struct {
+  int iters, restarts;
+  double rel_res;            /* final true FP64 relative residual           */
+  double rel_res_block[3];   /* per block (v, p^ff, p^pm), relative to ||b|| */
+  double t_setup, t_solve;   /* seconds                                     */
+} sd_stats;
+
+/* Solve A x = b.  d_b: device FP64 [N], or NULL for the assembled b.  d_x:
+ * device FP64 [N], the initial guess when use_x0 != 0 (else overwritten from
+ * zero) and the result.  Runs on hip_stream (NULL = default) and returns
+ * after the solve has finished.  SD_E_NOCONV still writes the best iterate
+ * and stats. */
+int sd_solve(sd_solver* s, const double* d_b, double* d_x, int use_x0,
+             sd_stats* stats, void* hip_stream);
+
+/* Building blocks of the iteration on device vectors of the problem's
+ * ordering (FP64, length N), exposed for testing and composition.
+ * y = A x with the assembled FP64 matrix: */
+int sd_apply_matrix(sd_solver* s, const double* d_x, double* d_y, void* hip_stream);
+/* z = P(r), one application of the configured block preconditioner (in FP32
+ * inside when the solver is mixed; input and output are FP64): */
+int sd_apply_preconditioner(sd_solver* s, const double* d_r, double* d_z,
+                            void* hip_stream);
+/* x = one V-cycle on block (0 = V, 1 = D~) for right-hand side b
+ * (device FP64 vectors of the block's size): */
+int sd_apply_vcycle(sd_solver* s, int block, const double* d_b, double* d_x,
+                    void* hip_stream);
+
+/* ---------------------------------------------------------------- serving */
+typedef struct {
+  size_t hbm_budget;   /* bytes the server may hold (0 = 80% of free HBM)     */
+  int max_slots;       /* concurrently active solves (default 8)             */
+  int device;          /* HIP device ordinal                                 */
+} sd_server_opts;
+
+int sd_server_create(const sd_server_opts* opts, sd_server** out);
+
+typedef struct {
+  sd_grid grid;
+  sd_physics phys;
+  sd_bcs bcs;
+  const double* K;     /* [ny_pm][nx] host                                  */
+  sd_forcing forcing;
+  sd_solver_opts opts;
+} sd_request;
+
+/* Queue a solve.  All host data is copied.  SD_E_NOMEM if the request can
+ * never fit the budget. */
+int sd_submit(sd_server* sv, const sd_request* req, uint64_t* ticket);
+
+enum { SD_REQ_PENDING = 0, SD_REQ_RUNNING = 1, SD_REQ_DONE = 2, SD_REQ_FAILED = 3 };
+
+typedef struct {
+  int state;               /* SD_REQ_*                                       */
+  int status;              /* sd_status of the solve when DONE/FAILED        */
+  const double* x_host;    /* solution [N] (valid until sd_result_release)   */
+  int64_t N;
+  sd_stats stats;
+  double t_submit, t_admit, t_done;   /* seconds on the server's clock      */
+} sd_result;
+
+/* Non-blocking. */
+int sd_poll(sd_server* sv, uint64_t ticket, sd_result* out);
+/* Block until the ticket is DONE or FAILED (or timeout_s elapses: SD_E_BUSY). */
+int sd_wait(sd_server* sv, uint64_t ticket, double timeout_s, sd_result* out);
+int sd_result_release(sd_server* sv, uint64_t ticket);
+int sd_cancel(sd_server* sv, uint64_t ticket);
+
+void sd_problem_destroy(sd_problem* pb);
+void sd_solver_destroy(sd_solver* s);
+void sd_server_destroy(sd_server* sv);
+
+const char* sd_status_string(int status);
+const char* sd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SD_H */

@@ -1,0 +1,386 @@
+// Host setup of the aggregation AMG hierarchy.
+//
+// The paper's velocity and Darcy sub-solves are one V-cycle of an aggregation
+// AMG (Sec. 5, solver setup).  Setup steps, all deterministic:
+//   strength   j strong for i iff j != i, same component, and
+//              (a_ij*a_ij) >= (theta*theta) * |a_ii*a_jj|; graph symmetrised;
+//   roots      maximal independent set of the strength graph (distance 1) or
+//              of its square (distance 2) by synchronous Luby rounds, priority
+//              (fmix32(i ^ seed(level)), i), seed(level) = 0x9E3779B9 (level+1);
+//   aggregates roots numbered in index order; a node with a root neighbour
+//              joins the root of largest |a_ij| (ties: smallest index); for
+//              distance-2 roots the leftover nodes join, in one synchronous
+//              sweep, the aggregate of their aggregated strong neighbour of
+//              largest |a_ij| (ties: smallest index);
+//   transfer   tentative P[i, agg(i)] = 1, or smoothed
+//              P = (I - w D^-1 A_F) P_t with A_F = diagonal + strong entries,
+//              w = 4 / (3 rho), rho = max_i sum_j |a_F,ij| / |a_ii|;
+//              R = P^T; A_c = R (A P) with Gustavson-ordered sums;
+//   coarsest   dense LU with partial pivoting and explicit inverse.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+
+#include "sd_internal.h"
+
+namespace sd {
+
+namespace {
+
+enum : int8_t { UND = 0, ROOT = 1, NONROOT = 2 };
+
+struct Graph {  // adjacency lists with sorted neighbours, no self loops
+  std::vector<int64_t> ptr;
+  std::vector<int32_t> adj;
+};
+
+double diag_of(const HostCSR& A, int64_t r) {
+  for (int64_t k = A.rowptr[r]; k < A.rowptr[r + 1]; ++k)
+    if (A.col[k] == r) return A.val[k];
+  throw Error(SD_E_INVALID, "AMG: missing diagonal entry");
+}
+
+std::vector<uint8_t> strong_mask(const HostCSR& A, const std::vector<int32_t>& comp,
+                                 const std::vector<double>& d, double theta) {
+  const double th2 = theta * theta;
+  std::vector<uint8_t> m((size_t)A.nnz(), 0);
+  for (int64_t i = 0; i < A.n_rows; ++i) {
+    for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) {
+      const int64_t j = A.col[k];
+      const double a = A.val[k];
+      m[k] = (j != i) && (comp[i] == comp[j]) && ((a * a) >= th2 * std::fabs(d[i] * d[j]));
+    }
+  }
+  return m;
+}
+
+Graph symmetric_strength(const HostCSR& A, const std::vector<uint8_t>& m) {
+  const int64_t n = A.n_rows;
+  std::vector<std::vector<int32_t>> nb((size_t)n);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k)
+      if (m[k]) {
+        nb[i].push_back(A.col[k]);
+        nb[A.col[k]].push_back((int32_t)i);
+      }
+  Graph G;
+  G.ptr.assign(1, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    auto& v = nb[i];
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    G.adj.insert(G.adj.end(), v.begin(), v.end());
+    G.ptr.push_back((int64_t)G.adj.size());
+  }
+  return G;
+}
+
+Graph square(const Graph& S) {
+  const int64_t n = (int64_t)S.ptr.size() - 1;
+  Graph G;
+  G.ptr.assign(1, 0);
+  std::vector<int32_t> tmp;
+  for (int64_t i = 0; i < n; ++i) {
+    tmp.clear();
+    for (int64_t k = S.ptr[i]; k < S.ptr[i + 1]; ++k) {
+      const int32_t j = S.adj[k];
+      tmp.push_back(j);
+      for (int64_t l = S.ptr[j]; l < S.ptr[j + 1]; ++l) tmp.push_back(S.adj[l]);
+    }
+    std::sort(tmp.begin(), tmp.end());
+    tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
+    for (int32_t j : tmp)
+      if (j != i) G.adj.push_back(j);
+    G.ptr.push_back((int64_t)G.adj.size());
+  }
+  return G;
+}
+
+std::vector<int8_t> luby_mis(const Graph& G, int level) {
+  const int64_t n = (int64_t)G.ptr.size() - 1;
+  const uint32_t seed = (uint32_t)(0x9E3779B9ull * (uint64_t)(level + 1));
+  std::vector<uint64_t> key((size_t)n);
+  for (int64_t i = 0; i < n; ++i)
+    key[i] = ((uint64_t)fmix32((uint32_t)i ^ seed) << 32) | (uint64_t)i;
+  std::vector<int8_t> state((size_t)n, UND);
+  std::vector<uint8_t> new_root((size_t)n, 0);
+  int64_t undecided = n;
+  while (undecided > 0) {
+    for (int64_t i = 0; i < n; ++i) {
+      new_root[i] = 0;
+      if (state[i] != UND) continue;
+      bool lost = false;
+      for (int64_t k = G.ptr[i]; k < G.ptr[i + 1] && !lost; ++k) {
+        const int32_t j = G.adj[k];
+        if (state[j] == UND && key[j] > key[i]) lost = true;
+      }
+      new_root[i] = !lost;
+    }
+    for (int64_t i = 0; i < n; ++i)
+      if (new_root[i]) state[i] = ROOT;
+    for (int64_t i = 0; i < n; ++i) {
+      if (state[i] != UND) continue;
+      for (int64_t k = G.ptr[i]; k < G.ptr[i + 1]; ++k)
+        if (new_root[G.adj[k]]) {
+          state[i] = NONROOT;
+          break;
+        }
+    }
+    undecided = 0;
+    for (int64_t i = 0; i < n; ++i) undecided += state[i] == UND;
+  }
+  return state;
+}
+
+// |a_ij| if (i, j) is stored, else 0.
+double abs_entry(const HostCSR& A, int64_t i, int32_t j) {
+  const int32_t* b = A.col.data() + A.rowptr[i];
+  const int32_t* e = A.col.data() + A.rowptr[i + 1];
+  const int32_t* p = std::lower_bound(b, e, j);
+  if (p != e && *p == j) return std::fabs(A.val[(size_t)(p - A.col.data())]);
+  return 0.0;
+}
+
+// One synchronous joining sweep (see header comment).
+void join_sweep(const HostCSR& A, const Graph& S, const std::vector<uint8_t>& src_ok,
+                std::vector<int32_t>& agg) {
+  const std::vector<int32_t> before = agg;
+  const int64_t n = A.n_rows;
+  for (int64_t i = 0; i < n; ++i) {
+    if (before[i] >= 0) continue;
+    double best_w = -1.0;
+    int32_t best_c = -1;
+    for (int64_t k = S.ptr[i]; k < S.ptr[i + 1]; ++k) {
+      const int32_t c = S.adj[k];
+      if (!src_ok[c]) continue;
+      const double w = abs_entry(A, i, c);
+      if (best_c < 0 || w > best_w) {  // ascending c: ties keep the smaller
+        best_w = w;
+        best_c = c;
+      }
+    }
+    if (best_c >= 0) agg[i] = before[best_c];
+  }
+}
+
+HostCSR tentative(const std::vector<int32_t>& agg, int64_t n_c) {
+  HostCSR P;
+  P.n_rows = (int64_t)agg.size();
+  P.n_cols = n_c;
+  P.rowptr.resize(agg.size() + 1);
+  P.col.resize(agg.size());
+  P.val.assign(agg.size(), 1.0);
+  for (size_t i = 0; i < agg.size(); ++i) {
+    P.rowptr[i] = (int64_t)i;
+    P.col[i] = agg[i];
+  }
+  P.rowptr[agg.size()] = (int64_t)agg.size();
+  return P;
+}
+
+HostCSR smoothed(const HostCSR& A, const std::vector<uint8_t>& strong,
+                 const std::vector<double>& d, const std::vector<int32_t>& agg,
+                 int64_t n_c) {
+  const int64_t n = A.n_rows;
+  double rho = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k)
+      if (strong[k] || A.col[k] == i) s = s + std::fabs(A.val[k]);
+    const double q = s / std::fabs(d[i]);
+    if (q > rho) rho = q;
+  }
+  const double wp = 4.0 / (3.0 * rho);
+  HostCSR P;
+  P.n_rows = n;
+  P.n_cols = n_c;
+  P.rowptr.assign(1, 0);
+  std::map<int32_t, double> acc;
+  for (int64_t i = 0; i < n; ++i) {
+    acc.clear();
+    for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) {
+      if (!(strong[k] || A.col[k] == i)) continue;
+      const int32_t J = agg[A.col[k]];
+      auto it = acc.find(J);
+      if (it == acc.end())
+        acc.emplace(J, 0.0 + A.val[k]);
+      else
+        it->second = it->second + A.val[k];
+    }
+    const double coef = wp / d[i];
+    for (auto& e : acc) {
+      const double base = (e.first == agg[i]) ? 1.0 : 0.0;
+      P.col.push_back(e.first);
+      P.val.push_back(base - coef * e.second);
+    }
+    P.rowptr.push_back((int64_t)P.col.size());
+  }
+  return P;
+}
+
+HostCSR transpose(const HostCSR& P) {
+  HostCSR R;
+  R.n_rows = P.n_cols;
+  R.n_cols = P.n_rows;
+  R.rowptr.assign((size_t)R.n_rows + 1, 0);
+  for (int32_t c : P.col) R.rowptr[(size_t)c + 1]++;
+  for (int64_t r = 0; r < R.n_rows; ++r) R.rowptr[r + 1] += R.rowptr[r];
+  R.col.resize(P.col.size());
+  R.val.resize(P.val.size());
+  std::vector<int64_t> pos(R.rowptr.begin(), R.rowptr.end() - 1);
+  for (int64_t i = 0; i < P.n_rows; ++i)  // ascending i keeps R's columns sorted
+    for (int64_t k = P.rowptr[i]; k < P.rowptr[i + 1]; ++k) {
+      const int64_t dst = pos[P.col[k]]++;
+      R.col[dst] = (int32_t)i;
+      R.val[dst] = P.val[k];
+    }
+  return R;
+}
+
+// Gustavson product: (XY)[i, J] accumulates x_ik * y_kJ over ascending k,
+// then over Y's row k in ascending J.  Structural pattern, zeros kept.
+HostCSR spgemm(const HostCSR& X, const HostCSR& Y) {
+  HostCSR Z;
+  Z.n_rows = X.n_rows;
+  Z.n_cols = Y.n_cols;
+  Z.rowptr.assign(1, 0);
+  std::vector<double> acc((size_t)Y.n_cols, 0.0);
+  std::vector<int64_t> mark((size_t)Y.n_cols, -1);
+  std::vector<int32_t> cols;
+  for (int64_t i = 0; i < X.n_rows; ++i) {
+    cols.clear();
+    for (int64_t k = X.rowptr[i]; k < X.rowptr[i + 1]; ++k) {
+      const int32_t kk = X.col[k];
+      const double xv = X.val[k];
+      for (int64_t l = Y.rowptr[kk]; l < Y.rowptr[kk + 1]; ++l) {
+        const int32_t J = Y.col[l];
+        const double prod = xv * Y.val[l];
+        if (mark[J] != i) {
+          mark[J] = i;
+          acc[J] = 0.0 + prod;
+          cols.push_back(J);
+        } else {
+          acc[J] = acc[J] + prod;
+        }
+      }
+    }
+    std::sort(cols.begin(), cols.end());
+    for (int32_t J : cols) {
+      Z.col.push_back(J);
+      Z.val.push_back(acc[J]);
+    }
+    Z.rowptr.push_back((int64_t)Z.col.size());
+  }
+  return Z;
+}
+
+void dense_inverse(std::vector<double>& M, int64_t n, std::vector<double>& inv) {
+  // LU with partial pivoting (row interchanges), then solve for the identity.
+  std::vector<int64_t> piv((size_t)n);
+  for (int64_t k = 0; k < n; ++k) {
+    int64_t p = k;
+    double best = std::fabs(M[k * n + k]);
+    for (int64_t r = k + 1; r < n; ++r)
+      if (std::fabs(M[r * n + k]) > best) {
+        best = std::fabs(M[r * n + k]);
+        p = r;
+      }
+    if (!(best > 0.0) || !std::isfinite(best))
+      throw Error(SD_E_BREAKDOWN, "AMG: singular coarsest operator");
+    piv[k] = p;
+    if (p != k)
+      for (int64_t c = 0; c < n; ++c) std::swap(M[k * n + c], M[p * n + c]);
+    const double inv_piv = 1.0 / M[k * n + k];
+    for (int64_t r = k + 1; r < n; ++r) {
+      const double l = M[r * n + k] * inv_piv;
+      M[r * n + k] = l;
+      if (l != 0.0)
+        for (int64_t c = k + 1; c < n; ++c) M[r * n + c] -= l * M[k * n + c];
+    }
+  }
+  inv.assign((size_t)(n * n), 0.0);
+  std::vector<double> y((size_t)n);
+  for (int64_t e = 0; e < n; ++e) {
+    // permuted unit vector
+    for (int64_t r = 0; r < n; ++r) y[r] = (r == e) ? 1.0 : 0.0;
+    for (int64_t k = 0; k < n; ++k)
+      if (piv[k] != k) std::swap(y[k], y[piv[k]]);
+    for (int64_t r = 0; r < n; ++r)
+      for (int64_t c = 0; c < r; ++c) y[r] -= M[r * n + c] * y[c];
+    for (int64_t r = n - 1; r >= 0; --r) {
+      for (int64_t c = r + 1; c < n; ++c) y[r] -= M[r * n + c] * y[c];
+      y[r] /= M[r * n + r];
+    }
+    for (int64_t r = 0; r < n; ++r) inv[r * n + e] = y[r];
+  }
+}
+
+}  // namespace
+
+void amg_setup_host(const HostCSR& A0, const std::vector<int32_t>& comp0, bool singular,
+                    const AMGOpts& o, HostHierarchy& h) {
+  if (o.mis != 1 && o.mis != 2) throw Error(SD_E_INVALID, "AMG: mis must be 1 or 2");
+  if (!(o.theta >= 0.0) || !(o.omega > 0.0) || o.coarse_max < 1 || o.max_levels < 1 ||
+      o.nu_pre < 0 || o.nu_post < 0)
+    throw Error(SD_E_INVALID, "AMG: bad options");
+  h.levels.clear();
+  h.levels.emplace_back();
+  h.levels[0].A = A0;
+  h.levels[0].comp = comp0;
+  while (h.levels.back().A.n_rows > o.coarse_max && (int)h.levels.size() < o.max_levels) {
+    const int lev = (int)h.levels.size() - 1;
+    const HostCSR& A = h.levels.back().A;
+    const std::vector<int32_t>& comp = h.levels.back().comp;
+    const int64_t n = A.n_rows;
+    std::vector<double> d((size_t)n);
+    for (int64_t i = 0; i < n; ++i) d[i] = diag_of(A, i);
+    std::vector<uint8_t> strong = strong_mask(A, comp, d, o.theta);
+    Graph S = symmetric_strength(A, strong);
+    std::vector<int8_t> state = o.mis == 1 ? luby_mis(S, lev) : luby_mis(square(S), lev);
+    std::vector<int32_t> agg((size_t)n, -1);
+    std::vector<int32_t> roots;
+    for (int64_t i = 0; i < n; ++i)
+      if (state[i] == ROOT) {
+        agg[i] = (int32_t)roots.size();
+        roots.push_back((int32_t)i);
+      }
+    std::vector<uint8_t> ok((size_t)n);
+    for (int64_t i = 0; i < n; ++i) ok[i] = state[i] == ROOT;
+    join_sweep(A, S, ok, agg);
+    if (o.mis == 2) {
+      for (int64_t i = 0; i < n; ++i) ok[i] = agg[i] >= 0;
+      join_sweep(A, S, ok, agg);
+    }
+    for (int64_t i = 0; i < n; ++i)
+      if (agg[i] < 0) throw Error(SD_E_INVALID, "AMG: node left without an aggregate");
+    const int64_t n_c = (int64_t)roots.size();
+    if ((double)n < o.min_ratio * (double)n_c) break;
+    HostLevel& L = h.levels.back();
+    L.P = o.smoothed ? smoothed(A, strong, d, agg, n_c) : tentative(agg, n_c);
+    L.R = transpose(L.P);
+    HostCSR AP = spgemm(A, L.P);
+    HostLevel next;
+    next.A = spgemm(L.R, AP);
+    next.comp.resize((size_t)n_c);
+    for (int64_t c = 0; c < n_c; ++c) next.comp[c] = comp[roots[c]];
+    L.agg = std::move(agg);
+    h.levels.push_back(std::move(next));
+  }
+  const HostCSR& Ac = h.levels.back().A;
+  const int64_t nc = Ac.n_rows;
+  if (nc > 4096) throw Error(SD_E_INVALID, "AMG: coarsest level too large for a dense solve");
+  std::vector<double> M((size_t)(nc * nc), 0.0);
+  for (int64_t r = 0; r < nc; ++r)
+    for (int64_t k = Ac.rowptr[r]; k < Ac.rowptr[r + 1]; ++k) M[r * nc + Ac.col[k]] = Ac.val[k];
+  if (singular) {
+    double tr = 0.0;
+    for (int64_t r = 0; r < nc; ++r) tr += M[r * nc + r];
+    const double s = tr / (double)(nc * nc);
+    for (auto& m : M) m = m + s;
+  }
+  dense_inverse(M, nc, h.Ainv);
+  h.n_coarse = nc;
+}
+
+}  // namespace sd

@@ -1,0 +1,283 @@
+// C ABI of the Stokes-Darcy library: handles, error reporting, argument checks.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <memory>
+#include <string>
+
+#include "sd.h"
+#include "solver.h"
+
+struct sd_problem {
+  sd::HostProblem hp;
+  bool device = false;
+  int device_id = 0;
+  sd_allocator alloc{};
+  bool has_alloc = false;
+  hipStream_t stream = nullptr;
+};
+
+struct sd_solver {
+  std::unique_ptr<sd::Solver> s;
+  sd_problem* pb = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+template <typename F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const sd::Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(SD_E_NOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(SD_E_INVALID, e.what());
+  } catch (...) {
+    return fail(SD_E_INVALID, "unknown error");
+  }
+}
+
+int require_device() {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+    (void)hipGetLastError();
+    throw sd::Error(SD_E_DEVICE, "no HIP device available");
+  }
+  int d = 0;
+  SD_HIP(hipGetDevice(&d));
+  return d;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sd_status_string(int status) {
+  switch (status) {
+    case SD_OK: return "SD_OK";
+    case SD_E_INVALID: return "SD_E_INVALID";
+    case SD_E_NOMEM: return "SD_E_NOMEM";
+    case SD_E_DEVICE: return "SD_E_DEVICE";
+    case SD_E_NOCONV: return "SD_E_NOCONV";
+    case SD_E_BREAKDOWN: return "SD_E_BREAKDOWN";
+    case SD_E_BUSY: return "SD_E_BUSY";
+    case SD_E_NOTFOUND: return "SD_E_NOTFOUND";
+    default: return "unknown status";
+  }
+}
+
+const char* sd_last_error(void) { return g_err.c_str(); }
+
+void sd_solver_opts_default(sd_solver_opts* o) {
+  if (!o) return;
+  o->krylov = SD_KRYLOV_FGMRES;
+  o->restart = 30;
+  o->maxit = 1000;
+  o->tol = 1e-8;
+  o->precond = SD_PREC_BGS;
+  o->schur = SD_SCHUR_MASS;
+  o->precision = SD_PRECISION_FP64;
+  o->amg = SD_AMG_SMOOTHED;
+  o->mis = 2;
+  o->theta = 0.08;
+  o->omega = 2.0 / 3.0;
+  o->nu_pre = 2;
+  o->nu_post = 2;
+  o->coarse_max = 256;
+  o->max_levels = 20;
+}
+
+static int assemble_impl(const sd_grid* grid, const sd_physics* phys, const sd_bcs* bcs,
+                         const double* K, const sd_forcing* forcing, bool device,
+                         const sd_allocator* alloc, void* stream, sd_problem** out) {
+  return guarded([&] {
+    if (!out) return fail(SD_E_INVALID, "out is NULL");
+    *out = nullptr;
+    std::unique_ptr<sd_problem> p(new sd_problem());
+    if (device) {
+      p->device_id = require_device();
+      p->device = true;
+      if (alloc && alloc->alloc && alloc->free) {
+        p->alloc = *alloc;
+        p->has_alloc = true;
+      }
+      p->stream = (hipStream_t)stream;
+    }
+    sd::assemble_host(grid, phys, bcs, K, forcing, p->hp);
+    *out = p.release();
+    return (int)SD_OK;
+  });
+}
+
+int sd_assemble(const sd_grid* grid, const sd_physics* phys, const sd_bcs* bcs, const double* K,
+                const sd_forcing* forcing, const sd_allocator* allocator, void* hip_stream,
+                sd_problem** out) {
+  return assemble_impl(grid, phys, bcs, K, forcing, true, allocator, hip_stream, out);
+}
+
+int sd_assemble_host(const sd_grid* grid, const sd_physics* phys, const sd_bcs* bcs,
+                     const double* K, const sd_forcing* forcing, sd_problem** out) {
+  return assemble_impl(grid, phys, bcs, K, forcing, false, nullptr, nullptr, out);
+}
+
+int sd_problem_info(const sd_problem* pb, int64_t* N, int64_t block_off[5], int64_t* nnz) {
+  if (!pb) return fail(SD_E_INVALID, "problem is NULL");
+  const sd::Layout& L = pb->hp.L;
+  if (N) *N = L.N;
+  if (block_off) {
+    block_off[0] = 0;
+    block_off[1] = L.off_v;
+    block_off[2] = L.off_p;
+    block_off[3] = L.off_q;
+    block_off[4] = L.N;
+  }
+  if (nnz) *nnz = pb->hp.A.nnz();
+  return SD_OK;
+}
+
+int sd_problem_csr(const sd_problem* pb, const int64_t** rowptr, const int32_t** col,
+                   const double** val, const double** b) {
+  if (!pb) return fail(SD_E_INVALID, "problem is NULL");
+  if (rowptr) *rowptr = pb->hp.A.rowptr.data();
+  if (col) *col = pb->hp.A.col.data();
+  if (val) *val = pb->hp.A.val.data();
+  if (b) *b = pb->hp.b.data();
+  return SD_OK;
+}
+
+static int setup_impl(sd_problem* pb, const sd_solver_opts* opts, bool device, sd_solver** out) {
+  return guarded([&] {
+    if (!pb || !out) return fail(SD_E_INVALID, "NULL argument");
+    *out = nullptr;
+    if (device && !pb->device)
+      return fail(SD_E_INVALID, "problem was assembled without a device (sd_assemble_host)");
+    std::unique_ptr<sd_solver> s(new sd_solver());
+    s->pb = pb;
+    s->s.reset(new sd::Solver());
+    s->s->setup_host(&pb->hp, opts);
+    if (device) {
+      SD_HIP(hipSetDevice(pb->device_id));
+      s->s->upload(pb->has_alloc ? &pb->alloc : nullptr, pb->stream);
+    }
+    *out = s.release();
+    return (int)SD_OK;
+  });
+}
+
+int sd_setup(sd_problem* pb, const sd_solver_opts* opts, sd_solver** out) {
+  return setup_impl(pb, opts, true, out);
+}
+
+int sd_setup_host(sd_problem* pb, const sd_solver_opts* opts, sd_solver** out) {
+  return setup_impl(pb, opts, false, out);
+}
+
+int sd_solver_levels(const sd_solver* s, int block, int* n_levels) {
+  if (!s || block < 0 || block > 1 || !n_levels) return fail(SD_E_INVALID, "bad argument");
+  *n_levels = (int)s->s->hh[block].levels.size();
+  return SD_OK;
+}
+
+int sd_solver_level_csr(const sd_solver* s, int block, int level, int which, int64_t* n_rows,
+                        int64_t* n_cols, const int64_t** rowptr, const int32_t** col,
+                        const double** val) {
+  if (!s || block < 0 || block > 1) return fail(SD_E_INVALID, "bad argument");
+  const auto& h = s->s->hh[block];
+  if (level < 0 || level >= (int)h.levels.size()) return fail(SD_E_INVALID, "bad level");
+  const sd::HostLevel& L = h.levels[(size_t)level];
+  const sd::HostCSR* M = which == 0 ? &L.A : which == 1 ? &L.P : which == 2 ? &L.R : nullptr;
+  if (!M) return fail(SD_E_INVALID, "which must be 0, 1 or 2");
+  if (which != 0 && level + 1 == (int)h.levels.size())
+    return fail(SD_E_INVALID, "the coarsest level has no transfer operators");
+  if (n_rows) *n_rows = M->n_rows;
+  if (n_cols) *n_cols = M->n_cols;
+  if (rowptr) *rowptr = M->rowptr.data();
+  if (col) *col = M->col.data();
+  if (val) *val = M->val.data();
+  return SD_OK;
+}
+
+int sd_solver_level_agg(const sd_solver* s, int block, int level, const int32_t** agg,
+                        int64_t* n) {
+  if (!s || block < 0 || block > 1) return fail(SD_E_INVALID, "bad argument");
+  const auto& h = s->s->hh[block];
+  if (level < 0 || level + 1 >= (int)h.levels.size())
+    return fail(SD_E_INVALID, "bad level (the coarsest level has no aggregates)");
+  if (agg) *agg = h.levels[(size_t)level].agg.data();
+  if (n) *n = (int64_t)h.levels[(size_t)level].agg.size();
+  return SD_OK;
+}
+
+int sd_solver_coarse_inverse(const sd_solver* s, int block, const double** inv, int64_t* n) {
+  if (!s || block < 0 || block > 1) return fail(SD_E_INVALID, "bad argument");
+  if (inv) *inv = s->s->hh[block].Ainv.data();
+  if (n) *n = s->s->hh[block].n_coarse;
+  return SD_OK;
+}
+
+int sd_solve(sd_solver* s, const double* d_b, double* d_x, int use_x0, sd_stats* stats,
+             void* hip_stream) {
+  return guarded([&] {
+    if (!s) return fail(SD_E_INVALID, "solver is NULL");
+    SD_HIP(hipSetDevice(s->pb->device_id));
+    const int rc = s->s->solve(d_b, d_x, use_x0, stats, (hipStream_t)hip_stream);
+    if (rc == SD_E_NOCONV) g_err = "maximum number of iterations reached";
+    if (rc == SD_E_BREAKDOWN) g_err = "non-finite value or zero pivot in the iteration";
+    return rc;
+  });
+}
+
+int sd_apply_matrix(sd_solver* s, const double* d_x, double* d_y, void* hip_stream) {
+  return guarded([&] {
+    if (!s || !d_x || !d_y) return fail(SD_E_INVALID, "NULL argument");
+    if (!s->s->on_device) return fail(SD_E_INVALID, "solver has no device data");
+    hipStream_t st = (hipStream_t)hip_stream;
+    sd::launch_spmv<double, double, double>(s->s->A64, d_x, d_y, nullptr, st);
+    SD_HIP(hipGetLastError());
+    SD_HIP(hipStreamSynchronize(st));
+    return (int)SD_OK;
+  });
+}
+
+int sd_apply_preconditioner(sd_solver* s, const double* d_r, double* d_z, void* hip_stream) {
+  return guarded([&] {
+    if (!s || !d_r || !d_z) return fail(SD_E_INVALID, "NULL argument");
+    if (!s->s->on_device) return fail(SD_E_INVALID, "solver has no device data");
+    hipStream_t st = (hipStream_t)hip_stream;
+    s->s->prec->apply_precond(*s->s, d_r, d_z, st);
+    SD_HIP(hipGetLastError());
+    SD_HIP(hipStreamSynchronize(st));
+    return (int)SD_OK;
+  });
+}
+
+int sd_apply_vcycle(sd_solver* s, int block, const double* d_b, double* d_x, void* hip_stream) {
+  return guarded([&] {
+    if (!s || !d_b || !d_x || block < 0 || block > 1) return fail(SD_E_INVALID, "bad argument");
+    if (!s->s->on_device) return fail(SD_E_INVALID, "solver has no device data");
+    hipStream_t st = (hipStream_t)hip_stream;
+    s->s->prec->apply_vcycle(*s->s, block, d_b, d_x, st);
+    SD_HIP(hipGetLastError());
+    SD_HIP(hipStreamSynchronize(st));
+    return (int)SD_OK;
+  });
+}
+
+void sd_problem_destroy(sd_problem* pb) { delete pb; }
+
+void sd_solver_destroy(sd_solver* s) {
+  if (!s) return;
+  if (s->pb && s->pb->device) (void)hipSetDevice(s->pb->device_id);
+  delete s;
+}
+
+}  // extern "C"

@@ -1,0 +1,118 @@
+// Device-side data structures and kernel launchers (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sd {
+
+constexpr int kMaxBasis = 32;       // FGMRES basis vectors held in registers (m <= 31)
+constexpr int kBlock = 256;         // threads per workgroup (4 wavefronts)
+constexpr int kDotBlocks = 512;     // workgroups of the fused reduction kernels
+constexpr int kPartStride = kMaxBasis + 4;
+
+// Sliced ELLPACK with 64-row slices (one wavefront per slice).  Entry (r, k)
+// of slice s lives at sptr[s] + 64 k + (r - 64 s); padding has val = 0.
+template <typename T>
+struct Sell {
+  const int* sptr = nullptr;
+  const int* col = nullptr;
+  const T* val = nullptr;
+  int n_rows = 0;
+  int n_cols = 0;
+};
+
+// Solver scalars resident in device memory.
+struct DevState {
+  int j;             // Arnoldi column being built
+  int k;             // columns completed in this cycle
+  int cycle_done;    // iteration kernels return immediately when set
+  int m;             // restart length
+  int converged;     // true residual <= target
+  int breakdown;     // non-finite value seen
+  int iters;         // total Arnoldi steps
+  int pad0;
+  double bnorm, target, cycle_drop, cycle_target, beta;
+  double resblk[4];
+  double sigma[kMaxBasis + 1];       // basis vector k is sigma[k] * V[k]
+  double H[(kMaxBasis + 1) * kMaxBasis];   // column-major, ld = kMaxBasis + 1
+  double cs[kMaxBasis], sn[kMaxBasis], g[kMaxBasis + 1], y[kMaxBasis];
+  double h1[kMaxBasis + 1], h2[kMaxBasis + 1];
+  // BiCGSTAB scalars
+  double rho, alpha, omega, dots[8];
+  unsigned int counter[8];
+};
+
+// Optional per-slot host flags written by the device (mapped pinned memory).
+struct HostFlags {
+  volatile int cycle_done[kMaxBasis + 2];
+  volatile double est[kMaxBasis + 2];
+};
+
+// ---- launchers (stream-ordered, no synchronisation) ----
+template <typename TM, typename TX, typename TY>
+void launch_spmv(const Sell<TM>& A, const TX* x, TY* y, const DevState* gate,
+                 hipStream_t s);
+// r = bscale * b - A x
+template <typename T, typename TB>
+void launch_residual(const Sell<T>& A, const TB* b, const double* bscale, const T* x,
+                     T* r, const DevState* gate, hipStream_t s);
+// x = w .* (bscale b) (one sweep from zero), or two sweeps from zero fused
+template <typename T, typename TB>
+void launch_jacobi_zero(const Sell<T>& A, const T* wd, const TB* b, const double* bscale,
+                        T* x, int two_sweeps, const DevState* gate, hipStream_t s);
+// x_out = x_in + w .* (bscale b - A x_in)
+template <typename T, typename TB>
+void launch_jacobi(const Sell<T>& A, const T* wd, const TB* b, const double* bscale,
+                   const T* x_in, T* x_out, const DevState* gate, hipStream_t s);
+// x += P xc
+template <typename T>
+void launch_prolong(const Sell<T>& P, const T* xc, T* x, const DevState* gate,
+                    hipStream_t s);
+// xc = Ainv bc (FP64 dense)
+template <typename T>
+void launch_coarse(const double* Ainv, int n, const T* bc, T* xc, const DevState* gate,
+                   hipStream_t s);
+// Block sweep: rows of the continuity and porous blocks.
+//   t = bscale * r[row] - (Cf y_v)[row]; rows < n_p: zp = xscale * t; else tq = t
+template <typename T>
+void launch_block_sweep(const Sell<T>& Cf, int n_p, const double* r, const double* bscale,
+                        const T* yv, double xscale, T* zp, T* tq, const DevState* gate,
+                        hipStream_t s);
+// Fused Arnoldi kernels for column j (FP64 basis V, leading dimension ldv):
+//   w = A z, h1 = sigma .* (V^T w)                       (spmv + first dot pass)
+//   w -= V (sigma .* h1), h2 = sigma .* (V^T w)          (second Gram-Schmidt pass)
+//   V[j+1] = w - V (sigma .* h2), ||V[j+1]||, Givens     (update, norm, rotations)
+template <typename TM, typename TZ>
+void launch_arnoldi_j(const Sell<TM>& A, const TZ* z, double* W, const double* V, int64_t ldv,
+                      int j, DevState* st, double* part, hipStream_t s);
+void launch_cgs_dots_j(double* W, const double* V, int64_t ldv, int n, int j, DevState* st,
+                       double* part, hipStream_t s);
+void launch_cgs_norm_j(const double* W, double* V, int64_t ldv, int n, int j, DevState* st,
+                       double* part, HostFlags* hf, hipStream_t s);
+void launch_trisolve(DevState* st, hipStream_t s);
+template <typename TZ>
+void launch_update_x(double* x, const TZ* Z, int64_t ldz, int n, DevState* st,
+                     hipStream_t s);
+// r = b - A x into V[0]; norms; starts a cycle.  x == nullptr means x = 0.
+void launch_restart_residual(const Sell<double>& A, const double* b, const double* x,
+                             double* r, const int64_t* blk_off, DevState* st, double* part,
+                             HostFlags* hf, hipStream_t s);
+// ||b||, sets target = tol ||b||.
+void launch_norm_b(const double* b, int n, double tol, DevState* st, double* part,
+                   hipStream_t s);
+void launch_init_state(DevState* st, int m, double cycle_drop, hipStream_t s);
+void launch_set_cycle_length(DevState* st, int m, hipStream_t s);
+// out = (T)(bscale * b)
+template <typename TB, typename T>
+void launch_scale_convert(const TB* b, const double* bscale, T* out, int n, const DevState* gate,
+                          hipStream_t s);
+
+// Type conversions and small vector helpers.
+template <typename TA, typename TB>
+void launch_convert(const TA* a, TB* b, int n, hipStream_t s);
+template <typename T>
+void launch_fill(T* a, T v, int n, hipStream_t s);
+
+}  // namespace sd

@@ -1,0 +1,679 @@
+// HIP kernels of the coupled Stokes-Darcy solver for gfx950 (CDNA4).
+//
+// Everything here is bandwidth-bound sparse or vector work (about 0.1 - 0.25
+// flop per byte), so the kernels are organised for coalesced HBM traffic:
+//   * sparse matrices are sliced ELLPACK with 64-row slices: one wavefront
+//     owns a slice, lane r owns row r, and entry k of all 64 rows is one
+//     contiguous 256 B (index) + 256/512 B (value) segment;
+//   * workgroup indices are remapped so that each of the 8 XCDs streams a
+//     contiguous range of rows (neighbouring rows share x entries in its L2);
+//   * reductions are two-stage and deterministic: wavefront shuffles, then
+//     LDS across the 4 wavefronts of a workgroup, then per-workgroup partials
+//     summed in a fixed order by the last workgroup to finish (an atomic
+//     ticket), which also performs the scalar follow-up work (Givens
+//     rotations, scale factors), saving a launch per reduction.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <type_traits>
+
+#include "device.h"
+
+namespace sd {
+
+namespace {
+
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = b & 7, k = b >> 3;
+  return x * q + (x < r ? x : r) + k;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <typename TM, typename TX>
+__device__ __forceinline__ TM sell_dot(const Sell<TM>& A, const TX* __restrict__ x, int row) {
+  const int s = row >> 6;
+  const int beg = A.sptr[s] + (row & 63);
+  const int end = A.sptr[s + 1];
+  TM acc = 0;
+#pragma unroll 4
+  for (int e = beg; e < end; e += 64) acc += A.val[e] * (TM)x[A.col[e]];
+  return acc;
+}
+
+__device__ __forceinline__ double scale_of(const double* s) { return s ? *s : 1.0; }
+
+template <typename T, typename TB>
+__device__ __forceinline__ T load_b(const TB* __restrict__ b, double s, int i) {
+  return (T)((double)b[i] * s);
+}
+
+// Sum the first nv entries of acc over the workgroup into part[block].
+template <int NV>
+__device__ __forceinline__ void block_partials(const double (&acc)[NV], int nv, double* part) {
+  __shared__ double red[kBlock / 64][NV];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    if (k < nv) {
+      const double v = wave_sum(acc[k]);
+      if (lane == 0) red[wave][k] = v;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nv) {
+    const int k = threadIdx.x;
+    part[(size_t)blockIdx.x * kPartStride + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+    __threadfence();
+  }
+  __syncthreads();
+}
+
+// True in exactly one workgroup: the last to arrive at the ticket.
+__device__ __forceinline__ bool last_block(unsigned int* counter) {
+  __shared__ int s_last;
+  if (threadIdx.x == 0) {
+    const unsigned prev = atomicAdd(counter, 1u);
+    s_last = prev == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!s_last) return false;
+  __threadfence();
+  return true;
+}
+
+// In the last workgroup: out[k] = sum over workgroups of part[b][k], k < nv,
+// in a fixed order; result left in out_sh (shared) for thread use.
+template <int NV>
+__device__ __forceinline__ void final_sums(const double* part, int nb, int nv, double* out_sh) {
+  __shared__ double red[kBlock / 64][NV];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kBlock) {
+    const double* p = part + (size_t)b * kPartStride;
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+      if (k < nv) acc[k] += p[k];
+  }
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    if (k < nv) {
+      const double v = wave_sum(acc[k]);
+      if (lane == 0) red[wave][k] = v;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nv) {
+    const int k = threadIdx.x;
+    out_sh[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+  }
+  __syncthreads();
+}
+
+inline int blocks_for(int n) { return (n + kBlock - 1) / kBlock; }
+
+inline int dot_blocks(int n) {
+  const int nb = (n + kBlock - 1) / kBlock;
+  return nb < kDotBlocks ? (nb > 0 ? nb : 1) : kDotBlocks;
+}
+
+// ----------------------------------------------------------------- kernels
+
+template <typename TM, typename TX, typename TY>
+__global__ __launch_bounds__(kBlock) void k_spmv(Sell<TM> A, const TX* __restrict__ x,
+                                                 TY* __restrict__ y, const DevState* gate) {
+  if (gate && gate->cycle_done) return;
+  const int row = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (row >= A.n_rows) return;
+  y[row] = (TY)sell_dot(A, x, row);
+}
+
+template <typename T, typename TB>
+__global__ __launch_bounds__(kBlock) void k_residual(Sell<T> A, const TB* __restrict__ b,
+                                                     const double* bscale,
+                                                     const T* __restrict__ x,
+                                                     T* __restrict__ r, const DevState* gate) {
+  if (gate && gate->cycle_done) return;
+  const int row = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (row >= A.n_rows) return;
+  const T bv = load_b<T>(b, scale_of(bscale), row);
+  r[row] = bv - sell_dot(A, x, row);
+}
+
+template <typename T, typename TB>
+__global__ __launch_bounds__(kBlock) void k_jacobi_zero(Sell<T> A, const T* __restrict__ wd,
+                                                        const TB* __restrict__ b,
+                                                        const double* bscale,
+                                                        T* __restrict__ x, int two,
+                                                        const DevState* gate) {
+  if (gate && gate->cycle_done) return;
+  const int row = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (row >= A.n_rows) return;
+  const double s = scale_of(bscale);
+  const T bi = load_b<T>(b, s, row);
+  const T x1 = wd[row] * bi;
+  if (!two) {
+    x[row] = x1;
+    return;
+  }
+  // second sweep from x1 = w .* b, computed on the fly at the neighbours
+  const int sl = row >> 6;
+  const int beg = A.sptr[sl] + (row & 63);
+  const int end = A.sptr[sl + 1];
+  T acc = 0;
+#pragma unroll 4
+  for (int e = beg; e < end; e += 64) {
+    const int c = A.col[e];
+    acc += A.val[e] * (wd[c] * load_b<T>(b, s, c));
+  }
+  x[row] = x1 + wd[row] * (bi - acc);
+}
+
+template <typename T, typename TB>
+__global__ __launch_bounds__(kBlock) void k_jacobi(Sell<T> A, const T* __restrict__ wd,
+                                                   const TB* __restrict__ b,
+                                                   const double* bscale,
+                                                   const T* __restrict__ xin,
+                                                   T* __restrict__ xout,
+                                                   const DevState* gate) {
+  if (gate && gate->cycle_done) return;
+  const int row = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (row >= A.n_rows) return;
+  const T bi = load_b<T>(b, scale_of(bscale), row);
+  xout[row] = xin[row] + wd[row] * (bi - sell_dot(A, xin, row));
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong(Sell<T> P, const T* __restrict__ xc,
+                                                    T* __restrict__ x, const DevState* gate) {
+  if (gate && gate->cycle_done) return;
+  const int row = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (row >= P.n_rows) return;
+  x[row] += sell_dot(P, xc, row);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_coarse(const double* __restrict__ Ainv, int n,
+                                                   const T* __restrict__ bc,
+                                                   T* __restrict__ xc, const DevState* gate) {
+  if (gate && gate->cycle_done) return;
+  const int w = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (w >= n) return;
+  const double* a = Ainv + (size_t)w * n;
+  double acc = 0.0;
+  for (int c = lane; c < n; c += 64) acc += a[c] * (double)bc[c];
+  acc = wave_sum(acc);
+  if (lane == 0) xc[w] = (T)acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_block_sweep(Sell<T> Cf, int n_p,
+                                                        const double* __restrict__ r,
+                                                        const double* bscale,
+                                                        const T* __restrict__ yv, double xscale,
+                                                        T* __restrict__ zp, T* __restrict__ tq,
+                                                        const DevState* gate) {
+  if (gate && gate->cycle_done) return;
+  const int row = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (row >= Cf.n_rows) return;
+  const T t = load_b<T>(r, scale_of(bscale), row) - sell_dot(Cf, yv, row);
+  if (row < n_p)
+    zp[row] = (T)xscale * t;
+  else
+    tq[row - n_p] = t;
+}
+
+template <typename TM, typename TZ>
+__global__ __launch_bounds__(kBlock) void k_arnoldi_spmv_dots(Sell<TM> A, const TZ* __restrict__ z,
+                                                              double* __restrict__ W,
+                                                              const double* __restrict__ V,
+                                                              int64_t ldv, int j, int R,
+                                                              DevState* st, double* part) {
+  if (st->cycle_done) return;
+  const int n = A.n_rows;
+  const int G = gridDim.x * kBlock;
+  const int gtid = blockIdx.x * kBlock + threadIdx.x;
+  double acc[kMaxBasis];
+#pragma unroll
+  for (int k = 0; k < kMaxBasis; ++k) acc[k] = 0.0;
+  for (int t = 0; t < R; ++t) {
+    const int row = gtid + t * G;
+    if (row < n) {
+      const double w = (double)sell_dot(A, z, row);
+      W[row] = w;
+#pragma unroll
+      for (int k = 0; k < kMaxBasis; ++k)
+        if (k <= j) acc[k] += V[(size_t)k * ldv + row] * w;
+    }
+  }
+  block_partials<kMaxBasis>(acc, j + 1, part);
+  if (!last_block(&st->counter[0])) return;
+  __shared__ double sums[kMaxBasis];
+  final_sums<kMaxBasis>(part, gridDim.x, j + 1, sums);
+  if ((int)threadIdx.x <= j) st->h1[threadIdx.x] = st->sigma[threadIdx.x] * sums[threadIdx.x];
+  if (threadIdx.x == 0) st->counter[0] = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cgs_axpy_dots(double* __restrict__ W,
+                                                          const double* __restrict__ V,
+                                                          int64_t ldv, int n, int j, int R,
+                                                          DevState* st, double* part) {
+  if (st->cycle_done) return;
+  __shared__ double c[kMaxBasis];
+  if ((int)threadIdx.x <= j) c[threadIdx.x] = st->h1[threadIdx.x] * st->sigma[threadIdx.x];
+  __syncthreads();
+  const int G = gridDim.x * kBlock;
+  const int gtid = blockIdx.x * kBlock + threadIdx.x;
+  double acc[kMaxBasis];
+#pragma unroll
+  for (int k = 0; k < kMaxBasis; ++k) acc[k] = 0.0;
+  for (int t = 0; t < R; ++t) {
+    const int row = gtid + t * G;
+    if (row < n) {
+      double v[kMaxBasis];
+#pragma unroll
+      for (int k = 0; k < kMaxBasis; ++k) v[k] = (k <= j) ? V[(size_t)k * ldv + row] : 0.0;
+      double w = W[row];
+#pragma unroll
+      for (int k = 0; k < kMaxBasis; ++k)
+        if (k <= j) w -= c[k] * v[k];
+      W[row] = w;
+#pragma unroll
+      for (int k = 0; k < kMaxBasis; ++k)
+        if (k <= j) acc[k] += v[k] * w;
+    }
+  }
+  block_partials<kMaxBasis>(acc, j + 1, part);
+  if (!last_block(&st->counter[1])) return;
+  __shared__ double sums[kMaxBasis];
+  final_sums<kMaxBasis>(part, gridDim.x, j + 1, sums);
+  if ((int)threadIdx.x <= j) st->h2[threadIdx.x] = st->sigma[threadIdx.x] * sums[threadIdx.x];
+  if (threadIdx.x == 0) st->counter[1] = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cgs_axpy_norm(const double* __restrict__ W,
+                                                          double* __restrict__ V, int64_t ldv,
+                                                          int n, int j, int R, DevState* st,
+                                                          double* part, HostFlags* hf) {
+  if (st->cycle_done) return;
+  __shared__ double c[kMaxBasis];
+  if ((int)threadIdx.x <= j) c[threadIdx.x] = st->h2[threadIdx.x] * st->sigma[threadIdx.x];
+  __syncthreads();
+  const int G = gridDim.x * kBlock;
+  const int gtid = blockIdx.x * kBlock + threadIdx.x;
+  double acc[1] = {0.0};
+  double* vn = V + (size_t)(j + 1) * ldv;
+  for (int t = 0; t < R; ++t) {
+    const int row = gtid + t * G;
+    if (row < n) {
+      double w = W[row];
+#pragma unroll
+      for (int k = 0; k < kMaxBasis; ++k)
+        if (k <= j) w -= c[k] * V[(size_t)k * ldv + row];
+      vn[row] = w;
+      acc[0] += w * w;
+    }
+  }
+  block_partials<1>(acc, 1, part);
+  if (!last_block(&st->counter[2])) return;
+  __shared__ double sums[1];
+  final_sums<1>(part, gridDim.x, 1, sums);
+  if (threadIdx.x == 0) {
+    const int ld = kMaxBasis + 1;
+    double* H = st->H + (size_t)j * ld;
+    const double hn = sqrt(sums[0]);
+    for (int i = 0; i <= j; ++i) H[i] = st->h1[i] + st->h2[i];
+    H[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+      const double t = st->cs[i] * H[i] + st->sn[i] * H[i + 1];
+      H[i + 1] = -st->sn[i] * H[i] + st->cs[i] * H[i + 1];
+      H[i] = t;
+    }
+    const double d = hypot(H[j], H[j + 1]);
+    int bad = !(d > 0.0) || !isfinite(d);
+    const double cj = bad ? 1.0 : H[j] / d;
+    const double sj = bad ? 0.0 : H[j + 1] / d;
+    st->cs[j] = cj;
+    st->sn[j] = sj;
+    H[j] = bad ? H[j] : d;
+    H[j + 1] = 0.0;
+    st->g[j + 1] = -sj * st->g[j];
+    st->g[j] = cj * st->g[j];
+    const double est = fabs(st->g[j + 1]);
+    bad = bad || !isfinite(est);
+    st->sigma[j + 1] = 1.0 / hn;
+    st->k = j + 1;
+    st->j = j + 1;
+    st->iters += 1;
+    if (bad) st->breakdown = 1;
+    const int done = bad || !(hn > 0.0) || est <= st->cycle_target || (j + 1) >= st->m;
+    st->cycle_done = done;
+    if (hf) {
+      hf->est[j] = est;
+      hf->cycle_done[j] = done;
+      __threadfence_system();
+    }
+    st->counter[2] = 0;
+  }
+}
+
+__global__ void k_trisolve(DevState* st) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int k = st->k;
+  const int ld = kMaxBasis + 1;
+  for (int i = k - 1; i >= 0; --i) {
+    double s = st->g[i];
+    for (int l = i + 1; l < k; ++l) s -= st->H[(size_t)l * ld + i] * st->y[l];
+    st->y[i] = s / st->H[(size_t)i * ld + i];
+  }
+}
+
+template <typename TZ>
+__global__ __launch_bounds__(kBlock) void k_update_x(double* __restrict__ x,
+                                                     const TZ* __restrict__ Z, int64_t ldz,
+                                                     int n, const DevState* st) {
+  const int row = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (row >= n) return;
+  const int k = st->k;
+  double s = x[row];
+  for (int l = 0; l < k; ++l) s += st->y[l] * (double)Z[(size_t)l * ldz + row];
+  x[row] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_restart_residual(Sell<double> A,
+                                                             const double* __restrict__ b,
+                                                             const double* __restrict__ x,
+                                                             double* __restrict__ r, int off_p,
+                                                             int off_q, int R, DevState* st,
+                                                             double* part, HostFlags* hf) {
+  const int n = A.n_rows;
+  const int G = gridDim.x * kBlock;
+  const int gtid = blockIdx.x * kBlock + threadIdx.x;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int t = 0; t < R; ++t) {
+    const int row = gtid + t * G;
+    if (row < n) {
+      const double rv = b[row] - (x ? sell_dot(A, x, row) : 0.0);
+      r[row] = rv;
+      const int blk = row < off_p ? 0 : (row < off_q ? 1 : 2);
+      acc[blk] += rv * rv;
+    }
+  }
+  block_partials<3>(acc, 3, part);
+  if (!last_block(&st->counter[3])) return;
+  __shared__ double sums[3];
+  final_sums<3>(part, gridDim.x, 3, sums);
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 3; ++k) st->resblk[k] = sums[k];
+    const double beta = sqrt((sums[0] + sums[1]) + sums[2]);
+    st->beta = beta;
+    st->sigma[0] = 1.0 / beta;
+    st->g[0] = beta;
+    st->j = 0;
+    st->k = 0;
+    const int fin = isfinite(beta);
+    const int conv = fin && beta <= st->target;
+    st->converged = conv;
+    if (!fin) st->breakdown = 1;
+    st->cycle_done = conv || !fin || !(beta > 0.0);
+    const double ct = st->cycle_drop * beta;
+    st->cycle_target = ct > st->target ? ct : st->target;
+    if (hf) {
+      hf->est[kMaxBasis + 1] = beta;
+      __threadfence_system();
+    }
+    st->counter[3] = 0;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_norm_b(const double* __restrict__ b, int n, int R,
+                                                   double tol, DevState* st, double* part) {
+  const int G = gridDim.x * kBlock;
+  const int gtid = blockIdx.x * kBlock + threadIdx.x;
+  double acc[1] = {0.0};
+  for (int t = 0; t < R; ++t) {
+    const int row = gtid + t * G;
+    if (row < n) acc[0] += b[row] * b[row];
+  }
+  block_partials<1>(acc, 1, part);
+  if (!last_block(&st->counter[4])) return;
+  __shared__ double sums[1];
+  final_sums<1>(part, gridDim.x, 1, sums);
+  if (threadIdx.x == 0) {
+    st->bnorm = sqrt(sums[0]);
+    st->target = tol * st->bnorm;
+    st->counter[4] = 0;
+  }
+}
+
+__global__ void k_init_state(DevState* st, int m, double drop) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  st->j = 0;
+  st->k = 0;
+  st->cycle_done = 0;
+  st->m = m;
+  st->converged = 0;
+  st->breakdown = 0;
+  st->iters = 0;
+  st->cycle_drop = drop;
+}
+
+__global__ void k_set_cycle_length(DevState* st, int m) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) st->m = m;
+}
+
+template <typename TB, typename T>
+__global__ __launch_bounds__(kBlock) void k_scale_convert(const TB* __restrict__ b,
+                                                          const double* bscale,
+                                                          T* __restrict__ out, int n,
+                                                          const DevState* gate) {
+  if (gate && gate->cycle_done) return;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) out[i] = load_b<T>(b, scale_of(bscale), i);
+}
+
+template <typename TA, typename TB>
+__global__ __launch_bounds__(kBlock) void k_convert(const TA* __restrict__ a, TB* __restrict__ b,
+                                                    int n) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) b[i] = (TB)a[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill(T* __restrict__ a, T v, int n) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+
+template <typename TM, typename TX, typename TY>
+void launch_spmv(const Sell<TM>& A, const TX* x, TY* y, const DevState* gate, hipStream_t s) {
+  if (A.n_rows <= 0) return;
+  k_spmv<TM, TX, TY><<<blocks_for(A.n_rows), kBlock, 0, s>>>(A, x, y, gate);
+}
+
+template <typename T, typename TB>
+void launch_residual(const Sell<T>& A, const TB* b, const double* bscale, const T* x, T* r,
+                     const DevState* gate, hipStream_t s) {
+  if (A.n_rows <= 0) return;
+  k_residual<T, TB><<<blocks_for(A.n_rows), kBlock, 0, s>>>(A, b, bscale, x, r, gate);
+}
+
+template <typename T, typename TB>
+void launch_jacobi_zero(const Sell<T>& A, const T* wd, const TB* b, const double* bscale, T* x,
+                        int two, const DevState* gate, hipStream_t s) {
+  if (A.n_rows <= 0) return;
+  k_jacobi_zero<T, TB><<<blocks_for(A.n_rows), kBlock, 0, s>>>(A, wd, b, bscale, x, two, gate);
+}
+
+template <typename T, typename TB>
+void launch_jacobi(const Sell<T>& A, const T* wd, const TB* b, const double* bscale,
+                   const T* x_in, T* x_out, const DevState* gate, hipStream_t s) {
+  if (A.n_rows <= 0) return;
+  k_jacobi<T, TB><<<blocks_for(A.n_rows), kBlock, 0, s>>>(A, wd, b, bscale, x_in, x_out, gate);
+}
+
+template <typename T>
+void launch_prolong(const Sell<T>& P, const T* xc, T* x, const DevState* gate, hipStream_t s) {
+  if (P.n_rows <= 0) return;
+  k_prolong<T><<<blocks_for(P.n_rows), kBlock, 0, s>>>(P, xc, x, gate);
+}
+
+template <typename T>
+void launch_coarse(const double* Ainv, int n, const T* bc, T* xc, const DevState* gate,
+                   hipStream_t s) {
+  if (n <= 0) return;
+  k_coarse<T><<<(n * 64 + kBlock - 1) / kBlock, kBlock, 0, s>>>(Ainv, n, bc, xc, gate);
+}
+
+template <typename T>
+void launch_block_sweep(const Sell<T>& Cf, int n_p, const double* r, const double* bscale,
+                        const T* yv, double xscale, T* zp, T* tq, const DevState* gate,
+                        hipStream_t s) {
+  if (Cf.n_rows <= 0) return;
+  k_block_sweep<T><<<blocks_for(Cf.n_rows), kBlock, 0, s>>>(Cf, n_p, r, bscale, yv, xscale, zp,
+                                                            tq, gate);
+}
+
+// Explicit-j variants used by the solver.
+template <typename TM, typename TZ>
+void launch_arnoldi_j(const Sell<TM>& A, const TZ* z, double* W, const double* V, int64_t ldv,
+                      int j, DevState* st, double* part, hipStream_t s) {
+  const int n = A.n_rows;
+  const int nb = dot_blocks(n);
+  const int R = (n + nb * kBlock - 1) / (nb * kBlock);
+  k_arnoldi_spmv_dots<TM, TZ><<<nb, kBlock, 0, s>>>(A, z, W, V, ldv, j, R, st, part);
+}
+
+void launch_cgs_dots_j(double* W, const double* V, int64_t ldv, int n, int j, DevState* st,
+                       double* part, hipStream_t s) {
+  const int nb = dot_blocks(n);
+  const int R = (n + nb * kBlock - 1) / (nb * kBlock);
+  k_cgs_axpy_dots<<<nb, kBlock, 0, s>>>(W, V, ldv, n, j, R, st, part);
+}
+
+void launch_cgs_norm_j(const double* W, double* V, int64_t ldv, int n, int j, DevState* st,
+                       double* part, HostFlags* hf, hipStream_t s) {
+  const int nb = dot_blocks(n);
+  const int R = (n + nb * kBlock - 1) / (nb * kBlock);
+  k_cgs_axpy_norm<<<nb, kBlock, 0, s>>>(W, V, ldv, n, j, R, st, part, hf);
+}
+
+
+void launch_trisolve(DevState* st, hipStream_t s) { k_trisolve<<<1, 64, 0, s>>>(st); }
+
+template <typename TZ>
+void launch_update_x(double* x, const TZ* Z, int64_t ldz, int n, DevState* st, hipStream_t s) {
+  if (n <= 0) return;
+  k_update_x<TZ><<<blocks_for(n), kBlock, 0, s>>>(x, Z, ldz, n, st);
+}
+
+void launch_restart_residual(const Sell<double>& A, const double* b, const double* x, double* r,
+                             const int64_t* blk_off, DevState* st, double* part, HostFlags* hf,
+                             hipStream_t s) {
+  const int n = A.n_rows;
+  const int nb = dot_blocks(n);
+  const int R = (n + nb * kBlock - 1) / (nb * kBlock);
+  k_restart_residual<<<nb, kBlock, 0, s>>>(A, b, x, r, (int)blk_off[2], (int)blk_off[3], R, st,
+                                            part, hf);
+}
+
+void launch_norm_b(const double* b, int n, double tol, DevState* st, double* part,
+                   hipStream_t s) {
+  const int nb = dot_blocks(n);
+  const int R = (n + nb * kBlock - 1) / (nb * kBlock);
+  k_norm_b<<<nb, kBlock, 0, s>>>(b, n, R, tol, st, part);
+}
+
+void launch_init_state(DevState* st, int m, double cycle_drop, hipStream_t s) {
+  k_init_state<<<1, 64, 0, s>>>(st, m, cycle_drop);
+}
+
+void launch_set_cycle_length(DevState* st, int m, hipStream_t s) {
+  k_set_cycle_length<<<1, 64, 0, s>>>(st, m);
+}
+
+template <typename TB, typename T>
+void launch_scale_convert(const TB* b, const double* bscale, T* out, int n, const DevState* gate,
+                          hipStream_t s) {
+  if (n <= 0) return;
+  k_scale_convert<TB, T><<<blocks_for(n), kBlock, 0, s>>>(b, bscale, out, n, gate);
+}
+
+template <typename TA, typename TB>
+void launch_convert(const TA* a, TB* b, int n, hipStream_t s) {
+  if (n <= 0) return;
+  k_convert<TA, TB><<<blocks_for(n), kBlock, 0, s>>>(a, b, n);
+}
+
+template <typename T>
+void launch_fill(T* a, T v, int n, hipStream_t s) {
+  if (n <= 0) return;
+  k_fill<T><<<blocks_for(n), kBlock, 0, s>>>(a, v, n);
+}
+
+// ------------------------------------------------------- instantiations
+#define SD_INST_T(T, TB)                                                                      \
+  template void launch_residual<T, TB>(const Sell<T>&, const TB*, const double*, const T*, T*, \
+                                       const DevState*, hipStream_t);                         \
+  template void launch_jacobi_zero<T, TB>(const Sell<T>&, const T*, const TB*, const double*, \
+                                          T*, int, const DevState*, hipStream_t);              \
+  template void launch_jacobi<T, TB>(const Sell<T>&, const T*, const TB*, const double*,      \
+                                     const T*, T*, const DevState*, hipStream_t);
+
+SD_INST_T(double, double)
+SD_INST_T(float, double)
+SD_INST_T(float, float)
+
+template void launch_spmv<double, double, double>(const Sell<double>&, const double*, double*,
+                                                  const DevState*, hipStream_t);
+template void launch_spmv<float, float, float>(const Sell<float>&, const float*, float*,
+                                               const DevState*, hipStream_t);
+template void launch_prolong<double>(const Sell<double>&, const double*, double*,
+                                     const DevState*, hipStream_t);
+template void launch_prolong<float>(const Sell<float>&, const float*, float*, const DevState*,
+                                    hipStream_t);
+template void launch_coarse<double>(const double*, int, const double*, double*,
+                                    const DevState*, hipStream_t);
+template void launch_coarse<float>(const double*, int, const float*, float*, const DevState*,
+                                   hipStream_t);
+template void launch_block_sweep<double>(const Sell<double>&, int, const double*,
+                                         const double*, const double*, double, double*,
+                                         double*, const DevState*, hipStream_t);
+template void launch_block_sweep<float>(const Sell<float>&, int, const double*, const double*,
+                                        const float*, double, float*, float*, const DevState*,
+                                        hipStream_t);
+template void launch_arnoldi_j<double, double>(const Sell<double>&, const double*, double*,
+                                               const double*, int64_t, int, DevState*, double*,
+                                               hipStream_t);
+template void launch_arnoldi_j<float, float>(const Sell<float>&, const float*, double*,
+                                             const double*, int64_t, int, DevState*, double*,
+                                             hipStream_t);
+template void launch_update_x<double>(double*, const double*, int64_t, int, DevState*,
+                                      hipStream_t);
+template void launch_update_x<float>(double*, const float*, int64_t, int, DevState*,
+                                     hipStream_t);
+template void launch_scale_convert<double, double>(const double*, const double*, double*, int,
+                                                   const DevState*, hipStream_t);
+template void launch_scale_convert<double, float>(const double*, const double*, float*, int,
+                                                  const DevState*, hipStream_t);
+template void launch_scale_convert<float, float>(const float*, const double*, float*, int,
+                                                 const DevState*, hipStream_t);
+template void launch_convert<float, float>(const float*, float*, int, hipStream_t);
+template void launch_convert<double, float>(const double*, float*, int, hipStream_t);
+template void launch_convert<float, double>(const float*, double*, int, hipStream_t);
+template void launch_convert<double, double>(const double*, double*, int, hipStream_t);
+template void launch_fill<double>(double*, double, int, hipStream_t);
+template void launch_fill<float>(float*, float, int, hipStream_t);
+
+}  // namespace sd

@@ -1,0 +1,91 @@
+// Internal declarations of the Stokes-Darcy library (host side).
+#pragma once
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "sd.h"
+
+namespace sd {
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+// Compressed sparse rows with ascending column indices in every row.
+struct HostCSR {
+  int64_t n_rows = 0, n_cols = 0;
+  std::vector<int64_t> rowptr;
+  std::vector<int32_t> col;
+  std::vector<double> val;
+  int64_t nnz() const { return (int64_t)col.size(); }
+};
+
+// Unknown numbering of the pressure-velocity block form.
+struct Layout {
+  int nx = 0, ny = 0, nyp = 0, nux = 0;
+  int64_t off_v = 0, off_p = 0, off_q = 0, N = 0;
+  int64_t u(int i, int j) const { return (int64_t)j * nux + (i - 1); }
+  int64_t v(int i, int j) const { return off_v + (int64_t)j * nx + i; }
+  int64_t p(int i, int j) const { return off_p + (int64_t)j * nx + i; }
+  int64_t q(int i, int k) const { return off_q + (int64_t)k * nx + i; }
+};
+
+struct HostProblem {
+  sd_grid grid{};
+  sd_physics phys{};
+  int bc[6] = {0, 0, 0, 0, 0, 0};
+  Layout L;
+  HostCSR A;
+  std::vector<double> b;
+  bool pm_singular = false;
+};
+
+void assemble_host(const sd_grid* g, const sd_physics* ph, const sd_bcs* bcs,
+                   const double* K, const sd_forcing* f, HostProblem& out);
+
+HostCSR extract_block(const HostCSR& A, int64_t r0, int64_t r1, int64_t c0,
+                      int64_t c1);
+
+// D~ = D' - C1' diag(V)^-1 B1' on the porous block.
+HostCSR darcy_interface_block(const HostCSR& D, const HostCSR& C1,
+                              const HostCSR& B1, const HostCSR& V);
+
+struct AMGOpts {
+  double theta = 0.08, omega = 2.0 / 3.0, min_ratio = 1.2;
+  int nu_pre = 2, nu_post = 2, coarse_max = 256, max_levels = 20;
+  bool smoothed = true;
+  int mis = 2;
+};
+
+struct HostLevel {
+  HostCSR A, P, R;             // P, R empty on the coarsest level
+  std::vector<int32_t> agg;    // empty on the coarsest level
+  std::vector<int32_t> comp;
+};
+
+struct HostHierarchy {
+  std::vector<HostLevel> levels;
+  std::vector<double> Ainv;    // dense row-major inverse of the coarsest A
+  int64_t n_coarse = 0;
+};
+
+void amg_setup_host(const HostCSR& A, const std::vector<int32_t>& comp,
+                    bool singular, const AMGOpts& o, HostHierarchy& h);
+
+// 32-bit finaliser of MurmurHash3 (public domain).
+inline uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
+}
+
+double wall_time();
+
+}  // namespace sd

@@ -1,0 +1,445 @@
+// Host orchestration of the device solve: SELL upload, AMG hierarchies, the
+// block preconditioner (Sec. 4) with V-cycle sub-solves (Sec. 5), and the
+// flexible GMRES driver with FP64 restart residuals.
+#include "solver.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <type_traits>
+
+namespace sd {
+
+double wall_time() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// ------------------------------------------------------------------ memory
+DeviceMem::~DeviceMem() {
+  for (void* p : ptrs_) {
+    if (has_)
+      alloc_.free(p, alloc_.ctx, stream_);
+    else
+      (void)hipFree(p);
+  }
+}
+
+void* DeviceMem::get(size_t bytes) {
+  bytes = (bytes + 255) & ~(size_t)255;
+  void* p = nullptr;
+  if (has_) {
+    p = alloc_.alloc(bytes, alloc_.ctx, stream_);
+    if (!p) throw Error(SD_E_NOMEM, "device allocation failed (allocator callback)");
+  } else {
+    if (hipMalloc(&p, bytes) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      throw Error(SD_E_NOMEM, "hipMalloc failed");
+    }
+  }
+  ptrs_.push_back(p);
+  total_ += bytes;
+  return p;
+}
+
+// -------------------------------------------------------------------- SELL
+template <typename T>
+Sell<T> upload_sell(const HostCSR& A, DeviceMem& mem, hipStream_t s) {
+  const int64_t n = A.n_rows;
+  const int64_t ns = (n + 63) / 64;
+  std::vector<int> sptr((size_t)ns + 1, 0);
+  int64_t tot = 0;
+  for (int64_t sl = 0; sl < ns; ++sl) {
+    int64_t w = 0;
+    for (int64_t r = sl * 64; r < std::min(n, sl * 64 + 64); ++r)
+      w = std::max(w, A.rowptr[r + 1] - A.rowptr[r]);
+    tot += 64 * w;
+    if (tot >= ((int64_t)1 << 31)) throw Error(SD_E_INVALID, "matrix too large for SELL-64");
+    sptr[sl + 1] = (int)tot;
+  }
+  std::vector<int> col((size_t)std::max<int64_t>(tot, 1), 0);
+  std::vector<T> val((size_t)std::max<int64_t>(tot, 1), (T)0);
+  for (int64_t sl = 0; sl < ns; ++sl) {
+    const int64_t w = (sptr[sl + 1] - sptr[sl]) / 64;
+    for (int64_t lane = 0; lane < 64; ++lane) {
+      const int64_t r = sl * 64 + lane;
+      int64_t len = 0, beg = 0;
+      if (r < n) {
+        beg = A.rowptr[r];
+        len = A.rowptr[r + 1] - beg;
+      }
+      for (int64_t k = 0; k < w; ++k) {
+        const int64_t e = sptr[sl] + 64 * k + lane;
+        if (k < len) {
+          col[e] = A.col[beg + k];
+          val[e] = (T)A.val[beg + k];
+        } else {
+          col[e] = len > 0 ? A.col[beg + len - 1] : 0;
+          val[e] = (T)0;
+        }
+      }
+    }
+  }
+  Sell<T> d;
+  d.n_rows = (int)n;
+  d.n_cols = (int)A.n_cols;
+  int* dsp = mem.array<int>(sptr.size());
+  int* dcol = mem.array<int>(col.size());
+  T* dval = mem.array<T>(val.size());
+  SD_HIP(hipMemcpyAsync(dsp, sptr.data(), sptr.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  SD_HIP(hipMemcpyAsync(dcol, col.data(), col.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  SD_HIP(hipMemcpyAsync(dval, val.data(), val.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  SD_HIP(hipStreamSynchronize(s));
+  d.sptr = dsp;
+  d.col = dcol;
+  d.val = dval;
+  return d;
+}
+
+template Sell<double> upload_sell<double>(const HostCSR&, DeviceMem&, hipStream_t);
+template Sell<float> upload_sell<float>(const HostCSR&, DeviceMem&, hipStream_t);
+
+// ------------------------------------------------------------ host setup
+static double diag_at(const HostCSR& A, int64_t r) {
+  for (int64_t k = A.rowptr[r]; k < A.rowptr[r + 1]; ++k)
+    if (A.col[k] == r) return A.val[k];
+  throw Error(SD_E_INVALID, "missing diagonal entry");
+}
+
+void Solver::setup_host(HostProblem* p, const sd_solver_opts* o) {
+  const double t0 = wall_time();
+  pb = p;
+  sd_solver_opts d;
+  sd_solver_opts_default(&d);
+  opts.o = o ? *o : d;
+  const sd_solver_opts& so = opts.o;
+  if (so.restart < 1 || so.restart > kMaxBasis - 1)
+    throw Error(SD_E_INVALID, "restart must be in 1..31");
+  if (!(so.tol > 0.0) || so.maxit < 1) throw Error(SD_E_INVALID, "tol > 0 and maxit >= 1 required");
+  if (so.precond != SD_PREC_BJ && so.precond != SD_PREC_BGS) throw Error(SD_E_INVALID, "precond");
+  if (so.schur != SD_SCHUR_IDENTITY && so.schur != SD_SCHUR_MASS) throw Error(SD_E_INVALID, "schur");
+  if (so.precision != SD_PRECISION_FP64 && so.precision != SD_PRECISION_MIXED)
+    throw Error(SD_E_INVALID, "precision");
+  if (so.krylov != SD_KRYLOV_FGMRES && so.krylov != SD_KRYLOV_BICGSTAB)
+    throw Error(SD_E_INVALID, "krylov");
+  if (so.amg != SD_AMG_PLAIN && so.amg != SD_AMG_SMOOTHED) throw Error(SD_E_INVALID, "amg");
+  opts.amg.theta = so.theta;
+  opts.amg.omega = so.omega;
+  opts.amg.nu_pre = so.nu_pre;
+  opts.amg.nu_post = so.nu_post;
+  opts.amg.coarse_max = so.coarse_max;
+  opts.amg.max_levels = so.max_levels;
+  opts.amg.smoothed = so.amg == SD_AMG_SMOOTHED;
+  opts.amg.mis = so.mis;
+
+  const Layout& L = p->L;
+  off[0] = 0;
+  off[1] = L.off_v;
+  off[2] = L.off_p;
+  off[3] = L.off_q;
+  off[4] = L.N;
+  N = (int)L.N;
+  HostCSR Vb = extract_block(p->A, 0, L.off_p, 0, L.off_p);
+  HostCSR Db = extract_block(p->A, L.off_q, L.N, L.off_q, L.N);
+  HostCSR C1 = extract_block(p->A, L.off_q, L.N, 0, L.off_p);
+  HostCSR B1 = extract_block(p->A, 0, L.off_p, L.off_q, L.N);
+  HostCSR Dt = darcy_interface_block(Db, C1, B1, Vb);
+  std::vector<int32_t> compV((size_t)L.off_p, 0);
+  for (int64_t i = L.off_v; i < L.off_p; ++i) compV[i] = 1;
+  std::vector<int32_t> compD((size_t)(L.N - L.off_q), 0);
+  amg_setup_host(Vb, compV, false, opts.amg, hh[0]);
+  amg_setup_host(Dt, compD, false, opts.amg, hh[1]);
+  if (so.precond == SD_PREC_BGS) {
+    Cf = extract_block(p->A, L.off_p, L.N, 0, L.off_p);
+  } else {
+    Cf.n_rows = L.N - L.off_p;
+    Cf.n_cols = L.off_p;
+    Cf.rowptr.assign((size_t)Cf.n_rows + 1, 0);
+  }
+  const double vol = (p->grid.Lx / (double)p->grid.nx) * (p->grid.H_ff / (double)p->grid.ny);
+  xscale = so.schur == SD_SCHUR_MASS ? p->phys.mu / vol : 1.0;
+  t_setup = wall_time() - t0;
+}
+
+Solver::~Solver() {
+  for (auto e : events) (void)hipEventDestroy(e);
+  if (hf) (void)hipHostFree((void*)hf);
+}
+
+void Solver::upload(const sd_allocator* alloc, hipStream_t s) {
+  const double t0 = wall_time();
+  mem.reset(new DeviceMem(alloc, s));
+  A64 = upload_sell<double>(pb->A, *mem, s);
+  b_dev = mem->array<double>((size_t)N);
+  SD_HIP(hipMemcpyAsync(b_dev, pb->b.data(), (size_t)N * sizeof(double), hipMemcpyHostToDevice, s));
+  ldv = ((int64_t)N + 63) / 64 * 64;
+  const int m = opts.o.restart;
+  V = mem->array<double>((size_t)(m + 1) * ldv);
+  W = mem->array<double>((size_t)ldv);
+  part = mem->array<double>((size_t)kDotBlocks * kPartStride);
+  st = static_cast<DevState*>(mem->get(sizeof(DevState)));
+  SD_HIP(hipMemsetAsync(st, 0, sizeof(DevState), s));
+  void* h = nullptr;
+  SD_HIP(hipHostMalloc(&h, sizeof(HostFlags), hipHostMallocMapped | hipHostMallocCoherent));
+  hf = static_cast<HostFlags*>(h);
+  std::memset(h, 0, sizeof(HostFlags));
+  void* hd = nullptr;
+  SD_HIP(hipHostGetDevicePointer(&hd, h, 0));
+  hf_dev = static_cast<HostFlags*>(hd);
+  events.resize((size_t)kMaxBasis + 2);
+  for (auto& e : events) SD_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  prec = opts.o.precision == SD_PRECISION_MIXED ? make_prec_fp32(*this, s) : make_prec_fp64(*this, s);
+  SD_HIP(hipStreamSynchronize(s));
+  on_device = true;
+  t_setup += wall_time() - t0;
+}
+
+int Solver::solve(const double* b, double* x, int use_x0, sd_stats* stats, hipStream_t s) {
+  if (!on_device) throw Error(SD_E_INVALID, "solver was set up without a device");
+  if (!x) throw Error(SD_E_INVALID, "x must be a device pointer");
+  if (!b) b = b_dev;
+  if (opts.o.krylov == SD_KRYLOV_BICGSTAB) return prec->bicgstab(*this, b, x, use_x0, stats, s);
+  return prec->fgmres(*this, b, x, use_x0, stats, s);
+}
+
+// ===================================================== precision-specific
+namespace {
+
+template <typename T>
+void upload_hierarchy(const HostHierarchy& h, DevHierarchy<T>& d, double omega, DeviceMem& mem,
+                      hipStream_t s) {
+  d.lev.resize(h.levels.size());
+  for (size_t l = 0; l < h.levels.size(); ++l) {
+    const HostLevel& H = h.levels[l];
+    DevLevel<T>& D = d.lev[l];
+    D.n = (int)H.A.n_rows;
+    D.A = upload_sell<T>(H.A, mem, s);
+    std::vector<T> wd((size_t)D.n);
+    for (int i = 0; i < D.n; ++i) wd[i] = (T)(omega / diag_at(H.A, i));
+    D.wd = mem.array<T>((size_t)D.n);
+    SD_HIP(hipMemcpyAsync(D.wd, wd.data(), wd.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    D.tmp = mem.array<T>((size_t)D.n);
+    D.r = mem.array<T>((size_t)D.n);
+    D.x = mem.array<T>((size_t)D.n);
+    D.b = mem.array<T>((size_t)D.n);
+    if (l + 1 < h.levels.size()) {
+      D.P = upload_sell<T>(H.P, mem, s);
+      D.R = upload_sell<T>(H.R, mem, s);
+    }
+    SD_HIP(hipStreamSynchronize(s));
+  }
+  d.n_coarse = (int)h.n_coarse;
+  d.Ainv = mem.array<double>(h.Ainv.size());
+  SD_HIP(hipMemcpyAsync(d.Ainv, h.Ainv.data(), h.Ainv.size() * sizeof(double),
+                        hipMemcpyHostToDevice, s));
+  SD_HIP(hipStreamSynchronize(s));
+}
+
+template <typename T>
+class PrecImpl : public PrecBase {
+ public:
+  DevHierarchy<T> H[2];
+  Sell<T> Cf;
+  Sell<T> Aarn;          // matrix of the Arnoldi product (FP64 A, or an FP32 copy)
+  T* Z = nullptr;        // m preconditioned vectors
+  T* tq = nullptr;       // porous right-hand side of the block sweep
+  T* tmpN = nullptr;     // scratch vector of length N (apply entry points)
+  int64_t ldz = 0;
+  int nu_pre = 2, nu_post = 2;
+
+  PrecImpl(Solver& S, hipStream_t s) {
+    DeviceMem& mem = *S.mem;
+    nu_pre = S.opts.amg.nu_pre;
+    nu_post = S.opts.amg.nu_post;
+    for (int b = 0; b < 2; ++b) upload_hierarchy<T>(S.hh[b], H[b], S.opts.amg.omega, mem, s);
+    Cf = upload_sell<T>(S.Cf, mem, s);
+    if constexpr (std::is_same<T, double>::value)
+      Aarn = S.A64;
+    else
+      Aarn = upload_sell<T>(S.pb->A, mem, s);
+    ldz = S.ldv;
+    Z = mem.array<T>((size_t)S.opts.o.restart * ldz);
+    tq = mem.array<T>((size_t)(S.N - S.off[3]) + 1);
+    tmpN = mem.array<T>((size_t)ldz);
+  }
+
+  // One V-cycle from x = 0 on block blk, level l; b of type TB scaled by *bs.
+  template <typename TB>
+  void vcycle(int blk, int l, const TB* b, const double* bs, T* x, const DevState* gate,
+              hipStream_t s) {
+    DevHierarchy<T>& h = H[blk];
+    DevLevel<T>& L = h.lev[l];
+    if (l == (int)h.lev.size() - 1) {
+      const T* bc = nullptr;
+      if constexpr (std::is_same<TB, T>::value) {
+        if (!bs) bc = b;
+      }
+      if (!bc) {  // scale / convert into the level's buffer first
+        launch_scale_convert<TB, T>(b, bs, L.b, L.n, gate, s);
+        bc = L.b;
+      }
+      launch_coarse<T>(h.Ainv, L.n, bc, x, gate, s);
+      return;
+    }
+    T* cur = x;
+    T* other = L.tmp;
+    if (nu_pre == 0) {
+      launch_fill<T>(cur, (T)0, L.n, s);
+    } else {
+      launch_jacobi_zero<T, TB>(L.A, L.wd, b, bs, cur, nu_pre >= 2 ? 1 : 0, gate, s);
+      for (int k = 2; k < nu_pre; ++k) {
+        launch_jacobi<T, TB>(L.A, L.wd, b, bs, cur, other, gate, s);
+        std::swap(cur, other);
+      }
+    }
+    launch_residual<T, TB>(L.A, b, bs, cur, L.r, gate, s);
+    DevLevel<T>& C = h.lev[l + 1];
+    launch_spmv<T, T, T>(L.R, L.r, C.b, gate, s);
+    vcycle<T>(blk, l + 1, C.b, nullptr, C.x, gate, s);
+    launch_prolong<T>(L.P, C.x, cur, gate, s);
+    for (int k = 0; k < nu_post; ++k) {
+      launch_jacobi<T, TB>(L.A, L.wd, b, bs, cur, other, gate, s);
+      std::swap(cur, other);
+    }
+    if (cur != x) launch_convert<T, T>(cur, x, L.n, s);
+  }
+
+  // z = P(bs * r): block preconditioner on a basis vector (FP64 input).
+  void apply(Solver& S, const double* r, const double* bs, T* z, const DevState* gate,
+             hipStream_t s) {
+    const int64_t* o = S.off;
+    vcycle<double>(0, 0, r, bs, z, gate, s);
+    launch_block_sweep<T>(Cf, (int)(o[3] - o[2]), r + o[2], bs, z, S.xscale, z + o[2], tq, gate, s);
+    vcycle<T>(1, 0, tq, nullptr, z + o[3], gate, s);
+  }
+
+  void apply_precond(Solver& S, const double* r, double* z, hipStream_t s) override {
+    if constexpr (std::is_same<T, double>::value) {
+      apply(S, r, nullptr, z, nullptr, s);
+    } else {
+      apply(S, r, nullptr, tmpN, nullptr, s);
+      launch_convert<T, double>(tmpN, z, S.N, s);
+    }
+  }
+
+  void apply_vcycle(Solver& S, int blk, const double* b, double* x, hipStream_t s) override {
+    const int n = H[blk].lev[0].n;
+    if constexpr (std::is_same<T, double>::value) {
+      vcycle<double>(blk, 0, b, nullptr, x, nullptr, s);
+    } else {
+      vcycle<double>(blk, 0, b, nullptr, tmpN, nullptr, s);
+      launch_convert<T, double>(tmpN, x, n, s);
+    }
+  }
+
+  struct HostState {
+    int j, k, cycle_done, m, converged, breakdown, iters, pad0;
+    double bnorm, target, cycle_drop, cycle_target, beta;
+    double resblk[4];
+  };
+
+  HostState read_state(Solver& S, hipStream_t s) {
+    HostState h;
+    SD_HIP(hipMemcpyAsync(&h, S.st, sizeof(HostState), hipMemcpyDeviceToHost, s));
+    SD_HIP(hipStreamSynchronize(s));
+    return h;
+  }
+
+  int fgmres(Solver& S, const double* b, double* x, int use_x0, sd_stats* stats,
+             hipStream_t s) override {
+    const double t0 = wall_time();
+    const sd_solver_opts& o = S.opts.o;
+    const int n = S.N;
+    const int m = o.restart;
+    const double drop = std::is_same<T, float>::value ? 1e-6 : 0.0;
+    launch_init_state(S.st, m, drop, s);
+    launch_norm_b(b, n, o.tol, S.st, S.part, s);
+    HostState hs = read_state(S, s);
+    sd_stats out{};
+    if (!(hs.bnorm > 0.0)) {
+      launch_fill<double>(x, 0.0, n, s);
+      SD_HIP(hipStreamSynchronize(s));
+      out.t_setup = S.t_setup;
+      out.t_solve = wall_time() - t0;
+      if (stats) *stats = out;
+      return std::isfinite(hs.bnorm) ? SD_OK : SD_E_INVALID;
+    }
+    if (!use_x0) launch_fill<double>(x, 0.0, n, s);
+    bool first = true;
+    int status = SD_E_NOCONV;
+    int restarts = 0;
+    const int depth = 2;
+    for (;;) {
+      const int it_done = hs.iters;
+      const int m_cycle = std::min(m, std::max(1, o.maxit - it_done));
+      // cycle length for this restart
+      launch_init_cycle(S, m_cycle, s);
+      launch_restart_residual(S.A64, b, (first && !use_x0) ? nullptr : x, S.V, S.off, S.st,
+                              S.part, S.hf_dev, s);
+      first = false;
+      hs = read_state(S, s);
+      if (hs.breakdown || !std::isfinite(hs.beta)) {
+        status = SD_E_BREAKDOWN;
+        break;
+      }
+      if (hs.converged) {
+        status = SD_OK;
+        break;
+      }
+      if (hs.iters >= o.maxit) {
+        status = SD_E_NOCONV;
+        break;
+      }
+      for (int j = 0; j <= kMaxBasis; ++j) S.hf->cycle_done[j] = 0;
+      int j_enq = 0;
+      for (int j = 0; j < m_cycle; ++j) {
+        T* zj = Z + (size_t)j * ldz;
+        apply(S, S.V + (size_t)j * S.ldv, &S.st->sigma[j], zj, S.st, s);
+        launch_arnoldi_j<T, T>(Aarn, zj, S.W, S.V, S.ldv, j, S.st, S.part, s);
+        launch_cgs_dots_j(S.W, S.V, S.ldv, n, j, S.st, S.part, s);
+        launch_cgs_norm_j(S.W, S.V, S.ldv, n, j, S.st, S.part, S.hf_dev, s);
+        SD_HIP(hipEventRecord(S.events[(size_t)j], s));
+        j_enq = j + 1;
+        if (j >= depth) {
+          SD_HIP(hipEventSynchronize(S.events[(size_t)(j - depth)]));
+          bool done = false;
+          for (int q = 0; q <= j - depth; ++q) done = done || S.hf->cycle_done[q];
+          if (done) break;
+        }
+      }
+      (void)j_enq;
+      launch_trisolve(S.st, s);
+      launch_update_x<T>(x, Z, ldz, n, S.st, s);
+      ++restarts;
+    }
+    out.iters = hs.iters;
+    out.restarts = restarts;
+    out.rel_res = hs.beta / hs.bnorm;
+    for (int k = 0; k < 3; ++k) out.rel_res_block[k] = std::sqrt(hs.resblk[k]) / hs.bnorm;
+    out.t_setup = S.t_setup;
+    out.t_solve = wall_time() - t0;
+    if (stats) *stats = out;
+    return status;
+  }
+
+  void launch_init_cycle(Solver& S, int m_cycle, hipStream_t s) {
+    // only the cycle length changes between cycles; counters stay zero
+    launch_set_cycle_length(S.st, m_cycle, s);
+  }
+
+  int bicgstab(Solver&, const double*, double*, int, sd_stats*, hipStream_t) override {
+    throw Error(SD_E_INVALID, "BiCGSTAB not available in this build");
+  }
+};
+
+}  // namespace
+
+std::unique_ptr<PrecBase> make_prec_fp64(Solver& S, hipStream_t s) {
+  return std::unique_ptr<PrecBase>(new PrecImpl<double>(S, s));
+}
+std::unique_ptr<PrecBase> make_prec_fp32(Solver& S, hipStream_t s) {
+  return std::unique_ptr<PrecBase>(new PrecImpl<float>(S, s));
+}
+
+}  // namespace sd

@@ -1,0 +1,120 @@
+// Device-resident solver: matrices, AMG hierarchies, Krylov workspace.
+#pragma once
+
+#include <memory>
+#include <vector>
+
+#include "device.h"
+#include "sd_internal.h"
+
+namespace sd {
+
+#define SD_HIP(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      throw ::sd::Error(SD_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Device allocations of one handle, through the caller's allocator or hipMalloc.
+class DeviceMem {
+ public:
+  DeviceMem() = default;
+  DeviceMem(const sd_allocator* a, hipStream_t s) : stream_(s) {
+    if (a && a->alloc && a->free) alloc_ = *a, has_ = true;
+  }
+  ~DeviceMem();
+  DeviceMem(const DeviceMem&) = delete;
+  DeviceMem& operator=(const DeviceMem&) = delete;
+  void* get(size_t bytes);
+  template <typename T>
+  T* array(size_t n) { return static_cast<T*>(get(n * sizeof(T) + 16)); }
+  size_t bytes() const { return total_; }
+
+ private:
+  sd_allocator alloc_{};
+  bool has_ = false;
+  hipStream_t stream_ = nullptr;
+  std::vector<void*> ptrs_;
+  size_t total_ = 0;
+};
+
+template <typename T>
+struct DevLevel {
+  int n = 0;
+  Sell<T> A, P, R;
+  T* wd = nullptr;     // omega / a_ii
+  T* x = nullptr;      // iterate (levels >= 1)
+  T* tmp = nullptr;
+  T* r = nullptr;
+  T* b = nullptr;      // right-hand side (levels >= 1)
+};
+
+template <typename T>
+struct DevHierarchy {
+  std::vector<DevLevel<T>> lev;
+  double* Ainv = nullptr;
+  int n_coarse = 0;
+};
+
+struct SolverOpts {
+  sd_solver_opts o;
+  AMGOpts amg;
+};
+
+class Solver;
+
+// Precision-specific part: preconditioner operators and the Arnoldi matrix.
+class PrecBase {
+ public:
+  virtual ~PrecBase() = default;
+  virtual int fgmres(Solver& S, const double* b, double* x, int use_x0, sd_stats* st,
+                     hipStream_t s) = 0;
+  virtual int bicgstab(Solver& S, const double* b, double* x, int use_x0, sd_stats* st,
+                       hipStream_t s) = 0;
+  virtual void apply_precond(Solver& S, const double* r, double* z, hipStream_t s) = 0;
+  virtual void apply_vcycle(Solver& S, int block, const double* b, double* x,
+                            hipStream_t s) = 0;
+};
+
+class Solver {
+ public:
+  HostProblem* pb = nullptr;        // not owned
+  SolverOpts opts;
+  HostHierarchy hh[2];              // 0: V, 1: Darcy block with interface correction
+  HostCSR Cf;                       // continuity and porous rows x velocity columns
+  double xscale = 1.0;
+  int64_t off[5] = {0, 0, 0, 0, 0};
+  int N = 0;
+  bool on_device = false;
+  double t_setup = 0.0;
+
+  // device
+  std::unique_ptr<DeviceMem> mem;
+  Sell<double> A64;
+  double* b_dev = nullptr;
+  double* V = nullptr;              // (m+1) basis vectors, unnormalised
+  double* W = nullptr;
+  double* part = nullptr;
+  DevState* st = nullptr;
+  HostFlags* hf = nullptr;          // mapped pinned memory (host view)
+  HostFlags* hf_dev = nullptr;      // the same memory as seen by kernels
+  int64_t ldv = 0;
+  std::vector<hipEvent_t> events;
+  std::unique_ptr<PrecBase> prec;
+
+  ~Solver();
+  void setup_host(HostProblem* p, const sd_solver_opts* o);
+  void upload(const sd_allocator* alloc, hipStream_t s);
+  size_t device_bytes() const { return mem ? mem->bytes() : 0; }
+  int solve(const double* b, double* x, int use_x0, sd_stats* stats, hipStream_t s);
+};
+
+// SELL construction on the host and upload.
+template <typename T>
+Sell<T> upload_sell(const HostCSR& A, DeviceMem& mem, hipStream_t s);
+
+std::unique_ptr<PrecBase> make_prec_fp64(Solver& S, hipStream_t s);
+std::unique_ptr<PrecBase> make_prec_fp32(Solver& S, hipStream_t s);
+
+}  // namespace sd

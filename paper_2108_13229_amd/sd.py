@@ -1,0 +1,345 @@
+"""ctypes binding of the C ABI declared in include/sd.h.
+
+Argument marshalling only: every step of assembly, setup and solve runs in
+the native library (host C++ for assembly and AMG setup, HIP kernels for the
+iteration).  PyTorch provides device memory and the current HIP stream.
+The library must have been built (``python -m paper_2108_13229_amd.build``);
+there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsd.so")
+
+SD_OK, SD_E_INVALID, SD_E_NOMEM, SD_E_DEVICE = 0, -1, -2, -3
+SD_E_NOCONV, SD_E_BREAKDOWN, SD_E_BUSY, SD_E_NOTFOUND = -4, -5, -6, -7
+BC = {"velocity": 0, "traction": 1, "pressure": 2, "noflow": 3}
+KRYLOV = {"fgmres": 0, "bicgstab": 1}
+PRECOND = {"BJ": 0, "BGS": 1}
+SCHUR = {"identity": 0, "mass": 1}
+PRECISION = {"fp64": 0, "mixed": 1}
+AMG = {"plain": 0, "smoothed": 1}
+REQ_STATE = {0: "pending", 1: "running", 2: "done", 3: "failed"}
+
+_dp = C.POINTER(C.c_double)
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("ny_pm", C.c_int),
+                ("Lx", C.c_double), ("H_ff", C.c_double), ("H_pm", C.c_double)]
+
+
+class Physics(C.Structure):
+    _fields_ = [("mu", C.c_double), ("alpha_bj", C.c_double)]
+
+
+class Bcs(C.Structure):
+    _fields_ = [("ff_left", C.c_int), ("ff_right", C.c_int), ("ff_top", C.c_int),
+                ("pm_left", C.c_int), ("pm_right", C.c_int), ("pm_bottom", C.c_int),
+                ("ff_left_n", _dp), ("ff_left_t", _dp), ("ff_right_n", _dp),
+                ("ff_right_t", _dp), ("ff_top_t", _dp), ("ff_top_n", _dp),
+                ("pm_left_p", _dp), ("pm_right_p", _dp), ("pm_bottom_p", _dp)]
+
+
+class Forcing(C.Structure):
+    _fields_ = [("f_u", _dp), ("f_v", _dp), ("q_pm", _dp)]
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", C.c_void_p), ("free", C.c_void_p), ("ctx", C.c_void_p)]
+
+
+class SolverOpts(C.Structure):
+    _fields_ = [("krylov", C.c_int), ("restart", C.c_int), ("maxit", C.c_int),
+                ("tol", C.c_double), ("precond", C.c_int), ("schur", C.c_int),
+                ("precision", C.c_int), ("amg", C.c_int), ("mis", C.c_int),
+                ("theta", C.c_double), ("omega", C.c_double), ("nu_pre", C.c_int),
+                ("nu_post", C.c_int), ("coarse_max", C.c_int), ("max_levels", C.c_int)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("rel_res", C.c_double),
+                ("rel_res_block", C.c_double * 3), ("t_setup", C.c_double),
+                ("t_solve", C.c_double)]
+
+    def as_dict(self):
+        return dict(iters=self.iters, restarts=self.restarts, rel_res=self.rel_res,
+                    rel_res_block=list(self.rel_res_block), t_setup=self.t_setup,
+                    t_solve=self.t_solve)
+
+
+class ServerOpts(C.Structure):
+    _fields_ = [("hbm_budget", C.c_size_t), ("max_slots", C.c_int), ("device", C.c_int)]
+
+
+class Request(C.Structure):
+    _fields_ = [("grid", Grid), ("phys", Physics), ("bcs", Bcs), ("K", _dp),
+                ("forcing", Forcing), ("opts", SolverOpts)]
+
+
+class Result(C.Structure):
+    _fields_ = [("state", C.c_int), ("status", C.c_int), ("x_host", _dp), ("N", C.c_int64),
+                ("stats", Stats), ("t_submit", C.c_double), ("t_admit", C.c_double),
+                ("t_done", C.c_double)]
+
+
+# every symbol declared in include/sd.h, with its signature
+_P = C.c_void_p
+SIGNATURES = {
+    "sd_assemble": (C.c_int, [C.POINTER(Grid), C.POINTER(Physics), C.POINTER(Bcs), _dp,
+                              C.POINTER(Forcing), C.POINTER(Allocator), _P, C.POINTER(_P)]),
+    "sd_assemble_host": (C.c_int, [C.POINTER(Grid), C.POINTER(Physics), C.POINTER(Bcs), _dp,
+                                   C.POINTER(Forcing), C.POINTER(_P)]),
+    "sd_problem_info": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                  C.POINTER(C.c_int64)]),
+    "sd_problem_csr": (C.c_int, [_P, C.POINTER(C.POINTER(C.c_int64)),
+                                 C.POINTER(C.POINTER(C.c_int32)), C.POINTER(_dp),
+                                 C.POINTER(_dp)]),
+    "sd_solver_opts_default": (None, [C.POINTER(SolverOpts)]),
+    "sd_setup": (C.c_int, [_P, C.POINTER(SolverOpts), C.POINTER(_P)]),
+    "sd_setup_host": (C.c_int, [_P, C.POINTER(SolverOpts), C.POINTER(_P)]),
+    "sd_solver_levels": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int)]),
+    "sd_solver_level_csr": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int64),
+                                      C.POINTER(C.c_int64), C.POINTER(C.POINTER(C.c_int64)),
+                                      C.POINTER(C.POINTER(C.c_int32)), C.POINTER(_dp)]),
+    "sd_solver_level_agg": (C.c_int, [_P, C.c_int, C.c_int, C.POINTER(C.POINTER(C.c_int32)),
+                                      C.POINTER(C.c_int64)]),
+    "sd_solver_coarse_inverse": (C.c_int, [_P, C.c_int, C.POINTER(_dp), C.POINTER(C.c_int64)]),
+    "sd_solve": (C.c_int, [_P, _P, _P, C.c_int, C.POINTER(Stats), _P]),
+    "sd_apply_matrix": (C.c_int, [_P, _P, _P, _P]),
+    "sd_apply_preconditioner": (C.c_int, [_P, _P, _P, _P]),
+    "sd_apply_vcycle": (C.c_int, [_P, C.c_int, _P, _P, _P]),
+    "sd_server_create": (C.c_int, [C.POINTER(ServerOpts), C.POINTER(_P)]),
+    "sd_submit": (C.c_int, [_P, C.POINTER(Request), C.POINTER(C.c_uint64)]),
+    "sd_poll": (C.c_int, [_P, C.c_uint64, C.POINTER(Result)]),
+    "sd_wait": (C.c_int, [_P, C.c_uint64, C.c_double, C.POINTER(Result)]),
+    "sd_result_release": (C.c_int, [_P, C.c_uint64]),
+    "sd_cancel": (C.c_int, [_P, C.c_uint64]),
+    "sd_problem_destroy": (None, [_P]),
+    "sd_solver_destroy": (None, [_P]),
+    "sd_server_destroy": (None, [_P]),
+    "sd_status_string": (C.c_char_p, [C.c_int]),
+    "sd_last_error": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libsd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} not built; run python -m paper_2108_13229_amd.build")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class SDError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{lib().sd_status_string(code).decode()}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != SD_OK:
+        raise SDError(rc, lib().sd_last_error().decode())
+    return rc
+
+
+def _ptr(a, keep):
+    if a is None:
+        return None
+    arr = np.ascontiguousarray(a, dtype=np.float64).ravel()
+    keep.append(arr)
+    return arr.ctypes.data_as(_dp)
+
+
+def _marshal(p, keep):
+    g = Grid(int(p.nx), int(p.ny), int(p.ny_pm), float(p.Lx), float(p.H_ff), float(p.H_pm))
+    ph = Physics(float(p.mu), float(p.alpha_bj))
+    b = Bcs(BC[p.ff_left], BC[p.ff_right], BC[p.ff_top], BC[p.pm_left], BC[p.pm_right],
+            BC[p.pm_bottom],
+            _ptr(p.ff_left_n, keep), _ptr(p.ff_left_t, keep), _ptr(p.ff_right_n, keep),
+            _ptr(p.ff_right_t, keep), _ptr(p.ff_top_t, keep), _ptr(p.ff_top_n, keep),
+            _ptr(p.pm_left_p, keep), _ptr(p.pm_right_p, keep), _ptr(p.pm_bottom_p, keep))
+    f = Forcing(_ptr(p.f_u, keep), _ptr(p.f_v, keep), _ptr(p.q_pm, keep))
+    K = _ptr(p.K, keep)
+    return g, ph, b, f, K
+
+
+def solver_opts(**kw) -> SolverOpts:
+    o = SolverOpts()
+    lib().sd_solver_opts_default(C.byref(o))
+    maps = dict(krylov=KRYLOV, precond=PRECOND, schur=SCHUR, precision=PRECISION, amg=AMG)
+    for k, v in kw.items():
+        if k in maps and isinstance(v, str):
+            v = maps[k][v]
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Problem:
+    """An assembled coupled system (host CSR, optionally bound to a device)."""
+
+    def __init__(self, p, device: bool = True):
+        keep = []
+        g, ph, b, f, K = _marshal(p, keep)
+        h = C.c_void_p()
+        if device:
+            _check(lib().sd_assemble(C.byref(g), C.byref(ph), C.byref(b), K, C.byref(f),
+                                     None, _stream(), C.byref(h)))
+        else:
+            _check(lib().sd_assemble_host(C.byref(g), C.byref(ph), C.byref(b), K, C.byref(f),
+                                          C.byref(h)))
+        self.h = h
+        self.device = device
+        N = C.c_int64()
+        off = (C.c_int64 * 5)()
+        nnz = C.c_int64()
+        _check(lib().sd_problem_info(h, C.byref(N), off, C.byref(nnz)))
+        self.N = N.value
+        self.block_off = np.array(list(off), dtype=np.int64)
+        self.nnz = nnz.value
+
+    def csr(self):
+        rp = C.POINTER(C.c_int64)()
+        ci = C.POINTER(C.c_int32)()
+        va = _dp()
+        bb = _dp()
+        _check(lib().sd_problem_csr(self.h, C.byref(rp), C.byref(ci), C.byref(va), C.byref(bb)))
+        rowptr = np.ctypeslib.as_array(rp, (self.N + 1,)).copy()
+        col = np.ctypeslib.as_array(ci, (self.nnz,)).copy()
+        val = np.ctypeslib.as_array(va, (self.nnz,)).copy()
+        b = np.ctypeslib.as_array(bb, (self.N,)).copy()
+        return rowptr, col, val, b
+
+    def close(self):
+        if self.h:
+            lib().sd_problem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Solver:
+    """AMG hierarchies + block preconditioner + Krylov workspace."""
+
+    def __init__(self, problem: Problem, device: Optional[bool] = None, **opts):
+        self.problem = problem
+        device = problem.device if device is None else device
+        self.device = device
+        self.opts = solver_opts(**opts)
+        h = C.c_void_p()
+        fn = lib().sd_setup if device else lib().sd_setup_host
+        _check(fn(problem.h, C.byref(self.opts), C.byref(h)))
+        self.h = h
+
+    # ---- hierarchy inspection (host copies)
+    def n_levels(self, block: int) -> int:
+        n = C.c_int()
+        _check(lib().sd_solver_levels(self.h, block, C.byref(n)))
+        return n.value
+
+    def level_csr(self, block: int, level: int, which: int = 0):
+        nr, nc = C.c_int64(), C.c_int64()
+        rp = C.POINTER(C.c_int64)()
+        ci = C.POINTER(C.c_int32)()
+        va = _dp()
+        _check(lib().sd_solver_level_csr(self.h, block, level, which, C.byref(nr), C.byref(nc),
+                                         C.byref(rp), C.byref(ci), C.byref(va)))
+        rowptr = np.ctypeslib.as_array(rp, (nr.value + 1,)).copy()
+        nnz = int(rowptr[-1])
+        col = np.ctypeslib.as_array(ci, (max(nnz, 1),))[:nnz].copy()
+        val = np.ctypeslib.as_array(va, (max(nnz, 1),))[:nnz].copy()
+        return (nr.value, nc.value), rowptr, col, val
+
+    def level_agg(self, block: int, level: int) -> np.ndarray:
+        a = C.POINTER(C.c_int32)()
+        n = C.c_int64()
+        _check(lib().sd_solver_level_agg(self.h, block, level, C.byref(a), C.byref(n)))
+        return np.ctypeslib.as_array(a, (n.value,)).copy()
+
+    def coarse_inverse(self, block: int) -> np.ndarray:
+        a = _dp()
+        n = C.c_int64()
+        _check(lib().sd_solver_coarse_inverse(self.h, block, C.byref(a), C.byref(n)))
+        return np.ctypeslib.as_array(a, (n.value * n.value,)).reshape(n.value, n.value).copy()
+
+    # ---- device operations (torch CUDA float64 tensors)
+    def solve(self, b=None, x=None, use_x0: bool = False):
+        import torch
+        N = self.problem.N
+        if x is None:
+            x = torch.zeros(N, dtype=torch.float64, device="cuda")
+        _require(x, N)
+        if b is not None:
+            _require(b, N)
+        st = Stats()
+        rc = lib().sd_solve(self.h, C.c_void_p(b.data_ptr()) if b is not None else None,
+                            C.c_void_p(x.data_ptr()), int(use_x0), C.byref(st), _stream())
+        if rc not in (SD_OK, SD_E_NOCONV):
+            _check(rc)
+        return x, st.as_dict(), rc
+
+    def apply_matrix(self, x):
+        import torch
+        _require(x, self.problem.N)
+        y = torch.empty_like(x)
+        _check(lib().sd_apply_matrix(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                     _stream()))
+        return y
+
+    def apply_preconditioner(self, r):
+        import torch
+        _require(r, self.problem.N)
+        z = torch.empty_like(r)
+        _check(lib().sd_apply_preconditioner(self.h, C.c_void_p(r.data_ptr()),
+                                             C.c_void_p(z.data_ptr()), _stream()))
+        return z
+
+    def apply_vcycle(self, block: int, b):
+        import torch
+        x = torch.empty_like(b)
+        _check(lib().sd_apply_vcycle(self.h, block, C.c_void_p(b.data_ptr()),
+                                     C.c_void_p(x.data_ptr()), _stream()))
+        return x
+
+    def close(self):
+        if self.h:
+            lib().sd_solver_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _require(t, n):
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.numel() == n):
+        raise ValueError(f"expected a contiguous CUDA float64 tensor of {n} entries")

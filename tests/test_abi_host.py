@@ -1,0 +1,118 @@
+"""C-ABI checks that need no GPU: exported symbols, argument validation, and
+bit-exact parity of the host assembly and AMG setup with the oracle."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from sdinputs import channel_problem, mms_problem
+from oracle import amg, precond
+from oracle.assemble import assemble
+
+sd = pytest.importorskip("paper_2108_13229_amd.sd")
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "sd.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sd_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = sd.lib()
+    names = _declared()
+    assert len(names) >= 25
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(sd.SIGNATURES)
+
+
+def _cases():
+    p_vel = channel_problem(20, 10, 8, seed=9)
+    p_vel.ff_right = "velocity"
+    p_vel.ff_right_n = np.linspace(0.0, 1e-3, 10)
+    p_vel.ff_right_t = np.linspace(-1e-4, 1e-4, 11)
+    p_mixbc = channel_problem(30, 12, 14, seed=11)
+    p_mixbc.pm_left = "pressure"
+    p_mixbc.pm_left_p = np.linspace(1.0, 2.0, 14)
+    return [mms_problem(32, 16)[0], mms_problem(24, 12, 9, K=3e-3, mu=0.5, alpha=0.7)[0],
+            channel_problem(64, 32, seed=1), channel_problem(45, 22, 17, seed=5), p_vel, p_mixbc]
+
+
+@pytest.mark.parametrize("p", _cases())
+def test_host_assembly_bit_exact(p):
+    P = sd.Problem(p, device=False)
+    rp, col, val, b = P.csr()
+    a = assemble(p)
+    assert np.array_equal(rp, a.A.indptr)
+    assert np.array_equal(col, a.A.indices)
+    assert np.array_equal(val, a.A.data)        # bit-for-bit
+    assert np.array_equal(b, a.b)
+    assert np.array_equal(P.block_off, a.layout.block_off)
+
+
+@pytest.mark.parametrize("amg_kind,mis", [("smoothed", 2), ("plain", 1), ("smoothed", 1),
+                                          ("plain", 2)])
+@pytest.mark.parametrize("pi", [0, 2, 3])
+def test_host_amg_bit_exact(amg_kind, mis, pi):
+    p = _cases()[pi]
+    P = sd.Problem(p, device=False)
+    S = sd.Solver(P, device=False, amg=amg_kind, mis=mis, coarse_max=64)
+    a = assemble(p)
+    opts = amg.AMGOptions(smoothed=amg_kind == "smoothed", mis=mis, coarse_max=64)
+    M = precond.build(p, a, "BGS", opts=opts)
+    for blk, h in [(0, M.hV), (1, M.hD)]:
+        nl = S.n_levels(blk)
+        assert nl == h.n_levels
+        for lev in range(nl):
+            L = h.levels[lev]
+            shape, rp, col, val = S.level_csr(blk, lev, 0)
+            assert np.array_equal(rp, L.A.indptr) and np.array_equal(col, L.A.indices)
+            assert np.array_equal(val, L.A.data)
+            if lev + 1 < nl:
+                assert np.array_equal(S.level_agg(blk, lev), L.agg)
+                for which, M_ in [(1, L.P), (2, L.R)]:
+                    _, rp, col, val = S.level_csr(blk, lev, which)
+                    assert np.array_equal(rp, M_.indptr) and np.array_equal(col, M_.indices)
+                    assert np.array_equal(val, M_.data)
+        inv = S.coarse_inverse(blk)
+        assert np.allclose(inv, h.Ainv, rtol=0, atol=1e-12 * np.abs(h.Ainv).max())
+
+
+def test_invalid_inputs_are_rejected():
+    p = channel_problem(16, 8, seed=1)
+    p.K = p.K.copy()
+    p.K[3, 4] = np.nan
+    with pytest.raises(sd.SDError) as e:
+        sd.Problem(p, device=False)
+    assert e.value.code == sd.SD_E_INVALID
+    p = channel_problem(16, 8, seed=1)
+    p.K = -p.K
+    with pytest.raises(sd.SDError):
+        sd.Problem(p, device=False)
+    p = channel_problem(1, 8, seed=1, corr_cells=0)
+    with pytest.raises(sd.SDError):
+        sd.Problem(p, device=False)
+    p = channel_problem(16, 8, seed=1)
+    p.ff_top = "traction"
+    with pytest.raises(sd.SDError):
+        sd.Problem(p, device=False)
+    p = channel_problem(16, 8, seed=1)
+    P = sd.Problem(p, device=False)
+    with pytest.raises(sd.SDError):
+        sd.Solver(P, device=False, restart=40)
+    with pytest.raises(sd.SDError):
+        sd.Solver(P, device=False, tol=0.0)
+    with pytest.raises(sd.SDError):
+        sd.Solver(P, device=True)        # host-only problem cannot get device data
+    assert sd.lib().sd_status_string(-4) == b"SD_E_NOCONV"
+
+
+def test_smallest_grid():
+    p = channel_problem(2, 2, 1, seed=1, corr_cells=0)
+    P = sd.Problem(p, device=False)
+    rp, col, val, b = P.csr()
+    a = assemble(p)
+    assert np.array_equal(val, a.A.data) and P.N == a.N == 2 * 2 + 2 * 2 + 4 + 2

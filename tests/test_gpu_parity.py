@@ -1,0 +1,192 @@
+"""GPU parity of the HIP path against the CPU oracle (through the C ABI)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from sdinputs import channel_problem, config_problem, mms_problem
+from oracle import amg, krylov, precond
+from oracle.assemble import assemble
+from oracle.direct import refined_solve
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+sd = pytest.importorskip("paper_2108_13229_amd.sd")
+EPS = np.finfo(np.float64).eps
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    sd.lib()
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+# problems spanning several 64-row slices with ragged tails
+SMALL = {
+    "mms32": lambda: mms_problem(32, 16)[0],
+    "mms_ragged": lambda: mms_problem(37, 19, 11, K=5e-3)[0],
+    "channel96": lambda: channel_problem(96, 48, seed=3),
+    "channel_ragged": lambda: channel_problem(75, 33, 29, seed=4),
+    "tiny": lambda: channel_problem(2, 2, 1, seed=1, corr_cells=0),
+}
+
+
+def _setup(p, **opts):
+    P = sd.Problem(p, device=True)
+    S = sd.Solver(P, **opts)
+    return P, S
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_spmv_parity(name):
+    p = SMALL[name]()
+    print("case", name, flush=True)
+    a = assemble(p)
+    P, S = _setup(p)
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal(a.N)
+    y = _host(S.apply_matrix(_dev(x)))
+    ref = a.A @ x
+    bound = 16 * EPS * (abs(a.A) @ np.abs(x)) + 1e-300
+    assert np.all(np.abs(y - ref) <= bound)
+
+
+@pytest.mark.parametrize("name", ["mms32", "channel96", "channel_ragged", "tiny"])
+@pytest.mark.parametrize("kind", ["smoothed", "plain"])
+def test_vcycle_parity(name, kind):
+    p = SMALL[name]()
+    print("case", name, kind, flush=True)
+    a = assemble(p)
+    opts = amg.AMGOptions(smoothed=kind == "smoothed", mis=2 if kind == "smoothed" else 1)
+    M = precond.build(p, a, "BGS", opts=opts)
+    P, S = _setup(p, amg=kind, mis=opts.mis)
+    rng = np.random.default_rng(11)
+    for blk, h in [(0, M.hV), (1, M.hD)]:
+        n = h.levels[0].A.shape[0]
+        b = rng.standard_normal(n)
+        x = _host(S.apply_vcycle(blk, _dev(b)))
+        ref = amg.vcycle(h, b)
+        assert np.linalg.norm(x - ref) <= 1e-12 * np.linalg.norm(ref)
+        assert np.max(np.abs(x - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("name", ["mms32", "channel96", "channel_ragged"])
+@pytest.mark.parametrize("variant,schur", [("BGS", "mass"), ("BJ", "mass"), ("BGS", "identity")])
+def test_block_preconditioner_parity(name, variant, schur):
+    p = SMALL[name]()
+    print("case", name, variant, schur, flush=True)
+    a = assemble(p)
+    M = precond.build(p, a, variant, schur=schur)
+    P, S = _setup(p, precond=variant, schur=schur)
+    r = np.random.default_rng(5).standard_normal(a.N)
+    z = _host(S.apply_preconditioner(_dev(r)))
+    ref = M(r)
+    assert np.linalg.norm(z - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_mixed_preconditioner_close_to_fp64():
+    p = SMALL["channel96"]()
+    a = assemble(p)
+    M = precond.build(p, a, "BGS")
+    P, S = _setup(p, precision="mixed")
+    r = np.random.default_rng(5).standard_normal(a.N)
+    z = _host(S.apply_preconditioner(_dev(r)))
+    ref = M(r)
+    assert np.linalg.norm(z - ref) <= 1e-5 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("name,variant,tol", [("mms32", "BJ", 1e-10), ("channel96", "BGS", 1e-8),
+                                               ("channel_ragged", "BGS", 1e-8)])
+def test_fgmres_fp64_matches_oracle(name, variant, tol):
+    p = SMALL[name]()
+    print("case", name, variant, flush=True)
+    a = assemble(p)
+    M = precond.build(p, a, variant)
+    ref = krylov.fgmres(a.A, a.b, M, tol=tol, m=30)
+    xs = refined_solve(a.A, a.b)
+    P, S = _setup(p, precond=variant, tol=tol)
+    x, st, rc = S.solve()
+    x = _host(x)
+    assert rc == sd.SD_OK
+    true_res = np.linalg.norm(a.b - a.A @ x) / np.linalg.norm(a.b)
+    assert true_res <= tol
+    assert abs(st["rel_res"] - true_res) <= 1e-3 * tol
+    # same algorithm, same operators: same iteration count (+-1) and iterate
+    assert abs(st["iters"] - ref.iters) <= 1
+    o = a.layout.block_off
+    for k in range(3):
+        sl = slice(o[[0, 2, 3][k]], o[[2, 3, 4][k]])
+        assert np.linalg.norm(x[sl] - ref.x[sl]) <= 1e-8 * np.linalg.norm(ref.x[sl]) + 1e-300
+    # and the error against the exact solution is that of the oracle's iterate
+    e_gpu = np.linalg.norm(x - xs) / np.linalg.norm(xs)
+    e_ref = np.linalg.norm(ref.x - xs) / np.linalg.norm(xs)
+    assert e_gpu <= 2 * e_ref + 1e-12
+
+
+def test_fgmres_mixed_precision():
+    p = SMALL["channel96"]()
+    a = assemble(p)
+    xs = refined_solve(a.A, a.b)
+    P, S = _setup(p, precision="mixed", tol=1e-8)
+    x, st, rc = S.solve()
+    x = _host(x)
+    assert rc == sd.SD_OK
+    assert np.linalg.norm(a.b - a.A @ x) <= 1e-8 * np.linalg.norm(a.b)
+    assert np.linalg.norm(x - xs) <= 1e-6 * np.linalg.norm(xs)
+
+
+def test_solve_repeatable_bitwise():
+    p = SMALL["channel_ragged"]()
+    P, S = _setup(p)
+    x1, st1, _ = S.solve()
+    x2, st2, _ = S.solve()
+    assert torch.equal(x1, x2) and st1["iters"] == st2["iters"]
+
+
+def test_edge_cases():
+    p = SMALL["channel96"]()
+    a = assemble(p)
+    P, S = _setup(p, maxit=3)
+    x, st, rc = S.solve()
+    assert rc == sd.SD_E_NOCONV and st["iters"] == 3
+    # zero right-hand side -> zero solution, no iterations
+    P, S = _setup(p)
+    x, st, rc = S.solve(b=torch.zeros(a.N, dtype=torch.float64, device="cuda"))
+    assert rc == sd.SD_OK and st["iters"] == 0 and float(x.abs().max()) == 0.0
+    # exact initial guess -> converged before the first iteration
+    xs = refined_solve(a.A, a.b)
+    x0 = _dev(xs)
+    x, st, rc = S.solve(x=x0, use_x0=True)
+    assert rc == sd.SD_OK and st["iters"] == 0
+    # custom right-hand side
+    b = np.random.default_rng(3).standard_normal(a.N)
+    x, st, rc = S.solve(b=_dev(b))
+    x = _host(x)
+    assert rc == sd.SD_OK
+    assert np.linalg.norm(b - a.A @ x) <= 1e-8 * np.linalg.norm(b)
+
+
+def test_c1_full_size_fp64():
+    """512x256 per subdomain, lognormal K: SpMV parity on the whole vector
+    and the solve's true residual checked with the oracle's matrix."""
+    p = config_problem("C1")
+    a = assemble(p)
+    P, S = _setup(p, precond="BGS", tol=1e-8)
+    x = np.random.default_rng(1).standard_normal(a.N)
+    y = _host(S.apply_matrix(_dev(x)))
+    assert np.all(np.abs(y - a.A @ x) <= 16 * EPS * (abs(a.A) @ np.abs(x)) + 1e-300)
+    xg, st, rc = S.solve()
+    xg = _host(xg)
+    print("C1 fp64", st, flush=True)
+    assert rc == sd.SD_OK
+    assert np.linalg.norm(a.b - a.A @ xg) <= 1e-8 * np.linalg.norm(a.b)
