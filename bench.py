@@ -1,0 +1,147 @@
+"""Benchmark: coupled Stokes-Darcy solves/s on one MI355X.
+
+Workload (the headline configuration): 512 x 256 cells in each subdomain
+(N = 524,288 unknowns), lognormal permeability ln K ~ N(ln 1e-4, 1) with an
+8-cell Gaussian correlation (seed 1), viscosity 1e-3, parabolic inflow of
+peak 1e-2, zero-traction outflow; block-Gauss-Seidel preconditioned
+FGMRES(30) with one smoothed-aggregation V-cycle per velocity and Darcy block
+and the viscosity-scaled pressure-mass Schur block, to relative residual
+1e-8.  One step = one complete solve from x = 0 with the matrix and the AMG
+hierarchy resident in HBM.  FP64 is the headline; the mixed-precision solver
+(FP32 preconditioner and Arnoldi product, FP64 outer residual) is reported
+beside it.  Inputs are synthetic and seeded.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = ("512x256 free-flow + 512x256 porous cells (N=524288), lognormal K seed 1, "
+            "BGS(SA-AMG V-cycle, mu*Mp^-1, SA-AMG V-cycle) + FGMRES(30), rel. residual 1e-8")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--nx", type=int, default=512)
+    ap.add_argument("--ny", type=int, default=256)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--restart", type=int, default=30)
+    return ap.parse_args()
+
+
+def run_solves(S, steps, warmup):
+    import torch
+    lat = []
+    its = []
+    for k in range(warmup + steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, st, rc = S.solve()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if rc != 0:
+            raise RuntimeError(f"solve did not converge (status {rc})")
+        if k >= warmup:
+            lat.append(dt)
+            its.append(st["iters"])
+    return np.array(lat), its, st, x
+
+
+def cpu_baseline(p, a_budget_s=30.0):
+    """The oracle's FP64 FGMRES with the same preconditioner, one solve,
+    single-threaded (setup excluded; timed separately)."""
+    from threadpoolctl import threadpool_limits
+    from oracle import krylov, precond
+    from oracle.assemble import assemble
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        a = assemble(p)
+        M = precond.build(p, a, "BGS")
+        t_setup = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        r = krylov.fgmres(a.A, a.b, M, tol=1e-8, m=30)
+        t_solve = time.perf_counter() - t0
+    return dict(value=1.0 / t_solve, unit="solves/s", cores=1, kind="oracle",
+                sample=f"one full FP64 solve of the same workload (oracle FGMRES, "
+                       f"{r.iters} iterations, {t_solve:.1f} s; assembly+AMG setup "
+                       f"{t_setup:.1f} s not included), 1 thread")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the solver has no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from sdinputs import channel_problem
+    from paper_2108_13229_amd import sd
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    p = channel_problem(args.nx, args.ny, seed=args.seed)
+    t0 = time.perf_counter()
+    P = sd.Problem(p, device=True)
+    t_asm = time.perf_counter() - t0
+    res = {}
+    for prec in (["fp64"] if args.no_mixed else ["fp64", "mixed"]):
+        t0 = time.perf_counter()
+        S = sd.Solver(P, precond="BGS", schur="mass", tol=1e-8, restart=args.restart,
+                      precision=prec)
+        t_setup = time.perf_counter() - t0
+        lat, its, st, x = run_solves(S, args.steps, args.warmup)
+        res[prec] = dict(solves_per_s=float(len(lat) / lat.sum()),
+                         ms_per_solve=float(1e3 * lat.mean()),
+                         p50_ms=float(1e3 * np.percentile(lat, 50)),
+                         p99_ms=float(1e3 * np.percentile(lat, 99)),
+                         iters=int(np.median(its)), restarts=st["restarts"],
+                         rel_res=st["rel_res"], setup_s=t_setup)
+        S.close()
+    head = res[args.precision]
+    out = {
+        "metric": "Stokes-Darcy solves/s to rel. residual 1e-8 (mixed vs FP64), p50/p99 latency",
+        "value": head["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_solve"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD if (args.nx, args.ny) == (512, 256)
+                   else f"{args.nx}x{args.ny} channel", "N": P.N, "nnz": P.nnz,
+                   "assembly_s": t_asm},
+        "p50_ms": head["p50_ms"],
+        "p99_ms": head["p99_ms"],
+        "fp64": res.get("fp64"),
+        "mixed": res.get("mixed"),
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(p)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -134,7 +134,7 @@ enum { SD_AMG_PLAIN = 0, SD_AMG_SMOOTHED = 1 };
 
 typedef struct {
   int krylov;        /* SD_KRYLOV_*                                            */
-  int restart;       /* FGMRES restart length m (1..64), default 30            */
+  int restart;       /* FGMRES restart length m (1..63), default 30            */
   int maxit;         /* total iteration cap, default 1000                      */
   double tol;        /* relative true FP64 residual ||b-Ax||/||b||             */
   int precond;       /* SD_PREC_BJ | SD_PREC_BGS                               */
@@ -145,7 +145,7 @@ typedef struct {
   double theta;      /* strength threshold, default 0.08                       */
   double omega;      /* Jacobi damping, default 2/3                            */
   int nu_pre, nu_post; /* Jacobi sweeps, default 2 / 2                         */
-  int coarse_max;    /* coarsest level size bound, default 256                 */
+  int coarse_max;    /* coarsest level size bound (dense inverse), default 2048 */
   int max_levels;    /* default 20                                             */
 } sd_solver_opts;
 

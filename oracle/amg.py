@@ -54,7 +54,7 @@ class AMGOptions:
     omega: float = 2.0 / 3.0
     nu_pre: int = 2
     nu_post: int = 2
-    coarse_max: int = 256
+    coarse_max: int = 2048
     max_levels: int = 20
     min_ratio: float = 1.2
     smoothed: bool = True        # smoothed (True) or plain (False) aggregation

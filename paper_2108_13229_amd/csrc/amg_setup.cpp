@@ -16,11 +16,12 @@
 //              P = (I - w D^-1 A_F) P_t with A_F = diagonal + strong entries,
 //              w = 4 / (3 rho), rho = max_i sum_j |a_F,ij| / |a_ii|;
 //              R = P^T; A_c = R (A P) with Gustavson-ordered sums;
-//   coarsest   dense LU with partial pivoting and explicit inverse.
+//   coarsest   dense blocked LU with partial pivoting and explicit inverse.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <thread>
 
 #include "sd_internal.h"
 
@@ -275,45 +276,97 @@ HostCSR spgemm(const HostCSR& X, const HostCSR& Y) {
   return Z;
 }
 
+// Run f(begin, end) over [r0, r1) split into contiguous chunks on threads.
+template <typename F>
+void parallel_rows(int64_t r0, int64_t r1, F&& f) {
+  const int64_t cnt = r1 - r0;
+  if (cnt <= 0) return;
+  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const int64_t nt = std::min<int64_t>(hw, (cnt + 63) / 64);
+  if (nt <= 1) {
+    f(r0, r1);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int64_t chunk = (cnt + nt - 1) / nt;
+  for (int64_t t = 0; t < nt; ++t) {
+    const int64_t a = r0 + t * chunk, b = std::min(r1, a + chunk);
+    if (a < b) th.emplace_back(f, a, b);
+  }
+  for (auto& x : th) x.join();
+}
+
+// Blocked right-looking LU with partial pivoting (row interchanges), then the
+// explicit inverse from L U X = P I.  Rows of each update are independent, so
+// the result does not depend on the thread count.
 void dense_inverse(std::vector<double>& M, int64_t n, std::vector<double>& inv) {
-  // LU with partial pivoting (row interchanges), then solve for the identity.
+  const int64_t NB = 64;
   std::vector<int64_t> piv((size_t)n);
-  for (int64_t k = 0; k < n; ++k) {
-    int64_t p = k;
-    double best = std::fabs(M[k * n + k]);
-    for (int64_t r = k + 1; r < n; ++r)
-      if (std::fabs(M[r * n + k]) > best) {
-        best = std::fabs(M[r * n + k]);
-        p = r;
+  for (int64_t kb = 0; kb < n; kb += NB) {
+    const int64_t ke = std::min(n, kb + NB);
+    for (int64_t k = kb; k < ke; ++k) {
+      int64_t p = k;
+      double best = std::fabs(M[k * n + k]);
+      for (int64_t r = k + 1; r < n; ++r)
+        if (std::fabs(M[r * n + k]) > best) {
+          best = std::fabs(M[r * n + k]);
+          p = r;
+        }
+      if (!(best > 0.0) || !std::isfinite(best))
+        throw Error(SD_E_BREAKDOWN, "AMG: singular coarsest operator");
+      piv[k] = p;
+      if (p != k)
+        for (int64_t c = 0; c < n; ++c) std::swap(M[k * n + c], M[p * n + c]);
+      const double inv_piv = 1.0 / M[k * n + k];
+      for (int64_t r = k + 1; r < n; ++r) {
+        const double l = M[r * n + k] * inv_piv;
+        M[r * n + k] = l;
+        if (l != 0.0)
+          for (int64_t c = k + 1; c < ke; ++c) M[r * n + c] -= l * M[k * n + c];
       }
-    if (!(best > 0.0) || !std::isfinite(best))
-      throw Error(SD_E_BREAKDOWN, "AMG: singular coarsest operator");
-    piv[k] = p;
-    if (p != k)
-      for (int64_t c = 0; c < n; ++c) std::swap(M[k * n + c], M[p * n + c]);
-    const double inv_piv = 1.0 / M[k * n + k];
-    for (int64_t r = k + 1; r < n; ++r) {
-      const double l = M[r * n + k] * inv_piv;
-      M[r * n + k] = l;
-      if (l != 0.0)
-        for (int64_t c = k + 1; c < n; ++c) M[r * n + c] -= l * M[k * n + c];
     }
+    // U12 = L11^-1 A12 (unit lower triangular)
+    for (int64_t k = kb; k < ke; ++k)
+      for (int64_t r = k + 1; r < ke; ++r) {
+        const double l = M[r * n + k];
+        if (l != 0.0)
+          for (int64_t c = ke; c < n; ++c) M[r * n + c] -= l * M[k * n + c];
+      }
+    // A22 -= L21 U12
+    parallel_rows(ke, n, [&](int64_t a, int64_t b) {
+      for (int64_t r = a; r < b; ++r)
+        for (int64_t k = kb; k < ke; ++k) {
+          const double l = M[r * n + k];
+          if (l == 0.0) continue;
+          double* dst = &M[r * n];
+          const double* src = &M[k * n];
+          for (int64_t c = ke; c < n; ++c) dst[c] -= l * src[c];
+        }
+    });
   }
+  std::vector<int64_t> perm((size_t)n);
+  for (int64_t i = 0; i < n; ++i) perm[i] = i;
+  for (int64_t k = 0; k < n; ++k) std::swap(perm[k], perm[piv[k]]);
   inv.assign((size_t)(n * n), 0.0);
-  std::vector<double> y((size_t)n);
-  for (int64_t e = 0; e < n; ++e) {
-    // permuted unit vector
-    for (int64_t r = 0; r < n; ++r) y[r] = (r == e) ? 1.0 : 0.0;
-    for (int64_t k = 0; k < n; ++k)
-      if (piv[k] != k) std::swap(y[k], y[piv[k]]);
+  for (int64_t r = 0; r < n; ++r) inv[r * n + perm[r]] = 1.0;
+  // columns are independent: forward (unit L) and backward (U) substitution
+  parallel_rows(0, n, [&](int64_t c0, int64_t c1) {
     for (int64_t r = 0; r < n; ++r)
-      for (int64_t c = 0; c < r; ++c) y[r] -= M[r * n + c] * y[c];
+      for (int64_t k = 0; k < r; ++k) {
+        const double l = M[r * n + k];
+        if (l == 0.0) continue;
+        for (int64_t c = c0; c < c1; ++c) inv[r * n + c] -= l * inv[k * n + c];
+      }
     for (int64_t r = n - 1; r >= 0; --r) {
-      for (int64_t c = r + 1; c < n; ++c) y[r] -= M[r * n + c] * y[c];
-      y[r] /= M[r * n + r];
+      for (int64_t k = r + 1; k < n; ++k) {
+        const double u = M[r * n + k];
+        if (u == 0.0) continue;
+        for (int64_t c = c0; c < c1; ++c) inv[r * n + c] -= u * inv[k * n + c];
+      }
+      const double d = M[r * n + r];
+      for (int64_t c = c0; c < c1; ++c) inv[r * n + c] /= d;
     }
-    for (int64_t r = 0; r < n; ++r) inv[r * n + e] = y[r];
-  }
+  });
 }
 
 }  // namespace

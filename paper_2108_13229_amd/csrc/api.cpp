@@ -92,7 +92,7 @@ void sd_solver_opts_default(sd_solver_opts* o) {
   o->omega = 2.0 / 3.0;
   o->nu_pre = 2;
   o->nu_post = 2;
-  o->coarse_max = 256;
+  o->coarse_max = 2048;
   o->max_levels = 20;
 }
 

@@ -7,10 +7,10 @@
 
 namespace sd {
 
-constexpr int kMaxBasis = 32;       // FGMRES basis vectors held in registers (m <= 31)
+constexpr int kMaxBasis = 64;       // FGMRES basis vectors (restart m <= 63)
 constexpr int kBlock = 256;         // threads per workgroup (4 wavefronts)
 constexpr int kDotBlocks = 512;     // workgroups of the fused reduction kernels
-constexpr int kPartStride = kMaxBasis + 4;
+constexpr int kPartStride = kMaxBasis + 4;   // partial-sum rows (k-major, kDotBlocks each)
 
 // Sliced ELLPACK with 64-row slices (one wavefront per slice).  Entry (r, k)
 // of slice s lives at sptr[s] + 64 k + (r - 64 s); padding has val = 0.
@@ -80,17 +80,15 @@ template <typename T>
 void launch_block_sweep(const Sell<T>& Cf, int n_p, const double* r, const double* bscale,
                         const T* yv, double xscale, T* zp, T* tq, const DevState* gate,
                         hipStream_t s);
-// Fused Arnoldi kernels for column j (FP64 basis V, leading dimension ldv):
-//   w = A z, h1 = sigma .* (V^T w)                       (spmv + first dot pass)
-//   w -= V (sigma .* h1), h2 = sigma .* (V^T w)          (second Gram-Schmidt pass)
-//   V[j+1] = w - V (sigma .* h2), ||V[j+1]||, Givens     (update, norm, rotations)
+// One Arnoldi step for column j (FP64 basis V, leading dimension ldv; the
+// basis is stored unnormalised, vector k being sigma[k] * V[k]):
+//   w = A z, h1 = sigma .* (V^T w)                     (spmv + first dot pass)
+//   w -= V (sigma .* h1), h2 = sigma .* (V^T w)        (second Gram-Schmidt pass)
+//   V[j+1] = w - V (sigma .* h2), ||V[j+1]||, Givens   (update, norm, rotations)
+// All kernels return immediately once st->cycle_done is set.
 template <typename TM, typename TZ>
-void launch_arnoldi_j(const Sell<TM>& A, const TZ* z, double* W, const double* V, int64_t ldv,
-                      int j, DevState* st, double* part, hipStream_t s);
-void launch_cgs_dots_j(double* W, const double* V, int64_t ldv, int n, int j, DevState* st,
-                       double* part, hipStream_t s);
-void launch_cgs_norm_j(const double* W, double* V, int64_t ldv, int n, int j, DevState* st,
-                       double* part, HostFlags* hf, hipStream_t s);
+void launch_arnoldi_step(const Sell<TM>& A, const TZ* z, double* W, double* V, int64_t ldv,
+                         int j, DevState* st, double* part, HostFlags* hf, hipStream_t s);
 void launch_trisolve(DevState* st, hipStream_t s);
 template <typename TZ>
 void launch_update_x(double* x, const TZ* Z, int64_t ldz, int n, DevState* st,

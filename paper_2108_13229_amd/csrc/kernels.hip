@@ -8,10 +8,12 @@
 //   * workgroup indices are remapped so that each of the 8 XCDs streams a
 //     contiguous range of rows (neighbouring rows share x entries in its L2);
 //   * reductions are two-stage and deterministic: wavefront shuffles, then
-//     LDS across the 4 wavefronts of a workgroup, then per-workgroup partials
-//     summed in a fixed order by the last workgroup to finish (an atomic
-//     ticket), which also performs the scalar follow-up work (Givens
-//     rotations, scale factors), saving a launch per reduction.
+//     LDS across the 4 wavefronts of a workgroup, then the per-workgroup
+//     partials are summed in a fixed order by a one-workgroup kernel that also
+//     does the scalar follow-up work (Givens rotations, scale factors).  A
+//     grid-wide "last workgroup" ticket would need an agent-scope release
+//     fence in every workgroup, which on this chip writes back the XCD's whole
+//     L2; a kernel boundary is far cheaper.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -52,7 +54,8 @@ __device__ __forceinline__ T load_b(const TB* __restrict__ b, double s, int i) {
   return (T)((double)b[i] * s);
 }
 
-// Sum the first nv entries of acc over the workgroup into part[block].
+// Sum the first nv entries of acc over the workgroup into the k-major
+// partial buffer: part[k * kDotBlocks + block].
 template <int NV>
 __device__ __forceinline__ void block_partials(const double (&acc)[NV], int nv, double* part) {
   __shared__ double red[kBlock / 64][NV];
@@ -67,27 +70,12 @@ __device__ __forceinline__ void block_partials(const double (&acc)[NV], int nv, 
   __syncthreads();
   if ((int)threadIdx.x < nv) {
     const int k = threadIdx.x;
-    part[(size_t)blockIdx.x * kPartStride + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
-    __threadfence();
+    part[(size_t)k * kDotBlocks + blockIdx.x] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
   }
-  __syncthreads();
 }
 
-// True in exactly one workgroup: the last to arrive at the ticket.
-__device__ __forceinline__ bool last_block(unsigned int* counter) {
-  __shared__ int s_last;
-  if (threadIdx.x == 0) {
-    const unsigned prev = atomicAdd(counter, 1u);
-    s_last = prev == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (!s_last) return false;
-  __threadfence();
-  return true;
-}
-
-// In the last workgroup: out[k] = sum over workgroups of part[b][k], k < nv,
-// in a fixed order; result left in out_sh (shared) for thread use.
+// Whole workgroup: out_sh[k] = sum over b < nb of part[k * kDotBlocks + b],
+// k < nv, in a fixed order (identical in every workgroup that calls it).
 template <int NV>
 __device__ __forceinline__ void final_sums(const double* part, int nb, int nv, double* out_sh) {
   __shared__ double red[kBlock / 64][NV];
@@ -96,10 +84,9 @@ __device__ __forceinline__ void final_sums(const double* part, int nb, int nv, d
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k] = 0.0;
   for (int b = threadIdx.x; b < nb; b += kBlock) {
-    const double* p = part + (size_t)b * kPartStride;
 #pragma unroll
     for (int k = 0; k < NV; ++k)
-      if (k < nv) acc[k] += p[k];
+      if (k < nv) acc[k] += part[(size_t)k * kDotBlocks + b];
   }
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
@@ -230,82 +217,101 @@ __global__ __launch_bounds__(kBlock) void k_block_sweep(Sell<T> Cf, int n_p,
     tq[row - n_p] = t;
 }
 
-template <typename TM, typename TZ>
-__global__ __launch_bounds__(kBlock) void k_arnoldi_spmv_dots(Sell<TM> A, const TZ* __restrict__ z,
-                                                              double* __restrict__ W,
-                                                              const double* __restrict__ V,
-                                                              int64_t ldv, int j, int R,
-                                                              DevState* st, double* part) {
+// ---- Arnoldi step j: (1) w = A z_j with partial dots V^T w; (2) reduce
+// them in every workgroup, w -= V c, partial dots; (3) reduce, V[j+1] =
+// w - V c2, partial squared norm; (4) finish: norm, Hessenberg column,
+// Givens rotation, convergence flag.  Partials are summed in a fixed order;
+// kernel boundaries order the memory traffic, so no grid-wide fences are
+// needed.  MV is the register-array width (basis vectors per row).
+
+template <int MV, typename TM, typename TZ>
+__global__ __launch_bounds__(kBlock) void k_arn_spmv_dots(Sell<TM> A, const TZ* __restrict__ z,
+                                                          double* __restrict__ W,
+                                                          const double* __restrict__ V,
+                                                          int64_t ldv, int j, int R,
+                                                          const DevState* st, double* part) {
   if (st->cycle_done) return;
   const int n = A.n_rows;
   const int G = gridDim.x * kBlock;
   const int gtid = blockIdx.x * kBlock + threadIdx.x;
-  double acc[kMaxBasis];
+  double acc[MV];
 #pragma unroll
-  for (int k = 0; k < kMaxBasis; ++k) acc[k] = 0.0;
+  for (int k = 0; k < MV; ++k) acc[k] = 0.0;
   for (int t = 0; t < R; ++t) {
     const int row = gtid + t * G;
     if (row < n) {
       const double w = (double)sell_dot(A, z, row);
       W[row] = w;
 #pragma unroll
-      for (int k = 0; k < kMaxBasis; ++k)
+      for (int k = 0; k < MV; ++k)
         if (k <= j) acc[k] += V[(size_t)k * ldv + row] * w;
     }
   }
-  block_partials<kMaxBasis>(acc, j + 1, part);
-  if (!last_block(&st->counter[0])) return;
-  __shared__ double sums[kMaxBasis];
-  final_sums<kMaxBasis>(part, gridDim.x, j + 1, sums);
-  if ((int)threadIdx.x <= j) st->h1[threadIdx.x] = st->sigma[threadIdx.x] * sums[threadIdx.x];
-  if (threadIdx.x == 0) st->counter[0] = 0;
+  block_partials<MV>(acc, j + 1, part);
 }
 
-__global__ __launch_bounds__(kBlock) void k_cgs_axpy_dots(double* __restrict__ W,
-                                                          const double* __restrict__ V,
-                                                          int64_t ldv, int n, int j, int R,
-                                                          DevState* st, double* part) {
-  if (st->cycle_done) return;
-  __shared__ double c[kMaxBasis];
-  if ((int)threadIdx.x <= j) c[threadIdx.x] = st->h1[threadIdx.x] * st->sigma[threadIdx.x];
+// c[k] = sigma_k * h_k with h_k = sigma_k * (partial-dot sum); workgroup 0
+// records h in st (hsel 1: h1, 2: h2).
+template <int MV>
+__device__ __forceinline__ void coefficients(const double* part, int nb, int j, DevState* st,
+                                             int hsel, double* c) {
+  __shared__ double sums[MV];
+  final_sums<MV>(part, nb, j + 1, sums);
+  if ((int)threadIdx.x <= j) {
+    const double sg = st->sigma[threadIdx.x];
+    const double h = sg * sums[threadIdx.x];
+    c[threadIdx.x] = h * sg;
+    if (blockIdx.x == 0) {
+      if (hsel == 1)
+        st->h1[threadIdx.x] = h;
+      else
+        st->h2[threadIdx.x] = h;
+    }
+  }
   __syncthreads();
+}
+
+template <int MV>
+__global__ __launch_bounds__(kBlock) void k_cgs_pass2(double* __restrict__ W,
+                                                      const double* __restrict__ V, int64_t ldv,
+                                                      int n, int j, int R, int nb_in,
+                                                      DevState* st, const double* part_in,
+                                                      double* part) {
+  if (st->cycle_done) return;
+  __shared__ double c[MV];
+  coefficients<MV>(part_in, nb_in, j, st, 1, c);
   const int G = gridDim.x * kBlock;
   const int gtid = blockIdx.x * kBlock + threadIdx.x;
-  double acc[kMaxBasis];
+  double acc[MV];
 #pragma unroll
-  for (int k = 0; k < kMaxBasis; ++k) acc[k] = 0.0;
+  for (int k = 0; k < MV; ++k) acc[k] = 0.0;
   for (int t = 0; t < R; ++t) {
     const int row = gtid + t * G;
     if (row < n) {
-      double v[kMaxBasis];
+      double v[MV];
 #pragma unroll
-      for (int k = 0; k < kMaxBasis; ++k) v[k] = (k <= j) ? V[(size_t)k * ldv + row] : 0.0;
+      for (int k = 0; k < MV; ++k) v[k] = (k <= j) ? V[(size_t)k * ldv + row] : 0.0;
       double w = W[row];
 #pragma unroll
-      for (int k = 0; k < kMaxBasis; ++k)
+      for (int k = 0; k < MV; ++k)
         if (k <= j) w -= c[k] * v[k];
       W[row] = w;
 #pragma unroll
-      for (int k = 0; k < kMaxBasis; ++k)
+      for (int k = 0; k < MV; ++k)
         if (k <= j) acc[k] += v[k] * w;
     }
   }
-  block_partials<kMaxBasis>(acc, j + 1, part);
-  if (!last_block(&st->counter[1])) return;
-  __shared__ double sums[kMaxBasis];
-  final_sums<kMaxBasis>(part, gridDim.x, j + 1, sums);
-  if ((int)threadIdx.x <= j) st->h2[threadIdx.x] = st->sigma[threadIdx.x] * sums[threadIdx.x];
-  if (threadIdx.x == 0) st->counter[1] = 0;
+  block_partials<MV>(acc, j + 1, part);
 }
 
-__global__ __launch_bounds__(kBlock) void k_cgs_axpy_norm(const double* __restrict__ W,
-                                                          double* __restrict__ V, int64_t ldv,
-                                                          int n, int j, int R, DevState* st,
-                                                          double* part, HostFlags* hf) {
+template <int MV>
+__global__ __launch_bounds__(kBlock) void k_cgs_pass3(const double* __restrict__ W,
+                                                      double* __restrict__ V, int64_t ldv, int n,
+                                                      int j, int R, int nb_in, DevState* st,
+                                                      const double* part_in, double* part) {
   if (st->cycle_done) return;
-  __shared__ double c[kMaxBasis];
-  if ((int)threadIdx.x <= j) c[threadIdx.x] = st->h2[threadIdx.x] * st->sigma[threadIdx.x];
-  __syncthreads();
+  __shared__ double c[MV];
+  coefficients<MV>(part_in, nb_in, j, st, 2, c);
   const int G = gridDim.x * kBlock;
   const int gtid = blockIdx.x * kBlock + threadIdx.x;
   double acc[1] = {0.0};
@@ -315,52 +321,54 @@ __global__ __launch_bounds__(kBlock) void k_cgs_axpy_norm(const double* __restri
     if (row < n) {
       double w = W[row];
 #pragma unroll
-      for (int k = 0; k < kMaxBasis; ++k)
+      for (int k = 0; k < MV; ++k)
         if (k <= j) w -= c[k] * V[(size_t)k * ldv + row];
       vn[row] = w;
       acc[0] += w * w;
     }
   }
   block_partials<1>(acc, 1, part);
-  if (!last_block(&st->counter[2])) return;
+}
+
+__global__ __launch_bounds__(kBlock) void k_arn_finish(const double* part, int nb, int j,
+                                                       DevState* st, HostFlags* hf) {
+  if (st->cycle_done) return;
   __shared__ double sums[1];
-  final_sums<1>(part, gridDim.x, 1, sums);
-  if (threadIdx.x == 0) {
-    const int ld = kMaxBasis + 1;
-    double* H = st->H + (size_t)j * ld;
-    const double hn = sqrt(sums[0]);
-    for (int i = 0; i <= j; ++i) H[i] = st->h1[i] + st->h2[i];
-    H[j + 1] = hn;
-    for (int i = 0; i < j; ++i) {
-      const double t = st->cs[i] * H[i] + st->sn[i] * H[i + 1];
-      H[i + 1] = -st->sn[i] * H[i] + st->cs[i] * H[i + 1];
-      H[i] = t;
-    }
-    const double d = hypot(H[j], H[j + 1]);
-    int bad = !(d > 0.0) || !isfinite(d);
-    const double cj = bad ? 1.0 : H[j] / d;
-    const double sj = bad ? 0.0 : H[j + 1] / d;
-    st->cs[j] = cj;
-    st->sn[j] = sj;
-    H[j] = bad ? H[j] : d;
-    H[j + 1] = 0.0;
-    st->g[j + 1] = -sj * st->g[j];
-    st->g[j] = cj * st->g[j];
-    const double est = fabs(st->g[j + 1]);
-    bad = bad || !isfinite(est);
-    st->sigma[j + 1] = 1.0 / hn;
-    st->k = j + 1;
-    st->j = j + 1;
-    st->iters += 1;
-    if (bad) st->breakdown = 1;
-    const int done = bad || !(hn > 0.0) || est <= st->cycle_target || (j + 1) >= st->m;
-    st->cycle_done = done;
-    if (hf) {
-      hf->est[j] = est;
-      hf->cycle_done[j] = done;
-      __threadfence_system();
-    }
-    st->counter[2] = 0;
+  final_sums<1>(part, nb, 1, sums);
+  if (threadIdx.x != 0) return;
+  const int ld = kMaxBasis + 1;
+  double* H = st->H + (size_t)j * ld;
+  const double hn = sqrt(sums[0]);
+  for (int i = 0; i <= j; ++i) H[i] = st->h1[i] + st->h2[i];
+  H[j + 1] = hn;
+  for (int i = 0; i < j; ++i) {
+    const double t = st->cs[i] * H[i] + st->sn[i] * H[i + 1];
+    H[i + 1] = -st->sn[i] * H[i] + st->cs[i] * H[i + 1];
+    H[i] = t;
+  }
+  const double d = hypot(H[j], H[j + 1]);
+  int bad = !(d > 0.0) || !isfinite(d);
+  const double cj = bad ? 1.0 : H[j] / d;
+  const double sj = bad ? 0.0 : H[j + 1] / d;
+  st->cs[j] = cj;
+  st->sn[j] = sj;
+  H[j] = bad ? H[j] : d;
+  H[j + 1] = 0.0;
+  st->g[j + 1] = -sj * st->g[j];
+  st->g[j] = cj * st->g[j];
+  const double est = fabs(st->g[j + 1]);
+  bad = bad || !isfinite(est);
+  st->sigma[j + 1] = 1.0 / hn;
+  st->k = j + 1;
+  st->j = j + 1;
+  st->iters += 1;
+  if (bad) st->breakdown = 1;
+  const int done = bad || !(hn > 0.0) || est <= st->cycle_target || (j + 1) >= st->m;
+  st->cycle_done = done;
+  if (hf) {
+    hf->est[j] = est;
+    hf->cycle_done[j] = done;
+    __threadfence_system();
   }
 }
 
@@ -391,8 +399,7 @@ __global__ __launch_bounds__(kBlock) void k_restart_residual(Sell<double> A,
                                                              const double* __restrict__ b,
                                                              const double* __restrict__ x,
                                                              double* __restrict__ r, int off_p,
-                                                             int off_q, int R, DevState* st,
-                                                             double* part, HostFlags* hf) {
+                                                             int off_q, int R, double* part) {
   const int n = A.n_rows;
   const int G = gridDim.x * kBlock;
   const int gtid = blockIdx.x * kBlock + threadIdx.x;
@@ -407,34 +414,35 @@ __global__ __launch_bounds__(kBlock) void k_restart_residual(Sell<double> A,
     }
   }
   block_partials<3>(acc, 3, part);
-  if (!last_block(&st->counter[3])) return;
+}
+
+__global__ __launch_bounds__(kBlock) void k_restart_finish(const double* part, int nb,
+                                                           DevState* st, HostFlags* hf) {
   __shared__ double sums[3];
-  final_sums<3>(part, gridDim.x, 3, sums);
-  if (threadIdx.x == 0) {
-    for (int k = 0; k < 3; ++k) st->resblk[k] = sums[k];
-    const double beta = sqrt((sums[0] + sums[1]) + sums[2]);
-    st->beta = beta;
-    st->sigma[0] = 1.0 / beta;
-    st->g[0] = beta;
-    st->j = 0;
-    st->k = 0;
-    const int fin = isfinite(beta);
-    const int conv = fin && beta <= st->target;
-    st->converged = conv;
-    if (!fin) st->breakdown = 1;
-    st->cycle_done = conv || !fin || !(beta > 0.0);
-    const double ct = st->cycle_drop * beta;
-    st->cycle_target = ct > st->target ? ct : st->target;
-    if (hf) {
-      hf->est[kMaxBasis + 1] = beta;
-      __threadfence_system();
-    }
-    st->counter[3] = 0;
+  final_sums<3>(part, nb, 3, sums);
+  if (threadIdx.x != 0) return;
+  for (int k = 0; k < 3; ++k) st->resblk[k] = sums[k];
+  const double beta = sqrt((sums[0] + sums[1]) + sums[2]);
+  st->beta = beta;
+  st->sigma[0] = 1.0 / beta;
+  st->g[0] = beta;
+  st->j = 0;
+  st->k = 0;
+  const int fin = isfinite(beta);
+  const int conv = fin && beta <= st->target;
+  st->converged = conv;
+  if (!fin) st->breakdown = 1;
+  st->cycle_done = conv || !fin || !(beta > 0.0);
+  const double ct = st->cycle_drop * beta;
+  st->cycle_target = ct > st->target ? ct : st->target;
+  if (hf) {
+    hf->est[kMaxBasis + 1] = beta;
+    __threadfence_system();
   }
 }
 
 __global__ __launch_bounds__(kBlock) void k_norm_b(const double* __restrict__ b, int n, int R,
-                                                   double tol, DevState* st, double* part) {
+                                                   double* part) {
   const int G = gridDim.x * kBlock;
   const int gtid = blockIdx.x * kBlock + threadIdx.x;
   double acc[1] = {0.0};
@@ -443,13 +451,15 @@ __global__ __launch_bounds__(kBlock) void k_norm_b(const double* __restrict__ b,
     if (row < n) acc[0] += b[row] * b[row];
   }
   block_partials<1>(acc, 1, part);
-  if (!last_block(&st->counter[4])) return;
+}
+
+__global__ __launch_bounds__(kBlock) void k_norm_b_finish(const double* part, int nb, double tol,
+                                                          DevState* st) {
   __shared__ double sums[1];
-  final_sums<1>(part, gridDim.x, 1, sums);
+  final_sums<1>(part, nb, 1, sums);
   if (threadIdx.x == 0) {
     st->bnorm = sqrt(sums[0]);
     st->target = tol * st->bnorm;
-    st->counter[4] = 0;
   }
 }
 
@@ -545,30 +555,28 @@ void launch_block_sweep(const Sell<T>& Cf, int n_p, const double* r, const doubl
                                                             tq, gate);
 }
 
-// Explicit-j variants used by the solver.
-template <typename TM, typename TZ>
-void launch_arnoldi_j(const Sell<TM>& A, const TZ* z, double* W, const double* V, int64_t ldv,
-                      int j, DevState* st, double* part, hipStream_t s) {
+template <int MV, typename TM, typename TZ>
+static void arnoldi_step(const Sell<TM>& A, const TZ* z, double* W, double* V, int64_t ldv, int j,
+                         DevState* st, double* part, HostFlags* hf, hipStream_t s) {
   const int n = A.n_rows;
   const int nb = dot_blocks(n);
   const int R = (n + nb * kBlock - 1) / (nb * kBlock);
-  k_arnoldi_spmv_dots<TM, TZ><<<nb, kBlock, 0, s>>>(A, z, W, V, ldv, j, R, st, part);
+  double* p1 = part;
+  double* p2 = part + (size_t)kDotBlocks * kPartStride;
+  k_arn_spmv_dots<MV, TM, TZ><<<nb, kBlock, 0, s>>>(A, z, W, V, ldv, j, R, st, p1);
+  k_cgs_pass2<MV><<<nb, kBlock, 0, s>>>(W, V, ldv, n, j, R, nb, st, p1, p2);
+  k_cgs_pass3<MV><<<nb, kBlock, 0, s>>>(W, V, ldv, n, j, R, nb, st, p2, p1);
+  k_arn_finish<<<1, kBlock, 0, s>>>(p1, nb, j, st, hf);
 }
 
-void launch_cgs_dots_j(double* W, const double* V, int64_t ldv, int n, int j, DevState* st,
-                       double* part, hipStream_t s) {
-  const int nb = dot_blocks(n);
-  const int R = (n + nb * kBlock - 1) / (nb * kBlock);
-  k_cgs_axpy_dots<<<nb, kBlock, 0, s>>>(W, V, ldv, n, j, R, st, part);
+template <typename TM, typename TZ>
+void launch_arnoldi_step(const Sell<TM>& A, const TZ* z, double* W, double* V, int64_t ldv, int j,
+                         DevState* st, double* part, HostFlags* hf, hipStream_t s) {
+  if (j + 1 <= 32)
+    arnoldi_step<32, TM, TZ>(A, z, W, V, ldv, j, st, part, hf, s);
+  else
+    arnoldi_step<kMaxBasis, TM, TZ>(A, z, W, V, ldv, j, st, part, hf, s);
 }
-
-void launch_cgs_norm_j(const double* W, double* V, int64_t ldv, int n, int j, DevState* st,
-                       double* part, HostFlags* hf, hipStream_t s) {
-  const int nb = dot_blocks(n);
-  const int R = (n + nb * kBlock - 1) / (nb * kBlock);
-  k_cgs_axpy_norm<<<nb, kBlock, 0, s>>>(W, V, ldv, n, j, R, st, part, hf);
-}
-
 
 void launch_trisolve(DevState* st, hipStream_t s) { k_trisolve<<<1, 64, 0, s>>>(st); }
 
@@ -584,15 +592,16 @@ void launch_restart_residual(const Sell<double>& A, const double* b, const doubl
   const int n = A.n_rows;
   const int nb = dot_blocks(n);
   const int R = (n + nb * kBlock - 1) / (nb * kBlock);
-  k_restart_residual<<<nb, kBlock, 0, s>>>(A, b, x, r, (int)blk_off[2], (int)blk_off[3], R, st,
-                                            part, hf);
+  k_restart_residual<<<nb, kBlock, 0, s>>>(A, b, x, r, (int)blk_off[2], (int)blk_off[3], R, part);
+  k_restart_finish<<<1, kBlock, 0, s>>>(part, nb, st, hf);
 }
 
 void launch_norm_b(const double* b, int n, double tol, DevState* st, double* part,
                    hipStream_t s) {
   const int nb = dot_blocks(n);
   const int R = (n + nb * kBlock - 1) / (nb * kBlock);
-  k_norm_b<<<nb, kBlock, 0, s>>>(b, n, R, tol, st, part);
+  k_norm_b<<<nb, kBlock, 0, s>>>(b, n, R, part);
+  k_norm_b_finish<<<1, kBlock, 0, s>>>(part, nb, tol, st);
 }
 
 void launch_init_state(DevState* st, int m, double cycle_drop, hipStream_t s) {
@@ -653,12 +662,12 @@ template void launch_block_sweep<double>(const Sell<double>&, int, const double*
 template void launch_block_sweep<float>(const Sell<float>&, int, const double*, const double*,
                                         const float*, double, float*, float*, const DevState*,
                                         hipStream_t);
-template void launch_arnoldi_j<double, double>(const Sell<double>&, const double*, double*,
-                                               const double*, int64_t, int, DevState*, double*,
-                                               hipStream_t);
-template void launch_arnoldi_j<float, float>(const Sell<float>&, const float*, double*,
-                                             const double*, int64_t, int, DevState*, double*,
-                                             hipStream_t);
+template void launch_arnoldi_step<double, double>(const Sell<double>&, const double*, double*,
+                                                  double*, int64_t, int, DevState*, double*,
+                                                  HostFlags*, hipStream_t);
+template void launch_arnoldi_step<float, float>(const Sell<float>&, const float*, double*,
+                                                double*, int64_t, int, DevState*, double*,
+                                                HostFlags*, hipStream_t);
 template void launch_update_x<double>(double*, const double*, int64_t, int, DevState*,
                                       hipStream_t);
 template void launch_update_x<float>(double*, const float*, int64_t, int, DevState*,

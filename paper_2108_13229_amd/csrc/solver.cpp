@@ -115,7 +115,7 @@ void Solver::setup_host(HostProblem* p, const sd_solver_opts* o) {
   opts.o = o ? *o : d;
   const sd_solver_opts& so = opts.o;
   if (so.restart < 1 || so.restart > kMaxBasis - 1)
-    throw Error(SD_E_INVALID, "restart must be in 1..31");
+    throw Error(SD_E_INVALID, "restart must be in 1..63");
   if (!(so.tol > 0.0) || so.maxit < 1) throw Error(SD_E_INVALID, "tol > 0 and maxit >= 1 required");
   if (so.precond != SD_PREC_BJ && so.precond != SD_PREC_BGS) throw Error(SD_E_INVALID, "precond");
   if (so.schur != SD_SCHUR_IDENTITY && so.schur != SD_SCHUR_MASS) throw Error(SD_E_INVALID, "schur");
@@ -163,7 +163,11 @@ void Solver::setup_host(HostProblem* p, const sd_solver_opts* o) {
 }
 
 Solver::~Solver() {
+  prec.reset();
+  if (stream) (void)hipStreamSynchronize(stream);
   for (auto e : events) (void)hipEventDestroy(e);
+  if (ev_join) (void)hipEventDestroy(ev_join);
+  if (stream) (void)hipStreamDestroy(stream);
   if (hf) (void)hipHostFree((void*)hf);
 }
 
@@ -177,7 +181,7 @@ void Solver::upload(const sd_allocator* alloc, hipStream_t s) {
   const int m = opts.o.restart;
   V = mem->array<double>((size_t)(m + 1) * ldv);
   W = mem->array<double>((size_t)ldv);
-  part = mem->array<double>((size_t)kDotBlocks * kPartStride);
+  part = mem->array<double>((size_t)2 * kDotBlocks * kPartStride);
   st = static_cast<DevState*>(mem->get(sizeof(DevState)));
   SD_HIP(hipMemsetAsync(st, 0, sizeof(DevState), s));
   void* h = nullptr;
@@ -189,6 +193,8 @@ void Solver::upload(const sd_allocator* alloc, hipStream_t s) {
   hf_dev = static_cast<HostFlags*>(hd);
   events.resize((size_t)kMaxBasis + 2);
   for (auto& e : events) SD_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  SD_HIP(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+  SD_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
   prec = opts.o.precision == SD_PRECISION_MIXED ? make_prec_fp32(*this, s) : make_prec_fp64(*this, s);
   SD_HIP(hipStreamSynchronize(s));
   on_device = true;
@@ -347,7 +353,12 @@ class PrecImpl : public PrecBase {
   }
 
   int fgmres(Solver& S, const double* b, double* x, int use_x0, sd_stats* stats,
-             hipStream_t s) override {
+             hipStream_t user) override {
+    // The iteration runs on the solver's own stream (graphs cannot be captured
+    // on the legacy default stream); it is ordered after the caller's stream.
+    hipStream_t s = S.stream;
+    SD_HIP(hipEventRecord(S.ev_join, user));
+    SD_HIP(hipStreamWaitEvent(s, S.ev_join, 0));
     const double t0 = wall_time();
     const sd_solver_opts& o = S.opts.o;
     const int n = S.N;
@@ -391,24 +402,37 @@ class PrecImpl : public PrecBase {
         status = SD_E_NOCONV;
         break;
       }
-      for (int j = 0; j <= kMaxBasis; ++j) S.hf->cycle_done[j] = 0;
-      int j_enq = 0;
-      for (int j = 0; j < m_cycle; ++j) {
-        T* zj = Z + (size_t)j * ldz;
-        apply(S, S.V + (size_t)j * S.ldv, &S.st->sigma[j], zj, S.st, s);
-        launch_arnoldi_j<T, T>(Aarn, zj, S.W, S.V, S.ldv, j, S.st, S.part, s);
-        launch_cgs_dots_j(S.W, S.V, S.ldv, n, j, S.st, S.part, s);
-        launch_cgs_norm_j(S.W, S.V, S.ldv, n, j, S.st, S.part, S.hf_dev, s);
-        SD_HIP(hipEventRecord(S.events[(size_t)j], s));
-        j_enq = j + 1;
-        if (j >= depth) {
-          SD_HIP(hipEventSynchronize(S.events[(size_t)(j - depth)]));
-          bool done = false;
-          for (int q = 0; q <= j - depth; ++q) done = done || S.hf->cycle_done[q];
-          if (done) break;
-        }
+      for (int j = 0; j <= kMaxBasis; ++j) {
+        S.hf->cycle_done[j] = 0;
+        S.hf->est[j] = 0.0;
       }
-      (void)j_enq;
+      // Run ahead of the device by up to `depth` iterations, except when the
+      // residual estimates predict the end of the cycle within that window
+      // (iterations enqueued after the cycle ends only waste time; their
+      // Arnoldi kernels return at once, their preconditioner work is unused).
+      const double ctarget = std::max(hs.target, drop * hs.beta);
+      int waited = -1;
+      auto wait_upto = [&](int q) {
+        for (int r = waited + 1; r <= q; ++r) SD_HIP(hipEventSynchronize(S.events[(size_t)r]));
+        if (q > waited) waited = q;
+      };
+      for (int j = 0; j < m_cycle; ++j) {
+        int ahead = depth;
+        if (waited >= 1) {
+          const double e1 = S.hf->est[waited], e0 = S.hf->est[waited - 1];
+          const double rho = e0 > 0.0 ? e1 / e0 : 1.0;
+          if (rho > 0.0 && rho < 1.0) {
+            const double need = std::log(ctarget / e1) / std::log(rho);
+            if (need <= (double)(j - waited) + 1.0) ahead = 0;
+          }
+        }
+        if (j - 1 - ahead >= 0) wait_upto(j - 1 - ahead);
+        bool done = false;
+        for (int q = 0; q <= waited; ++q) done = done || S.hf->cycle_done[q];
+        if (done) break;
+        iteration(S, j, s);
+        SD_HIP(hipEventRecord(S.events[(size_t)j], s));
+      }
       launch_trisolve(S.st, s);
       launch_update_x<T>(x, Z, ldz, n, S.st, s);
       ++restarts;
@@ -421,6 +445,32 @@ class PrecImpl : public PrecBase {
     out.t_solve = wall_time() - t0;
     if (stats) *stats = out;
     return status;
+  }
+
+  // Enqueue Arnoldi step j (preconditioner + orthogonalisation) as a graph.
+  std::vector<hipGraphExec_t> graphs;
+  void iteration(Solver& S, int j, hipStream_t s) {
+    if (graphs.empty()) graphs.assign((size_t)kMaxBasis, nullptr);
+    if (!graphs[(size_t)j]) {
+      hipGraph_t g = nullptr;
+      SD_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      enqueue_iteration(S, j, s);
+      SD_HIP(hipStreamEndCapture(s, &g));
+      hipGraphExec_t ge = nullptr;
+      SD_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+      SD_HIP(hipGraphDestroy(g));
+      graphs[(size_t)j] = ge;
+    }
+    SD_HIP(hipGraphLaunch(graphs[(size_t)j], s));
+  }
+  void enqueue_iteration(Solver& S, int j, hipStream_t s) {
+    T* zj = Z + (size_t)j * ldz;
+    apply(S, S.V + (size_t)j * S.ldv, &S.st->sigma[j], zj, nullptr, s);
+    launch_arnoldi_step<T, T>(Aarn, zj, S.W, S.V, S.ldv, j, S.st, S.part, S.hf_dev, s);
+  }
+  ~PrecImpl() override {
+    for (auto g : graphs)
+      if (g) (void)hipGraphExecDestroy(g);
   }
 
   void launch_init_cycle(Solver& S, int m_cycle, hipStream_t s) {

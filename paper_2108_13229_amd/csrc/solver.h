@@ -101,6 +101,8 @@ class Solver {
   HostFlags* hf_dev = nullptr;      // the same memory as seen by kernels
   int64_t ldv = 0;
   std::vector<hipEvent_t> events;
+  hipEvent_t ev_join = nullptr;
+  hipStream_t stream = nullptr;     // internal non-blocking stream (default priority)
   std::unique_ptr<PrecBase> prec;
 
   ~Solver();

@@ -102,7 +102,7 @@ def test_invalid_inputs_are_rejected():
     p = channel_problem(16, 8, seed=1)
     P = sd.Problem(p, device=False)
     with pytest.raises(sd.SDError):
-        sd.Solver(P, device=False, restart=40)
+        sd.Solver(P, device=False, restart=64)
     with pytest.raises(sd.SDError):
         sd.Solver(P, device=False, tol=0.0)
     with pytest.raises(sd.SDError):
