@@ -11,6 +11,7 @@ constexpr int kMaxBasis = 64;       // FGMRES basis vectors (restart m <= 63)
 constexpr int kBlock = 256;         // threads per workgroup (4 wavefronts)
 constexpr int kDotBlocks = 512;     // workgroups of the fused reduction kernels
 constexpr int kPartStride = kMaxBasis + 4;   // partial-sum rows (k-major, kDotBlocks each)
+constexpr int kGsMaxBlocks = 1024;          // row blocks of the Gram-Schmidt kernels
 
 // Sliced ELLPACK with 64-row slices (one wavefront per slice).  Entry (r, k)
 // of slice s lives at sptr[s] + 64 k + (r - 64 s); padding has val = 0.

@@ -217,128 +217,226 @@ __global__ __launch_bounds__(kBlock) void k_block_sweep(Sell<T> Cf, int n_p,
     tq[row - n_p] = t;
 }
 
-// ---- Arnoldi step j: (1) w = A z_j with partial dots V^T w; (2) reduce
-// them in every workgroup, w -= V c, partial dots; (3) reduce, V[j+1] =
-// w - V c2, partial squared norm; (4) finish: norm, Hessenberg column,
-// Givens rotation, convergence flag.  Partials are summed in a fixed order;
-// kernel boundaries order the memory traffic, so no grid-wide fences are
-// needed.  MV is the register-array width (basis vectors per row).
+// ---- Arnoldi step j.  Multi-vector Gram-Schmidt passes use a row-block x
+// vector-per-wavefront layout: a workgroup of 16 wavefronts owns a block of
+// rows; wavefront w handles basis vectors w, w+16, w+32, w+48 over those rows
+// (one accumulator per vector and lane), so every basis entry is read once,
+// coalesced, with few registers.  Row sums across vectors (the axpy) go
+// through LDS.  Passes: (1) w = A z_j with partial dots V^T w; (2) reduce the
+// partials (every workgroup, same fixed order), w -= V c, partial dots;
+// (3) reduce, V[j+1] = w - V c2, partial squared norm; (4) finish: norm,
+// Hessenberg column, Givens rotation, convergence flag.
 
-template <int MV, typename TM, typename TZ>
-__global__ __launch_bounds__(kBlock) void k_arn_spmv_dots(Sell<TM> A, const TZ* __restrict__ z,
-                                                          double* __restrict__ W,
-                                                          const double* __restrict__ V,
-                                                          int64_t ldv, int j, int R,
-                                                          const DevState* st, double* part) {
-  if (st->cycle_done) return;
-  const int n = A.n_rows;
-  const int G = gridDim.x * kBlock;
-  const int gtid = blockIdx.x * kBlock + threadIdx.x;
-  double acc[MV];
-#pragma unroll
-  for (int k = 0; k < MV; ++k) acc[k] = 0.0;
-  for (int t = 0; t < R; ++t) {
-    const int row = gtid + t * G;
-    if (row < n) {
-      const double w = (double)sell_dot(A, z, row);
-      W[row] = w;
-#pragma unroll
-      for (int k = 0; k < MV; ++k)
-        if (k <= j) acc[k] += V[(size_t)k * ldv + row] * w;
-    }
-  }
-  block_partials<MV>(acc, j + 1, part);
-}
+constexpr int kGsThreads = 1024;
+constexpr int kGsWaves = kGsThreads / 64;
+constexpr int kGsVpw = kMaxBasis / kGsWaves;     // basis vectors per wavefront
+constexpr int kGsRound = 256;                     // rows per LDS round (4 per lane)
 
-// c[k] = sigma_k * h_k with h_k = sigma_k * (partial-dot sum); workgroup 0
-// records h in st (hsel 1: h1, 2: h2).
-template <int MV>
-__device__ __forceinline__ void coefficients(const double* part, int nb, int j, DevState* st,
-                                             int hsel, double* c) {
-  __shared__ double sums[MV];
-  final_sums<MV>(part, nb, j + 1, sums);
-  if ((int)threadIdx.x <= j) {
-    const double sg = st->sigma[threadIdx.x];
-    const double h = sg * sums[threadIdx.x];
-    c[threadIdx.x] = h * sg;
+// c[k] = sigma_k * h_k, h_k = sigma_k * sum_b part[k][b] (fixed order);
+// workgroup 0 records h in st (hsel 1: h1, 2: h2).
+__device__ __forceinline__ void gs_coefficients(const double* part, int nb, int j, DevState* st,
+                                                int hsel, double* c, double* scratch) {
+  const int t = threadIdx.x;
+  const int k = t >> 4, sub = t & 15;             // 64 k x 16 partial sums
+  double s = 0.0;
+  if (k <= j)
+    for (int b = sub; b < nb; b += 16) s += part[(size_t)k * kGsMaxBlocks + b];
+  scratch[sub * kMaxBasis + k] = s;
+  __syncthreads();
+  if (t <= j) {
+    double a = 0.0;
+    for (int q = 0; q < 16; ++q) a += scratch[q * kMaxBasis + t];
+    const double sg = st->sigma[t];
+    const double h = sg * a;
+    c[t] = h * sg;
     if (blockIdx.x == 0) {
       if (hsel == 1)
-        st->h1[threadIdx.x] = h;
+        st->h1[t] = h;
       else
-        st->h2[threadIdx.x] = h;
+        st->h2[t] = h;
     }
   }
   __syncthreads();
 }
 
-template <int MV>
-__global__ __launch_bounds__(kBlock) void k_cgs_pass2(double* __restrict__ W,
-                                                      const double* __restrict__ V, int64_t ldv,
-                                                      int n, int j, int R, int nb_in,
-                                                      DevState* st, const double* part_in,
-                                                      double* part) {
+template <typename TM, typename TZ>
+__global__ __launch_bounds__(kGsThreads) void k_gs_spmv_dots(Sell<TM> A, const TZ* __restrict__ z,
+                                                             double* __restrict__ W,
+                                                             const double* __restrict__ V,
+                                                             int64_t ldv, int j, int rpb,
+                                                             const DevState* st, double* part) {
   if (st->cycle_done) return;
-  __shared__ double c[MV];
-  coefficients<MV>(part_in, nb_in, j, st, 1, c);
-  const int G = gridDim.x * kBlock;
-  const int gtid = blockIdx.x * kBlock + threadIdx.x;
-  double acc[MV];
-#pragma unroll
-  for (int k = 0; k < MV; ++k) acc[k] = 0.0;
-  for (int t = 0; t < R; ++t) {
-    const int row = gtid + t * G;
+  extern __shared__ double wt[];                  // rpb entries
+  const int n = A.n_rows;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r0 = blockIdx.x * rpb;
+  for (int sl = wave; sl < rpb / 64; sl += kGsWaves) {
+    const int row = r0 + sl * 64 + lane;
+    double w = 0.0;
     if (row < n) {
-      double v[MV];
-#pragma unroll
-      for (int k = 0; k < MV; ++k) v[k] = (k <= j) ? V[(size_t)k * ldv + row] : 0.0;
-      double w = W[row];
-#pragma unroll
-      for (int k = 0; k < MV; ++k)
-        if (k <= j) w -= c[k] * v[k];
+      w = (double)sell_dot(A, z, row);
       W[row] = w;
+    }
+    wt[sl * 64 + lane] = w;
+  }
+  __syncthreads();
+  double acc[kGsVpw];
 #pragma unroll
-      for (int k = 0; k < MV; ++k)
-        if (k <= j) acc[k] += v[k] * w;
+  for (int q = 0; q < kGsVpw; ++q) acc[q] = 0.0;
+  for (int base = 0; base < rpb; base += kGsRound) {
+#pragma unroll
+    for (int u = 0; u < kGsRound / 64; ++u) {
+      const int lr = base + u * 64 + lane;
+      const int row = r0 + lr;
+      if (row < n) {
+        const double w = wt[lr];
+#pragma unroll
+        for (int q = 0; q < kGsVpw; ++q) {
+          const int k = wave + kGsWaves * q;
+          if (k <= j) acc[q] += V[(size_t)k * ldv + row] * w;
+        }
+      }
     }
   }
-  block_partials<MV>(acc, j + 1, part);
+#pragma unroll
+  for (int q = 0; q < kGsVpw; ++q) {
+    const int k = wave + kGsWaves * q;
+    const double s = wave_sum(acc[q]);
+    if (k <= j && lane == 0) part[(size_t)k * kGsMaxBlocks + blockIdx.x] = s;
+  }
 }
 
-template <int MV>
-__global__ __launch_bounds__(kBlock) void k_cgs_pass3(const double* __restrict__ W,
-                                                      double* __restrict__ V, int64_t ldv, int n,
-                                                      int j, int R, int nb_in, DevState* st,
-                                                      const double* part_in, double* part) {
+__global__ __launch_bounds__(kGsThreads) void k_gs_pass2(double* __restrict__ W,
+                                                         const double* __restrict__ V,
+                                                         int64_t ldv, int n, int j, int rpb,
+                                                         int nb_in, DevState* st,
+                                                         const double* part_in, double* part) {
   if (st->cycle_done) return;
-  __shared__ double c[MV];
-  coefficients<MV>(part_in, nb_in, j, st, 2, c);
-  const int G = gridDim.x * kBlock;
-  const int gtid = blockIdx.x * kBlock + threadIdx.x;
-  double acc[1] = {0.0};
-  double* vn = V + (size_t)(j + 1) * ldv;
-  for (int t = 0; t < R; ++t) {
-    const int row = gtid + t * G;
-    if (row < n) {
-      double w = W[row];
+  __shared__ double c[kMaxBasis];
+  __shared__ double red[kGsWaves][kGsRound];
+  __shared__ double wt[kGsRound];
+  gs_coefficients(part_in, nb_in, j, st, 1, c, &red[0][0]);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r0 = blockIdx.x * rpb;
+  double acc[kGsVpw], cq[kGsVpw];
 #pragma unroll
-      for (int k = 0; k < MV; ++k)
-        if (k <= j) w -= c[k] * V[(size_t)k * ldv + row];
-      vn[row] = w;
-      acc[0] += w * w;
+  for (int q = 0; q < kGsVpw; ++q) {
+    const int k = wave + kGsWaves * q;
+    acc[q] = 0.0;
+    cq[q] = k <= j ? c[k] : 0.0;
+  }
+  for (int base = 0; base < rpb; base += kGsRound) {
+    double v[kGsVpw][kGsRound / 64];
+#pragma unroll
+    for (int u = 0; u < kGsRound / 64; ++u) {
+      const int row = r0 + base + u * 64 + lane;
+      double ps = 0.0;
+#pragma unroll
+      for (int q = 0; q < kGsVpw; ++q) {
+        const int k = wave + kGsWaves * q;
+        v[q][u] = (k <= j && row < n) ? V[(size_t)k * ldv + row] : 0.0;
+        ps += cq[q] * v[q][u];
+      }
+      red[wave][u * 64 + lane] = ps;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < kGsRound) {
+      const int row = r0 + base + threadIdx.x;
+      double s = 0.0;
+#pragma unroll
+      for (int w = 0; w < kGsWaves; ++w) s += red[w][threadIdx.x];
+      double wv = 0.0;
+      if (row < n) {
+        wv = W[row] - s;
+        W[row] = wv;
+      }
+      wt[threadIdx.x] = wv;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kGsRound / 64; ++u) {
+      const double wv = wt[u * 64 + lane];
+#pragma unroll
+      for (int q = 0; q < kGsVpw; ++q) acc[q] += v[q][u] * wv;
     }
   }
-  block_partials<1>(acc, 1, part);
+#pragma unroll
+  for (int q = 0; q < kGsVpw; ++q) {
+    const int k = wave + kGsWaves * q;
+    const double s = wave_sum(acc[q]);
+    if (k <= j && lane == 0) part[(size_t)k * kGsMaxBlocks + blockIdx.x] = s;
+  }
+}
+
+__global__ __launch_bounds__(kGsThreads) void k_gs_pass3(const double* __restrict__ W,
+                                                         double* __restrict__ V, int64_t ldv,
+                                                         int n, int j, int rpb, int nb_in,
+                                                         DevState* st, const double* part_in,
+                                                         double* part) {
+  if (st->cycle_done) return;
+  __shared__ double c[kMaxBasis];
+  __shared__ double red[kGsWaves][kGsRound];
+  gs_coefficients(part_in, nb_in, j, st, 2, c, &red[0][0]);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r0 = blockIdx.x * rpb;
+  double cq[kGsVpw];
+#pragma unroll
+  for (int q = 0; q < kGsVpw; ++q) {
+    const int k = wave + kGsWaves * q;
+    cq[q] = k <= j ? c[k] : 0.0;
+  }
+  double* vn = V + (size_t)(j + 1) * ldv;
+  double nrm = 0.0;
+  for (int base = 0; base < rpb; base += kGsRound) {
+#pragma unroll
+    for (int u = 0; u < kGsRound / 64; ++u) {
+      const int row = r0 + base + u * 64 + lane;
+      double ps = 0.0;
+#pragma unroll
+      for (int q = 0; q < kGsVpw; ++q) {
+        const int k = wave + kGsWaves * q;
+        if (k <= j && row < n) ps += cq[q] * V[(size_t)k * ldv + row];
+      }
+      red[wave][u * 64 + lane] = ps;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < kGsRound) {
+      const int row = r0 + base + threadIdx.x;
+      double s = 0.0;
+#pragma unroll
+      for (int w = 0; w < kGsWaves; ++w) s += red[w][threadIdx.x];
+      if (row < n) {
+        const double wv = W[row] - s;
+        vn[row] = wv;
+        nrm += wv * wv;
+      }
+    }
+    __syncthreads();
+  }
+  // threads 0..255 (wavefronts 0..3) hold the norm contributions
+  if (wave < kGsRound / 64) {
+    const double s = wave_sum(nrm);
+    if (lane == 0) red[0][wave] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    part[blockIdx.x] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
 }
 
 __global__ __launch_bounds__(kBlock) void k_arn_finish(const double* part, int nb, int j,
                                                        DevState* st, HostFlags* hf) {
   if (st->cycle_done) return;
-  __shared__ double sums[1];
-  final_sums<1>(part, nb, 1, sums);
+  __shared__ double red[kBlock / 64];
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kBlock) acc += part[b];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
   if (threadIdx.x != 0) return;
+  const double nrm2 = ((red[0] + red[1]) + red[2]) + red[3];
   const int ld = kMaxBasis + 1;
   double* H = st->H + (size_t)j * ld;
-  const double hn = sqrt(sums[0]);
+  const double hn = sqrt(nrm2);
   for (int i = 0; i <= j; ++i) H[i] = st->h1[i] + st->h2[i];
   H[j + 1] = hn;
   for (int i = 0; i < j; ++i) {
@@ -555,27 +653,25 @@ void launch_block_sweep(const Sell<T>& Cf, int n_p, const double* r, const doubl
                                                             tq, gate);
 }
 
-template <int MV, typename TM, typename TZ>
-static void arnoldi_step(const Sell<TM>& A, const TZ* z, double* W, double* V, int64_t ldv, int j,
-                         DevState* st, double* part, HostFlags* hf, hipStream_t s) {
-  const int n = A.n_rows;
-  const int nb = dot_blocks(n);
-  const int R = (n + nb * kBlock - 1) / (nb * kBlock);
-  double* p1 = part;
-  double* p2 = part + (size_t)kDotBlocks * kPartStride;
-  k_arn_spmv_dots<MV, TM, TZ><<<nb, kBlock, 0, s>>>(A, z, W, V, ldv, j, R, st, p1);
-  k_cgs_pass2<MV><<<nb, kBlock, 0, s>>>(W, V, ldv, n, j, R, nb, st, p1, p2);
-  k_cgs_pass3<MV><<<nb, kBlock, 0, s>>>(W, V, ldv, n, j, R, nb, st, p2, p1);
-  k_arn_finish<<<1, kBlock, 0, s>>>(p1, nb, j, st, hf);
+int gs_rows_per_block(int n) {
+  int rpb = 2048;
+  while ((n + rpb - 1) / rpb > kGsMaxBlocks) rpb *= 2;
+  return rpb;
 }
 
 template <typename TM, typename TZ>
 void launch_arnoldi_step(const Sell<TM>& A, const TZ* z, double* W, double* V, int64_t ldv, int j,
                          DevState* st, double* part, HostFlags* hf, hipStream_t s) {
-  if (j + 1 <= 32)
-    arnoldi_step<32, TM, TZ>(A, z, W, V, ldv, j, st, part, hf, s);
-  else
-    arnoldi_step<kMaxBasis, TM, TZ>(A, z, W, V, ldv, j, st, part, hf, s);
+  const int n = A.n_rows;
+  const int rpb = gs_rows_per_block(n);
+  const int nb = (n + rpb - 1) / rpb;
+  double* p1 = part;
+  double* p2 = part + (size_t)(kMaxBasis + 1) * kGsMaxBlocks;
+  k_gs_spmv_dots<TM, TZ><<<nb, kGsThreads, (size_t)rpb * sizeof(double), s>>>(A, z, W, V, ldv, j,
+                                                                            rpb, st, p1);
+  k_gs_pass2<<<nb, kGsThreads, 0, s>>>(W, V, ldv, n, j, rpb, nb, st, p1, p2);
+  k_gs_pass3<<<nb, kGsThreads, 0, s>>>(W, V, ldv, n, j, rpb, nb, st, p2, p1);
+  k_arn_finish<<<1, kBlock, 0, s>>>(p1, nb, j, st, hf);
 }
 
 void launch_trisolve(DevState* st, hipStream_t s) { k_trisolve<<<1, 64, 0, s>>>(st); }

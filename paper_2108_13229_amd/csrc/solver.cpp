@@ -181,7 +181,8 @@ void Solver::upload(const sd_allocator* alloc, hipStream_t s) {
   const int m = opts.o.restart;
   V = mem->array<double>((size_t)(m + 1) * ldv);
   W = mem->array<double>((size_t)ldv);
-  part = mem->array<double>((size_t)2 * kDotBlocks * kPartStride);
+  part = mem->array<double>(std::max((size_t)2 * (kMaxBasis + 1) * kGsMaxBlocks,
+                                     (size_t)kDotBlocks * kPartStride));
   st = static_cast<DevState*>(mem->get(sizeof(DevState)));
   SD_HIP(hipMemsetAsync(st, 0, sizeof(DevState), s));
   void* h = nullptr;
