@@ -4,7 +4,7 @@ Workload (the headline configuration): 512 x 256 cells in each subdomain
 (N = 524,288 unknowns), lognormal permeability ln K ~ N(ln 1e-4, 1) with an
 8-cell Gaussian correlation (seed 1), viscosity 1e-3, parabolic inflow of
 peak 1e-2, zero-traction outflow; block-Gauss-Seidel preconditioned
-FGMRES(30) with one smoothed-aggregation V-cycle per velocity and Darcy block
+FGMRES(60) with one smoothed-aggregation V-cycle per velocity and Darcy block
 and the viscosity-scaled pressure-mass Schur block, to relative residual
 1e-8.  One step = one complete solve from x = 0 with the matrix and the AMG
 hierarchy resident in HBM.  FP64 is the headline; the mixed-precision solver
@@ -29,7 +29,9 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = ("512x256 free-flow + 512x256 porous cells (N=524288), lognormal K seed 1, "
-            "BGS(SA-AMG V-cycle, mu*Mp^-1, SA-AMG V-cycle) + FGMRES(30), rel. residual 1e-8")
+            "BGS(SA-AMG V-cycle, mu*Mp^-1, SA-AMG V-cycle) + FGMRES(m), rel. residual 1e-8")
+ROOFLINE_KERNEL = "k_gs_spmv_dots<double, double>"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_arnoldi_spmv_c1.json")
 
 
 def parse():
@@ -43,7 +45,11 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--restart", type=int, default=60)
+    ap.add_argument("--roofline-solves", type=int, default=3)
+    ap.add_argument("--counter-run", action="store_true",
+                    help="one FP64 solve with plain (non-graph) launches plus a 512 MiB "
+                         "device copy, for hardware-counter passes")
     return ap.parse_args()
 
 
@@ -65,7 +71,53 @@ def run_solves(S, steps, warmup):
     return np.array(lat), its, st, x
 
 
-def cpu_baseline(p, a_budget_s=30.0):
+def roofline(S, n_solves):
+    """Dominant kernel (w = A z_j fused with the first Gram-Schmidt dot pass):
+    its launches are bracketed by HIP events on the solver's stream during
+    n_solves solves of the same workload; achieved = algorithmic bytes of
+    those launches / their summed durations."""
+    S.profile("arnoldi_spmv")
+    for _ in range(n_solves):
+        S.solve()
+    r = S.profile_read()
+    S.profile("off")
+    achieved = r["bytes"] / r["seconds"] / 1e9
+    traffic = None
+    try:
+        import hashlib
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+        src = os.path.join(ROOT, "paper_2108_13229_amd", "csrc", "kernels.hip")
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if t.get("kernels_hip_sha256") == sha:
+            traffic = t["hbm_bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        traffic = None
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": ROOFLINE_KERNEL, "launches": r["launches"],
+            "avg_launch_us": 1e6 * r["seconds"] / r["launches"],
+            "alg_bytes_per_launch": r["bytes"] / r["launches"]}
+
+
+def counter_run(sd, p, restart):
+    """Kernels launched one by one (no graph replay) so that per-dispatch
+    counters attach to each kernel; then a plain 512 MiB device-to-device copy
+    whose FETCH_SIZE / WRITE_SIZE calibrate the counters (64 Mi doubles)."""
+    import torch
+    P = sd.Problem(p, device=True)
+    S = sd.Solver(P, precond="BGS", schur="mass", tol=1e-8, restart=restart)
+    S.profile("arnoldi_spmv")
+    x, st, rc = S.solve()
+    torch.cuda.synchronize()
+    a = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"counter_run": True, "iters": st["iters"], "copy_bytes": a.numel() * 8}))
+
+
+def cpu_baseline(p, restart):
     """The oracle's FP64 FGMRES with the same preconditioner, one solve,
     single-threaded (setup excluded; timed separately)."""
     from threadpoolctl import threadpool_limits
@@ -77,7 +129,7 @@ def cpu_baseline(p, a_budget_s=30.0):
         M = precond.build(p, a, "BGS")
         t_setup = time.perf_counter() - t0
         t0 = time.perf_counter()
-        r = krylov.fgmres(a.A, a.b, M, tol=1e-8, m=30)
+        r = krylov.fgmres(a.A, a.b, M, tol=1e-8, m=restart)
         t_solve = time.perf_counter() - t0
     return dict(value=1.0 / t_solve, unit="solves/s", cores=1, kind="oracle",
                 sample=f"one full FP64 solve of the same workload (oracle FGMRES, "
@@ -99,10 +151,14 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     p = channel_problem(args.nx, args.ny, seed=args.seed)
+    if args.counter_run:
+        counter_run(sd, p, args.restart)
+        return
     t0 = time.perf_counter()
     P = sd.Problem(p, device=True)
     t_asm = time.perf_counter() - t0
     res = {}
+    roof = None
     for prec in (["fp64"] if args.no_mixed else ["fp64", "mixed"]):
         t0 = time.perf_counter()
         S = sd.Solver(P, precond="BGS", schur="mass", tol=1e-8, restart=args.restart,
@@ -115,6 +171,8 @@ def main():
                          p99_ms=float(1e3 * np.percentile(lat, 99)),
                          iters=int(np.median(its)), restarts=st["restarts"],
                          rel_res=st["rel_res"], setup_s=t_setup)
+        if prec == args.precision and args.roofline_solves > 0:
+            roof = roofline(S, args.roofline_solves)
         S.close()
     head = res[args.precision]
     out = {
@@ -135,11 +193,13 @@ def main():
                    "assembly_s": t_asm},
         "p50_ms": head["p50_ms"],
         "p99_ms": head["p99_ms"],
+        "restart": args.restart,
         "fp64": res.get("fp64"),
         "mixed": res.get("mixed"),
+        "roofline": roof,
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(p)
+        out["cpu_baseline"] = cpu_baseline(p, args.restart)
     print(json.dumps(out))
 
 

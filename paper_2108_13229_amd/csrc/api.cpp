@@ -272,6 +272,24 @@ int sd_apply_vcycle(sd_solver* s, int block, const double* d_b, double* d_x, voi
   });
 }
 
+int sd_solver_profile(sd_solver* s, int kernel_class) {
+  if (!s || kernel_class < 0 || kernel_class > 3) return fail(SD_E_INVALID, "bad argument");
+  s->s->prof_class = kernel_class;
+  s->s->prof_launches = 0;
+  s->s->prof_seconds = 0.0;
+  s->s->prof_bytes = 0.0;
+  return SD_OK;
+}
+
+int sd_solver_profile_read(const sd_solver* s, int64_t* launches, double* seconds,
+                           double* bytes) {
+  if (!s) return fail(SD_E_INVALID, "solver is NULL");
+  if (launches) *launches = s->s->prof_launches;
+  if (seconds) *seconds = s->s->prof_seconds;
+  if (bytes) *bytes = s->s->prof_bytes;
+  return SD_OK;
+}
+
 void sd_problem_destroy(sd_problem* pb) { delete pb; }
 
 void sd_solver_destroy(sd_solver* s) {

@@ -87,9 +87,12 @@ void launch_block_sweep(const Sell<T>& Cf, int n_p, const double* r, const doubl
 //   w -= V (sigma .* h1), h2 = sigma .* (V^T w)        (second Gram-Schmidt pass)
 //   V[j+1] = w - V (sigma .* h2), ||V[j+1]||, Givens   (update, norm, rotations)
 // All kernels return immediately once st->cycle_done is set.
+// ev (optional, 2 events): recorded around the kernel selected by prof_class
+// (1: spmv + first dot pass, 2: second Gram-Schmidt pass).
 template <typename TM, typename TZ>
 void launch_arnoldi_step(const Sell<TM>& A, const TZ* z, double* W, double* V, int64_t ldv,
-                         int j, DevState* st, double* part, HostFlags* hf, hipStream_t s);
+                         int j, DevState* st, double* part, HostFlags* hf, hipStream_t s,
+                         int prof_class = 0, hipEvent_t* ev = nullptr);
 void launch_trisolve(DevState* st, hipStream_t s);
 template <typename TZ>
 void launch_update_x(double* x, const TZ* Z, int64_t ldz, int n, DevState* st,

@@ -661,15 +661,20 @@ int gs_rows_per_block(int n) {
 
 template <typename TM, typename TZ>
 void launch_arnoldi_step(const Sell<TM>& A, const TZ* z, double* W, double* V, int64_t ldv, int j,
-                         DevState* st, double* part, HostFlags* hf, hipStream_t s) {
+                         DevState* st, double* part, HostFlags* hf, hipStream_t s, int prof_class,
+                         hipEvent_t* ev) {
   const int n = A.n_rows;
   const int rpb = gs_rows_per_block(n);
   const int nb = (n + rpb - 1) / rpb;
   double* p1 = part;
   double* p2 = part + (size_t)(kMaxBasis + 1) * kGsMaxBlocks;
+  if (ev && prof_class == 1) (void)hipEventRecord(ev[0], s);
   k_gs_spmv_dots<TM, TZ><<<nb, kGsThreads, (size_t)rpb * sizeof(double), s>>>(A, z, W, V, ldv, j,
                                                                             rpb, st, p1);
+  if (ev && prof_class == 1) (void)hipEventRecord(ev[1], s);
+  if (ev && prof_class == 2) (void)hipEventRecord(ev[0], s);
   k_gs_pass2<<<nb, kGsThreads, 0, s>>>(W, V, ldv, n, j, rpb, nb, st, p1, p2);
+  if (ev && prof_class == 2) (void)hipEventRecord(ev[1], s);
   k_gs_pass3<<<nb, kGsThreads, 0, s>>>(W, V, ldv, n, j, rpb, nb, st, p2, p1);
   k_arn_finish<<<1, kBlock, 0, s>>>(p1, nb, j, st, hf);
 }
@@ -760,10 +765,10 @@ template void launch_block_sweep<float>(const Sell<float>&, int, const double*, 
                                         hipStream_t);
 template void launch_arnoldi_step<double, double>(const Sell<double>&, const double*, double*,
                                                   double*, int64_t, int, DevState*, double*,
-                                                  HostFlags*, hipStream_t);
+                                                  HostFlags*, hipStream_t, int, hipEvent_t*);
 template void launch_arnoldi_step<float, float>(const Sell<float>&, const float*, double*,
                                                 double*, int64_t, int, DevState*, double*,
-                                                HostFlags*, hipStream_t);
+                                                HostFlags*, hipStream_t, int, hipEvent_t*);
 template void launch_update_x<double>(double*, const double*, int64_t, int, DevState*,
                                       hipStream_t);
 template void launch_update_x<float>(double*, const float*, int64_t, int, DevState*,

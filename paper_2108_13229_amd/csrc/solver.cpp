@@ -166,6 +166,7 @@ Solver::~Solver() {
   prec.reset();
   if (stream) (void)hipStreamSynchronize(stream);
   for (auto e : events) (void)hipEventDestroy(e);
+  for (auto e : prof_ev) (void)hipEventDestroy(e);
   if (ev_join) (void)hipEventDestroy(ev_join);
   if (stream) (void)hipStreamDestroy(stream);
   if (hf) (void)hipHostFree((void*)hf);
@@ -195,6 +196,10 @@ void Solver::upload(const sd_allocator* alloc, hipStream_t s) {
   events.resize((size_t)kMaxBasis + 2);
   for (auto& e : events) SD_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   SD_HIP(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+  prof_ev.resize((size_t)2 * kMaxBasis);
+  for (auto& e : prof_ev) SD_HIP(hipEventCreate(&e));
+  nnz_A = pb->A.nnz();
+  nnz_V0 = hh[0].levels[0].A.nnz();
   SD_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
   prec = opts.o.precision == SD_PRECISION_MIXED ? make_prec_fp32(*this, s) : make_prec_fp64(*this, s);
   SD_HIP(hipStreamSynchronize(s));
@@ -306,11 +311,24 @@ class PrecImpl : public PrecBase {
     vcycle<T>(blk, l + 1, C.b, nullptr, C.x, gate, s);
     launch_prolong<T>(L.P, C.x, cur, gate, s);
     for (int k = 0; k < nu_post; ++k) {
+      const bool timed = prof_jacobi_ev && blk == 0 && l == 0 && k + 1 == nu_post;
+      if (timed) SD_HIP(hipEventRecord(prof_jacobi_ev[0], s));
       launch_jacobi<T, TB>(L.A, L.wd, b, bs, cur, other, gate, s);
+      if (timed) SD_HIP(hipEventRecord(prof_jacobi_ev[1], s));
       std::swap(cur, other);
     }
     if (cur != x) launch_convert<T, T>(cur, x, L.n, s);
   }
+
+  // apply() with events around the last post-smoothing sweep of the finest
+  // velocity level (the same kernel and arguments as in apply()).
+  void apply_profiled_jacobi(Solver& S, const double* r, const double* bs, T* z, hipStream_t s,
+                             hipEvent_t* ev) {
+    prof_jacobi_ev = ev;
+    apply(S, r, bs, z, nullptr, s);
+    prof_jacobi_ev = nullptr;
+  }
+  hipEvent_t* prof_jacobi_ev = nullptr;
 
   // z = P(bs * r): block preconditioner on a basis vector (FP64 input).
   void apply(Solver& S, const double* r, const double* bs, T* z, const DevState* gate,
@@ -437,6 +455,7 @@ class PrecImpl : public PrecBase {
       launch_trisolve(S.st, s);
       launch_update_x<T>(x, Z, ldz, n, S.st, s);
       ++restarts;
+      if (S.prof_class != 0) collect_profile(S, s);
     }
     out.iters = hs.iters;
     out.restarts = restarts;
@@ -451,6 +470,18 @@ class PrecImpl : public PrecBase {
   // Enqueue Arnoldi step j (preconditioner + orthogonalisation) as a graph.
   std::vector<hipGraphExec_t> graphs;
   void iteration(Solver& S, int j, hipStream_t s) {
+    if (S.prof_class != 0) {  // measurement mode: plain launches with events
+      hipEvent_t* ev = &S.prof_ev[(size_t)2 * j];
+      T* zj = Z + (size_t)j * ldz;
+      if (S.prof_class == 3) {
+        apply_profiled_jacobi(S, S.V + (size_t)j * S.ldv, &S.st->sigma[j], zj, s, ev);
+      } else {
+        apply(S, S.V + (size_t)j * S.ldv, &S.st->sigma[j], zj, nullptr, s);
+      }
+      launch_arnoldi_step<T, T>(Aarn, zj, S.W, S.V, S.ldv, j, S.st, S.part, S.hf_dev, s,
+                                S.prof_class, ev);
+      return;
+    }
     if (graphs.empty()) graphs.assign((size_t)kMaxBasis, nullptr);
     if (!graphs[(size_t)j]) {
       hipGraph_t g = nullptr;
@@ -472,6 +503,30 @@ class PrecImpl : public PrecBase {
   ~PrecImpl() override {
     for (auto g : graphs)
       if (g) (void)hipGraphExecDestroy(g);
+  }
+
+  // Add the event-timed launches of the cycle that just ran (columns
+  // 0..k-1; later columns returned at once and are not counted).
+  void collect_profile(Solver& S, hipStream_t s) {
+    SD_HIP(hipStreamSynchronize(s));
+    int k = 0;
+    SD_HIP(hipMemcpy(&k, &S.st->k, sizeof(int), hipMemcpyDeviceToHost));
+    const double n = (double)S.N;
+    const double tz = (double)sizeof(T);
+    for (int j = 0; j < k; ++j) {
+      float ms = 0.0f;
+      SD_HIP(hipEventElapsedTime(&ms, S.prof_ev[(size_t)2 * j], S.prof_ev[(size_t)2 * j + 1]));
+      S.prof_seconds += 1e-3 * ms;
+      S.prof_launches += 1;
+      if (S.prof_class == 1)  // A (values + indices), z, w, j+1 basis vectors
+        S.prof_bytes += (double)S.nnz_A * (tz + 4.0) + n * (tz + 8.0) + (j + 1) * 8.0 * n;
+      else if (S.prof_class == 2)  // j+1 basis vectors, w read and written
+        S.prof_bytes += (j + 1) * 8.0 * n + 16.0 * n;
+      else {  // V level 0: A_V (values + indices), x_in, b, w, x_out
+        const double nv = (double)S.off[2];
+        S.prof_bytes += (double)S.nnz_V0 * (tz + 4.0) + nv * (3.0 * tz + 8.0);
+      }
+    }
   }
 
   void launch_init_cycle(Solver& S, int m_cycle, hipStream_t s) {

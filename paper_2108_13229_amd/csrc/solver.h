@@ -104,6 +104,12 @@ class Solver {
   hipEvent_t ev_join = nullptr;
   hipStream_t stream = nullptr;     // internal non-blocking stream (default priority)
   std::unique_ptr<PrecBase> prec;
+  // measurement mode: events around one kernel class (0 = off)
+  int prof_class = 0;
+  int64_t prof_launches = 0;
+  double prof_seconds = 0.0, prof_bytes = 0.0;
+  std::vector<hipEvent_t> prof_ev;   // 2 per Arnoldi column
+  int64_t nnz_A = 0, nnz_V0 = 0;
 
   ~Solver();
   void setup_host(HostProblem* p, const sd_solver_opts* o);

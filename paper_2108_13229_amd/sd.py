@@ -115,6 +115,9 @@ SIGNATURES = {
     "sd_apply_matrix": (C.c_int, [_P, _P, _P, _P]),
     "sd_apply_preconditioner": (C.c_int, [_P, _P, _P, _P]),
     "sd_apply_vcycle": (C.c_int, [_P, C.c_int, _P, _P, _P]),
+    "sd_solver_profile": (C.c_int, [_P, C.c_int]),
+    "sd_solver_profile_read": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                         C.POINTER(C.c_double)]),
     "sd_server_create": (C.c_int, [C.POINTER(ServerOpts), C.POINTER(_P)]),
     "sd_submit": (C.c_int, [_P, C.POINTER(Request), C.POINTER(C.c_uint64)]),
     "sd_poll": (C.c_int, [_P, C.c_uint64, C.POINTER(Result)]),
@@ -326,6 +329,16 @@ class Solver:
         _check(lib().sd_apply_vcycle(self.h, block, C.c_void_p(b.data_ptr()),
                                      C.c_void_p(x.data_ptr()), _stream()))
         return x
+
+    PROFILE = {"off": 0, "arnoldi_spmv": 1, "gs_pass2": 2, "jacobi_v0": 3}
+
+    def profile(self, kernel_class: str):
+        _check(lib().sd_solver_profile(self.h, self.PROFILE[kernel_class]))
+
+    def profile_read(self):
+        n, sec, by = C.c_int64(), C.c_double(), C.c_double()
+        _check(lib().sd_solver_profile_read(self.h, C.byref(n), C.byref(sec), C.byref(by)))
+        return dict(launches=n.value, seconds=sec.value, bytes=by.value)
 
     def close(self):
         if self.h:
