@@ -41,7 +41,7 @@ struct DevState {
   double cs[kMaxBasis], sn[kMaxBasis], g[kMaxBasis + 1], y[kMaxBasis];
   double h1[kMaxBasis + 1], h2[kMaxBasis + 1];
   // BiCGSTAB scalars
-  double rho, alpha, omega, dots[8];
+  double rho, alpha, omega, bbeta, dots[8];
   unsigned int counter[8];
 };
 
@@ -110,6 +110,23 @@ void launch_set_cycle_length(DevState* st, int m, hipStream_t s);
 template <typename TB, typename T>
 void launch_scale_convert(const TB* b, const double* bscale, T* out, int n, const DevState* gate,
                           hipStream_t s);
+
+// BiCGSTAB work vectors (FP64 Krylov vectors; y, z preconditioned, type T).
+template <typename T>
+struct BicgVecs {
+  double *r = nullptr, *rhat = nullptr, *p = nullptr, *v = nullptr, *s = nullptr, *t = nullptr;
+  T *y = nullptr, *z = nullptr;
+};
+// which: 0 = p update; 1 = v = A y, alpha, s = r - alpha v, x += alpha y,
+// ||s||; 2 = t = A z, omega, x += omega z, r = s - omega t, ||r||, next rho.
+template <typename T>
+void launch_bicg_iteration_part(int which, const Sell<double>& A, BicgVecs<T>& w, double* x,
+                                DevState* st, double* part, HostFlags* hf, int slot,
+                                hipStream_t s);
+// r = b - A x (x null: zero), rhat = r, p = v = 0, scalars reset.
+void launch_bicg_restart(const Sell<double>& A, const double* b, const double* x, double* r,
+                         double* rhat, double* p, double* v, DevState* st, double* part,
+                         hipStream_t s);
 
 // Type conversions and small vector helpers.
 template <typename TA, typename TB>

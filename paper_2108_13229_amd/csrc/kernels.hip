@@ -561,6 +561,185 @@ __global__ __launch_bounds__(kBlock) void k_norm_b_finish(const double* part, in
   }
 }
 
+// ---- BiCGSTAB (right preconditioned, van der Vorst).  Vectors FP64; the
+// preconditioned vectors y, z are in the preconditioner precision T.  Scalars
+// live in DevState (rho, alpha, omega, bbeta); dots[] hold finished sums.
+// Every kernel returns at once when st->cycle_done is set (converged,
+// breakdown, or iteration cap), so enqueued iterations beyond that point
+// leave x untouched.
+
+// p = r + beta (p - omega v)
+__global__ __launch_bounds__(kBlock) void k_bicg_p(int n, const double* __restrict__ r,
+                                                   double* __restrict__ p,
+                                                   const double* __restrict__ v,
+                                                   const DevState* st) {
+  if (st->cycle_done) return;
+  const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (i >= n) return;
+  p[i] = r[i] + st->bbeta * (p[i] - st->omega * v[i]);
+}
+
+// out = A y (FP64 matrix, y in TY); partial dots: out.u1 (and out.out if two)
+template <typename TY>
+__global__ __launch_bounds__(kBlock) void k_bicg_spmv(Sell<double> A, const TY* __restrict__ y,
+                                                      double* __restrict__ out,
+                                                      const double* __restrict__ u1, int two,
+                                                      int R, const DevState* st, double* part) {
+  if (st->cycle_done) return;
+  const int n = A.n_rows;
+  const int G = gridDim.x * kBlock;
+  const int gtid = blockIdx.x * kBlock + threadIdx.x;
+  double acc[2] = {0.0, 0.0};
+  for (int t = 0; t < R; ++t) {
+    const int row = gtid + t * G;
+    if (row < n) {
+      const double w = sell_dot(A, y, row);
+      out[row] = w;
+      acc[0] += w * u1[row];
+      acc[1] += w * w;
+    }
+  }
+  block_partials<2>(acc, two ? 2 : 1, part);
+}
+
+// s = r - alpha v ; x += alpha y ; partial s.s
+template <typename TY>
+__global__ __launch_bounds__(kBlock) void k_bicg_s(int n, const double* __restrict__ r,
+                                                   const double* __restrict__ v,
+                                                   double* __restrict__ s,
+                                                   double* __restrict__ x,
+                                                   const TY* __restrict__ y, int R,
+                                                   const DevState* st, double* part) {
+  if (st->cycle_done) return;
+  const int G = gridDim.x * kBlock;
+  const int gtid = blockIdx.x * kBlock + threadIdx.x;
+  const double al = st->alpha;
+  double acc[1] = {0.0};
+  for (int t = 0; t < R; ++t) {
+    const int i = gtid + t * G;
+    if (i < n) {
+      const double si = r[i] - al * v[i];
+      s[i] = si;
+      x[i] += al * (double)y[i];
+      acc[0] += si * si;
+    }
+  }
+  block_partials<1>(acc, 1, part);
+}
+
+// x += omega z ; r = s - omega t ; partial r.r and rhat.r
+template <typename TY>
+__global__ __launch_bounds__(kBlock) void k_bicg_r(int n, const double* __restrict__ s,
+                                                   const double* __restrict__ t,
+                                                   double* __restrict__ r,
+                                                   double* __restrict__ x,
+                                                   const TY* __restrict__ z,
+                                                   const double* __restrict__ rhat, int R,
+                                                   const DevState* st, double* part) {
+  if (st->cycle_done) return;
+  const int G = gridDim.x * kBlock;
+  const int gtid = blockIdx.x * kBlock + threadIdx.x;
+  const double om = st->omega;
+  double acc[2] = {0.0, 0.0};
+  for (int q = 0; q < R; ++q) {
+    const int i = gtid + q * G;
+    if (i < n) {
+      x[i] += om * (double)z[i];
+      const double ri = s[i] - om * t[i];
+      r[i] = ri;
+      acc[0] += ri * ri;
+      acc[1] += rhat[i] * ri;
+    }
+  }
+  block_partials<2>(acc, 2, part);
+}
+
+// One-workgroup scalar steps.  op 0: alpha = rho / (rhat.v);
+// op 1: ||s|| test; op 2: omega = (t.s)/(t.t); op 3: ||r|| test, next rho
+// and beta; op 4: restart values (rho = r.r, bbeta = 0, omega = alpha = 1).
+__global__ __launch_bounds__(kBlock) void k_bicg_scalar(const double* part, int nb, int op,
+                                                        DevState* st, HostFlags* hf, int slot) {
+  if (op != 4 && st->cycle_done) return;
+  __shared__ double sums[2];
+  const int nv = (op == 0 || op == 1 || op == 4) ? 1 : 2;
+  final_sums<2>(part, nb, nv, sums);
+  if (threadIdx.x != 0) return;
+  int done = 0, bad = 0;
+  if (op == 0) {
+    const double den = sums[0];
+    const double al = st->rho / den;
+    bad = !(den != 0.0) || !isfinite(al);
+    st->alpha = al;
+  } else if (op == 1) {
+    const double sn = sqrt(sums[0]);
+    st->dots[0] = sn;
+    done = sn <= st->target;
+    st->converged = done;
+    bad = !isfinite(sn);
+  } else if (op == 2) {
+    const double tt = sums[1];
+    const double om = sums[0] / tt;
+    bad = !(tt > 0.0) || !isfinite(om) || om == 0.0;
+    st->omega = om;
+  } else if (op == 3) {
+    const double rn = sqrt(sums[0]);
+    const double rho_new = sums[1];
+    st->dots[1] = rn;
+    st->iters += 1;
+    done = rn <= st->target;
+    st->converged = done;
+    st->bbeta = (rho_new / st->rho) * (st->alpha / st->omega);
+    bad = !isfinite(rn) || !(rho_new != 0.0) || !isfinite(st->bbeta);
+    st->rho = rho_new;
+    if (!done && st->iters >= st->m) done = 1;   // iteration cap of this cycle
+  } else {
+    const double rr = sums[0];
+    st->rho = rr;
+    st->bbeta = 0.0;
+    st->alpha = 1.0;
+    st->omega = 1.0;
+    st->beta = sqrt(rr);
+    st->converged = st->beta <= st->target;
+    st->cycle_done = st->converged || !isfinite(st->beta) || !(st->beta > 0.0);
+    if (!isfinite(st->beta)) st->breakdown = 1;
+    return;
+  }
+  if (op == 1 && done) st->iters += 1;   // converged halfway through an iteration
+  if (bad) st->breakdown = 1;
+  if (done || bad) st->cycle_done = 1;
+  if (hf && (op == 1 || op == 3)) {
+    hf->cycle_done[slot] = st->cycle_done;
+    __threadfence_system();
+  }
+}
+
+// r = b - A x (x may be null: zero), rhat = r, p = v = 0; partial r.r
+__global__ __launch_bounds__(kBlock) void k_bicg_restart(Sell<double> A,
+                                                         const double* __restrict__ b,
+                                                         const double* __restrict__ x,
+                                                         double* __restrict__ r,
+                                                         double* __restrict__ rhat,
+                                                         double* __restrict__ p,
+                                                         double* __restrict__ v, int R,
+                                                         double* part) {
+  const int n = A.n_rows;
+  const int G = gridDim.x * kBlock;
+  const int gtid = blockIdx.x * kBlock + threadIdx.x;
+  double acc[2] = {0.0, 0.0};
+  for (int t = 0; t < R; ++t) {
+    const int row = gtid + t * G;
+    if (row < n) {
+      const double rv = b[row] - (x ? sell_dot(A, x, row) : 0.0);
+      r[row] = rv;
+      rhat[row] = rv;
+      p[row] = 0.0;
+      v[row] = 0.0;
+      acc[0] += rv * rv;
+    }
+  }
+  block_partials<2>(acc, 1, part);
+}
+
 __global__ void k_init_state(DevState* st, int m, double drop) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   st->j = 0;
@@ -704,6 +883,49 @@ void launch_norm_b(const double* b, int n, double tol, DevState* st, double* par
   k_norm_b<<<nb, kBlock, 0, s>>>(b, n, R, part);
   k_norm_b_finish<<<1, kBlock, 0, s>>>(part, nb, tol, st);
 }
+
+template <typename T>
+void launch_bicg_iteration_part(int which, const Sell<double>& A, BicgVecs<T>& w, double* x,
+                                DevState* st, double* part, HostFlags* hf, int slot,
+                                hipStream_t s) {
+  const int n = A.n_rows;
+  const int nb = dot_blocks(n);
+  const int R = (n + nb * kBlock - 1) / (nb * kBlock);
+  switch (which) {
+    case 0:  // p update (before M p)
+      k_bicg_p<<<blocks_for(n), kBlock, 0, s>>>(n, w.r, w.p, w.v, st);
+      break;
+    case 1:  // v = A y, alpha, s, ||s||
+      k_bicg_spmv<T><<<nb, kBlock, 0, s>>>(A, w.y, w.v, w.rhat, 0, R, st, part);
+      k_bicg_scalar<<<1, kBlock, 0, s>>>(part, nb, 0, st, hf, slot);
+      k_bicg_s<T><<<nb, kBlock, 0, s>>>(n, w.r, w.v, w.s, x, w.y, R, st, part);
+      k_bicg_scalar<<<1, kBlock, 0, s>>>(part, nb, 1, st, hf, slot);
+      break;
+    default:  // t = A z, omega, x, r, ||r||, next rho
+      k_bicg_spmv<T><<<nb, kBlock, 0, s>>>(A, w.z, w.t, w.s, 1, R, st, part);
+      k_bicg_scalar<<<1, kBlock, 0, s>>>(part, nb, 2, st, hf, slot);
+      k_bicg_r<T><<<nb, kBlock, 0, s>>>(n, w.s, w.t, w.r, x, w.z, w.rhat, R, st, part);
+      k_bicg_scalar<<<1, kBlock, 0, s>>>(part, nb, 3, st, hf, slot);
+      break;
+  }
+}
+
+void launch_bicg_restart(const Sell<double>& A, const double* b, const double* x, double* r,
+                         double* rhat, double* p, double* v, DevState* st, double* part,
+                         hipStream_t s) {
+  const int n = A.n_rows;
+  const int nb = dot_blocks(n);
+  const int R = (n + nb * kBlock - 1) / (nb * kBlock);
+  k_bicg_restart<<<nb, kBlock, 0, s>>>(A, b, x, r, rhat, p, v, R, part);
+  k_bicg_scalar<<<1, kBlock, 0, s>>>(part, nb, 4, st, nullptr, 0);
+}
+
+template void launch_bicg_iteration_part<double>(int, const Sell<double>&, BicgVecs<double>&,
+                                                 double*, DevState*, double*, HostFlags*, int,
+                                                 hipStream_t);
+template void launch_bicg_iteration_part<float>(int, const Sell<double>&, BicgVecs<float>&,
+                                                double*, DevState*, double*, HostFlags*, int,
+                                                hipStream_t);
 
 void launch_init_state(DevState* st, int m, double cycle_drop, hipStream_t s) {
   k_init_state<<<1, 64, 0, s>>>(st, m, cycle_drop);

@@ -503,6 +503,7 @@ class PrecImpl : public PrecBase {
   ~PrecImpl() override {
     for (auto g : graphs)
       if (g) (void)hipGraphExecDestroy(g);
+    if (bicg_graph) (void)hipGraphExecDestroy(bicg_graph);
   }
 
   // Add the event-timed launches of the cycle that just ran (columns
@@ -534,9 +535,121 @@ class PrecImpl : public PrecBase {
     launch_set_cycle_length(S.st, m_cycle, s);
   }
 
-  int bicgstab(Solver&, const double*, double*, int, sd_stats*, hipStream_t) override {
-    throw Error(SD_E_INVALID, "BiCGSTAB not available in this build");
+  // ------------------------------------------------------------ BiCGSTAB
+  BicgVecs<T> bw;
+  hipGraphExec_t bicg_graph = nullptr;
+
+  void bicg_alloc(Solver& S) {
+    if (bw.r) return;
+    DeviceMem& mem = *S.mem;
+    const size_t n = (size_t)S.ldv;
+    bw.r = mem.array<double>(n);
+    bw.rhat = mem.array<double>(n);
+    bw.p = mem.array<double>(n);
+    bw.v = mem.array<double>(n);
+    bw.s = mem.array<double>(n);
+    bw.t = mem.array<double>(n);
+    bw.y = mem.array<T>(n);
+    bw.z = mem.array<T>(n);
   }
+
+  void bicg_enqueue_iteration(Solver& S, double* x, hipStream_t s) {
+    launch_bicg_iteration_part<T>(0, S.A64, bw, x, S.st, S.part, S.hf_dev, 0, s);
+    apply(S, bw.p, nullptr, bw.y, nullptr, s);
+    launch_bicg_iteration_part<T>(1, S.A64, bw, x, S.st, S.part, S.hf_dev, 0, s);
+    apply(S, bw.s, nullptr, bw.z, nullptr, s);
+    launch_bicg_iteration_part<T>(2, S.A64, bw, x, S.st, S.part, S.hf_dev, 0, s);
+  }
+
+  int bicgstab(Solver& S, const double* b, double* x, int use_x0, sd_stats* stats,
+               hipStream_t user) override {
+    hipStream_t s = S.stream;
+    SD_HIP(hipEventRecord(S.ev_join, user));
+    SD_HIP(hipStreamWaitEvent(s, S.ev_join, 0));
+    bicg_alloc(S);
+    const double t0 = wall_time();
+    const sd_solver_opts& o = S.opts.o;
+    const int n = S.N;
+    launch_init_state(S.st, o.maxit, 0.0, s);
+    launch_norm_b(b, n, o.tol, S.st, S.part, s);
+    HostState hs = read_state(S, s);
+    sd_stats out{};
+    if (!(hs.bnorm > 0.0)) {
+      launch_fill<double>(x, 0.0, n, s);
+      SD_HIP(hipStreamSynchronize(s));
+      out.t_setup = S.t_setup;
+      out.t_solve = wall_time() - t0;
+      if (stats) *stats = out;
+      return std::isfinite(hs.bnorm) ? SD_OK : SD_E_INVALID;
+    }
+    if (!use_x0) launch_fill<double>(x, 0.0, n, s);
+    // the graph bakes in x; rebuild it when the caller's buffer changes
+    if (bicg_graph && bicg_x != x) {
+      SD_HIP(hipGraphExecDestroy(bicg_graph));
+      bicg_graph = nullptr;
+    }
+    bool first = true;
+    int status = SD_E_NOCONV, restarts = 0, breakdowns = 0, last_iters = -1;
+    const int depth = 2;
+    for (;;) {
+      launch_bicg_restart(S.A64, b, (first && !use_x0) ? nullptr : x, bw.r, bw.rhat, bw.p,
+                          bw.v, S.st, S.part, s);
+      first = false;
+      hs = read_state(S, s);
+      if (!std::isfinite(hs.beta)) {
+        status = SD_E_BREAKDOWN;
+        break;
+      }
+      if (hs.converged) {
+        status = SD_OK;
+        break;
+      }
+      if (hs.iters >= o.maxit) {
+        status = SD_E_NOCONV;
+        break;
+      }
+      if (hs.breakdown) {  // a breakdown restarts from the true residual
+        if (hs.iters == last_iters || ++breakdowns > 20) {
+          status = SD_E_BREAKDOWN;
+          break;
+        }
+        SD_HIP(hipMemsetAsync(&S.st->breakdown, 0, sizeof(int), s));
+      }
+      last_iters = hs.iters;
+      S.hf->cycle_done[0] = 0;
+      if (!bicg_graph) {
+        hipGraph_t g = nullptr;
+        SD_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        bicg_enqueue_iteration(S, x, s);
+        SD_HIP(hipStreamEndCapture(s, &g));
+        SD_HIP(hipGraphInstantiate(&bicg_graph, g, nullptr, nullptr, 0));
+        SD_HIP(hipGraphDestroy(g));
+        bicg_x = x;
+      }
+      const int cap = o.maxit - hs.iters;
+      for (int it = 0; it < cap; ++it) {
+        SD_HIP(hipGraphLaunch(bicg_graph, s));
+        SD_HIP(hipEventRecord(S.events[(size_t)(it % (depth + 1))], s));
+        if (it >= depth) {
+          SD_HIP(hipEventSynchronize(S.events[(size_t)((it - depth) % (depth + 1))]));
+          if (S.hf->cycle_done[0]) break;
+        }
+      }
+      ++restarts;
+    }
+    // final true residual with per-block norms
+    launch_restart_residual(S.A64, b, x, S.V, S.off, S.st, S.part, nullptr, s);
+    HostState fin = read_state(S, s);
+    out.iters = fin.iters;
+    out.restarts = restarts;
+    out.rel_res = fin.beta / fin.bnorm;
+    for (int k = 0; k < 3; ++k) out.rel_res_block[k] = std::sqrt(fin.resblk[k]) / fin.bnorm;
+    out.t_setup = S.t_setup;
+    out.t_solve = wall_time() - t0;
+    if (stats) *stats = out;
+    return status;
+  }
+  double* bicg_x = nullptr;
 };
 
 }  // namespace

@@ -190,3 +190,47 @@ def test_c1_full_size_fp64():
     print("C1 fp64", st, flush=True)
     assert rc == sd.SD_OK
     assert np.linalg.norm(a.b - a.A @ xg) <= 1e-8 * np.linalg.norm(a.b)
+
+
+@pytest.mark.parametrize("name,variant", [("mms32", "BJ"), ("channel96", "BGS"),
+                                          ("channel_ragged", "BGS")])
+def test_bicgstab_matches_oracle(name, variant):
+    p = SMALL[name]()
+    print("case", name, variant, flush=True)
+    a = assemble(p)
+    M = precond.build(p, a, variant)
+    ref = krylov.bicgstab(a.A, a.b, M, tol=1e-8)
+    xs = refined_solve(a.A, a.b)
+    P, S = _setup(p, krylov="bicgstab", precond=variant, tol=1e-8)
+    x, st, rc = S.solve()
+    x = _host(x)
+    assert rc == sd.SD_OK
+    assert np.linalg.norm(a.b - a.A @ x) <= 1e-8 * np.linalg.norm(a.b)
+    e_gpu = np.linalg.norm(x - xs) / np.linalg.norm(xs)
+    e_ref = np.linalg.norm(ref.x - xs) / np.linalg.norm(xs)
+    assert e_gpu <= 10 * e_ref + 1e-10
+    # BiCGSTAB's path is rounding-sensitive over many steps; step by step the
+    # GPU iterate follows the oracle's
+    for k, bound in ((5, 1e-9), (10, 1e-7)):
+        rk = krylov.bicgstab(a.A, a.b, M, tol=1e-30, maxit=k)
+        P, S = _setup(p, krylov="bicgstab", precond=variant, tol=1e-30, maxit=k)
+        xk, stk, rc = S.solve()
+        assert rc == sd.SD_E_NOCONV and stk["iters"] == k
+        xk = _host(xk)
+        assert np.linalg.norm(xk - rk.x) <= bound * np.linalg.norm(rk.x)
+
+
+def test_bicgstab_mixed_and_repeat():
+    p = SMALL["channel96"]()
+    a = assemble(p)
+    P, S = _setup(p, krylov="bicgstab", precision="mixed", tol=1e-8)
+    x1, st1, rc = S.solve()
+    assert rc == sd.SD_OK
+    x1h = _host(x1)
+    assert np.linalg.norm(a.b - a.A @ x1h) <= 1e-8 * np.linalg.norm(a.b)
+    x2, st2, rc = S.solve()
+    assert torch.equal(x1, x2)
+    # new output buffer: the captured graph must follow it
+    x3 = torch.full((a.N,), 7.0, dtype=torch.float64, device="cuda")
+    x3, st3, rc = S.solve(x=x3)
+    assert torch.equal(x1, x3)
