@@ -168,6 +168,8 @@ Solver::~Solver() {
   for (auto e : events) (void)hipEventDestroy(e);
   for (auto e : prof_ev) (void)hipEventDestroy(e);
   if (ev_join) (void)hipEventDestroy(ev_join);
+  if (ev_state) (void)hipEventDestroy(ev_state);
+  if (hs) (void)hipHostFree(hs);
   if (stream) (void)hipStreamDestroy(stream);
   if (hf) (void)hipHostFree((void*)hf);
 }
@@ -196,6 +198,11 @@ void Solver::upload(const sd_allocator* alloc, hipStream_t s) {
   events.resize((size_t)kMaxBasis + 2);
   for (auto& e : events) SD_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   SD_HIP(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+  SD_HIP(hipEventCreateWithFlags(&ev_state, hipEventDisableTiming));
+  void* hsp = nullptr;
+  SD_HIP(hipHostMalloc(&hsp, sizeof(HostState), hipHostMallocDefault));
+  hs = static_cast<HostState*>(hsp);
+  std::memset(hsp, 0, sizeof(HostState));
   prof_ev.resize((size_t)2 * kMaxBasis);
   for (auto& e : prof_ev) SD_HIP(hipEventCreate(&e));
   nnz_A = pb->A.nnz();
@@ -358,12 +365,6 @@ class PrecImpl : public PrecBase {
     }
   }
 
-  struct HostState {
-    int j, k, cycle_done, m, converged, breakdown, iters, pad0;
-    double bnorm, target, cycle_drop, cycle_target, beta;
-    double resblk[4];
-  };
-
   HostState read_state(Solver& S, hipStream_t s) {
     HostState h;
     SD_HIP(hipMemcpyAsync(&h, S.st, sizeof(HostState), hipMemcpyDeviceToHost, s));
@@ -371,100 +372,167 @@ class PrecImpl : public PrecBase {
     return h;
   }
 
-  int fgmres(Solver& S, const double* b, double* x, int use_x0, sd_stats* stats,
-             hipStream_t user) override {
-    // The iteration runs on the solver's own stream (graphs cannot be captured
-    // on the legacy default stream); it is ordered after the caller's stream.
+  // ------------------------------------------------- resumable FGMRES driver
+  // A solve is a state machine advanced by step(): it only enqueues work and
+  // polls events, so a request loop can interleave many solves; sd_solve runs
+  // the same machine with blocking waits.
+  void start(Solver& S, SolveRun& R) override {
+    R.phase = SolveRun::INIT;
+    R.first = true;
+    R.restarts = 0;
+    R.status = SD_E_NOCONV;
+    R.t0 = wall_time();
+    R.out = sd_stats{};
+  }
+
+  static bool ready(hipEvent_t e, bool block) {
+    if (block) {
+      SD_HIP(hipEventSynchronize(e));
+      return true;
+    }
+    const hipError_t q = hipEventQuery(e);
+    if (q == hipSuccess) return true;
+    if (q == hipErrorNotReady) return false;
+    SD_HIP(q);
+    return false;
+  }
+
+  void async_state(Solver& S, hipStream_t s) {
+    SD_HIP(hipMemcpyAsync(S.hs, S.st, sizeof(HostState), hipMemcpyDeviceToHost, s));
+    SD_HIP(hipEventRecord(S.ev_state, s));
+  }
+
+  void finish(Solver& S, SolveRun& R, int status) {
+    const HostState& hs = *S.hs;
+    R.status = status;
+    R.out.iters = hs.iters;
+    R.out.restarts = R.restarts;
+    R.out.rel_res = hs.bnorm > 0.0 ? hs.beta / hs.bnorm : 0.0;
+    for (int k = 0; k < 3; ++k)
+      R.out.rel_res_block[k] = hs.bnorm > 0.0 ? std::sqrt(hs.resblk[k]) / hs.bnorm : 0.0;
+    R.out.t_setup = S.t_setup;
+    R.out.t_solve = wall_time() - R.t0;
+    R.phase = SolveRun::DONE;
+  }
+
+  bool step(Solver& S, SolveRun& R, bool block) override {
     hipStream_t s = S.stream;
-    SD_HIP(hipEventRecord(S.ev_join, user));
-    SD_HIP(hipStreamWaitEvent(s, S.ev_join, 0));
-    const double t0 = wall_time();
     const sd_solver_opts& o = S.opts.o;
     const int n = S.N;
     const int m = o.restart;
     const double drop = std::is_same<T, float>::value ? 1e-6 : 0.0;
-    launch_init_state(S.st, m, drop, s);
-    launch_norm_b(b, n, o.tol, S.st, S.part, s);
-    HostState hs = read_state(S, s);
-    sd_stats out{};
-    if (!(hs.bnorm > 0.0)) {
-      launch_fill<double>(x, 0.0, n, s);
-      SD_HIP(hipStreamSynchronize(s));
-      out.t_setup = S.t_setup;
-      out.t_solve = wall_time() - t0;
-      if (stats) *stats = out;
-      return std::isfinite(hs.bnorm) ? SD_OK : SD_E_INVALID;
-    }
-    if (!use_x0) launch_fill<double>(x, 0.0, n, s);
-    bool first = true;
-    int status = SD_E_NOCONV;
-    int restarts = 0;
     const int depth = 2;
-    for (;;) {
-      const int it_done = hs.iters;
-      const int m_cycle = std::min(m, std::max(1, o.maxit - it_done));
-      // cycle length for this restart
-      launch_init_cycle(S, m_cycle, s);
-      launch_restart_residual(S.A64, b, (first && !use_x0) ? nullptr : x, S.V, S.off, S.st,
-                              S.part, S.hf_dev, s);
-      first = false;
-      hs = read_state(S, s);
-      if (hs.breakdown || !std::isfinite(hs.beta)) {
-        status = SD_E_BREAKDOWN;
-        break;
+    switch (R.phase) {
+      case SolveRun::INIT:
+        launch_init_state(S.st, m, drop, s);
+        launch_norm_b(R.b, n, o.tol, S.st, S.part, s);
+        async_state(S, s);
+        R.phase = SolveRun::WAIT_NORM;
+        return true;
+      case SolveRun::WAIT_NORM:
+        if (!ready(S.ev_state, block)) return false;
+        if (!(S.hs->bnorm > 0.0)) {
+          launch_fill<double>(R.x, 0.0, n, s);
+          SD_HIP(hipStreamSynchronize(s));
+          S.hs->beta = 0.0;
+          finish(S, R, std::isfinite(S.hs->bnorm) ? SD_OK : SD_E_INVALID);
+          return true;
+        }
+        if (!R.use_x0) launch_fill<double>(R.x, 0.0, n, s);
+        R.phase = SolveRun::RESTART;
+        return true;
+      case SolveRun::RESTART: {
+        launch_restart_residual(S.A64, R.b, (R.first && !R.use_x0) ? nullptr : R.x, S.V, S.off,
+                                S.st, S.part, S.hf_dev, s);
+        R.first = false;
+        async_state(S, s);
+        R.phase = SolveRun::WAIT_RESTART;
+        return true;
       }
-      if (hs.converged) {
-        status = SD_OK;
-        break;
+      case SolveRun::WAIT_RESTART: {
+        if (!ready(S.ev_state, block)) return false;
+        const HostState& hs = *S.hs;
+        if (hs.breakdown || !std::isfinite(hs.beta)) {
+          finish(S, R, SD_E_BREAKDOWN);
+          return true;
+        }
+        if (hs.converged) {
+          finish(S, R, SD_OK);
+          return true;
+        }
+        if (hs.iters >= o.maxit) {
+          finish(S, R, SD_E_NOCONV);
+          return true;
+        }
+        for (int j = 0; j <= kMaxBasis; ++j) {
+          S.hf->cycle_done[j] = 0;
+          S.hf->est[j] = 0.0;
+        }
+        R.ctarget = std::max(hs.target, drop * hs.beta);
+        R.m_cycle = std::min(m, std::max(1, o.maxit - hs.iters));
+        launch_init_cycle(S, R.m_cycle, s);
+        R.j_enq = 0;
+        R.completed = -1;
+        R.phase = SolveRun::ITER;
+        return true;
       }
-      if (hs.iters >= o.maxit) {
-        status = SD_E_NOCONV;
-        break;
-      }
-      for (int j = 0; j <= kMaxBasis; ++j) {
-        S.hf->cycle_done[j] = 0;
-        S.hf->est[j] = 0.0;
-      }
-      // Run ahead of the device by up to `depth` iterations, except when the
-      // residual estimates predict the end of the cycle within that window
-      // (iterations enqueued after the cycle ends only waste time; their
-      // Arnoldi kernels return at once, their preconditioner work is unused).
-      const double ctarget = std::max(hs.target, drop * hs.beta);
-      int waited = -1;
-      auto wait_upto = [&](int q) {
-        for (int r = waited + 1; r <= q; ++r) SD_HIP(hipEventSynchronize(S.events[(size_t)r]));
-        if (q > waited) waited = q;
-      };
-      for (int j = 0; j < m_cycle; ++j) {
+      case SolveRun::ITER: {
+        while (R.completed + 1 < R.j_enq && ready(S.events[(size_t)(R.completed + 1)], false))
+          ++R.completed;
+        bool done = false;
+        for (int q = 0; q <= R.completed; ++q) done = done || S.hf->cycle_done[q];
+        if (done || R.j_enq == R.m_cycle) {
+          launch_trisolve(S.st, s);
+          launch_update_x<T>(R.x, Z, ldz, n, S.st, s);
+          ++R.restarts;
+          if (S.prof_class != 0) collect_profile(S, s);
+          R.phase = SolveRun::RESTART;
+          return true;
+        }
+        // Run ahead of the device by up to `depth` columns, except when the
+        // residual estimates predict the end of the cycle within that window.
         int ahead = depth;
-        if (waited >= 1) {
-          const double e1 = S.hf->est[waited], e0 = S.hf->est[waited - 1];
+        if (R.completed >= 1) {
+          const double e1 = S.hf->est[R.completed], e0 = S.hf->est[R.completed - 1];
           const double rho = e0 > 0.0 ? e1 / e0 : 1.0;
           if (rho > 0.0 && rho < 1.0) {
-            const double need = std::log(ctarget / e1) / std::log(rho);
-            if (need <= (double)(j - waited) + 1.0) ahead = 0;
+            const double need = std::log(R.ctarget / e1) / std::log(rho);
+            if (need <= (double)(R.j_enq - R.completed)) ahead = 0;
           }
         }
-        if (j - 1 - ahead >= 0) wait_upto(j - 1 - ahead);
-        bool done = false;
-        for (int q = 0; q <= waited; ++q) done = done || S.hf->cycle_done[q];
-        if (done) break;
-        iteration(S, j, s);
-        SD_HIP(hipEventRecord(S.events[(size_t)j], s));
+        if (R.j_enq - 1 - R.completed <= ahead) {
+          iteration(S, R.j_enq, s);
+          SD_HIP(hipEventRecord(S.events[(size_t)R.j_enq], s));
+          ++R.j_enq;
+          return true;
+        }
+        if (block) {
+          SD_HIP(hipEventSynchronize(S.events[(size_t)(R.completed + 1)]));
+          return true;
+        }
+        return false;
       }
-      launch_trisolve(S.st, s);
-      launch_update_x<T>(x, Z, ldz, n, S.st, s);
-      ++restarts;
-      if (S.prof_class != 0) collect_profile(S, s);
+      case SolveRun::DONE:
+        return false;
     }
-    out.iters = hs.iters;
-    out.restarts = restarts;
-    out.rel_res = hs.beta / hs.bnorm;
-    for (int k = 0; k < 3; ++k) out.rel_res_block[k] = std::sqrt(hs.resblk[k]) / hs.bnorm;
-    out.t_setup = S.t_setup;
-    out.t_solve = wall_time() - t0;
-    if (stats) *stats = out;
-    return status;
+    return false;
+  }
+
+  int fgmres(Solver& S, const double* b, double* x, int use_x0, sd_stats* stats,
+             hipStream_t user) override {
+    // The iteration runs on the solver's own stream (graphs cannot be captured
+    // on the legacy default stream); it is ordered after the caller's stream.
+    SD_HIP(hipEventRecord(S.ev_join, user));
+    SD_HIP(hipStreamWaitEvent(S.stream, S.ev_join, 0));
+    SolveRun R;
+    R.b = b;
+    R.x = x;
+    R.use_x0 = use_x0;
+    start(S, R);
+    while (R.phase != SolveRun::DONE) step(S, R, true);
+    SD_HIP(hipStreamSynchronize(S.stream));
+    if (stats) *stats = R.out;
+    return R.status;
   }
 
   // Enqueue Arnoldi step j (preconditioner + orthogonalisation) as a graph.

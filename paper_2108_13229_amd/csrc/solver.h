@@ -64,6 +64,27 @@ struct SolverOpts {
 
 class Solver;
 
+// Solver scalars as copied to the host (prefix of DevState).
+struct HostState {
+  int j, k, cycle_done, m, converged, breakdown, iters, pad0;
+  double bnorm, target, cycle_drop, cycle_target, beta;
+  double resblk[4];
+};
+
+// Progress of one resumable FGMRES solve.
+struct SolveRun {
+  enum Phase { INIT, WAIT_NORM, RESTART, WAIT_RESTART, ITER, DONE };
+  Phase phase = INIT;
+  const double* b = nullptr;
+  double* x = nullptr;
+  int use_x0 = 0;
+  bool first = true;
+  int restarts = 0, status = SD_E_NOCONV;
+  int m_cycle = 0, j_enq = 0, completed = -1;
+  double ctarget = 0.0, t0 = 0.0;
+  sd_stats out{};
+};
+
 // Precision-specific part: preconditioner operators and the Arnoldi matrix.
 class PrecBase {
  public:
@@ -72,6 +93,10 @@ class PrecBase {
                      hipStream_t s) = 0;
   virtual int bicgstab(Solver& S, const double* b, double* x, int use_x0, sd_stats* st,
                        hipStream_t s) = 0;
+  // resumable FGMRES: start() then step() until run.phase == DONE; step()
+  // returns whether it made progress (it never blocks unless block is set)
+  virtual void start(Solver& S, SolveRun& run) = 0;
+  virtual bool step(Solver& S, SolveRun& run, bool block) = 0;
   virtual void apply_precond(Solver& S, const double* r, double* z, hipStream_t s) = 0;
   virtual void apply_vcycle(Solver& S, int block, const double* b, double* x,
                             hipStream_t s) = 0;
@@ -102,6 +127,8 @@ class Solver {
   int64_t ldv = 0;
   std::vector<hipEvent_t> events;
   hipEvent_t ev_join = nullptr;
+  hipEvent_t ev_state = nullptr;    // marks a finished state copy to hs
+  HostState* hs = nullptr;          // pinned host copy of the solver scalars
   hipStream_t stream = nullptr;     // internal non-blocking stream (default priority)
   std::unique_ptr<PrecBase> prec;
   // measurement mode: events around one kernel class (0 = off)

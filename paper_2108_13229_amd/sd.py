@@ -352,6 +352,64 @@ class Solver:
             pass
 
 
+class Server:
+    """Request loop (continuous batching) on one GPU; see sd_server_* in sd.h."""
+
+    def __init__(self, max_slots: int = 8, hbm_budget: int = 0, device: int = 0):
+        o = ServerOpts(hbm_budget, max_slots, device)
+        h = C.c_void_p()
+        _check(lib().sd_server_create(C.byref(o), C.byref(h)))
+        self.h = h
+
+    def submit(self, p, **opts) -> int:
+        keep = []
+        g, ph, b, f, K = _marshal(p, keep)
+        req = Request(g, ph, b, K, f, solver_opts(**opts))
+        t = C.c_uint64()
+        _check(lib().sd_submit(self.h, C.byref(req), C.byref(t)))
+        return t.value
+
+    @staticmethod
+    def _result(r: "Result", with_x: bool):
+        d = dict(state=REQ_STATE.get(r.state, r.state), status=r.status, N=r.N,
+                 stats=r.stats.as_dict(), t_submit=r.t_submit, t_admit=r.t_admit,
+                 t_done=r.t_done)
+        if with_x and r.x_host:
+            d["x"] = np.ctypeslib.as_array(r.x_host, (r.N,)).copy()
+        return d
+
+    def poll(self, ticket: int, with_x: bool = False):
+        r = Result()
+        _check(lib().sd_poll(self.h, ticket, C.byref(r)))
+        return self._result(r, with_x)
+
+    def wait(self, ticket: int, timeout: float = 600.0, with_x: bool = True):
+        r = Result()
+        rc = lib().sd_wait(self.h, ticket, timeout, C.byref(r))
+        if rc not in (SD_OK, SD_E_BUSY):
+            _check(rc)
+        d = self._result(r, with_x)
+        d["timed_out"] = rc == SD_E_BUSY
+        return d
+
+    def release(self, ticket: int):
+        _check(lib().sd_result_release(self.h, ticket))
+
+    def cancel(self, ticket: int):
+        _check(lib().sd_cancel(self.h, ticket))
+
+    def close(self):
+        if self.h:
+            lib().sd_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def _require(t, n):
     import torch
     if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.numel() == n):
