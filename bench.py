@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--restart", type=int, default=60)
     ap.add_argument("--roofline-solves", type=int, default=3)
+    ap.add_argument("--serving", type=int, default=0,
+                    help="serving mode: replay a seeded trace of this many requests")
+    ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--counter-run", action="store_true",
                     help="one FP64 solve with plain (non-graph) launches plus a 512 MiB "
                          "device copy, for hardware-counter passes")
@@ -117,6 +120,83 @@ def counter_run(sd, p, restart):
     print(json.dumps({"counter_run": True, "iters": st["iters"], "copy_bytes": a.numel() * 8}))
 
 
+def replay(sd, probs, arrivals, slots, **opts):
+    """Submit each request at its arrival time (seconds after start); returns
+    per-request latency (done - arrival) and the makespan."""
+    S = sd.Server(max_slots=slots)
+    t0 = time.perf_counter()
+    tickets = []
+    for p, ta in zip(probs, arrivals):
+        dt = ta - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append((S.submit(p, **opts), time.perf_counter() - t0))
+    lat, iters = [], []
+    t_end = 0.0
+    for (t, t_sub), ta in zip(tickets, arrivals):
+        r = S.wait(t, timeout=600, with_x=False)
+        if r["status"] != 0:
+            raise RuntimeError(f"request failed: {r['status']}")
+        # server clock and wall clock share the start within milliseconds;
+        # latency = completion - arrival on the server clock
+        lat.append(r["t_done"] - (r["t_submit"] - (t_sub - ta)))
+        iters.append(r["stats"]["iters"])
+        t_end = max(t_end, r["t_done"])
+        S.release(t)
+    S.close()
+    return np.array(lat), time.perf_counter() - t0, iters
+
+
+def serving(sd, args):
+    """Seeded request stream (grid uniform over 64x32 ... 512x256 per
+    subdomain, lognormal K with sigma ~ U[0.5, 2], inflow ~ U[1e-3, 1e-1]):
+    saturated throughput with all requests queued at t = 0, then Poisson
+    arrivals at 0.9x that rate; baseline: one request at a time in FP64."""
+    import torch
+    from sdinputs import serving_trace, trace_problem
+    n = args.serving
+    trace0 = serving_trace(n, rate_per_s=0.0, seed=7)
+    probs = [trace_problem(t) for t in trace0]
+    opts = dict(tol=1e-8, restart=args.restart, precision="mixed")
+    lat_sat, span_sat, _ = replay(sd, probs, [0.0] * n, args.slots, **opts)
+    rate = 0.9 * n / span_sat
+    trace = serving_trace(n, rate_per_s=rate, seed=7)
+    arr = [t["t_arrival"] for t in trace]
+    lat, span, iters = replay(sd, probs, arr, args.slots, **opts)
+    # FP64 one request at a time (assembly, setup, solve), same arrivals
+    t0 = time.perf_counter()
+    lat1 = []
+    for p, ta in zip(probs, arr):
+        dt = ta - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        P = sd.Problem(p)
+        Sv = sd.Solver(P, tol=1e-8, restart=args.restart)
+        x, st, rc = Sv.solve()
+        torch.cuda.synchronize()
+        lat1.append(time.perf_counter() - t0 - ta)
+        Sv.close()
+        P.close()
+    span1 = time.perf_counter() - t0
+    out = {
+        "metric": "Stokes-Darcy serving: solves/s and p50/p99 latency (mixed, continuous batching)",
+        "value": n / span, "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+        "requests": n, "slots": args.slots, "arrival_rate_per_s": rate,
+        "saturated_solves_per_s": n / span_sat,
+        "p50_ms": 1e3 * float(np.percentile(lat, 50)),
+        "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+        "median_iters": float(np.median(iters)),
+        "fp64_one_at_a_time": {"solves_per_s": n / span1,
+                               "p50_ms": 1e3 * float(np.percentile(lat1, 50)),
+                               "p99_ms": 1e3 * float(np.percentile(lat1, 99))},
+        "data": "synthetic", "dtype": "f32+f64",
+        "config": {"workload": "Poisson request stream, grids 64x32..512x256 per subdomain, "
+                               "lognormal K sigma U[0.5,2], inflow U[1e-3,1e-1], seed 7",
+                   "restart": args.restart},
+    }
+    print(json.dumps(out))
+
+
 def cpu_baseline(p, restart):
     """The oracle's FP64 FGMRES with the same preconditioner, one solve,
     single-threaded (setup excluded; timed separately)."""
@@ -150,6 +230,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
+    if args.serving:
+        serving(sd, args)
+        return
     p = channel_problem(args.nx, args.ny, seed=args.seed)
     if args.counter_run:
         counter_run(sd, p, args.restart)
