@@ -13,8 +13,10 @@ constexpr int kDotBlocks = 512;     // workgroups of the fused reduction kernels
 constexpr int kPartStride = kMaxBasis + 4;   // partial-sum rows (k-major, kDotBlocks each)
 constexpr int kGsMaxBlocks = 1024;          // row blocks of the Gram-Schmidt kernels
 
-// Sliced ELLPACK with 64-row slices (one wavefront per slice).  Entry (r, k)
-// of slice s lives at sptr[s] + 64 k + (r - 64 s); padding has val = 0.
+// Sparse matrix on the device.  lpr == 1: sliced ELLPACK with 64-row slices
+// (one wavefront per slice); entry (r, k) of slice s lives at
+// sptr[s] + 64 k + (r - 64 s), padding has val = 0.  lpr > 1: CSR (sptr holds
+// the n_rows + 1 row pointers) read by lpr lanes per row.
 template <typename T>
 struct Sell {
   const int* sptr = nullptr;
@@ -22,6 +24,7 @@ struct Sell {
   const T* val = nullptr;
   int n_rows = 0;
   int n_cols = 0;
+  int lpr = 1;
 };
 
 // Solver scalars resident in device memory.

@@ -112,57 +112,83 @@ inline int dot_blocks(int n) {
 
 // ----------------------------------------------------------------- kernels
 
-template <typename TM, typename TX, typename TY>
+// Row access for the V-cycle kernels.  LPR == 1: SELL-64, one lane per row.
+// LPR > 1: CSR (A.sptr holds the row pointers) with LPR consecutive lanes per
+// row and a shuffle reduction; used on coarse levels, whose smoothed-
+// aggregation rows are long and few, where one lane per row leaves the chip
+// idle and serialises the gathers.  f(c) supplies the multiplied vector entry.
+template <int LPR, typename TM, typename F>
+__device__ __forceinline__ TM row_sum(const Sell<TM>& A, int row, int sub, F f) {
+  TM acc = 0;
+  if constexpr (LPR == 1) {
+    const int s = row >> 6;
+    const int beg = A.sptr[s] + (row & 63);
+    const int end = A.sptr[s + 1];
+#pragma unroll 4
+    for (int e = beg; e < end; e += 64) acc += A.val[e] * f(A.col[e]);
+  } else {
+    const int end = A.sptr[row + 1];
+#pragma unroll 2
+    for (int e = A.sptr[row] + sub; e < end; e += LPR) acc += A.val[e] * f(A.col[e]);
+#pragma unroll
+    for (int o = LPR / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LPR);
+  }
+  return acc;
+}
+
+// thread -> (row, lane within the row group), XCD-contiguous row ranges
+template <int LPR>
+__device__ __forceinline__ int2 row_of_thread() {
+  const int gt = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  return make_int2(gt / LPR, gt % LPR);
+}
+
+template <int LPR, typename TM, typename TX, typename TY>
 __global__ __launch_bounds__(kBlock) void k_spmv(Sell<TM> A, const TX* __restrict__ x,
                                                  TY* __restrict__ y, const DevState* gate) {
   if (gate && gate->cycle_done) return;
-  const int row = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  if (row >= A.n_rows) return;
-  y[row] = (TY)sell_dot(A, x, row);
+  const int2 rs = row_of_thread<LPR>();
+  if (rs.x >= A.n_rows) return;
+  const TM v = row_sum<LPR>(A, rs.x, rs.y, [&](int c) { return (TM)x[c]; });
+  if (rs.y == 0) y[rs.x] = (TY)v;
 }
 
-template <typename T, typename TB>
+template <int LPR, typename T, typename TB>
 __global__ __launch_bounds__(kBlock) void k_residual(Sell<T> A, const TB* __restrict__ b,
                                                      const double* bscale,
                                                      const T* __restrict__ x,
                                                      T* __restrict__ r, const DevState* gate) {
   if (gate && gate->cycle_done) return;
-  const int row = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  if (row >= A.n_rows) return;
-  const T bv = load_b<T>(b, scale_of(bscale), row);
-  r[row] = bv - sell_dot(A, x, row);
+  const int2 rs = row_of_thread<LPR>();
+  if (rs.x >= A.n_rows) return;
+  const T ax = row_sum<LPR>(A, rs.x, rs.y, [&](int c) { return x[c]; });
+  if (rs.y == 0) r[rs.x] = load_b<T>(b, scale_of(bscale), rs.x) - ax;
 }
 
-template <typename T, typename TB>
+// x = w .* b (one sweep from zero) or two sweeps from zero fused: the first
+// sweep's values x1 = w .* b are recomputed at the neighbours.
+template <int LPR, typename T, typename TB>
 __global__ __launch_bounds__(kBlock) void k_jacobi_zero(Sell<T> A, const T* __restrict__ wd,
                                                         const TB* __restrict__ b,
                                                         const double* bscale,
                                                         T* __restrict__ x, int two,
                                                         const DevState* gate) {
   if (gate && gate->cycle_done) return;
-  const int row = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const int2 rs = row_of_thread<LPR>();
+  const int row = rs.x;
   if (row >= A.n_rows) return;
   const double s = scale_of(bscale);
   const T bi = load_b<T>(b, s, row);
   const T x1 = wd[row] * bi;
   if (!two) {
-    x[row] = x1;
+    if (rs.y == 0) x[row] = x1;
     return;
   }
-  // second sweep from x1 = w .* b, computed on the fly at the neighbours
-  const int sl = row >> 6;
-  const int beg = A.sptr[sl] + (row & 63);
-  const int end = A.sptr[sl + 1];
-  T acc = 0;
-#pragma unroll 4
-  for (int e = beg; e < end; e += 64) {
-    const int c = A.col[e];
-    acc += A.val[e] * (wd[c] * load_b<T>(b, s, c));
-  }
-  x[row] = x1 + wd[row] * (bi - acc);
+  const T acc = row_sum<LPR>(A, row, rs.y, [&](int c) { return wd[c] * load_b<T>(b, s, c); });
+  if (rs.y == 0) x[row] = x1 + wd[row] * (bi - acc);
 }
 
-template <typename T, typename TB>
+template <int LPR, typename T, typename TB>
 __global__ __launch_bounds__(kBlock) void k_jacobi(Sell<T> A, const T* __restrict__ wd,
                                                    const TB* __restrict__ b,
                                                    const double* bscale,
@@ -170,21 +196,26 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(Sell<T> A, const T* __restric
                                                    T* __restrict__ xout,
                                                    const DevState* gate) {
   if (gate && gate->cycle_done) return;
-  const int row = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const int2 rs = row_of_thread<LPR>();
+  const int row = rs.x;
   if (row >= A.n_rows) return;
-  const T bi = load_b<T>(b, scale_of(bscale), row);
-  xout[row] = xin[row] + wd[row] * (bi - sell_dot(A, xin, row));
+  const T ax = row_sum<LPR>(A, row, rs.y, [&](int c) { return xin[c]; });
+  if (rs.y == 0)
+    xout[row] = xin[row] + wd[row] * (load_b<T>(b, scale_of(bscale), row) - ax);
 }
 
-template <typename T>
+template <int LPR, typename T>
 __global__ __launch_bounds__(kBlock) void k_prolong(Sell<T> P, const T* __restrict__ xc,
                                                     T* __restrict__ x, const DevState* gate) {
   if (gate && gate->cycle_done) return;
-  const int row = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  if (row >= P.n_rows) return;
-  x[row] += sell_dot(P, xc, row);
+  const int2 rs = row_of_thread<LPR>();
+  if (rs.x >= P.n_rows) return;
+  const T v = row_sum<LPR>(P, rs.x, rs.y, [&](int c) { return xc[c]; });
+  if (rs.y == 0) x[rs.x] += v;
 }
 
+// xc = Ainv bc, FP64 dense inverse, one wavefront per row with four
+// independent partial sums per lane.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_coarse(const double* __restrict__ Ainv, int n,
                                                    const T* __restrict__ bc,
@@ -194,9 +225,16 @@ __global__ __launch_bounds__(kBlock) void k_coarse(const double* __restrict__ Ai
   const int lane = threadIdx.x & 63;
   if (w >= n) return;
   const double* a = Ainv + (size_t)w * n;
-  double acc = 0.0;
-  for (int c = lane; c < n; c += 64) acc += a[c] * (double)bc[c];
-  acc = wave_sum(acc);
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int c = lane;
+  for (; c + 192 < n; c += 256) {
+    s0 += a[c] * (double)bc[c];
+    s1 += a[c + 64] * (double)bc[c + 64];
+    s2 += a[c + 128] * (double)bc[c + 128];
+    s3 += a[c + 192] * (double)bc[c + 192];
+  }
+  for (; c < n; c += 64) s0 += a[c] * (double)bc[c];
+  const double acc = wave_sum((s0 + s1) + (s2 + s3));
   if (lane == 0) xc[w] = (T)acc;
 }
 
@@ -783,37 +821,64 @@ __global__ __launch_bounds__(kBlock) void k_fill(T* __restrict__ a, T v, int n) 
 
 // ---------------------------------------------------------------- launchers
 
+inline int blocks_lpr(int n, int lpr) { return (int)(((int64_t)n * lpr + kBlock - 1) / kBlock); }
+
 template <typename TM, typename TX, typename TY>
 void launch_spmv(const Sell<TM>& A, const TX* x, TY* y, const DevState* gate, hipStream_t s) {
   if (A.n_rows <= 0) return;
-  k_spmv<TM, TX, TY><<<blocks_for(A.n_rows), kBlock, 0, s>>>(A, x, y, gate);
+  switch (A.lpr) {
+    case 4: k_spmv<4, TM, TX, TY><<<blocks_lpr(A.n_rows, 4), kBlock, 0, s>>>(A, x, y, gate); break;
+    case 8: k_spmv<8, TM, TX, TY><<<blocks_lpr(A.n_rows, 8), kBlock, 0, s>>>(A, x, y, gate); break;
+    case 16: k_spmv<16, TM, TX, TY><<<blocks_lpr(A.n_rows, 16), kBlock, 0, s>>>(A, x, y, gate); break;
+    default: k_spmv<1, TM, TX, TY><<<blocks_lpr(A.n_rows, 1), kBlock, 0, s>>>(A, x, y, gate); break;
+  }
 }
 
 template <typename T, typename TB>
 void launch_residual(const Sell<T>& A, const TB* b, const double* bscale, const T* x, T* r,
                      const DevState* gate, hipStream_t s) {
   if (A.n_rows <= 0) return;
-  k_residual<T, TB><<<blocks_for(A.n_rows), kBlock, 0, s>>>(A, b, bscale, x, r, gate);
+  switch (A.lpr) {
+    case 4: k_residual<4, T, TB><<<blocks_lpr(A.n_rows, 4), kBlock, 0, s>>>(A, b, bscale, x, r, gate); break;
+    case 8: k_residual<8, T, TB><<<blocks_lpr(A.n_rows, 8), kBlock, 0, s>>>(A, b, bscale, x, r, gate); break;
+    case 16: k_residual<16, T, TB><<<blocks_lpr(A.n_rows, 16), kBlock, 0, s>>>(A, b, bscale, x, r, gate); break;
+    default: k_residual<1, T, TB><<<blocks_lpr(A.n_rows, 1), kBlock, 0, s>>>(A, b, bscale, x, r, gate); break;
+  }
 }
 
 template <typename T, typename TB>
 void launch_jacobi_zero(const Sell<T>& A, const T* wd, const TB* b, const double* bscale, T* x,
                         int two, const DevState* gate, hipStream_t s) {
   if (A.n_rows <= 0) return;
-  k_jacobi_zero<T, TB><<<blocks_for(A.n_rows), kBlock, 0, s>>>(A, wd, b, bscale, x, two, gate);
+  switch (A.lpr) {
+    case 4: k_jacobi_zero<4, T, TB><<<blocks_lpr(A.n_rows, 4), kBlock, 0, s>>>(A, wd, b, bscale, x, two, gate); break;
+    case 8: k_jacobi_zero<8, T, TB><<<blocks_lpr(A.n_rows, 8), kBlock, 0, s>>>(A, wd, b, bscale, x, two, gate); break;
+    case 16: k_jacobi_zero<16, T, TB><<<blocks_lpr(A.n_rows, 16), kBlock, 0, s>>>(A, wd, b, bscale, x, two, gate); break;
+    default: k_jacobi_zero<1, T, TB><<<blocks_lpr(A.n_rows, 1), kBlock, 0, s>>>(A, wd, b, bscale, x, two, gate); break;
+  }
 }
 
 template <typename T, typename TB>
 void launch_jacobi(const Sell<T>& A, const T* wd, const TB* b, const double* bscale,
                    const T* x_in, T* x_out, const DevState* gate, hipStream_t s) {
   if (A.n_rows <= 0) return;
-  k_jacobi<T, TB><<<blocks_for(A.n_rows), kBlock, 0, s>>>(A, wd, b, bscale, x_in, x_out, gate);
+  switch (A.lpr) {
+    case 4: k_jacobi<4, T, TB><<<blocks_lpr(A.n_rows, 4), kBlock, 0, s>>>(A, wd, b, bscale, x_in, x_out, gate); break;
+    case 8: k_jacobi<8, T, TB><<<blocks_lpr(A.n_rows, 8), kBlock, 0, s>>>(A, wd, b, bscale, x_in, x_out, gate); break;
+    case 16: k_jacobi<16, T, TB><<<blocks_lpr(A.n_rows, 16), kBlock, 0, s>>>(A, wd, b, bscale, x_in, x_out, gate); break;
+    default: k_jacobi<1, T, TB><<<blocks_lpr(A.n_rows, 1), kBlock, 0, s>>>(A, wd, b, bscale, x_in, x_out, gate); break;
+  }
 }
 
 template <typename T>
 void launch_prolong(const Sell<T>& P, const T* xc, T* x, const DevState* gate, hipStream_t s) {
   if (P.n_rows <= 0) return;
-  k_prolong<T><<<blocks_for(P.n_rows), kBlock, 0, s>>>(P, xc, x, gate);
+  switch (P.lpr) {
+    case 4: k_prolong<4, T><<<blocks_lpr(P.n_rows, 4), kBlock, 0, s>>>(P, xc, x, gate); break;
+    case 8: k_prolong<8, T><<<blocks_lpr(P.n_rows, 8), kBlock, 0, s>>>(P, xc, x, gate); break;
+    case 16: k_prolong<16, T><<<blocks_lpr(P.n_rows, 16), kBlock, 0, s>>>(P, xc, x, gate); break;
+    default: k_prolong<1, T><<<blocks_lpr(P.n_rows, 1), kBlock, 0, s>>>(P, xc, x, gate); break;
+  }
 }
 
 template <typename T>

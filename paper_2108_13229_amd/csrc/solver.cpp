@@ -44,9 +44,44 @@ void* DeviceMem::get(size_t bytes) {
 }
 
 // -------------------------------------------------------------------- SELL
+// Device format choice: SELL-64 for long matrices with short rows; CSR with
+// 4, 8 or 16 lanes per row for short matrices or long rows (coarse AMG
+// levels and transfer operators), when the kernels that use it allow.
+static int lanes_per_row(const HostCSR& A, bool allow_csr) {
+  if (!allow_csr || A.n_rows == 0) return 1;
+  const double avg = (double)A.nnz() / (double)A.n_rows;
+  if (avg <= 12.0 && A.n_rows >= 16384) return 1;
+  return avg <= 16.0 ? 4 : (avg <= 48.0 ? 8 : 16);
+}
+
 template <typename T>
-Sell<T> upload_sell(const HostCSR& A, DeviceMem& mem, hipStream_t s) {
+Sell<T> upload_sell(const HostCSR& A, DeviceMem& mem, hipStream_t s, bool allow_csr) {
   const int64_t n = A.n_rows;
+  const int lpr = lanes_per_row(A, allow_csr);
+  if (lpr > 1) {
+    if (A.nnz() >= ((int64_t)1 << 31)) throw Error(SD_E_INVALID, "matrix too large for int32 CSR");
+    std::vector<int> rp((size_t)n + 1);
+    for (int64_t r = 0; r <= n; ++r) rp[r] = (int)A.rowptr[r];
+    std::vector<T> val((size_t)std::max<int64_t>(A.nnz(), 1), (T)0);
+    for (int64_t k = 0; k < A.nnz(); ++k) val[k] = (T)A.val[k];
+    int* drp = mem.array<int>(rp.size());
+    int* dcol = mem.array<int>((size_t)std::max<int64_t>(A.nnz(), 1));
+    T* dval = mem.array<T>(val.size());
+    SD_HIP(hipMemcpyAsync(drp, rp.data(), rp.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    if (A.nnz() > 0)
+      SD_HIP(hipMemcpyAsync(dcol, A.col.data(), (size_t)A.nnz() * sizeof(int),
+                            hipMemcpyHostToDevice, s));
+    SD_HIP(hipMemcpyAsync(dval, val.data(), val.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    SD_HIP(hipStreamSynchronize(s));
+    Sell<T> d;
+    d.n_rows = (int)n;
+    d.n_cols = (int)A.n_cols;
+    d.sptr = drp;
+    d.col = dcol;
+    d.val = dval;
+    d.lpr = lpr;
+    return d;
+  }
   const int64_t ns = (n + 63) / 64;
   std::vector<int> sptr((size_t)ns + 1, 0);
   int64_t tot = 0;
@@ -97,8 +132,8 @@ Sell<T> upload_sell(const HostCSR& A, DeviceMem& mem, hipStream_t s) {
   return d;
 }
 
-template Sell<double> upload_sell<double>(const HostCSR&, DeviceMem&, hipStream_t);
-template Sell<float> upload_sell<float>(const HostCSR&, DeviceMem&, hipStream_t);
+template Sell<double> upload_sell<double>(const HostCSR&, DeviceMem&, hipStream_t, bool);
+template Sell<float> upload_sell<float>(const HostCSR&, DeviceMem&, hipStream_t, bool);
 
 // ------------------------------------------------------------ host setup
 static double diag_at(const HostCSR& A, int64_t r) {
@@ -233,7 +268,7 @@ void upload_hierarchy(const HostHierarchy& h, DevHierarchy<T>& d, double omega, 
     const HostLevel& H = h.levels[l];
     DevLevel<T>& D = d.lev[l];
     D.n = (int)H.A.n_rows;
-    D.A = upload_sell<T>(H.A, mem, s);
+    D.A = upload_sell<T>(H.A, mem, s, true);
     std::vector<T> wd((size_t)D.n);
     for (int i = 0; i < D.n; ++i) wd[i] = (T)(omega / diag_at(H.A, i));
     D.wd = mem.array<T>((size_t)D.n);
@@ -243,8 +278,8 @@ void upload_hierarchy(const HostHierarchy& h, DevHierarchy<T>& d, double omega, 
     D.x = mem.array<T>((size_t)D.n);
     D.b = mem.array<T>((size_t)D.n);
     if (l + 1 < h.levels.size()) {
-      D.P = upload_sell<T>(H.P, mem, s);
-      D.R = upload_sell<T>(H.R, mem, s);
+      D.P = upload_sell<T>(H.P, mem, s, true);
+      D.R = upload_sell<T>(H.R, mem, s, true);
     }
     SD_HIP(hipStreamSynchronize(s));
   }

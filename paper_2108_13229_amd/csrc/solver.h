@@ -147,7 +147,7 @@ class Solver {
 
 // SELL construction on the host and upload.
 template <typename T>
-Sell<T> upload_sell(const HostCSR& A, DeviceMem& mem, hipStream_t s);
+Sell<T> upload_sell(const HostCSR& A, DeviceMem& mem, hipStream_t s, bool allow_csr = false);
 
 std::unique_ptr<PrecBase> make_prec_fp64(Solver& S, hipStream_t s);
 std::unique_ptr<PrecBase> make_prec_fp32(Solver& S, hipStream_t s);
