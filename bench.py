@@ -30,7 +30,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = ("512x256 free-flow + 512x256 porous cells (N=524288), lognormal K seed 1, "
             "BGS(SA-AMG V-cycle, mu*Mp^-1, SA-AMG V-cycle) + FGMRES(m), rel. residual 1e-8")
-ROOFLINE_KERNEL = "k_gs_spmv_dots<double, double>"
+ROOFLINE_KERNEL = "k_arn_project<double, double>"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_arnoldi_spmv_c1.json")
 
 

@@ -203,10 +203,12 @@ int sd_apply_vcycle(sd_solver* s, int block, const double* d_b, double* d_x,
 /* Measurement: bracket every launch of one kernel class with HIP events
  * during subsequent sd_solve calls (those solves then launch kernels one by
  * one instead of replaying graphs).  kernel_class: 0 = off,
- * SD_PROF_ARNOLDI_SPMV (w = A z_j fused with the first Gram-Schmidt dot
- * pass), SD_PROF_GS_PASS2 (second Gram-Schmidt pass), SD_PROF_JACOBI_V0
- * (damped-Jacobi sweep on the finest velocity level).  Resets the counters. */
-enum { SD_PROF_OFF = 0, SD_PROF_ARNOLDI_SPMV = 1, SD_PROF_GS_PASS2 = 2, SD_PROF_JACOBI_V0 = 3 };
+ * SD_PROF_ARNOLDI_SPMV (w = A z_j fused with the projection pass over the
+ * basis), SD_PROF_ARNOLDI_UPDATE (the Gram-Schmidt update pass),
+ * SD_PROF_JACOBI_V0 (damped-Jacobi sweep on the finest velocity level).
+ * Resets the counters. */
+enum { SD_PROF_OFF = 0, SD_PROF_ARNOLDI_SPMV = 1, SD_PROF_ARNOLDI_UPDATE = 2,
+       SD_PROF_JACOBI_V0 = 3 };
 int sd_solver_profile(sd_solver* s, int kernel_class);
 /* Launches timed, their summed event durations (seconds) and the summed
  * algorithmic bytes of those launches (each matrix entry, vector entry and

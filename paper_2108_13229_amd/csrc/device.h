@@ -12,6 +12,10 @@ constexpr int kBlock = 256;         // threads per workgroup (4 wavefronts)
 constexpr int kDotBlocks = 512;     // workgroups of the fused reduction kernels
 constexpr int kPartStride = kMaxBasis + 4;   // partial-sum rows (k-major, kDotBlocks each)
 constexpr int kGsMaxBlocks = 1024;          // row blocks of the Gram-Schmidt kernels
+// partial-sum rows of the Gram-Schmidt kernels (kGsMaxBlocks each):
+// V^T u at kGsRowA, V^T w at kGsRowB, then u.u, u.w, w.w
+constexpr int kGsRowA = 0, kGsRowB = kMaxBasis, kGsRowC = 2 * kMaxBasis;
+constexpr int kGsPartRows = 2 * kMaxBasis + 3;
 
 // Sparse matrix on the device.  lpr == 1: sliced ELLPACK with 64-row slices
 // (one wavefront per slice); entry (r, k) of slice s lives at
@@ -39,10 +43,10 @@ struct DevState {
   int pad0;
   double bnorm, target, cycle_drop, cycle_target, beta;
   double resblk[4];
-  double sigma[kMaxBasis + 1];       // basis vector k is sigma[k] * V[k]
+  double sigma[kMaxBasis + 1];       // preconditioner input scale of V[k]
   double H[(kMaxBasis + 1) * kMaxBasis];   // column-major, ld = kMaxBasis + 1
   double cs[kMaxBasis], sn[kMaxBasis], g[kMaxBasis + 1], y[kMaxBasis];
-  double h1[kMaxBasis + 1], h2[kMaxBasis + 1];
+  double h1[kMaxBasis + 1];          // first-pass coefficients of the open column
   // BiCGSTAB scalars
   double rho, alpha, omega, bbeta, dots[8];
   unsigned int counter[8];
@@ -84,18 +88,24 @@ template <typename T>
 void launch_block_sweep(const Sell<T>& Cf, int n_p, const double* r, const double* bscale,
                         const T* yv, double xscale, T* zp, T* tq, const DevState* gate,
                         hipStream_t s);
-// One Arnoldi step for column j (FP64 basis V, leading dimension ldv; the
-// basis is stored unnormalised, vector k being sigma[k] * V[k]):
-//   w = A z, h1 = sigma .* (V^T w)                     (spmv + first dot pass)
-//   w -= V (sigma .* h1), h2 = sigma .* (V^T w)        (second Gram-Schmidt pass)
-//   V[j+1] = w - V (sigma .* h2), ||V[j+1]||, Givens   (update, norm, rotations)
+// One Arnoldi step j with delayed reorthogonalisation (FP64 basis V, leading
+// dimension ldv).  On entry V[0..j-1] are orthonormal and V[j] holds u_j, the
+// once-orthogonalised candidate; z = M(sigma_j u_j).  The step computes
+// w = A z and, with one reduction and two passes over the basis, normalises
+// v_j = (u_j - V a)/nu (a = V^T u_j), writes the candidate u_{j+1} =
+// w - V b - h_jj v_j into V[j+1], completes Hessenberg column j-1, its Givens
+// rotation and the residual estimate (flags for column j-1 at index j), and
+// records column j's first-pass coefficients and sigma_{j+1}.
 // All kernels return immediately once st->cycle_done is set.
 // ev (optional, 2 events): recorded around the kernel selected by prof_class
-// (1: spmv + first dot pass, 2: second Gram-Schmidt pass).
+// (1: product + projection pass, 2: update pass).
 template <typename TM, typename TZ>
 void launch_arnoldi_step(const Sell<TM>& A, const TZ* z, double* W, double* V, int64_t ldv,
                          int j, DevState* st, double* part, HostFlags* hf, hipStream_t s,
                          int prof_class = 0, hipEvent_t* ev = nullptr);
+// Completes column j-1 = m-1 at the end of a full cycle of m = j columns.
+void launch_arnoldi_close(int n, double* V, int64_t ldv, int j, DevState* st, double* part,
+                          HostFlags* hf, hipStream_t s);
 void launch_trisolve(DevState* st, hipStream_t s);
 template <typename TZ>
 void launch_update_x(double* x, const TZ* Z, int64_t ldz, int n, DevState* st,

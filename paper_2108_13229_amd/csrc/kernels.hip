@@ -255,83 +255,114 @@ __global__ __launch_bounds__(kBlock) void k_block_sweep(Sell<T> Cf, int n_p,
     tq[row - n_p] = t;
 }
 
-// ---- Arnoldi step j.  Multi-vector Gram-Schmidt passes use a row-block x
-// vector-per-wavefront layout: a workgroup of 16 wavefronts owns a block of
-// rows; wavefront w handles basis vectors w, w+16, w+32, w+48 over those rows
-// (one accumulator per vector and lane), so every basis entry is read once,
-// coalesced, with few registers.  Row sums across vectors (the axpy) go
-// through LDS.  Passes: (1) w = A z_j with partial dots V^T w; (2) reduce the
-// partials (every workgroup, same fixed order), w -= V c, partial dots;
-// (3) reduce, V[j+1] = w - V c2, partial squared norm; (4) finish: norm,
-// Hessenberg column, Givens rotation, convergence flag.
+// ---- Arnoldi step j: classical Gram-Schmidt with one reorthogonalisation
+// (CGS2), the reorthogonalisation of each vector delayed by one step so that
+// it shares a pass over the basis with the projection of the next vector
+// (delayed CGS2: Swirydowicz, Langou, Ananthan, Yang, Thomas, "Low
+// synchronization Gram-Schmidt and GMRES algorithms", 2021).
+//
+// On entry to step j the basis slots 0..j-1 hold orthonormal v_0..v_{j-1},
+// slot j holds u_j, the once-orthogonalised (unnormalised) candidate for v_j,
+// and the preconditioner has produced z_j = M(sigma_j u_j).  Two kernels:
+//   project: w = A z_j; partial sums of a = V^T u_j, b = V^T w, u_j.u_j,
+//            u_j.w and w.w (one pass over the basis);
+//   update:  every workgroup reduces the partials in the same fixed order;
+//            nu = sqrt(u.u - a.a), v_j = (u_j - V a)/nu, h_jj = (u.w - a.b)/nu,
+//            u_{j+1} = w - V b - h_jj v_j (one pass over the basis).
+//            Workgroup 0 completes Hessenberg column j-1 (first-pass
+//            coefficients + a, subdiagonal nu), applies the Givens rotations
+//            and sets the convergence flag; the residual estimate therefore
+//            trails the basis by one step.
+// In exact arithmetic a = 0 and the iterates are those of CGS2 FGMRES.  A
+// closing step (project without the product, update without row work)
+// completes the last column of a full cycle.  Layout: row-block x
+// vector-per-wavefront; a workgroup of 16 wavefronts owns a block of rows,
+// wavefront w handles basis vectors w, w+16, w+32, w+48 (one accumulator per
+// vector and lane), so every basis entry is read once, coalesced; row sums
+// across vectors go through LDS.
 
 constexpr int kGsThreads = 1024;
 constexpr int kGsWaves = kGsThreads / 64;
 constexpr int kGsVpw = kMaxBasis / kGsWaves;     // basis vectors per wavefront
 constexpr int kGsRound = 256;                     // rows per LDS round (4 per lane)
+constexpr int kSumStride = 2 * kMaxBasis + 4;
 
-// c[k] = sigma_k * h_k, h_k = sigma_k * sum_b part[k][b] (fixed order);
-// workgroup 0 records h in st (hsel 1: h1, 2: h2).
-__device__ __forceinline__ void gs_coefficients(const double* part, int nb, int j, DevState* st,
-                                                int hsel, double* c, double* scratch) {
+// sums[i], i < 2j + 3: a_0..a_{j-1}, b_0..b_{j-1}, u.u, u.w, w.w, each the sum
+// over the nb row blocks in a fixed order (identical in every workgroup).
+__device__ __forceinline__ void arn_sums(const double* part, int nb, int j, double* sums,
+                                         double* scratch) {
+  const int nr = 2 * j + 3;
   const int t = threadIdx.x;
-  const int k = t >> 4, sub = t & 15;             // 64 k x 16 partial sums
-  double s = 0.0;
-  if (k <= j)
-    for (int b = sub; b < nb; b += 16) s += part[(size_t)k * kGsMaxBlocks + b];
-  scratch[sub * kMaxBasis + k] = s;
-  __syncthreads();
-  if (t <= j) {
-    double a = 0.0;
-    for (int q = 0; q < 16; ++q) a += scratch[q * kMaxBasis + t];
-    const double sg = st->sigma[t];
-    const double h = sg * a;
-    c[t] = h * sg;
-    if (blockIdx.x == 0) {
-      if (hsel == 1)
-        st->h1[t] = h;
-      else
-        st->h2[t] = h;
+  for (int i0 = 0; i0 < nr; i0 += kGsThreads / 16) {
+    const int i = i0 + (t >> 4), sub = t & 15;
+    if (i < nr) {
+      const int row = i < j ? kGsRowA + i : (i < 2 * j ? kGsRowB + (i - j) : kGsRowC + (i - 2 * j));
+      const double* p = part + (size_t)row * kGsMaxBlocks;
+      double s = 0.0;
+      for (int b = sub; b < nb; b += 16) s += p[b];
+      scratch[sub * kSumStride + i] = s;
     }
+  }
+  __syncthreads();
+  if (t < nr) {
+    double a = 0.0;
+    for (int q = 0; q < 16; ++q) a += scratch[q * kSumStride + t];
+    sums[t] = a;
   }
   __syncthreads();
 }
 
 template <typename TM, typename TZ>
-__global__ __launch_bounds__(kGsThreads) void k_gs_spmv_dots(Sell<TM> A, const TZ* __restrict__ z,
-                                                             double* __restrict__ W,
-                                                             const double* __restrict__ V,
-                                                             int64_t ldv, int j, int rpb,
-                                                             const DevState* st, double* part) {
+__global__ __launch_bounds__(kGsThreads) void k_arn_project(Sell<TM> A, const TZ* __restrict__ z,
+                                                            double* __restrict__ W,
+                                                            const double* __restrict__ V,
+                                                            int64_t ldv, int n, int j, int rpb,
+                                                            int spmv, const DevState* st,
+                                                            double* part) {
   if (st->cycle_done) return;
-  extern __shared__ double wt[];                  // rpb entries
-  const int n = A.n_rows;
+  extern __shared__ double sh[];                  // w and u_j of the block's rows
+  double* wt = sh;
+  double* ut = sh + rpb;
+  __shared__ double red3[kGsWaves][3];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r0 = blockIdx.x * rpb;
+  const double* uj = V + (size_t)j * ldv;
+  double cuu = 0.0, cuw = 0.0, cww = 0.0;
   for (int sl = wave; sl < rpb / 64; sl += kGsWaves) {
     const int row = r0 + sl * 64 + lane;
-    double w = 0.0;
+    double w = 0.0, u = 0.0;
     if (row < n) {
-      w = (double)sell_dot(A, z, row);
-      W[row] = w;
+      u = uj[row];
+      if (spmv) {
+        w = (double)sell_dot(A, z, row);
+        W[row] = w;
+      }
     }
     wt[sl * 64 + lane] = w;
+    ut[sl * 64 + lane] = u;
+    cuu += u * u;
+    cuw += u * w;
+    cww += w * w;
   }
   __syncthreads();
-  double acc[kGsVpw];
+  double aa[kGsVpw], ab[kGsVpw];
 #pragma unroll
-  for (int q = 0; q < kGsVpw; ++q) acc[q] = 0.0;
+  for (int q = 0; q < kGsVpw; ++q) aa[q] = ab[q] = 0.0;
   for (int base = 0; base < rpb; base += kGsRound) {
 #pragma unroll
-    for (int u = 0; u < kGsRound / 64; ++u) {
-      const int lr = base + u * 64 + lane;
+    for (int u4 = 0; u4 < kGsRound / 64; ++u4) {
+      const int lr = base + u4 * 64 + lane;
       const int row = r0 + lr;
       if (row < n) {
-        const double w = wt[lr];
+        const double w = wt[lr], u = ut[lr];
 #pragma unroll
         for (int q = 0; q < kGsVpw; ++q) {
           const int k = wave + kGsWaves * q;
-          if (k <= j) acc[q] += V[(size_t)k * ldv + row] * w;
+          if (k < j) {
+            const double x = V[(size_t)k * ldv + row];
+            aa[q] += x * u;
+            ab[q] += x * w;
+          }
         }
       }
     }
@@ -339,173 +370,192 @@ __global__ __launch_bounds__(kGsThreads) void k_gs_spmv_dots(Sell<TM> A, const T
 #pragma unroll
   for (int q = 0; q < kGsVpw; ++q) {
     const int k = wave + kGsWaves * q;
-    const double s = wave_sum(acc[q]);
-    if (k <= j && lane == 0) part[(size_t)k * kGsMaxBlocks + blockIdx.x] = s;
-  }
-}
-
-__global__ __launch_bounds__(kGsThreads) void k_gs_pass2(double* __restrict__ W,
-                                                         const double* __restrict__ V,
-                                                         int64_t ldv, int n, int j, int rpb,
-                                                         int nb_in, DevState* st,
-                                                         const double* part_in, double* part) {
-  if (st->cycle_done) return;
-  __shared__ double c[kMaxBasis];
-  __shared__ double red[kGsWaves][kGsRound];
-  __shared__ double wt[kGsRound];
-  gs_coefficients(part_in, nb_in, j, st, 1, c, &red[0][0]);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int r0 = blockIdx.x * rpb;
-  double acc[kGsVpw], cq[kGsVpw];
-#pragma unroll
-  for (int q = 0; q < kGsVpw; ++q) {
-    const int k = wave + kGsWaves * q;
-    acc[q] = 0.0;
-    cq[q] = k <= j ? c[k] : 0.0;
-  }
-  for (int base = 0; base < rpb; base += kGsRound) {
-    double v[kGsVpw][kGsRound / 64];
-#pragma unroll
-    for (int u = 0; u < kGsRound / 64; ++u) {
-      const int row = r0 + base + u * 64 + lane;
-      double ps = 0.0;
-#pragma unroll
-      for (int q = 0; q < kGsVpw; ++q) {
-        const int k = wave + kGsWaves * q;
-        v[q][u] = (k <= j && row < n) ? V[(size_t)k * ldv + row] : 0.0;
-        ps += cq[q] * v[q][u];
-      }
-      red[wave][u * 64 + lane] = ps;
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < kGsRound) {
-      const int row = r0 + base + threadIdx.x;
-      double s = 0.0;
-#pragma unroll
-      for (int w = 0; w < kGsWaves; ++w) s += red[w][threadIdx.x];
-      double wv = 0.0;
-      if (row < n) {
-        wv = W[row] - s;
-        W[row] = wv;
-      }
-      wt[threadIdx.x] = wv;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < kGsRound / 64; ++u) {
-      const double wv = wt[u * 64 + lane];
-#pragma unroll
-      for (int q = 0; q < kGsVpw; ++q) acc[q] += v[q][u] * wv;
+    const double sa = wave_sum(aa[q]);
+    const double sb = wave_sum(ab[q]);
+    if (k < j && lane == 0) {
+      part[(size_t)(kGsRowA + k) * kGsMaxBlocks + blockIdx.x] = sa;
+      part[(size_t)(kGsRowB + k) * kGsMaxBlocks + blockIdx.x] = sb;
     }
   }
-#pragma unroll
-  for (int q = 0; q < kGsVpw; ++q) {
-    const int k = wave + kGsWaves * q;
-    const double s = wave_sum(acc[q]);
-    if (k <= j && lane == 0) part[(size_t)k * kGsMaxBlocks + blockIdx.x] = s;
-  }
-}
-
-__global__ __launch_bounds__(kGsThreads) void k_gs_pass3(const double* __restrict__ W,
-                                                         double* __restrict__ V, int64_t ldv,
-                                                         int n, int j, int rpb, int nb_in,
-                                                         DevState* st, const double* part_in,
-                                                         double* part) {
-  if (st->cycle_done) return;
-  __shared__ double c[kMaxBasis];
-  __shared__ double red[kGsWaves][kGsRound];
-  gs_coefficients(part_in, nb_in, j, st, 2, c, &red[0][0]);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int r0 = blockIdx.x * rpb;
-  double cq[kGsVpw];
-#pragma unroll
-  for (int q = 0; q < kGsVpw; ++q) {
-    const int k = wave + kGsWaves * q;
-    cq[q] = k <= j ? c[k] : 0.0;
-  }
-  double* vn = V + (size_t)(j + 1) * ldv;
-  double nrm = 0.0;
-  for (int base = 0; base < rpb; base += kGsRound) {
-#pragma unroll
-    for (int u = 0; u < kGsRound / 64; ++u) {
-      const int row = r0 + base + u * 64 + lane;
-      double ps = 0.0;
-#pragma unroll
-      for (int q = 0; q < kGsVpw; ++q) {
-        const int k = wave + kGsWaves * q;
-        if (k <= j && row < n) ps += cq[q] * V[(size_t)k * ldv + row];
-      }
-      red[wave][u * 64 + lane] = ps;
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < kGsRound) {
-      const int row = r0 + base + threadIdx.x;
-      double s = 0.0;
-#pragma unroll
-      for (int w = 0; w < kGsWaves; ++w) s += red[w][threadIdx.x];
-      if (row < n) {
-        const double wv = W[row] - s;
-        vn[row] = wv;
-        nrm += wv * wv;
-      }
-    }
-    __syncthreads();
-  }
-  // threads 0..255 (wavefronts 0..3) hold the norm contributions
-  if (wave < kGsRound / 64) {
-    const double s = wave_sum(nrm);
-    if (lane == 0) red[0][wave] = s;
+  cuu = wave_sum(cuu);
+  cuw = wave_sum(cuw);
+  cww = wave_sum(cww);
+  if (lane == 0) {
+    red3[wave][0] = cuu;
+    red3[wave][1] = cuw;
+    red3[wave][2] = cww;
   }
   __syncthreads();
-  if (threadIdx.x == 0)
-    part[blockIdx.x] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+  if (threadIdx.x < 3) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kGsWaves; ++w) s += red3[w][threadIdx.x];
+    part[(size_t)(kGsRowC + threadIdx.x) * kGsMaxBlocks + blockIdx.x] = s;
+  }
 }
 
-__global__ __launch_bounds__(kBlock) void k_arn_finish(const double* part, int nb, int j,
-                                                       DevState* st, HostFlags* hf) {
-  if (st->cycle_done) return;
-  __shared__ double red[kBlock / 64];
-  double acc = 0.0;
-  for (int b = threadIdx.x; b < nb; b += kBlock) acc += part[b];
-  acc = wave_sum(acc);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  const double nrm2 = ((red[0] + red[1]) + red[2]) + red[3];
+// Workgroup 0 of the update kernel: complete column jc = j - 1 (if any),
+// rotate it, update g and the flags; record column j's first-pass
+// coefficients and the input scale of the next preconditioner application.
+__device__ void arn_column(int j, int update, const double* sums, const double* sc,
+                           DevState* st, HostFlags* hf, double* hc, double* rot) {
+  const int t = threadIdx.x;
   const int ld = kMaxBasis + 1;
-  double* H = st->H + (size_t)j * ld;
-  const double hn = sqrt(nrm2);
-  for (int i = 0; i <= j; ++i) H[i] = st->h1[i] + st->h2[i];
-  H[j + 1] = hn;
-  for (int i = 0; i < j; ++i) {
-    const double t = st->cs[i] * H[i] + st->sn[i] * H[i + 1];
-    H[i + 1] = -st->sn[i] * H[i] + st->cs[i] * H[i + 1];
-    H[i] = t;
+  const int jc = j - 1;
+  if (j >= 1) {
+    if (t < j) hc[t] = st->h1[t] + sums[t];
+    if (t < jc) {
+      rot[t] = st->cs[t];
+      rot[kMaxBasis + t] = st->sn[t];
+    }
   }
-  const double d = hypot(H[j], H[j + 1]);
-  int bad = !(d > 0.0) || !isfinite(d);
-  const double cj = bad ? 1.0 : H[j] / d;
-  const double sj = bad ? 0.0 : H[j + 1] / d;
-  st->cs[j] = cj;
-  st->sn[j] = sj;
-  H[j] = bad ? H[j] : d;
-  H[j + 1] = 0.0;
-  st->g[j + 1] = -sj * st->g[j];
-  st->g[j] = cj * st->g[j];
-  const double est = fabs(st->g[j + 1]);
-  bad = bad || !isfinite(est);
-  st->sigma[j + 1] = 1.0 / hn;
-  st->k = j + 1;
-  st->j = j + 1;
-  st->iters += 1;
-  if (bad) st->breakdown = 1;
-  const int done = bad || !(hn > 0.0) || est <= st->cycle_target || (j + 1) >= st->m;
-  st->cycle_done = done;
-  if (hf) {
-    hf->est[j] = est;
-    hf->cycle_done[j] = done;
-    __threadfence_system();
+  __syncthreads();
+  if (t == 0) {
+    int done = 0;
+    if (j >= 1) {
+      const double nu = sc[2];
+      hc[j] = nu;
+      for (int i = 0; i < jc; ++i) {
+        const double c = rot[i], s = rot[kMaxBasis + i];
+        const double x = c * hc[i] + s * hc[i + 1];
+        hc[i + 1] = -s * hc[i] + c * hc[i + 1];
+        hc[i] = x;
+      }
+      const double d = hypot(hc[jc], hc[j]);
+      int bad = !(d > 0.0) || !isfinite(d) || !isfinite(nu);
+      const double cj = bad ? 1.0 : hc[jc] / d;
+      const double sj = bad ? 0.0 : hc[j] / d;
+      st->cs[jc] = cj;
+      st->sn[jc] = sj;
+      hc[jc] = bad ? hc[jc] : d;
+      hc[j] = 0.0;
+      const double gj = st->g[jc];
+      st->g[j] = -sj * gj;
+      st->g[jc] = cj * gj;
+      const double est = fabs(sj * gj);
+      bad = bad || !isfinite(est);
+      st->k = j;
+      st->iters += 1;
+      if (bad) st->breakdown = 1;
+      done = bad || !(nu > 0.0) || est <= st->cycle_target || j >= st->m || !update;
+      st->cycle_done = done;
+      if (hf) {
+        hf->est[j] = est;
+        hf->cycle_done[j] = done;
+      }
+    } else if (hf) {
+      hf->est[0] = st->g[0];
+      hf->cycle_done[0] = 0;
+    }
+    if (update && !done) {
+      st->h1[j] = sc[3];
+      st->sigma[j + 1] = sc[4];
+    }
+    st->j = j + 1;
+    if (hf) __threadfence_system();
   }
+  __syncthreads();
+  if (j >= 1 && t <= j) st->H[(size_t)jc * ld + t] = hc[t];
+  if (update && t < j) st->h1[t] = sums[j + t];
+}
+
+// Row work of the update kernel: v_j = inv u_j - V (inv a), u_{j+1} =
+// w - V (b - t a) - t u_j over this workgroup's block of rows.
+__device__ __forceinline__ void arn_rows(const double* __restrict__ W, double* __restrict__ V,
+                                         int64_t ldv, int n, int j, int rpb, const double* sums,
+                                         const double* sc, double* cf,
+                                         double (&red)[2][kGsWaves][kGsRound]) {
+  const int t = threadIdx.x;
+  if (t < j) {
+    cf[t] = sc[0] * sums[t];
+    cf[kMaxBasis + t] = sums[j + t] - sc[1] * sums[t];
+  }
+  __syncthreads();
+  const int wave = t >> 6, lane = t & 63;
+  const int r0 = blockIdx.x * rpb;
+  double ca[kGsVpw], cb[kGsVpw];
+#pragma unroll
+  for (int q = 0; q < kGsVpw; ++q) {
+    const int k = wave + kGsWaves * q;
+    ca[q] = k < j ? cf[k] : 0.0;
+    cb[q] = k < j ? cf[kMaxBasis + k] : 0.0;
+  }
+  const double inv = sc[0], tt = sc[1];
+  double* uj = V + (size_t)j * ldv;
+  double* un = V + (size_t)(j + 1) * ldv;
+  for (int base = 0; base < rpb; base += kGsRound) {
+#pragma unroll
+    for (int u4 = 0; u4 < kGsRound / 64; ++u4) {
+      const int row = r0 + base + u4 * 64 + lane;
+      double p1 = 0.0, p2 = 0.0;
+#pragma unroll
+      for (int q = 0; q < kGsVpw; ++q) {
+        const int k = wave + kGsWaves * q;
+        if (k < j && row < n) {
+          const double x = V[(size_t)k * ldv + row];
+          p1 += ca[q] * x;
+          p2 += cb[q] * x;
+        }
+      }
+      red[0][wave][u4 * 64 + lane] = p1;
+      red[1][wave][u4 * 64 + lane] = p2;
+    }
+    __syncthreads();
+    if (t < kGsRound) {
+      const int row = r0 + base + t;
+      double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+      for (int w = 0; w < kGsWaves; ++w) {
+        s1 += red[0][w][t];
+        s2 += red[1][w][t];
+      }
+      if (row < n) {
+        const double u = uj[row];
+        uj[row] = inv * u - s1;
+        un[row] = W[row] - s2 - tt * u;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kGsThreads) void k_arn_update(const double* __restrict__ W,
+                                                           double* __restrict__ V, int64_t ldv,
+                                                           int n, int j, int rpb, int nb,
+                                                           int update, DevState* st,
+                                                           const double* part, HostFlags* hf) {
+  if (st->cycle_done) return;
+  __shared__ double red[2][kGsWaves][kGsRound];
+  __shared__ double sums[kSumStride];
+  __shared__ double cf[2 * kMaxBasis];
+  __shared__ double sc[8];
+  arn_sums(part, nb, j, sums, &red[0][0][0]);
+  const int t = threadIdx.x;
+  if (t == 0) {
+    double aa = 0.0, ab = 0.0, bb = 0.0;
+    for (int k = 0; k < j; ++k) {
+      aa += sums[k] * sums[k];
+      ab += sums[k] * sums[j + k];
+      bb += sums[j + k] * sums[j + k];
+    }
+    const double uu = sums[2 * j], uw = sums[2 * j + 1], ww = sums[2 * j + 2];
+    const double nu2 = uu - aa;
+    const double nu = nu2 > 0.0 ? sqrt(nu2) : 0.0;
+    const double inv = nu > 0.0 ? 1.0 / nu : 0.0;
+    const double hjj = (uw - ab) * inv;
+    const double rest = ww - bb - hjj * hjj;
+    const double floor = 1e-16 * ww;
+    sc[0] = inv;
+    sc[1] = hjj * inv;
+    sc[2] = nu;
+    sc[3] = hjj;
+    sc[4] = ww > 0.0 ? 1.0 / sqrt(rest > floor ? rest : floor) : 1.0;
+  }
+  __syncthreads();
+  // the last workgroup completes the Hessenberg column after its rows
+  if (update) arn_rows(W, V, ldv, n, j, rpb, sums, sc, cf, red);
+  if (blockIdx.x == gridDim.x - 1)
+    arn_column(j, update, sums, sc, st, hf, &red[0][0][0], &red[1][0][0]);
 }
 
 __global__ void k_trisolve(DevState* st) {
@@ -910,17 +960,22 @@ void launch_arnoldi_step(const Sell<TM>& A, const TZ* z, double* W, double* V, i
   const int n = A.n_rows;
   const int rpb = gs_rows_per_block(n);
   const int nb = (n + rpb - 1) / rpb;
-  double* p1 = part;
-  double* p2 = part + (size_t)(kMaxBasis + 1) * kGsMaxBlocks;
   if (ev && prof_class == 1) (void)hipEventRecord(ev[0], s);
-  k_gs_spmv_dots<TM, TZ><<<nb, kGsThreads, (size_t)rpb * sizeof(double), s>>>(A, z, W, V, ldv, j,
-                                                                            rpb, st, p1);
+  k_arn_project<TM, TZ><<<nb, kGsThreads, (size_t)2 * rpb * sizeof(double), s>>>(
+      A, z, W, V, ldv, n, j, rpb, 1, st, part);
   if (ev && prof_class == 1) (void)hipEventRecord(ev[1], s);
   if (ev && prof_class == 2) (void)hipEventRecord(ev[0], s);
-  k_gs_pass2<<<nb, kGsThreads, 0, s>>>(W, V, ldv, n, j, rpb, nb, st, p1, p2);
+  k_arn_update<<<nb, kGsThreads, 0, s>>>(W, V, ldv, n, j, rpb, nb, 1, st, part, hf);
   if (ev && prof_class == 2) (void)hipEventRecord(ev[1], s);
-  k_gs_pass3<<<nb, kGsThreads, 0, s>>>(W, V, ldv, n, j, rpb, nb, st, p2, p1);
-  k_arn_finish<<<1, kBlock, 0, s>>>(p1, nb, j, st, hf);
+}
+
+void launch_arnoldi_close(int n, double* V, int64_t ldv, int j, DevState* st, double* part,
+                          HostFlags* hf, hipStream_t s) {
+  const int rpb = gs_rows_per_block(n);
+  const int nb = (n + rpb - 1) / rpb;
+  k_arn_project<double, double><<<nb, kGsThreads, (size_t)2 * rpb * sizeof(double), s>>>(
+      Sell<double>{}, nullptr, nullptr, V, ldv, n, j, rpb, 0, st, part);
+  k_arn_update<<<1, kGsThreads, 0, s>>>(nullptr, V, ldv, n, j, rpb, nb, 0, st, part, hf);
 }
 
 void launch_trisolve(DevState* st, hipStream_t s) { k_trisolve<<<1, 64, 0, s>>>(st); }

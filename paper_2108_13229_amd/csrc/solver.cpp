@@ -219,7 +219,7 @@ void Solver::upload(const sd_allocator* alloc, hipStream_t s) {
   const int m = opts.o.restart;
   V = mem->array<double>((size_t)(m + 1) * ldv);
   W = mem->array<double>((size_t)ldv);
-  part = mem->array<double>(std::max((size_t)2 * (kMaxBasis + 1) * kGsMaxBlocks,
+  part = mem->array<double>(std::max((size_t)kGsPartRows * kGsMaxBlocks,
                                      (size_t)kDotBlocks * kPartStride));
   st = static_cast<DevState*>(mem->get(sizeof(DevState)));
   SD_HIP(hipMemsetAsync(st, 0, sizeof(DevState), s));
@@ -517,6 +517,8 @@ class PrecImpl : public PrecBase {
         bool done = false;
         for (int q = 0; q <= R.completed; ++q) done = done || S.hf->cycle_done[q];
         if (done || R.j_enq == R.m_cycle) {
+          // a full cycle's last column is completed by the closing step
+          if (!done) launch_arnoldi_close(n, S.V, S.ldv, R.j_enq, S.st, S.part, S.hf_dev, s);
           launch_trisolve(S.st, s);
           launch_update_x<T>(R.x, Z, ldz, n, S.st, s);
           ++R.restarts;
@@ -624,8 +626,8 @@ class PrecImpl : public PrecBase {
       S.prof_launches += 1;
       if (S.prof_class == 1)  // A (values + indices), z, w, j+1 basis vectors
         S.prof_bytes += (double)S.nnz_A * (tz + 4.0) + n * (tz + 8.0) + (j + 1) * 8.0 * n;
-      else if (S.prof_class == 2)  // j+1 basis vectors, w read and written
-        S.prof_bytes += (j + 1) * 8.0 * n + 16.0 * n;
+      else if (S.prof_class == 2)  // j basis vectors, u_j and w read; v_j, u_{j+1} written
+        S.prof_bytes += (j + 4) * 8.0 * n;
       else {  // V level 0: A_V (values + indices), x_in, b, w, x_out
         const double nv = (double)S.off[2];
         S.prof_bytes += (double)S.nnz_V0 * (tz + 4.0) + nv * (3.0 * tz + 8.0);

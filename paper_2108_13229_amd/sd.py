@@ -330,7 +330,7 @@ class Solver:
                                      C.c_void_p(x.data_ptr()), _stream()))
         return x
 
-    PROFILE = {"off": 0, "arnoldi_spmv": 1, "gs_pass2": 2, "jacobi_v0": 3}
+    PROFILE = {"off": 0, "arnoldi_spmv": 1, "arnoldi_update": 2, "jacobi_v0": 3}
 
     def profile(self, kernel_class: str):
         _check(lib().sd_solver_profile(self.h, self.PROFILE[kernel_class]))
