@@ -371,6 +371,28 @@ void dense_inverse(std::vector<double>& M, int64_t n, std::vector<double>& inv) 
 
 }  // namespace
 
+HostCSR residual_restriction(const HostCSR& A, const HostCSR& R) {
+  const HostCSR RA = spgemm(R, A);
+  HostCSR Q;
+  Q.n_rows = R.n_rows;
+  Q.n_cols = 2 * A.n_cols;
+  Q.rowptr.assign(1, 0);
+  Q.col.reserve((size_t)(R.nnz() + RA.nnz()));
+  Q.val.reserve((size_t)(R.nnz() + RA.nnz()));
+  for (int64_t i = 0; i < R.n_rows; ++i) {
+    for (int64_t k = R.rowptr[i]; k < R.rowptr[i + 1]; ++k) {
+      Q.col.push_back(R.col[k]);
+      Q.val.push_back(R.val[k]);
+    }
+    for (int64_t k = RA.rowptr[i]; k < RA.rowptr[i + 1]; ++k) {
+      Q.col.push_back((int32_t)(A.n_cols + RA.col[k]));
+      Q.val.push_back(-RA.val[k]);
+    }
+    Q.rowptr.push_back((int64_t)Q.col.size());
+  }
+  return Q;
+}
+
 void amg_setup_host(const HostCSR& A0, const std::vector<int32_t>& comp0, bool singular,
                     const AMGOpts& o, HostHierarchy& h) {
   if (o.mis != 1 && o.mis != 2) throw Error(SD_E_INVALID, "AMG: mis must be 1 or 2");

@@ -29,6 +29,8 @@ struct Sell {
   int n_rows = 0;
   int n_cols = 0;
   int lpr = 1;
+  int width = 0;   // > 0: every row padded to this width (SELL: slice s at
+                   // 64 * width * s; CSR: row r at width * r), sptr not read
 };
 
 // Solver scalars resident in device memory.
@@ -74,6 +76,11 @@ void launch_jacobi_zero(const Sell<T>& A, const T* wd, const TB* b, const double
 template <typename T, typename TB>
 void launch_jacobi(const Sell<T>& A, const T* wd, const TB* b, const double* bscale,
                    const T* x_in, T* x_out, const DevState* gate, hipStream_t s);
+// bc = Q [bscale b; x] with Q = [R | -R A] (n_fine = length of b and x):
+// the restricted residual R (bscale b - A x) in one pass
+template <typename T, typename TB>
+void launch_restrict_residual(const Sell<T>& Q, const TB* b, const double* bscale, const T* x,
+                              int n_fine, T* bc, const DevState* gate, hipStream_t s);
 // x += P xc
 template <typename T>
 void launch_prolong(const Sell<T>& P, const T* xc, T* x, const DevState* gate,

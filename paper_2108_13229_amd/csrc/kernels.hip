@@ -117,23 +117,49 @@ inline int dot_blocks(int n) {
 // row and a shuffle reduction; used on coarse levels, whose smoothed-
 // aggregation rows are long and few, where one lane per row leaves the chip
 // idle and serialises the gathers.  f(c) supplies the multiplied vector entry.
+// A uniform row width (A.width > 0) spares the pointer load at the head of
+// each row's dependent load chain.
 template <int LPR, typename TM, typename F>
 __device__ __forceinline__ TM row_sum(const Sell<TM>& A, int row, int sub, F f) {
   TM acc = 0;
   if constexpr (LPR == 1) {
-    const int s = row >> 6;
-    const int beg = A.sptr[s] + (row & 63);
-    const int end = A.sptr[s + 1];
+    int beg, end;
+    if (A.width) {
+      beg = (row >> 6) * (64 * A.width) + (row & 63);
+      end = beg + 64 * A.width;
+    } else {
+      const int s = row >> 6;
+      beg = A.sptr[s] + (row & 63);
+      end = A.sptr[s + 1];
+    }
 #pragma unroll 4
     for (int e = beg; e < end; e += 64) acc += A.val[e] * f(A.col[e]);
   } else {
-    const int end = A.sptr[row + 1];
+    int beg, end;
+    if (A.width) {
+      beg = row * A.width + sub;
+      end = (row + 1) * A.width;
+    } else {
+      beg = A.sptr[row] + sub;
+      end = A.sptr[row + 1];
+    }
 #pragma unroll 2
-    for (int e = A.sptr[row] + sub; e < end; e += LPR) acc += A.val[e] * f(A.col[e]);
+    for (int e = beg; e < end; e += LPR) acc += A.val[e] * f(A.col[e]);
 #pragma unroll
     for (int o = LPR / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LPR);
   }
   return acc;
+}
+
+// The cycle-done flag of the gated kernels, read with a vector load through
+// an opaque pointer so that it is in flight together with the kernel's first
+// loads (a scalar load would be waited for before them); the kernels test it
+// just before their stores.
+__device__ __forceinline__ int gate_flag(const DevState* gate) {
+  if (!gate) return 0;
+  const int* p = &gate->cycle_done;
+  asm volatile("" : "+v"(p));
+  return *p;
 }
 
 // thread -> (row, lane within the row group), XCD-contiguous row ranges
@@ -146,11 +172,11 @@ __device__ __forceinline__ int2 row_of_thread() {
 template <int LPR, typename TM, typename TX, typename TY>
 __global__ __launch_bounds__(kBlock) void k_spmv(Sell<TM> A, const TX* __restrict__ x,
                                                  TY* __restrict__ y, const DevState* gate) {
-  if (gate && gate->cycle_done) return;
   const int2 rs = row_of_thread<LPR>();
   if (rs.x >= A.n_rows) return;
+  const int stop = gate_flag(gate);
   const TM v = row_sum<LPR>(A, rs.x, rs.y, [&](int c) { return (TM)x[c]; });
-  if (rs.y == 0) y[rs.x] = (TY)v;
+  if (rs.y == 0 && !stop) y[rs.x] = (TY)v;
 }
 
 template <int LPR, typename T, typename TB>
@@ -158,34 +184,52 @@ __global__ __launch_bounds__(kBlock) void k_residual(Sell<T> A, const TB* __rest
                                                      const double* bscale,
                                                      const T* __restrict__ x,
                                                      T* __restrict__ r, const DevState* gate) {
-  if (gate && gate->cycle_done) return;
   const int2 rs = row_of_thread<LPR>();
   if (rs.x >= A.n_rows) return;
+  const int stop = gate_flag(gate);
   const T ax = row_sum<LPR>(A, rs.x, rs.y, [&](int c) { return x[c]; });
-  if (rs.y == 0) r[rs.x] = load_b<T>(b, scale_of(bscale), rs.x) - ax;
+  if (rs.y == 0 && !stop) r[rs.x] = load_b<T>(b, scale_of(bscale), rs.x) - ax;
 }
 
 // x = w .* b (one sweep from zero) or two sweeps from zero fused: the first
 // sweep's values x1 = w .* b are recomputed at the neighbours.
+// bc = Q [bscale b; x] = R (bscale b - A x): residual and restriction in one
+// product over the coarse rows (columns >= n_fine address x).
+template <int LPR, typename T, typename TB>
+__global__ __launch_bounds__(kBlock) void k_restrict_residual(Sell<T> Q, const TB* __restrict__ b,
+                                                              const double* bscale,
+                                                              const T* __restrict__ x,
+                                                              int n_fine, T* __restrict__ bc,
+                                                              const DevState* gate) {
+  const int2 rs = row_of_thread<LPR>();
+  if (rs.x >= Q.n_rows) return;
+  const int stop = gate_flag(gate);
+  const double sc = scale_of(bscale);
+  const T v = row_sum<LPR>(Q, rs.x, rs.y, [&](int c) {
+    return c < n_fine ? load_b<T>(b, sc, c) : x[c - n_fine];
+  });
+  if (rs.y == 0 && !stop) bc[rs.x] = v;
+}
+
 template <int LPR, typename T, typename TB>
 __global__ __launch_bounds__(kBlock) void k_jacobi_zero(Sell<T> A, const T* __restrict__ wd,
                                                         const TB* __restrict__ b,
                                                         const double* bscale,
                                                         T* __restrict__ x, int two,
                                                         const DevState* gate) {
-  if (gate && gate->cycle_done) return;
   const int2 rs = row_of_thread<LPR>();
   const int row = rs.x;
   if (row >= A.n_rows) return;
+  const int stop = gate_flag(gate);
   const double s = scale_of(bscale);
   const T bi = load_b<T>(b, s, row);
   const T x1 = wd[row] * bi;
   if (!two) {
-    if (rs.y == 0) x[row] = x1;
+    if (rs.y == 0 && !stop) x[row] = x1;
     return;
   }
   const T acc = row_sum<LPR>(A, row, rs.y, [&](int c) { return wd[c] * load_b<T>(b, s, c); });
-  if (rs.y == 0) x[row] = x1 + wd[row] * (bi - acc);
+  if (rs.y == 0 && !stop) x[row] = x1 + wd[row] * (bi - acc);
 }
 
 template <int LPR, typename T, typename TB>
@@ -195,47 +239,46 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(Sell<T> A, const T* __restric
                                                    const T* __restrict__ xin,
                                                    T* __restrict__ xout,
                                                    const DevState* gate) {
-  if (gate && gate->cycle_done) return;
   const int2 rs = row_of_thread<LPR>();
   const int row = rs.x;
   if (row >= A.n_rows) return;
+  const int stop = gate_flag(gate);
   const T ax = row_sum<LPR>(A, row, rs.y, [&](int c) { return xin[c]; });
-  if (rs.y == 0)
+  if (rs.y == 0 && !stop)
     xout[row] = xin[row] + wd[row] * (load_b<T>(b, scale_of(bscale), row) - ax);
 }
 
 template <int LPR, typename T>
 __global__ __launch_bounds__(kBlock) void k_prolong(Sell<T> P, const T* __restrict__ xc,
                                                     T* __restrict__ x, const DevState* gate) {
-  if (gate && gate->cycle_done) return;
   const int2 rs = row_of_thread<LPR>();
   if (rs.x >= P.n_rows) return;
+  const int stop = gate_flag(gate);
   const T v = row_sum<LPR>(P, rs.x, rs.y, [&](int c) { return xc[c]; });
-  if (rs.y == 0) x[rs.x] += v;
+  if (rs.y == 0 && !stop) x[rs.x] += v;
 }
 
-// xc = Ainv bc, FP64 dense inverse, one wavefront per row with four
-// independent partial sums per lane.
+// xc = Ainv bc, FP64 dense inverse: one workgroup per row (the coarse rows
+// are few), each thread with up to eight loads in flight.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_coarse(const double* __restrict__ Ainv, int n,
                                                    const T* __restrict__ bc,
                                                    T* __restrict__ xc, const DevState* gate) {
-  if (gate && gate->cycle_done) return;
-  const int w = (blockIdx.x * kBlock + threadIdx.x) >> 6;
-  const int lane = threadIdx.x & 63;
-  if (w >= n) return;
-  const double* a = Ainv + (size_t)w * n;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int c = lane;
-  for (; c + 192 < n; c += 256) {
-    s0 += a[c] * (double)bc[c];
-    s1 += a[c + 64] * (double)bc[c + 64];
-    s2 += a[c + 128] * (double)bc[c + 128];
-    s3 += a[c + 192] * (double)bc[c + 192];
+  __shared__ double red[kBlock / 64];
+  const int stop = gate_flag(gate);
+  const double* a = Ainv + (size_t)blockIdx.x * n;
+  double sp[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int c0 = threadIdx.x; c0 < n; c0 += 8 * kBlock) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int c = c0 + u * kBlock;
+      if (c < n) sp[u & 3] += a[c] * (double)bc[c];
+    }
   }
-  for (; c < n; c += 64) s0 += a[c] * (double)bc[c];
-  const double acc = wave_sum((s0 + s1) + (s2 + s3));
-  if (lane == 0) xc[w] = (T)acc;
+  const double v = wave_sum((sp[0] + sp[1]) + (sp[2] + sp[3]));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0 && !stop) xc[blockIdx.x] = (T)(((red[0] + red[1]) + red[2]) + red[3]);
 }
 
 template <typename T>
@@ -245,10 +288,11 @@ __global__ __launch_bounds__(kBlock) void k_block_sweep(Sell<T> Cf, int n_p,
                                                         const T* __restrict__ yv, double xscale,
                                                         T* __restrict__ zp, T* __restrict__ tq,
                                                         const DevState* gate) {
-  if (gate && gate->cycle_done) return;
   const int row = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (row >= Cf.n_rows) return;
+  const int stop = gate_flag(gate);
   const T t = load_b<T>(r, scale_of(bscale), row) - sell_dot(Cf, yv, row);
+  if (stop) return;
   if (row < n_p)
     zp[row] = (T)xscale * t;
   else
@@ -312,6 +356,30 @@ __device__ __forceinline__ void arn_sums(const double* part, int nb, int j, doub
   __syncthreads();
 }
 
+// Rows ra and rb (slices of equal or different width) of a SELL-64 matrix
+// in one loop: two independent load chains per lane.
+template <typename TM, typename TX>
+__device__ __forceinline__ void sell_dot2(const Sell<TM>& A, const TX* __restrict__ x, int ra,
+                                          int rb, bool hb, TM& out_a, TM& out_b) {
+  int ea = A.sptr[ra >> 6] + (ra & 63);
+  const int enda = A.sptr[(ra >> 6) + 1];
+  int eb = 0, endb = 0;
+  if (hb) {
+    eb = A.sptr[rb >> 6] + (rb & 63);
+    endb = A.sptr[(rb >> 6) + 1];
+  }
+  TM aa = 0, ab = 0;
+#pragma unroll 2
+  for (; ea < enda && eb < endb; ea += 64, eb += 64) {
+    aa += A.val[ea] * (TM)x[A.col[ea]];
+    ab += A.val[eb] * (TM)x[A.col[eb]];
+  }
+  for (; ea < enda; ea += 64) aa += A.val[ea] * (TM)x[A.col[ea]];
+  for (; eb < endb; eb += 64) ab += A.val[eb] * (TM)x[A.col[eb]];
+  out_a = aa;
+  out_b = ab;
+}
+
 template <typename TM, typename TZ>
 __global__ __launch_bounds__(kGsThreads) void k_arn_project(Sell<TM> A, const TZ* __restrict__ z,
                                                             double* __restrict__ W,
@@ -324,57 +392,108 @@ __global__ __launch_bounds__(kGsThreads) void k_arn_project(Sell<TM> A, const TZ
   double* wt = sh;
   double* ut = sh + rpb;
   __shared__ double red3[kGsWaves][3];
+  __shared__ double red2[kGsWaves][2];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r0 = blockIdx.x * rpb;
+  const int ns = rpb / 64;                        // slices of the block (multiple of 32)
   const double* uj = V + (size_t)j * ldv;
   double cuu = 0.0, cuw = 0.0, cww = 0.0;
-  for (int sl = wave; sl < rpb / 64; sl += kGsWaves) {
-    const int row = r0 + sl * 64 + lane;
-    double w = 0.0, u = 0.0;
-    if (row < n) {
-      u = uj[row];
+  for (int sl = wave; sl < ns; sl += 2 * kGsWaves) {
+    const int la = sl * 64 + lane, lb = la + kGsWaves * 64;
+    const int ra = r0 + la, rb = r0 + lb;
+    double wa = 0.0, wb = 0.0, ua = 0.0, ub = 0.0;
+    if (ra < n) {
+      ua = uj[ra];
+      if (rb < n) ub = uj[rb];
       if (spmv) {
-        w = (double)sell_dot(A, z, row);
-        W[row] = w;
+        TM sa, sb;
+        sell_dot2(A, z, ra, rb, rb < n, sa, sb);
+        wa = (double)sa;
+        W[ra] = wa;
+        if (rb < n) {
+          wb = (double)sb;
+          W[rb] = wb;
+        }
       }
     }
-    wt[sl * 64 + lane] = w;
-    ut[sl * 64 + lane] = u;
-    cuu += u * u;
-    cuw += u * w;
-    cww += w * w;
+    wt[la] = wa;
+    wt[lb] = wb;
+    ut[la] = ua;
+    ut[lb] = ub;
+    cuu += ua * ua + ub * ub;
+    cuw += ua * wa + ub * wb;
+    cww += wa * wa + wb * wb;
   }
   __syncthreads();
-  double aa[kGsVpw], ab[kGsVpw];
+  if (j >= kGsWaves) {
+    // wavefront w: basis vectors w, w+16, w+32, w+48 over all rows of the block
+    double aa[kGsVpw], ab[kGsVpw];
 #pragma unroll
-  for (int q = 0; q < kGsVpw; ++q) aa[q] = ab[q] = 0.0;
-  for (int base = 0; base < rpb; base += kGsRound) {
+    for (int q = 0; q < kGsVpw; ++q) aa[q] = ab[q] = 0.0;
+    for (int base = 0; base < rpb; base += kGsRound) {
 #pragma unroll
-    for (int u4 = 0; u4 < kGsRound / 64; ++u4) {
-      const int lr = base + u4 * 64 + lane;
-      const int row = r0 + lr;
-      if (row < n) {
-        const double w = wt[lr], u = ut[lr];
+      for (int u4 = 0; u4 < kGsRound / 64; ++u4) {
+        const int lr = base + u4 * 64 + lane;
+        const int row = r0 + lr;
+        if (row < n) {
+          const double w = wt[lr], u = ut[lr];
 #pragma unroll
-        for (int q = 0; q < kGsVpw; ++q) {
-          const int k = wave + kGsWaves * q;
-          if (k < j) {
-            const double x = V[(size_t)k * ldv + row];
-            aa[q] += x * u;
-            ab[q] += x * w;
+          for (int q = 0; q < kGsVpw; ++q) {
+            const int k = wave + kGsWaves * q;
+            if (k < j) {
+              const double x = V[(size_t)k * ldv + row];
+              aa[q] += x * u;
+              ab[q] += x * w;
+            }
           }
         }
       }
     }
-  }
 #pragma unroll
-  for (int q = 0; q < kGsVpw; ++q) {
-    const int k = wave + kGsWaves * q;
-    const double sa = wave_sum(aa[q]);
-    const double sb = wave_sum(ab[q]);
-    if (k < j && lane == 0) {
-      part[(size_t)(kGsRowA + k) * kGsMaxBlocks + blockIdx.x] = sa;
-      part[(size_t)(kGsRowB + k) * kGsMaxBlocks + blockIdx.x] = sb;
+    for (int q = 0; q < kGsVpw; ++q) {
+      const int k = wave + kGsWaves * q;
+      const double sa = wave_sum(aa[q]);
+      const double sb = wave_sum(ab[q]);
+      if (k < j && lane == 0) {
+        part[(size_t)(kGsRowA + k) * kGsMaxBlocks + blockIdx.x] = sa;
+        part[(size_t)(kGsRowB + k) * kGsMaxBlocks + blockIdx.x] = sb;
+      }
+    }
+  } else if (j > 0) {
+    // fewer vectors than wavefronts: g wavefronts per vector, each over every
+    // g-th slice; their sums are added in a fixed order
+    const int g = kGsWaves / j;
+    const int k = wave / g, p = wave - k * g;
+    double sa = 0.0, sb = 0.0;
+    if (k < j) {
+      const double* vk = V + (size_t)k * ldv;
+#pragma unroll 4
+      for (int sl = p; sl < ns; sl += g) {
+        const int lr = sl * 64 + lane;
+        const int row = r0 + lr;
+        if (row < n) {
+          const double x = vk[row];
+          sa += x * ut[lr];
+          sb += x * wt[lr];
+        }
+      }
+    }
+    sa = wave_sum(sa);
+    sb = wave_sum(sb);
+    if (lane == 0) {
+      red2[wave][0] = sa;
+      red2[wave][1] = sb;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < j) {
+      const int kk = threadIdx.x;
+      double ta = 0.0, tb = 0.0;
+      for (int q = 0; q < g; ++q) {
+        ta += red2[kk * g + q][0];
+        tb += red2[kk * g + q][1];
+      }
+      part[(size_t)(kGsRowA + kk) * kGsMaxBlocks + blockIdx.x] = ta;
+      part[(size_t)(kGsRowB + kk) * kGsMaxBlocks + blockIdx.x] = tb;
     }
   }
   cuu = wave_sum(cuu);
@@ -460,62 +579,46 @@ __device__ void arn_column(int j, int update, const double* sums, const double* 
 }
 
 // Row work of the update kernel: v_j = inv u_j - V (inv a), u_{j+1} =
-// w - V (b - t a) - t u_j over this workgroup's block of rows.
+// w - V (b - t a) - t u_j.  No dot products here, so the layout is one row
+// per lane (two rows per thread in flight), the coefficients broadcast from
+// LDS, and each row's sums run over the basis in ascending order.
 __device__ __forceinline__ void arn_rows(const double* __restrict__ W, double* __restrict__ V,
                                          int64_t ldv, int n, int j, int rpb, const double* sums,
-                                         const double* sc, double* cf,
-                                         double (&red)[2][kGsWaves][kGsRound]) {
+                                         const double* sc, double* cf) {
   const int t = threadIdx.x;
   if (t < j) {
     cf[t] = sc[0] * sums[t];
     cf[kMaxBasis + t] = sums[j + t] - sc[1] * sums[t];
   }
   __syncthreads();
-  const int wave = t >> 6, lane = t & 63;
-  const int r0 = blockIdx.x * rpb;
-  double ca[kGsVpw], cb[kGsVpw];
-#pragma unroll
-  for (int q = 0; q < kGsVpw; ++q) {
-    const int k = wave + kGsWaves * q;
-    ca[q] = k < j ? cf[k] : 0.0;
-    cb[q] = k < j ? cf[kMaxBasis + k] : 0.0;
-  }
   const double inv = sc[0], tt = sc[1];
   double* uj = V + (size_t)j * ldv;
   double* un = V + (size_t)(j + 1) * ldv;
-  for (int base = 0; base < rpb; base += kGsRound) {
-#pragma unroll
-    for (int u4 = 0; u4 < kGsRound / 64; ++u4) {
-      const int row = r0 + base + u4 * 64 + lane;
-      double p1 = 0.0, p2 = 0.0;
-#pragma unroll
-      for (int q = 0; q < kGsVpw; ++q) {
-        const int k = wave + kGsWaves * q;
-        if (k < j && row < n) {
-          const double x = V[(size_t)k * ldv + row];
-          p1 += ca[q] * x;
-          p2 += cb[q] * x;
-        }
-      }
-      red[0][wave][u4 * 64 + lane] = p1;
-      red[1][wave][u4 * 64 + lane] = p2;
+  const int r0 = blockIdx.x * rpb;
+  const int r1 = min(r0 + rpb, n);
+  for (int ra = r0 + t; ra < r1; ra += 2 * kGsThreads) {
+    const int rb = ra + kGsThreads;
+    const bool hb = rb < r1;
+    double p1a = 0.0, p2a = 0.0, p1b = 0.0, p2b = 0.0;
+#pragma unroll 4
+    for (int k = 0; k < j; ++k) {
+      const double* vk = V + (size_t)k * ldv;
+      const double xa = vk[ra];
+      const double xb = hb ? vk[rb] : 0.0;
+      const double ca = cf[k], cb = cf[kMaxBasis + k];
+      p1a += ca * xa;
+      p2a += cb * xa;
+      p1b += ca * xb;
+      p2b += cb * xb;
     }
-    __syncthreads();
-    if (t < kGsRound) {
-      const int row = r0 + base + t;
-      double s1 = 0.0, s2 = 0.0;
-#pragma unroll
-      for (int w = 0; w < kGsWaves; ++w) {
-        s1 += red[0][w][t];
-        s2 += red[1][w][t];
-      }
-      if (row < n) {
-        const double u = uj[row];
-        uj[row] = inv * u - s1;
-        un[row] = W[row] - s2 - tt * u;
-      }
+    const double ua = uj[ra];
+    uj[ra] = inv * ua - p1a;
+    un[ra] = W[ra] - p2a - tt * ua;
+    if (hb) {
+      const double ub = uj[rb];
+      uj[rb] = inv * ub - p1b;
+      un[rb] = W[rb] - p2b - tt * ub;
     }
-    __syncthreads();
   }
 }
 
@@ -525,11 +628,11 @@ __global__ __launch_bounds__(kGsThreads) void k_arn_update(const double* __restr
                                                            int update, DevState* st,
                                                            const double* part, HostFlags* hf) {
   if (st->cycle_done) return;
-  __shared__ double red[2][kGsWaves][kGsRound];
+  __shared__ double scratch[16 * kSumStride];
   __shared__ double sums[kSumStride];
   __shared__ double cf[2 * kMaxBasis];
   __shared__ double sc[8];
-  arn_sums(part, nb, j, sums, &red[0][0][0]);
+  arn_sums(part, nb, j, sums, scratch);
   const int t = threadIdx.x;
   if (t == 0) {
     double aa = 0.0, ab = 0.0, bb = 0.0;
@@ -553,19 +656,31 @@ __global__ __launch_bounds__(kGsThreads) void k_arn_update(const double* __restr
   }
   __syncthreads();
   // the last workgroup completes the Hessenberg column after its rows
-  if (update) arn_rows(W, V, ldv, n, j, rpb, sums, sc, cf, red);
-  if (blockIdx.x == gridDim.x - 1)
-    arn_column(j, update, sums, sc, st, hf, &red[0][0][0], &red[1][0][0]);
+  if (update) arn_rows(W, V, ldv, n, j, rpb, sums, sc, cf);
+  if (blockIdx.x == gridDim.x - 1) {
+    __syncthreads();
+    arn_column(j, update, sums, sc, st, hf, scratch, scratch + 2 * kMaxBasis);
+  }
 }
 
-__global__ void k_trisolve(DevState* st) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// y = R^-1 g for the k x k upper triangle R of H (one wavefront): the
+// triangle is staged in LDS, then column-oriented back substitution.
+__global__ __launch_bounds__(64) void k_trisolve(DevState* st) {
+  __shared__ double Rs[kMaxBasis][kMaxBasis];     // Rs[l][i] = R(i, l)
+  __shared__ double sv[kMaxBasis];
   const int k = st->k;
+  const int t = threadIdx.x;
   const int ld = kMaxBasis + 1;
+  for (int l = 0; l < k; ++l)
+    if (t <= l) Rs[l][t] = st->H[(size_t)l * ld + t];
+  if (t < k) sv[t] = st->g[t];
+  __syncthreads();
   for (int i = k - 1; i >= 0; --i) {
-    double s = st->g[i];
-    for (int l = i + 1; l < k; ++l) s -= st->H[(size_t)l * ld + i] * st->y[l];
-    st->y[i] = s / st->H[(size_t)i * ld + i];
+    const double yi = sv[i] / Rs[i][i];
+    __syncthreads();
+    if (t < i) sv[t] -= Rs[i][t] * yi;
+    if (t == 0) st->y[i] = yi;
+    __syncthreads();
   }
 }
 
@@ -849,9 +964,11 @@ __global__ __launch_bounds__(kBlock) void k_scale_convert(const TB* __restrict__
                                                           const double* bscale,
                                                           T* __restrict__ out, int n,
                                                           const DevState* gate) {
-  if (gate && gate->cycle_done) return;
   const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) out[i] = load_b<T>(b, scale_of(bscale), i);
+  if (i >= n) return;
+  const int stop = gate_flag(gate);
+  const T v = load_b<T>(b, scale_of(bscale), i);
+  if (!stop) out[i] = v;
 }
 
 template <typename TA, typename TB>
@@ -880,6 +997,7 @@ void launch_spmv(const Sell<TM>& A, const TX* x, TY* y, const DevState* gate, hi
     case 4: k_spmv<4, TM, TX, TY><<<blocks_lpr(A.n_rows, 4), kBlock, 0, s>>>(A, x, y, gate); break;
     case 8: k_spmv<8, TM, TX, TY><<<blocks_lpr(A.n_rows, 8), kBlock, 0, s>>>(A, x, y, gate); break;
     case 16: k_spmv<16, TM, TX, TY><<<blocks_lpr(A.n_rows, 16), kBlock, 0, s>>>(A, x, y, gate); break;
+    case 32: k_spmv<32, TM, TX, TY><<<blocks_lpr(A.n_rows, 32), kBlock, 0, s>>>(A, x, y, gate); break;
     default: k_spmv<1, TM, TX, TY><<<blocks_lpr(A.n_rows, 1), kBlock, 0, s>>>(A, x, y, gate); break;
   }
 }
@@ -892,6 +1010,7 @@ void launch_residual(const Sell<T>& A, const TB* b, const double* bscale, const 
     case 4: k_residual<4, T, TB><<<blocks_lpr(A.n_rows, 4), kBlock, 0, s>>>(A, b, bscale, x, r, gate); break;
     case 8: k_residual<8, T, TB><<<blocks_lpr(A.n_rows, 8), kBlock, 0, s>>>(A, b, bscale, x, r, gate); break;
     case 16: k_residual<16, T, TB><<<blocks_lpr(A.n_rows, 16), kBlock, 0, s>>>(A, b, bscale, x, r, gate); break;
+    case 32: k_residual<32, T, TB><<<blocks_lpr(A.n_rows, 32), kBlock, 0, s>>>(A, b, bscale, x, r, gate); break;
     default: k_residual<1, T, TB><<<blocks_lpr(A.n_rows, 1), kBlock, 0, s>>>(A, b, bscale, x, r, gate); break;
   }
 }
@@ -904,6 +1023,7 @@ void launch_jacobi_zero(const Sell<T>& A, const T* wd, const TB* b, const double
     case 4: k_jacobi_zero<4, T, TB><<<blocks_lpr(A.n_rows, 4), kBlock, 0, s>>>(A, wd, b, bscale, x, two, gate); break;
     case 8: k_jacobi_zero<8, T, TB><<<blocks_lpr(A.n_rows, 8), kBlock, 0, s>>>(A, wd, b, bscale, x, two, gate); break;
     case 16: k_jacobi_zero<16, T, TB><<<blocks_lpr(A.n_rows, 16), kBlock, 0, s>>>(A, wd, b, bscale, x, two, gate); break;
+    case 32: k_jacobi_zero<32, T, TB><<<blocks_lpr(A.n_rows, 32), kBlock, 0, s>>>(A, wd, b, bscale, x, two, gate); break;
     default: k_jacobi_zero<1, T, TB><<<blocks_lpr(A.n_rows, 1), kBlock, 0, s>>>(A, wd, b, bscale, x, two, gate); break;
   }
 }
@@ -916,7 +1036,21 @@ void launch_jacobi(const Sell<T>& A, const T* wd, const TB* b, const double* bsc
     case 4: k_jacobi<4, T, TB><<<blocks_lpr(A.n_rows, 4), kBlock, 0, s>>>(A, wd, b, bscale, x_in, x_out, gate); break;
     case 8: k_jacobi<8, T, TB><<<blocks_lpr(A.n_rows, 8), kBlock, 0, s>>>(A, wd, b, bscale, x_in, x_out, gate); break;
     case 16: k_jacobi<16, T, TB><<<blocks_lpr(A.n_rows, 16), kBlock, 0, s>>>(A, wd, b, bscale, x_in, x_out, gate); break;
+    case 32: k_jacobi<32, T, TB><<<blocks_lpr(A.n_rows, 32), kBlock, 0, s>>>(A, wd, b, bscale, x_in, x_out, gate); break;
     default: k_jacobi<1, T, TB><<<blocks_lpr(A.n_rows, 1), kBlock, 0, s>>>(A, wd, b, bscale, x_in, x_out, gate); break;
+  }
+}
+
+template <typename T, typename TB>
+void launch_restrict_residual(const Sell<T>& Q, const TB* b, const double* bscale, const T* x,
+                              int n_fine, T* bc, const DevState* gate, hipStream_t s) {
+  if (Q.n_rows <= 0) return;
+  switch (Q.lpr) {
+    case 4: k_restrict_residual<4, T, TB><<<blocks_lpr(Q.n_rows, 4), kBlock, 0, s>>>(Q, b, bscale, x, n_fine, bc, gate); break;
+    case 8: k_restrict_residual<8, T, TB><<<blocks_lpr(Q.n_rows, 8), kBlock, 0, s>>>(Q, b, bscale, x, n_fine, bc, gate); break;
+    case 16: k_restrict_residual<16, T, TB><<<blocks_lpr(Q.n_rows, 16), kBlock, 0, s>>>(Q, b, bscale, x, n_fine, bc, gate); break;
+    case 32: k_restrict_residual<32, T, TB><<<blocks_lpr(Q.n_rows, 32), kBlock, 0, s>>>(Q, b, bscale, x, n_fine, bc, gate); break;
+    default: k_restrict_residual<1, T, TB><<<blocks_lpr(Q.n_rows, 1), kBlock, 0, s>>>(Q, b, bscale, x, n_fine, bc, gate); break;
   }
 }
 
@@ -927,6 +1061,7 @@ void launch_prolong(const Sell<T>& P, const T* xc, T* x, const DevState* gate, h
     case 4: k_prolong<4, T><<<blocks_lpr(P.n_rows, 4), kBlock, 0, s>>>(P, xc, x, gate); break;
     case 8: k_prolong<8, T><<<blocks_lpr(P.n_rows, 8), kBlock, 0, s>>>(P, xc, x, gate); break;
     case 16: k_prolong<16, T><<<blocks_lpr(P.n_rows, 16), kBlock, 0, s>>>(P, xc, x, gate); break;
+    case 32: k_prolong<32, T><<<blocks_lpr(P.n_rows, 32), kBlock, 0, s>>>(P, xc, x, gate); break;
     default: k_prolong<1, T><<<blocks_lpr(P.n_rows, 1), kBlock, 0, s>>>(P, xc, x, gate); break;
   }
 }
@@ -935,7 +1070,7 @@ template <typename T>
 void launch_coarse(const double* Ainv, int n, const T* bc, T* xc, const DevState* gate,
                    hipStream_t s) {
   if (n <= 0) return;
-  k_coarse<T><<<(n * 64 + kBlock - 1) / kBlock, kBlock, 0, s>>>(Ainv, n, bc, xc, gate);
+  k_coarse<T><<<n, kBlock, 0, s>>>(Ainv, n, bc, xc, gate);
 }
 
 template <typename T>
@@ -1081,7 +1216,9 @@ void launch_fill(T* a, T v, int n, hipStream_t s) {
   template void launch_jacobi_zero<T, TB>(const Sell<T>&, const T*, const TB*, const double*, \
                                           T*, int, const DevState*, hipStream_t);              \
   template void launch_jacobi<T, TB>(const Sell<T>&, const T*, const TB*, const double*,      \
-                                     const T*, T*, const DevState*, hipStream_t);
+                                     const T*, T*, const DevState*, hipStream_t);             \
+  template void launch_restrict_residual<T, TB>(const Sell<T>&, const TB*, const double*,     \
+                                                const T*, int, T*, const DevState*, hipStream_t);
 
 SD_INST_T(double, double)
 SD_INST_T(float, double)

@@ -76,6 +76,10 @@ struct HostHierarchy {
 void amg_setup_host(const HostCSR& A, const std::vector<int32_t>& comp,
                     bool singular, const AMGOpts& o, HostHierarchy& h);
 
+// Q = [R | -R A] (n_c x 2n): the restricted residual R (b - A x) = Q [b; x]
+// in one sparse product, so that a V-cycle level needs no residual vector.
+HostCSR residual_restriction(const HostCSR& A, const HostCSR& R);
+
 // 32-bit finaliser of MurmurHash3 (public domain).
 inline uint32_t fmix32(uint32_t h) {
   h ^= h >> 16;

@@ -50,53 +50,89 @@ void* DeviceMem::get(size_t bytes) {
 static int lanes_per_row(const HostCSR& A, bool allow_csr) {
   if (!allow_csr || A.n_rows == 0) return 1;
   const double avg = (double)A.nnz() / (double)A.n_rows;
-  if (avg <= 12.0 && A.n_rows >= 16384) return 1;
-  return avg <= 16.0 ? 4 : (avg <= 48.0 ? 8 : 16);
+  if (avg <= 12.0 && A.n_rows >= 65536) return 1;
+  return avg <= 16.0 ? 4 : (avg <= 48.0 ? 8 : (avg <= 96.0 ? 16 : 32));
 }
 
+template <typename T>
+static Sell<T> copy_sell(const std::vector<int>& ptr, const std::vector<int>& col,
+                         const std::vector<T>& val, int64_t n, int64_t n_cols, int lpr, int width,
+                         DeviceMem& mem, hipStream_t s) {
+  Sell<T> d;
+  d.n_rows = (int)n;
+  d.n_cols = (int)n_cols;
+  d.lpr = lpr;
+  d.width = width;
+  int* dp = mem.array<int>(std::max<size_t>(ptr.size(), 1));
+  int* dcol = mem.array<int>(std::max<size_t>(col.size(), 1));
+  T* dval = mem.array<T>(std::max<size_t>(val.size(), 1));
+  if (!ptr.empty())
+    SD_HIP(hipMemcpyAsync(dp, ptr.data(), ptr.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  if (!col.empty())
+    SD_HIP(hipMemcpyAsync(dcol, col.data(), col.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  if (!val.empty())
+    SD_HIP(hipMemcpyAsync(dval, val.data(), val.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  SD_HIP(hipStreamSynchronize(s));
+  d.sptr = dp;
+  d.col = dcol;
+  d.val = dval;
+  return d;
+}
+
+// Upload as SELL-64 (one lane per row) or, for hierarchy matrices with few or
+// long rows (allow_csr), as CSR read by lpr lanes per row.  Hierarchy
+// matrices whose rows pad to one common width at modest cost get that
+// uniform width, which spares the kernels the row-pointer load.  Padding
+// entries repeat the row's last column with value 0.
 template <typename T>
 Sell<T> upload_sell(const HostCSR& A, DeviceMem& mem, hipStream_t s, bool allow_csr) {
   const int64_t n = A.n_rows;
   const int lpr = lanes_per_row(A, allow_csr);
+  int64_t maxlen = 0;
+  for (int64_t r = 0; r < n; ++r) maxlen = std::max(maxlen, A.rowptr[r + 1] - A.rowptr[r]);
   if (lpr > 1) {
+    const int64_t w = (maxlen + lpr - 1) / lpr * lpr;
+    const bool uniform = w > 0 && (double)(n * w) <= 2.0 * (double)A.nnz();
+    if (uniform) {
+      if (n * w >= ((int64_t)1 << 31)) throw Error(SD_E_INVALID, "matrix too large for int32 CSR");
+      std::vector<int> col((size_t)(n * w), 0);
+      std::vector<T> val((size_t)(n * w), (T)0);
+      for (int64_t r = 0; r < n; ++r) {
+        const int64_t beg = A.rowptr[r], len = A.rowptr[r + 1] - beg;
+        for (int64_t k = 0; k < w; ++k) {
+          col[r * w + k] = k < len ? A.col[beg + k] : (len > 0 ? A.col[beg + len - 1] : 0);
+          val[r * w + k] = k < len ? (T)A.val[beg + k] : (T)0;
+        }
+      }
+      return copy_sell<T>({}, col, val, n, A.n_cols, lpr, (int)w, mem, s);
+    }
     if (A.nnz() >= ((int64_t)1 << 31)) throw Error(SD_E_INVALID, "matrix too large for int32 CSR");
     std::vector<int> rp((size_t)n + 1);
     for (int64_t r = 0; r <= n; ++r) rp[r] = (int)A.rowptr[r];
-    std::vector<T> val((size_t)std::max<int64_t>(A.nnz(), 1), (T)0);
+    std::vector<T> val((size_t)A.nnz());
     for (int64_t k = 0; k < A.nnz(); ++k) val[k] = (T)A.val[k];
-    int* drp = mem.array<int>(rp.size());
-    int* dcol = mem.array<int>((size_t)std::max<int64_t>(A.nnz(), 1));
-    T* dval = mem.array<T>(val.size());
-    SD_HIP(hipMemcpyAsync(drp, rp.data(), rp.size() * sizeof(int), hipMemcpyHostToDevice, s));
-    if (A.nnz() > 0)
-      SD_HIP(hipMemcpyAsync(dcol, A.col.data(), (size_t)A.nnz() * sizeof(int),
-                            hipMemcpyHostToDevice, s));
-    SD_HIP(hipMemcpyAsync(dval, val.data(), val.size() * sizeof(T), hipMemcpyHostToDevice, s));
-    SD_HIP(hipStreamSynchronize(s));
-    Sell<T> d;
-    d.n_rows = (int)n;
-    d.n_cols = (int)A.n_cols;
-    d.sptr = drp;
-    d.col = dcol;
-    d.val = dval;
-    d.lpr = lpr;
-    return d;
+    return copy_sell<T>(rp, A.col, val, n, A.n_cols, lpr, 0, mem, s);
   }
   const int64_t ns = (n + 63) / 64;
-  std::vector<int> sptr((size_t)ns + 1, 0);
+  std::vector<int64_t> width((size_t)ns, 0);
   int64_t tot = 0;
   for (int64_t sl = 0; sl < ns; ++sl) {
-    int64_t w = 0;
     for (int64_t r = sl * 64; r < std::min(n, sl * 64 + 64); ++r)
-      w = std::max(w, A.rowptr[r + 1] - A.rowptr[r]);
-    tot += 64 * w;
-    if (tot >= ((int64_t)1 << 31)) throw Error(SD_E_INVALID, "matrix too large for SELL-64");
-    sptr[sl + 1] = (int)tot;
+      width[sl] = std::max(width[sl], A.rowptr[r + 1] - A.rowptr[r]);
+    tot += 64 * width[sl];
   }
-  std::vector<int> col((size_t)std::max<int64_t>(tot, 1), 0);
-  std::vector<T> val((size_t)std::max<int64_t>(tot, 1), (T)0);
+  const bool uniform = allow_csr && maxlen > 0 && (double)(64 * ns * maxlen) <= 1.3 * (double)tot;
+  if (uniform) {
+    for (auto& w : width) w = maxlen;
+    tot = 64 * ns * maxlen;
+  }
+  if (tot >= ((int64_t)1 << 31)) throw Error(SD_E_INVALID, "matrix too large for SELL-64");
+  std::vector<int> sptr((size_t)ns + 1, 0);
+  for (int64_t sl = 0; sl < ns; ++sl) sptr[sl + 1] = (int)(sptr[sl] + 64 * width[sl]);
+  std::vector<int> col((size_t)tot, 0);
+  std::vector<T> val((size_t)tot, (T)0);
   for (int64_t sl = 0; sl < ns; ++sl) {
-    const int64_t w = (sptr[sl + 1] - sptr[sl]) / 64;
+    const int64_t w = width[sl];
     for (int64_t lane = 0; lane < 64; ++lane) {
       const int64_t r = sl * 64 + lane;
       int64_t len = 0, beg = 0;
@@ -116,20 +152,7 @@ Sell<T> upload_sell(const HostCSR& A, DeviceMem& mem, hipStream_t s, bool allow_
       }
     }
   }
-  Sell<T> d;
-  d.n_rows = (int)n;
-  d.n_cols = (int)A.n_cols;
-  int* dsp = mem.array<int>(sptr.size());
-  int* dcol = mem.array<int>(col.size());
-  T* dval = mem.array<T>(val.size());
-  SD_HIP(hipMemcpyAsync(dsp, sptr.data(), sptr.size() * sizeof(int), hipMemcpyHostToDevice, s));
-  SD_HIP(hipMemcpyAsync(dcol, col.data(), col.size() * sizeof(int), hipMemcpyHostToDevice, s));
-  SD_HIP(hipMemcpyAsync(dval, val.data(), val.size() * sizeof(T), hipMemcpyHostToDevice, s));
-  SD_HIP(hipStreamSynchronize(s));
-  d.sptr = dsp;
-  d.col = dcol;
-  d.val = dval;
-  return d;
+  return copy_sell<T>(sptr, col, val, n, A.n_cols, 1, uniform ? (int)maxlen : 0, mem, s);
 }
 
 template Sell<double> upload_sell<double>(const HostCSR&, DeviceMem&, hipStream_t, bool);
@@ -274,12 +297,19 @@ void upload_hierarchy(const HostHierarchy& h, DevHierarchy<T>& d, double omega, 
     D.wd = mem.array<T>((size_t)D.n);
     SD_HIP(hipMemcpyAsync(D.wd, wd.data(), wd.size() * sizeof(T), hipMemcpyHostToDevice, s));
     D.tmp = mem.array<T>((size_t)D.n);
-    D.r = mem.array<T>((size_t)D.n);
     D.x = mem.array<T>((size_t)D.n);
     D.b = mem.array<T>((size_t)D.n);
     if (l + 1 < h.levels.size()) {
       D.P = upload_sell<T>(H.P, mem, s, true);
-      D.R = upload_sell<T>(H.R, mem, s, true);
+      // On the finest level the stencil rows read x coalesced (one lane per
+      // row), so the residual and the restriction stay separate there; on
+      // coarser levels, where launches are latency bound, they are fused.
+      if (l == 0) {
+        D.R = upload_sell<T>(H.R, mem, s, true);
+        D.r = mem.array<T>((size_t)D.n);
+      } else {
+        D.Q = upload_sell<T>(residual_restriction(H.A, H.R), mem, s, true);
+      }
     }
     SD_HIP(hipStreamSynchronize(s));
   }
@@ -347,9 +377,13 @@ class PrecImpl : public PrecBase {
         std::swap(cur, other);
       }
     }
-    launch_residual<T, TB>(L.A, b, bs, cur, L.r, gate, s);
     DevLevel<T>& C = h.lev[l + 1];
-    launch_spmv<T, T, T>(L.R, L.r, C.b, gate, s);
+    if (l == 0) {
+      launch_residual<T, TB>(L.A, b, bs, cur, L.r, gate, s);
+      launch_spmv<T, T, T>(L.R, L.r, C.b, gate, s);
+    } else {
+      launch_restrict_residual<T, TB>(L.Q, b, bs, cur, L.n, C.b, gate, s);
+    }
     vcycle<T>(blk, l + 1, C.b, nullptr, C.x, gate, s);
     launch_prolong<T>(L.P, C.x, cur, gate, s);
     for (int k = 0; k < nu_post; ++k) {

@@ -42,11 +42,13 @@ class DeviceMem {
 template <typename T>
 struct DevLevel {
   int n = 0;
-  Sell<T> A, P, R;
+  Sell<T> A, P;
+  Sell<T> R;           // restriction (finest level)
+  Sell<T> Q;           // [R | -R A]: restricted residual from [b; x] (coarser levels)
   T* wd = nullptr;     // omega / a_ii
   T* x = nullptr;      // iterate (levels >= 1)
   T* tmp = nullptr;
-  T* r = nullptr;
+  T* r = nullptr;      // residual (finest level)
   T* b = nullptr;      // right-hand side (levels >= 1)
 };
 
@@ -118,7 +120,7 @@ class Solver {
   std::unique_ptr<DeviceMem> mem;
   Sell<double> A64;
   double* b_dev = nullptr;
-  double* V = nullptr;              // (m+1) basis vectors, unnormalised
+  double* V = nullptr;              // (m+1) basis slots: orthonormal vectors + the open candidate
   double* W = nullptr;
   double* part = nullptr;
   DevState* st = nullptr;
