@@ -371,6 +371,76 @@ void dense_inverse(std::vector<double>& M, int64_t n, std::vector<double>& inv) 
 
 }  // namespace
 
+namespace {
+
+// X + alpha Y (union pattern, rows sorted by column).
+HostCSR add_scaled(const HostCSR& X, const HostCSR& Y, double alpha) {
+  HostCSR Z;
+  Z.n_rows = X.n_rows;
+  Z.n_cols = X.n_cols;
+  Z.rowptr.assign(1, 0);
+  for (int64_t i = 0; i < X.n_rows; ++i) {
+    int64_t a = X.rowptr[i], ae = X.rowptr[i + 1], b = Y.rowptr[i], be = Y.rowptr[i + 1];
+    while (a < ae || b < be) {
+      if (b >= be || (a < ae && X.col[a] < Y.col[b])) {
+        Z.col.push_back(X.col[a]);
+        Z.val.push_back(X.val[a]);
+        ++a;
+      } else if (a >= ae || Y.col[b] < X.col[a]) {
+        Z.col.push_back(Y.col[b]);
+        Z.val.push_back(alpha * Y.val[b]);
+        ++b;
+      } else {
+        Z.col.push_back(X.col[a]);
+        Z.val.push_back(X.val[a] + alpha * Y.val[b]);
+        ++a;
+        ++b;
+      }
+    }
+    Z.rowptr.push_back((int64_t)Z.col.size());
+  }
+  return Z;
+}
+
+// diag(s) X (rows scaled) or X diag(s) (columns scaled).
+HostCSR scale_rows(HostCSR X, const std::vector<double>& s) {
+  for (int64_t i = 0; i < X.n_rows; ++i)
+    for (int64_t k = X.rowptr[i]; k < X.rowptr[i + 1]; ++k) X.val[k] = s[i] * X.val[k];
+  return X;
+}
+HostCSR scale_cols(HostCSR X, const std::vector<double>& s) {
+  for (size_t k = 0; k < X.col.size(); ++k) X.val[k] = X.val[k] * s[X.col[k]];
+  return X;
+}
+
+std::vector<double> jacobi_weights(const HostCSR& A, double omega) {
+  std::vector<double> w((size_t)A.n_rows);
+  for (int64_t i = 0; i < A.n_rows; ++i) w[i] = omega / diag_of(A, i);
+  return w;
+}
+
+}  // namespace
+
+HostCSR presmoothed_restriction(const HostCSR& A, const HostCSR& R, double omega) {
+  const std::vector<double> w = jacobi_weights(A, omega);
+  const HostCSR T = scale_cols(A, w);                 // A W
+  HostCSR I;
+  I.n_rows = I.n_cols = A.n_rows;
+  I.rowptr.resize((size_t)A.n_rows + 1);
+  I.col.resize((size_t)A.n_rows);
+  I.val.assign((size_t)A.n_rows, 1.0);
+  for (int64_t i = 0; i <= A.n_rows; ++i) I.rowptr[i] = i;
+  for (int64_t i = 0; i < A.n_rows; ++i) I.col[i] = (int32_t)i;
+  // I - A M2 = I - 2 A W + (A W)(A W)
+  const HostCSR E = add_scaled(add_scaled(I, T, -2.0), spgemm(T, T), 1.0);
+  return spgemm(R, E);
+}
+
+HostCSR smoothed_correction(const HostCSR& A, const HostCSR& P, double omega) {
+  const std::vector<double> w = jacobi_weights(A, omega);
+  return add_scaled(P, scale_rows(spgemm(A, P), w), -1.0);
+}
+
 HostCSR residual_restriction(const HostCSR& A, const HostCSR& R) {
   const HostCSR RA = spgemm(R, A);
   HostCSR Q;

@@ -81,6 +81,17 @@ void launch_jacobi(const Sell<T>& A, const T* wd, const TB* b, const double* bsc
 template <typename T, typename TB>
 void launch_restrict_residual(const Sell<T>& Q, const TB* b, const double* bscale, const T* x,
                               int n_fine, T* bc, const DevState* gate, hipStream_t s);
+// Two damped-Jacobi sweeps from zero on A (x) and bc = G b, one launch
+// (G = R (I - A M2) from presmoothed_restriction, 64 lanes per row)
+template <typename T, typename TB>
+void launch_presmooth_restrict(const Sell<T>& A, const T* wd, const Sell<T>& G, const TB* b,
+                               const double* bscale, T* x, T* bc, const DevState* gate,
+                               hipStream_t s);
+// xout = x + w .* (bscale b - A x) + F xc (F = P - W A P, stored with A's lanes)
+template <typename T, typename TB>
+void launch_prolong_smooth(const Sell<T>& A, const Sell<T>& F, const T* wd, const TB* b,
+                           const double* bscale, const T* x, const T* xc, T* xout,
+                           const DevState* gate, hipStream_t s);
 // x += P xc
 template <typename T>
 void launch_prolong(const Sell<T>& P, const T* xc, T* x, const DevState* gate,

@@ -112,43 +112,47 @@ inline int dot_blocks(int n) {
 
 // ----------------------------------------------------------------- kernels
 
-// Row access for the V-cycle kernels.  LPR == 1: SELL-64, one lane per row.
-// LPR > 1: CSR (A.sptr holds the row pointers) with LPR consecutive lanes per
-// row and a shuffle reduction; used on coarse levels, whose smoothed-
-// aggregation rows are long and few, where one lane per row leaves the chip
-// idle and serialises the gathers.  f(c) supplies the multiplied vector entry.
-// A uniform row width (A.width > 0) spares the pointer load at the head of
-// each row's dependent load chain.
+// Row access for the V-cycle kernels: SELL-C with C = 64 / LPR rows per
+// slice and LPR lanes per row.  A wavefront owns one slice; lane
+// (sub, r) = (lane / C, lane % C) handles entries sub, sub + LPR, ... of row
+// r, and entry k of row r lives at slice base + k C + r, so each load
+// instruction reads 64 consecutive entries and the gathers of C neighbouring
+// rows share cache lines.  LPR == 1 is SELL-64 (finest levels, short rows);
+// LPR > 1 serves coarse levels and transfer operators, whose rows are long
+// and few.  A uniform width (A.width > 0, a multiple of LPR) replaces the
+// slice pointers and spares their load at the head of each load chain.
 template <int LPR, typename TM, typename F>
 __device__ __forceinline__ TM row_sum(const Sell<TM>& A, int row, int sub, F f) {
-  TM acc = 0;
-  if constexpr (LPR == 1) {
-    int beg, end;
-    if (A.width) {
-      beg = (row >> 6) * (64 * A.width) + (row & 63);
-      end = beg + 64 * A.width;
-    } else {
-      const int s = row >> 6;
-      beg = A.sptr[s] + (row & 63);
-      end = A.sptr[s + 1];
-    }
-#pragma unroll 4
-    for (int e = beg; e < end; e += 64) acc += A.val[e] * f(A.col[e]);
+  constexpr int C = 64 / LPR;
+  const int sl = row / C, r = row - sl * C;
+  int beg, end;
+  if (A.width) {
+    beg = sl * (C * A.width);
+    end = beg + C * A.width;
   } else {
-    int beg, end;
-    if (A.width) {
-      beg = row * A.width + sub;
-      end = (row + 1) * A.width;
-    } else {
-      beg = A.sptr[row] + sub;
-      end = A.sptr[row + 1];
-    }
-#pragma unroll 2
-    for (int e = beg; e < end; e += LPR) acc += A.val[e] * f(A.col[e]);
-#pragma unroll
-    for (int o = LPR / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LPR);
+    beg = A.sptr[sl];
+    end = A.sptr[sl + 1];
   }
+  TM acc = 0;
+#pragma unroll 4
+  for (int e = beg + sub * C + r; e < end; e += 64) acc += A.val[e] * f(A.col[e]);
+#pragma unroll
+  for (int o = C; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
   return acc;
+}
+
+// thread -> (row, lane within the row group); consecutive wavefronts of a
+// workgroup take consecutive slices, workgroups XCD-contiguous row ranges
+template <int LPR>
+__device__ __forceinline__ int2 row_of_thread(int block, int nblocks) {
+  constexpr int C = 64 / LPR;
+  const int gt = xcd_block(block, nblocks) * kBlock + threadIdx.x;
+  const int lane = gt & 63;
+  return make_int2((gt >> 6) * C + lane % C, lane / C);
+}
+template <int LPR>
+__device__ __forceinline__ int2 row_of_thread() {
+  return row_of_thread<LPR>(blockIdx.x, gridDim.x);
 }
 
 // The cycle-done flag of the gated kernels, read with a vector load through
@@ -162,12 +166,6 @@ __device__ __forceinline__ int gate_flag(const DevState* gate) {
   return *p;
 }
 
-// thread -> (row, lane within the row group), XCD-contiguous row ranges
-template <int LPR>
-__device__ __forceinline__ int2 row_of_thread() {
-  const int gt = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  return make_int2(gt / LPR, gt % LPR);
-}
 
 template <int LPR, typename TM, typename TX, typename TY>
 __global__ __launch_bounds__(kBlock) void k_spmv(Sell<TM> A, const TX* __restrict__ x,
@@ -209,6 +207,56 @@ __global__ __launch_bounds__(kBlock) void k_restrict_residual(Sell<T> Q, const T
     return c < n_fine ? load_b<T>(b, sc, c) : x[c - n_fine];
   });
   if (rs.y == 0 && !stop) bc[rs.x] = v;
+}
+
+// Pre-smoothing and restriction in one launch, both from b alone: the first
+// nb_a workgroups run two damped-Jacobi sweeps from zero on the rows of A
+// (x = (2W - W A W) b), the others compute bc = G b with G = R (I - A M2)
+// (one wavefront per row: G's rows are long).
+template <int LA, typename T, typename TB>
+__global__ __launch_bounds__(kBlock) void k_presmooth_restrict(Sell<T> A, const T* __restrict__ wd,
+                                                               Sell<T> G, const TB* __restrict__ b,
+                                                               const double* bscale,
+                                                               T* __restrict__ x,
+                                                               T* __restrict__ bc, int nb_a,
+                                                               const DevState* gate) {
+  const int stop = gate_flag(gate);
+  const double s = scale_of(bscale);
+  if ((int)blockIdx.x < nb_a) {
+    const int2 rs = row_of_thread<LA>(blockIdx.x, nb_a);
+    const int row = rs.x, sub = rs.y;
+    if (row >= A.n_rows) return;
+    const T bi = load_b<T>(b, s, row);
+    const T acc = row_sum<LA>(A, row, sub, [&](int c) { return wd[c] * load_b<T>(b, s, c); });
+    if (sub == 0 && !stop) x[row] = wd[row] * bi + wd[row] * (bi - acc);
+  } else {
+    const int2 rs = row_of_thread<64>(blockIdx.x - nb_a, gridDim.x - nb_a);
+    const int row = rs.x, sub = rs.y;
+    if (row >= G.n_rows) return;
+    const T v = row_sum<64>(G, row, sub, [&](int c) { return load_b<T>(b, s, c); });
+    if (sub == 0 && !stop) bc[row] = v;
+  }
+}
+
+// Coarse correction and the first post-smoothing sweep in one pass:
+// xout = x + W (b - A x) + F xc with F = P - W A P (F stored with A's lanes).
+template <int LA, typename T, typename TB>
+__global__ __launch_bounds__(kBlock) void k_prolong_smooth(Sell<T> A, Sell<T> F,
+                                                           const T* __restrict__ wd,
+                                                           const TB* __restrict__ b,
+                                                           const double* bscale,
+                                                           const T* __restrict__ x,
+                                                           const T* __restrict__ xc,
+                                                           T* __restrict__ xout,
+                                                           const DevState* gate) {
+  const int2 rs = row_of_thread<LA>();
+  const int row = rs.x;
+  if (row >= A.n_rows) return;
+  const int stop = gate_flag(gate);
+  const T ax = row_sum<LA>(A, row, rs.y, [&](int c) { return x[c]; });
+  const T fx = row_sum<LA>(F, row, rs.y, [&](int c) { return xc[c]; });
+  if (rs.y == 0 && !stop)
+    xout[row] = x[row] + wd[row] * (load_b<T>(b, scale_of(bscale), row) - ax) + fx;
 }
 
 template <int LPR, typename T, typename TB>
@@ -988,7 +1036,13 @@ __global__ __launch_bounds__(kBlock) void k_fill(T* __restrict__ a, T v, int n) 
 
 // ---------------------------------------------------------------- launchers
 
-inline int blocks_lpr(int n, int lpr) { return (int)(((int64_t)n * lpr + kBlock - 1) / kBlock); }
+[[noreturn]] void throw_launch(const char* what);
+
+// workgroups for n rows in SELL-C slices of 64 / lpr rows, one wavefront each
+inline int blocks_lpr(int n, int lpr) {
+  const int64_t c = 64 / lpr, waves = ((int64_t)n + c - 1) / c;
+  return (int)((waves * 64 + kBlock - 1) / kBlock);
+}
 
 template <typename TM, typename TX, typename TY>
 void launch_spmv(const Sell<TM>& A, const TX* x, TY* y, const DevState* gate, hipStream_t s) {
@@ -998,6 +1052,7 @@ void launch_spmv(const Sell<TM>& A, const TX* x, TY* y, const DevState* gate, hi
     case 8: k_spmv<8, TM, TX, TY><<<blocks_lpr(A.n_rows, 8), kBlock, 0, s>>>(A, x, y, gate); break;
     case 16: k_spmv<16, TM, TX, TY><<<blocks_lpr(A.n_rows, 16), kBlock, 0, s>>>(A, x, y, gate); break;
     case 32: k_spmv<32, TM, TX, TY><<<blocks_lpr(A.n_rows, 32), kBlock, 0, s>>>(A, x, y, gate); break;
+    case 64: k_spmv<64, TM, TX, TY><<<blocks_lpr(A.n_rows, 64), kBlock, 0, s>>>(A, x, y, gate); break;
     default: k_spmv<1, TM, TX, TY><<<blocks_lpr(A.n_rows, 1), kBlock, 0, s>>>(A, x, y, gate); break;
   }
 }
@@ -1011,6 +1066,7 @@ void launch_residual(const Sell<T>& A, const TB* b, const double* bscale, const 
     case 8: k_residual<8, T, TB><<<blocks_lpr(A.n_rows, 8), kBlock, 0, s>>>(A, b, bscale, x, r, gate); break;
     case 16: k_residual<16, T, TB><<<blocks_lpr(A.n_rows, 16), kBlock, 0, s>>>(A, b, bscale, x, r, gate); break;
     case 32: k_residual<32, T, TB><<<blocks_lpr(A.n_rows, 32), kBlock, 0, s>>>(A, b, bscale, x, r, gate); break;
+    case 64: k_residual<64, T, TB><<<blocks_lpr(A.n_rows, 64), kBlock, 0, s>>>(A, b, bscale, x, r, gate); break;
     default: k_residual<1, T, TB><<<blocks_lpr(A.n_rows, 1), kBlock, 0, s>>>(A, b, bscale, x, r, gate); break;
   }
 }
@@ -1024,6 +1080,7 @@ void launch_jacobi_zero(const Sell<T>& A, const T* wd, const TB* b, const double
     case 8: k_jacobi_zero<8, T, TB><<<blocks_lpr(A.n_rows, 8), kBlock, 0, s>>>(A, wd, b, bscale, x, two, gate); break;
     case 16: k_jacobi_zero<16, T, TB><<<blocks_lpr(A.n_rows, 16), kBlock, 0, s>>>(A, wd, b, bscale, x, two, gate); break;
     case 32: k_jacobi_zero<32, T, TB><<<blocks_lpr(A.n_rows, 32), kBlock, 0, s>>>(A, wd, b, bscale, x, two, gate); break;
+    case 64: k_jacobi_zero<64, T, TB><<<blocks_lpr(A.n_rows, 64), kBlock, 0, s>>>(A, wd, b, bscale, x, two, gate); break;
     default: k_jacobi_zero<1, T, TB><<<blocks_lpr(A.n_rows, 1), kBlock, 0, s>>>(A, wd, b, bscale, x, two, gate); break;
   }
 }
@@ -1037,6 +1094,7 @@ void launch_jacobi(const Sell<T>& A, const T* wd, const TB* b, const double* bsc
     case 8: k_jacobi<8, T, TB><<<blocks_lpr(A.n_rows, 8), kBlock, 0, s>>>(A, wd, b, bscale, x_in, x_out, gate); break;
     case 16: k_jacobi<16, T, TB><<<blocks_lpr(A.n_rows, 16), kBlock, 0, s>>>(A, wd, b, bscale, x_in, x_out, gate); break;
     case 32: k_jacobi<32, T, TB><<<blocks_lpr(A.n_rows, 32), kBlock, 0, s>>>(A, wd, b, bscale, x_in, x_out, gate); break;
+    case 64: k_jacobi<64, T, TB><<<blocks_lpr(A.n_rows, 64), kBlock, 0, s>>>(A, wd, b, bscale, x_in, x_out, gate); break;
     default: k_jacobi<1, T, TB><<<blocks_lpr(A.n_rows, 1), kBlock, 0, s>>>(A, wd, b, bscale, x_in, x_out, gate); break;
   }
 }
@@ -1050,7 +1108,42 @@ void launch_restrict_residual(const Sell<T>& Q, const TB* b, const double* bscal
     case 8: k_restrict_residual<8, T, TB><<<blocks_lpr(Q.n_rows, 8), kBlock, 0, s>>>(Q, b, bscale, x, n_fine, bc, gate); break;
     case 16: k_restrict_residual<16, T, TB><<<blocks_lpr(Q.n_rows, 16), kBlock, 0, s>>>(Q, b, bscale, x, n_fine, bc, gate); break;
     case 32: k_restrict_residual<32, T, TB><<<blocks_lpr(Q.n_rows, 32), kBlock, 0, s>>>(Q, b, bscale, x, n_fine, bc, gate); break;
+    case 64: k_restrict_residual<64, T, TB><<<blocks_lpr(Q.n_rows, 64), kBlock, 0, s>>>(Q, b, bscale, x, n_fine, bc, gate); break;
     default: k_restrict_residual<1, T, TB><<<blocks_lpr(Q.n_rows, 1), kBlock, 0, s>>>(Q, b, bscale, x, n_fine, bc, gate); break;
+  }
+}
+
+template <typename T, typename TB>
+void launch_presmooth_restrict(const Sell<T>& A, const T* wd, const Sell<T>& G, const TB* b,
+                               const double* bscale, T* x, T* bc, const DevState* gate,
+                               hipStream_t s) {
+  if (A.n_rows <= 0) return;
+  if (G.lpr != 64) throw_launch("presmooth_restrict: G must use 64 lanes per row");
+  const int nb_a = blocks_lpr(A.n_rows, A.lpr);
+  const int nb = nb_a + blocks_lpr(G.n_rows, 64);
+  switch (A.lpr) {
+    case 4: k_presmooth_restrict<4, T, TB><<<nb, kBlock, 0, s>>>(A, wd, G, b, bscale, x, bc, nb_a, gate); break;
+    case 8: k_presmooth_restrict<8, T, TB><<<nb, kBlock, 0, s>>>(A, wd, G, b, bscale, x, bc, nb_a, gate); break;
+    case 16: k_presmooth_restrict<16, T, TB><<<nb, kBlock, 0, s>>>(A, wd, G, b, bscale, x, bc, nb_a, gate); break;
+    case 32: k_presmooth_restrict<32, T, TB><<<nb, kBlock, 0, s>>>(A, wd, G, b, bscale, x, bc, nb_a, gate); break;
+    case 64: k_presmooth_restrict<64, T, TB><<<nb, kBlock, 0, s>>>(A, wd, G, b, bscale, x, bc, nb_a, gate); break;
+    default: k_presmooth_restrict<1, T, TB><<<nb, kBlock, 0, s>>>(A, wd, G, b, bscale, x, bc, nb_a, gate); break;
+  }
+}
+
+template <typename T, typename TB>
+void launch_prolong_smooth(const Sell<T>& A, const Sell<T>& F, const T* wd, const TB* b,
+                           const double* bscale, const T* x, const T* xc, T* xout,
+                           const DevState* gate, hipStream_t s) {
+  if (A.n_rows <= 0) return;
+  if (F.lpr != A.lpr) throw_launch("prolong_smooth: F must use A's lanes per row");
+  switch (A.lpr) {
+    case 4: k_prolong_smooth<4, T, TB><<<blocks_lpr(A.n_rows, 4), kBlock, 0, s>>>(A, F, wd, b, bscale, x, xc, xout, gate); break;
+    case 8: k_prolong_smooth<8, T, TB><<<blocks_lpr(A.n_rows, 8), kBlock, 0, s>>>(A, F, wd, b, bscale, x, xc, xout, gate); break;
+    case 16: k_prolong_smooth<16, T, TB><<<blocks_lpr(A.n_rows, 16), kBlock, 0, s>>>(A, F, wd, b, bscale, x, xc, xout, gate); break;
+    case 32: k_prolong_smooth<32, T, TB><<<blocks_lpr(A.n_rows, 32), kBlock, 0, s>>>(A, F, wd, b, bscale, x, xc, xout, gate); break;
+    case 64: k_prolong_smooth<64, T, TB><<<blocks_lpr(A.n_rows, 64), kBlock, 0, s>>>(A, F, wd, b, bscale, x, xc, xout, gate); break;
+    default: k_prolong_smooth<1, T, TB><<<blocks_lpr(A.n_rows, 1), kBlock, 0, s>>>(A, F, wd, b, bscale, x, xc, xout, gate); break;
   }
 }
 
@@ -1062,6 +1155,7 @@ void launch_prolong(const Sell<T>& P, const T* xc, T* x, const DevState* gate, h
     case 8: k_prolong<8, T><<<blocks_lpr(P.n_rows, 8), kBlock, 0, s>>>(P, xc, x, gate); break;
     case 16: k_prolong<16, T><<<blocks_lpr(P.n_rows, 16), kBlock, 0, s>>>(P, xc, x, gate); break;
     case 32: k_prolong<32, T><<<blocks_lpr(P.n_rows, 32), kBlock, 0, s>>>(P, xc, x, gate); break;
+    case 64: k_prolong<64, T><<<blocks_lpr(P.n_rows, 64), kBlock, 0, s>>>(P, xc, x, gate); break;
     default: k_prolong<1, T><<<blocks_lpr(P.n_rows, 1), kBlock, 0, s>>>(P, xc, x, gate); break;
   }
 }
@@ -1218,7 +1312,13 @@ void launch_fill(T* a, T v, int n, hipStream_t s) {
   template void launch_jacobi<T, TB>(const Sell<T>&, const T*, const TB*, const double*,      \
                                      const T*, T*, const DevState*, hipStream_t);             \
   template void launch_restrict_residual<T, TB>(const Sell<T>&, const TB*, const double*,     \
-                                                const T*, int, T*, const DevState*, hipStream_t);
+                                                const T*, int, T*, const DevState*, hipStream_t); \
+  template void launch_presmooth_restrict<T, TB>(const Sell<T>&, const T*, const Sell<T>&,     \
+                                                 const TB*, const double*, T*, T*,             \
+                                                 const DevState*, hipStream_t);                \
+  template void launch_prolong_smooth<T, TB>(const Sell<T>&, const Sell<T>&, const T*,         \
+                                             const TB*, const double*, const T*, const T*, T*, \
+                                             const DevState*, hipStream_t);
 
 SD_INST_T(double, double)
 SD_INST_T(float, double)

@@ -80,6 +80,15 @@ void amg_setup_host(const HostCSR& A, const std::vector<int32_t>& comp,
 // in one sparse product, so that a V-cycle level needs no residual vector.
 HostCSR residual_restriction(const HostCSR& A, const HostCSR& R);
 
+// With W = diag(omega / a_ii) and M2 = 2W - W A W (two damped-Jacobi sweeps
+// from zero):
+//   G = R (I - A M2)   restricted residual after the pre-smoothing, from b;
+//   F = P - W A P      coarse correction plus its share of the first
+//                      post-smoothing sweep: x + P xc followed by one sweep is
+//                      x + W (b - A x) + F xc.
+HostCSR presmoothed_restriction(const HostCSR& A, const HostCSR& R, double omega);
+HostCSR smoothed_correction(const HostCSR& A, const HostCSR& P, double omega);
+
 // 32-bit finaliser of MurmurHash3 (public domain).
 inline uint32_t fmix32(uint32_t h) {
   h ^= h >> 16;

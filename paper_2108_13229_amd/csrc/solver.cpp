@@ -47,11 +47,14 @@ void* DeviceMem::get(size_t bytes) {
 // Device format choice: SELL-64 for long matrices with short rows; CSR with
 // 4, 8 or 16 lanes per row for short matrices or long rows (coarse AMG
 // levels and transfer operators), when the kernels that use it allow.
-static int lanes_per_row(const HostCSR& A, bool allow_csr) {
+[[noreturn]] void throw_launch(const char* what) { throw Error(SD_E_INVALID, what); }
+
+static int lanes_per_row(const HostCSR& A, bool allow_csr, int force_lpr) {
+  if (force_lpr > 0) return force_lpr;
   if (!allow_csr || A.n_rows == 0) return 1;
   const double avg = (double)A.nnz() / (double)A.n_rows;
   if (avg <= 12.0 && A.n_rows >= 65536) return 1;
-  return avg <= 16.0 ? 4 : (avg <= 48.0 ? 8 : (avg <= 96.0 ? 16 : 32));
+  return avg <= 16.0 ? 4 : (avg <= 48.0 ? 8 : (avg <= 96.0 ? 16 : (avg <= 192.0 ? 32 : 64)));
 }
 
 template <typename T>
@@ -79,69 +82,52 @@ static Sell<T> copy_sell(const std::vector<int>& ptr, const std::vector<int>& co
   return d;
 }
 
-// Upload as SELL-64 (one lane per row) or, for hierarchy matrices with few or
-// long rows (allow_csr), as CSR read by lpr lanes per row.  Hierarchy
-// matrices whose rows pad to one common width at modest cost get that
-// uniform width, which spares the kernels the row-pointer load.  Padding
-// entries repeat the row's last column with value 0.
+// Upload as SELL-C: slices of C = 64 / lpr rows, entry k of row r of slice s
+// at sptr[s] + k C + (r - s C), slice width = longest row of the slice rounded
+// up to a multiple of lpr (padding repeats the row's last column with value
+// 0).  lpr = 1 (SELL-64) unless allow_csr picks more lanes for matrices with
+// few or long rows.  Hierarchy matrices whose slices pad to one common width
+// at modest cost get that uniform width, which spares the kernels the slice
+// pointer load.
 template <typename T>
-Sell<T> upload_sell(const HostCSR& A, DeviceMem& mem, hipStream_t s, bool allow_csr) {
+Sell<T> upload_sell(const HostCSR& A, DeviceMem& mem, hipStream_t s, bool allow_csr,
+                    int force_lpr) {
   const int64_t n = A.n_rows;
-  const int lpr = lanes_per_row(A, allow_csr);
-  int64_t maxlen = 0;
-  for (int64_t r = 0; r < n; ++r) maxlen = std::max(maxlen, A.rowptr[r + 1] - A.rowptr[r]);
-  if (lpr > 1) {
-    const int64_t w = (maxlen + lpr - 1) / lpr * lpr;
-    const bool uniform = w > 0 && (double)(n * w) <= 2.0 * (double)A.nnz();
-    if (uniform) {
-      if (n * w >= ((int64_t)1 << 31)) throw Error(SD_E_INVALID, "matrix too large for int32 CSR");
-      std::vector<int> col((size_t)(n * w), 0);
-      std::vector<T> val((size_t)(n * w), (T)0);
-      for (int64_t r = 0; r < n; ++r) {
-        const int64_t beg = A.rowptr[r], len = A.rowptr[r + 1] - beg;
-        for (int64_t k = 0; k < w; ++k) {
-          col[r * w + k] = k < len ? A.col[beg + k] : (len > 0 ? A.col[beg + len - 1] : 0);
-          val[r * w + k] = k < len ? (T)A.val[beg + k] : (T)0;
-        }
-      }
-      return copy_sell<T>({}, col, val, n, A.n_cols, lpr, (int)w, mem, s);
-    }
-    if (A.nnz() >= ((int64_t)1 << 31)) throw Error(SD_E_INVALID, "matrix too large for int32 CSR");
-    std::vector<int> rp((size_t)n + 1);
-    for (int64_t r = 0; r <= n; ++r) rp[r] = (int)A.rowptr[r];
-    std::vector<T> val((size_t)A.nnz());
-    for (int64_t k = 0; k < A.nnz(); ++k) val[k] = (T)A.val[k];
-    return copy_sell<T>(rp, A.col, val, n, A.n_cols, lpr, 0, mem, s);
-  }
-  const int64_t ns = (n + 63) / 64;
+  const int lpr = lanes_per_row(A, allow_csr, force_lpr);
+  const int64_t C = 64 / lpr;
+  const int64_t ns = (n + C - 1) / C;
   std::vector<int64_t> width((size_t)ns, 0);
-  int64_t tot = 0;
+  int64_t tot = 0, wmax = 0;
   for (int64_t sl = 0; sl < ns; ++sl) {
-    for (int64_t r = sl * 64; r < std::min(n, sl * 64 + 64); ++r)
-      width[sl] = std::max(width[sl], A.rowptr[r + 1] - A.rowptr[r]);
-    tot += 64 * width[sl];
+    int64_t w = 0;
+    for (int64_t r = sl * C; r < std::min(n, sl * C + C); ++r)
+      w = std::max(w, A.rowptr[r + 1] - A.rowptr[r]);
+    w = (w + lpr - 1) / lpr * lpr;
+    width[sl] = w;
+    wmax = std::max(wmax, w);
+    tot += C * w;
   }
-  const bool uniform = allow_csr && maxlen > 0 && (double)(64 * ns * maxlen) <= 1.3 * (double)tot;
+  const bool uniform = allow_csr && wmax > 0 && (double)(C * ns * wmax) <= 1.3 * (double)tot;
   if (uniform) {
-    for (auto& w : width) w = maxlen;
-    tot = 64 * ns * maxlen;
+    for (auto& w : width) w = wmax;
+    tot = C * ns * wmax;
   }
-  if (tot >= ((int64_t)1 << 31)) throw Error(SD_E_INVALID, "matrix too large for SELL-64");
+  if (tot >= ((int64_t)1 << 31)) throw Error(SD_E_INVALID, "matrix too large for int32 SELL");
   std::vector<int> sptr((size_t)ns + 1, 0);
-  for (int64_t sl = 0; sl < ns; ++sl) sptr[sl + 1] = (int)(sptr[sl] + 64 * width[sl]);
+  for (int64_t sl = 0; sl < ns; ++sl) sptr[sl + 1] = (int)(sptr[sl] + C * width[sl]);
   std::vector<int> col((size_t)tot, 0);
   std::vector<T> val((size_t)tot, (T)0);
   for (int64_t sl = 0; sl < ns; ++sl) {
     const int64_t w = width[sl];
-    for (int64_t lane = 0; lane < 64; ++lane) {
-      const int64_t r = sl * 64 + lane;
+    for (int64_t ri = 0; ri < C; ++ri) {
+      const int64_t r = sl * C + ri;
       int64_t len = 0, beg = 0;
       if (r < n) {
         beg = A.rowptr[r];
         len = A.rowptr[r + 1] - beg;
       }
       for (int64_t k = 0; k < w; ++k) {
-        const int64_t e = sptr[sl] + 64 * k + lane;
+        const int64_t e = sptr[sl] + C * k + ri;
         if (k < len) {
           col[e] = A.col[beg + k];
           val[e] = (T)A.val[beg + k];
@@ -152,11 +138,11 @@ Sell<T> upload_sell(const HostCSR& A, DeviceMem& mem, hipStream_t s, bool allow_
       }
     }
   }
-  return copy_sell<T>(sptr, col, val, n, A.n_cols, 1, uniform ? (int)maxlen : 0, mem, s);
+  return copy_sell<T>(sptr, col, val, n, A.n_cols, lpr, uniform ? (int)wmax : 0, mem, s);
 }
 
-template Sell<double> upload_sell<double>(const HostCSR&, DeviceMem&, hipStream_t, bool);
-template Sell<float> upload_sell<float>(const HostCSR&, DeviceMem&, hipStream_t, bool);
+template Sell<double> upload_sell<double>(const HostCSR&, DeviceMem&, hipStream_t, bool, int);
+template Sell<float> upload_sell<float>(const HostCSR&, DeviceMem&, hipStream_t, bool, int);
 
 // ------------------------------------------------------------ host setup
 static double diag_at(const HostCSR& A, int64_t r) {
@@ -283,9 +269,13 @@ int Solver::solve(const double* b, double* x, int use_x0, sd_stats* stats, hipSt
 // ===================================================== precision-specific
 namespace {
 
+// Levels below this size are latency bound: their smoothing is fused with
+// the transfers (fewer, wider launches); larger levels keep separate passes.
+constexpr int64_t kFuseRows = 65536;
+
 template <typename T>
-void upload_hierarchy(const HostHierarchy& h, DevHierarchy<T>& d, double omega, DeviceMem& mem,
-                      hipStream_t s) {
+void upload_hierarchy(const HostHierarchy& h, DevHierarchy<T>& d, double omega, int nu_pre,
+                      int nu_post, DeviceMem& mem, hipStream_t s) {
   d.lev.resize(h.levels.size());
   for (size_t l = 0; l < h.levels.size(); ++l) {
     const HostLevel& H = h.levels[l];
@@ -304,11 +294,19 @@ void upload_hierarchy(const HostHierarchy& h, DevHierarchy<T>& d, double omega, 
       // On the finest level the stencil rows read x coalesced (one lane per
       // row), so the residual and the restriction stay separate there; on
       // coarser levels, where launches are latency bound, they are fused.
-      if (l == 0) {
+      D.fuse_pre = l > 0 && nu_pre == 2;
+      D.fuse_post = nu_post >= 1 && (l > 0 || H.A.n_rows < kFuseRows);
+      if (D.fuse_pre) {
+        D.G = upload_sell<T>(presmoothed_restriction(H.A, H.R, omega), mem, s, true, 64);
+      } else if (l == 0) {
         D.R = upload_sell<T>(H.R, mem, s, true);
         D.r = mem.array<T>((size_t)D.n);
       } else {
         D.Q = upload_sell<T>(residual_restriction(H.A, H.R), mem, s, true);
+      }
+      if (D.fuse_post) {
+        D.F = upload_sell<T>(smoothed_correction(H.A, H.P, omega), mem, s, true, D.A.lpr);
+        D.P = Sell<T>{};
       }
     }
     SD_HIP(hipStreamSynchronize(s));
@@ -336,7 +334,8 @@ class PrecImpl : public PrecBase {
     DeviceMem& mem = *S.mem;
     nu_pre = S.opts.amg.nu_pre;
     nu_post = S.opts.amg.nu_post;
-    for (int b = 0; b < 2; ++b) upload_hierarchy<T>(S.hh[b], H[b], S.opts.amg.omega, mem, s);
+    for (int b = 0; b < 2; ++b)
+      upload_hierarchy<T>(S.hh[b], H[b], S.opts.amg.omega, nu_pre, nu_post, mem, s);
     Cf = upload_sell<T>(S.Cf, mem, s);
     if constexpr (std::is_same<T, double>::value)
       Aarn = S.A64;
@@ -368,25 +367,36 @@ class PrecImpl : public PrecBase {
     }
     T* cur = x;
     T* other = L.tmp;
-    if (nu_pre == 0) {
-      launch_fill<T>(cur, (T)0, L.n, s);
+    DevLevel<T>& C = h.lev[l + 1];
+    if (L.fuse_pre) {
+      launch_presmooth_restrict<T, TB>(L.A, L.wd, L.G, b, bs, cur, C.b, gate, s);
     } else {
-      launch_jacobi_zero<T, TB>(L.A, L.wd, b, bs, cur, nu_pre >= 2 ? 1 : 0, gate, s);
-      for (int k = 2; k < nu_pre; ++k) {
-        launch_jacobi<T, TB>(L.A, L.wd, b, bs, cur, other, gate, s);
-        std::swap(cur, other);
+      if (nu_pre == 0) {
+        launch_fill<T>(cur, (T)0, L.n, s);
+      } else {
+        launch_jacobi_zero<T, TB>(L.A, L.wd, b, bs, cur, nu_pre >= 2 ? 1 : 0, gate, s);
+        for (int k = 2; k < nu_pre; ++k) {
+          launch_jacobi<T, TB>(L.A, L.wd, b, bs, cur, other, gate, s);
+          std::swap(cur, other);
+        }
+      }
+      if (l == 0) {
+        launch_residual<T, TB>(L.A, b, bs, cur, L.r, gate, s);
+        launch_spmv<T, T, T>(L.R, L.r, C.b, gate, s);
+      } else {
+        launch_restrict_residual<T, TB>(L.Q, b, bs, cur, L.n, C.b, gate, s);
       }
     }
-    DevLevel<T>& C = h.lev[l + 1];
-    if (l == 0) {
-      launch_residual<T, TB>(L.A, b, bs, cur, L.r, gate, s);
-      launch_spmv<T, T, T>(L.R, L.r, C.b, gate, s);
-    } else {
-      launch_restrict_residual<T, TB>(L.Q, b, bs, cur, L.n, C.b, gate, s);
-    }
     vcycle<T>(blk, l + 1, C.b, nullptr, C.x, gate, s);
-    launch_prolong<T>(L.P, C.x, cur, gate, s);
-    for (int k = 0; k < nu_post; ++k) {
+    int k0 = 0;
+    if (L.fuse_post) {
+      launch_prolong_smooth<T, TB>(L.A, L.F, L.wd, b, bs, cur, C.x, other, gate, s);
+      std::swap(cur, other);
+      k0 = 1;
+    } else {
+      launch_prolong<T>(L.P, C.x, cur, gate, s);
+    }
+    for (int k = k0; k < nu_post; ++k) {
       const bool timed = prof_jacobi_ev && blk == 0 && l == 0 && k + 1 == nu_post;
       if (timed) SD_HIP(hipEventRecord(prof_jacobi_ev[0], s));
       launch_jacobi<T, TB>(L.A, L.wd, b, bs, cur, other, gate, s);

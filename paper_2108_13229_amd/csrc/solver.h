@@ -45,6 +45,9 @@ struct DevLevel {
   Sell<T> A, P;
   Sell<T> R;           // restriction (finest level)
   Sell<T> Q;           // [R | -R A]: restricted residual from [b; x] (coarser levels)
+  Sell<T> G;           // R (I - A M2): restricted residual after pre-smoothing, from b
+  Sell<T> F;           // P - W A P: correction fused with the first post-sweep
+  bool fuse_pre = false, fuse_post = false;
   T* wd = nullptr;     // omega / a_ii
   T* x = nullptr;      // iterate (levels >= 1)
   T* tmp = nullptr;
@@ -149,7 +152,8 @@ class Solver {
 
 // SELL construction on the host and upload.
 template <typename T>
-Sell<T> upload_sell(const HostCSR& A, DeviceMem& mem, hipStream_t s, bool allow_csr = false);
+Sell<T> upload_sell(const HostCSR& A, DeviceMem& mem, hipStream_t s, bool allow_csr = false,
+                    int force_lpr = 0);
 
 std::unique_ptr<PrecBase> make_prec_fp64(Solver& S, hipStream_t s);
 std::unique_ptr<PrecBase> make_prec_fp32(Solver& S, hipStream_t s);
