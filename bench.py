@@ -1,17 +1,22 @@
 """Benchmark: coupled Stokes-Darcy solves/s on one MI355X.
 
-Workload (the headline configuration): 512 x 256 cells in each subdomain
-(N = 524,288 unknowns), lognormal permeability ln K ~ N(ln 1e-4, 1) with an
-8-cell Gaussian correlation (seed 1), viscosity 1e-3, parabolic inflow of
-peak 1e-2, zero-traction outflow; block-Gauss-Seidel preconditioned
-FGMRES(60) with one smoothed-aggregation V-cycle per velocity and Darcy block
-and the viscosity-scaled pressure-mass Schur block, to relative residual
-1e-8.  One step = one complete solve from x = 0 with the matrix and the AMG
-hierarchy resident in HBM.  FP64 is the headline; the mixed-precision solver
-(FP32 preconditioner and Arnoldi product, FP64 outer residual) is reported
-beside it.  Inputs are synthetic and seeded.
+Workload C1 (default, the headline configuration): 512 x 256 cells in each
+subdomain (N = 524,288 unknowns), lognormal permeability
+ln K ~ N(ln 1e-4, 1) with an 8-cell Gaussian correlation (seed 1), viscosity
+1e-3, parabolic inflow of peak 1e-2, zero-traction outflow;
+block-Gauss-Seidel preconditioned FGMRES(60) with one smoothed-aggregation
+V-cycle per velocity and Darcy block and the viscosity-scaled pressure-mass
+Schur block, to relative residual 1e-8.  One step = one complete solve from
+x = 0 with the matrix and the AMG hierarchy resident in HBM.  FP64 is the
+headline; the mixed-precision solvers are reported beside it ("mixed": FP32
+preconditioner, FP64 Arnoldi product and outer residual; "mixed32": the
+Arnoldi product in FP32 too).  --config C2: the same physics at 1024 x 512
+(seed 2, N = 2,097,152), mixed precision as the headline.  Inputs are
+synthetic and seeded.  With the CPU leg on, the oracle also provides an FP64
+reference solution (its FGMRES to relative residual 1e-12) against which the
+per-block errors of every GPU solution are reported.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config C1|C2] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -30,7 +35,11 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = ("512x256 free-flow + 512x256 porous cells (N=524288), lognormal K seed 1, "
             "BGS(SA-AMG V-cycle, mu*Mp^-1, SA-AMG V-cycle) + FGMRES(m), rel. residual 1e-8")
-ROOFLINE_KERNEL = "k_arn_project<double, double>"
+ROOFLINE_KERNEL = {"fp64": "k_arn_project<double, double>",
+                   "mixed": "k_arn_project<double, float>",
+                   "mixed32": "k_arn_project<float, float>"}
+WORKLOAD_C2 = ("1024x512 free-flow + 1024x512 porous cells (N=2097152), lognormal K seed 2, "
+               "BGS(SA-AMG V-cycle, mu*Mp^-1, SA-AMG V-cycle) + FGMRES(m), rel. residual 1e-8")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_arnoldi_spmv_c1.json")
 
 
@@ -39,12 +48,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--nx", type=int, default=512)
-    ap.add_argument("--ny", type=int, default=256)
-    ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--config", default="C1", choices=["C1", "C2"])
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the CPU oracle leg (baseline timing and reference solution)")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--precision", default=None, choices=["fp64", "mixed", "mixed32"],
+                    help="headline precision (default: fp64 for C1, mixed for C2)")
     ap.add_argument("--restart", type=int, default=60)
     ap.add_argument("--roofline-solves", type=int, default=3)
     ap.add_argument("--serving", type=int, default=0,
@@ -71,10 +80,18 @@ def run_solves(S, steps, warmup):
         if k >= warmup:
             lat.append(dt)
             its.append(st["iters"])
-    return np.array(lat), its, st, x
+    return np.array(lat), its, st, x.cpu().numpy()
 
 
-def roofline(S, n_solves):
+def block_errors(x, ref, off):
+    """Relative error per block: velocity (u, v), free-flow and porous pressure."""
+    out = []
+    for lo, hi in ((off[0], off[2]), (off[2], off[3]), (off[3], off[4])):
+        out.append(float(np.linalg.norm(x[lo:hi] - ref[lo:hi]) / np.linalg.norm(ref[lo:hi])))
+    return out
+
+
+def roofline(S, n_solves, precision):
     """Dominant kernel (w = A z_j fused with the first Gram-Schmidt dot pass):
     its launches are bracketed by HIP events on the solver's stream during
     n_solves solves of the same workload; achieved = algorithmic bytes of
@@ -98,7 +115,7 @@ def roofline(S, n_solves):
         traffic = None
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": ROOFLINE_KERNEL, "launches": r["launches"],
+            "kernel": ROOFLINE_KERNEL[precision], "launches": r["launches"],
             "avg_launch_us": 1e6 * r["seconds"] / r["launches"],
             "alg_bytes_per_launch": r["bytes"] / r["launches"]}
 
@@ -197,24 +214,31 @@ def serving(sd, args):
     print(json.dumps(out))
 
 
-def cpu_baseline(p, restart):
+def cpu_baseline(p, restart, timed=True):
     """The oracle's FP64 FGMRES with the same preconditioner, one solve,
-    single-threaded (setup excluded; timed separately)."""
+    single-threaded (setup excluded; timed separately); then, with every
+    host thread, the oracle's reference solution (FGMRES to relative
+    residual 1e-12) for the per-block errors of the GPU solutions."""
     from threadpoolctl import threadpool_limits
     from oracle import krylov, precond
     from oracle.assemble import assemble
+    base = None
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         a = assemble(p)
         M = precond.build(p, a, "BGS")
         t_setup = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        r = krylov.fgmres(a.A, a.b, M, tol=1e-8, m=restart)
-        t_solve = time.perf_counter() - t0
-    return dict(value=1.0 / t_solve, unit="solves/s", cores=1, kind="oracle",
-                sample=f"one full FP64 solve of the same workload (oracle FGMRES, "
-                       f"{r.iters} iterations, {t_solve:.1f} s; assembly+AMG setup "
-                       f"{t_setup:.1f} s not included), 1 thread")
+        if timed:
+            t0 = time.perf_counter()
+            r = krylov.fgmres(a.A, a.b, M, tol=1e-8, m=restart)
+            t_solve = time.perf_counter() - t0
+            base = dict(value=1.0 / t_solve, unit="solves/s", cores=1, kind="oracle",
+                        sample=f"one full FP64 solve of the same workload (oracle FGMRES, "
+                               f"{r.iters} iterations, {t_solve:.1f} s; assembly+AMG setup "
+                               f"{t_setup:.1f} s not included), 1 thread")
+    ref = krylov.fgmres(a.A, a.b, M, tol=1e-12, m=restart, maxit=5000)
+    rel = float(np.linalg.norm(a.b - a.A @ ref.x) / np.linalg.norm(a.b))
+    return base, ref.x, f"oracle FP64 FGMRES to relative residual {rel:.1e} ({ref.iters} iterations)"
 
 
 def main():
@@ -224,7 +248,7 @@ def main():
               "the solver has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     import torch
-    from sdinputs import channel_problem
+    from sdinputs import config_problem
     from paper_2108_13229_amd import sd
 
     if not torch.cuda.is_available():
@@ -233,31 +257,36 @@ def main():
     if args.serving:
         serving(sd, args)
         return
-    p = channel_problem(args.nx, args.ny, seed=args.seed)
+    p = config_problem(args.config)
     if args.counter_run:
         counter_run(sd, p, args.restart)
         return
+    headline = args.precision or ("fp64" if args.config == "C1" else "mixed")
     t0 = time.perf_counter()
     P = sd.Problem(p, device=True)
     t_asm = time.perf_counter() - t0
-    res = {}
+    res, xs = {}, {}
     roof = None
-    for prec in (["fp64"] if args.no_mixed else ["fp64", "mixed"]):
+    precs = ["fp64"] if args.no_mixed else ["fp64", "mixed", "mixed32"]
+    if headline not in precs:
+        precs.append(headline)
+    for prec in precs:
         t0 = time.perf_counter()
         S = sd.Solver(P, precond="BGS", schur="mass", tol=1e-8, restart=args.restart,
                       precision=prec)
         t_setup = time.perf_counter() - t0
         lat, its, st, x = run_solves(S, args.steps, args.warmup)
+        xs[prec] = x
         res[prec] = dict(solves_per_s=float(len(lat) / lat.sum()),
                          ms_per_solve=float(1e3 * lat.mean()),
                          p50_ms=float(1e3 * np.percentile(lat, 50)),
                          p99_ms=float(1e3 * np.percentile(lat, 99)),
                          iters=int(np.median(its)), restarts=st["restarts"],
                          rel_res=st["rel_res"], setup_s=t_setup)
-        if prec == args.precision and args.roofline_solves > 0:
-            roof = roofline(S, args.roofline_solves)
+        if prec == headline and args.roofline_solves > 0:
+            roof = roofline(S, args.roofline_solves, prec)
         S.close()
-    head = res[args.precision]
+    head = res[headline]
     out = {
         "metric": "Stokes-Darcy solves/s to rel. residual 1e-8 (mixed vs FP64), p50/p99 latency",
         "value": head["solves_per_s"],
@@ -269,20 +298,40 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "dtype": "f64" if headline == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD if (args.nx, args.ny) == (512, 256)
-                   else f"{args.nx}x{args.ny} channel", "N": P.N, "nnz": P.nnz,
-                   "assembly_s": t_asm},
+        "config": {"workload": WORKLOAD if args.config == "C1" else WORKLOAD_C2,
+                   "N": P.N, "nnz": P.nnz, "assembly_s": t_asm, "precision": headline},
         "p50_ms": head["p50_ms"],
         "p99_ms": head["p99_ms"],
         "restart": args.restart,
         "fp64": res.get("fp64"),
         "mixed": res.get("mixed"),
+        "mixed32": res.get("mixed32"),
         "roofline": roof,
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(p, args.restart)
+        base, ref, ref_kind = cpu_baseline(p, args.restart, timed=args.config == "C1")
+        if base is not None:
+            out["cpu_baseline"] = base
+        off = P.block_off
+        acc = {"reference": ref_kind, "blocks": ["velocity", "free-flow pressure",
+                                                 "porous pressure"]}
+        for prec, x in xs.items():
+            acc[prec] = block_errors(x, ref, off)
+        acc["mixed_vs_fp64"] = block_errors(xs.get("mixed", xs[headline]), xs["fp64"], off)
+        # tolerance at which the FP64 solve's error is <= 1e-8 in every block
+        need = None
+        for tol in (1e-9, 1e-10, 1e-11):
+            S = sd.Solver(P, precond="BGS", schur="mass", tol=tol, restart=args.restart)
+            x, st, rc = S.solve()
+            e = block_errors(x.cpu().numpy(), ref, off)
+            S.close()
+            if max(e) <= 1e-8:
+                need = {"tol": tol, "iters": st["iters"], "errors": e}
+                break
+        acc["fp64_tol_for_1e-8_error"] = need
+        out["accuracy"] = acc
     print(json.dumps(out))
 
 

@@ -129,7 +129,13 @@ int sd_problem_csr(const sd_problem* pb, const int64_t** rowptr,
 enum { SD_KRYLOV_FGMRES = 0, SD_KRYLOV_BICGSTAB = 1 };
 enum { SD_PREC_BJ = 0, SD_PREC_BGS = 1 };
 enum { SD_SCHUR_IDENTITY = 0, SD_SCHUR_MASS = 1 };
-enum { SD_PRECISION_FP64 = 0, SD_PRECISION_MIXED = 1 };
+/* MIXED: preconditioner (AMG hierarchies, smoothers, block sweeps) in FP32
+ * with FP32 accumulation; Arnoldi product, basis, Hessenberg, x and the
+ * restart residual in FP64 (flexible GMRES absorbs the FP32 preconditioner).
+ * MIXED32: the Arnoldi product w = A z in FP32 as well; a cycle then also
+ * ends once its implicit residual estimate has dropped by 1e-6, the accuracy
+ * an FP32 product can support, and the FP64 restart residual refines. */
+enum { SD_PRECISION_FP64 = 0, SD_PRECISION_MIXED = 1, SD_PRECISION_MIXED32 = 2 };
 enum { SD_AMG_PLAIN = 0, SD_AMG_SMOOTHED = 1 };
 
 typedef struct {
@@ -139,7 +145,7 @@ typedef struct {
   double tol;        /* relative true FP64 residual ||b-Ax||/||b||             */
   int precond;       /* SD_PREC_BJ | SD_PREC_BGS                               */
   int schur;         /* middle block: identity or mu * M_p^-1                  */
-  int precision;     /* SD_PRECISION_FP64 | SD_PRECISION_MIXED                 */
+  int precision;     /* SD_PRECISION_FP64 | _MIXED | _MIXED32                  */
   int amg;           /* SD_AMG_SMOOTHED (default) | SD_AMG_PLAIN               */
   int mis;           /* root independent set distance: 1 or 2 (default 2)     */
   double theta;      /* strength threshold, default 0.08                       */

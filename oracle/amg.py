@@ -17,12 +17,17 @@ oracle fixes every step so that the hierarchy is reproducible bit-for-bit:
    synchronous sweep, the aggregate of the strong neighbour with the largest
    |a_ij| among the nodes aggregated so far (ties: smallest index);
 4. prolongation: tentative P_t[i, agg(i)] = 1.  "plain" (non-smooth, the
-   paper's choice) uses P = P_t; "smoothed" uses
-   P = (I - w_p D_F^-1 A_F) P_t with A_F the diagonal plus strong entries of
-   A, w_p = 4 / (3 rho_G) and rho_G = max_i sum_j |a_F,ij| / |a_ii| the
-   Gershgorin bound of D_F^-1 A_F;  entry P[i, J] = [J == agg(i)] -
-   (w_p / a_ii) * (sum over the row's A_F entries a_ij with agg(j) = J, in
-   ascending j);
+   paper's choice) uses P = P_t; "smoothed" uses the smoothed-aggregation
+   prolongator of Vanek, Mandel and Brezina (Computing 56, 1996),
+   P = (I - w_p D_F^-1 A_F) P_t, with the filtered matrix A_F = strong
+   entries of A plus a diagonal into which the weak entries are lumped,
+   a_F,ii = a_ii + sum of the row's weak a_ij (ascending j), so that A_F and
+   A have the same row sums; w_p = 4 / (3 rho_G), rho_G = max_i sum_j
+   |a_F,ij| / |a_F,ii| the Gershgorin bound of D_F^-1 A_F; entry
+   P[i, J] = [J == agg(i)] - (w_p / a_F,ii) * (sum over the row's A_F
+   entries with agg(j) = J, in ascending j).  A row whose lumped diagonal
+   vanishes (|a_F,ii| <= 1e-8 |a_ii|: every connection weak and zero row
+   sum) keeps its tentative row and is left out of rho_G;
 5. restriction R = P^T; Galerkin A_c = R (A P), each product summed in the
    row-by-row (Gustavson) order: (A P)[i, J] accumulates a_ik p_kJ over
    ascending k, then over P's row k in ascending J; A_c[I, J] accumulates
@@ -187,16 +192,26 @@ def smoothed_prolongator(A: sp.csr_matrix, comp: np.ndarray, theta: float,
     A = A.tocsr()
     n = A.shape[0]
     rows = _rows_of(A)
-    keep = strong_mask(A, comp, theta) | (rows == A.indices)
-    d = A.diagonal()
-    # Gershgorin bound of D^-1 A_F, row sums in stored (ascending) order
+    isdiag = rows == A.indices
+    strong = strong_mask(A, comp, theta)
+    weak = ~strong & ~isdiag
+    aii = A.diagonal()
+    # lumped diagonal: a_ii plus the row's weak entries in stored (ascending) order
+    dF = aii.copy()
+    np.add.at(dF, rows[weak], A.data[weak])
+    valid = np.abs(dF) > 1e-8 * np.abs(aii)
+    keep = strong | isdiag
+    vals = A.data.copy()
+    vals[isdiag] = dF[rows[isdiag]]
+    # Gershgorin bound of D_F^-1 A_F over the smoothed rows, stored order
     absum = np.zeros(n)
-    np.add.at(absum, rows[keep], np.abs(A.data[keep]))
-    rho = float(np.max(absum / np.abs(d)))
-    wp = 4.0 / (3.0 * rho)
-    r, c, a = rows[keep], A.indices[keep], A.data[keep]
+    np.add.at(absum, rows[keep], np.abs(vals[keep]))
+    rho = float(np.max(absum[valid] / np.abs(dF[valid]))) if valid.any() else 0.0
+    wp = 4.0 / (3.0 * rho) if rho > 0.0 else 0.0
+    sel = keep & valid[rows]
+    r, c, a = rows[sel], A.indices[sel], vals[sel]
     J = agg[c]
-    # per (i, J): sum of a_ij over ascending j (entries are in CSR order)
+    # per (i, J): sum of a_F,ij over ascending j (entries are in CSR order)
     key = r * n_c + J
     ukey, inv = np.unique(key, return_inverse=True)
     s = np.zeros(ukey.size)
@@ -204,7 +219,14 @@ def smoothed_prolongator(A: sp.csr_matrix, comp: np.ndarray, theta: float,
     ri = ukey // n_c
     cj = ukey % n_c
     base = (cj == agg[ri]).astype(np.float64)
-    val = base - (wp / d[ri]) * s
+    val = base - (wp / dF[ri]) * s
+    # rows left unsmoothed keep P_t
+    fixed = np.flatnonzero(~valid)
+    ri = np.concatenate([ri, fixed])
+    cj = np.concatenate([cj, agg[fixed]])
+    val = np.concatenate([val, np.ones(fixed.size)])
+    order = np.lexsort((cj, ri))
+    ri, cj, val = ri[order], cj[order], val[order]
     indptr = np.zeros(n + 1, dtype=np.int64)
     np.add.at(indptr, ri + 1, 1)
     indptr = np.cumsum(indptr)

@@ -13,8 +13,10 @@
 //              sweep, the aggregate of their aggregated strong neighbour of
 //              largest |a_ij| (ties: smallest index);
 //   transfer   tentative P[i, agg(i)] = 1, or smoothed
-//              P = (I - w D^-1 A_F) P_t with A_F = diagonal + strong entries,
-//              w = 4 / (3 rho), rho = max_i sum_j |a_F,ij| / |a_ii|;
+//              P = (I - w D_F^-1 A_F) P_t, A_F = strong entries + a diagonal
+//              with the weak entries lumped in (equal row sums),
+//              w = 4 / (3 rho), rho = max_i sum_j |a_F,ij| / |a_F,ii|; rows
+//              whose lumped diagonal vanishes keep P_t;
 //              R = P^T; A_c = R (A P) with Gustavson-ordered sums;
 //   coarsest   dense blocked LU with partial pivoting and explicit inverse.
 #include <algorithm>
@@ -184,32 +186,53 @@ HostCSR smoothed(const HostCSR& A, const std::vector<uint8_t>& strong,
                  const std::vector<double>& d, const std::vector<int32_t>& agg,
                  int64_t n_c) {
   const int64_t n = A.n_rows;
+  // filtered diagonal: a_ii plus the row's weak entries in stored order
+  std::vector<double> dF(d);
+  std::vector<uint8_t> valid((size_t)n);
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k)
+      if (!strong[k] && A.col[k] != i) dF[i] = dF[i] + A.val[k];
+    valid[i] = std::fabs(dF[i]) > 1e-8 * std::fabs(d[i]);
+  }
   double rho = 0.0;
   for (int64_t i = 0; i < n; ++i) {
+    if (!valid[i]) continue;
     double s = 0.0;
-    for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k)
-      if (strong[k] || A.col[k] == i) s = s + std::fabs(A.val[k]);
-    const double q = s / std::fabs(d[i]);
+    for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) {
+      if (A.col[k] == i)
+        s = s + std::fabs(dF[i]);
+      else if (strong[k])
+        s = s + std::fabs(A.val[k]);
+    }
+    const double q = s / std::fabs(dF[i]);
     if (q > rho) rho = q;
   }
-  const double wp = 4.0 / (3.0 * rho);
+  const double wp = rho > 0.0 ? 4.0 / (3.0 * rho) : 0.0;
   HostCSR P;
   P.n_rows = n;
   P.n_cols = n_c;
   P.rowptr.assign(1, 0);
   std::map<int32_t, double> acc;
   for (int64_t i = 0; i < n; ++i) {
+    if (!valid[i]) {
+      P.col.push_back(agg[i]);
+      P.val.push_back(1.0);
+      P.rowptr.push_back((int64_t)P.col.size());
+      continue;
+    }
     acc.clear();
     for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) {
-      if (!(strong[k] || A.col[k] == i)) continue;
+      const bool diag = A.col[k] == i;
+      if (!(strong[k] || diag)) continue;
+      const double v = diag ? dF[i] : A.val[k];
       const int32_t J = agg[A.col[k]];
       auto it = acc.find(J);
       if (it == acc.end())
-        acc.emplace(J, 0.0 + A.val[k]);
+        acc.emplace(J, 0.0 + v);
       else
-        it->second = it->second + A.val[k];
+        it->second = it->second + v;
     }
-    const double coef = wp / d[i];
+    const double coef = wp / dF[i];
     for (auto& e : acc) {
       const double base = (e.first == agg[i]) ? 1.0 : 0.0;
       P.col.push_back(e.first);

@@ -1348,6 +1348,9 @@ template void launch_arnoldi_step<double, double>(const Sell<double>&, const dou
 template void launch_arnoldi_step<float, float>(const Sell<float>&, const float*, double*,
                                                 double*, int64_t, int, DevState*, double*,
                                                 HostFlags*, hipStream_t, int, hipEvent_t*);
+template void launch_arnoldi_step<double, float>(const Sell<double>&, const float*, double*,
+                                                double*, int64_t, int, DevState*, double*,
+                                                HostFlags*, hipStream_t, int, hipEvent_t*);
 template void launch_update_x<double>(double*, const double*, int64_t, int, DevState*,
                                       hipStream_t);
 template void launch_update_x<float>(double*, const float*, int64_t, int, DevState*,

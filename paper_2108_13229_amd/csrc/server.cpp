@@ -67,9 +67,9 @@ int64_t unknowns(const sd_grid& g, int ff_right) {
 size_t estimate_bytes(const sd_grid& g, int ff_right, const sd_solver_opts& o) {
   const double N = (double)unknowns(g, ff_right);
   const double nnz = 8.0 * N;
-  const double tb = o.precision == SD_PRECISION_MIXED ? 4.0 : 8.0;
+  const double tb = o.precision != SD_PRECISION_FP64 ? 4.0 : 8.0;
   double b = nnz * 12.0 * 1.2;                                  // FP64 A (SELL)
-  if (o.precision == SD_PRECISION_MIXED) b += nnz * 8.0 * 1.2;  // FP32 copy
+  if (o.precision == SD_PRECISION_MIXED32) b += nnz * 8.0 * 1.2;  // FP32 copy
   b += 2.5 * nnz * (4.0 + tb) * 1.2;                            // hierarchies, P, R
   b += 12.0 * N * tb;                                           // level work vectors
   const double nc = std::min(N, (double)o.coarse_max);

@@ -163,7 +163,8 @@ void Solver::setup_host(HostProblem* p, const sd_solver_opts* o) {
   if (!(so.tol > 0.0) || so.maxit < 1) throw Error(SD_E_INVALID, "tol > 0 and maxit >= 1 required");
   if (so.precond != SD_PREC_BJ && so.precond != SD_PREC_BGS) throw Error(SD_E_INVALID, "precond");
   if (so.schur != SD_SCHUR_IDENTITY && so.schur != SD_SCHUR_MASS) throw Error(SD_E_INVALID, "schur");
-  if (so.precision != SD_PRECISION_FP64 && so.precision != SD_PRECISION_MIXED)
+  if (so.precision != SD_PRECISION_FP64 && so.precision != SD_PRECISION_MIXED &&
+      so.precision != SD_PRECISION_MIXED32)
     throw Error(SD_E_INVALID, "precision");
   if (so.krylov != SD_KRYLOV_FGMRES && so.krylov != SD_KRYLOV_BICGSTAB)
     throw Error(SD_E_INVALID, "krylov");
@@ -252,7 +253,7 @@ void Solver::upload(const sd_allocator* alloc, hipStream_t s) {
   nnz_A = pb->A.nnz();
   nnz_V0 = hh[0].levels[0].A.nnz();
   SD_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
-  prec = opts.o.precision == SD_PRECISION_MIXED ? make_prec_fp32(*this, s) : make_prec_fp64(*this, s);
+  prec = opts.o.precision == SD_PRECISION_FP64 ? make_prec_fp64(*this, s) : make_prec_fp32(*this, s);
   SD_HIP(hipStreamSynchronize(s));
   on_device = true;
   t_setup += wall_time() - t0;
@@ -323,7 +324,8 @@ class PrecImpl : public PrecBase {
  public:
   DevHierarchy<T> H[2];
   Sell<T> Cf;
-  Sell<T> Aarn;          // matrix of the Arnoldi product (FP64 A, or an FP32 copy)
+  Sell<float> A32;       // FP32 copy of A for the Arnoldi product (MIXED32 only)
+  bool arn32 = false;
   T* Z = nullptr;        // m preconditioned vectors
   T* tq = nullptr;       // porous right-hand side of the block sweep
   T* tmpN = nullptr;     // scratch vector of length N (apply entry points)
@@ -337,10 +339,8 @@ class PrecImpl : public PrecBase {
     for (int b = 0; b < 2; ++b)
       upload_hierarchy<T>(S.hh[b], H[b], S.opts.amg.omega, nu_pre, nu_post, mem, s);
     Cf = upload_sell<T>(S.Cf, mem, s);
-    if constexpr (std::is_same<T, double>::value)
-      Aarn = S.A64;
-    else
-      Aarn = upload_sell<T>(S.pb->A, mem, s);
+    arn32 = S.opts.o.precision == SD_PRECISION_MIXED32;
+    if (arn32) A32 = upload_sell<float>(S.pb->A, mem, s);
     ldz = S.ldv;
     Z = mem.array<T>((size_t)S.opts.o.restart * ldz);
     tq = mem.array<T>((size_t)(S.N - S.off[3]) + 1);
@@ -499,7 +499,7 @@ class PrecImpl : public PrecBase {
     const sd_solver_opts& o = S.opts.o;
     const int n = S.N;
     const int m = o.restart;
-    const double drop = std::is_same<T, float>::value ? 1e-6 : 0.0;
+    const double drop = arn32 ? 1e-6 : 0.0;
     const int depth = 2;
     switch (R.phase) {
       case SolveRun::INIT:
@@ -627,8 +627,7 @@ class PrecImpl : public PrecBase {
       } else {
         apply(S, S.V + (size_t)j * S.ldv, &S.st->sigma[j], zj, nullptr, s);
       }
-      launch_arnoldi_step<T, T>(Aarn, zj, S.W, S.V, S.ldv, j, S.st, S.part, S.hf_dev, s,
-                                S.prof_class, ev);
+      arnoldi(S, zj, j, s, S.prof_class, ev);
       return;
     }
     if (graphs.empty()) graphs.assign((size_t)kMaxBasis, nullptr);
@@ -647,7 +646,19 @@ class PrecImpl : public PrecBase {
   void enqueue_iteration(Solver& S, int j, hipStream_t s) {
     T* zj = Z + (size_t)j * ldz;
     apply(S, S.V + (size_t)j * S.ldv, &S.st->sigma[j], zj, nullptr, s);
-    launch_arnoldi_step<T, T>(Aarn, zj, S.W, S.V, S.ldv, j, S.st, S.part, S.hf_dev, s);
+    arnoldi(S, zj, j, s, 0, nullptr);
+  }
+  // w = A z_j with the FP64 matrix, or the FP32 copy under MIXED32
+  void arnoldi(Solver& S, const T* zj, int j, hipStream_t s, int prof_class, hipEvent_t* ev) {
+    if constexpr (std::is_same<T, float>::value) {
+      if (arn32) {
+        launch_arnoldi_step<float, float>(A32, zj, S.W, S.V, S.ldv, j, S.st, S.part, S.hf_dev, s,
+                                          prof_class, ev);
+        return;
+      }
+    }
+    launch_arnoldi_step<double, T>(S.A64, zj, S.W, S.V, S.ldv, j, S.st, S.part, S.hf_dev, s,
+                                   prof_class, ev);
   }
   ~PrecImpl() override {
     for (auto g : graphs)
@@ -669,7 +680,8 @@ class PrecImpl : public PrecBase {
       S.prof_seconds += 1e-3 * ms;
       S.prof_launches += 1;
       if (S.prof_class == 1)  // A (values + indices), z, w, j+1 basis vectors
-        S.prof_bytes += (double)S.nnz_A * (tz + 4.0) + n * (tz + 8.0) + (j + 1) * 8.0 * n;
+        S.prof_bytes += (double)S.nnz_A * ((arn32 ? 4.0 : 8.0) + 4.0) + n * (tz + 8.0) +
+                        (j + 1) * 8.0 * n;
       else if (S.prof_class == 2)  // j basis vectors, u_j and w read; v_j, u_{j+1} written
         S.prof_bytes += (j + 4) * 8.0 * n;
       else {  // V level 0: A_V (values + indices), x_in, b, w, x_out

@@ -23,7 +23,7 @@ BC = {"velocity": 0, "traction": 1, "pressure": 2, "noflow": 3}
 KRYLOV = {"fgmres": 0, "bicgstab": 1}
 PRECOND = {"BJ": 0, "BGS": 1}
 SCHUR = {"identity": 0, "mass": 1}
-PRECISION = {"fp64": 0, "mixed": 1}
+PRECISION = {"fp64": 0, "mixed": 1, "mixed32": 2}
 AMG = {"plain": 0, "smoothed": 1}
 REQ_STATE = {0: "pending", 1: "running", 2: "done", 3: "failed"}
 

@@ -133,11 +133,12 @@ def test_fgmres_fp64_matches_oracle(name, variant, tol):
     assert e_gpu <= 2 * e_ref + 1e-12
 
 
-def test_fgmres_mixed_precision():
+@pytest.mark.parametrize("precision", ["mixed", "mixed32"])
+def test_fgmres_mixed_precision(precision):
     p = SMALL["channel96"]()
     a = assemble(p)
     xs = refined_solve(a.A, a.b)
-    P, S = _setup(p, precision="mixed", tol=1e-8)
+    P, S = _setup(p, precision=precision, tol=1e-8)
     x, st, rc = S.solve()
     x = _host(x)
     assert rc == sd.SD_OK

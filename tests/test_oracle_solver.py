@@ -98,6 +98,65 @@ def test_aggregation_partition_and_galerkin(smoothed, mis_dist):
             assert np.allclose(L.R.toarray(), Pd.T)
 
 
+def _neumann_diffusion(n, sigma, seed):
+    """Cell-centred two-point diffusion on an n x n grid with a lognormal
+    coefficient (harmonic face means) and no-flux walls: every row sums to 0."""
+    K = np.exp(sigma * np.random.default_rng(seed).standard_normal((n, n)))
+    idx = np.arange(n * n).reshape(n, n)
+    r, c, v = [], [], []
+    diag = np.zeros(n * n)
+    for (i0, j0), (i1, j1) in (((0, 0), (1, 0)), ((0, 0), (0, 1))):
+        a = idx[i0:n - i1, j0:n - j1].ravel()
+        b = idx[i1:, j1:].ravel()
+        Ka, Kb = K.ravel()[a], K.ravel()[b]
+        t = 2.0 * Ka * Kb / (Ka + Kb)
+        r += [a, b]
+        c += [b, a]
+        v += [-t, -t]
+        np.add.at(diag, a, t)
+        np.add.at(diag, b, t)
+    r.append(np.arange(n * n))
+    c.append(np.arange(n * n))
+    v.append(diag)
+    A = sp.csr_matrix((np.concatenate(v), (np.concatenate(r), np.concatenate(c))),
+                      shape=(n * n, n * n))
+    A.sort_indices()
+    return A
+
+
+def test_smoothed_prolongator_preserves_constants_with_weak_couplings():
+    """Smoothed aggregation (Vanek, Mandel, Brezina 1996) smooths P_t with the
+    filtered matrix whose diagonal absorbs the dropped weak entries, so A_F
+    keeps A's row sums; for a zero-row-sum operator every level's P then maps
+    the coarse constant to the fine constant (A_c = R A P keeps zero row
+    sums).  A rough coefficient makes many couplings weak on every level."""
+    A = _neumann_diffusion(32, 1.5, 5)
+    h = amg.setup(A, np.zeros(A.shape[0], dtype=np.int32), True,
+                  amg.AMGOptions(coarse_max=30))
+    assert h.n_levels >= 3
+    for L in h.levels[:-1]:
+        n_c = L.P.shape[1]
+        assert np.max(np.abs(L.P @ np.ones(n_c) - 1.0)) < 1e-12
+        rows = np.repeat(np.arange(L.A.shape[0]), np.diff(L.A.indptr))
+        weak = ~amg.strong_mask(L.A, L.comp, 0.08) & (rows != L.A.indices)
+        assert weak.any()
+    # the same smoothing without the lumping loses the constant on a level
+    # with weak couplings: the pin above would catch a dropped lumping
+    L = h.levels[1]
+    Ad = L.A.toarray()
+    n = Ad.shape[0]
+    rows = np.repeat(np.arange(n), np.diff(L.A.indptr))
+    strong = amg.strong_mask(L.A, L.comp, 0.08)
+    AF = np.zeros_like(Ad)
+    AF[rows[strong], L.A.indices[strong]] = L.A.data[strong]
+    AF[np.arange(n), np.arange(n)] = np.diag(Ad)
+    rho = np.max(np.abs(AF).sum(axis=1) / np.abs(np.diag(Ad)))
+    Pt = np.zeros((n, L.P.shape[1]))
+    Pt[np.arange(n), L.agg] = 1.0
+    P_unlumped = Pt - (4.0 / (3.0 * rho)) * (AF / np.diag(Ad)[:, None]) @ Pt
+    assert np.max(np.abs(P_unlumped.sum(axis=1) - 1.0)) > 1e-3
+
+
 def test_spgemm_order_is_row_by_row():
     """The oracle's ordered sparse product equals an explicit loop bit-for-bit."""
     rng = np.random.default_rng(3)
