@@ -49,6 +49,7 @@ struct DevState {
   double H[(kMaxBasis + 1) * kMaxBasis];   // column-major, ld = kMaxBasis + 1
   double cs[kMaxBasis], sn[kMaxBasis], g[kMaxBasis + 1], y[kMaxBasis];
   double h1[kMaxBasis + 1];          // first-pass coefficients of the open column
+  double sums[2 * kMaxBasis + 3];    // reduced Gram-Schmidt dot products of the step
   // BiCGSTAB scalars
   double rho, alpha, omega, bbeta, dots[8];
   unsigned int counter[8];

@@ -355,16 +355,18 @@ __global__ __launch_bounds__(kBlock) void k_block_sweep(Sell<T> Cf, int n_p,
 //
 // On entry to step j the basis slots 0..j-1 hold orthonormal v_0..v_{j-1},
 // slot j holds u_j, the once-orthogonalised (unnormalised) candidate for v_j,
-// and the preconditioner has produced z_j = M(sigma_j u_j).  Two kernels:
+// and the preconditioner has produced z_j = M(sigma_j u_j).  Three kernels:
 //   project: w = A z_j; partial sums of a = V^T u_j, b = V^T w, u_j.u_j,
 //            u_j.w and w.w (one pass over the basis);
-//   update:  every workgroup reduces the partials in the same fixed order;
-//            nu = sqrt(u.u - a.a), v_j = (u_j - V a)/nu, h_jj = (u.w - a.b)/nu,
-//            u_{j+1} = w - V b - h_jj v_j (one pass over the basis).
-//            Workgroup 0 completes Hessenberg column j-1 (first-pass
-//            coefficients + a, subdiagonal nu), applies the Givens rotations
-//            and sets the convergence flag; the residual estimate therefore
-//            trails the basis by one step.
+//   sum:     one workgroup per partial-sum row adds the rows' partials in
+//            a fixed order;
+//   update:  every workgroup derives nu = sqrt(u.u - a.a) and
+//            h_jj = (u.w - a.b)/nu from the sums and writes
+//            v_j = (u_j - V a)/nu, u_{j+1} = w - V b - h_jj v_j (one pass
+//            over the basis); the last workgroup completes Hessenberg
+//            column j-1 (first-pass coefficients + a, subdiagonal nu),
+//            applies the Givens rotations and sets the convergence flag
+//            (the residual estimate trails the basis by one step).
 // In exact arithmetic a = 0 and the iterates are those of CGS2 FGMRES.  A
 // closing step (project without the product, update without row work)
 // completes the last column of a full cycle.  Layout: row-block x
@@ -378,31 +380,6 @@ constexpr int kGsWaves = kGsThreads / 64;
 constexpr int kGsVpw = kMaxBasis / kGsWaves;     // basis vectors per wavefront
 constexpr int kGsRound = 256;                     // rows per LDS round (4 per lane)
 constexpr int kSumStride = 2 * kMaxBasis + 4;
-
-// sums[i], i < 2j + 3: a_0..a_{j-1}, b_0..b_{j-1}, u.u, u.w, w.w, each the sum
-// over the nb row blocks in a fixed order (identical in every workgroup).
-__device__ __forceinline__ void arn_sums(const double* part, int nb, int j, double* sums,
-                                         double* scratch) {
-  const int nr = 2 * j + 3;
-  const int t = threadIdx.x;
-  for (int i0 = 0; i0 < nr; i0 += kGsThreads / 16) {
-    const int i = i0 + (t >> 4), sub = t & 15;
-    if (i < nr) {
-      const int row = i < j ? kGsRowA + i : (i < 2 * j ? kGsRowB + (i - j) : kGsRowC + (i - 2 * j));
-      const double* p = part + (size_t)row * kGsMaxBlocks;
-      double s = 0.0;
-      for (int b = sub; b < nb; b += 16) s += p[b];
-      scratch[sub * kSumStride + i] = s;
-    }
-  }
-  __syncthreads();
-  if (t < nr) {
-    double a = 0.0;
-    for (int q = 0; q < 16; ++q) a += scratch[q * kSumStride + t];
-    sums[t] = a;
-  }
-  __syncthreads();
-}
 
 // Rows ra and rb (slices of equal or different width) of a SELL-64 matrix
 // in one loop: two independent load chains per lane.
@@ -443,31 +420,35 @@ __global__ __launch_bounds__(kGsThreads) void k_arn_project(Sell<TM> A, const TZ
   __shared__ double red2[kGsWaves][2];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r0 = blockIdx.x * rpb;
-  const int ns = rpb / 64;                        // slices of the block (multiple of 32)
+  const int ns = rpb / 64;                        // slices of the block (multiple of 16)
   const double* uj = V + (size_t)j * ldv;
   double cuu = 0.0, cuw = 0.0, cww = 0.0;
   for (int sl = wave; sl < ns; sl += 2 * kGsWaves) {
+    const bool two = sl + kGsWaves < ns;          // a second slice for this wavefront
     const int la = sl * 64 + lane, lb = la + kGsWaves * 64;
     const int ra = r0 + la, rb = r0 + lb;
+    const bool hb = two && rb < n;
     double wa = 0.0, wb = 0.0, ua = 0.0, ub = 0.0;
     if (ra < n) {
       ua = uj[ra];
-      if (rb < n) ub = uj[rb];
+      if (hb) ub = uj[rb];
       if (spmv) {
         TM sa, sb;
-        sell_dot2(A, z, ra, rb, rb < n, sa, sb);
+        sell_dot2(A, z, ra, rb, hb, sa, sb);
         wa = (double)sa;
         W[ra] = wa;
-        if (rb < n) {
+        if (hb) {
           wb = (double)sb;
           W[rb] = wb;
         }
       }
     }
     wt[la] = wa;
-    wt[lb] = wb;
     ut[la] = ua;
-    ut[lb] = ub;
+    if (two) {
+      wt[lb] = wb;
+      ut[lb] = ub;
+    }
     cuu += ua * ua + ub * ub;
     cuw += ua * wa + ub * wb;
     cww += wa * wa + wb * wb;
@@ -561,7 +542,7 @@ __global__ __launch_bounds__(kGsThreads) void k_arn_project(Sell<TM> A, const TZ
   }
 }
 
-// Workgroup 0 of the update kernel: complete column jc = j - 1 (if any),
+// Scalar part of the update kernel: complete column jc = j - 1 (if any),
 // rotate it, update g and the flags; record column j's first-pass
 // coefficients and the input scale of the next preconditioner application.
 __device__ void arn_column(int j, int update, const double* sums, const double* sc,
@@ -631,15 +612,9 @@ __device__ void arn_column(int j, int update, const double* sums, const double* 
 // per lane (two rows per thread in flight), the coefficients broadcast from
 // LDS, and each row's sums run over the basis in ascending order.
 __device__ __forceinline__ void arn_rows(const double* __restrict__ W, double* __restrict__ V,
-                                         int64_t ldv, int n, int j, int rpb, const double* sums,
-                                         const double* sc, double* cf) {
+                                         int64_t ldv, int n, int j, int rpb, const double* cf,
+                                         double inv, double tt) {
   const int t = threadIdx.x;
-  if (t < j) {
-    cf[t] = sc[0] * sums[t];
-    cf[kMaxBasis + t] = sums[j + t] - sc[1] * sums[t];
-  }
-  __syncthreads();
-  const double inv = sc[0], tt = sc[1];
   double* uj = V + (size_t)j * ldv;
   double* un = V + (size_t)(j + 1) * ldv;
   const int r0 = blockIdx.x * rpb;
@@ -670,18 +645,41 @@ __device__ __forceinline__ void arn_rows(const double* __restrict__ W, double* _
   }
 }
 
+// One workgroup per partial-sum row (2j + 3 rows): the sum over the
+// projection workgroups, in a fixed order, into st->sums.
+__global__ __launch_bounds__(kBlock) void k_arn_sum_rows(const double* part, int nb, int j,
+                                                         DevState* st) {
+  const int stop = gate_flag(st);
+  __shared__ double red[kBlock / 64];
+  const int i = blockIdx.x;
+  const int row = i < j ? kGsRowA + i : (i < 2 * j ? kGsRowB + (i - j) : kGsRowC + (i - 2 * j));
+  const double* p = part + (size_t)row * kGsMaxBlocks;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kBlock) s += p[b];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0 && !stop) st->sums[i] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// Update pass of Arnoldi step j: every workgroup derives the coefficients
+// from the 2j + 3 sums (same arithmetic in each), streams its rows, and the
+// last workgroup completes the Hessenberg column.  With update == 0 (closing
+// step, one workgroup) only the column is completed.
 __global__ __launch_bounds__(kGsThreads) void k_arn_update(const double* __restrict__ W,
                                                            double* __restrict__ V, int64_t ldv,
-                                                           int n, int j, int rpb, int nb,
-                                                           int update, DevState* st,
-                                                           const double* part, HostFlags* hf) {
-  if (st->cycle_done) return;
-  __shared__ double scratch[16 * kSumStride];
+                                                           int n, int j, int rpb, int update,
+                                                           DevState* st, HostFlags* hf) {
+  __shared__ double scratch[4 * kMaxBasis];
   __shared__ double sums[kSumStride];
   __shared__ double cf[2 * kMaxBasis];
   __shared__ double sc[8];
-  arn_sums(part, nb, j, sums, scratch);
   const int t = threadIdx.x;
+  const int nr = 2 * j + 3;
+  const int stop = st->cycle_done;
+  if (t < nr) sums[t] = st->sums[t];
+  __syncthreads();
+  if (stop) return;
   if (t == 0) {
     double aa = 0.0, ab = 0.0, bb = 0.0;
     for (int k = 0; k < j; ++k) {
@@ -703,8 +701,14 @@ __global__ __launch_bounds__(kGsThreads) void k_arn_update(const double* __restr
     sc[4] = ww > 0.0 ? 1.0 / sqrt(rest > floor ? rest : floor) : 1.0;
   }
   __syncthreads();
-  // the last workgroup completes the Hessenberg column after its rows
-  if (update) arn_rows(W, V, ldv, n, j, rpb, sums, sc, cf);
+  if (update) {
+    if (t < j) {
+      cf[t] = sc[0] * sums[t];
+      cf[kMaxBasis + t] = sums[j + t] - sc[1] * sums[t];
+    }
+    __syncthreads();
+    arn_rows(W, V, ldv, n, j, rpb, cf, sc[0], sc[1]);
+  }
   if (blockIdx.x == gridDim.x - 1) {
     __syncthreads();
     arn_column(j, update, sums, sc, st, hf, scratch, scratch + 2 * kMaxBasis);
@@ -1176,35 +1180,42 @@ void launch_block_sweep(const Sell<T>& Cf, int n_p, const double* r, const doubl
                                                             tq, gate);
 }
 
-int gs_rows_per_block(int n) {
-  int rpb = 2048;
+// Rows per workgroup: the projection kernel takes 1024 (two workgroups per
+// CU overlap one's latency-bound product phase with the other's streaming),
+// the update kernel 2048; both grow when the partial sums would exceed
+// kGsMaxBlocks workgroups.
+int gs_rows_per_block(int n, int base) {
+  int rpb = base;
   while ((n + rpb - 1) / rpb > kGsMaxBlocks) rpb *= 2;
   return rpb;
 }
+constexpr int kProjectRows = 1024, kUpdateRows = 2048;
 
 template <typename TM, typename TZ>
 void launch_arnoldi_step(const Sell<TM>& A, const TZ* z, double* W, double* V, int64_t ldv, int j,
                          DevState* st, double* part, HostFlags* hf, hipStream_t s, int prof_class,
                          hipEvent_t* ev) {
   const int n = A.n_rows;
-  const int rpb = gs_rows_per_block(n);
-  const int nb = (n + rpb - 1) / rpb;
+  const int rp = gs_rows_per_block(n, kProjectRows), ru = gs_rows_per_block(n, kUpdateRows);
+  const int np = (n + rp - 1) / rp, nu = (n + ru - 1) / ru;
   if (ev && prof_class == 1) (void)hipEventRecord(ev[0], s);
-  k_arn_project<TM, TZ><<<nb, kGsThreads, (size_t)2 * rpb * sizeof(double), s>>>(
-      A, z, W, V, ldv, n, j, rpb, 1, st, part);
+  k_arn_project<TM, TZ><<<np, kGsThreads, (size_t)2 * rp * sizeof(double), s>>>(
+      A, z, W, V, ldv, n, j, rp, 1, st, part);
   if (ev && prof_class == 1) (void)hipEventRecord(ev[1], s);
+  k_arn_sum_rows<<<2 * j + 3, kBlock, 0, s>>>(part, np, j, st);
   if (ev && prof_class == 2) (void)hipEventRecord(ev[0], s);
-  k_arn_update<<<nb, kGsThreads, 0, s>>>(W, V, ldv, n, j, rpb, nb, 1, st, part, hf);
+  k_arn_update<<<nu, kGsThreads, 0, s>>>(W, V, ldv, n, j, ru, 1, st, hf);
   if (ev && prof_class == 2) (void)hipEventRecord(ev[1], s);
 }
 
 void launch_arnoldi_close(int n, double* V, int64_t ldv, int j, DevState* st, double* part,
                           HostFlags* hf, hipStream_t s) {
-  const int rpb = gs_rows_per_block(n);
-  const int nb = (n + rpb - 1) / rpb;
-  k_arn_project<double, double><<<nb, kGsThreads, (size_t)2 * rpb * sizeof(double), s>>>(
-      Sell<double>{}, nullptr, nullptr, V, ldv, n, j, rpb, 0, st, part);
-  k_arn_update<<<1, kGsThreads, 0, s>>>(nullptr, V, ldv, n, j, rpb, nb, 0, st, part, hf);
+  const int rp = gs_rows_per_block(n, kProjectRows);
+  const int np = (n + rp - 1) / rp;
+  k_arn_project<double, double><<<np, kGsThreads, (size_t)2 * rp * sizeof(double), s>>>(
+      Sell<double>{}, nullptr, nullptr, V, ldv, n, j, rp, 0, st, part);
+  k_arn_sum_rows<<<2 * j + 3, kBlock, 0, s>>>(part, np, j, st);
+  k_arn_update<<<1, kGsThreads, 0, s>>>(nullptr, V, ldv, n, j, kUpdateRows, 0, st, hf);
 }
 
 void launch_trisolve(DevState* st, hipStream_t s) { k_trisolve<<<1, 64, 0, s>>>(st); }
