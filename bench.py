@@ -40,7 +40,7 @@ ROOFLINE_KERNEL = {"fp64": "k_arn_project<double, double>",
                    "mixed32": "k_arn_project<float, float>"}
 WORKLOAD_C2 = ("1024x512 free-flow + 1024x512 porous cells (N=2097152), lognormal K seed 2, "
                "BGS(SA-AMG V-cycle, mu*Mp^-1, SA-AMG V-cycle) + FGMRES(m), rel. residual 1e-8")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_arnoldi_spmv_c1.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_arnoldi_project_c1.json")
 
 
 def parse():
@@ -91,11 +91,14 @@ def block_errors(x, ref, off):
     return out
 
 
-def roofline(S, n_solves, precision):
-    """Dominant kernel (w = A z_j fused with the first Gram-Schmidt dot pass):
-    its launches are bracketed by HIP events on the solver's stream during
-    n_solves solves of the same workload; achieved = algorithmic bytes of
-    those launches / their summed durations."""
+def roofline(S, n_solves, precision, config):
+    """Dominant kernel (w = A z_j fused with the projection pass of the
+    Gram-Schmidt step over the basis): its launches are bracketed by HIP
+    events on the solver's stream during n_solves solves of the same
+    workload; achieved = algorithmic bytes of those launches / their summed
+    durations.  traffic = HBM bytes per launch from the committed counter
+    passes (FETCH_SIZE + WRITE_SIZE, copy-calibrated), when they were taken
+    on this kernel source, workload and precision."""
     S.profile("arnoldi_spmv")
     for _ in range(n_solves):
         S.solve()
@@ -109,7 +112,8 @@ def roofline(S, n_solves, precision):
             t = json.load(f)
         src = os.path.join(ROOT, "paper_2108_13229_amd", "csrc", "kernels.hip")
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if t.get("kernels_hip_sha256") == sha:
+        if (t.get("kernels_hip_sha256") == sha and t.get("kernel") == ROOFLINE_KERNEL[precision]
+                and config == "C1"):
             traffic = t["hbm_bytes_per_launch"]
     except (OSError, ValueError, KeyError):
         traffic = None
@@ -284,7 +288,7 @@ def main():
                          iters=int(np.median(its)), restarts=st["restarts"],
                          rel_res=st["rel_res"], setup_s=t_setup)
         if prec == headline and args.roofline_solves > 0:
-            roof = roofline(S, args.roofline_solves, prec)
+            roof = roofline(S, args.roofline_solves, prec, args.config)
         S.close()
     head = res[headline]
     out = {
