@@ -22,7 +22,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <map>
+#include <mutex>
 #include <thread>
 
 #include "sd_internal.h"
@@ -30,6 +32,29 @@
 namespace sd {
 
 namespace {
+
+// Run f(begin, end) over [r0, r1) split into contiguous chunks on threads,
+// at least `grain` rows per thread (small ranges run inline: thread start-up
+// would cost more than the rows, and concurrent setups share the host).
+template <typename F>
+void parallel_rows(int64_t r0, int64_t r1, F&& f, int64_t grain = 8192) {
+  const int64_t cnt = r1 - r0;
+  if (cnt <= 0) return;
+  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const int64_t nt = std::min<int64_t>(hw, cnt / std::max<int64_t>(grain, 1));
+  if (nt <= 1) {
+    f(r0, r1);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int64_t chunk = (cnt + nt - 1) / nt;
+  for (int64_t t = 1; t < nt; ++t) {
+    const int64_t a = r0 + t * chunk, b = std::min(r1, a + chunk);
+    if (a < b) th.emplace_back(f, a, b);
+  }
+  f(r0, std::min(r1, r0 + chunk));
+  for (auto& x : th) x.join();
+}
 
 enum : int8_t { UND = 0, ROOT = 1, NONROOT = 2 };
 
@@ -48,56 +73,85 @@ std::vector<uint8_t> strong_mask(const HostCSR& A, const std::vector<int32_t>& c
                                  const std::vector<double>& d, double theta) {
   const double th2 = theta * theta;
   std::vector<uint8_t> m((size_t)A.nnz(), 0);
-  for (int64_t i = 0; i < A.n_rows; ++i) {
-    for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) {
-      const int64_t j = A.col[k];
-      const double a = A.val[k];
-      m[k] = (j != i) && (comp[i] == comp[j]) && ((a * a) >= th2 * std::fabs(d[i] * d[j]));
+  parallel_rows(0, A.n_rows, [&](int64_t r0, int64_t r1) {
+    for (int64_t i = r0; i < r1; ++i) {
+      for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) {
+        const int64_t j = A.col[k];
+        const double a = A.val[k];
+        m[k] = (j != i) && (comp[i] == comp[j]) && ((a * a) >= th2 * std::fabs(d[i] * d[j]));
+      }
     }
-  }
+  });
   return m;
+}
+
+// Rows of a graph built in parallel: build(i, out) appends row i's sorted
+// neighbours; row ranges run on threads and are concatenated in order.
+template <typename B>
+Graph build_graph(int64_t n, B build) {
+  struct Part {
+    int64_t r0 = 0;
+    std::vector<int64_t> len;
+    std::vector<int32_t> adj;
+  };
+  std::vector<Part> parts;
+  std::mutex mu;
+  parallel_rows(0, n, [&](int64_t r0, int64_t r1) {
+    Part pt;
+    pt.r0 = r0;
+    std::vector<int32_t> tmp;
+    for (int64_t i = r0; i < r1; ++i) {
+      tmp.clear();
+      build(i, tmp);
+      pt.len.push_back((int64_t)tmp.size());
+      pt.adj.insert(pt.adj.end(), tmp.begin(), tmp.end());
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    parts.push_back(std::move(pt));
+  });
+  std::sort(parts.begin(), parts.end(), [](const Part& a, const Part& b) { return a.r0 < b.r0; });
+  Graph G;
+  G.ptr.assign(1, 0);
+  for (const Part& pt : parts) {
+    for (int64_t l : pt.len) G.ptr.push_back(G.ptr.back() + l);
+    G.adj.insert(G.adj.end(), pt.adj.begin(), pt.adj.end());
+  }
+  return G;
 }
 
 Graph symmetric_strength(const HostCSR& A, const std::vector<uint8_t>& m) {
   const int64_t n = A.n_rows;
-  std::vector<std::vector<int32_t>> nb((size_t)n);
+  // transpose of the strong pattern (counting sort: rows of S^T ascending)
+  std::vector<int64_t> tp((size_t)n + 1, 0);
+  for (int64_t k = 0; k < A.nnz(); ++k)
+    if (m[k]) ++tp[(size_t)A.col[k] + 1];
+  for (int64_t i = 0; i < n; ++i) tp[i + 1] += tp[i];
+  std::vector<int32_t> tadj((size_t)tp[n]);
+  std::vector<int64_t> fill(tp.begin(), tp.end() - 1);
   for (int64_t i = 0; i < n; ++i)
     for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k)
-      if (m[k]) {
-        nb[i].push_back(A.col[k]);
-        nb[A.col[k]].push_back((int32_t)i);
-      }
-  Graph G;
-  G.ptr.assign(1, 0);
-  for (int64_t i = 0; i < n; ++i) {
-    auto& v = nb[i];
+      if (m[k]) tadj[(size_t)fill[A.col[k]]++] = (int32_t)i;
+  return build_graph(n, [&](int64_t i, std::vector<int32_t>& v) {
+    for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k)
+      if (m[k]) v.push_back(A.col[k]);
+    for (int64_t k = tp[i]; k < tp[i + 1]; ++k) v.push_back(tadj[k]);
     std::sort(v.begin(), v.end());
     v.erase(std::unique(v.begin(), v.end()), v.end());
-    G.adj.insert(G.adj.end(), v.begin(), v.end());
-    G.ptr.push_back((int64_t)G.adj.size());
-  }
-  return G;
+  });
 }
 
 Graph square(const Graph& S) {
   const int64_t n = (int64_t)S.ptr.size() - 1;
-  Graph G;
-  G.ptr.assign(1, 0);
-  std::vector<int32_t> tmp;
-  for (int64_t i = 0; i < n; ++i) {
-    tmp.clear();
+  return build_graph(n, [&](int64_t i, std::vector<int32_t>& v) {
     for (int64_t k = S.ptr[i]; k < S.ptr[i + 1]; ++k) {
       const int32_t j = S.adj[k];
-      tmp.push_back(j);
-      for (int64_t l = S.ptr[j]; l < S.ptr[j + 1]; ++l) tmp.push_back(S.adj[l]);
+      v.push_back(j);
+      for (int64_t l = S.ptr[j]; l < S.ptr[j + 1]; ++l) v.push_back(S.adj[l]);
     }
-    std::sort(tmp.begin(), tmp.end());
-    tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
-    for (int32_t j : tmp)
-      if (j != i) G.adj.push_back(j);
-    G.ptr.push_back((int64_t)G.adj.size());
-  }
-  return G;
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    v.erase(std::remove(v.begin(), v.end(), (int32_t)i), v.end());
+  });
 }
 
 std::vector<int8_t> luby_mis(const Graph& G, int level) {
@@ -109,27 +163,33 @@ std::vector<int8_t> luby_mis(const Graph& G, int level) {
   std::vector<int8_t> state((size_t)n, UND);
   std::vector<uint8_t> new_root((size_t)n, 0);
   int64_t undecided = n;
+  // synchronous rounds: every decision reads the state at the round's start,
+  // so the row ranges of a phase can run on threads
   while (undecided > 0) {
-    for (int64_t i = 0; i < n; ++i) {
-      new_root[i] = 0;
-      if (state[i] != UND) continue;
-      bool lost = false;
-      for (int64_t k = G.ptr[i]; k < G.ptr[i + 1] && !lost; ++k) {
-        const int32_t j = G.adj[k];
-        if (state[j] == UND && key[j] > key[i]) lost = true;
+    parallel_rows(0, n, [&](int64_t r0, int64_t r1) {
+      for (int64_t i = r0; i < r1; ++i) {
+        new_root[i] = 0;
+        if (state[i] != UND) continue;
+        bool lost = false;
+        for (int64_t k = G.ptr[i]; k < G.ptr[i + 1] && !lost; ++k) {
+          const int32_t j = G.adj[k];
+          if (state[j] == UND && key[j] > key[i]) lost = true;
+        }
+        new_root[i] = !lost;
       }
-      new_root[i] = !lost;
-    }
+    });
     for (int64_t i = 0; i < n; ++i)
       if (new_root[i]) state[i] = ROOT;
-    for (int64_t i = 0; i < n; ++i) {
-      if (state[i] != UND) continue;
-      for (int64_t k = G.ptr[i]; k < G.ptr[i + 1]; ++k)
-        if (new_root[G.adj[k]]) {
-          state[i] = NONROOT;
-          break;
-        }
-    }
+    parallel_rows(0, n, [&](int64_t r0, int64_t r1) {
+      for (int64_t i = r0; i < r1; ++i) {
+        if (state[i] != UND) continue;
+        for (int64_t k = G.ptr[i]; k < G.ptr[i + 1]; ++k)
+          if (new_root[G.adj[k]]) {
+            state[i] = NONROOT;
+            break;
+          }
+      }
+    });
     undecided = 0;
     for (int64_t i = 0; i < n; ++i) undecided += state[i] == UND;
   }
@@ -212,7 +272,7 @@ HostCSR smoothed(const HostCSR& A, const std::vector<uint8_t>& strong,
   P.n_rows = n;
   P.n_cols = n_c;
   P.rowptr.assign(1, 0);
-  std::map<int32_t, double> acc;
+  std::vector<std::pair<int32_t, double>> acc;   // (aggregate, running sum), few per row
   for (int64_t i = 0; i < n; ++i) {
     if (!valid[i]) {
       P.col.push_back(agg[i]);
@@ -226,12 +286,14 @@ HostCSR smoothed(const HostCSR& A, const std::vector<uint8_t>& strong,
       if (!(strong[k] || diag)) continue;
       const double v = diag ? dF[i] : A.val[k];
       const int32_t J = agg[A.col[k]];
-      auto it = acc.find(J);
-      if (it == acc.end())
-        acc.emplace(J, 0.0 + v);
+      size_t q = 0;
+      while (q < acc.size() && acc[q].first != J) ++q;
+      if (q == acc.size())
+        acc.emplace_back(J, 0.0 + v);
       else
-        it->second = it->second + v;
+        acc[q].second = acc[q].second + v;
     }
+    std::sort(acc.begin(), acc.end());
     const double coef = wp / dF[i];
     for (auto& e : acc) {
       const double base = (e.first == agg[i]) ? 1.0 : 0.0;
@@ -262,67 +324,74 @@ HostCSR transpose(const HostCSR& P) {
   return R;
 }
 
+
+
 // Gustavson product: (XY)[i, J] accumulates x_ik * y_kJ over ascending k,
-// then over Y's row k in ascending J.  Structural pattern, zeros kept.
+// then over Y's row k in ascending J.  Structural pattern, zeros kept.  Rows
+// are independent: contiguous row ranges run on threads, each row summed in
+// the same order as a serial loop, so the result does not depend on the
+// thread count.
 HostCSR spgemm(const HostCSR& X, const HostCSR& Y) {
+  struct Part {
+    int64_t r0 = 0;
+    std::vector<int64_t> len;
+    std::vector<int32_t> col;
+    std::vector<double> val;
+  };
+  std::vector<Part> parts;
+  std::mutex mu;
+  parallel_rows(0, X.n_rows, [&](int64_t r0, int64_t r1) {
+    Part pt;
+    pt.r0 = r0;
+    std::vector<double> acc((size_t)Y.n_cols, 0.0);
+    std::vector<int64_t> mark((size_t)Y.n_cols, -1);
+    std::vector<int32_t> cols;
+    for (int64_t i = r0; i < r1; ++i) {
+      cols.clear();
+      for (int64_t k = X.rowptr[i]; k < X.rowptr[i + 1]; ++k) {
+        const int32_t kk = X.col[k];
+        const double xv = X.val[k];
+        for (int64_t l = Y.rowptr[kk]; l < Y.rowptr[kk + 1]; ++l) {
+          const int32_t J = Y.col[l];
+          const double prod = xv * Y.val[l];
+          if (mark[J] != i) {
+            mark[J] = i;
+            acc[J] = 0.0 + prod;
+            cols.push_back(J);
+          } else {
+            acc[J] = acc[J] + prod;
+          }
+        }
+      }
+      std::sort(cols.begin(), cols.end());
+      for (int32_t J : cols) {
+        pt.col.push_back(J);
+        pt.val.push_back(acc[J]);
+      }
+      pt.len.push_back((int64_t)cols.size());
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    parts.push_back(std::move(pt));
+  });
+  std::sort(parts.begin(), parts.end(), [](const Part& a, const Part& b) { return a.r0 < b.r0; });
   HostCSR Z;
   Z.n_rows = X.n_rows;
   Z.n_cols = Y.n_cols;
   Z.rowptr.assign(1, 0);
-  std::vector<double> acc((size_t)Y.n_cols, 0.0);
-  std::vector<int64_t> mark((size_t)Y.n_cols, -1);
-  std::vector<int32_t> cols;
-  for (int64_t i = 0; i < X.n_rows; ++i) {
-    cols.clear();
-    for (int64_t k = X.rowptr[i]; k < X.rowptr[i + 1]; ++k) {
-      const int32_t kk = X.col[k];
-      const double xv = X.val[k];
-      for (int64_t l = Y.rowptr[kk]; l < Y.rowptr[kk + 1]; ++l) {
-        const int32_t J = Y.col[l];
-        const double prod = xv * Y.val[l];
-        if (mark[J] != i) {
-          mark[J] = i;
-          acc[J] = 0.0 + prod;
-          cols.push_back(J);
-        } else {
-          acc[J] = acc[J] + prod;
-        }
-      }
-    }
-    std::sort(cols.begin(), cols.end());
-    for (int32_t J : cols) {
-      Z.col.push_back(J);
-      Z.val.push_back(acc[J]);
-    }
-    Z.rowptr.push_back((int64_t)Z.col.size());
+  for (const Part& pt : parts) {
+    for (int64_t l : pt.len) Z.rowptr.push_back(Z.rowptr.back() + l);
+    Z.col.insert(Z.col.end(), pt.col.begin(), pt.col.end());
+    Z.val.insert(Z.val.end(), pt.val.begin(), pt.val.end());
   }
   return Z;
-}
-
-// Run f(begin, end) over [r0, r1) split into contiguous chunks on threads.
-template <typename F>
-void parallel_rows(int64_t r0, int64_t r1, F&& f) {
-  const int64_t cnt = r1 - r0;
-  if (cnt <= 0) return;
-  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  const int64_t nt = std::min<int64_t>(hw, (cnt + 63) / 64);
-  if (nt <= 1) {
-    f(r0, r1);
-    return;
-  }
-  std::vector<std::thread> th;
-  const int64_t chunk = (cnt + nt - 1) / nt;
-  for (int64_t t = 0; t < nt; ++t) {
-    const int64_t a = r0 + t * chunk, b = std::min(r1, a + chunk);
-    if (a < b) th.emplace_back(f, a, b);
-  }
-  for (auto& x : th) x.join();
 }
 
 // Blocked right-looking LU with partial pivoting (row interchanges), then the
 // explicit inverse from L U X = P I.  Rows of each update are independent, so
 // the result does not depend on the thread count.
 void dense_inverse(std::vector<double>& M, int64_t n, std::vector<double>& inv) {
+  // rows of the dense updates are long: small chunks pay off above n ~ 512
+  const int64_t dense_grain = n >= 512 ? 64 : n + 1;
   const int64_t NB = 64;
   std::vector<int64_t> piv((size_t)n);
   for (int64_t kb = 0; kb < n; kb += NB) {
@@ -365,7 +434,7 @@ void dense_inverse(std::vector<double>& M, int64_t n, std::vector<double>& inv) 
           const double* src = &M[k * n];
           for (int64_t c = ke; c < n; ++c) dst[c] -= l * src[c];
         }
-    });
+    }, dense_grain);
   }
   std::vector<int64_t> perm((size_t)n);
   for (int64_t i = 0; i < n; ++i) perm[i] = i;
@@ -389,7 +458,7 @@ void dense_inverse(std::vector<double>& M, int64_t n, std::vector<double>& inv) 
       const double d = M[r * n + r];
       for (int64_t c = c0; c < c1; ++c) inv[r * n + c] /= d;
     }
-  });
+  }, dense_grain);
 }
 
 }  // namespace
@@ -447,21 +516,19 @@ std::vector<double> jacobi_weights(const HostCSR& A, double omega) {
 HostCSR presmoothed_restriction(const HostCSR& A, const HostCSR& R, double omega) {
   const std::vector<double> w = jacobi_weights(A, omega);
   const HostCSR T = scale_cols(A, w);                 // A W
-  HostCSR I;
-  I.n_rows = I.n_cols = A.n_rows;
-  I.rowptr.resize((size_t)A.n_rows + 1);
-  I.col.resize((size_t)A.n_rows);
-  I.val.assign((size_t)A.n_rows, 1.0);
-  for (int64_t i = 0; i <= A.n_rows; ++i) I.rowptr[i] = i;
-  for (int64_t i = 0; i < A.n_rows; ++i) I.col[i] = (int32_t)i;
-  // I - A M2 = I - 2 A W + (A W)(A W)
-  const HostCSR E = add_scaled(add_scaled(I, T, -2.0), spgemm(T, T), 1.0);
-  return spgemm(R, E);
+  // R (I - A M2) = R - 2 R A W + (R A W)(A W), the product with R first
+  const HostCSR RAW = scale_cols(spgemm(R, A), w);
+  return add_scaled(add_scaled(R, RAW, -2.0), spgemm(RAW, T), 1.0);
 }
 
-HostCSR smoothed_correction(const HostCSR& A, const HostCSR& P, double omega) {
+HostCSR smoothed_correction(const HostCSR& A, const HostCSR& P, const HostCSR& AP,
+                            double omega) {
   const std::vector<double> w = jacobi_weights(A, omega);
-  return add_scaled(P, scale_rows(spgemm(A, P), w), -1.0);
+  return add_scaled(P, scale_rows(AP, w), -1.0);
+}
+
+void parallel_ranges(int64_t r0, int64_t r1, const std::function<void(int64_t, int64_t)>& f) {
+  parallel_rows(r0, r1, f);
 }
 
 HostCSR residual_restriction(const HostCSR& A, const HostCSR& R) {
@@ -527,9 +594,9 @@ void amg_setup_host(const HostCSR& A0, const std::vector<int32_t>& comp0, bool s
     HostLevel& L = h.levels.back();
     L.P = o.smoothed ? smoothed(A, strong, d, agg, n_c) : tentative(agg, n_c);
     L.R = transpose(L.P);
-    HostCSR AP = spgemm(A, L.P);
+    L.AP = spgemm(A, L.P);
     HostLevel next;
-    next.A = spgemm(L.R, AP);
+    next.A = spgemm(L.R, L.AP);
     next.comp.resize((size_t)n_c);
     for (int64_t c = 0; c < n_c; ++c) next.comp[c] = comp[roots[c]];
     L.agg = std::move(agg);

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -63,6 +64,7 @@ struct AMGOpts {
 
 struct HostLevel {
   HostCSR A, P, R;             // P, R empty on the coarsest level
+  HostCSR AP;                  // A P (the first Galerkin factor)
   std::vector<int32_t> agg;    // empty on the coarsest level
   std::vector<int32_t> comp;
 };
@@ -76,6 +78,9 @@ struct HostHierarchy {
 void amg_setup_host(const HostCSR& A, const std::vector<int32_t>& comp,
                     bool singular, const AMGOpts& o, HostHierarchy& h);
 
+// f(a, b) over contiguous sub-ranges of [r0, r1) on up to 16 threads.
+void parallel_ranges(int64_t r0, int64_t r1, const std::function<void(int64_t, int64_t)>& f);
+
 // Q = [R | -R A] (n_c x 2n): the restricted residual R (b - A x) = Q [b; x]
 // in one sparse product, so that a V-cycle level needs no residual vector.
 HostCSR residual_restriction(const HostCSR& A, const HostCSR& R);
@@ -87,7 +92,8 @@ HostCSR residual_restriction(const HostCSR& A, const HostCSR& R);
 //                      post-smoothing sweep: x + P xc followed by one sweep is
 //                      x + W (b - A x) + F xc.
 HostCSR presmoothed_restriction(const HostCSR& A, const HostCSR& R, double omega);
-HostCSR smoothed_correction(const HostCSR& A, const HostCSR& P, double omega);
+HostCSR smoothed_correction(const HostCSR& A, const HostCSR& P, const HostCSR& AP,
+                            double omega);
 
 // 32-bit finaliser of MurmurHash3 (public domain).
 inline uint32_t fmix32(uint32_t h) {

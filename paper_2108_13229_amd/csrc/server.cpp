@@ -121,7 +121,6 @@ void sd_server::retire(Request* r, int status, const std::string& err) {
     (void)hipStreamSynchronize(r->solver->stream);
   }
   r->solver.reset();
-  if (r->d_x) (void)hipFree(r->d_x);
   r->d_x = nullptr;
   r->hp.reset();
   std::lock_guard<std::mutex> lk(mu);
@@ -156,10 +155,7 @@ void sd_server::prep_loop(hipStream_t prep_stream) {
       r->solver.reset(new sd::Solver());
       r->solver->setup_host(r->hp.get(), &r->opts);
       r->solver->upload(nullptr, prep_stream);
-      if (hipMalloc(&r->d_x, (size_t)r->N * sizeof(double)) != hipSuccess) {
-        (void)hipGetLastError();
-        throw sd::Error(SD_E_NOMEM, "hipMalloc failed for the solution vector");
-      }
+      r->d_x = r->solver->mem->array<double>((size_t)r->N);
     } catch (const sd::Error& e) {
       code = e.code;
       msg = e.what();
@@ -170,7 +166,6 @@ void sd_server::prep_loop(hipStream_t prep_stream) {
     std::lock_guard<std::mutex> lk(mu);
     if (code != SD_OK) {
       r->solver.reset();
-      if (r->d_x) (void)hipFree(r->d_x);
       r->d_x = nullptr;
       r->hp.reset();
       r->status = code;
@@ -302,7 +297,8 @@ int sd_server_create(const sd_server_opts* opts, sd_server** out) {
   s->budget = s->opts.hbm_budget ? s->opts.hbm_budget : (size_t)(0.8 * (double)free_b);
   // host preparation (assembly, AMG setup, upload) of several admitted
   // requests runs in parallel
-  const int n_prep = std::max(1, std::min(4, s->opts.max_slots));
+  const int hw = (int)std::max(2u, std::thread::hardware_concurrency());
+  const int n_prep = std::max(1, std::min({8, s->opts.max_slots, hw / 2}));
   for (int k = 0; k < n_prep; ++k) {
     hipStream_t ps = nullptr;
     if (hipStreamCreateWithFlags(&ps, hipStreamNonBlocking) != hipSuccess) return SD_E_DEVICE;
@@ -434,12 +430,10 @@ void sd_server_destroy(sd_server* sv) {
   for (Request* r : sv->active) {
     if (r->solver) (void)hipStreamSynchronize(r->solver->stream);
     r->solver.reset();
-    if (r->d_x) (void)hipFree(r->d_x);
     r->d_x = nullptr;
   }
   for (Request* r : sv->ready) {
     r->solver.reset();
-    if (r->d_x) (void)hipFree(r->d_x);
     r->d_x = nullptr;
   }
   for (hipStream_t ps : sv->prep_streams) (void)hipStreamDestroy(ps);

@@ -7,6 +7,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <map>
 #include <type_traits>
 
 namespace sd {
@@ -17,30 +19,71 @@ double wall_time() {
 }
 
 // ------------------------------------------------------------------ memory
+constexpr size_t kChunkBytes = (size_t)32 << 20;
+
 DeviceMem::~DeviceMem() {
-  for (void* p : ptrs_) {
+  for (void* p : chunks_) {
     if (has_)
       alloc_.free(p, alloc_.ctx, stream_);
     else
-      (void)hipFree(p);
+      (void)hipFreeAsync(p, nullptr);
   }
 }
 
-void* DeviceMem::get(size_t bytes) {
-  bytes = (bytes + 255) & ~(size_t)255;
+void* DeviceMem::chunk(size_t bytes) {
   void* p = nullptr;
   if (has_) {
     p = alloc_.alloc(bytes, alloc_.ctx, stream_);
     if (!p) throw Error(SD_E_NOMEM, "device allocation failed (allocator callback)");
   } else {
-    if (hipMalloc(&p, bytes) != hipSuccess || !p) {
+    if (hipMallocAsync(&p, bytes, stream_) != hipSuccess || !p) {
       (void)hipGetLastError();
-      throw Error(SD_E_NOMEM, "hipMalloc failed");
+      throw Error(SD_E_NOMEM, "hipMallocAsync failed");
     }
   }
-  ptrs_.push_back(p);
-  total_ += bytes;
+  chunks_.push_back(p);
   return p;
+}
+
+void* DeviceMem::get(size_t bytes) {
+  bytes = (bytes + 255) & ~(size_t)255;
+  total_ += bytes;
+  if (bytes > kChunkBytes / 4) return chunk(bytes);   // large arrays: a chunk of their own
+  if (!cur_ || cur_off_ + bytes > cur_cap_) {
+    cur_ = static_cast<char*>(chunk(kChunkBytes));
+    cur_off_ = 0;
+    cur_cap_ = kChunkBytes;
+  }
+  void* p = cur_ + cur_off_;
+  cur_off_ += bytes;
+  return p;
+}
+
+namespace {
+std::mutex g_pinned_mu;
+std::map<std::pair<size_t, bool>, std::vector<void*>> g_pinned_free;
+}  // namespace
+
+void* pinned_acquire(size_t bytes, bool mapped) {
+  {
+    std::lock_guard<std::mutex> lk(g_pinned_mu);
+    auto& v = g_pinned_free[{bytes, mapped}];
+    if (!v.empty()) {
+      void* p = v.back();
+      v.pop_back();
+      return p;
+    }
+  }
+  void* p = nullptr;
+  SD_HIP(hipHostMalloc(&p, bytes,
+                       mapped ? (hipHostMallocMapped | hipHostMallocCoherent) : hipHostMallocDefault));
+  return p;
+}
+
+void pinned_release(void* p, size_t bytes, bool mapped) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_pinned_mu);
+  g_pinned_free[{bytes, mapped}].push_back(p);
 }
 
 // -------------------------------------------------------------------- SELL
@@ -117,27 +160,29 @@ Sell<T> upload_sell(const HostCSR& A, DeviceMem& mem, hipStream_t s, bool allow_
   for (int64_t sl = 0; sl < ns; ++sl) sptr[sl + 1] = (int)(sptr[sl] + C * width[sl]);
   std::vector<int> col((size_t)tot, 0);
   std::vector<T> val((size_t)tot, (T)0);
-  for (int64_t sl = 0; sl < ns; ++sl) {
-    const int64_t w = width[sl];
-    for (int64_t ri = 0; ri < C; ++ri) {
-      const int64_t r = sl * C + ri;
-      int64_t len = 0, beg = 0;
-      if (r < n) {
-        beg = A.rowptr[r];
-        len = A.rowptr[r + 1] - beg;
-      }
-      for (int64_t k = 0; k < w; ++k) {
-        const int64_t e = sptr[sl] + C * k + ri;
-        if (k < len) {
-          col[e] = A.col[beg + k];
-          val[e] = (T)A.val[beg + k];
-        } else {
-          col[e] = len > 0 ? A.col[beg + len - 1] : 0;
-          val[e] = (T)0;
+  parallel_ranges(0, ns, [&](int64_t s0, int64_t s1) {
+    for (int64_t sl = s0; sl < s1; ++sl) {
+      const int64_t w = width[sl];
+      for (int64_t ri = 0; ri < C; ++ri) {
+        const int64_t r = sl * C + ri;
+        int64_t len = 0, beg = 0;
+        if (r < n) {
+          beg = A.rowptr[r];
+          len = A.rowptr[r + 1] - beg;
+        }
+        for (int64_t k = 0; k < w; ++k) {
+          const int64_t e = sptr[sl] + C * k + ri;
+          if (k < len) {
+            col[e] = A.col[beg + k];
+            val[e] = (T)A.val[beg + k];
+          } else {
+            col[e] = len > 0 ? A.col[beg + len - 1] : 0;
+            val[e] = (T)0;
+          }
         }
       }
     }
-  }
+  });
   return copy_sell<T>(sptr, col, val, n, A.n_cols, lpr, uniform ? (int)wmax : 0, mem, s);
 }
 
@@ -214,9 +259,9 @@ Solver::~Solver() {
   for (auto e : prof_ev) (void)hipEventDestroy(e);
   if (ev_join) (void)hipEventDestroy(ev_join);
   if (ev_state) (void)hipEventDestroy(ev_state);
-  if (hs) (void)hipHostFree(hs);
+  pinned_release(hs, sizeof(HostState), false);
   if (stream) (void)hipStreamDestroy(stream);
-  if (hf) (void)hipHostFree((void*)hf);
+  pinned_release((void*)hf, sizeof(HostFlags), true);
 }
 
 void Solver::upload(const sd_allocator* alloc, hipStream_t s) {
@@ -233,8 +278,7 @@ void Solver::upload(const sd_allocator* alloc, hipStream_t s) {
                                      (size_t)kDotBlocks * kPartStride));
   st = static_cast<DevState*>(mem->get(sizeof(DevState)));
   SD_HIP(hipMemsetAsync(st, 0, sizeof(DevState), s));
-  void* h = nullptr;
-  SD_HIP(hipHostMalloc(&h, sizeof(HostFlags), hipHostMallocMapped | hipHostMallocCoherent));
+  void* h = pinned_acquire(sizeof(HostFlags), true);
   hf = static_cast<HostFlags*>(h);
   std::memset(h, 0, sizeof(HostFlags));
   void* hd = nullptr;
@@ -244,8 +288,7 @@ void Solver::upload(const sd_allocator* alloc, hipStream_t s) {
   for (auto& e : events) SD_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   SD_HIP(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
   SD_HIP(hipEventCreateWithFlags(&ev_state, hipEventDisableTiming));
-  void* hsp = nullptr;
-  SD_HIP(hipHostMalloc(&hsp, sizeof(HostState), hipHostMallocDefault));
+  void* hsp = pinned_acquire(sizeof(HostState), false);
   hs = static_cast<HostState*>(hsp);
   std::memset(hsp, 0, sizeof(HostState));
   prof_ev.resize((size_t)2 * kMaxBasis);
@@ -306,7 +349,7 @@ void upload_hierarchy(const HostHierarchy& h, DevHierarchy<T>& d, double omega, 
         D.Q = upload_sell<T>(residual_restriction(H.A, H.R), mem, s, true);
       }
       if (D.fuse_post) {
-        D.F = upload_sell<T>(smoothed_correction(H.A, H.P, omega), mem, s, true, D.A.lpr);
+        D.F = upload_sell<T>(smoothed_correction(H.A, H.P, H.AP, omega), mem, s, true, D.A.lpr);
         D.P = Sell<T>{};
       }
     }

@@ -16,7 +16,10 @@ namespace sd {
       throw ::sd::Error(SD_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-// Device allocations of one handle, through the caller's allocator or hipMalloc.
+// Device allocations of one handle: 256-byte aligned pieces carved from a few
+// large chunks, which come from the caller's allocator or from the
+// stream-ordered pool (hipMallocAsync / hipFreeAsync, no device-wide
+// synchronisation, so handles can come and go while other solves run).
 class DeviceMem {
  public:
   DeviceMem() = default;
@@ -32,12 +35,20 @@ class DeviceMem {
   size_t bytes() const { return total_; }
 
  private:
+  void* chunk(size_t bytes);
   sd_allocator alloc_{};
   bool has_ = false;
   hipStream_t stream_ = nullptr;
-  std::vector<void*> ptrs_;
+  std::vector<void*> chunks_;
+  char* cur_ = nullptr;
+  size_t cur_off_ = 0, cur_cap_ = 0;
   size_t total_ = 0;
 };
+
+// Pinned host blocks (mapped for device writes when asked) reused across
+// solver handles; never returned to the driver before the process ends.
+void* pinned_acquire(size_t bytes, bool mapped);
+void pinned_release(void* p, size_t bytes, bool mapped);
 
 template <typename T>
 struct DevLevel {
