@@ -313,9 +313,10 @@ int Solver::solve(const double* b, double* x, int use_x0, sd_stats* stats, hipSt
 // ===================================================== precision-specific
 namespace {
 
-// Levels below this size are latency bound: their smoothing is fused with
-// the transfers (fewer, wider launches); larger levels keep separate passes.
-constexpr int64_t kFuseRows = 65536;
+// Levels below these sizes are latency bound: their smoothing is fused with
+// the transfers (fewer, wider launches); larger levels keep separate passes,
+// whose one-lane-per-row stencil gathers are coalesced.
+constexpr int64_t kFusePreRows = 196608, kFusePostRows = 65536;
 
 template <typename T>
 void upload_hierarchy(const HostHierarchy& h, DevHierarchy<T>& d, double omega, int nu_pre,
@@ -335,11 +336,8 @@ void upload_hierarchy(const HostHierarchy& h, DevHierarchy<T>& d, double omega, 
     D.b = mem.array<T>((size_t)D.n);
     if (l + 1 < h.levels.size()) {
       D.P = upload_sell<T>(H.P, mem, s, true);
-      // On the finest level the stencil rows read x coalesced (one lane per
-      // row), so the residual and the restriction stay separate there; on
-      // coarser levels, where launches are latency bound, they are fused.
-      D.fuse_pre = l > 0 && nu_pre == 2;
-      D.fuse_post = nu_post >= 1 && (l > 0 || H.A.n_rows < kFuseRows);
+      D.fuse_pre = nu_pre == 2 && (l > 0 || H.A.n_rows < kFusePreRows);
+      D.fuse_post = nu_post >= 1 && (l > 0 || H.A.n_rows < kFusePostRows);
       if (D.fuse_pre) {
         D.G = upload_sell<T>(presmoothed_restriction(H.A, H.R, omega), mem, s, true, 64);
       } else if (l == 0) {
