@@ -399,7 +399,9 @@ __device__ __forceinline__ void sell_dot2(const Sell<TM>& A, const TX* __restric
     aa += A.val[ea] * (TM)x[A.col[ea]];
     ab += A.val[eb] * (TM)x[A.col[eb]];
   }
+#pragma unroll 4
   for (; ea < enda; ea += 64) aa += A.val[ea] * (TM)x[A.col[ea]];
+#pragma unroll 4
   for (; eb < endb; eb += 64) ab += A.val[eb] * (TM)x[A.col[eb]];
   out_a = aa;
   out_b = ab;
