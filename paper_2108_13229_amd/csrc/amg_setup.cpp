@@ -439,26 +439,54 @@ void dense_inverse(std::vector<double>& M, int64_t n, std::vector<double>& inv) 
   std::vector<int64_t> perm((size_t)n);
   for (int64_t i = 0; i < n; ++i) perm[i] = i;
   for (int64_t k = 0; k < n; ++k) std::swap(perm[k], perm[piv[k]]);
-  inv.assign((size_t)(n * n), 0.0);
-  for (int64_t r = 0; r < n; ++r) inv[r * n + perm[r]] = 1.0;
-  // columns are independent: forward (unit L) and backward (U) substitution
+  // A^-1 = U^-1 L^-1 P: B = U^-1 L^-1 column block by column block (columns
+  // are independent), rows in blocks of NB so that each source row is applied
+  // to a block of rows held in cache; then the columns are permuted.
+  std::vector<double> B((size_t)(n * n), 0.0);
+  for (int64_t i = 0; i < n; ++i) B[i * n + i] = 1.0;
   parallel_rows(0, n, [&](int64_t c0, int64_t c1) {
-    for (int64_t r = 0; r < n; ++r)
-      for (int64_t k = 0; k < r; ++k) {
-        const double l = M[r * n + k];
-        if (l == 0.0) continue;
-        for (int64_t c = c0; c < c1; ++c) inv[r * n + c] -= l * inv[k * n + c];
+    // forward: unit lower L; column c of L^-1 vanishes above row c
+    for (int64_t rb0 = c0; rb0 < n; rb0 += NB) {
+      const int64_t rb1 = std::min(n, rb0 + NB);
+      for (int64_t k = c0; k < rb1; ++k) {
+        const int64_t ce = std::min(c1, k + 1);
+        const double* src = &B[k * n];
+        for (int64_t r = std::max(rb0, k + 1); r < rb1; ++r) {
+          const double l = M[r * n + k];
+          if (l == 0.0) continue;
+          double* dst = &B[r * n];
+          for (int64_t c = c0; c < ce; ++c) dst[c] -= l * src[c];
+        }
       }
-    for (int64_t r = n - 1; r >= 0; --r) {
-      for (int64_t k = r + 1; k < n; ++k) {
-        const double u = M[r * n + k];
-        if (u == 0.0) continue;
-        for (int64_t c = c0; c < c1; ++c) inv[r * n + c] -= u * inv[k * n + c];
+    }
+    // backward: U, rows in descending blocks
+    for (int64_t rb1 = n; rb1 > 0; rb1 -= NB) {
+      const int64_t rb0 = std::max<int64_t>(0, rb1 - NB);
+      for (int64_t k = n - 1; k >= rb1; --k) {
+        const double* src = &B[k * n];
+        for (int64_t r = rb0; r < rb1; ++r) {
+          const double u = M[r * n + k];
+          if (u == 0.0) continue;
+          double* dst = &B[r * n];
+          for (int64_t c = c0; c < c1; ++c) dst[c] -= u * src[c];
+        }
       }
-      const double d = M[r * n + r];
-      for (int64_t c = c0; c < c1; ++c) inv[r * n + c] /= d;
+      for (int64_t r = rb1 - 1; r >= rb0; --r) {
+        double* dst = &B[r * n];
+        for (int64_t k = r + 1; k < rb1; ++k) {
+          const double u = M[r * n + k];
+          if (u == 0.0) continue;
+          const double* src = &B[k * n];
+          for (int64_t c = c0; c < c1; ++c) dst[c] -= u * src[c];
+        }
+        const double d = M[r * n + r];
+        for (int64_t c = c0; c < c1; ++c) dst[c] /= d;
+      }
     }
   }, dense_grain);
+  inv.assign((size_t)(n * n), 0.0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t r = 0; r < n; ++r) inv[i * n + perm[r]] = B[i * n + r];
 }
 
 }  // namespace
