@@ -69,9 +69,10 @@ void launch_spmv(const Sell<TM>& A, const TX* x, TY* y, const DevState* gate,
 template <typename T, typename TB>
 void launch_residual(const Sell<T>& A, const TB* b, const double* bscale, const T* x,
                      T* r, const DevState* gate, hipStream_t s);
-// x = w .* (bscale b) (one sweep from zero), or two sweeps from zero fused
+// x = w .* (bscale b) (one sweep from zero), or two sweeps from zero fused;
+// AW = A diag(w) (read only for two sweeps)
 template <typename T, typename TB>
-void launch_jacobi_zero(const Sell<T>& A, const T* wd, const TB* b, const double* bscale,
+void launch_jacobi_zero(const Sell<T>& AW, const T* wd, const TB* b, const double* bscale,
                         T* x, int two_sweeps, const DevState* gate, hipStream_t s);
 // x_out = x_in + w .* (bscale b - A x_in)
 template <typename T, typename TB>
@@ -82,10 +83,10 @@ void launch_jacobi(const Sell<T>& A, const T* wd, const TB* b, const double* bsc
 template <typename T, typename TB>
 void launch_restrict_residual(const Sell<T>& Q, const TB* b, const double* bscale, const T* x,
                               int n_fine, T* bc, const DevState* gate, hipStream_t s);
-// Two damped-Jacobi sweeps from zero on A (x) and bc = G b, one launch
-// (G = R (I - A M2) from presmoothed_restriction, 64 lanes per row)
+// Two damped-Jacobi sweeps from zero (x; AW = A diag(w)) and bc = G b, one
+// launch (G = R (I - A M2) from presmoothed_restriction, 64 lanes per row)
 template <typename T, typename TB>
-void launch_presmooth_restrict(const Sell<T>& A, const T* wd, const Sell<T>& G, const TB* b,
+void launch_presmooth_restrict(const Sell<T>& AW, const T* wd, const Sell<T>& G, const TB* b,
                                const double* bscale, T* x, T* bc, const DevState* gate,
                                hipStream_t s);
 // xout = x + w .* (bscale b - A x) + F xc (F = P - W A P, stored with A's lanes)

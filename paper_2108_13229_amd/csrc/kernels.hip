@@ -211,8 +211,8 @@ __global__ __launch_bounds__(kBlock) void k_restrict_residual(Sell<T> Q, const T
 
 // Pre-smoothing and restriction in one launch, both from b alone: the first
 // nb_a workgroups run two damped-Jacobi sweeps from zero on the rows of A
-// (x = (2W - W A W) b), the others compute bc = G b with G = R (I - A M2)
-// (one wavefront per row: G's rows are long).
+// (x = (2W - W A W) b, with A passed as A diag(w)), the others compute
+// bc = G b with G = R (I - A M2) (one wavefront per row: G's rows are long).
 template <int LA, typename T, typename TB>
 __global__ __launch_bounds__(kBlock) void k_presmooth_restrict(Sell<T> A, const T* __restrict__ wd,
                                                                Sell<T> G, const TB* __restrict__ b,
@@ -227,7 +227,7 @@ __global__ __launch_bounds__(kBlock) void k_presmooth_restrict(Sell<T> A, const 
     const int row = rs.x, sub = rs.y;
     if (row >= A.n_rows) return;
     const T bi = load_b<T>(b, s, row);
-    const T acc = row_sum<LA>(A, row, sub, [&](int c) { return wd[c] * load_b<T>(b, s, c); });
+    const T acc = row_sum<LA>(A, row, sub, [&](int c) { return load_b<T>(b, s, c); });
     if (sub == 0 && !stop) x[row] = wd[row] * bi + wd[row] * (bi - acc);
   } else {
     const int2 rs = row_of_thread<64>(blockIdx.x - nb_a, gridDim.x - nb_a);
@@ -276,7 +276,9 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_zero(Sell<T> A, const T* __re
     if (rs.y == 0 && !stop) x[row] = x1;
     return;
   }
-  const T acc = row_sum<LPR>(A, row, rs.y, [&](int c) { return wd[c] * load_b<T>(b, s, c); });
+  // A holds A diag(w) here, so the first sweep's values w_c b_c at the
+  // neighbours cost one gather each
+  const T acc = row_sum<LPR>(A, row, rs.y, [&](int c) { return load_b<T>(b, s, c); });
   if (rs.y == 0 && !stop) x[row] = x1 + wd[row] * (bi - acc);
 }
 

@@ -327,14 +327,21 @@ void upload_hierarchy(const HostHierarchy& h, DevHierarchy<T>& d, double omega, 
     DevLevel<T>& D = d.lev[l];
     D.n = (int)H.A.n_rows;
     D.A = upload_sell<T>(H.A, mem, s, true);
+    std::vector<double> w((size_t)D.n);
+    for (int i = 0; i < D.n; ++i) w[i] = omega / diag_at(H.A, i);
     std::vector<T> wd((size_t)D.n);
-    for (int i = 0; i < D.n; ++i) wd[i] = (T)(omega / diag_at(H.A, i));
+    for (int i = 0; i < D.n; ++i) wd[i] = (T)w[i];
     D.wd = mem.array<T>((size_t)D.n);
     SD_HIP(hipMemcpyAsync(D.wd, wd.data(), wd.size() * sizeof(T), hipMemcpyHostToDevice, s));
     D.tmp = mem.array<T>((size_t)D.n);
     D.x = mem.array<T>((size_t)D.n);
     D.b = mem.array<T>((size_t)D.n);
     if (l + 1 < h.levels.size()) {
+      if (nu_pre >= 2) {
+        HostCSR AW = H.A;
+        for (size_t k = 0; k < AW.val.size(); ++k) AW.val[k] = H.A.val[k] * w[AW.col[k]];
+        D.AW = upload_sell<T>(AW, mem, s, true, D.A.lpr);
+      }
       D.P = upload_sell<T>(H.P, mem, s, true);
       D.fuse_pre = nu_pre == 2 && (l > 0 || H.A.n_rows < kFusePreRows);
       D.fuse_post = nu_post >= 1 && (l > 0 || H.A.n_rows < kFusePostRows);
@@ -410,12 +417,13 @@ class PrecImpl : public PrecBase {
     T* other = L.tmp;
     DevLevel<T>& C = h.lev[l + 1];
     if (L.fuse_pre) {
-      launch_presmooth_restrict<T, TB>(L.A, L.wd, L.G, b, bs, cur, C.b, gate, s);
+      launch_presmooth_restrict<T, TB>(L.AW, L.wd, L.G, b, bs, cur, C.b, gate, s);
     } else {
       if (nu_pre == 0) {
         launch_fill<T>(cur, (T)0, L.n, s);
       } else {
-        launch_jacobi_zero<T, TB>(L.A, L.wd, b, bs, cur, nu_pre >= 2 ? 1 : 0, gate, s);
+        launch_jacobi_zero<T, TB>(nu_pre >= 2 ? L.AW : L.A, L.wd, b, bs, cur, nu_pre >= 2 ? 1 : 0,
+                                  gate, s);
         for (int k = 2; k < nu_pre; ++k) {
           launch_jacobi<T, TB>(L.A, L.wd, b, bs, cur, other, gate, s);
           std::swap(cur, other);
