@@ -107,6 +107,10 @@ def test_invalid_inputs_are_rejected():
         sd.Solver(P, device=False, tol=0.0)
     with pytest.raises(sd.SDError):
         sd.Solver(P, device=True)        # host-only problem cannot get device data
+    for bad in (dict(precision=3), dict(precision=-1), dict(nu_pre=-1), dict(coarse_max=0),
+                dict(mis=3), dict(omega=0.0)):
+        with pytest.raises(sd.SDError):
+            sd.Solver(P, device=False, **bad)
     assert sd.lib().sd_status_string(-4) == b"SD_E_NOCONV"
 
 

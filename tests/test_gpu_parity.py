@@ -80,6 +80,25 @@ def test_vcycle_parity(name, kind):
         assert np.max(np.abs(x - ref)) <= 1e-11 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("nu_pre,nu_post", [(1, 1), (3, 2), (2, 0), (0, 2)])
+def test_vcycle_parity_other_sweep_counts(nu_pre, nu_post):
+    """Sweep counts other than 2 + 2 take the unfused level kernels (separate
+    sweeps, the [R | -R A] restriction, plain prolongation)."""
+    p = SMALL["channel96"]()
+    print("case sweeps", nu_pre, nu_post, flush=True)
+    a = assemble(p)
+    opts = amg.AMGOptions(nu_pre=nu_pre, nu_post=nu_post)
+    M = precond.build(p, a, "BGS", opts=opts)
+    P, S = _setup(p, nu_pre=nu_pre, nu_post=nu_post)
+    rng = np.random.default_rng(13)
+    for blk, h in [(0, M.hV), (1, M.hD)]:
+        n = h.levels[0].A.shape[0]
+        b = rng.standard_normal(n)
+        x = _host(S.apply_vcycle(blk, _dev(b)))
+        ref = amg.vcycle(h, b)
+        assert np.linalg.norm(x - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
 @pytest.mark.parametrize("name", ["mms32", "channel96", "channel_ragged"])
 @pytest.mark.parametrize("variant,schur", [("BGS", "mass"), ("BJ", "mass"), ("BGS", "identity")])
 def test_block_preconditioner_parity(name, variant, schur):
