@@ -17,4 +17,5 @@ Modules
   krylov    FGMRES(m) with classical Gram-Schmidt twice, BiCGSTAB, and the
             mixed-precision iterative-refinement driver
   hashing   the 32-bit integer finaliser used for aggregation priorities
+  transient backward-Euler steps of the transient free flow (Sec. 2)
 """

@@ -1,6 +1,9 @@
 """Assembly of the monolithic coupled Stokes-Darcy system (oracle).
 
-Follows Sec. 2 of the paper: stationary creeping Stokes flow in symmetric
+Test infrastructure: only the tests, the smoke check and the benchmark's CPU
+baseline use this package; the library never does.
+
+Follows Sec. 2 of the paper: creeping Stokes flow in symmetric
 gradient form (momentum flux (pI - tau) n with tau = mu (grad v + grad v^T),
 rho = 1), Darcy's law with continuity in the porous medium, and at the
 interface the normal-stress balance, the Beavers-Joseph-Saffman slip
@@ -27,7 +30,15 @@ momentum / mass fluxes = source x |CV|"):
   dx [p_{i,0} - 2 mu (v_{i,1} - v_{i,0})/dy - q_top + (mu/K_top)(dy_pm/2) v_{i,0}] = 0;
 * mass-flux continuity: the porous top cell's outward interface flux is
   dx * v_{i,0}, the same unknown as the free-flow normal velocity;
-* Dirichlet velocity faces are eliminated and lifted into b.
+* Dirichlet velocity faces are eliminated and lifted into b;
+* time (dt > 0): the transient momentum equation of Sec. 2 with the paper's
+  first-order backward Euler step.  A momentum row integrates dv/dt over its
+  control volume, which adds |CV|/dt to the diagonal of every interior u and
+  v face row (rho = 1); b then holds the data part only, and one step's
+  right-hand side adds (|CV|/dt) v^n on those rows (``oracle.transient``).
+  The outflow u rows and the Gamma rows are boundary and interface
+  conditions, not momentum balances of a control volume, and the Darcy
+  equations carry no storage term, so none of these rows gets one.
 
 Floating-point evaluation order of every coefficient is fixed (see the
 named coefficients below); the assembled values are reproducible bit-for-bit
@@ -122,6 +133,7 @@ class Assembled:
     b: np.ndarray
     layout: Layout
     pm_singular: bool          # D' has the constant vector in its kernel
+    mass: np.ndarray = None    # |CV|/dt on the rows with a time derivative
 
     @property
     def N(self):
@@ -150,6 +162,11 @@ def assemble(p: Problem) -> Assembled:
     dyp = p.H_pm / nyp
     vol = dx * dy
     volp = dx * dyp
+    dt = float(p.dt)
+    if not (math.isfinite(dt) and dt >= 0.0):
+        raise ValueError("dt must be finite and >= 0")
+    mvol = vol / dt if dt > 0.0 else 0.0   # backward-Euler mass coefficient
+    mass = np.zeros(L.N)
     # named coefficients (fixed evaluation order)
     cx = (2.0 * mu) * (dy / dx)          # u rows, normal stress E/W
     cy = mu * (dx / dy)                  # u rows, shear N/S
@@ -201,6 +218,9 @@ def assemble(p: Problem) -> Assembled:
     aN = np.where(top, cyt, cy)
     aS = np.where(gam, cg, cy)
     diag = ((cx + cx) + aN) + aS
+    if dt > 0.0:
+        diag = diag + mvol
+        mass[r.ravel()] = mvol
     add(r, r, diag)
     add(r, L.u(i - 1, j), -cx, i - 1 >= 1)
     east_unknown = (i + 1 <= nx - 1) | right_tr
@@ -240,6 +260,9 @@ def assemble(p: Problem) -> Assembled:
     aE = np.where(east, 0.0 if right_tr else cxw, cxv)
     aW = np.where(west, cxw, cxv)
     diag = ((cyy + cyy) + aE) + aW
+    if dt > 0.0:
+        diag = diag + mvol
+        mass[r.ravel()] = mvol
     add(r, r, diag)
     add(r, L.v(i, np.minimum(j + 1, ny - 1)), -cyy, j + 1 <= ny - 1)
     add(r, L.v(i, j - 1), -cyy)
@@ -337,7 +360,7 @@ def assemble(p: Problem) -> Assembled:
     A.sort_indices()
     pm_singular = (p.pm_left == BC_NOFLOW and p.pm_right == BC_NOFLOW
                    and p.pm_bottom == BC_NOFLOW)
-    return Assembled(A=A, b=b, layout=L, pm_singular=pm_singular)
+    return Assembled(A=A, b=b, layout=L, pm_singular=pm_singular, mass=mass)
 
 
 def split_solution(x: np.ndarray, L: Layout):

@@ -30,7 +30,9 @@ BC_NOFLOW = "noflow"
 
 @dataclasses.dataclass
 class Problem:
-    """Everything that defines one stationary coupled solve.
+    """Everything that defines one coupled solve: a stationary problem, or
+    (dt > 0) the linear system of one backward-Euler time step, whose
+    right-hand side the data below give without the previous-step term.
 
     Boundary data conventions (all optional, ``None`` means zero):
       ff_left_n  [ny]     normal velocity u at the left faces (x = 0)
@@ -73,6 +75,7 @@ class Problem:
     f_u: Optional[np.ndarray] = None
     f_v: Optional[np.ndarray] = None
     q_pm: Optional[np.ndarray] = None
+    dt: float = 0.0                          # backward-Euler step, 0 = stationary
 
     @property
     def dx(self) -> float:
@@ -252,6 +255,27 @@ def mms_problem(nx: int, ny: int, ny_pm: Optional[int] = None, K: float = 1e-2,
     return p, m
 
 
+def mms_transient_problem(nx: int, ny: int, dt: float, t: float, g, dg,
+                          **kw) -> tuple[Problem, MMS]:
+    """Time-scaled manufactured solution (u, v, p, P)(x, y, t) =
+    g(t) (u, v, p, P)(x, y) at time ``t``: the boundary data and the porous
+    source of ``mms_problem`` times g(t); the free-flow forcing times g(t) plus
+    dg(t) (u, v), the velocity's time derivative (the porous medium has no
+    storage term).  ``dt`` is the step the matrix is assembled for."""
+    p, m = mms_problem(nx, ny, **kw)
+    gt, dgt = float(g(t)), float(dg(t))
+    for name in ("ff_left_n", "ff_left_t", "ff_right_n", "ff_right_t",
+                 "ff_top_t", "ff_top_n", "pm_left_p", "pm_right_p",
+                 "pm_bottom_p", "q_pm"):
+        setattr(p, name, gt * getattr(p, name))
+    xu, yu = u_face_xy(p)
+    xv, yv = v_face_xy(p)
+    p.f_u = gt * p.f_u + dgt * m.u(xu, yu)
+    p.f_v = gt * p.f_v + dgt * m.v(xv, yv)
+    p.dt = float(dt)
+    return p, m
+
+
 # ----------------------------------------------------------------------------
 # Channel flow over a heterogeneous porous bed
 # ----------------------------------------------------------------------------
@@ -280,7 +304,12 @@ def channel_problem(nx: int, ny: int, ny_pm: Optional[int] = None, *,
 
 def config_problem(name: str) -> Problem:
     """C0: 32x16 manufactured solution; C1: 512x256 channel (seed 1);
-    C2: 1024x512 channel (seed 2); small channel cases for tests."""
+    C2: 1024x512 channel (seed 2); T1: the C1 channel as the system of one
+    backward-Euler step of 0.1 (its flow started from rest)."""
+    if name == "T1":
+        p = channel_problem(512, 256, seed=1)
+        p.dt = 0.1
+        return p
     if name == "C0":
         return mms_problem(32, 16)[0]
     if name == "C1":
