@@ -171,6 +171,8 @@ def aggregate(A: sp.csr_matrix, S: sp.csr_matrix, level: int, mis_dist: int):
     Aabs = abs(A.tocsr())
 
     def wfun(r, c):
+        if r.size == 0:          # no candidate left (sparse indexing would give 1 x 0)
+            return np.zeros(0)
         return np.asarray(Aabs[r, c]).ravel()
 
     is_root = state == ROOT

@@ -17,6 +17,17 @@ diagonal block: the paper's identity, or the inverse of a viscosity-scaled
 pressure mass matrix, X = mu M_p^-1 with M_p = diag(dx dy) (the Schur
 complement B^T V^-1 B is approximated by M_p / mu; with C = -B^T its sign is
 positive).
+
+For the system of one backward-Euler step (mass |CV|/dt on the velocity
+diagonal) M_p / mu only describes the Schur complement of the viscous part:
+once sqrt(nu dt) is small against the domain, the mass term governs the
+smooth pressure modes and FGMRES with X = mu M_p^-1 stalls.  The third choice
+is the Cahouet-Chabard approximation (Cahouet & Chabard, "Some fast 3D finite
+element solvers for the generalized Stokes problem", 1988), the sum of the
+inverses of the viscous and the mass parts of the Schur complement:
+X = mu M_p^-1 + L_p^-1 with L_p = B^T D^-1 B, D the velocity mass |CV|/dt on
+the rows with a time derivative and V's own diagonal on the others (Gamma
+and outflow faces, which have none); L_p^-1 is one AMG V-cycle.
 """
 from __future__ import annotations
 
@@ -30,6 +41,7 @@ from .assemble import Assembled
 
 SCHUR_IDENTITY = "identity"
 SCHUR_MASS = "mass"
+SCHUR_CC = "cc"
 
 
 @dataclasses.dataclass
@@ -41,8 +53,9 @@ class BlockPreconditioner:
     C: object                  # continuity rows x velocity columns
     C1: object                 # porous rows x velocity columns
     off: np.ndarray            # [0, off_v, off_p, off_q, N]
-    xscale: float              # X = xscale * I
+    xscale: float              # X = xscale * I (+ L_p^-1 with SCHUR_CC)
     dtype: type = np.float64
+    hL: amg_mod.Hierarchy = None   # AMG hierarchy of L_p (SCHUR_CC only)
 
     def __post_init__(self):
         dt = self.dtype
@@ -50,6 +63,13 @@ class BlockPreconditioner:
         self._C1 = self.C1.astype(dt)
         self._mV = amg_mod.level_mats(self.hV, dt)
         self._mD = amg_mod.level_mats(self.hD, dt)
+        self._mL = None if self.hL is None else amg_mod.level_mats(self.hL, dt)
+
+    def middle(self, t: np.ndarray) -> np.ndarray:
+        y = self.dtype(self.xscale) * t
+        if self.hL is not None:
+            y = y + amg_mod.vcycle(self.hL, t, self.dtype, mats=self._mL)
+        return y
 
     def __call__(self, r: np.ndarray) -> np.ndarray:
         dt = self.dtype
@@ -57,12 +77,11 @@ class BlockPreconditioner:
         r = r.astype(dt)
         rv, rp, rq = r[o[0]:o[2]], r[o[2]:o[3]], r[o[3]:o[4]]
         yv = amg_mod.vcycle(self.hV, rv, dt, mats=self._mV)
-        s = dt(self.xscale)
         if self.variant == "BJ":
-            yp = s * rp
+            yp = self.middle(rp)
             yq = amg_mod.vcycle(self.hD, rq, dt, mats=self._mD)
         elif self.variant == "BGS":
-            yp = s * (rp - self._C @ yv)
+            yp = self.middle(rp - self._C @ yv)
             yq = amg_mod.vcycle(self.hD, rq - self._C1 @ yv, dt, mats=self._mD)
         else:
             raise ValueError(self.variant)
@@ -95,6 +114,23 @@ def darcy_interface_block(blk) -> "sp.csr_matrix":
     return D
 
 
+def pressure_operator(a: Assembled) -> "sp.csr_matrix":
+    """L_p = B^T D^-1 B = -C D^-1 B on the free-flow pressure cells, with
+    D = |CV|/dt on the velocity rows with a time derivative and diag(V) on the
+    others.  Evaluated as ((-C) diag(1/D)) B."""
+    if a.mass is None or not np.any(a.mass):
+        raise ValueError("the Cahouet-Chabard middle block needs a backward-Euler system")
+    blk = a.blocks()
+    o = a.layout.block_off
+    m = a.mass[o[0]:o[2]]
+    Vd = blk["V"].diagonal()
+    d = np.where(m != 0.0, m, Vd)
+    L = ((-blk["C"]) @ sp.diags(1.0 / d)) @ blk["B"]
+    L = L.tocsr()
+    L.sort_indices()
+    return L
+
+
 def build(p, a: Assembled, variant: str = "BGS", schur: str = SCHUR_MASS,
           opts: amg_mod.AMGOptions | None = None, dtype=np.float64) -> BlockPreconditioner:
     opts = opts or amg_mod.AMGOptions()
@@ -103,10 +139,14 @@ def build(p, a: Assembled, variant: str = "BGS", schur: str = SCHUR_MASS,
     Dt = darcy_interface_block(blk)
     hD = amg_mod.setup(Dt, np.zeros(Dt.shape[0], dtype=np.int32), False, opts)
     vol = (p.Lx / p.nx) * (p.H_ff / p.ny)
-    xscale = p.mu / vol if schur == SCHUR_MASS else 1.0
+    xscale = p.mu / vol if schur in (SCHUR_MASS, SCHUR_CC) else 1.0
+    hL = None
+    if schur == SCHUR_CC:
+        Lp = pressure_operator(a)
+        hL = amg_mod.setup(Lp, np.zeros(Lp.shape[0], dtype=np.int32), False, opts)
     return BlockPreconditioner(variant=variant, schur=schur, hV=hV, hD=hD,
                                C=blk["C"], C1=blk["C1"], off=a.layout.block_off,
-                               xscale=xscale, dtype=dtype)
+                               xscale=xscale, dtype=dtype, hL=hL)
 
 
 def exact_block_preconditioner(a: Assembled, variant: str, S_inv):

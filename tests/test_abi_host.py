@@ -37,8 +37,15 @@ def _cases():
     p_mixbc = channel_problem(30, 12, 14, seed=11)
     p_mixbc.pm_left = "pressure"
     p_mixbc.pm_left_p = np.linspace(1.0, 2.0, 14)
+    p_tr = channel_problem(40, 20, 12, seed=4)
+    p_tr.dt = 0.1                                    # one backward-Euler step
+    p_vel_tr = channel_problem(20, 10, 8, seed=9)
+    p_vel_tr.ff_right = "velocity"
+    p_vel_tr.ff_right_n = np.linspace(0.0, 1e-3, 10)
+    p_vel_tr.dt = 3e-4
     return [mms_problem(32, 16)[0], mms_problem(24, 12, 9, K=3e-3, mu=0.5, alpha=0.7)[0],
-            channel_problem(64, 32, seed=1), channel_problem(45, 22, 17, seed=5), p_vel, p_mixbc]
+            channel_problem(64, 32, seed=1), channel_problem(45, 22, 17, seed=5), p_vel, p_mixbc,
+            p_tr, p_vel_tr]
 
 
 @pytest.mark.parametrize("p", _cases())
@@ -55,7 +62,7 @@ def test_host_assembly_bit_exact(p):
 
 @pytest.mark.parametrize("amg_kind,mis", [("smoothed", 2), ("plain", 1), ("smoothed", 1),
                                           ("plain", 2)])
-@pytest.mark.parametrize("pi", [0, 2, 3])
+@pytest.mark.parametrize("pi", [0, 2, 3, 6])
 def test_host_amg_bit_exact(amg_kind, mis, pi):
     p = _cases()[pi]
     P = sd.Problem(p, device=False)
@@ -99,6 +106,12 @@ def test_invalid_inputs_are_rejected():
     p.ff_top = "traction"
     with pytest.raises(sd.SDError):
         sd.Problem(p, device=False)
+    for dt in (-0.1, float("nan"), float("inf")):
+        p = channel_problem(16, 8, seed=1)
+        p.dt = dt
+        with pytest.raises(sd.SDError) as e:
+            sd.Problem(p, device=False)
+        assert e.value.code == sd.SD_E_INVALID
     p = channel_problem(16, 8, seed=1)
     P = sd.Problem(p, device=False)
     with pytest.raises(sd.SDError):

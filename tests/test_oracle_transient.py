@@ -120,3 +120,85 @@ def test_zero_dt_is_the_stationary_assembly():
     with pytest.raises(ValueError):
         p.dt = -1.0
         assemble(p)
+
+
+# ---- Cahouet-Chabard middle block for backward-Euler systems ----
+
+from sdinputs import mms_problem  # noqa: E402
+from oracle import krylov, precond  # noqa: E402
+
+
+def test_pressure_operator_is_the_scaled_pressure_laplacian():
+    """Away from Gamma and the outflow, L_p = B^T D^-1 B with D = dx dy / dt
+    is dt times the 5-point pressure Laplacian with unit-ratio weights
+    (dy/dx, dx/dy); at walls and inflow faces (eliminated velocities) it has
+    Neumann rows (zero row sums)."""
+    p = channel_problem(12, 8, 6, seed=2)
+    p.dt = 0.3
+    a = assemble(p)
+    Lp = precond.pressure_operator(a).toarray()
+    dx, dy = p.Lx / p.nx, p.H_ff / p.ny
+    assert np.array_equal(Lp, Lp.T)
+    cell = lambda i, j: j * p.nx + i
+    for j in range(1, p.ny):                   # rows off Gamma
+        for i in range(0, p.nx - 1):           # cells off the outflow
+            c = cell(i, j)
+            nb = {}
+            if i > 0:
+                nb[cell(i - 1, j)] = 0.3 * dy / dx
+            nb[cell(i + 1, j)] = 0.3 * dy / dx
+            nb[cell(i, j - 1)] = 0.3 * dx / dy
+            if j + 1 < p.ny:
+                nb[cell(i, j + 1)] = 0.3 * dx / dy
+            row = Lp[c]
+            for k, w in nb.items():
+                assert row[k] == pytest.approx(-w, rel=1e-12)
+            assert row[c] == pytest.approx(sum(nb.values()), rel=1e-12)
+            assert np.count_nonzero(row) == len(nb) + 1
+            assert abs(row.sum()) <= 1e-12 * row[c]
+    assert np.all(np.linalg.eigvalsh(Lp) > 0)
+
+
+@pytest.mark.parametrize("maker", ["channel", "mms"])
+def test_cahouet_chabard_spectral_equivalence(maker):
+    """The preconditioned Schur complement X S (S = B^T V^-1 B exact, X the
+    Cahouet-Chabard block with an exact L_p solve) keeps its spectrum in a
+    fixed interval as dt shrinks and h halves; mu M_p^-1 alone lets the
+    smallest eigenvalue go to zero with dt."""
+    for n in (16, 32):
+        for dt in (1e-4, 1e-2):
+            p = channel_problem(n, n // 2, seed=2) if maker == "channel" else mms_problem(n, n // 2)[0]
+            p.dt = dt
+            a = assemble(p)
+            blk = a.blocks()
+            V, B = blk["V"].toarray(), blk["B"].toarray()
+            S = B.T @ np.linalg.solve(V, B)
+            vol = (p.Lx / p.nx) * (p.H_ff / p.ny)
+            X = (p.mu / vol) * np.eye(S.shape[0]) + np.linalg.inv(
+                precond.pressure_operator(a).toarray())
+            ev = np.linalg.eigvals(X @ S)
+            assert np.abs(ev.imag).max() <= 1e-8 * np.abs(ev).max()
+            assert 0.25 <= ev.real.min() and ev.real.max() <= 6.0, (n, dt, ev.real.min(),
+                                                                     ev.real.max())
+            ev0 = np.linalg.eigvals((p.mu / vol) * S).real
+            if dt == 1e-4:
+                assert ev0.min() < 0.01
+
+
+def test_cahouet_chabard_fgmres_iterations_do_not_grow_with_h():
+    its = []
+    for n in (96, 192):
+        p = channel_problem(n, n // 2, seed=3)
+        p.dt = 0.1
+        a = assemble(p)
+        M = precond.build(p, a, "BGS", schur=precond.SCHUR_CC)
+        r = krylov.fgmres(a.A, a.b, M, tol=1e-8, m=30, maxit=300)
+        assert r.converged
+        its.append(r.iters)
+    assert its[1] <= its[0] + 8 and its[1] <= 70, its
+
+
+def test_cahouet_chabard_rejects_stationary_systems():
+    p = channel_problem(16, 8, seed=3)
+    with pytest.raises(ValueError):
+        precond.build(p, assemble(p), "BGS", schur=precond.SCHUR_CC)
