@@ -11,12 +11,16 @@ x = 0 with the matrix and the AMG hierarchy resident in HBM.  FP64 is the
 headline; the mixed-precision solvers are reported beside it ("mixed": FP32
 preconditioner, FP64 Arnoldi product and outer residual; "mixed32": the
 Arnoldi product in FP32 too).  --config C2: the same physics at 1024 x 512
-(seed 2, N = 2,097,152), mixed precision as the headline.  Inputs are
+(seed 2, N = 2,097,152), mixed precision as the headline.  --config T1:
+the C1 channel as a transient flow started from rest, 20 backward-Euler
+steps of dt = 0.1 with the hierarchies set up once and every step
+warm-started from the previous state (Cahouet-Chabard middle block); one
+step = one time step.  Inputs are
 synthetic and seeded.  With the CPU leg on, the oracle also provides an FP64
 reference solution (its FGMRES to relative residual 1e-12) against which the
 per-block errors of every GPU solution are reported.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config C1|C2] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config C1|C2|T1] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -48,7 +52,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="C1", choices=["C1", "C2"])
+    ap.add_argument("--config", default="C1", choices=["C1", "C2", "T1"])
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the CPU oracle leg (baseline timing and reference solution)")
     ap.add_argument("--no-mixed", action="store_true")
@@ -220,6 +224,81 @@ def serving(sd, args):
     print(json.dumps(out))
 
 
+WORKLOAD_T1 = ("512x256 free-flow + 512x256 porous cells (N=524288), lognormal K seed 1, "
+               "flow from rest, backward Euler dt=0.1, hierarchies set up once; "
+               "BGS(SA-AMG V-cycle, Cahouet-Chabard mu*Mp^-1 + SA-AMG(B^T D^-1 B), SA-AMG "
+               "V-cycle) + FGMRES(m) warm-started, rel. residual 1e-8 per step")
+
+
+def transient(sd, args, p):
+    """Backward-Euler time stepping: args.steps steps (default 20) from rest
+    on the step matrix, timed as one sd_advance call after an untimed warm-up
+    run of args.warmup steps."""
+    import torch
+    n_steps = args.steps
+    t0 = time.perf_counter()
+    P = sd.Problem(p, device=True)
+    t_asm = time.perf_counter() - t0
+    res = {}
+    roof = None
+    for prec in ["fp64"] if args.no_mixed else ["fp64", "mixed"]:
+        t0 = time.perf_counter()
+        S = sd.Solver(P, precond="BGS", schur="cc", tol=1e-8, restart=args.restart,
+                      precision=prec)
+        t_setup = time.perf_counter() - t0
+        if args.warmup > 0:
+            xw = torch.zeros(P.N, dtype=torch.float64, device="cuda")
+            S.advance(xw, args.warmup)
+        x = torch.zeros(P.N, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats, done, rc = S.advance(x, n_steps)
+        torch.cuda.synchronize()
+        span = time.perf_counter() - t0
+        if rc != 0:
+            raise RuntimeError(f"time step {done + 1} failed (status {rc})")
+        res[prec] = dict(steps_per_s=n_steps / span, ms_per_step=1e3 * span / n_steps,
+                         iters_per_step=[s["iters"] for s in stats],
+                         max_rel_res=max(s["rel_res"] for s in stats), setup_s=t_setup)
+        if prec == "fp64" and args.roofline_solves > 0:
+            roof = roofline(S, args.roofline_solves, prec, "T1")
+        S.close()
+    # the viscous Schur block alone on the same step system (first step)
+    S = sd.Solver(P, precond="BGS", schur="mass", tol=1e-8, restart=args.restart, maxit=300)
+    x0, st, rc = S.solve()
+    S.close()
+    head = res["fp64"]
+    out = {
+        "metric": "backward-Euler time steps/s to rel. residual 1e-8 per step",
+        "value": head["steps_per_s"], "unit": "steps/s", "n_gpus": 1,
+        "steps": n_steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": WORKLOAD_T1, "N": P.N, "nnz": P.nnz, "dt": p.dt,
+                   "assembly_s": t_asm, "precision": "fp64"},
+        "restart": args.restart, "fp64": res.get("fp64"), "mixed": res.get("mixed"),
+        "viscous_schur_only_step1": {"iters": st["iters"], "status": rc,
+                                     "rel_res": st["rel_res"], "maxit": 300},
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        from threadpoolctl import threadpool_limits
+        from oracle import krylov, precond
+        from oracle.assemble import assemble
+        with threadpool_limits(limits=1):
+            a = assemble(p)
+            M = precond.build(p, a, "BGS", schur=precond.SCHUR_CC)
+            t0 = time.perf_counter()
+            r = krylov.fgmres(a.A, a.b, M, tol=1e-8, m=args.restart)
+            t1 = time.perf_counter() - t0
+        out["cpu_baseline"] = dict(
+            value=1.0 / t1, unit="steps/s", cores=1, kind="oracle",
+            sample=f"the first time step (from rest) of the same workload: oracle FGMRES with "
+                   f"the same preconditioner, {r.iters} iterations, {t1:.1f} s; assembly and "
+                   f"AMG setup not included; 1 thread")
+    print(json.dumps(out))
+
+
 def cpu_baseline(p, restart, timed=True):
     """The oracle's FP64 FGMRES with the same preconditioner, one solve,
     single-threaded (setup excluded; timed separately); then, with every
@@ -264,6 +343,9 @@ def main():
         serving(sd, args)
         return
     p = config_problem(args.config)
+    if args.config == "T1":
+        transient(sd, args, p)
+        return
     if args.counter_run:
         counter_run(sd, p, args.restart)
         return

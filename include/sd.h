@@ -2,8 +2,9 @@
  * sd.h -- C ABI of the MI355X coupled Stokes-Darcy solver.
  *
  * The library assembles the monolithic system of the paper's Sec. 2 (free
- * flow: stationary creeping Stokes in symmetric-gradient form on a staggered
- * grid; porous medium: Darcy's law with two-point fluxes; interface Gamma:
+ * flow: creeping Stokes in symmetric-gradient form on a staggered grid,
+ * stationary or one backward-Euler step of the transient equations; porous
+ * medium: Darcy's law with two-point fluxes; interface Gamma:
  * normal-stress balance, Beavers-Joseph-Saffman slip, normal mass-flux
  * continuity) in the pressure-velocity block form
  *
@@ -76,6 +77,7 @@ typedef struct {
 typedef struct {
   double mu;                  /* dynamic viscosity (rho = 1, nu = mu)          */
   double alpha_bj;            /* Beavers-Joseph coefficient                    */
+  double dt;                  /* backward-Euler time step; 0 = stationary      */
 } sd_physics;
 
 typedef enum { SD_BC_VELOCITY = 0, SD_BC_TRACTION = 1, SD_BC_PRESSURE = 2,
@@ -128,7 +130,15 @@ int sd_problem_csr(const sd_problem* pb, const int64_t** rowptr,
 
 enum { SD_KRYLOV_FGMRES = 0, SD_KRYLOV_BICGSTAB = 1 };
 enum { SD_PREC_BJ = 0, SD_PREC_BGS = 1 };
-enum { SD_SCHUR_IDENTITY = 0, SD_SCHUR_MASS = 1 };
+/* Middle (free-flow pressure) block of the preconditioner: the paper's
+ * identity; mu M_p^-1 (the viscous Schur complement, M_p = diag(dx dy)); or,
+ * for backward-Euler systems only (phys.dt > 0), the Cahouet-Chabard form
+ * mu M_p^-1 + L_p^-1 (Cahouet & Chabard 1988) with L_p = B^T D^-1 B, D the
+ * velocity mass dx dy / dt on rows with a time derivative and diag(V) on the
+ * others, L_p^-1 one AMG V-cycle (hierarchy block 2).  It keeps the
+ * iteration count bounded when sqrt(mu dt) is small against the domain,
+ * where mu M_p^-1 alone stalls. */
+enum { SD_SCHUR_IDENTITY = 0, SD_SCHUR_MASS = 1, SD_SCHUR_CC = 2 };
 /* MIXED: preconditioner (AMG hierarchies, smoothers, block sweeps) in FP32
  * with FP32 accumulation; Arnoldi product, basis, Hessenberg, x and the
  * restart residual in FP64 (flexible GMRES absorbs the FP32 preconditioner).
@@ -166,7 +176,8 @@ int sd_setup(sd_problem* pb, const sd_solver_opts* opts, sd_solver** out);
 /* Host-only setup (no device work), for inspection. */
 int sd_setup_host(sd_problem* pb, const sd_solver_opts* opts, sd_solver** out);
 
-/* Hierarchy inspection: block 0 = V, 1 = D~.  n_levels counts the coarsest. */
+/* Hierarchy inspection: block 0 = V, 1 = D~, 2 = L_p (SD_SCHUR_CC only;
+ * otherwise it has 0 levels).  n_levels counts the coarsest. */
 int sd_solver_levels(const sd_solver* s, int block, int* n_levels);
 /* which: 0 = A_l, 1 = P_l (n_l x n_{l+1}), 2 = R_l.  Host CSR views. */
 int sd_solver_level_csr(const sd_solver* s, int block, int level, int which,
@@ -193,6 +204,35 @@ typedef struct {
 int sd_solve(sd_solver* s, const double* d_b, double* d_x, int use_x0,
              sd_stats* stats, void* hip_stream);
 
+/* Time stepping (Sec. 2: transient Stokes in the free flow, stationary Darcy
+ * in the porous medium, first-order backward Euler in time).  With
+ * phys.dt > 0 the assembled matrix is that of one step: every interior u and
+ * v face row (not the outflow u faces, not the Gamma rows) integrates dv/dt
+ * over its control volume, adding m = |CV|/dt = dx dy / dt (rho = 1) to its
+ * diagonal; the assembled b is the step's data part (boundary data and
+ * sources).  The step from state x^n solves A x^{n+1} = b_data + M x^n.
+ *
+ * sd_step_rhs: d_b_out = d_b_data + m d_x_prev on those rows and d_b_data on
+ * the others (device FP64 vectors of length N; d_b_data NULL = the assembled
+ * b).  Each entry is one rounded product and one rounded sum, never fused,
+ * so the result is reproducible bit for bit.  d_b_out may alias either input.
+ * Enqueued on hip_stream; returns without waiting.  SD_E_INVALID for a
+ * stationary problem or a NULL vector. */
+int sd_step_rhs(sd_solver* s, const double* d_b_data, const double* d_x_prev,
+                double* d_b_out, void* hip_stream);
+
+/* n_steps backward-Euler steps with the data part d_b_data (NULL = the
+ * assembled b) held fixed: each step forms its right-hand side as
+ * sd_step_rhs does and solves it with this solver's hierarchies (set up once
+ * for all steps), starting from the previous state.  d_x: device FP64 [N],
+ * the state at t on entry, at t + n_steps dt on return.  stats: NULL or an
+ * array of n_steps entries, one per step.  steps_done: NULL or the number of
+ * steps completed.  Stops at the first step that fails and returns its
+ * status; d_x then holds that step's best iterate.  Returns after the last
+ * step has finished. */
+int sd_advance(sd_solver* s, const double* d_b_data, double* d_x, int n_steps,
+               sd_stats* stats, int* steps_done, void* hip_stream);
+
 /* Building blocks of the iteration on device vectors of the problem's
  * ordering (FP64, length N), exposed for testing and composition.
  * y = A x with the assembled FP64 matrix: */
@@ -201,7 +241,7 @@ int sd_apply_matrix(sd_solver* s, const double* d_x, double* d_y, void* hip_stre
  * inside when the solver is mixed; input and output are FP64): */
 int sd_apply_preconditioner(sd_solver* s, const double* d_r, double* d_z,
                             void* hip_stream);
-/* x = one V-cycle on block (0 = V, 1 = D~) for right-hand side b
+/* x = one V-cycle on block (0 = V, 1 = D~, 2 = L_p) for right-hand side b
  * (device FP64 vectors of the block's size): */
 int sd_apply_vcycle(sd_solver* s, int block, const double* d_b, double* d_x,
                     void* hip_stream);

@@ -125,8 +125,12 @@ def pressure_operator(a: Assembled) -> "sp.csr_matrix":
     m = a.mass[o[0]:o[2]]
     Vd = blk["V"].diagonal()
     d = np.where(m != 0.0, m, Vd)
-    L = ((-blk["C"]) @ sp.diags(1.0 / d)) @ blk["B"]
-    L = L.tocsr()
+    C = blk["C"].tocsr()
+    C.sort_indices()
+    # (-C) diag(1/D), entry by entry, then the product with B: each entry of
+    # L_p sums its terms in ascending velocity index
+    X = sp.csr_matrix(((-C.data) * (1.0 / d)[C.indices], C.indices, C.indptr), shape=C.shape)
+    L = (X @ blk["B"].tocsr()).tocsr()
     L.sort_indices()
     return L
 

@@ -541,6 +541,10 @@ std::vector<double> jacobi_weights(const HostCSR& A, double omega) {
 
 }  // namespace
 
+HostCSR scaled_product(const HostCSR& X, const std::vector<double>& s, const HostCSR& Y) {
+  return spgemm(scale_cols(X, s), Y);
+}
+
 HostCSR presmoothed_restriction(const HostCSR& A, const HostCSR& R, double omega) {
   const std::vector<double> w = jacobi_weights(A, omega);
   const HostCSR T = scale_cols(A, w);                 // A W

@@ -182,7 +182,7 @@ int sd_setup_host(sd_problem* pb, const sd_solver_opts* opts, sd_solver** out) {
 }
 
 int sd_solver_levels(const sd_solver* s, int block, int* n_levels) {
-  if (!s || block < 0 || block > 1 || !n_levels) return fail(SD_E_INVALID, "bad argument");
+  if (!s || block < 0 || block > 2 || !n_levels) return fail(SD_E_INVALID, "bad argument");
   *n_levels = (int)s->s->hh[block].levels.size();
   return SD_OK;
 }
@@ -190,7 +190,7 @@ int sd_solver_levels(const sd_solver* s, int block, int* n_levels) {
 int sd_solver_level_csr(const sd_solver* s, int block, int level, int which, int64_t* n_rows,
                         int64_t* n_cols, const int64_t** rowptr, const int32_t** col,
                         const double** val) {
-  if (!s || block < 0 || block > 1) return fail(SD_E_INVALID, "bad argument");
+  if (!s || block < 0 || block > 2) return fail(SD_E_INVALID, "bad argument");
   const auto& h = s->s->hh[block];
   if (level < 0 || level >= (int)h.levels.size()) return fail(SD_E_INVALID, "bad level");
   const sd::HostLevel& L = h.levels[(size_t)level];
@@ -208,7 +208,7 @@ int sd_solver_level_csr(const sd_solver* s, int block, int level, int which, int
 
 int sd_solver_level_agg(const sd_solver* s, int block, int level, const int32_t** agg,
                         int64_t* n) {
-  if (!s || block < 0 || block > 1) return fail(SD_E_INVALID, "bad argument");
+  if (!s || block < 0 || block > 2) return fail(SD_E_INVALID, "bad argument");
   const auto& h = s->s->hh[block];
   if (level < 0 || level + 1 >= (int)h.levels.size())
     return fail(SD_E_INVALID, "bad level (the coarsest level has no aggregates)");
@@ -218,7 +218,8 @@ int sd_solver_level_agg(const sd_solver* s, int block, int level, const int32_t*
 }
 
 int sd_solver_coarse_inverse(const sd_solver* s, int block, const double** inv, int64_t* n) {
-  if (!s || block < 0 || block > 1) return fail(SD_E_INVALID, "bad argument");
+  if (!s || block < 0 || block > 2) return fail(SD_E_INVALID, "bad argument");
+  if (s->s->hh[block].levels.empty()) return fail(SD_E_INVALID, "block has no hierarchy");
   if (inv) *inv = s->s->hh[block].Ainv.data();
   if (n) *n = s->s->hh[block].n_coarse;
   return SD_OK;
@@ -233,6 +234,54 @@ int sd_solve(sd_solver* s, const double* d_b, double* d_x, int use_x0, sd_stats*
     if (rc == SD_E_NOCONV) g_err = "maximum number of iterations reached";
     if (rc == SD_E_BREAKDOWN) g_err = "non-finite value or zero pivot in the iteration";
     return rc;
+  });
+}
+
+static void step_rhs_impl(sd_solver* s, const double* d_b, const double* d_x, double* d_out,
+                          hipStream_t st) {
+  const sd::HostProblem& hp = s->pb->hp;
+  if (!(hp.mass > 0.0))
+    throw sd::Error(SD_E_INVALID, "problem is stationary (assembled with phys.dt = 0)");
+  if (!s->s->on_device) throw sd::Error(SD_E_INVALID, "solver has no device data");
+  if (!d_x || !d_out) throw sd::Error(SD_E_INVALID, "NULL device vector");
+  const sd::Layout& L = hp.L;
+  sd::launch_step_rhs(d_b ? d_b : s->s->b_dev, d_x, d_out, hp.mass, (int)L.N, L.nux, L.nx,
+                      (int)L.off_v, (int)L.off_p, st);
+  SD_HIP(hipGetLastError());
+}
+
+int sd_step_rhs(sd_solver* s, const double* d_b_data, const double* d_x_prev, double* d_b_out,
+                void* hip_stream) {
+  return guarded([&] {
+    if (!s) return fail(SD_E_INVALID, "solver is NULL");
+    SD_HIP(hipSetDevice(s->pb->device_id));
+    step_rhs_impl(s, d_b_data, d_x_prev, d_b_out, (hipStream_t)hip_stream);
+    return (int)SD_OK;
+  });
+}
+
+int sd_advance(sd_solver* s, const double* d_b_data, double* d_x, int n_steps, sd_stats* stats,
+               int* steps_done, void* hip_stream) {
+  return guarded([&] {
+    if (steps_done) *steps_done = 0;
+    if (!s) return fail(SD_E_INVALID, "solver is NULL");
+    if (n_steps < 0) return fail(SD_E_INVALID, "n_steps must be >= 0");
+    SD_HIP(hipSetDevice(s->pb->device_id));
+    sd::Solver& S = *s->s;
+    hipStream_t st = (hipStream_t)hip_stream;
+    for (int k = 0; k < n_steps; ++k) {
+      step_rhs_impl(s, d_b_data, d_x, S.step_b, st);
+      sd_stats one{};
+      const int rc = S.solve(S.step_b, d_x, 1, &one, st);
+      if (stats) stats[k] = one;
+      if (rc != SD_OK) {
+        if (rc == SD_E_NOCONV) g_err = "a time step reached the maximum number of iterations";
+        if (rc == SD_E_BREAKDOWN) g_err = "non-finite value or zero pivot in a time step";
+        return rc;
+      }
+      if (steps_done) *steps_done = k + 1;
+    }
+    return (int)SD_OK;
   });
 }
 
@@ -262,7 +311,9 @@ int sd_apply_preconditioner(sd_solver* s, const double* d_r, double* d_z, void* 
 
 int sd_apply_vcycle(sd_solver* s, int block, const double* d_b, double* d_x, void* hip_stream) {
   return guarded([&] {
-    if (!s || !d_b || !d_x || block < 0 || block > 1) return fail(SD_E_INVALID, "bad argument");
+    if (!s || !d_b || !d_x || block < 0 || block > 2) return fail(SD_E_INVALID, "bad argument");
+    if (s->s->hh[block].levels.empty())
+      return fail(SD_E_INVALID, "block 2 exists only with SD_SCHUR_CC");
     if (!s->s->on_device) return fail(SD_E_INVALID, "solver has no device data");
     hipStream_t st = (hipStream_t)hip_stream;
     s->s->prec->apply_vcycle(*s->s, block, d_b, d_x, st);

@@ -1,6 +1,6 @@
 // Host assembly of the coupled Stokes-Darcy system.
 //
-// Model (Sec. 2 of the paper): stationary creeping Stokes flow, momentum flux
+// Model (Sec. 2 of the paper): creeping Stokes flow, momentum flux
 // (pI - tau) n with tau = mu (grad v + grad v^T), in the free flow; Darcy's law
 // with mass continuity in the porous medium; on the interface the normal-stress
 // balance, Beavers-Joseph-Saffman slip and normal mass-flux continuity.
@@ -13,7 +13,11 @@
 //     beta = alpha/sqrt(K_f), K_f harmonic mean of the two porous cells below;
 //   * traction outflow: n.(pI - tau)n at the last cell centre = data;
 //   * Gamma rows: dx [p - 2 mu (v_1 - v_0)/dy - q_top + (mu/K)(dy_pm/2) v_0] = 0;
-//   * porous top cells: interface flux dx * v_{i,0}.
+//   * porous top cells: interface flux dx * v_{i,0};
+//   * dt > 0: the transient momentum equation with the paper's backward Euler
+//     step adds |CV|/dt (rho = 1) to the diagonal of every interior u and v
+//     face row; the outflow u rows, the Gamma rows and the Darcy rows are
+//     conditions without a time derivative.  b holds the data part only.
 // Each coefficient is evaluated as one fixed IEEE-double expression (the file
 // is compiled without floating-point contraction), so the values are
 // reproducible bit-for-bit.
@@ -69,6 +73,8 @@ void assemble_host(const sd_grid* g, const sd_physics* ph, const sd_bcs* bcs,
     throw Error(SD_E_INVALID, "extents must be finite and positive");
   if (!finite_pos(ph->mu) || !finite_pos(ph->alpha_bj))
     throw Error(SD_E_INVALID, "mu and alpha_bj must be finite and positive");
+  if (!(std::isfinite(ph->dt) && ph->dt >= 0.0))
+    throw Error(SD_E_INVALID, "dt must be finite and >= 0 (0 = stationary)");
   if (bcs->ff_left != SD_BC_VELOCITY || bcs->ff_top != SD_BC_VELOCITY)
     throw Error(SD_E_INVALID, "free-flow left and top boundaries must be SD_BC_VELOCITY");
   if (bcs->ff_right != SD_BC_VELOCITY && bcs->ff_right != SD_BC_TRACTION)
@@ -134,6 +140,9 @@ void assemble_host(const sd_grid* g, const sd_physics* ph, const sd_bcs* bcs,
   const double dyp = g->H_pm / (double)nyp;
   const double vol = dx * dy;
   const double volp = dx * dyp;
+  const bool transient = ph->dt > 0.0;
+  const double mvol = transient ? vol / ph->dt : 0.0;
+  P.mass = mvol;
   const double cx = (2.0 * mu) * (dy / dx);
   const double cy = mu * (dx / dy);
   const double cyt = mu * (dx / (0.5 * dy));
@@ -171,7 +180,9 @@ void assemble_host(const sd_grid* g, const sd_physics* ph, const sd_bcs* bcs,
       const double gm = gg * mu;
       const double aN = top ? cyt : cy;
       const double aS = gam ? cg : cy;
-      rb.add(r, ((cx + cx) + aN) + aS);
+      double d = ((cx + cx) + aN) + aS;
+      if (transient) d = d + mvol;
+      rb.add(r, d);
       if (i - 1 >= 1) rb.add(L.u(i - 1, j), -cx);
       if (i + 1 <= nx - 1 || right_tr) rb.add(L.u(i + 1, j), -cx);
       if (!top) rb.add(L.u(i, j + 1), -cy);
@@ -211,7 +222,9 @@ void assemble_host(const sd_grid* g, const sd_physics* ph, const sd_bcs* bcs,
       const bool west = i == 0, east = i == nx - 1;
       const double aE = east ? (right_tr ? 0.0 : cxw) : cxv;
       const double aW = west ? cxw : cxv;
-      rb.add(r, ((cyy + cyy) + aE) + aW);
+      double d = ((cyy + cyy) + aE) + aW;
+      if (transient) d = d + mvol;
+      rb.add(r, d);
       if (j + 1 <= ny - 1) rb.add(L.v(i, j + 1), -cyy);
       rb.add(L.v(i, j - 1), -cyy);
       if (!east) rb.add(L.v(i + 1, j), -cxv);

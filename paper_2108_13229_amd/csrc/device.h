@@ -103,11 +103,15 @@ template <typename T>
 void launch_coarse(const double* Ainv, int n, const T* bc, T* xc, const DevState* gate,
                    hipStream_t s);
 // Block sweep: rows of the continuity and porous blocks.
-//   t = bscale * r[row] - (Cf y_v)[row]; rows < n_p: zp = xscale * t; else tq = t
+//   t = bscale * r[row] - (Cf y_v)[row]; rows < n_p: zp = xscale * t (and
+//   tp = t when tp is not null); else tq = t
 template <typename T>
 void launch_block_sweep(const Sell<T>& Cf, int n_p, const double* r, const double* bscale,
-                        const T* yv, double xscale, T* zp, T* tq, const DevState* gate,
+                        const T* yv, double xscale, T* zp, T* tq, T* tp, const DevState* gate,
                         hipStream_t s);
+// y += a
+template <typename T>
+void launch_add(const T* a, T* y, int n, const DevState* gate, hipStream_t s);
 // One Arnoldi step j with delayed reorthogonalisation (FP64 basis V, leading
 // dimension ldv).  On entry V[0..j-1] are orthonormal and V[j] holds u_j, the
 // once-orthogonalised candidate; z = M(sigma_j u_j).  The step computes
@@ -166,5 +170,11 @@ template <typename TA, typename TB>
 void launch_convert(const TA* a, TB* b, int n, hipStream_t s);
 template <typename T>
 void launch_fill(T* a, T v, int n, hipStream_t s);
+
+// Backward-Euler right-hand side: out = b + m x on the velocity rows with a
+// time derivative (u rows r < off_v with r % nux + 1 <= nx - 1, v rows
+// off_v + nx <= r < off_p), b elsewhere; no fused multiply-add.
+void launch_step_rhs(const double* b, const double* x, double* out, double m, int n, int nux,
+                     int nx, int off_v, int off_p, hipStream_t s);
 
 }  // namespace sd

@@ -337,16 +337,32 @@ __global__ __launch_bounds__(kBlock) void k_block_sweep(Sell<T> Cf, int n_p,
                                                         const double* bscale,
                                                         const T* __restrict__ yv, double xscale,
                                                         T* __restrict__ zp, T* __restrict__ tq,
+                                                        T* __restrict__ tp,
                                                         const DevState* gate) {
   const int row = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (row >= Cf.n_rows) return;
   const int stop = gate_flag(gate);
   const T t = load_b<T>(r, scale_of(bscale), row) - sell_dot(Cf, yv, row);
   if (stop) return;
-  if (row < n_p)
+  if (row < n_p) {
     zp[row] = (T)xscale * t;
-  else
+    if (tp) tp[row] = t;     // right-hand side of the pressure-operator V-cycle
+  } else {
     tq[row - n_p] = t;
+  }
+}
+
+// y += a (the pressure-operator V-cycle's share of the middle block).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_add(const T* __restrict__ a, T* __restrict__ y, int n,
+                                                const DevState* gate) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int stop = gate_flag(gate);
+  const T v = a[i];
+  const T w = y[i];
+  if (stop) return;
+  y[i] = w + v;
 }
 
 // ---- Arnoldi step j: classical Gram-Schmidt with one reorthogonalisation
@@ -1040,6 +1056,28 @@ __global__ __launch_bounds__(kBlock) void k_fill(T* __restrict__ a, T v, int n) 
   if (i < n) a[i] = v;
 }
 
+// Right-hand side of one backward-Euler step: out = b + m x on the rows whose
+// momentum balance has a time derivative (u faces i = 1..nx-1 of the first
+// n_u rows, v faces off the interface: rows off_v + nx .. off_p - 1), b on
+// the others.  One rounded product and one rounded sum per row, never fused,
+// so the result is reproducible bit for bit.  out may alias b or x (each
+// thread reads its row before writing it).
+__global__ __launch_bounds__(kBlock) void k_step_rhs(const double* b, const double* x,
+                                                     double* out, double m, int n, int nux,
+                                                     int nx, int off_v, int off_p) {
+#pragma clang fp contract(off)
+  const int r = blockIdx.x * kBlock + threadIdx.x;
+  if (r >= n) return;
+  const bool has = r < off_v ? (r % nux) + 1 <= nx - 1 : (r >= off_v + nx && r < off_p);
+  const double br = b[r];
+  if (has) {
+    const double mx = m * x[r];
+    out[r] = br + mx;
+  } else {
+    out[r] = br;
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
@@ -1177,11 +1215,17 @@ void launch_coarse(const double* Ainv, int n, const T* bc, T* xc, const DevState
 
 template <typename T>
 void launch_block_sweep(const Sell<T>& Cf, int n_p, const double* r, const double* bscale,
-                        const T* yv, double xscale, T* zp, T* tq, const DevState* gate,
+                        const T* yv, double xscale, T* zp, T* tq, T* tp, const DevState* gate,
                         hipStream_t s) {
   if (Cf.n_rows <= 0) return;
   k_block_sweep<T><<<blocks_for(Cf.n_rows), kBlock, 0, s>>>(Cf, n_p, r, bscale, yv, xscale, zp,
-                                                            tq, gate);
+                                                            tq, tp, gate);
+}
+
+template <typename T>
+void launch_add(const T* a, T* y, int n, const DevState* gate, hipStream_t s) {
+  if (n <= 0) return;
+  k_add<T><<<blocks_for(n), kBlock, 0, s>>>(a, y, n, gate);
 }
 
 // Rows per workgroup: the projection kernel takes 1024 (two workgroups per
@@ -1318,6 +1362,12 @@ void launch_fill(T* a, T v, int n, hipStream_t s) {
   k_fill<T><<<blocks_for(n), kBlock, 0, s>>>(a, v, n);
 }
 
+void launch_step_rhs(const double* b, const double* x, double* out, double m, int n, int nux,
+                     int nx, int off_v, int off_p, hipStream_t s) {
+  if (n <= 0) return;
+  k_step_rhs<<<blocks_for(n), kBlock, 0, s>>>(b, x, out, m, n, nux, nx, off_v, off_p);
+}
+
 // ------------------------------------------------------- instantiations
 #define SD_INST_T(T, TB)                                                                      \
   template void launch_residual<T, TB>(const Sell<T>&, const TB*, const double*, const T*, T*, \
@@ -1353,10 +1403,12 @@ template void launch_coarse<float>(const double*, int, const float*, float*, con
                                    hipStream_t);
 template void launch_block_sweep<double>(const Sell<double>&, int, const double*,
                                          const double*, const double*, double, double*,
-                                         double*, const DevState*, hipStream_t);
+                                         double*, double*, const DevState*, hipStream_t);
 template void launch_block_sweep<float>(const Sell<float>&, int, const double*, const double*,
-                                        const float*, double, float*, float*, const DevState*,
-                                        hipStream_t);
+                                        const float*, double, float*, float*, float*,
+                                        const DevState*, hipStream_t);
+template void launch_add<double>(const double*, double*, int, const DevState*, hipStream_t);
+template void launch_add<float>(const float*, float*, int, const DevState*, hipStream_t);
 template void launch_arnoldi_step<double, double>(const Sell<double>&, const double*, double*,
                                                   double*, int64_t, int, DevState*, double*,
                                                   HostFlags*, hipStream_t, int, hipEvent_t*);

@@ -29,6 +29,11 @@ struct HostCSR {
 struct Layout {
   int nx = 0, ny = 0, nyp = 0, nux = 0;
   int64_t off_v = 0, off_p = 0, off_q = 0, N = 0;
+  // rows with a time derivative: u faces i <= nx-1 and v faces j >= 1
+  bool has_mass(int64_t r) const {
+    if (r < off_v) return (int)(r % nux) + 1 <= nx - 1;
+    return r >= off_v + nx && r < off_p;
+  }
   int64_t u(int i, int j) const { return (int64_t)j * nux + (i - 1); }
   int64_t v(int i, int j) const { return off_v + (int64_t)j * nx + i; }
   int64_t p(int i, int j) const { return off_p + (int64_t)j * nx + i; }
@@ -43,6 +48,7 @@ struct HostProblem {
   HostCSR A;
   std::vector<double> b;
   bool pm_singular = false;
+  double mass = 0.0;           // |CV|/dt of the backward-Euler rows (0: stationary)
 };
 
 void assemble_host(const sd_grid* g, const sd_physics* ph, const sd_bcs* bcs,
@@ -84,6 +90,10 @@ void parallel_ranges(int64_t r0, int64_t r1, const std::function<void(int64_t, i
 // Q = [R | -R A] (n_c x 2n): the restricted residual R (b - A x) = Q [b; x]
 // in one sparse product, so that a V-cycle level needs no residual vector.
 HostCSR residual_restriction(const HostCSR& A, const HostCSR& R);
+
+// (X diag(s)) Y: every entry of X scaled by s of its column, then the
+// product, each result entry summed in ascending inner index.
+HostCSR scaled_product(const HostCSR& X, const std::vector<double>& s, const HostCSR& Y);
 
 // With W = diag(omega / a_ii) and M2 = 2W - W A W (two damped-Jacobi sweeps
 // from zero):

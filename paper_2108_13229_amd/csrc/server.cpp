@@ -72,8 +72,9 @@ size_t estimate_bytes(const sd_grid& g, int ff_right, const sd_solver_opts& o) {
   if (o.precision == SD_PRECISION_MIXED32) b += nnz * 8.0 * 1.2;  // FP32 copy
   b += 2.5 * nnz * (4.0 + tb) * 1.2;                            // hierarchies, P, R
   b += 12.0 * N * tb;                                           // level work vectors
+  if (o.schur == SD_SCHUR_CC) b += 0.25 * 2.5 * nnz * (4.0 + tb) * 1.2;  // L_p hierarchy
   const double nc = std::min(N, (double)o.coarse_max);
-  b += 2.0 * nc * nc * 8.0;                                     // coarse inverses
+  b += (o.schur == SD_SCHUR_CC ? 3.0 : 2.0) * nc * nc * 8.0;    // coarse inverses
   b += (o.restart + 2.0) * N * 8.0 + o.restart * N * tb;        // basis, Z, W
   b += 4.0 * N * 8.0 + (4 << 20);                               // b, x, misc
   return (size_t)b;

@@ -207,7 +207,11 @@ void Solver::setup_host(HostProblem* p, const sd_solver_opts* o) {
     throw Error(SD_E_INVALID, "restart must be in 1..63");
   if (!(so.tol > 0.0) || so.maxit < 1) throw Error(SD_E_INVALID, "tol > 0 and maxit >= 1 required");
   if (so.precond != SD_PREC_BJ && so.precond != SD_PREC_BGS) throw Error(SD_E_INVALID, "precond");
-  if (so.schur != SD_SCHUR_IDENTITY && so.schur != SD_SCHUR_MASS) throw Error(SD_E_INVALID, "schur");
+  if (so.schur != SD_SCHUR_IDENTITY && so.schur != SD_SCHUR_MASS && so.schur != SD_SCHUR_CC)
+    throw Error(SD_E_INVALID, "schur");
+  if (so.schur == SD_SCHUR_CC && !(p->mass > 0.0))
+    throw Error(SD_E_INVALID,
+                "SD_SCHUR_CC needs a backward-Euler system (problem assembled with phys.dt > 0)");
   if (so.precision != SD_PRECISION_FP64 && so.precision != SD_PRECISION_MIXED &&
       so.precision != SD_PRECISION_MIXED32)
     throw Error(SD_E_INVALID, "precision");
@@ -240,6 +244,20 @@ void Solver::setup_host(HostProblem* p, const sd_solver_opts* o) {
   std::vector<int32_t> compD((size_t)(L.N - L.off_q), 0);
   amg_setup_host(Vb, compV, false, opts.amg, hh[0]);
   amg_setup_host(Dt, compD, false, opts.amg, hh[1]);
+  hh[2] = HostHierarchy();
+  if (so.schur == SD_SCHUR_CC) {
+    // L_p = B^T D^-1 B = (-C) diag(1/D) B, D = |CV|/dt on the velocity rows
+    // with a time derivative and diag(V) on the others
+    HostCSR Cm = extract_block(p->A, L.off_p, L.off_q, 0, L.off_p);
+    for (double& v : Cm.val) v = -v;
+    HostCSR Bp = extract_block(p->A, 0, L.off_p, L.off_p, L.off_q);
+    std::vector<double> dinv((size_t)L.off_p);
+    for (int64_t k = 0; k < L.off_p; ++k)
+      dinv[(size_t)k] = 1.0 / (L.has_mass(k) ? p->mass : diag_at(Vb, k));
+    HostCSR Lp = scaled_product(Cm, dinv, Bp);
+    std::vector<int32_t> compP((size_t)(L.off_q - L.off_p), 0);
+    amg_setup_host(Lp, compP, false, opts.amg, hh[2]);
+  }
   if (so.precond == SD_PREC_BGS) {
     Cf = extract_block(p->A, L.off_p, L.N, 0, L.off_p);
   } else {
@@ -248,7 +266,7 @@ void Solver::setup_host(HostProblem* p, const sd_solver_opts* o) {
     Cf.rowptr.assign((size_t)Cf.n_rows + 1, 0);
   }
   const double vol = (p->grid.Lx / (double)p->grid.nx) * (p->grid.H_ff / (double)p->grid.ny);
-  xscale = so.schur == SD_SCHUR_MASS ? p->phys.mu / vol : 1.0;
+  xscale = so.schur == SD_SCHUR_IDENTITY ? 1.0 : p->phys.mu / vol;
   t_setup = wall_time() - t0;
 }
 
@@ -269,6 +287,7 @@ void Solver::upload(const sd_allocator* alloc, hipStream_t s) {
   mem.reset(new DeviceMem(alloc, s));
   A64 = upload_sell<double>(pb->A, *mem, s);
   b_dev = mem->array<double>((size_t)N);
+  if (pb->mass > 0.0) step_b = mem->array<double>((size_t)N);
   SD_HIP(hipMemcpyAsync(b_dev, pb->b.data(), (size_t)N * sizeof(double), hipMemcpyHostToDevice, s));
   ldv = ((int64_t)N + 63) / 64 * 64;
   const int m = opts.o.restart;
@@ -370,12 +389,15 @@ void upload_hierarchy(const HostHierarchy& h, DevHierarchy<T>& d, double omega, 
 template <typename T>
 class PrecImpl : public PrecBase {
  public:
-  DevHierarchy<T> H[2];
+  DevHierarchy<T> H[3];  // V, D~ and (Cahouet-Chabard middle block) L_p
   Sell<T> Cf;
   Sell<float> A32;       // FP32 copy of A for the Arnoldi product (MIXED32 only)
   bool arn32 = false;
   T* Z = nullptr;        // m preconditioned vectors
   T* tq = nullptr;       // porous right-hand side of the block sweep
+  T* tp = nullptr;       // pressure right-hand side of the L_p V-cycle (cc only)
+  T* yl = nullptr;       // its result
+  bool cc = false;
   T* tmpN = nullptr;     // scratch vector of length N (apply entry points)
   int64_t ldz = 0;
   int nu_pre = 2, nu_post = 2;
@@ -384,8 +406,13 @@ class PrecImpl : public PrecBase {
     DeviceMem& mem = *S.mem;
     nu_pre = S.opts.amg.nu_pre;
     nu_post = S.opts.amg.nu_post;
-    for (int b = 0; b < 2; ++b)
+    cc = !S.hh[2].levels.empty();
+    for (int b = 0; b < (cc ? 3 : 2); ++b)
       upload_hierarchy<T>(S.hh[b], H[b], S.opts.amg.omega, nu_pre, nu_post, mem, s);
+    if (cc) {
+      tp = mem.array<T>((size_t)(S.off[3] - S.off[2]));
+      yl = mem.array<T>((size_t)(S.off[3] - S.off[2]));
+    }
     Cf = upload_sell<T>(S.Cf, mem, s);
     arn32 = S.opts.o.precision == SD_PRECISION_MIXED32;
     if (arn32) A32 = upload_sell<float>(S.pb->A, mem, s);
@@ -469,8 +496,14 @@ class PrecImpl : public PrecBase {
   void apply(Solver& S, const double* r, const double* bs, T* z, const DevState* gate,
              hipStream_t s) {
     const int64_t* o = S.off;
+    const int n_p = (int)(o[3] - o[2]);
     vcycle<double>(0, 0, r, bs, z, gate, s);
-    launch_block_sweep<T>(Cf, (int)(o[3] - o[2]), r + o[2], bs, z, S.xscale, z + o[2], tq, gate, s);
+    launch_block_sweep<T>(Cf, n_p, r + o[2], bs, z, S.xscale, z + o[2], tq, cc ? tp : nullptr,
+                          gate, s);
+    if (cc) {
+      vcycle<T>(2, 0, tp, nullptr, yl, gate, s);
+      launch_add<T>(yl, z + o[2], n_p, gate, s);
+    }
     vcycle<T>(1, 0, tq, nullptr, z + o[3], gate, s);
   }
 

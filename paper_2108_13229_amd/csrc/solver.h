@@ -123,7 +123,8 @@ class Solver {
  public:
   HostProblem* pb = nullptr;        // not owned
   SolverOpts opts;
-  HostHierarchy hh[2];              // 0: V, 1: Darcy block with interface correction
+  HostHierarchy hh[3];              // 0: V, 1: Darcy block with interface correction,
+                                    // 2: pressure operator L_p (SD_SCHUR_CC only)
   HostCSR Cf;                       // continuity and porous rows x velocity columns
   double xscale = 1.0;
   int64_t off[5] = {0, 0, 0, 0, 0};
@@ -135,6 +136,7 @@ class Solver {
   std::unique_ptr<DeviceMem> mem;
   Sell<double> A64;
   double* b_dev = nullptr;
+  double* step_b = nullptr;         // backward-Euler right-hand side (sd_advance)
   double* V = nullptr;              // (m+1) basis slots: orthonormal vectors + the open candidate
   double* W = nullptr;
   double* part = nullptr;

@@ -22,7 +22,7 @@ SD_E_NOCONV, SD_E_BREAKDOWN, SD_E_BUSY, SD_E_NOTFOUND = -4, -5, -6, -7
 BC = {"velocity": 0, "traction": 1, "pressure": 2, "noflow": 3}
 KRYLOV = {"fgmres": 0, "bicgstab": 1}
 PRECOND = {"BJ": 0, "BGS": 1}
-SCHUR = {"identity": 0, "mass": 1}
+SCHUR = {"identity": 0, "mass": 1, "cc": 2}
 PRECISION = {"fp64": 0, "mixed": 1, "mixed32": 2}
 AMG = {"plain": 0, "smoothed": 1}
 REQ_STATE = {0: "pending", 1: "running", 2: "done", 3: "failed"}
@@ -36,7 +36,7 @@ class Grid(C.Structure):
 
 
 class Physics(C.Structure):
-    _fields_ = [("mu", C.c_double), ("alpha_bj", C.c_double)]
+    _fields_ = [("mu", C.c_double), ("alpha_bj", C.c_double), ("dt", C.c_double)]
 
 
 class Bcs(C.Structure):
@@ -112,6 +112,8 @@ SIGNATURES = {
                                       C.POINTER(C.c_int64)]),
     "sd_solver_coarse_inverse": (C.c_int, [_P, C.c_int, C.POINTER(_dp), C.POINTER(C.c_int64)]),
     "sd_solve": (C.c_int, [_P, _P, _P, C.c_int, C.POINTER(Stats), _P]),
+    "sd_step_rhs": (C.c_int, [_P, _P, _P, _P, _P]),
+    "sd_advance": (C.c_int, [_P, _P, _P, C.c_int, C.POINTER(Stats), C.POINTER(C.c_int), _P]),
     "sd_apply_matrix": (C.c_int, [_P, _P, _P, _P]),
     "sd_apply_preconditioner": (C.c_int, [_P, _P, _P, _P]),
     "sd_apply_vcycle": (C.c_int, [_P, C.c_int, _P, _P, _P]),
@@ -171,7 +173,7 @@ def _ptr(a, keep):
 
 def _marshal(p, keep):
     g = Grid(int(p.nx), int(p.ny), int(p.ny_pm), float(p.Lx), float(p.H_ff), float(p.H_pm))
-    ph = Physics(float(p.mu), float(p.alpha_bj))
+    ph = Physics(float(p.mu), float(p.alpha_bj), float(getattr(p, "dt", 0.0)))
     b = Bcs(BC[p.ff_left], BC[p.ff_right], BC[p.ff_top], BC[p.pm_left], BC[p.pm_right],
             BC[p.pm_bottom],
             _ptr(p.ff_left_n, keep), _ptr(p.ff_left_t, keep), _ptr(p.ff_right_n, keep),
@@ -306,6 +308,37 @@ class Solver:
         if rc not in (SD_OK, SD_E_NOCONV):
             _check(rc)
         return x, st.as_dict(), rc
+
+    def step_rhs(self, x_prev, b_data=None, out=None):
+        """Right-hand side of one backward-Euler step from state x_prev."""
+        import torch
+        N = self.problem.N
+        _require(x_prev, N)
+        if b_data is not None:
+            _require(b_data, N)
+        out = torch.empty_like(x_prev) if out is None else out
+        _require(out, N)
+        _check(lib().sd_step_rhs(self.h, C.c_void_p(b_data.data_ptr()) if b_data is not None
+                                 else None, C.c_void_p(x_prev.data_ptr()),
+                                 C.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def advance(self, x, n_steps: int, b_data=None):
+        """n_steps backward-Euler steps in place on x; returns (per-step stats,
+        steps completed, status)."""
+        N = self.problem.N
+        _require(x, N)
+        if b_data is not None:
+            _require(b_data, N)
+        st = (Stats * max(n_steps, 1))()
+        done = C.c_int()
+        rc = lib().sd_advance(self.h, C.c_void_p(b_data.data_ptr()) if b_data is not None
+                              else None, C.c_void_p(x.data_ptr()), int(n_steps), st,
+                              C.byref(done), _stream())
+        if rc not in (SD_OK, SD_E_NOCONV):
+            _check(rc)
+        return [st[k].as_dict() for k in range(done.value if rc == SD_OK else
+                                                 min(done.value + 1, n_steps))], done.value, rc
 
     def apply_matrix(self, x):
         import torch

@@ -133,3 +133,35 @@ def test_smallest_grid():
     rp, col, val, b = P.csr()
     a = assemble(p)
     assert np.array_equal(val, a.A.data) and P.N == a.N == 2 * 2 + 2 * 2 + 4 + 2
+
+
+@pytest.mark.parametrize("amg_kind,mis", [("smoothed", 2), ("plain", 1)])
+@pytest.mark.parametrize("pi", [6, 7])
+def test_host_pressure_operator_hierarchy_bit_exact(amg_kind, mis, pi):
+    """Cahouet-Chabard middle block: L_p and its AMG hierarchy (block 2)."""
+    p = _cases()[pi]
+    P = sd.Problem(p, device=False)
+    S = sd.Solver(P, device=False, amg=amg_kind, mis=mis, coarse_max=64, schur="cc")
+    a = assemble(p)
+    opts = amg.AMGOptions(smoothed=amg_kind == "smoothed", mis=mis, coarse_max=64)
+    M = precond.build(p, a, "BGS", schur=precond.SCHUR_CC, opts=opts)
+    h = M.hL
+    assert S.n_levels(2) == h.n_levels >= 2
+    for lev in range(h.n_levels):
+        L = h.levels[lev]
+        _, rp, col, val = S.level_csr(2, lev, 0)
+        assert np.array_equal(rp, L.A.indptr) and np.array_equal(col, L.A.indices)
+        assert np.array_equal(val, L.A.data)
+        if lev + 1 < h.n_levels:
+            assert np.array_equal(S.level_agg(2, lev), L.agg)
+    inv = S.coarse_inverse(2)
+    assert np.allclose(inv, h.Ainv, rtol=0, atol=1e-12 * np.abs(h.Ainv).max())
+
+
+def test_pressure_operator_needs_a_time_step():
+    P = sd.Problem(channel_problem(16, 8, seed=1), device=False)
+    with pytest.raises(sd.SDError) as e:
+        sd.Solver(P, device=False, schur="cc")
+    assert e.value.code == sd.SD_E_INVALID
+    S = sd.Solver(P, device=False)
+    assert S.n_levels(2) == 0

@@ -1,0 +1,180 @@
+"""GPU parity of backward-Euler time stepping (Sec. 2: transient free flow,
+first-order backward Euler) against the oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+from sdinputs import channel_problem, config_problem, mms_transient_problem
+from oracle import amg, krylov, precond
+from oracle.assemble import assemble
+from oracle.transient import backward_euler, step_rhs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+sd = pytest.importorskip("paper_2108_13229_amd.sd")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    sd.lib()
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _channel_vel_right():
+    p = channel_problem(37, 19, 11, seed=8)
+    p.ff_right = "velocity"
+    p.ff_right_n = np.linspace(0.0, 1e-3, 19)
+    p.dt = 2e-3
+    return p
+
+
+def _channel_tr():
+    p = channel_problem(96, 48, seed=3)
+    p.dt = 0.05
+    return p
+
+
+CASES = {"channel96_dt0.05": _channel_tr, "ragged_velocity_right": _channel_vel_right}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_step_rhs_bit_exact(name):
+    p = CASES[name]()
+    print("case", name, flush=True)
+    a = assemble(p)
+    P = sd.Problem(p, device=True)
+    S = sd.Solver(P)
+    rng = np.random.default_rng(21)
+    x = rng.standard_normal(a.N)
+    bd = rng.standard_normal(a.N)
+    # assembled data part, an explicit one, and the output written in place
+    assert np.array_equal(_host(S.step_rhs(_dev(x))), step_rhs(a, a.b, x))
+    assert np.array_equal(_host(S.step_rhs(_dev(x), b_data=_dev(bd))), step_rhs(a, bd, x))
+    xd = _dev(x)
+    S.step_rhs(xd, b_data=_dev(bd), out=xd)
+    assert np.array_equal(_host(xd), step_rhs(a, bd, x))
+
+
+def test_step_rhs_rejects_stationary_problem():
+    p = channel_problem(16, 8, seed=1)
+    S = sd.Solver(sd.Problem(p, device=True))
+    with pytest.raises(sd.SDError) as e:
+        S.step_rhs(_dev(np.zeros(assemble(p).N)))
+    assert e.value.code == sd.SD_E_INVALID
+    with pytest.raises(sd.SDError):
+        S.advance(_dev(np.zeros(assemble(p).N)), 1)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_advance_matches_oracle_steps(precision):
+    """Five steps from rest with the Cahouet-Chabard middle block: the same
+    algorithm per step (oracle FGMRES with the same preconditioner,
+    warm-started from the previous state)."""
+    p = _channel_tr()
+    print("case channel96 dt=0.05", precision, flush=True)
+    a = assemble(p)
+    M = precond.build(p, a, "BGS", schur=precond.SCHUR_CC)
+    tol = 1e-10
+    its = []
+    steps = backward_euler(a, np.zeros(a.N), 5,
+                           solve=lambda A, r, xp=[np.zeros(a.N)]: _warm(A, r, M, tol, xp, its))
+    P = sd.Problem(p, device=True)
+    S = sd.Solver(P, tol=tol, precision=precision, schur="cc")
+    x = _dev(np.zeros(a.N))
+    stats, done, rc = S.advance(x, 5)
+    assert rc == sd.SD_OK and done == 5 and len(stats) == 5
+    xg = _host(x)
+    ref = steps[-1]
+    assert np.linalg.norm(xg - ref) <= 1e-8 * np.linalg.norm(ref)
+    for st, it in zip(stats, its):
+        assert st["rel_res"] <= tol
+        assert abs(st["iters"] - it) <= (1 if precision == "fp64" else 3), (st, it)
+
+
+def _warm(A, r, M, tol, xp, its):
+    res = krylov.fgmres(A, r, M, tol=tol, m=30, x0=xp[0])
+    assert res.converged
+    xp[0] = res.x
+    its.append(res.iters)
+    return res.x
+
+
+def test_pressure_operator_vcycle_and_preconditioner_parity():
+    p = _channel_tr()
+    a = assemble(p)
+    M = precond.build(p, a, "BGS", schur=precond.SCHUR_CC)
+    P = sd.Problem(p, device=True)
+    S = sd.Solver(P, schur="cc")
+    rng = np.random.default_rng(13)
+    n_p = M.hL.levels[0].A.shape[0]
+    b = rng.standard_normal(n_p)
+    x = _host(S.apply_vcycle(2, _dev(b)))
+    ref = amg.vcycle(M.hL, b)
+    assert np.linalg.norm(x - ref) <= 1e-12 * np.linalg.norm(ref)
+    r = rng.standard_normal(a.N)
+    z = _host(S.apply_preconditioner(_dev(r)))
+    ref = M(r)
+    assert np.linalg.norm(z - ref) <= 1e-12 * np.linalg.norm(ref)
+    Sm = sd.Solver(P, schur="cc", precision="mixed")
+    z = _host(Sm.apply_preconditioner(_dev(r)))
+    assert np.linalg.norm(z - ref) <= 1e-5 * np.linalg.norm(ref)
+    Sbj = sd.Solver(P, schur="cc", precond="BJ")
+    Mbj = precond.build(p, a, "BJ", schur=precond.SCHUR_CC)
+    z = _host(Sbj.apply_preconditioner(_dev(r)))
+    ref = Mbj(r)
+    assert np.linalg.norm(z - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_time_dependent_data_manufactured_solution():
+    """Linear-in-time manufactured solution with data that change every
+    step: step_rhs + solve(use_x0) on the GPU reproduce the oracle's states,
+    whose error against the exact solution is the spatial one."""
+    g, dg = (lambda t: 1.0 + 20.0 * t), (lambda t: 20.0)
+    n, dt, ns = 64, 0.01, 5
+    p0, m = mms_transient_problem(n, n // 2, dt, 0.0, g, dg)
+    a = assemble(p0)
+    datas = [assemble(mms_transient_problem(n, n // 2, dt, k * dt, g, dg)[0]).b
+             for k in range(ns + 1)]
+    x0 = np.random.default_rng(3).standard_normal(a.N) * 0.1
+    ref = backward_euler(a, x0, ns, b_data=lambda k: datas[k])
+    P = sd.Problem(p0, device=True)
+    S = sd.Solver(P, tol=1e-11, schur="cc")
+    x = _dev(x0)
+    rhs = torch.empty_like(x)
+    for k in range(1, ns + 1):
+        S.step_rhs(x, b_data=_dev(datas[k]), out=rhs)
+        x, st, rc = S.solve(b=rhs, x=x, use_x0=True)
+        assert rc == sd.SD_OK
+        xk = _host(x)
+        assert np.linalg.norm(xk - ref[k - 1]) <= 1e-8 * np.linalg.norm(ref[k - 1])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_advance_full_size_residuals(precision):
+    """512 x 256 per subdomain (N = 524,288), dt = 0.1: every step's true
+    residual, A x^{n+1} - (b + M x^n) with the oracle's matrix, meets the
+    tolerance, with the Cahouet-Chabard middle block."""
+    p = config_problem("T1")
+    a = assemble(p)
+    P = sd.Problem(p, device=True)
+    S = sd.Solver(P, tol=1e-8, restart=60, precision=precision, schur="cc")
+    x = _dev(np.zeros(a.N))
+    prev = np.zeros(a.N)
+    for k in range(3):
+        stats, done, rc = S.advance(x, 1)
+        print("T1", precision, k, stats[0], flush=True)
+        assert rc == sd.SD_OK and done == 1
+        xk = _host(x)
+        rhs = step_rhs(a, a.b, prev)
+        assert np.linalg.norm(rhs - a.A @ xk) <= 1e-8 * np.linalg.norm(rhs)
+        prev = xk
