@@ -18,4 +18,5 @@ Modules
             mixed-precision iterative-refinement driver
   hashing   the 32-bit integer finaliser used for aggregation priorities
   transient backward-Euler steps of the transient free flow (Sec. 2)
+  assemble3d the same model and closures on a 3-D box grid
 """

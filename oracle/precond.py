@@ -89,9 +89,13 @@ class BlockPreconditioner:
 
 
 def velocity_components(a: Assembled) -> np.ndarray:
+    """Component of every velocity unknown: 0 = u, 1 = v, 2 = w (3-D)."""
     o = a.layout.block_off
     comp = np.zeros(int(o[2]), dtype=np.int32)
     comp[o[1]:o[2]] = 1
+    off_w = getattr(a.layout, "off_w", None)
+    if off_w is not None:
+        comp[off_w:o[2]] = 2
     return comp
 
 
@@ -142,7 +146,7 @@ def build(p, a: Assembled, variant: str = "BGS", schur: str = SCHUR_MASS,
     hV = amg_mod.setup(blk["V"], velocity_components(a), False, opts)
     Dt = darcy_interface_block(blk)
     hD = amg_mod.setup(Dt, np.zeros(Dt.shape[0], dtype=np.int32), False, opts)
-    vol = (p.Lx / p.nx) * (p.H_ff / p.ny)
+    vol = ((p.Lx / p.nx) * (p.H_ff / p.ny)) * p.dz     # dz = 1 in 2-D
     xscale = p.mu / vol if schur in (SCHUR_MASS, SCHUR_CC) else 1.0
     hL = None
     if schur == SCHUR_CC:

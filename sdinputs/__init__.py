@@ -76,6 +76,23 @@ class Problem:
     f_v: Optional[np.ndarray] = None
     q_pm: Optional[np.ndarray] = None
     dt: float = 0.0                          # backward-Euler step, 0 = stationary
+    # ---- third dimension (nz = 0: the 2-D problem above) ----
+    nz: int = 0                              # spanwise cells (z), both subdomains
+    Lz: float = 1.0
+    pm_back: str = BC_NOFLOW                 # porous sides z = 0 / z = Lz
+    pm_front: str = BC_NOFLOW
+    ff_left_tz: Optional[np.ndarray] = None   # w on the left wall [ny, nz+1]
+    ff_right_tz: Optional[np.ndarray] = None  # w or t_z.(pI - tau)n at x = Lx [ny, nz+1]
+    ff_top_tz: Optional[np.ndarray] = None    # w on the top wall [nz+1, nx]
+    ff_back_u: Optional[np.ndarray] = None    # wall z = 0: u [ny, nx+1], v [ny+1, nx],
+    ff_back_v: Optional[np.ndarray] = None    #   normal w [ny, nx]
+    ff_back_n: Optional[np.ndarray] = None
+    ff_front_u: Optional[np.ndarray] = None   # wall z = Lz: same shapes
+    ff_front_v: Optional[np.ndarray] = None
+    ff_front_n: Optional[np.ndarray] = None
+    pm_back_p: Optional[np.ndarray] = None    # [ny_pm, nx]
+    pm_front_p: Optional[np.ndarray] = None
+    f_w: Optional[np.ndarray] = None          # [ny, nz+1, nx]
 
     @property
     def dx(self) -> float:
@@ -92,6 +109,10 @@ class Problem:
     @property
     def y_gamma(self) -> float:
         return self.H_pm
+
+    @property
+    def dz(self) -> float:
+        return self.Lz / self.nz if self.nz > 0 else 1.0
 
 
 # ----------------------------------------------------------------------------
@@ -124,20 +145,66 @@ def pm_cell_xy(p: Problem):
     return np.meshgrid(x, y)
 
 
+def u_face_xyz(p: Problem):
+    """3-D: coordinates of all u faces, arrays of shape [ny, nz, nx+1]."""
+    y = p.y_gamma + (np.arange(p.ny) + 0.5) * p.dy
+    z = (np.arange(p.nz) + 0.5) * p.dz
+    x = np.arange(p.nx + 1) * p.dx
+    Y, Z, X = np.meshgrid(y, z, x, indexing="ij")
+    return X, Y, Z
+
+
+def v_face_xyz(p: Problem):
+    """3-D: all v faces, [ny+1, nz, nx]."""
+    y = p.y_gamma + np.arange(p.ny + 1) * p.dy
+    z = (np.arange(p.nz) + 0.5) * p.dz
+    x = (np.arange(p.nx) + 0.5) * p.dx
+    Y, Z, X = np.meshgrid(y, z, x, indexing="ij")
+    return X, Y, Z
+
+
+def w_face_xyz(p: Problem):
+    """3-D: all w faces, [ny, nz+1, nx]."""
+    y = p.y_gamma + (np.arange(p.ny) + 0.5) * p.dy
+    z = np.arange(p.nz + 1) * p.dz
+    x = (np.arange(p.nx) + 0.5) * p.dx
+    Y, Z, X = np.meshgrid(y, z, x, indexing="ij")
+    return X, Y, Z
+
+
+def ff_cell_xyz(p: Problem):
+    """3-D: free-flow cell centres, [ny, nz, nx]."""
+    y = p.y_gamma + (np.arange(p.ny) + 0.5) * p.dy
+    z = (np.arange(p.nz) + 0.5) * p.dz
+    x = (np.arange(p.nx) + 0.5) * p.dx
+    Y, Z, X = np.meshgrid(y, z, x, indexing="ij")
+    return X, Y, Z
+
+
+def pm_cell_xyz(p: Problem):
+    """3-D: porous cell centres, [ny_pm, nz, nx]."""
+    y = (np.arange(p.ny_pm) + 0.5) * p.dy_pm
+    z = (np.arange(p.nz) + 0.5) * p.dz
+    x = (np.arange(p.nx) + 0.5) * p.dx
+    Y, Z, X = np.meshgrid(y, z, x, indexing="ij")
+    return X, Y, Z
+
+
 # ----------------------------------------------------------------------------
 # Permeability fields
 # ----------------------------------------------------------------------------
 
 def lognormal_K(nx: int, ny_pm: int, K_geo: float, sigma: float,
-                corr_cells: float, seed: int) -> np.ndarray:
+                corr_cells: float, seed: int, nz: Optional[int] = None) -> np.ndarray:
     """ln K ~ N(ln K_geo, sigma^2) per cell with a Gaussian-smoothed
     correlation: iid N(0,1) (PCG64 from ``seed``), Gaussian filter with a
     standard deviation of ``corr_cells`` cells (reflecting borders, truncated
-    at 4 sigma), re-standardised to zero mean and unit variance."""
+    at 4 sigma), re-standardised to zero mean and unit variance.  With ``nz``
+    the field is 3-D, shape [ny_pm, nz, nx]."""
     from scipy.ndimage import gaussian_filter
 
     rng = np.random.default_rng(seed)
-    z = rng.standard_normal((ny_pm, nx))
+    z = rng.standard_normal((ny_pm, nx) if nz is None else (ny_pm, nz, nx))
     if corr_cells > 0:
         z = gaussian_filter(z, sigma=corr_cells, mode="reflect", truncate=4.0)
     z = (z - z.mean()) / z.std()
@@ -300,14 +367,141 @@ def channel_problem(nx: int, ny: int, ny_pm: Optional[int] = None, *,
     return p
 
 
+# ----------------------------------------------------------------------------
+# Three dimensions: x streamwise, y normal to Gamma, z spanwise
+# ----------------------------------------------------------------------------
+
+def mms3d_problem(nx: int, ny: int, nz: int, plane: str = "xy",
+                  K: float = 1e-2, mu: float = 1.0, alpha: float = 1.0) -> tuple[Problem, MMS]:
+    """3-D manufactured solution made of the 2-D one of ``MMS``.  plane "xy":
+    (u, v, p, P) = MMS(x, y) and w = 0, constant in z; plane "zy": the same
+    solution turned into the (z, y) plane, u = 0, v = MMS.v(z, y),
+    w = MMS.u(z, y), p = MMS.p(z, y), P = MMS.P(z, y), constant in x.  Both
+    meet the three interface conditions (BJS on u and on w).  Unit box
+    [0,1] x [0,1] x [0,1] with Gamma at y = 1/2; free-flow velocity data on the
+    left, top and both z walls, traction on the right, Dirichlet pressure on
+    every outer porous side."""
+    p = Problem(nx=nx, ny=ny, ny_pm=ny, nz=nz, Lx=1.0, H_ff=0.5, H_pm=0.5, Lz=1.0, mu=mu,
+                alpha_bj=alpha, K=np.full((ny, nz, nx), K), ff_left=BC_VELOCITY,
+                ff_right=BC_TRACTION, ff_top=BC_VELOCITY, pm_left=BC_PRESSURE,
+                pm_right=BC_PRESSURE, pm_bottom=BC_PRESSURE, pm_back=BC_PRESSURE,
+                pm_front=BC_PRESSURE)
+    m = MMS(K=K, mu=mu, alpha=alpha, y_gamma=0.5)
+    if plane == "xy":
+        U = lambda x, y, z: m.u(x, y) + np.zeros(np.broadcast(x, y, z).shape)
+        V = lambda x, y, z: m.v(x, y) + np.zeros(np.broadcast(x, y, z).shape)
+        W = lambda x, y, z: np.zeros(np.broadcast(x, y, z).shape)
+        Pf = lambda x, y, z: m.p(x, y) + np.zeros(np.broadcast(x, y, z).shape)
+        Pm = lambda x, y, z: m.P(x, y) + np.zeros(np.broadcast(x, y, z).shape)
+        Fx = lambda x, y, z: m.f_x(x, y)
+        Fy = lambda x, y, z: m.f_y(x, y)
+        Fz = lambda x, y, z: np.zeros(np.broadcast(x, y, z).shape)
+        S = lambda x, y, z: m.s_pm(x, y)
+        Tn = lambda y, z: m.flux_n(1.0, y) + np.zeros(np.broadcast(y, z).shape)
+        Tt = lambda y, z: m.flux_t(1.0, y) + np.zeros(np.broadcast(y, z).shape)
+        Tz = lambda y, z: np.zeros(np.broadcast(y, z).shape)
+    elif plane == "zy":
+        U = lambda x, y, z: np.zeros(np.broadcast(x, y, z).shape)
+        V = lambda x, y, z: m.v(z, y) + np.zeros(np.broadcast(x, y, z).shape)
+        W = lambda x, y, z: m.u(z, y) + np.zeros(np.broadcast(x, y, z).shape)
+        Pf = lambda x, y, z: m.p(z, y) + np.zeros(np.broadcast(x, y, z).shape)
+        Pm = lambda x, y, z: m.P(z, y) + np.zeros(np.broadcast(x, y, z).shape)
+        Fx = lambda x, y, z: np.zeros(np.broadcast(x, y, z).shape)
+        Fy = lambda x, y, z: m.f_y(z, y)
+        Fz = lambda x, y, z: m.f_x(z, y)
+        S = lambda x, y, z: m.s_pm(z, y)
+        Tn = lambda y, z: m.p(z, y)           # n.(pI - tau)n with u = 0, d/dx = 0
+        Tt = lambda y, z: np.zeros(np.broadcast(y, z).shape)
+        Tz = lambda y, z: np.zeros(np.broadcast(y, z).shape)
+    else:
+        raise ValueError(plane)
+    dx, dy, dz, yg = p.dx, p.dy, p.dz, 0.5
+    yc = yg + (np.arange(ny) + 0.5) * dy
+    yv = yg + np.arange(ny + 1) * dy
+    zc = (np.arange(nz) + 0.5) * dz
+    zw = np.arange(nz + 1) * dz
+    xu = np.arange(nx + 1) * dx
+    xc = (np.arange(nx) + 0.5) * dx
+    ytop = yg + 0.5
+    ypm = (np.arange(ny) + 0.5) * p.dy_pm
+    g2 = lambda a, b: np.meshgrid(a, b, indexing="ij")
+    Y, Z = g2(yc, zc)
+    p.ff_left_n = U(0.0, Y, Z)
+    Y, Z = g2(yv, zc)
+    p.ff_left_t = V(0.0, Y, Z)
+    p.ff_right_t = Tt(Y, Z)
+    Y, Z = g2(yc, zw)
+    p.ff_left_tz = W(0.0, Y, Z)
+    p.ff_right_tz = Tz(Y, Z)
+    Y, Z = g2(yc, zc)
+    p.ff_right_n = Tn(Y, Z)
+    Z, X = g2(zc, xu)
+    p.ff_top_t = U(X, ytop, Z)
+    Z, X = g2(zc, xc)
+    p.ff_top_n = V(X, ytop, Z)
+    Z, X = g2(zw, xc)
+    p.ff_top_tz = W(X, ytop, Z)
+    for zval, tag in ((0.0, "back"), (1.0, "front")):
+        Y, X = g2(yc, xu)
+        setattr(p, f"ff_{tag}_u", U(X, Y, zval))
+        Y, X = g2(yv, xc)
+        setattr(p, f"ff_{tag}_v", V(X, Y, zval))
+        Y, X = g2(yc, xc)
+        setattr(p, f"ff_{tag}_n", W(X, Y, zval))
+        Y, X = g2(ypm, xc)
+        setattr(p, f"pm_{tag}_p", Pm(X, Y, zval))
+    Y, Z = g2(ypm, zc)
+    p.pm_left_p = Pm(0.0, Y, Z)
+    p.pm_right_p = Pm(1.0, Y, Z)
+    Z, X = g2(zc, xc)
+    p.pm_bottom_p = Pm(X, 0.0, Z)
+    X, Y, Z = u_face_xyz(p)
+    p.f_u = Fx(X, Y, Z)
+    X, Y, Z = v_face_xyz(p)
+    p.f_v = Fy(X, Y, Z)
+    X, Y, Z = w_face_xyz(p)
+    p.f_w = Fz(X, Y, Z)
+    X, Y, Z = pm_cell_xyz(p)
+    p.q_pm = S(X, Y, Z)
+    ex = dict(u=U, v=V, w=W, p=Pf, P=Pm)
+    return p, ex
+
+
+def channel3d_problem(nx: int, ny: int, nz: int, ny_pm: Optional[int] = None, *,
+                      mu: float = 1e-3, K_geo: float = 1e-4, sigma: float = 1.0,
+                      corr_cells: float = 6.0, seed: int = 4, U: float = 1e-2,
+                      alpha: float = 1.0, Lx: float = 1.0, H_ff: float = 0.5,
+                      H_pm: float = 0.5, Lz: float = 1.0) -> Problem:
+    """3-D channel over a porous bed: inflow u = 16 U s (H - s) z (Lz - z) /
+    (H^2 Lz^2) on the left (s = y - y_G), zero traction on the right, no-slip
+    top and z walls, no-flow on every outer porous side, lognormal K."""
+    ny_pm = ny if ny_pm is None else ny_pm
+    K = lognormal_K(nx, ny_pm, K_geo, sigma, corr_cells, seed, nz=nz)
+    p = Problem(nx=nx, ny=ny, ny_pm=ny_pm, nz=nz, Lx=Lx, H_ff=H_ff, H_pm=H_pm, Lz=Lz,
+                mu=mu, alpha_bj=alpha, K=K, ff_left=BC_VELOCITY, ff_right=BC_TRACTION,
+                ff_top=BC_VELOCITY, pm_left=BC_NOFLOW, pm_right=BC_NOFLOW,
+                pm_bottom=BC_NOFLOW, pm_back=BC_NOFLOW, pm_front=BC_NOFLOW)
+    s = (np.arange(ny) + 0.5) * p.dy
+    z = (np.arange(nz) + 0.5) * p.dz
+    S, Z = np.meshgrid(s, z, indexing="ij")
+    p.ff_left_n = 16.0 * U * S * (H_ff - S) * Z * (Lz - Z) / (H_ff * H_ff * Lz * Lz)
+    return p
+
+
 # Named workloads (cells per subdomain) ---------------------------------------
 
 def config_problem(name: str) -> Problem:
     """C0: 32x16 manufactured solution; C1: 512x256 channel (seed 1);
     C2: 1024x512 channel (seed 2); T1: the C1 channel as the system of one
-    backward-Euler step of 0.1 (its flow started from rest)."""
+    backward-Euler step of 0.1 (its flow started from rest); C4: 3-D channel,
+    96 x 48 x 96 cells per subdomain (x, y, z), one backward-Euler step of
+    0.1."""
     if name == "T1":
         p = channel_problem(512, 256, seed=1)
+        p.dt = 0.1
+        return p
+    if name == "C4":
+        p = channel3d_problem(96, 48, 96, seed=4)
         p.dt = 0.1
         return p
     if name == "C0":
