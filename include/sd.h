@@ -35,6 +35,10 @@
  * traction right boundary, nx-1 with a velocity one), v faces (j = 0..ny-1,
  * j = 0 on Gamma), free-flow cell pressures, porous cell pressures (row k = 0
  * at the bottom).  Dirichlet velocity faces are eliminated and lifted into b.
+ * 3-D (nz > 0): the box has depth Lz with nz cell layers in z; unknowns u, v,
+ * w (z faces k = 1..nz-1), p, q, each ordered (row j, layer k, column i) with
+ * i fastest; the velocity block is u, v, w.  The interface conditions hold
+ * for both tangential velocities.
  */
 #ifndef SD_H
 #define SD_H
@@ -72,6 +76,8 @@ typedef struct {
 typedef struct {
   int nx, ny, ny_pm;          /* cells: columns, free-flow rows, porous rows  */
   double Lx, H_ff, H_pm;      /* extents; Gamma at y = H_pm                    */
+  int nz;                     /* spanwise cells (z); 0 = the 2-D problem       */
+  double Lz;                  /* spanwise extent (3-D only)                    */
 } sd_grid;
 
 typedef struct {
@@ -84,28 +90,48 @@ typedef enum { SD_BC_VELOCITY = 0, SD_BC_TRACTION = 1, SD_BC_PRESSURE = 2,
                SD_BC_NOFLOW = 3 } sd_bc_type;
 
 /* Boundary conditions.  Free-flow left and top: SD_BC_VELOCITY; right:
- * SD_BC_VELOCITY or SD_BC_TRACTION; porous left/right/bottom: SD_BC_PRESSURE
- * or SD_BC_NOFLOW.  Data arrays may be NULL (zero):
+ * SD_BC_VELOCITY or SD_BC_TRACTION; porous left/right/bottom (and back/front
+ * in 3-D): SD_BC_PRESSURE or SD_BC_NOFLOW.  Data arrays may be NULL (zero).
+ * 2-D shapes:
  *   ff_left_n [ny] u at x=0;  ff_left_t [ny+1] v on the left wall at y_G + j dy
  *   ff_right_n [ny]  u (velocity) or n.(pI - tau)n (traction) at x = Lx
  *   ff_right_t [ny+1] v (velocity) or t.(pI - tau)n (traction), y_G + j dy
  *   ff_top_t [nx+1] u on the top wall at x = i dx; ff_top_n [nx] v on the top
- *   pm_left_p, pm_right_p [ny_pm], pm_bottom_p [nx] Dirichlet pressures     */
+ *   pm_left_p, pm_right_p [ny_pm], pm_bottom_p [nx] Dirichlet pressures
+ * 3-D (x streamwise, y normal to Gamma, z spanwise; the z walls of the free
+ * flow are velocity walls; every array row-major with x fastest):
+ *   ff_left_n, ff_right_n [ny][nz]; ff_left_t, ff_right_t [ny+1][nz];
+ *   ff_left_tz, ff_right_tz [ny][nz+1] (w, or t_z.(pI - tau)n for traction);
+ *   ff_top_t [nz][nx+1], ff_top_n [nz][nx], ff_top_tz [nz+1][nx] (w);
+ *   ff_back_* on z = 0 and ff_front_* on z = Lz: _u [ny][nx+1], _v [ny+1][nx],
+ *   _n (normal w) [ny][nx];
+ *   pm_left_p, pm_right_p [ny_pm][nz], pm_bottom_p [nz][nx],
+ *   pm_back_p, pm_front_p [ny_pm][nx]. */
 typedef struct {
   int ff_left, ff_right, ff_top, pm_left, pm_right, pm_bottom;
   const double *ff_left_n, *ff_left_t, *ff_right_n, *ff_right_t;
   const double *ff_top_t, *ff_top_n;
   const double *pm_left_p, *pm_right_p, *pm_bottom_p;
+  /* 3-D only */
+  const double *ff_left_tz, *ff_right_tz, *ff_top_tz;
+  const double *ff_back_u, *ff_back_v, *ff_back_n;
+  const double *ff_front_u, *ff_front_v, *ff_front_n;
+  const double *pm_back_p, *pm_front_p;
+  int pm_back, pm_front;
 } sd_bcs;
 
 /* Forcing sampled at DoF locations (NULL = 0): f_u [ny][nx+1] at all u faces,
- * f_v [ny+1][nx] at all v faces, q_pm [ny_pm][nx] porous source. */
+ * f_v [ny+1][nx] at all v faces, q_pm [ny_pm][nx] porous source; in 3-D
+ * f_u [ny][nz][nx+1], f_v [ny+1][nz][nx], f_w [ny][nz+1][nx],
+ * q_pm [ny_pm][nz][nx]. */
 typedef struct {
   const double *f_u, *f_v, *q_pm;
+  const double *f_w;
 } sd_forcing;
 
 /* Assemble the coupled system (Sec. 2) on the host and upload it to the
- * current device.  K: [ny_pm][nx] positive permeabilities (host).  The matrix
+ * current device.  K: [ny_pm][nx] (3-D: [ny_pm][nz][nx]) positive
+ * permeabilities (host).  The matrix
  * is kept in FP64; its values are those of the documented stencil evaluated
  * in IEEE double without contraction.  allocator may be NULL; hip_stream may
  * be NULL (default stream). */
@@ -281,7 +307,8 @@ typedef struct {
 } sd_request;
 
 /* Queue a solve.  All host data is copied.  SD_E_NOMEM if the request can
- * never fit the budget. */
+ * never fit the budget; SD_E_INVALID for a 3-D grid (the request loop serves
+ * 2-D problems) or a krylov other than FGMRES. */
 int sd_submit(sd_server* sv, const sd_request* req, uint64_t* ticket);
 
 enum { SD_REQ_PENDING = 0, SD_REQ_RUNNING = 1, SD_REQ_DONE = 2, SD_REQ_FAILED = 3 };

@@ -246,7 +246,7 @@ static void step_rhs_impl(sd_solver* s, const double* d_b, const double* d_x, do
   if (!d_x || !d_out) throw sd::Error(SD_E_INVALID, "NULL device vector");
   const sd::Layout& L = hp.L;
   sd::launch_step_rhs(d_b ? d_b : s->s->b_dev, d_x, d_out, hp.mass, (int)L.N, L.nux, L.nx,
-                      (int)L.off_v, (int)L.off_p, st);
+                      (int)L.off_v, L.nx * L.nzc(), (int)L.off_w, (int)L.off_p, st);
   SD_HIP(hipGetLastError());
 }
 

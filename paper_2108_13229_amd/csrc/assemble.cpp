@@ -40,32 +40,32 @@ void check_array(const double* a, int64_t n, const char* what) {
       throw Error(SD_E_INVALID, std::string("non-finite value in ") + what);
 }
 
-struct RowBuilder {
-  HostCSR& A;
-  std::vector<std::pair<int32_t, double>> row;
-  explicit RowBuilder(HostCSR& a) : A(a) {}
-  void add(int64_t c, double v) { row.emplace_back((int32_t)c, v); }
-  void finish() {
-    std::sort(row.begin(), row.end(),
-              [](const std::pair<int32_t, double>& a,
-                 const std::pair<int32_t, double>& b) { return a.first < b.first; });
-    for (size_t k = 1; k < row.size(); ++k)
-      if (row[k].first == row[k - 1].first)
-        throw Error(SD_E_INVALID, "internal: duplicate matrix entry");
-    for (auto& e : row) {
-      A.col.push_back(e.first);
-      A.val.push_back(e.second);
-    }
-    A.rowptr.push_back((int64_t)A.col.size());
-    row.clear();
-  }
-};
-
 }  // namespace
+
+void RowBuilder::finish() {
+  std::sort(row.begin(), row.end(),
+            [](const std::pair<int32_t, double>& a, const std::pair<int32_t, double>& b) {
+              return a.first < b.first;
+            });
+  for (size_t k = 1; k < row.size(); ++k)
+    if (row[k].first == row[k - 1].first)
+      throw Error(SD_E_INVALID, "internal: duplicate matrix entry");
+  for (auto& e : row) {
+    A.col.push_back(e.first);
+    A.val.push_back(e.second);
+  }
+  A.rowptr.push_back((int64_t)A.col.size());
+  row.clear();
+}
 
 void assemble_host(const sd_grid* g, const sd_physics* ph, const sd_bcs* bcs,
                    const double* K, const sd_forcing* f, HostProblem& P) {
   if (!g || !ph || !bcs || !K) throw Error(SD_E_INVALID, "null argument");
+  if (g->nz < 0) throw Error(SD_E_INVALID, "nz must be >= 0 (0 = 2-D)");
+  if (g->nz > 0) {
+    assemble_host_3d(g, ph, bcs, K, f, P);
+    return;
+  }
   const int nx = g->nx, ny = g->ny, nyp = g->ny_pm;
   if (nx < 2 || ny < 2 || nyp < 1)
     throw Error(SD_E_INVALID, "need nx >= 2, ny >= 2, ny_pm >= 1");
@@ -108,6 +108,7 @@ void assemble_host(const sd_grid* g, const sd_physics* ph, const sd_bcs* bcs,
   L.nux = right_tr ? nx : nx - 1;
   L.off_v = (int64_t)L.nux * ny;
   L.off_p = L.off_v + (int64_t)nx * ny;
+  L.off_w = L.off_p;
   L.off_q = L.off_p + (int64_t)nx * ny;
   L.N = L.off_q + (int64_t)nx * nyp;
   if (L.N >= (int64_t)1 << 31) throw Error(SD_E_INVALID, "problem too large for 32-bit indices");

@@ -5,6 +5,7 @@
 #include <functional>
 #include <stdexcept>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "sd.h"
@@ -26,18 +27,29 @@ struct HostCSR {
 };
 
 // Unknown numbering of the pressure-velocity block form.
+// 2-D: u, v, p, q; 3-D (nz > 0): u, v, w, p, q with (row j, layer k,
+// column i) order, i fastest.  In 2-D off_w = off_p (no w block).
 struct Layout {
-  int nx = 0, ny = 0, nyp = 0, nux = 0;
-  int64_t off_v = 0, off_p = 0, off_q = 0, N = 0;
-  // rows with a time derivative: u faces i <= nx-1 and v faces j >= 1
+  int nx = 0, ny = 0, nyp = 0, nux = 0, nz = 0;
+  int64_t off_v = 0, off_w = 0, off_p = 0, off_q = 0, N = 0;
+  int nzc() const { return nz > 0 ? nz : 1; }
+  // rows with a time derivative: u faces i <= nx-1, v faces j >= 1, all w faces
   bool has_mass(int64_t r) const {
     if (r < off_v) return (int)(r % nux) + 1 <= nx - 1;
-    return r >= off_v + nx && r < off_p;
+    if (r < off_w) return r >= off_v + (int64_t)nx * nzc();
+    return r < off_p;
   }
   int64_t u(int i, int j) const { return (int64_t)j * nux + (i - 1); }
   int64_t v(int i, int j) const { return off_v + (int64_t)j * nx + i; }
   int64_t p(int i, int j) const { return off_p + (int64_t)j * nx + i; }
   int64_t q(int i, int k) const { return off_q + (int64_t)k * nx + i; }
+  int64_t u3(int i, int j, int k) const { return ((int64_t)j * nz + k) * nux + (i - 1); }
+  int64_t v3(int i, int j, int k) const { return off_v + ((int64_t)j * nz + k) * nx + i; }
+  int64_t w3(int i, int j, int k) const {
+    return off_w + ((int64_t)j * (nz - 1) + (k - 1)) * nx + i;
+  }
+  int64_t p3(int i, int j, int k) const { return off_p + ((int64_t)j * nz + k) * nx + i; }
+  int64_t q3(int i, int j, int k) const { return off_q + ((int64_t)j * nz + k) * nx + i; }
 };
 
 struct HostProblem {
@@ -53,6 +65,19 @@ struct HostProblem {
 
 void assemble_host(const sd_grid* g, const sd_physics* ph, const sd_bcs* bcs,
                    const double* K, const sd_forcing* f, HostProblem& out);
+// The 3-D box (g->nz > 0); assemble_host dispatches to it.
+void assemble_host_3d(const sd_grid* g, const sd_physics* ph, const sd_bcs* bcs,
+                      const double* K, const sd_forcing* f, HostProblem& out);
+
+// Row builder shared by the assembly routines: entries of one row are
+// collected, sorted by column and appended to A.
+struct RowBuilder {
+  HostCSR& A;
+  std::vector<std::pair<int32_t, double>> row;
+  explicit RowBuilder(HostCSR& a) : A(a) {}
+  void add(int64_t c, double v) { row.emplace_back((int32_t)c, v); }
+  void finish();
+};
 
 HostCSR extract_block(const HostCSR& A, int64_t r0, int64_t r1, int64_t c0,
                       int64_t c1);

@@ -317,12 +317,17 @@ int sd_submit(sd_server* sv, const sd_request* req, uint64_t* ticket) {
   if (!sv || !req || !ticket || !req->K) return SD_E_INVALID;
   const sd_grid& g = req->grid;
   if (g.nx < 2 || g.ny < 2 || g.ny_pm < 1) return SD_E_INVALID;
+  if (g.nz != 0) return SD_E_INVALID;   // the request loop serves 2-D problems
   if (req->opts.krylov != SD_KRYLOV_FGMRES) return SD_E_INVALID;  // resumable driver
   std::unique_ptr<Request> r(new Request());
   r->grid = g;
   r->phys = req->phys;
   r->opts = req->opts;
   r->bcs = req->bcs;
+  r->bcs.ff_left_tz = r->bcs.ff_right_tz = r->bcs.ff_top_tz = nullptr;   // 3-D only
+  r->bcs.ff_back_u = r->bcs.ff_back_v = r->bcs.ff_back_n = nullptr;
+  r->bcs.ff_front_u = r->bcs.ff_front_v = r->bcs.ff_front_n = nullptr;
+  r->bcs.pm_back_p = r->bcs.pm_front_p = nullptr;
   const int64_t nx = g.nx, ny = g.ny, nyp = g.ny_pm;
   r->K.assign(req->K, req->K + nx * nyp);
   const double* src[9] = {req->bcs.ff_left_n, req->bcs.ff_left_t, req->bcs.ff_right_n,
@@ -340,6 +345,7 @@ int sd_submit(sd_server* sv, const sd_request* req, uint64_t* ticket) {
       *dst[k] = nullptr;
     }
   }
+  r->forcing.f_w = nullptr;
   const double* fs[3] = {req->forcing.f_u, req->forcing.f_v, req->forcing.q_pm};
   const int64_t fl[3] = {ny * (nx + 1), (ny + 1) * nx, nyp * nx};
   const double** fd[3] = {&r->forcing.f_u, &r->forcing.f_v, &r->forcing.q_pm};

@@ -240,7 +240,8 @@ void Solver::setup_host(HostProblem* p, const sd_solver_opts* o) {
   HostCSR B1 = extract_block(p->A, 0, L.off_p, L.off_q, L.N);
   HostCSR Dt = darcy_interface_block(Db, C1, B1, Vb);
   std::vector<int32_t> compV((size_t)L.off_p, 0);
-  for (int64_t i = L.off_v; i < L.off_p; ++i) compV[i] = 1;
+  for (int64_t i = L.off_v; i < L.off_w; ++i) compV[i] = 1;
+  for (int64_t i = L.off_w; i < L.off_p; ++i) compV[i] = 2;   // w (3-D)
   std::vector<int32_t> compD((size_t)(L.N - L.off_q), 0);
   amg_setup_host(Vb, compV, false, opts.amg, hh[0]);
   amg_setup_host(Dt, compD, false, opts.amg, hh[1]);
@@ -265,7 +266,8 @@ void Solver::setup_host(HostProblem* p, const sd_solver_opts* o) {
     Cf.n_cols = L.off_p;
     Cf.rowptr.assign((size_t)Cf.n_rows + 1, 0);
   }
-  const double vol = (p->grid.Lx / (double)p->grid.nx) * (p->grid.H_ff / (double)p->grid.ny);
+  const double dz = p->L.nz > 0 ? p->grid.Lz / (double)p->grid.nz : 1.0;
+  const double vol = ((p->grid.Lx / (double)p->grid.nx) * (p->grid.H_ff / (double)p->grid.ny)) * dz;
   xscale = so.schur == SD_SCHUR_IDENTITY ? 1.0 : p->phys.mu / vol;
   t_setup = wall_time() - t0;
 }

@@ -32,7 +32,8 @@ _dp = C.POINTER(C.c_double)
 
 class Grid(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("ny_pm", C.c_int),
-                ("Lx", C.c_double), ("H_ff", C.c_double), ("H_pm", C.c_double)]
+                ("Lx", C.c_double), ("H_ff", C.c_double), ("H_pm", C.c_double),
+                ("nz", C.c_int), ("Lz", C.c_double)]
 
 
 class Physics(C.Structure):
@@ -44,11 +45,16 @@ class Bcs(C.Structure):
                 ("pm_left", C.c_int), ("pm_right", C.c_int), ("pm_bottom", C.c_int),
                 ("ff_left_n", _dp), ("ff_left_t", _dp), ("ff_right_n", _dp),
                 ("ff_right_t", _dp), ("ff_top_t", _dp), ("ff_top_n", _dp),
-                ("pm_left_p", _dp), ("pm_right_p", _dp), ("pm_bottom_p", _dp)]
+                ("pm_left_p", _dp), ("pm_right_p", _dp), ("pm_bottom_p", _dp),
+                ("ff_left_tz", _dp), ("ff_right_tz", _dp), ("ff_top_tz", _dp),
+                ("ff_back_u", _dp), ("ff_back_v", _dp), ("ff_back_n", _dp),
+                ("ff_front_u", _dp), ("ff_front_v", _dp), ("ff_front_n", _dp),
+                ("pm_back_p", _dp), ("pm_front_p", _dp),
+                ("pm_back", C.c_int), ("pm_front", C.c_int)]
 
 
 class Forcing(C.Structure):
-    _fields_ = [("f_u", _dp), ("f_v", _dp), ("q_pm", _dp)]
+    _fields_ = [("f_u", _dp), ("f_v", _dp), ("q_pm", _dp), ("f_w", _dp)]
 
 
 class Allocator(C.Structure):
@@ -172,14 +178,22 @@ def _ptr(a, keep):
 
 
 def _marshal(p, keep):
-    g = Grid(int(p.nx), int(p.ny), int(p.ny_pm), float(p.Lx), float(p.H_ff), float(p.H_pm))
+    nz = int(getattr(p, "nz", 0))
+    g = Grid(int(p.nx), int(p.ny), int(p.ny_pm), float(p.Lx), float(p.H_ff), float(p.H_pm),
+             nz, float(getattr(p, "Lz", 1.0)))
     ph = Physics(float(p.mu), float(p.alpha_bj), float(getattr(p, "dt", 0.0)))
     b = Bcs(BC[p.ff_left], BC[p.ff_right], BC[p.ff_top], BC[p.pm_left], BC[p.pm_right],
             BC[p.pm_bottom],
             _ptr(p.ff_left_n, keep), _ptr(p.ff_left_t, keep), _ptr(p.ff_right_n, keep),
             _ptr(p.ff_right_t, keep), _ptr(p.ff_top_t, keep), _ptr(p.ff_top_n, keep),
-            _ptr(p.pm_left_p, keep), _ptr(p.pm_right_p, keep), _ptr(p.pm_bottom_p, keep))
-    f = Forcing(_ptr(p.f_u, keep), _ptr(p.f_v, keep), _ptr(p.q_pm, keep))
+            _ptr(p.pm_left_p, keep), _ptr(p.pm_right_p, keep), _ptr(p.pm_bottom_p, keep),
+            *[_ptr(getattr(p, n, None), keep) for n in (
+                "ff_left_tz", "ff_right_tz", "ff_top_tz", "ff_back_u", "ff_back_v",
+                "ff_back_n", "ff_front_u", "ff_front_v", "ff_front_n", "pm_back_p",
+                "pm_front_p")],
+            BC[getattr(p, "pm_back", "noflow")], BC[getattr(p, "pm_front", "noflow")])
+    f = Forcing(_ptr(p.f_u, keep), _ptr(p.f_v, keep), _ptr(p.q_pm, keep),
+                _ptr(getattr(p, "f_w", None), keep))
     K = _ptr(p.K, keep)
     return g, ph, b, f, K
 

@@ -165,3 +165,57 @@ def test_pressure_operator_needs_a_time_step():
     assert e.value.code == sd.SD_E_INVALID
     S = sd.Solver(P, device=False)
     assert S.n_levels(2) == 0
+
+
+def _cases3d():
+    from sdinputs import channel3d_problem, mms3d_problem
+    c_vel = channel3d_problem(9, 6, 7, 4, seed=3)
+    c_vel.ff_right = "velocity"
+    c_vel.ff_right_n = np.full((6, 7), 1e-3)
+    c_vel.ff_right_tz = np.linspace(-1e-4, 1e-4, 6 * 8).reshape(6, 8)
+    c_vel.dt = 0.05
+    c_p = channel3d_problem(10, 6, 8, 5, seed=2)
+    c_p.pm_back, c_p.pm_front = "pressure", "pressure"
+    c_p.pm_back_p = np.linspace(0.0, 1.0, 5 * 10).reshape(5, 10)
+    c_p.dt = 0.2
+    return [mms3d_problem(8, 4, 6, "xy")[0], mms3d_problem(9, 5, 7, "zy")[0],
+            channel3d_problem(12, 6, 8, seed=1), c_vel, c_p,
+            mms3d_problem(6, 4, 1, "xy")[0]]
+
+
+@pytest.mark.parametrize("ci", range(6))
+def test_host_assembly_3d_bit_exact(ci):
+    from oracle.assemble3d import assemble3d
+    p = _cases3d()[ci]
+    P = sd.Problem(p, device=False)
+    rp, col, val, b = P.csr()
+    a = assemble3d(p)
+    assert np.array_equal(rp, a.A.indptr)
+    assert np.array_equal(col, a.A.indices)
+    assert np.array_equal(val, a.A.data)        # bit-for-bit
+    assert np.array_equal(b, a.b)
+    assert np.array_equal(P.block_off, a.layout.block_off)
+
+
+@pytest.mark.parametrize("ci", [2, 3])
+@pytest.mark.parametrize("schur", ["mass", "cc"])
+def test_host_amg_3d_bit_exact(ci, schur):
+    from oracle.assemble3d import assemble3d
+    p = _cases3d()[ci]
+    if schur == "cc" and not p.dt:
+        p.dt = 0.1
+    P = sd.Problem(p, device=False)
+    S = sd.Solver(P, device=False, coarse_max=64, schur=schur)
+    a = assemble3d(p)
+    M = precond.build(p, a, "BGS", schur=schur, opts=amg.AMGOptions(coarse_max=64))
+    hs = [(0, M.hV), (1, M.hD)] + ([(2, M.hL)] if schur == "cc" else [])
+    for blk, h in hs:
+        assert S.n_levels(blk) == h.n_levels
+        for lev in range(h.n_levels):
+            L = h.levels[lev]
+            _, rp, col, val = S.level_csr(blk, lev, 0)
+            assert np.array_equal(rp, L.A.indptr) and np.array_equal(col, L.A.indices)
+            assert np.array_equal(val, L.A.data)
+            if lev + 1 < h.n_levels:
+                assert np.array_equal(S.level_agg(blk, lev), L.agg)
+
