@@ -279,17 +279,26 @@ def setup(A: sp.csr_matrix, comp: np.ndarray, singular: bool = False,
     A.sort_indices()
     comp = np.asarray(comp)
     levels = [Level(A=A, comp=comp)]
+    # strength threshold of the current level: halved (for this level and
+    # all coarser ones) whenever aggregation would shrink a level by less
+    # than min_ratio -- the level-dependent threshold of smoothed aggregation
+    # (Vanek, Mandel, Brezina 1996), applied where coarsening stalls (the
+    # wide Galerkin stencils of 3-D velocity blocks); at most 6 halvings
+    theta = opts.theta
     while (levels[-1].A.shape[0] > opts.coarse_max
            and len(levels) < opts.max_levels):
         L = levels[-1]
         lev = len(levels) - 1
-        S = strength_graph(L.A, L.comp, opts.theta)
+        S = strength_graph(L.A, L.comp, theta)
         agg, roots = aggregate(L.A, S, lev, opts.mis)
         n_c = roots.size
         if L.A.shape[0] < opts.min_ratio * n_c:
+            if theta > opts.theta / 64.0:
+                theta = theta / 2.0
+                continue
             break
         if opts.smoothed:
-            P = smoothed_prolongator(L.A, L.comp, opts.theta, agg, n_c)
+            P = smoothed_prolongator(L.A, L.comp, theta, agg, n_c)
         else:
             P = tentative(agg, n_c)
         R = P.T.tocsr()

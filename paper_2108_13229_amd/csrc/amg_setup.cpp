@@ -595,6 +595,12 @@ void amg_setup_host(const HostCSR& A0, const std::vector<int32_t>& comp0, bool s
   h.levels.emplace_back();
   h.levels[0].A = A0;
   h.levels[0].comp = comp0;
+  // Strength threshold of the current level: halved for this level and the
+  // coarser ones whenever aggregation would shrink a level by less than
+  // min_ratio (the level-dependent threshold of smoothed aggregation, Vanek,
+  // Mandel, Brezina 1996, applied where coarsening stalls, as on the wide
+  // Galerkin stencils of 3-D velocity blocks); at most 6 halvings.
+  double theta = o.theta;
   while (h.levels.back().A.n_rows > o.coarse_max && (int)h.levels.size() < o.max_levels) {
     const int lev = (int)h.levels.size() - 1;
     const HostCSR& A = h.levels.back().A;
@@ -602,7 +608,7 @@ void amg_setup_host(const HostCSR& A0, const std::vector<int32_t>& comp0, bool s
     const int64_t n = A.n_rows;
     std::vector<double> d((size_t)n);
     for (int64_t i = 0; i < n; ++i) d[i] = diag_of(A, i);
-    std::vector<uint8_t> strong = strong_mask(A, comp, d, o.theta);
+    std::vector<uint8_t> strong = strong_mask(A, comp, d, theta);
     Graph S = symmetric_strength(A, strong);
     std::vector<int8_t> state = o.mis == 1 ? luby_mis(S, lev) : luby_mis(square(S), lev);
     std::vector<int32_t> agg((size_t)n, -1);
@@ -622,7 +628,13 @@ void amg_setup_host(const HostCSR& A0, const std::vector<int32_t>& comp0, bool s
     for (int64_t i = 0; i < n; ++i)
       if (agg[i] < 0) throw Error(SD_E_INVALID, "AMG: node left without an aggregate");
     const int64_t n_c = (int64_t)roots.size();
-    if ((double)n < o.min_ratio * (double)n_c) break;
+    if ((double)n < o.min_ratio * (double)n_c) {
+      if (theta > o.theta / 64.0) {
+        theta = theta / 2.0;
+        continue;
+      }
+      break;
+    }
     HostLevel& L = h.levels.back();
     L.P = o.smoothed ? smoothed(A, strong, d, agg, n_c) : tentative(agg, n_c);
     L.R = transpose(L.P);
