@@ -281,9 +281,10 @@ def setup(A: sp.csr_matrix, comp: np.ndarray, singular: bool = False,
     levels = [Level(A=A, comp=comp)]
     # strength threshold of the current level: halved (for this level and
     # all coarser ones) whenever aggregation would shrink a level by less
-    # than min_ratio -- the level-dependent threshold of smoothed aggregation
-    # (Vanek, Mandel, Brezina 1996), applied where coarsening stalls (the
-    # wide Galerkin stencils of 3-D velocity blocks); at most 6 halvings
+    # than a factor of 2 -- the level-dependent threshold of smoothed
+    # aggregation (Vanek, Mandel, Brezina 1996), applied where coarsening
+    # stalls (the wide Galerkin stencils of 3-D hierarchies); at most 6
+    # halvings; below min_ratio the hierarchy ends
     theta = opts.theta
     while (levels[-1].A.shape[0] > opts.coarse_max
            and len(levels) < opts.max_levels):
@@ -292,10 +293,10 @@ def setup(A: sp.csr_matrix, comp: np.ndarray, singular: bool = False,
         S = strength_graph(L.A, L.comp, theta)
         agg, roots = aggregate(L.A, S, lev, opts.mis)
         n_c = roots.size
+        if L.A.shape[0] < 2.0 * n_c and theta > opts.theta / 64.0:
+            theta = theta / 2.0
+            continue
         if L.A.shape[0] < opts.min_ratio * n_c:
-            if theta > opts.theta / 64.0:
-                theta = theta / 2.0
-                continue
             break
         if opts.smoothed:
             P = smoothed_prolongator(L.A, L.comp, theta, agg, n_c)

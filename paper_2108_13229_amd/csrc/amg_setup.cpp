@@ -596,10 +596,11 @@ void amg_setup_host(const HostCSR& A0, const std::vector<int32_t>& comp0, bool s
   h.levels[0].A = A0;
   h.levels[0].comp = comp0;
   // Strength threshold of the current level: halved for this level and the
-  // coarser ones whenever aggregation would shrink a level by less than
-  // min_ratio (the level-dependent threshold of smoothed aggregation, Vanek,
+  // coarser ones whenever aggregation would shrink a level by less than a
+  // factor of 2 (the level-dependent threshold of smoothed aggregation, Vanek,
   // Mandel, Brezina 1996, applied where coarsening stalls, as on the wide
-  // Galerkin stencils of 3-D velocity blocks); at most 6 halvings.
+  // Galerkin stencils of 3-D hierarchies); at most 6 halvings; below
+  // min_ratio the hierarchy ends.
   double theta = o.theta;
   while (h.levels.back().A.n_rows > o.coarse_max && (int)h.levels.size() < o.max_levels) {
     const int lev = (int)h.levels.size() - 1;
@@ -628,13 +629,11 @@ void amg_setup_host(const HostCSR& A0, const std::vector<int32_t>& comp0, bool s
     for (int64_t i = 0; i < n; ++i)
       if (agg[i] < 0) throw Error(SD_E_INVALID, "AMG: node left without an aggregate");
     const int64_t n_c = (int64_t)roots.size();
-    if ((double)n < o.min_ratio * (double)n_c) {
-      if (theta > o.theta / 64.0) {
-        theta = theta / 2.0;
-        continue;
-      }
-      break;
+    if ((double)n < 2.0 * (double)n_c && theta > o.theta / 64.0) {
+      theta = theta / 2.0;
+      continue;
     }
+    if ((double)n < o.min_ratio * (double)n_c) break;
     HostLevel& L = h.levels.back();
     L.P = o.smoothed ? smoothed(A, strong, d, agg, n_c) : tentative(agg, n_c);
     L.R = transpose(L.P);

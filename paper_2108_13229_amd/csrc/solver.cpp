@@ -338,6 +338,14 @@ namespace {
 // the transfers (fewer, wider launches); larger levels keep separate passes,
 // whose one-lane-per-row stencil gathers are coalesced.
 constexpr int64_t kFusePreRows = 196608, kFusePostRows = 65536;
+// Fusion pays while the fused operators stay about as sparse as the passes
+// they replace.  On the wide Galerkin stencils of 3-D hierarchies
+// G = R (I - A M2) grows to 4-18x the nonzeros of Q = [R | -RA] and
+// F = P - W A P to 0.75-0.8x those of A (2-D: at most 1.9x and 0.55x), so such
+// levels keep separate passes; G is not even formed above an average row
+// width of kFuseMaxRowWidth.
+constexpr double kFuseMaxGOverQ = 3.0, kFuseMaxFOverA = 0.65;
+constexpr int64_t kFuseMaxRowWidth = 64;
 
 template <typename T>
 void upload_hierarchy(const HostHierarchy& h, DevHierarchy<T>& d, double omega, int nu_pre,
@@ -364,18 +372,31 @@ void upload_hierarchy(const HostHierarchy& h, DevHierarchy<T>& d, double omega, 
         D.AW = upload_sell<T>(AW, mem, s, true, D.A.lpr);
       }
       D.P = upload_sell<T>(H.P, mem, s, true);
-      D.fuse_pre = nu_pre == 2 && (l > 0 || H.A.n_rows < kFusePreRows);
-      D.fuse_post = nu_post >= 1 && (l > 0 || H.A.n_rows < kFusePostRows);
+      const int64_t nnzA = H.A.nnz();
+      HostCSR G, Q, F;
+      if (l > 0) Q = residual_restriction(H.A, H.R);
+      D.fuse_pre = nu_pre == 2 && (l > 0 || H.A.n_rows < kFusePreRows) &&
+                   nnzA <= kFuseMaxRowWidth * H.A.n_rows;
       if (D.fuse_pre) {
-        D.G = upload_sell<T>(presmoothed_restriction(H.A, H.R, omega), mem, s, true, 64);
+        G = presmoothed_restriction(H.A, H.R, omega);
+        const int64_t replaced = l > 0 ? Q.nnz() : H.R.nnz() + nnzA;
+        D.fuse_pre = (double)G.nnz() <= kFuseMaxGOverQ * (double)replaced;
+      }
+      D.fuse_post = nu_post >= 1 && (l > 0 || H.A.n_rows < kFusePostRows);
+      if (D.fuse_post) {
+        F = smoothed_correction(H.A, H.P, H.AP, omega);
+        D.fuse_post = l == 0 || (double)F.nnz() <= kFuseMaxFOverA * (double)nnzA;
+      }
+      if (D.fuse_pre) {
+        D.G = upload_sell<T>(G, mem, s, true, 64);
       } else if (l == 0) {
         D.R = upload_sell<T>(H.R, mem, s, true);
         D.r = mem.array<T>((size_t)D.n);
       } else {
-        D.Q = upload_sell<T>(residual_restriction(H.A, H.R), mem, s, true);
+        D.Q = upload_sell<T>(Q, mem, s, true);
       }
       if (D.fuse_post) {
-        D.F = upload_sell<T>(smoothed_correction(H.A, H.P, H.AP, omega), mem, s, true, D.A.lpr);
+        D.F = upload_sell<T>(F, mem, s, true, D.A.lpr);
         D.P = Sell<T>{};
       }
     }
