@@ -6,11 +6,13 @@ normal stress sigma = p - 2 mu dv/dy (the free-flow side of the normal-stress
 balance); the porous-medium solver S_pm takes sigma as the interface
 pressure, closed over the half porous cell by Darcy's law, and returns the
 interface normal velocity.  The coupling iterates the fixed-point problem
-S_pm(S_ff(v)) = v with a post-processing step (here Aitken's dynamic
-relaxation) and stops with the paper's two relative convergence measures on
-the interface pressure and velocity.  At the fixed point every interface row
-of the monolithic system holds, so the result equals the monolithic
-solution.
+S_pm(S_ff(v)) = v with a post-processing step -- Aitken's dynamic
+relaxation, or the paper's choice, the interface quasi-Newton method with an
+inverse Jacobian from a least-squares fit of the input/output history
+(IQN-ILS, Degroote, Bathe, Vierendeels 2009) -- and stops with the paper's
+two relative convergence measures on the interface pressure and velocity.
+At the fixed point every interface row of the monolithic system holds, so
+the result equals the monolithic solution.
 """
 from __future__ import annotations
 
@@ -86,8 +88,12 @@ def _subsolvers(p: Problem, a: Assembled):
 
 
 def solve_dn(p: Problem, a: Assembled, eps: float = 1e-10, maxit: int = 500,
-             omega0: float = 0.5) -> DNResult:
-    """Dirichlet-Neumann fixed point with Aitken relaxation."""
+             omega0: float = 0.5, accel: str = "aitken") -> DNResult:
+    """Dirichlet-Neumann fixed point with Aitken relaxation (accel="aitken")
+    or IQN-ILS post-processing (accel="iqn-ils").  Iteration k maps the
+    interface velocity v_k to sigma_k = S_ff(v_k) and vt_k = S_pm(sigma_k),
+    r_k = vt_k - v_k, and stops once both relative measures of Sec. 3 hold:
+    ||sigma_k - sigma_{k-1}|| < eps ||sigma_k|| and ||r_k|| < eps ||vt_k||."""
     S_ff, S_pm, to_mono = _subsolvers(p, a)
     nx = a.layout.nx
     v = np.zeros(nx)
@@ -96,6 +102,7 @@ def solve_dn(p: Problem, a: Assembled, eps: float = 1e-10, maxit: int = 500,
     omega = omega0
     hist = []
     x_ff = q = None
+    R_hist, Vt_hist = [], []          # IQN-ILS: residuals and outputs so far
     for k in range(1, maxit + 1):
         sigma, x_ff = S_ff(v)
         vt, q = S_pm(sigma)
@@ -106,16 +113,38 @@ def solve_dn(p: Problem, a: Assembled, eps: float = 1e-10, maxit: int = 500,
         hist.append((float(dp), float(np.linalg.norm(r))))
         if ok_p and ok_v:
             return DNResult(to_mono(x_ff, v, q), k, True, hist)
-        if r_old is not None:
-            dr = r - r_old
-            den = float(dr @ dr)
-            # Aitken's update; a step that left the residual unchanged gives
-            # no secant information, so the initial relaxation is restored
-            omega = -omega * float(r_old @ dr) / den if den > 0 else omega0
-        v = v + omega * r
+        if accel == "aitken":
+            if r_old is not None:
+                dr = r - r_old
+                den = float(dr @ dr)
+                # Aitken's update; a step that left the residual unchanged gives
+                # no secant information, so the initial relaxation is restored
+                omega = -omega * float(r_old @ dr) / den if den > 0 else omega0
+            v = v + omega * r
+        elif accel == "iqn-ils":
+            v = _iqn_ils_step(v, vt, r, R_hist, Vt_hist, omega0)
+        else:
+            raise ValueError(accel)
         r_old = r
         sigma_old = sigma
     return DNResult(to_mono(x_ff, v, q), maxit, False, hist)
+
+
+def _iqn_ils_step(v, vt, r, R_hist, Vt_hist, omega0):
+    """One IQN-ILS update.  With the history of residuals r_i and outputs
+    vt_i, the columns dR_i = r_{i+1} - r_i and dVt_i = vt_{i+1} - vt_i are
+    secant pairs of the inverse Jacobian; the coefficients c minimise
+    ||dR c + r_k|| (the residual change that would cancel r_k, in the span of
+    the observed changes) and the next input is vt_k + dVt c.  The first
+    iteration, without history, relaxes with omega0."""
+    R_hist.append(r.copy())
+    Vt_hist.append(vt.copy())
+    if len(R_hist) == 1:
+        return v + omega0 * r
+    dR = np.column_stack([R_hist[i + 1] - R_hist[i] for i in range(len(R_hist) - 1)])
+    dV = np.column_stack([Vt_hist[i + 1] - Vt_hist[i] for i in range(len(Vt_hist) - 1)])
+    c = np.linalg.lstsq(dR, -r, rcond=1e-12)[0]
+    return vt + dV @ c
 
 
 def solve_interface_gmres(p: Problem, a: Assembled, tol: float = 1e-14) -> np.ndarray:

@@ -212,3 +212,63 @@ def test_dn_detects_a_planted_error():
     xs = solve(A.tocsr(), a.b)
     r = solve_dn(p, a)
     assert np.linalg.norm(r.x - xs) > 1e-6 * np.linalg.norm(xs)
+
+
+@pytest.mark.parametrize("nx,ny", [(32, 16), (64, 32)])
+def test_iqn_ils_reaches_the_monolithic_solution(nx, ny):
+    """The paper's post-processing (Sec. 3): IQN-ILS converges to the same
+    fixed point as Aitken, the monolithic solution, in fewer iterations."""
+    p = channel_problem(nx, ny, seed=3)
+    a = assemble(p)
+    xs = refined_solve(a.A, a.b)
+    ri = solve_dn(p, a, accel="iqn-ils")
+    ra = solve_dn(p, a, accel="aitken")
+    assert ri.converged and ra.converged
+    assert np.linalg.norm(ri.x - xs) <= 1e-10 * np.linalg.norm(xs)
+    assert ri.iters <= ra.iters
+
+
+def _interface_map(p, a):
+    from oracle.dn import _subsolvers
+    S_ff, S_pm, _ = _subsolvers(p, a)
+    return lambda v: S_pm(S_ff(v)[0])[0]
+
+
+@pytest.mark.parametrize("sign", [1.0, -1.0])
+def test_iqn_ils_terminates_on_the_affine_interface_map(sign):
+    """The interface map is affine in n = nx unknowns: once n independent
+    secant pairs are known the least-squares inverse Jacobian is exact, so
+    IQN-ILS reaches the root within n + 2 iterations.  A planted sign error
+    in the update (sign = -1) does not."""
+    from oracle.dn import _iqn_ils_step
+    p = channel_problem(16, 8, seed=3)
+    a = assemble(p)
+    H = _interface_map(p, a)
+    n = a.layout.nx
+    v = np.zeros(n)
+    Rh, Vh = [], []
+    r0 = None
+    done_at = None
+    for k in range(n + 3):
+        vt = H(v)
+        r = vt - v
+        r0 = np.linalg.norm(r) if r0 is None else r0
+        if np.linalg.norm(r) <= 1e-12 * r0:
+            done_at = k
+            break
+        if sign > 0:
+            v = _iqn_ils_step(v, vt, r, Rh, Vh, 0.5)
+        else:
+            Rh.append(r.copy())
+            Vh.append(vt.copy())
+            if len(Rh) == 1:
+                v = v + 0.5 * r
+            else:
+                dR = np.column_stack([Rh[i + 1] - Rh[i] for i in range(len(Rh) - 1)])
+                dV = np.column_stack([Vh[i + 1] - Vh[i] for i in range(len(Vh) - 1)])
+                c = np.linalg.lstsq(dR, -r, rcond=1e-12)[0]
+                v = vt - dV @ c
+    if sign > 0:
+        assert done_at is not None and done_at <= n + 2
+    else:
+        assert done_at is None
