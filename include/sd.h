@@ -288,6 +288,50 @@ int sd_solver_profile(sd_solver* s, int kernel_class);
 int sd_solver_profile_read(const sd_solver* s, int64_t* launches, double* seconds,
                            double* bytes);
 
+/* ------------------------------------------------- partitioned coupling */
+/* The partitioned Dirichlet-Neumann coupling of Sec. 3: the free flow takes
+ * the interface normal velocity v as Dirichlet data and returns the normal
+ * stress sigma = p - 2 mu dv/dy on Gamma; the porous medium takes sigma as
+ * its interface pressure, closed over the half top cell by Darcy's law
+ * (transmissibility Ay K_top/(mu dy_pm/2)), and returns the interface
+ * velocity.  The fixed point S_pm(S_ff(v)) = v is the monolithic solution.
+ * Post-processing: Aitken relaxation, or IQN-ILS (the paper's choice: a
+ * quasi-Newton step with the inverse Jacobian fitted in the least-squares
+ * sense to the history of inputs and outputs, Degroote et al. 2009).  The
+ * iteration stops when ||sigma_k - sigma_{k-1}|| < eps ||sigma_k|| and
+ * ||vt_k - v_k|| < eps ||vt_k|| (Sec. 3).  Both subdomain systems are solved
+ * on the GPU by FGMRES with the block preconditioner (the missing block left
+ * out), to the tolerance in the sub-solver options, each warm-started from
+ * its previous state; SD_SCHUR_CC falls back to SD_SCHUR_MASS.  The
+ * interface vectors (nx or nx nz values) are kept on the host. */
+typedef struct sd_dn sd_dn;
+enum { SD_DN_AITKEN = 0, SD_DN_IQN_ILS = 1 };
+typedef struct {
+  int accel;        /* SD_DN_AITKEN | SD_DN_IQN_ILS (default)                  */
+  double eps;       /* relative interface tolerance, default 1e-8              */
+  int maxit;        /* coupling iterations, default 200                         */
+  double omega0;    /* first relaxation factor, default 0.5                     */
+} sd_dn_opts;
+typedef struct {
+  int iters, converged;       /* coupling iterations; 1 if the rule was met   */
+  int ff_iters, pm_iters;     /* FGMRES iterations summed over the sub-solves  */
+  double t_solve;             /* seconds                                       */
+} sd_dn_stats;
+void sd_dn_opts_default(sd_dn_opts* o);
+/* Split an assembled device problem and set up both subdomain solvers
+ * (sub: their options, NULL = defaults).  The problem must outlive the
+ * handle. */
+int sd_dn_setup(sd_problem* pb, const sd_solver_opts* sub, sd_dn** out);
+/* Solve A x = b by the coupling iteration.  d_b: device FP64 [N] or NULL (the
+ * assembled b); its interface rows must be zero, as assembled and as
+ * sd_step_rhs leaves them (SD_E_INVALID otherwise).  d_x: device FP64 [N],
+ * written in the monolithic ordering (the interface velocity is the last
+ * input v).  Returns SD_E_NOCONV after maxit iterations (x and stats still
+ * written), or a sub-solver's failure status.  Returns after the solve. */
+int sd_dn_solve(sd_dn* h, const sd_dn_opts* o, const double* d_b, double* d_x,
+                sd_dn_stats* stats, void* hip_stream);
+void sd_dn_destroy(sd_dn* h);
+
 /* ---------------------------------------------------------------- serving */
 typedef struct {
   size_t hbm_budget;   /* bytes the server may hold (0 = 80% of free HBM)     */

@@ -5,17 +5,9 @@
 #include <memory>
 #include <string>
 
+#include "handles.h"
 #include "sd.h"
 #include "solver.h"
-
-struct sd_problem {
-  sd::HostProblem hp;
-  bool device = false;
-  int device_id = 0;
-  sd_allocator alloc{};
-  bool has_alloc = false;
-  hipStream_t stream = nullptr;
-};
 
 struct sd_solver {
   std::unique_ptr<sd::Solver> s;
@@ -33,17 +25,7 @@ int fail(int code, const std::string& msg) {
 
 template <typename F>
 int guarded(F&& f) {
-  try {
-    return f();
-  } catch (const sd::Error& e) {
-    return fail(e.code, e.what());
-  } catch (const std::bad_alloc&) {
-    return fail(SD_E_NOMEM, "host allocation failed");
-  } catch (const std::exception& e) {
-    return fail(SD_E_INVALID, e.what());
-  } catch (...) {
-    return fail(SD_E_INVALID, "unknown error");
-  }
+  return sd::guarded_call(std::forward<F>(f));
 }
 
 int require_device() {
@@ -58,6 +40,8 @@ int require_device() {
 }
 
 }  // namespace
+
+void sd::set_last_error(const std::string& msg) { g_err = msg; }
 
 extern "C" {
 

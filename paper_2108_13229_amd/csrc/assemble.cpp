@@ -120,6 +120,7 @@ void assemble_host(const sd_grid* g, const sd_physics* ph, const sd_bcs* bcs,
   P.L = L;
   P.pm_singular = bcs->pm_left == SD_BC_NOFLOW && bcs->pm_right == SD_BC_NOFLOW &&
                   bcs->pm_bottom == SD_BC_NOFLOW;
+  P.K.assign(K, K + nK);
 
   auto data = [](const double* a, int64_t k) { return a ? a[k] : 0.0; };
   const double* uL = bcs->ff_left_n;

@@ -109,6 +109,7 @@ void assemble_host_3d(const sd_grid* g, const sd_physics* ph, const sd_bcs* bcs,
   P.pm_singular = bcs->pm_left == SD_BC_NOFLOW && bcs->pm_right == SD_BC_NOFLOW &&
                   bcs->pm_bottom == SD_BC_NOFLOW && bcs->pm_back == SD_BC_NOFLOW &&
                   bcs->pm_front == SD_BC_NOFLOW;
+  P.K.assign(K, K + nK);
 
   auto d = [](const double* a, int64_t k) { return a ? a[k] : 0.0; };
   const double *uL = bcs->ff_left_n, *vL = bcs->ff_left_t, *wL = bcs->ff_left_tz;

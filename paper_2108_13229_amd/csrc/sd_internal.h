@@ -61,6 +61,7 @@ struct HostProblem {
   std::vector<double> b;
   bool pm_singular = false;
   double mass = 0.0;           // |CV|/dt of the backward-Euler rows (0: stationary)
+  std::vector<double> K;       // porous permeabilities, [ny_pm][nz][nx]
 };
 
 void assemble_host(const sd_grid* g, const sd_physics* ph, const sd_bcs* bcs,

@@ -243,8 +243,12 @@ void Solver::setup_host(HostProblem* p, const sd_solver_opts* o) {
   for (int64_t i = L.off_v; i < L.off_w; ++i) compV[i] = 1;
   for (int64_t i = L.off_w; i < L.off_p; ++i) compV[i] = 2;   // w (3-D)
   std::vector<int32_t> compD((size_t)(L.N - L.off_q), 0);
-  amg_setup_host(Vb, compV, false, opts.amg, hh[0]);
-  amg_setup_host(Dt, compD, false, opts.amg, hh[1]);
+  // a subdomain system (partitioned coupling) may have no velocity or no
+  // porous block: its hierarchy then stays empty and its V-cycle is skipped
+  hh[0] = HostHierarchy();
+  hh[1] = HostHierarchy();
+  if (L.off_p > 0) amg_setup_host(Vb, compV, false, opts.amg, hh[0]);
+  if (L.N > L.off_q) amg_setup_host(Dt, compD, false, opts.amg, hh[1]);
   hh[2] = HostHierarchy();
   if (so.schur == SD_SCHUR_CC) {
     // L_p = B^T D^-1 B = (-C) diag(1/D) B, D = |CV|/dt on the velocity rows
@@ -315,7 +319,7 @@ void Solver::upload(const sd_allocator* alloc, hipStream_t s) {
   prof_ev.resize((size_t)2 * kMaxBasis);
   for (auto& e : prof_ev) SD_HIP(hipEventCreate(&e));
   nnz_A = pb->A.nnz();
-  nnz_V0 = hh[0].levels[0].A.nnz();
+  nnz_V0 = hh[0].levels.empty() ? 0 : hh[0].levels[0].A.nnz();
   SD_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
   prec = opts.o.precision == SD_PRECISION_FP64 ? make_prec_fp64(*this, s) : make_prec_fp32(*this, s);
   SD_HIP(hipStreamSynchronize(s));
@@ -430,8 +434,9 @@ class PrecImpl : public PrecBase {
     nu_pre = S.opts.amg.nu_pre;
     nu_post = S.opts.amg.nu_post;
     cc = !S.hh[2].levels.empty();
-    for (int b = 0; b < (cc ? 3 : 2); ++b)
-      upload_hierarchy<T>(S.hh[b], H[b], S.opts.amg.omega, nu_pre, nu_post, mem, s);
+    for (int b = 0; b < 3; ++b)
+      if (!S.hh[b].levels.empty())
+        upload_hierarchy<T>(S.hh[b], H[b], S.opts.amg.omega, nu_pre, nu_post, mem, s);
     if (cc) {
       tp = mem.array<T>((size_t)(S.off[3] - S.off[2]));
       yl = mem.array<T>((size_t)(S.off[3] - S.off[2]));
@@ -520,14 +525,14 @@ class PrecImpl : public PrecBase {
              hipStream_t s) {
     const int64_t* o = S.off;
     const int n_p = (int)(o[3] - o[2]);
-    vcycle<double>(0, 0, r, bs, z, gate, s);
+    if (!H[0].lev.empty()) vcycle<double>(0, 0, r, bs, z, gate, s);
     launch_block_sweep<T>(Cf, n_p, r + o[2], bs, z, S.xscale, z + o[2], tq, cc ? tp : nullptr,
                           gate, s);
     if (cc) {
       vcycle<T>(2, 0, tp, nullptr, yl, gate, s);
       launch_add<T>(yl, z + o[2], n_p, gate, s);
     }
-    vcycle<T>(1, 0, tq, nullptr, z + o[3], gate, s);
+    if (!H[1].lev.empty()) vcycle<T>(1, 0, tq, nullptr, z + o[3], gate, s);
   }
 
   void apply_precond(Solver& S, const double* r, double* z, hipStream_t s) override {
@@ -540,6 +545,7 @@ class PrecImpl : public PrecBase {
   }
 
   void apply_vcycle(Solver& S, int blk, const double* b, double* x, hipStream_t s) override {
+    if (H[blk].lev.empty()) throw Error(SD_E_INVALID, "block has no hierarchy");
     const int n = H[blk].lev[0].n;
     if constexpr (std::is_same<T, double>::value) {
       vcycle<double>(blk, 0, b, nullptr, x, nullptr, s);

@@ -80,6 +80,22 @@ class Stats(C.Structure):
                     t_solve=self.t_solve)
 
 
+class DNOpts(C.Structure):
+    _fields_ = [("accel", C.c_int), ("eps", C.c_double), ("maxit", C.c_int),
+                ("omega0", C.c_double)]
+
+
+class DNStats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("ff_iters", C.c_int),
+                ("pm_iters", C.c_int), ("t_solve", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+DN_ACCEL = {"aitken": 0, "iqn-ils": 1}
+
+
 class ServerOpts(C.Structure):
     _fields_ = [("hbm_budget", C.c_size_t), ("max_slots", C.c_int), ("device", C.c_int)]
 
@@ -121,6 +137,10 @@ SIGNATURES = {
     "sd_step_rhs": (C.c_int, [_P, _P, _P, _P, _P]),
     "sd_advance": (C.c_int, [_P, _P, _P, C.c_int, C.POINTER(Stats), C.POINTER(C.c_int), _P]),
     "sd_apply_matrix": (C.c_int, [_P, _P, _P, _P]),
+    "sd_dn_opts_default": (None, [C.POINTER(DNOpts)]),
+    "sd_dn_setup": (C.c_int, [_P, C.POINTER(SolverOpts), C.POINTER(_P)]),
+    "sd_dn_solve": (C.c_int, [_P, C.POINTER(DNOpts), _P, _P, C.POINTER(DNStats), _P]),
+    "sd_dn_destroy": (None, [_P]),
     "sd_apply_preconditioner": (C.c_int, [_P, _P, _P, _P]),
     "sd_apply_vcycle": (C.c_int, [_P, C.c_int, _P, _P, _P]),
     "sd_solver_profile": (C.c_int, [_P, C.c_int]),
@@ -390,6 +410,44 @@ class Solver:
     def close(self):
         if self.h:
             lib().sd_solver_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Partitioned:
+    """Dirichlet-Neumann coupling of the two subdomain solvers (device)."""
+
+    def __init__(self, problem: Problem, **sub_opts):
+        self.problem = problem
+        self.opts = solver_opts(**sub_opts)
+        h = C.c_void_p()
+        _check(lib().sd_dn_setup(problem.h, C.byref(self.opts), C.byref(h)))
+        self.h = h
+
+    def solve(self, accel: str = "iqn-ils", eps: float = 1e-8, maxit: int = 200,
+              omega0: float = 0.5, b=None, x=None):
+        import torch
+        N = self.problem.N
+        x = torch.zeros(N, dtype=torch.float64, device="cuda") if x is None else x
+        _require(x, N)
+        if b is not None:
+            _require(b, N)
+        o = DNOpts(DN_ACCEL[accel], float(eps), int(maxit), float(omega0))
+        st = DNStats()
+        rc = lib().sd_dn_solve(self.h, C.byref(o), C.c_void_p(b.data_ptr()) if b is not None
+                               else None, C.c_void_p(x.data_ptr()), C.byref(st), _stream())
+        if rc not in (SD_OK, SD_E_NOCONV):
+            _check(rc)
+        return x, st.as_dict(), rc
+
+    def close(self):
+        if self.h:
+            lib().sd_dn_destroy(self.h)
             self.h = None
 
     def __del__(self):
