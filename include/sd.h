@@ -316,6 +316,7 @@ typedef struct {
   int iters, converged;       /* coupling iterations; 1 if the rule was met   */
   int ff_iters, pm_iters;     /* FGMRES iterations summed over the sub-solves  */
   double t_solve;             /* seconds                                       */
+  double dp_rel, dv_rel;      /* last ||dsigma||/||sigma|| and ||r||/||vt||    */
 } sd_dn_stats;
 void sd_dn_opts_default(sd_dn_opts* o);
 /* Split an assembled device problem and set up both subdomain solvers

@@ -28,59 +28,59 @@ namespace sd {
 
 namespace {
 
-// Least squares min ||M c + r|| by Householder QR of the m x k matrix M
-// (column-major); a column whose remaining norm falls below 1e-12 ||M||_F
-// (dependent on the earlier ones) is dropped and gets coefficient 0.
-std::vector<double> lsq(std::vector<double> M, int64_t m, int k, std::vector<double> r) {
-  double fro = 0.0;
-  for (double x : M) fro += x * x;
-  fro = std::sqrt(fro);
-  for (auto& x : r) x = -x;
-  std::vector<std::vector<double>> hv;   // Householder vectors of kept columns
-  std::vector<int> cols;
-  for (int j = 0; j < k; ++j) {
-    double* a = &M[(size_t)j * m];
-    for (size_t t = 0; t < hv.size(); ++t) {   // apply earlier reflections
-      const std::vector<double>& v = hv[t];
-      const int64_t o = (int64_t)t;
+// Incremental QR of the IQN-ILS residual-difference matrix: columns are
+// appended one per coupling iteration (earlier ones never change), each
+// orthogonalised against the kept ones by classical Gram-Schmidt applied
+// twice; a column left with less than 1e-12 of its norm depends on the
+// earlier ones and is dropped together with its output difference.
+struct IncrementalQR {
+  int64_t m = 0;
+  std::vector<std::vector<double>> q;    // orthonormal columns
+  std::vector<std::vector<double>> rcol; // column t of R (length t + 1)
+  std::vector<std::vector<double>> dv;   // output differences of kept columns
+  void clear() { q.clear(); rcol.clear(); dv.clear(); }
+  void append(const std::vector<double>& c0, const std::vector<double>& dvt) {
+    std::vector<double> c = c0;
+    const size_t k = q.size();
+    std::vector<double> h(k + 1, 0.0);
+    double n0 = 0.0;
+    for (double x : c) n0 += x * x;
+    n0 = std::sqrt(n0);
+    if (!(n0 > 0.0)) return;
+    for (int pass = 0; pass < 2; ++pass)
+      for (size_t t = 0; t < k; ++t) {
+        double d = 0.0;
+        for (int64_t i = 0; i < m; ++i) d += q[t][(size_t)i] * c[(size_t)i];
+        for (int64_t i = 0; i < m; ++i) c[(size_t)i] -= d * q[t][(size_t)i];
+        h[t] += d;
+      }
+    double rho = 0.0;
+    for (double x : c) rho += x * x;
+    rho = std::sqrt(rho);
+    if (rho <= 1e-12 * n0) return;
+    for (double& x : c) x /= rho;
+    h[k] = rho;
+    q.push_back(std::move(c));
+    rcol.push_back(std::move(h));
+    dv.push_back(dvt);
+  }
+  // coefficients c of min ||dR c + r||: R c = -Q^T r
+  std::vector<double> solve(const std::vector<double>& r) const {
+    const size_t k = q.size();
+    std::vector<double> y(k, 0.0), c(k, 0.0);
+    for (size_t t = 0; t < k; ++t) {
       double d = 0.0;
-      for (int64_t i = o; i < m; ++i) d += v[(size_t)(i - o)] * a[i];
-      for (int64_t i = o; i < m; ++i) a[i] -= 2.0 * d * v[(size_t)(i - o)];
+      for (int64_t i = 0; i < m; ++i) d += q[t][(size_t)i] * r[(size_t)i];
+      y[t] = -d;
     }
-    const int64_t o = (int64_t)hv.size();
-    double nrm = 0.0;
-    for (int64_t i = o; i < m; ++i) nrm += a[i] * a[i];
-    nrm = std::sqrt(nrm);
-    if (nrm <= 1e-12 * fro || o >= m) continue;          // dependent column
-    std::vector<double> v((size_t)(m - o));
-    const double alpha = a[o] > 0 ? -nrm : nrm;
-    for (int64_t i = o; i < m; ++i) v[(size_t)(i - o)] = a[i];
-    v[0] -= alpha;
-    double vn = 0.0;
-    for (double x : v) vn += x * x;
-    vn = std::sqrt(vn);
-    for (double& x : v) x /= vn;
-    for (int64_t i = o; i < m; ++i) a[i] = i == o ? alpha : 0.0;
-    hv.push_back(std::move(v));
-    cols.push_back(j);
+    for (size_t t = k; t-- > 0;) {
+      double acc = y[t];
+      for (size_t u = t + 1; u < k; ++u) acc -= rcol[u][t] * c[u];
+      c[t] = acc / rcol[t][t];
+    }
+    return c;
   }
-  const int kk = (int)hv.size();
-  for (int t = 0; t < kk; ++t) {                      // Q^T (-r)
-    const std::vector<double>& v = hv[(size_t)t];
-    double d = 0.0;
-    for (int64_t i = t; i < m; ++i) d += v[(size_t)(i - t)] * r[(size_t)i];
-    for (int64_t i = t; i < m; ++i) r[(size_t)i] -= 2.0 * d * v[(size_t)(i - t)];
-  }
-  std::vector<double> y((size_t)kk, 0.0);
-  for (int t = kk - 1; t >= 0; --t) {                 // R y = (Q^T (-r))_{0..kk-1}
-    double acc = r[(size_t)t];
-    for (int u = t + 1; u < kk; ++u) acc -= M[(size_t)cols[(size_t)u] * m + t] * y[(size_t)u];
-    y[(size_t)t] = acc / M[(size_t)cols[(size_t)t] * m + t];
-  }
-  std::vector<double> c((size_t)k, 0.0);
-  for (int t = 0; t < kk; ++t) c[(size_t)cols[(size_t)t]] = y[(size_t)t];
-  return c;
-}
+};
 
 double norm2(const std::vector<double>& a) {
   double s = 0.0;
@@ -243,7 +243,9 @@ int DNSolver::solve(const sd_dn_opts& d, const double* d_b, double* d_x, sd_dn_s
   SD_HIP(hipStreamSynchronize(s));
   std::vector<double> v((size_t)nG, 0.0), sigma((size_t)nG), vt((size_t)nG), r((size_t)nG);
   std::vector<double> sigma_old, r_old, top((size_t)nG), p0((size_t)nG), v1((size_t)nG);
-  std::vector<std::vector<double>> Rh, Vh;
+  std::vector<double> r_prev, vt_prev;
+  IncrementalQR qr;
+  qr.m = nG;
   double omega = d.omega0;
   int status = SD_E_NOCONV;
   for (int k = 1; k <= d.maxit; ++k) {
@@ -288,6 +290,12 @@ int DNSolver::solve(const sd_dn_opts& d, const double* d_b, double* d_x, sd_dn_s
       ok_p = norm2(ds) < d.eps * norm2(sigma);
     }
     const bool ok_v = norm2(r) < d.eps * norm2(vt);
+    st.dv_rel = norm2(r) / norm2(vt);
+    if (!sigma_old.empty()) {
+      double dd = 0.0;
+      for (int64_t g = 0; g < nG; ++g) dd += (sigma[g] - sigma_old[g]) * (sigma[g] - sigma_old[g]);
+      st.dp_rel = std::sqrt(dd) / norm2(sigma);
+    }
     if (ok_p && ok_v) {
       st.converged = 1;
       status = SD_OK;
@@ -305,25 +313,29 @@ int DNSolver::solve(const sd_dn_opts& d, const double* d_b, double* d_x, sd_dn_s
       }
       for (int64_t g = 0; g < nG; ++g) v[g] = v[g] + omega * r[g];
     } else {
-      Rh.push_back(r);
-      Vh.push_back(vt);
-      if (Rh.size() == 1) {
+      // IQN-ILS: secant pairs (r_k - r_{k-1}, vt_k - vt_{k-1}); the next input
+      // is vt_k + dVt c with c = argmin ||dR c + r_k||; the first iteration
+      // relaxes with omega0
+      if (!r_prev.empty()) {
+        std::vector<double> dr((size_t)nG), dvt((size_t)nG);
+        for (int64_t g = 0; g < nG; ++g) {
+          dr[g] = r[g] - r_prev[g];
+          dvt[g] = vt[g] - vt_prev[g];
+        }
+        qr.append(dr, dvt);
+      }
+      if (qr.q.empty()) {
         for (int64_t g = 0; g < nG; ++g) v[g] = v[g] + d.omega0 * r[g];
       } else {
-        const int kc = (int)Rh.size() - 1;
-        std::vector<double> dR((size_t)nG * kc), dV((size_t)nG * kc);
-        for (int c = 0; c < kc; ++c)
-          for (int64_t g = 0; g < nG; ++g) {
-            dR[(size_t)c * nG + g] = Rh[c + 1][g] - Rh[c][g];
-            dV[(size_t)c * nG + g] = Vh[c + 1][g] - Vh[c][g];
-          }
-        const std::vector<double> cf = lsq(dR, nG, kc, r);
+        const std::vector<double> cf = qr.solve(r);
         for (int64_t g = 0; g < nG; ++g) {
           double acc = vt[g];
-          for (int c = 0; c < kc; ++c) acc += dV[(size_t)c * nG + g] * cf[(size_t)c];
+          for (size_t c = 0; c < cf.size(); ++c) acc += qr.dv[c][(size_t)g] * cf[c];
           v[g] = acc;
         }
       }
+      r_prev = r;
+      vt_prev = vt;
     }
     r_old = r;
     sigma_old = sigma;

@@ -87,7 +87,8 @@ class DNOpts(C.Structure):
 
 class DNStats(C.Structure):
     _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("ff_iters", C.c_int),
-                ("pm_iters", C.c_int), ("t_solve", C.c_double)]
+                ("pm_iters", C.c_int), ("t_solve", C.c_double), ("dp_rel", C.c_double),
+                ("dv_rel", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
