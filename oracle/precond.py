@@ -18,6 +18,15 @@ pressure mass matrix, X = mu M_p^-1 with M_p = diag(dx dy) (the Schur
 complement B^T V^-1 B is approximated by M_p / mu; with C = -B^T its sign is
 positive).
 
+Two-domain variants (Sec. 4, Table 2): with the free-flow block A' =
+[[V, B], [C, 0]] preconditioned by one inexact Uzawa step (y_v = P_V r_v,
+y_p = omega (r_p - C y_v), a Richardson step on the Schur complement
+-C V^-1 B with omega = 1/lambda_max, lambda_max estimated by power
+iteration on -C P_V B), P^td_BGS(P_A', P_D') coincides with the pv
+block-Gauss-Seidel form with X = omega I, and P^td_BJ(P_A', P_D') =
+diag(P_A', P_D') keeps the v -> p coupling inside A' but drops the porous
+coupling C1' (y_pm = P_D' r_pm).
+
 For the system of one backward-Euler step (mass |CV|/dt on the velocity
 diagonal) M_p / mu only describes the Schur complement of the viscous part:
 once sqrt(nu dt) is small against the domain, the mass term governs the
@@ -42,6 +51,8 @@ from .assemble import Assembled
 SCHUR_IDENTITY = "identity"
 SCHUR_MASS = "mass"
 SCHUR_CC = "cc"
+SCHUR_UZAWA = "uzawa"
+UZAWA_POWER_ITERS = 30
 
 
 @dataclasses.dataclass
@@ -80,7 +91,10 @@ class BlockPreconditioner:
         if self.variant == "BJ":
             yp = self.middle(rp)
             yq = amg_mod.vcycle(self.hD, rq, dt, mats=self._mD)
-        elif self.variant == "BGS":
+        elif self.variant == "TD_BJ":
+            yp = self.middle(rp - self._C @ yv)
+            yq = amg_mod.vcycle(self.hD, rq, dt, mats=self._mD)
+        elif self.variant in ("BGS", "TD_BGS"):
             yp = self.middle(rp - self._C @ yv)
             yq = amg_mod.vcycle(self.hD, rq - self._C1 @ yv, dt, mats=self._mD)
         else:
@@ -139,6 +153,23 @@ def pressure_operator(a: Assembled) -> "sp.csr_matrix":
     return L
 
 
+def uzawa_relaxation(blk, hV, iters: int = UZAWA_POWER_ITERS) -> float:
+    """omega = 1/lambda_max of the inexact Schur complement -C P_V B (P_V one
+    V-cycle on V), lambda_max from `iters` power iterations started at the
+    normalised ones vector: x <- y/||y|| with y = -C P_V B x, lambda = ||y||
+    of the last step (Sec. 5: one Richardson iteration, its relaxation
+    estimated by power iteration)."""
+    B, C = blk["B"], blk["C"]
+    n = B.shape[1]
+    x = np.ones(n) / np.sqrt(n)
+    lam = 1.0
+    for _ in range(iters):
+        y = -(C @ amg_mod.vcycle(hV, B @ x))
+        lam = float(np.linalg.norm(y))
+        x = y / lam
+    return 1.0 / lam
+
+
 def build(p, a: Assembled, variant: str = "BGS", schur: str = SCHUR_MASS,
           opts: amg_mod.AMGOptions | None = None, dtype=np.float64) -> BlockPreconditioner:
     opts = opts or amg_mod.AMGOptions()
@@ -148,6 +179,9 @@ def build(p, a: Assembled, variant: str = "BGS", schur: str = SCHUR_MASS,
     hD = amg_mod.setup(Dt, np.zeros(Dt.shape[0], dtype=np.int32), False, opts)
     vol = ((p.Lx / p.nx) * (p.H_ff / p.ny)) * p.dz     # dz = 1 in 2-D
     xscale = p.mu / vol if schur in (SCHUR_MASS, SCHUR_CC) else 1.0
+    if variant in ("TD_BJ", "TD_BGS"):
+        schur = SCHUR_UZAWA
+        xscale = uzawa_relaxation(blk, hV)
     hL = None
     if schur == SCHUR_CC:
         Lp = pressure_operator(a)

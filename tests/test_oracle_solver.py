@@ -362,3 +362,47 @@ def test_lognormal_field_statistics():
     c = np.mean(zc[:, :-lag] * zc[:, lag:])
     assert abs(c - np.exp(-lag ** 2 / (4 * 64.0))) < 0.1
     assert np.array_equal(K, lognormal_K(256, 128, 1e-4, 1.0, 8.0, seed=1))
+
+
+# ---- two-domain variants with an inexact Uzawa step (Sec. 4, Table 2) ----
+
+def test_uzawa_power_iteration_estimates_lambda_max():
+    from oracle import amg as amg_mod
+    p = channel_problem(32, 16, seed=3)
+    a = assemble(p)
+    M = precond.build(p, a, "TD_BGS")
+    blk = a.blocks()
+    n = blk["B"].shape[1]
+    op = np.column_stack([-(blk["C"] @ amg_mod.vcycle(M.hV, blk["B"] @ e)) for e in np.eye(n)])
+    lam = np.max(np.abs(np.linalg.eigvals(op)))
+    lam_est = 1.0 / M.xscale
+    assert 0.9 * lam <= lam_est <= (1 + 1e-9) * lam, (lam_est, lam)
+
+
+def test_two_domain_block_jacobi_drops_only_the_porous_coupling():
+    from oracle import amg as amg_mod
+    p = channel_problem(24, 12, seed=2)
+    a = assemble(p)
+    Mj = precond.build(p, a, "TD_BJ")
+    Mg = precond.build(p, a, "TD_BGS")
+    assert Mj.xscale == Mg.xscale
+    r = np.random.default_rng(1).standard_normal(a.N)
+    o = a.layout.block_off
+    zj, zg = Mj(r), Mg(r)
+    assert np.array_equal(zj[:o[3]], zg[:o[3]])          # same P_A' (Uzawa step)
+    assert np.array_equal(zj[o[3]:], amg_mod.vcycle(Mj.hD, r[o[3]:]))
+    assert not np.allclose(zg[o[3]:], zj[o[3]:])
+
+
+@pytest.mark.parametrize("variant", ["TD_BJ", "TD_BGS"])
+def test_two_domain_variants_converge(variant):
+    p = channel_problem(64, 32, seed=3)
+    a = assemble(p)
+    xs = refined_solve(a.A, a.b)
+    M = precond.build(p, a, variant)
+    r = krylov.fgmres(a.A, a.b, M, tol=1e-10, m=60)
+    assert r.converged
+    assert np.linalg.norm(r.x - xs) <= 1e-7 * np.linalg.norm(xs)
+    ident = krylov.fgmres(a.A, a.b, precond.build(p, a, "BGS", schur="identity"), tol=1e-10, m=60)
+    if variant == "TD_BGS":
+        assert r.iters < ident.iters
