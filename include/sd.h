@@ -155,7 +155,16 @@ int sd_problem_csr(const sd_problem* pb, const int64_t** rowptr,
                    const int32_t** col, const double** val, const double** b);
 
 enum { SD_KRYLOV_FGMRES = 0, SD_KRYLOV_BICGSTAB = 1 };
-enum { SD_PREC_BJ = 0, SD_PREC_BGS = 1 };
+/* Block preconditioners (Sec. 4): the pressure-velocity block-Jacobi and
+ * block-Gauss-Seidel forms P^pv_BJ / P^pv_BGS, and the two-domain forms
+ * P^td_BJ / P^td_BGS whose free-flow block A' = [[V, B], [C, 0]] is
+ * preconditioned by one inexact Uzawa step: y_v = P_V r_v,
+ * y_p = omega (r_p - C y_v), a Richardson step on the Schur complement with
+ * omega = 1/lambda_max(-C P_V B) from 30 power iterations at set-up (the
+ * schur option is ignored for them).  TD_BGS then equals the pv
+ * block-Gauss-Seidel form with middle block omega I; TD_BJ keeps the v -> p
+ * coupling inside A' and drops the porous coupling (y_pm = P_D' r_pm). */
+enum { SD_PREC_BJ = 0, SD_PREC_BGS = 1, SD_PREC_TD_BJ = 2, SD_PREC_TD_BGS = 3 };
 /* Middle (free-flow pressure) block of the preconditioner: the paper's
  * identity; mu M_p^-1 (the viscous Schur complement, M_p = diag(dx dy)); or,
  * for backward-Euler systems only (phys.dt > 0), the Cahouet-Chabard form
@@ -179,7 +188,7 @@ typedef struct {
   int restart;       /* FGMRES restart length m (1..63), default 30            */
   int maxit;         /* total iteration cap, default 1000                      */
   double tol;        /* relative true FP64 residual ||b-Ax||/||b||             */
-  int precond;       /* SD_PREC_BJ | SD_PREC_BGS                               */
+  int precond;       /* SD_PREC_BJ | SD_PREC_BGS | SD_PREC_TD_BJ | SD_PREC_TD_BGS */
   int schur;         /* middle block: identity or mu * M_p^-1                  */
   int precision;     /* SD_PRECISION_FP64 | _MIXED | _MIXED32                  */
   int amg;           /* SD_AMG_SMOOTHED (default) | SD_AMG_PLAIN               */
@@ -282,6 +291,9 @@ int sd_apply_vcycle(sd_solver* s, int block, const double* d_b, double* d_x,
 enum { SD_PROF_OFF = 0, SD_PROF_ARNOLDI_SPMV = 1, SD_PROF_ARNOLDI_UPDATE = 2,
        SD_PROF_JACOBI_V0 = 3 };
 int sd_solver_profile(sd_solver* s, int kernel_class);
+/* The scale X of the middle block's mu M_p^-1, identity or Uzawa term
+ * (X = mu/(dx dy dz), 1, or omega). */
+int sd_solver_middle_scale(const sd_solver* s, double* x);
 /* Launches timed, their summed event durations (seconds) and the summed
  * algorithmic bytes of those launches (each matrix entry, vector entry and
  * index read or written once; padding excluded). */

@@ -316,6 +316,12 @@ int sd_solver_profile(sd_solver* s, int kernel_class) {
   return SD_OK;
 }
 
+int sd_solver_middle_scale(const sd_solver* s, double* x) {
+  if (!s || !x) return fail(SD_E_INVALID, "NULL argument");
+  *x = s->s->xscale;
+  return SD_OK;
+}
+
 int sd_solver_profile_read(const sd_solver* s, int64_t* launches, double* seconds,
                            double* bytes) {
   if (!s) return fail(SD_E_INVALID, "solver is NULL");

@@ -206,7 +206,7 @@ void Solver::setup_host(HostProblem* p, const sd_solver_opts* o) {
   if (so.restart < 1 || so.restart > kMaxBasis - 1)
     throw Error(SD_E_INVALID, "restart must be in 1..63");
   if (!(so.tol > 0.0) || so.maxit < 1) throw Error(SD_E_INVALID, "tol > 0 and maxit >= 1 required");
-  if (so.precond != SD_PREC_BJ && so.precond != SD_PREC_BGS) throw Error(SD_E_INVALID, "precond");
+  if (so.precond < SD_PREC_BJ || so.precond > SD_PREC_TD_BGS) throw Error(SD_E_INVALID, "precond");
   if (so.schur != SD_SCHUR_IDENTITY && so.schur != SD_SCHUR_MASS && so.schur != SD_SCHUR_CC)
     throw Error(SD_E_INVALID, "schur");
   if (so.schur == SD_SCHUR_CC && !(p->mass > 0.0))
@@ -263,8 +263,13 @@ void Solver::setup_host(HostProblem* p, const sd_solver_opts* o) {
     std::vector<int32_t> compP((size_t)(L.off_q - L.off_p), 0);
     amg_setup_host(Lp, compP, false, opts.amg, hh[2]);
   }
-  if (so.precond == SD_PREC_BGS) {
+  if (so.precond == SD_PREC_BGS || so.precond == SD_PREC_TD_BGS) {
     Cf = extract_block(p->A, L.off_p, L.N, 0, L.off_p);
+  } else if (so.precond == SD_PREC_TD_BJ) {
+    // continuity rows keep their velocity coupling, porous rows lose theirs
+    Cf = extract_block(p->A, L.off_p, L.off_q, 0, L.off_p);
+    Cf.n_rows = L.N - L.off_p;
+    Cf.rowptr.resize((size_t)Cf.n_rows + 1, Cf.rowptr.back());
   } else {
     Cf.n_rows = L.N - L.off_p;
     Cf.n_cols = L.off_p;
@@ -273,6 +278,10 @@ void Solver::setup_host(HostProblem* p, const sd_solver_opts* o) {
   const double dz = p->L.nz > 0 ? p->grid.Lz / (double)p->grid.nz : 1.0;
   const double vol = ((p->grid.Lx / (double)p->grid.nx) * (p->grid.H_ff / (double)p->grid.ny)) * dz;
   xscale = so.schur == SD_SCHUR_IDENTITY ? 1.0 : p->phys.mu / vol;
+  if (so.precond == SD_PREC_TD_BJ || so.precond == SD_PREC_TD_BGS) {
+    if (so.schur == SD_SCHUR_CC) throw Error(SD_E_INVALID, "two-domain forms use the Uzawa block");
+    xscale = 1.0;   // replaced by the Uzawa relaxation once the V-cycle is on the device
+  }
   t_setup = wall_time() - t0;
 }
 
@@ -323,8 +332,48 @@ void Solver::upload(const sd_allocator* alloc, hipStream_t s) {
   SD_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
   prec = opts.o.precision == SD_PRECISION_FP64 ? make_prec_fp64(*this, s) : make_prec_fp32(*this, s);
   SD_HIP(hipStreamSynchronize(s));
+  if ((opts.o.precond == SD_PREC_TD_BJ || opts.o.precond == SD_PREC_TD_BGS) && off[2] > 0 &&
+      off[3] > off[2])
+    xscale = uzawa_relaxation(s);
   on_device = true;
   t_setup += wall_time() - t0;
+}
+
+// omega = 1/lambda_max of -C P_V B, P_V one V-cycle on the velocity block,
+// by power iteration from the normalised ones vector (the inexact Uzawa step
+// of the two-domain preconditioners).  Products with B and C run on the host,
+// the V-cycle on the device.
+double Solver::uzawa_relaxation(hipStream_t s) {
+  const int64_t nv = off[2], np_ = off[3] - off[2];
+  HostCSR Bh = extract_block(pb->A, 0, nv, nv, off[3]);
+  HostCSR Ch = extract_block(pb->A, nv, off[3], 0, nv);
+  double* d_in = mem->array<double>((size_t)nv);
+  double* d_out = mem->array<double>((size_t)nv);
+  std::vector<double> x((size_t)np_, 1.0 / std::sqrt((double)np_)), t((size_t)nv), y((size_t)np_);
+  double lam = 1.0;
+  for (int it = 0; it < kUzawaPowerIters; ++it) {
+    for (int64_t r = 0; r < nv; ++r) {
+      double acc = 0.0;
+      for (int64_t k = Bh.rowptr[r]; k < Bh.rowptr[r + 1]; ++k) acc += Bh.val[k] * x[Bh.col[k]];
+      t[r] = acc;
+    }
+    SD_HIP(hipMemcpyAsync(d_in, t.data(), (size_t)nv * 8, hipMemcpyHostToDevice, s));
+    prec->apply_vcycle(*this, 0, d_in, d_out, s);
+    SD_HIP(hipMemcpyAsync(t.data(), d_out, (size_t)nv * 8, hipMemcpyDeviceToHost, s));
+    SD_HIP(hipStreamSynchronize(s));
+    double nrm = 0.0;
+    for (int64_t r = 0; r < np_; ++r) {
+      double acc = 0.0;
+      for (int64_t k = Ch.rowptr[r]; k < Ch.rowptr[r + 1]; ++k) acc += Ch.val[k] * t[Ch.col[k]];
+      y[r] = -acc;
+      nrm += y[r] * y[r];
+    }
+    lam = std::sqrt(nrm);
+    if (!(lam > 0.0) || !std::isfinite(lam))
+      throw Error(SD_E_INVALID, "Uzawa relaxation: degenerate Schur complement");
+    for (int64_t r = 0; r < np_; ++r) x[r] = y[r] / lam;
+  }
+  return 1.0 / lam;
 }
 
 int Solver::solve(const double* b, double* x, int use_x0, sd_stats* stats, hipStream_t s) {

@@ -162,7 +162,10 @@ class Solver {
   void upload(const sd_allocator* alloc, hipStream_t s);
   size_t device_bytes() const { return mem ? mem->bytes() : 0; }
   int solve(const double* b, double* x, int use_x0, sd_stats* stats, hipStream_t s);
+  double uzawa_relaxation(hipStream_t s);
 };
+
+constexpr int kUzawaPowerIters = 30;
 
 // SELL construction on the host and upload.
 template <typename T>

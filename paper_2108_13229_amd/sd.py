@@ -21,7 +21,7 @@ SD_OK, SD_E_INVALID, SD_E_NOMEM, SD_E_DEVICE = 0, -1, -2, -3
 SD_E_NOCONV, SD_E_BREAKDOWN, SD_E_BUSY, SD_E_NOTFOUND = -4, -5, -6, -7
 BC = {"velocity": 0, "traction": 1, "pressure": 2, "noflow": 3}
 KRYLOV = {"fgmres": 0, "bicgstab": 1}
-PRECOND = {"BJ": 0, "BGS": 1}
+PRECOND = {"BJ": 0, "BGS": 1, "TD_BJ": 2, "TD_BGS": 3}
 SCHUR = {"identity": 0, "mass": 1, "cc": 2}
 PRECISION = {"fp64": 0, "mixed": 1, "mixed32": 2}
 AMG = {"plain": 0, "smoothed": 1}
@@ -145,6 +145,7 @@ SIGNATURES = {
     "sd_apply_preconditioner": (C.c_int, [_P, _P, _P, _P]),
     "sd_apply_vcycle": (C.c_int, [_P, C.c_int, _P, _P, _P]),
     "sd_solver_profile": (C.c_int, [_P, C.c_int]),
+    "sd_solver_middle_scale": (C.c_int, [_P, C.POINTER(C.c_double)]),
     "sd_solver_profile_read": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                          C.POINTER(C.c_double)]),
     "sd_server_create": (C.c_int, [C.POINTER(ServerOpts), C.POINTER(_P)]),
@@ -397,6 +398,11 @@ class Solver:
         _check(lib().sd_apply_vcycle(self.h, block, C.c_void_p(b.data_ptr()),
                                      C.c_void_p(x.data_ptr()), _stream()))
         return x
+
+    def middle_scale(self) -> float:
+        x = C.c_double()
+        _check(lib().sd_solver_middle_scale(self.h, C.byref(x)))
+        return x.value
 
     PROFILE = {"off": 0, "arnoldi_spmv": 1, "arnoldi_update": 2, "jacobi_v0": 3}
 

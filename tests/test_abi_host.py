@@ -121,7 +121,7 @@ def test_invalid_inputs_are_rejected():
     with pytest.raises(sd.SDError):
         sd.Solver(P, device=True)        # host-only problem cannot get device data
     for bad in (dict(precision=3), dict(precision=-1), dict(nu_pre=-1), dict(coarse_max=0),
-                dict(mis=3), dict(omega=0.0)):
+                dict(mis=3), dict(omega=0.0), dict(precond=4), dict(precond=-1)):
         with pytest.raises(sd.SDError):
             sd.Solver(P, device=False, **bad)
     assert sd.lib().sd_status_string(-4) == b"SD_E_NOCONV"
@@ -219,3 +219,12 @@ def test_host_amg_3d_bit_exact(ci, schur):
             if lev + 1 < h.n_levels:
                 assert np.array_equal(S.level_agg(blk, lev), L.agg)
 
+
+
+@pytest.mark.parametrize("variant", ["TD_BJ", "TD_BGS"])
+def test_two_domain_setup_on_host(variant):
+    p = channel_problem(24, 12, seed=2)
+    P = sd.Problem(p, device=False)
+    S = sd.Solver(P, device=False, precond=variant, coarse_max=64)
+    assert S.n_levels(0) >= 2 and S.n_levels(1) >= 2
+    assert S.middle_scale() == 1.0      # omega needs the device V-cycle

@@ -308,3 +308,25 @@ def test_bicgstab_mixed_and_repeat():
     x3 = torch.full((a.N,), 7.0, dtype=torch.float64, device="cuda")
     x3, st3, rc = S.solve(x=x3)
     assert torch.equal(x1, x3)
+
+
+@pytest.mark.parametrize("variant", ["TD_BJ", "TD_BGS"])
+def test_two_domain_uzawa_variants(variant):
+    """Two-domain forms with one inexact Uzawa step: the relaxation omega
+    (power iteration through the device V-cycle), one preconditioner
+    application and the FGMRES iteration agree with the oracle."""
+    p = SMALL["channel96"]()
+    print("case channel96", variant, flush=True)
+    a = assemble(p)
+    M = precond.build(p, a, variant)
+    P, S = _setup(p, precond=variant, tol=1e-10)
+    assert abs(S.middle_scale() - M.xscale) <= 1e-9 * M.xscale
+    r = np.random.default_rng(17).standard_normal(a.N)
+    z = _host(S.apply_preconditioner(_dev(r)))
+    ref = M(r)
+    assert np.linalg.norm(z - ref) <= 1e-10 * np.linalg.norm(ref)
+    res = krylov.fgmres(a.A, a.b, M, tol=1e-10, m=30)
+    x, st, rc = S.solve()
+    assert rc == sd.SD_OK and abs(st["iters"] - res.iters) <= 1
+    xs = refined_solve(a.A, a.b)
+    assert np.linalg.norm(_host(x) - xs) <= 1e-7 * np.linalg.norm(xs)
