@@ -67,6 +67,9 @@ def parse():
     ap.add_argument("--partitioned", action="store_true",
                     help="the Dirichlet-Neumann coupling (Aitken, IQN-ILS) beside the "
                          "monolithic solve on the chosen 2-D workload")
+    ap.add_argument("--variants", action="store_true",
+                    help="the monolithic preconditioner variants of the paper's Table 2 "
+                         "(pv-BJ/BGS with AMG, td-BJ/BGS with Uzawa and AMG) on the workload")
     ap.add_argument("--counter-run", action="store_true",
                     help="one FP64 solve with plain (non-graph) launches plus a 512 MiB "
                          "device copy, for hardware-counter passes")
@@ -353,6 +356,32 @@ def partitioned(sd, args, p):
     print(json.dumps(out))
 
 
+def variants(sd, args, p):
+    """The iterative monolithic rows of the paper's Table 2 with FGMRES(m):
+    P^pv_BJ(AMG, AMG) and P^pv_BGS(AMG, AMG) with the paper's identity middle
+    block, P^td_BJ(Uzawa, AMG) and P^td_BGS(Uzawa, AMG), beside this
+    library's default (pv-BGS with mu M_p^-1); FP64, tolerance 1e-8."""
+    P = sd.Problem(p, device=True)
+    rows = [("pv-BJ(AMG,AMG), identity", dict(precond="BJ", schur="identity")),
+            ("pv-BGS(AMG,AMG), identity", dict(precond="BGS", schur="identity")),
+            ("td-BJ(Uzawa,AMG)", dict(precond="TD_BJ")),
+            ("td-BGS(Uzawa,AMG)", dict(precond="TD_BGS")),
+            ("pv-BGS(AMG,AMG), mu*Mp^-1 (default)", dict(precond="BGS", schur="mass"))]
+    out = {"metric": "Stokes-Darcy solves/s per preconditioner variant (FGMRES, FP64, tol 1e-8)",
+           "unit": "solves/s", "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": WORKLOAD if args.config == "C1" else WORKLOAD_C2,
+                      "N": P.N, "restart": args.restart}, "variants": {}}
+    for name, o in rows:
+        S = sd.Solver(P, tol=1e-8, restart=args.restart, maxit=3000, **o)
+        lat, its, st, x = run_solves(S, max(2, args.steps // 4), 1)
+        out["variants"][name] = dict(solves_per_s=float(len(lat) / lat.sum()),
+                                     ms_per_solve=float(1e3 * lat.mean()),
+                                     iters=int(np.median(its)), middle_scale=S.middle_scale())
+        S.close()
+    out["value"] = out["variants"]["pv-BGS(AMG,AMG), mu*Mp^-1 (default)"]["solves_per_s"]
+    print(json.dumps(out))
+
+
 def cpu_baseline(p, restart, timed=True):
     """The oracle's FP64 FGMRES with the same preconditioner, one solve,
     single-threaded (setup excluded; timed separately); then, with every
@@ -402,6 +431,9 @@ def main():
         return
     if args.partitioned:
         partitioned(sd, args, p)
+        return
+    if args.variants:
+        variants(sd, args, p)
         return
     if args.counter_run:
         counter_run(sd, p, args.restart)
