@@ -31,6 +31,11 @@ momentum / mass fluxes = source x |CV|"):
 * mass-flux continuity: the porous top cell's outward interface flux is
   dx * v_{i,0}, the same unknown as the free-flow normal velocity;
 * Dirichlet velocity faces are eliminated and lifted into b;
+* full Beavers-Joseph (``Problem.bj_full``): the slip condition keeps the
+  porous tangential velocity u_pm = -(K_f/mu)(q_i - q_{i-1})/dx at the face,
+  so the south shear flux becomes g mu [(2 dx/dy)(u - u_pm) + (v_i - v_{i-1})]:
+  the u rows of the first free-flow row couple to the two porous top cells
+  below with +-cg (K_f/mu)/dx (the paper's experiments use BJS);
 * time (dt > 0): the transient momentum equation of Sec. 2 with the paper's
   first-order backward Euler step.  A momentum row integrates dv/dt over its
   control volume, which adds |CV|/dt to the diagonal of every interior u and
@@ -235,6 +240,10 @@ def assemble(p: Problem) -> Assembled:
     add(r, L.v(i - 1, j), np.where(gam, -gm, -mu))
     add(r, L.p(i, j), dy)
     add(r, L.p(i - 1, j), -dy)
+    if p.bj_full:
+        cbj = cg * ((Kf / mu) / dx)
+        add(r, L.q(i, nyp - 1), cbj, gam)
+        add(r, L.q(i - 1, nyp - 1), -cbj, gam)
     rhs = fu[j, i] * vol
     rhs = np.where(i - 1 == 0, rhs + cx * uL[j], rhs)
     if not right_tr:

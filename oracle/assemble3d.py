@@ -20,7 +20,9 @@ assembly.  Additional closures in 3-D:
   beta = alpha/sqrt(K_f), K_f the harmonic mean of the two porous top cells
   beside the face (along x for u, along z for w);
 * Gamma rows Ay [p - 2 mu (v_1 - v_0)/dy - q_top + (mu/K_top)(dy_pm/2) v_0] = 0;
-* porous cells: six two-point fluxes, interface flux Ay v_{i,0,k}.
+* porous cells: six two-point fluxes, interface flux Ay v_{i,0,k};
+* full Beavers-Joseph (``bj_full``): as in 2-D, for u along x and for w
+  along z (porous tangential velocity -(K_f/mu) dq/dz at a w face).
 
 Unknown order (pv blocks): u (j, k, i), v (j, k, i), w (j, k, i), p (j, k, i),
 q (j, k, i), the last index fastest.  Velocity block = u, v, w.
@@ -228,6 +230,11 @@ def assemble3d(p: Problem) -> Assembled3:
     add(r, L.w(i - 1, j, kb), -mdy, ~back)
     add(r, L.p(i, j, k), Ax)
     add(r, L.p(i - 1, j, k), -Ax)
+    if p.bj_full:          # porous tangential velocity in the slip condition
+        Kf = harm(K[nyp - 1, k, i - 1], K[nyp - 1, k, i])
+        cbj = cg * ((Kf / mu) / dx)
+        add(r, L.q(i, nyp - 1, k), cbj, gam)
+        add(r, L.q(i - 1, nyp - 1, k), -cbj, gam)
     rhs = fu[j, k, i] * vol
     rhs = np.where(i - 1 == 0, rhs + cx * uL[j, k], rhs)
     if not right_tr:
@@ -343,6 +350,11 @@ def assemble3d(p: Problem) -> Assembled3:
         add(r, L.v(i, j, k - 1), np.where(gam, -gmw, -mdx))
         add(r, L.p(i, j, k), Az)
         add(r, L.p(i, j, k - 1), -Az)
+        if p.bj_full:
+            Kf = harm(K[nyp - 1, k - 1, i], K[nyp - 1, k, i])
+            cbj = cgw * ((Kf / mu) / dz)
+            add(r, L.q(i, nyp - 1, k), cbj, gam)
+            add(r, L.q(i, nyp - 1, k - 1), -cbj, gam)
         rhs = fw[j, k, i] * vol
         rhs = np.where(k - 1 == 0, rhs + czz * wB[j, i], rhs)
         rhs = np.where(k + 1 == nz, rhs + czz * wF[j, i], rhs)

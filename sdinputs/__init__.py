@@ -76,6 +76,7 @@ class Problem:
     f_v: Optional[np.ndarray] = None
     q_pm: Optional[np.ndarray] = None
     dt: float = 0.0                          # backward-Euler step, 0 = stationary
+    bj_full: bool = False                    # slip with the porous tangential velocity
     # ---- third dimension (nz = 0: the 2-D problem above) ----
     nz: int = 0                              # spanwise cells (z), both subdomains
     Lz: float = 1.0
@@ -222,12 +223,15 @@ class MMS:
     porous-medium pressure y cos(pi x).  h = h0 + h1 s + s^2 with
     h0 = -K/mu (normal mass flux continuity), h1 = (sqrt(K)/alpha)(2 + pi^2 h0)
     (Beavers-Joseph-Saffman slip) and Q0 = y_G + 2 mu h1 (normal stress
-    balance).  Valid for constant K."""
+    balance).  Valid for constant K.  With bj_full the slip condition keeps
+    the porous tangential velocity -(K/mu) dP/dx (full Beavers-Joseph), and
+    h1 = (sqrt(K)/alpha)(2 + pi^2 h0) - (K/mu) pi^2 y_G."""
 
     K: float
     mu: float
     alpha: float
     y_gamma: float
+    bj_full: bool = False
 
     @property
     def h0(self):
@@ -235,7 +239,10 @@ class MMS:
 
     @property
     def h1(self):
-        return math.sqrt(self.K) / self.alpha * (2.0 + math.pi ** 2 * self.h0)
+        h1 = math.sqrt(self.K) / self.alpha * (2.0 + math.pi ** 2 * self.h0)
+        if self.bj_full:
+            h1 -= self.K / self.mu * math.pi ** 2 * self.y_gamma
+        return h1
 
     @property
     def Q0(self):
@@ -288,16 +295,18 @@ class MMS:
 
 def mms_problem(nx: int, ny: int, ny_pm: Optional[int] = None, K: float = 1e-2,
                 mu: float = 1.0, alpha: float = 1.0, Lx: float = 1.0,
-                H_ff: float = 0.5, H_pm: float = 0.5) -> tuple[Problem, MMS]:
+                H_ff: float = 0.5, H_pm: float = 0.5,
+                bj_full: bool = False) -> tuple[Problem, MMS]:
     """Manufactured-solution problem: free-flow velocity given on the left and
     top, momentum flux (traction) on the right, Dirichlet pressure on the three
-    outer porous-medium sides."""
+    outer porous-medium sides; bj_full: the full Beavers-Joseph variant."""
     ny_pm = ny if ny_pm is None else ny_pm
     p = Problem(nx=nx, ny=ny, ny_pm=ny_pm, Lx=Lx, H_ff=H_ff, H_pm=H_pm, mu=mu,
                 alpha_bj=alpha, K=np.full((ny_pm, nx), K),
                 ff_left=BC_VELOCITY, ff_right=BC_TRACTION, ff_top=BC_VELOCITY,
-                pm_left=BC_PRESSURE, pm_right=BC_PRESSURE, pm_bottom=BC_PRESSURE)
-    m = MMS(K=K, mu=mu, alpha=alpha, y_gamma=H_pm)
+                pm_left=BC_PRESSURE, pm_right=BC_PRESSURE, pm_bottom=BC_PRESSURE,
+                bj_full=bj_full)
+    m = MMS(K=K, mu=mu, alpha=alpha, y_gamma=H_pm, bj_full=bj_full)
     yc = p.y_gamma + (np.arange(ny) + 0.5) * p.dy
     yv = p.y_gamma + np.arange(ny + 1) * p.dy
     xu = np.arange(nx + 1) * p.dx

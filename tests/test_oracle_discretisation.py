@@ -272,3 +272,68 @@ def test_iqn_ils_terminates_on_the_affine_interface_map(sign):
         assert done_at is not None and done_at <= n + 2
     else:
         assert done_at is None
+
+
+# ---- full Beavers-Joseph condition (porous tangential velocity kept) ----
+
+def test_full_bj_mms_satisfies_the_condition():
+    sy = pytest.importorskip("sympy")
+    x, y = sy.symbols("x y")
+    K, mu, al, yg = 1e-2, 1.0, 1.0, 0.5
+    m = MMS(K=K, mu=mu, alpha=al, y_gamma=yg, bj_full=True)
+    s = y - yg
+    h = m.h0 + m.h1 * s + s ** 2
+    psi = -sy.sin(sy.pi * x) * h / sy.pi
+    u = sy.diff(psi, y)
+    v = -sy.diff(psi, x)
+    p = sy.cos(sy.pi * x) * (m.Q0 + s)
+    P = y * sy.cos(sy.pi * x)
+    txy = mu * (sy.diff(u, y) + sy.diff(v, x))
+    u_pm = -K / mu * sy.diff(P, x)
+    for X in np.linspace(0.05, 0.95, 7):
+        sub = {x: X, y: yg}
+        # (u_ff - u_pm) - sqrt(K)/(alpha mu) tau_xy = 0 on Gamma
+        assert abs(float((u - u_pm - math.sqrt(K) / (al * mu) * txy).subs(sub))) < 1e-12
+        assert abs(float((p - 2 * mu * sy.diff(v, y) - P).subs(sub))) < 1e-12
+        assert abs(float((-K / mu * sy.diff(P, y) - v).subs(sub))) < 1e-12
+
+
+def _mms_errors_bj(n, assemble_full):
+    p, m = mms_problem(n, n // 2, bj_full=True)
+    p.bj_full = assemble_full
+    a = assemble(p)
+    x = solve(a.A, a.b)
+    u, v, pp, q = split_solution(x, a.layout)
+    xu, yu = u_face_xy(p)
+    xv, yv = v_face_xy(p)
+    xc, yc = ff_cell_xy(p)
+    xq, yq = pm_cell_xy(p)
+    return np.array([np.abs(u - m.u(xu, yu)[:, 1:]).max(),
+                     np.abs(v - m.v(xv, yv)[:-1, :]).max(),
+                     np.abs(pp - m.p(xc, yc)).max(),
+                     np.abs(q - m.P(xq, yq)).max()])
+
+
+def test_full_bj_convergence_and_a_planted_bjs_closure():
+    ns = [32, 64, 128]
+    errs = np.array([_mms_errors_bj(n, True) for n in ns])
+    assert np.all(np.diff(errs, axis=0) < 0)
+    slope = -np.polyfit(np.log2(ns), np.log2(errs), 1)[0]
+    assert np.all(slope >= 0.85), slope
+    # the same data with the BJS closure (porous tangential velocity dropped)
+    bad = np.array([_mms_errors_bj(n, False) for n in ns[1:]])
+    assert bad[-1, 0] > 5 * errs[-1, 0]
+
+
+def test_full_bj_couples_only_the_first_row_u_faces_to_the_top_cells():
+    p = channel_problem(16, 8, seed=3)
+    A0 = assemble(p).A
+    p.bj_full = True
+    a = assemble(p)
+    d = (a.A - A0).tocoo()
+    L = a.layout
+    nz = d.data != 0
+    rows, cols = d.row[nz], d.col[nz]
+    assert set(rows) == {L.u(i, 0) for i in range(1, L.nu_x + 1) if i <= p.nx - 1}
+    assert set(cols) <= {L.q(i, p.ny_pm - 1) for i in range(p.nx)}
+    assert np.allclose(np.asarray(d.tocsr().sum(axis=1)).ravel()[rows], 0.0, atol=1e-15)
