@@ -84,6 +84,11 @@ typedef struct {
   double mu;                  /* dynamic viscosity (rho = 1, nu = mu)          */
   double alpha_bj;            /* Beavers-Joseph coefficient                    */
   double dt;                  /* backward-Euler time step; 0 = stationary      */
+  int bj_full;                /* 0: Beavers-Joseph-Saffman (the paper's);
+                                 1: full Beavers-Joseph, the slip condition
+                                 keeps the porous tangential velocity
+                                 -(K_f/mu) dq/dt along Gamma (not supported by
+                                 the partitioned coupling)                    */
 } sd_physics;
 
 typedef enum { SD_BC_VELOCITY = 0, SD_BC_TRACTION = 1, SD_BC_PRESSURE = 2,

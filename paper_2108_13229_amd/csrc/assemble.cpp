@@ -14,6 +14,9 @@
 //   * traction outflow: n.(pI - tau)n at the last cell centre = data;
 //   * Gamma rows: dx [p - 2 mu (v_1 - v_0)/dy - q_top + (mu/K)(dy_pm/2) v_0] = 0;
 //   * porous top cells: interface flux dx * v_{i,0};
+//   * full Beavers-Joseph (phys.bj_full): the slip velocity is measured
+//     against the porous tangential velocity -(K_f/mu)(q_i - q_{i-1})/dx, so
+//     Gamma's u rows couple to the two top cells with +-cg (K_f/mu)/dx;
 //   * dt > 0: the transient momentum equation with the paper's backward Euler
 //     step adds |CV|/dt (rho = 1) to the diagonal of every interior u and v
 //     face row; the outflow u rows, the Gamma rows and the Darcy rows are
@@ -197,6 +200,11 @@ void assemble_host(const sd_grid* g, const sd_physics* ph, const sd_bcs* bcs,
       rb.add(L.v(i - 1, j), gam ? -gm : -mu);
       rb.add(L.p(i, j), dy);
       rb.add(L.p(i - 1, j), -dy);
+      if (ph->bj_full && gam) {   // porous tangential velocity in the slip condition
+        const double cbj = cg * ((Kf / mu) / dx);
+        rb.add(L.q(i, nyp - 1), cbj);
+        rb.add(L.q(i - 1, nyp - 1), -cbj);
+      }
       rb.finish();
       double rhs = data(fu, (int64_t)j * (nx + 1) + i) * vol;
       if (i - 1 == 0) rhs = rhs + cx * data(uL, j);

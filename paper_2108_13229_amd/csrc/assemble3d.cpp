@@ -15,7 +15,9 @@
 //     beta = alpha/sqrt(K_f), K_f the harmonic mean of the two porous top
 //     cells beside the face;
 //   * Gamma rows: Ay [p - 2 mu (v_1 - v_0)/dy - q_top + (mu/K)(dy_pm/2) v_0] = 0;
-//   * porous cells: six two-point fluxes, interface flux Ay v_{i,0,k}.
+//   * porous cells: six two-point fluxes, interface flux Ay v_{i,0,k};
+//   * full Beavers-Joseph (phys.bj_full): as in 2-D, along x for u and along
+//     z for w.
 // Unknowns u, v, w, p, q, each ordered (j, k, i) with i fastest.  Every
 // coefficient is one fixed IEEE-double expression (no contraction), so the
 // values are reproducible bit for bit.
@@ -199,6 +201,12 @@ void assemble_host_3d(const sd_grid* g, const sd_physics* ph, const sd_bcs* bcs,
         }
         rb.add(L.p3(i, j, k), Ax);
         rb.add(L.p3(i - 1, j, k), -Ax);
+        if (ph->bj_full && gam) {   // porous tangential velocity in the slip condition
+          const double Kf = harm(Kat(i - 1, nyp - 1, k), Kat(i, nyp - 1, k));
+          const double cbj = cg * ((Kf / mu) / dx);
+          rb.add(L.q3(i, nyp - 1, k), cbj);
+          rb.add(L.q3(i - 1, nyp - 1, k), -cbj);
+        }
         rb.finish();
         double rhs = d(fu, jk * (nx + 1) + i) * vol;
         if (i - 1 == 0) rhs = rhs + cx * d(uL, jk);
@@ -315,6 +323,12 @@ void assemble_host_3d(const sd_grid* g, const sd_physics* ph, const sd_bcs* bcs,
         rb.add(L.v3(i, j, k - 1), gam ? -gmw : -mdx);
         rb.add(L.p3(i, j, k), Az);
         rb.add(L.p3(i, j, k - 1), -Az);
+        if (ph->bj_full && gam) {
+          const double Kf = harm(Kat(i, nyp - 1, k - 1), Kat(i, nyp - 1, k));
+          const double cbj = cgw * ((Kf / mu) / dz);
+          rb.add(L.q3(i, nyp - 1, k), cbj);
+          rb.add(L.q3(i, nyp - 1, k - 1), -cbj);
+        }
         rb.finish();
         const int64_t jz1 = (int64_t)j * (nz + 1) + k;
         double rhs = d(fw, jz1 * nx + i) * vol;

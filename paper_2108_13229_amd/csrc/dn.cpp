@@ -374,6 +374,8 @@ int sd_dn_setup(sd_problem* pb, const sd_solver_opts* sub, sd_dn** out) {
     if (!pb || !out) throw sd::Error(SD_E_INVALID, "NULL argument");
     *out = nullptr;
     if (!pb->device) throw sd::Error(SD_E_INVALID, "problem was assembled without a device");
+    if (pb->hp.phys.bj_full)
+      throw sd::Error(SD_E_INVALID, "the partitioned coupling supports the BJS condition only");
     SD_HIP(hipSetDevice(pb->device_id));
     sd_solver_opts d;
     sd_solver_opts_default(&d);

@@ -37,7 +37,8 @@ class Grid(C.Structure):
 
 
 class Physics(C.Structure):
-    _fields_ = [("mu", C.c_double), ("alpha_bj", C.c_double), ("dt", C.c_double)]
+    _fields_ = [("mu", C.c_double), ("alpha_bj", C.c_double), ("dt", C.c_double),
+                ("bj_full", C.c_int)]
 
 
 class Bcs(C.Structure):
@@ -203,7 +204,8 @@ def _marshal(p, keep):
     nz = int(getattr(p, "nz", 0))
     g = Grid(int(p.nx), int(p.ny), int(p.ny_pm), float(p.Lx), float(p.H_ff), float(p.H_pm),
              nz, float(getattr(p, "Lz", 1.0)))
-    ph = Physics(float(p.mu), float(p.alpha_bj), float(getattr(p, "dt", 0.0)))
+    ph = Physics(float(p.mu), float(p.alpha_bj), float(getattr(p, "dt", 0.0)),
+                 int(bool(getattr(p, "bj_full", False))))
     b = Bcs(BC[p.ff_left], BC[p.ff_right], BC[p.ff_top], BC[p.pm_left], BC[p.pm_right],
             BC[p.pm_bottom],
             _ptr(p.ff_left_n, keep), _ptr(p.ff_left_t, keep), _ptr(p.ff_right_n, keep),

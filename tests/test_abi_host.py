@@ -43,9 +43,11 @@ def _cases():
     p_vel_tr.ff_right = "velocity"
     p_vel_tr.ff_right_n = np.linspace(0.0, 1e-3, 10)
     p_vel_tr.dt = 3e-4
+    p_bj = channel_problem(30, 14, 9, seed=6)
+    p_bj.bj_full = True
     return [mms_problem(32, 16)[0], mms_problem(24, 12, 9, K=3e-3, mu=0.5, alpha=0.7)[0],
             channel_problem(64, 32, seed=1), channel_problem(45, 22, 17, seed=5), p_vel, p_mixbc,
-            p_tr, p_vel_tr]
+            p_tr, p_vel_tr, mms_problem(20, 10, bj_full=True)[0], p_bj]
 
 
 @pytest.mark.parametrize("p", _cases())
@@ -178,12 +180,14 @@ def _cases3d():
     c_p.pm_back, c_p.pm_front = "pressure", "pressure"
     c_p.pm_back_p = np.linspace(0.0, 1.0, 5 * 10).reshape(5, 10)
     c_p.dt = 0.2
+    c_bj = channel3d_problem(9, 5, 7, 4, seed=5)
+    c_bj.bj_full = True
     return [mms3d_problem(8, 4, 6, "xy")[0], mms3d_problem(9, 5, 7, "zy")[0],
             channel3d_problem(12, 6, 8, seed=1), c_vel, c_p,
-            mms3d_problem(6, 4, 1, "xy")[0]]
+            mms3d_problem(6, 4, 1, "xy")[0], c_bj]
 
 
-@pytest.mark.parametrize("ci", range(6))
+@pytest.mark.parametrize("ci", range(7))
 def test_host_assembly_3d_bit_exact(ci):
     from oracle.assemble3d import assemble3d
     p = _cases3d()[ci]

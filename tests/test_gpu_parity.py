@@ -330,3 +330,22 @@ def test_two_domain_uzawa_variants(variant):
     assert rc == sd.SD_OK and abs(st["iters"] - res.iters) <= 1
     xs = refined_solve(a.A, a.b)
     assert np.linalg.norm(_host(x) - xs) <= 1e-7 * np.linalg.norm(xs)
+
+
+def test_full_beavers_joseph_solve():
+    """Full Beavers-Joseph slip (porous tangential velocity kept): the GPU
+    solve matches the oracle's FGMRES and the direct solution; the
+    partitioned coupling refuses the option."""
+    p = channel_problem(96, 48, seed=3)
+    p.bj_full = True
+    a = assemble(p)
+    M = precond.build(p, a, "BGS")
+    ref = krylov.fgmres(a.A, a.b, M, tol=1e-10, m=30)
+    P, S = _setup(p, tol=1e-10)
+    x, st, rc = S.solve()
+    assert rc == sd.SD_OK and abs(st["iters"] - ref.iters) <= 1
+    xs = refined_solve(a.A, a.b)
+    assert np.linalg.norm(_host(x) - xs) <= 1e-7 * np.linalg.norm(xs)
+    with pytest.raises(sd.SDError) as e:
+        sd.Partitioned(P)
+    assert e.value.code == sd.SD_E_INVALID
