@@ -64,14 +64,29 @@ from sdinputs import (BC_NOFLOW, BC_PRESSURE, BC_TRACTION, BC_VELOCITY,
 
 @dataclasses.dataclass
 class Layout:
-    """Unknown index maps.  u faces i = 1..nu_x (nu_x = nx with an outflow
-    face, nx - 1 otherwise) per free-flow row j; v faces j = 0..ny-1 (j = 0 on
-    Gamma); p cells; porous cells q (row k = 0 at the bottom)."""
+    """Unknown index maps.  u faces i = i_first..i_last per free-flow row j
+    (i_first = 0 with a traction left boundary, 1 otherwise; i_last = nx with
+    a traction right boundary, nx - 1 otherwise; nu_x of them); v faces: the
+    n_gamma interface faces first (free-flow columns i0..i0+nx_pm-1 of row
+    j = 0, over the porous block), then rows j = 1..ny-1; p cells; porous
+    cells q (nx_pm columns, row k = 0 at the bottom).  With the porous block
+    as wide as the free flow this is the plain (row j, column i) order."""
 
     nx: int
     ny: int
     ny_pm: int
     nu_x: int
+    nx_pm: int = 0
+    i0: int = 0
+    i_first: int = 1
+
+    def __post_init__(self):
+        if self.nx_pm == 0:
+            self.nx_pm = self.nx
+
+    @property
+    def n_gamma(self):
+        return self.nx_pm
 
     @property
     def off_u(self):
@@ -83,7 +98,7 @@ class Layout:
 
     @property
     def off_p(self):
-        return self.off_v + self.nx * self.ny
+        return self.off_v + self.n_gamma + self.nx * (self.ny - 1)
 
     @property
     def off_q(self):
@@ -91,7 +106,7 @@ class Layout:
 
     @property
     def N(self):
-        return self.off_q + self.nx * self.ny_pm
+        return self.off_q + self.nx_pm * self.ny_pm
 
     @property
     def block_off(self):
@@ -99,16 +114,25 @@ class Layout:
                         dtype=np.int64)
 
     def u(self, i, j):
-        return self.off_u + j * self.nu_x + (i - 1)
+        return self.off_u + j * self.nu_x + (i - self.i_first)
 
     def v(self, i, j):
-        return self.off_v + j * self.nx + i
+        """v face (i, j); for j = 0 only the interface faces are unknowns."""
+        return np.where(np.asarray(j) == 0, self.off_v + (np.asarray(i) - self.i0),
+                        self.off_v + self.n_gamma + (np.asarray(j) - 1) * self.nx
+                        + np.asarray(i))
 
     def p(self, i, j):
         return self.off_p + j * self.nx + i
 
     def q(self, i, k):
-        return self.off_q + k * self.nx + i
+        """Porous cell of porous column i (0..nx_pm-1) and row k."""
+        return self.off_q + k * self.nx_pm + i
+
+    def over(self, i):
+        """Free-flow column i lies over the porous block."""
+        i = np.asarray(i)
+        return (i >= self.i0) & (i < self.i0 + self.nx_pm)
 
 
 def all_faces_dof(nx: int, ny: int, ny_pm: int) -> int:
@@ -120,12 +144,17 @@ def all_faces_dof(nx: int, ny: int, ny_pm: int) -> int:
 def layout_of(p: Problem) -> Layout:
     if p.nx < 2 or p.ny < 2 or p.ny_pm < 1:
         raise ValueError("need nx >= 2, ny >= 2, ny_pm >= 1")
-    if p.ff_left != BC_VELOCITY or p.ff_top != BC_VELOCITY:
-        raise ValueError("left and top free-flow boundaries must be velocity")
-    if p.ff_right not in (BC_VELOCITY, BC_TRACTION):
-        raise ValueError("right free-flow boundary: velocity or traction")
-    nu_x = p.nx if p.ff_right == BC_TRACTION else p.nx - 1
-    return Layout(p.nx, p.ny, p.ny_pm, nu_x)
+    if p.ff_top != BC_VELOCITY:
+        raise ValueError("the top free-flow boundary must be velocity")
+    for side in (p.ff_left, p.ff_right):
+        if side not in (BC_VELOCITY, BC_TRACTION):
+            raise ValueError("left/right free-flow boundaries: velocity or traction")
+    nx_pm = p.nx_pm or p.nx
+    if nx_pm < 1 or p.pm_i0 < 0 or p.pm_i0 + nx_pm > p.nx:
+        raise ValueError("the porous block must lie under the free flow")
+    i_first = 0 if p.ff_left == BC_TRACTION else 1
+    i_last = p.nx if p.ff_right == BC_TRACTION else p.nx - 1
+    return Layout(p.nx, p.ny, p.ny_pm, i_last - i_first + 1, nx_pm, p.pm_i0, i_first)
 
 
 def _arr(a, n):
@@ -158,8 +187,9 @@ class Assembled:
 def assemble(p: Problem) -> Assembled:
     L = layout_of(p)
     nx, ny, nyp = p.nx, p.ny, p.ny_pm
+    npm, i0 = L.nx_pm, L.i0
     mu, alpha = float(p.mu), float(p.alpha_bj)
-    K = np.asarray(p.K, dtype=np.float64).reshape(nyp, nx)
+    K = np.asarray(p.K, dtype=np.float64).reshape(nyp, npm)
     if not np.all(np.isfinite(K)) or np.any(K <= 0):
         raise ValueError("K must be finite and positive")
     dx = p.Lx / nx
@@ -180,6 +210,7 @@ def assemble(p: Problem) -> Assembled:
     cxv = mu * (dy / dx)                 # v rows, shear E/W
     cxw = mu * (dy / (0.5 * dx))         # v rows, shear at a side wall
     right_tr = p.ff_right == BC_TRACTION
+    left_tr = p.ff_left == BC_TRACTION
 
     uL = _arr(p.ff_left_n, ny)
     vL = _arr(p.ff_left_t, ny + 1)
@@ -189,10 +220,10 @@ def assemble(p: Problem) -> Assembled:
     vT = _arr(p.ff_top_n, nx)
     pL = _arr(p.pm_left_p, nyp)
     pR = _arr(p.pm_right_p, nyp)
-    pB = _arr(p.pm_bottom_p, nx)
+    pB = _arr(p.pm_bottom_p, npm)
     fu = _arr(p.f_u, (ny, nx + 1))
     fv = _arr(p.f_v, (ny + 1, nx))
-    fq = _arr(p.q_pm, (nyp, nx))
+    fq = _arr(p.q_pm, (nyp, npm))
 
     rows, cols, vals = [], [], []
     b = np.zeros(L.N)
@@ -211,46 +242,62 @@ def assemble(p: Problem) -> Assembled:
     j, i = np.meshgrid(np.arange(ny), np.arange(1, nx), indexing="ij")
     r = L.u(i, j)
     top = j == ny - 1
-    gam = j == 0
+    bot = j == 0
+    # faces of the first row whose two cells lie over the porous block obey
+    # BJS; the others meet the bottom wall (no slip over half a cell)
+    gam = bot & L.over(i - 1) & L.over(i)
     # BJS factor per face (harmonic mean of the two porous top cells below)
-    Ka = K[nyp - 1, i - 1]
-    Kb = K[nyp - 1, i]
+    Ka = K[nyp - 1, np.clip(i - 1 - i0, 0, npm - 1)]
+    Kb = K[nyp - 1, np.clip(i - i0, 0, npm - 1)]
     Kf = (2.0 * Ka * Kb) / (Ka + Kb)
     beta = alpha / np.sqrt(Kf)
     g = beta / (beta + 2.0 / dy)
     cg = (g * mu) * ((2.0 * dx) / dy)
     gm = g * mu
     aN = np.where(top, cyt, cy)
-    aS = np.where(gam, cg, cy)
+    aS = np.where(gam, cg, np.where(bot, cyt, cy))
     diag = ((cx + cx) + aN) + aS
     if dt > 0.0:
         diag = diag + mvol
         mass[r.ravel()] = mvol
     add(r, r, diag)
-    add(r, L.u(i - 1, j), -cx, i - 1 >= 1)
+    add(r, L.u(i - 1, j), -cx, (i - 1 >= 1) | left_tr)
     east_unknown = (i + 1 <= nx - 1) | right_tr
     add(r, L.u(np.minimum(i + 1, L.nu_x), j), -cx, east_unknown)
     add(r, L.u(i, np.minimum(j + 1, ny - 1)), -cy, ~top)
-    add(r, L.u(i, np.maximum(j - 1, 0)), -cy, ~gam)
+    add(r, L.u(i, np.maximum(j - 1, 0)), -cy, ~bot)
     # shear cross terms: -mu[(v_{i,j+1} - v_{i-1,j+1}) - (v_{i,j} - v_{i-1,j})]
     jn = np.minimum(j + 1, ny - 1)
     add(r, L.v(i, jn), -mu, ~top)
     add(r, L.v(i - 1, jn), mu, ~top)
-    add(r, L.v(i, j), np.where(gam, gm, mu))
-    add(r, L.v(i - 1, j), np.where(gam, -gm, -mu))
+    # the first row's bottom v faces are interface unknowns or wall (zero)
+    add(r, L.v(i, j), np.where(gam, gm, mu), ~bot | L.over(i))
+    add(r, L.v(i - 1, j), np.where(gam, -gm, -mu), ~bot | L.over(i - 1))
     add(r, L.p(i, j), dy)
     add(r, L.p(i - 1, j), -dy)
     if p.bj_full:
         cbj = cg * ((Kf / mu) / dx)
-        add(r, L.q(i, nyp - 1), cbj, gam)
-        add(r, L.q(i - 1, nyp - 1), -cbj, gam)
+        add(r, L.q(np.clip(i - i0, 0, npm - 1), nyp - 1), cbj, gam)
+        add(r, L.q(np.clip(i - 1 - i0, 0, npm - 1), nyp - 1), -cbj, gam)
     rhs = fu[j, i] * vol
-    rhs = np.where(i - 1 == 0, rhs + cx * uL[j], rhs)
+    if not left_tr:
+        rhs = np.where(i - 1 == 0, rhs + cx * uL[j], rhs)
     if not right_tr:
         rhs = np.where(i + 1 == nx, rhs + cx * uR[j], rhs)
     rhs = np.where(top, rhs + cyt * uT[i], rhs)
     rhs = np.where(top, rhs + mu * (vT[np.minimum(i, nx - 1)] - vT[i - 1]), rhs)
     b[r.ravel()] = rhs.ravel()
+
+    # ---------------- u rows, traction faces i = 0 (inflow side) -------------
+    # n.(pI - tau)n at the first cell centre equals the datum (pressure-driven
+    # inflow: the datum is the prescribed pressure)
+    if left_tr:
+        jj = np.arange(ny)
+        r = L.u(0, jj)
+        add(r, r, np.full(ny, cx))
+        add(r, L.u(1, jj), -cx)
+        add(r, L.p(0, jj), dy)
+        b[r] = uL * dy
 
     # ---------------- u rows, outflow faces i = nx ----------------
     if right_tr:
@@ -267,14 +314,14 @@ def assemble(p: Problem) -> Assembled:
     west = i == 0
     east = i == nx - 1
     aE = np.where(east, 0.0 if right_tr else cxw, cxv)
-    aW = np.where(west, cxw, cxv)
+    aW = np.where(west, 0.0 if left_tr else cxw, cxv)
     diag = ((cyy + cyy) + aE) + aW
     if dt > 0.0:
         diag = diag + mvol
         mass[r.ravel()] = mvol
     add(r, r, diag)
     add(r, L.v(i, np.minimum(j + 1, ny - 1)), -cyy, j + 1 <= ny - 1)
-    add(r, L.v(i, j - 1), -cyy)
+    add(r, L.v(i, j - 1), -cyy, (j - 1 >= 1) | L.over(i))   # wall faces are zero
     add(r, L.v(np.minimum(i + 1, nx - 1), j), -cxv, ~east)
     add(r, L.v(np.maximum(i - 1, 0), j), -cxv, ~west)
     # shear cross terms: -mu[(u_{i+1,j} - u_{i+1,j-1}) - (u_{i,j} - u_{i,j-1})]
@@ -289,8 +336,11 @@ def assemble(p: Problem) -> Assembled:
     add(r, L.p(i, j - 1), -dx)
     rhs = fv[j, i] * vol
     rhs = np.where(j + 1 == ny, rhs + cyy * vT[i], rhs)
-    rhs = np.where(west, rhs + cxw * vL[j], rhs)
-    rhs = np.where(west, rhs - mu * (uL[j] - uL[j - 1]), rhs)
+    if left_tr:
+        rhs = np.where(west, rhs - vL[j] * dy, rhs)
+    else:
+        rhs = np.where(west, rhs + cxw * vL[j], rhs)
+        rhs = np.where(west, rhs - mu * (uL[j] - uL[j - 1]), rhs)
     if right_tr:
         rhs = np.where(east, rhs - vR[j] * dy, rhs)
     else:
@@ -299,14 +349,14 @@ def assemble(p: Problem) -> Assembled:
     b[r.ravel()] = rhs.ravel()
 
     # ---------------- Gamma rows (v_{i,0}) ----------------
-    i = np.arange(nx)
+    i = np.arange(i0, i0 + npm)
     r = L.v(i, 0)
-    Kt = K[nyp - 1, i]
+    Kt = K[nyp - 1, i - i0]
     dg = ((mu / Kt) * (0.5 * dyp)) * dx
     add(r, r, cyy + dg)
     add(r, L.v(i, 1), -cyy)
     add(r, L.p(i, 0), dx)
-    add(r, L.q(i, nyp - 1), -dx)
+    add(r, L.q(i - i0, nyp - 1), -dx)
     b[r] = 0.0
 
     # ---------------- free-flow continuity ----------------
@@ -314,18 +364,19 @@ def assemble(p: Problem) -> Assembled:
     r = L.p(i, j)
     e_unk = (i + 1 <= nx - 1) | right_tr
     add(r, L.u(np.minimum(i + 1, L.nu_x), j), dy, e_unk)
-    add(r, L.u(np.maximum(i, 1), j), -dy, i >= 1)
+    add(r, L.u(np.maximum(i, L.i_first), j), -dy, (i >= 1) | left_tr)
     add(r, L.v(i, np.minimum(j + 1, ny - 1)), dx, j + 1 <= ny - 1)
-    add(r, L.v(i, j), -dx)
+    add(r, L.v(i, j), -dx, (j >= 1) | L.over(i))
     rhs = np.zeros_like(r, dtype=np.float64)
-    rhs = np.where(i == 0, rhs + dy * uL[j], rhs)
+    if not left_tr:
+        rhs = np.where(i == 0, rhs + dy * uL[j], rhs)
     if not right_tr:
         rhs = np.where(i + 1 == nx, rhs - dy * uR[j], rhs)
     rhs = np.where(j + 1 == ny, rhs - dx * vT[i], rhs)
     b[r.ravel()] = rhs.ravel()
 
     # ---------------- porous medium (TPFA) ----------------
-    k, i = np.meshgrid(np.arange(nyp), np.arange(nx), indexing="ij")
+    k, i = np.meshgrid(np.arange(nyp), np.arange(npm), indexing="ij")
     r = L.q(i, k)
     Kc = K[k, i]
 
@@ -336,7 +387,7 @@ def assemble(p: Problem) -> Assembled:
         return ((area / mu) * Kc) / (0.5 * d)
 
     zero = np.zeros_like(Kc)
-    TE = np.where(i + 1 <= nx - 1, t_int(dyp, dx, K[k, np.minimum(i + 1, nx - 1)]),
+    TE = np.where(i + 1 <= npm - 1, t_int(dyp, dx, K[k, np.minimum(i + 1, npm - 1)]),
                   t_dir(dyp, dx) if p.pm_right == BC_PRESSURE else zero)
     TW = np.where(i >= 1, t_int(dyp, dx, K[k, np.maximum(i - 1, 0)]),
                   t_dir(dyp, dx) if p.pm_left == BC_PRESSURE else zero)
@@ -344,14 +395,14 @@ def assemble(p: Problem) -> Assembled:
     TS = np.where(k >= 1, t_int(dx, dyp, K[np.maximum(k - 1, 0), i]),
                   t_dir(dx, dyp) if p.pm_bottom == BC_PRESSURE else zero)
     add(r, r, ((TE + TW) + TN) + TS)
-    add(r, L.q(np.minimum(i + 1, nx - 1), k), -TE, i + 1 <= nx - 1)
+    add(r, L.q(np.minimum(i + 1, npm - 1), k), -TE, i + 1 <= npm - 1)
     add(r, L.q(np.maximum(i - 1, 0), k), -TW, i >= 1)
     add(r, L.q(i, np.minimum(k + 1, nyp - 1)), -TN, k + 1 <= nyp - 1)
     add(r, L.q(i, np.maximum(k - 1, 0)), -TS, k >= 1)
-    add(r, L.v(i, 0), dx, k == nyp - 1)
+    add(r, L.v(i + i0, 0), dx, k == nyp - 1)
     rhs = fq[k, i] * volp
     if p.pm_right == BC_PRESSURE:
-        rhs = np.where(i == nx - 1, rhs + TE * pR[k], rhs)
+        rhs = np.where(i == npm - 1, rhs + TE * pR[k], rhs)
     if p.pm_left == BC_PRESSURE:
         rhs = np.where(i == 0, rhs + TW * pL[k], rhs)
     if p.pm_bottom == BC_PRESSURE:
@@ -373,7 +424,11 @@ def assemble(p: Problem) -> Assembled:
 
 
 def split_solution(x: np.ndarray, L: Layout):
-    """Return (u [ny, nu_x], v [ny, nx], p [ny, nx], q [ny_pm, nx])."""
+    """Return (u [ny, nu_x], v [ny, nx], p [ny, nx], q [ny_pm, nx_pm]); the
+    bottom wall faces of v (outside the porous block) are zero."""
     o = L.block_off
-    return (x[o[0]:o[1]].reshape(L.ny, L.nu_x), x[o[1]:o[2]].reshape(L.ny, L.nx),
-            x[o[2]:o[3]].reshape(L.ny, L.nx), x[o[3]:o[4]].reshape(L.ny_pm, L.nx))
+    v = np.zeros((L.ny, L.nx))
+    v[0, L.i0:L.i0 + L.nx_pm] = x[o[1]:o[1] + L.n_gamma]
+    v[1:] = x[o[1] + L.n_gamma:o[2]].reshape(L.ny - 1, L.nx)
+    return (x[o[0]:o[1]].reshape(L.ny, L.nu_x), v,
+            x[o[2]:o[3]].reshape(L.ny, L.nx), x[o[3]:o[4]].reshape(L.ny_pm, L.nx_pm))

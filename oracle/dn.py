@@ -37,10 +37,11 @@ class DNResult:
 
 def _subsolvers(p: Problem, a: Assembled):
     L = a.layout
-    nx, nyp = L.nx, L.ny_pm
+    nx, nyp, npm, i0 = L.nx, L.ny_pm, L.nx_pm, L.i0
     A = a.A.tocsr()
     N = L.N
-    gam = L.v(np.arange(nx), 0)                       # interface v unknowns
+    cols = np.arange(i0, i0 + npm)                    # free-flow columns over the block
+    gam = L.v(cols, 0)                                # interface v unknowns
     ff = np.arange(L.off_q)
     ff_int = np.setdiff1d(ff, gam)                    # free-flow unknowns/rows
     pm = np.arange(L.off_q, N)
@@ -52,18 +53,18 @@ def _subsolvers(p: Problem, a: Assembled):
     dy = p.H_ff / p.ny
     dyp = p.H_pm / nyp
     dx = p.Lx / nx
-    K = np.asarray(p.K, dtype=np.float64).reshape(nyp, nx)
+    K = np.asarray(p.K, dtype=np.float64).reshape(nyp, npm)
     Kt = K[nyp - 1, :]
     mu = p.mu
-    top = L.q(np.arange(nx), nyp - 1) - L.off_q
+    top = L.q(np.arange(npm), nyp - 1) - L.off_q
     TB = dx * Kt / (mu * 0.5 * dyp)                   # half-cell Darcy transmissibility
     D = A[pm][:, pm].tocsr()
     D = (D + sp.csr_matrix((TB, (top, top)), shape=D.shape)).tocsc()
     lu_pm = spla.splu(D)
     b_pm = a.b[pm]
     pos = {int(g): k for k, g in enumerate(ff_int)}
-    ip0 = np.array([pos[int(L.p(i, 0))] for i in range(nx)])
-    iv1 = np.array([pos[int(L.v(i, 1))] for i in range(nx)])
+    ip0 = np.array([pos[int(L.p(i, 0))] for i in cols])
+    iv1 = np.array([pos[int(L.v(i, 1))] for i in cols])
 
     def S_ff(vg):
         x = lu_ff.solve(b_ff - A_ffg @ vg)
@@ -95,7 +96,7 @@ def solve_dn(p: Problem, a: Assembled, eps: float = 1e-10, maxit: int = 500,
     r_k = vt_k - v_k, and stops once both relative measures of Sec. 3 hold:
     ||sigma_k - sigma_{k-1}|| < eps ||sigma_k|| and ||r_k|| < eps ||vt_k||."""
     S_ff, S_pm, to_mono = _subsolvers(p, a)
-    nx = a.layout.nx
+    nx = a.layout.n_gamma
     v = np.zeros(nx)
     sigma_old = None
     r_old = None
@@ -153,7 +154,7 @@ def solve_interface_gmres(p: Problem, a: Assembled, tol: float = 1e-14) -> np.nd
     assembled interface Jacobian), an alternative route to the same fixed
     point used as a cross-check of the Aitken iteration."""
     S_ff, S_pm, to_mono = _subsolvers(p, a)
-    nx = a.layout.nx
+    nx = a.layout.n_gamma
 
     def R(v):
         return S_pm(S_ff(v)[0])[0] - v

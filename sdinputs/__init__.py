@@ -77,6 +77,9 @@ class Problem:
     q_pm: Optional[np.ndarray] = None
     dt: float = 0.0                          # backward-Euler step, 0 = stationary
     bj_full: bool = False                    # slip with the porous tangential velocity
+    # ---- porous block narrower than the free flow (2-D) ----
+    nx_pm: int = 0                           # porous columns (0 = nx)
+    pm_i0: int = 0                           # first free-flow column over the block
     # ---- third dimension (nz = 0: the 2-D problem above) ----
     nz: int = 0                              # spanwise cells (z), both subdomains
     Lz: float = 1.0
@@ -495,6 +498,29 @@ def channel3d_problem(nx: int, ny: int, nz: int, ny_pm: Optional[int] = None, *,
     S, Z = np.meshgrid(s, z, indexing="ij")
     p.ff_left_n = 16.0 * U * S * (H_ff - S) * Z * (Lz - Z) / (H_ff * H_ff * Lz * Lz)
     return p
+
+
+def paper_setup_problem(n: int, p_in: float = 0.0, *, K: float = 1e-6, mu: float = 1e-3,
+                        alpha: float = 1.0, dt: float = 2e5) -> Problem:
+    """The geometry of the paper's experiments (Sec. 5): a 3 x 1 free-flow
+    channel [0,3] x [1,2] over a 1 x 1 porous block [1,2] x [0,1] under its
+    middle third, n x n cells per unit square; pressure p_in on the left and 0
+    on the right of the channel (traction data: the normal momentum flux equals
+    the pressure, no tangential traction), no-slip top and bottom walls beside
+    the block, p = 0 at the bottom of the block and no flow through its sides;
+    constant K; one backward-Euler step of dt."""
+    p = Problem(nx=3 * n, ny=n, ny_pm=n, Lx=3.0, H_ff=1.0, H_pm=1.0, mu=mu, alpha_bj=alpha,
+                K=np.full((n, n), K), ff_left=BC_TRACTION, ff_right=BC_TRACTION,
+                ff_top=BC_VELOCITY, pm_left=BC_NOFLOW, pm_right=BC_NOFLOW,
+                pm_bottom=BC_PRESSURE, nx_pm=n, pm_i0=n, dt=dt)
+    p.ff_left_n = np.full(n, float(p_in))
+    return p
+
+
+def paper_inflow_pressure(t: float, t_end: float = 50e5, dp_max: float = 1e-9) -> float:
+    """Half-cosine pressure difference rising from 0 at t = 0 to dp_max at
+    t_end: dp_max (1 - cos(pi t / t_end)) / 2."""
+    return dp_max * 0.5 * (1.0 - math.cos(math.pi * t / t_end))
 
 
 # Named workloads (cells per subdomain) ---------------------------------------

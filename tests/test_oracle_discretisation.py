@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 import scipy.sparse as sp
 
-from sdinputs import (MMS, channel_problem, ff_cell_xy, mms_problem, pm_cell_xy,
+from sdinputs import (MMS, channel_problem, ff_cell_xy, mms_problem, paper_setup_problem, pm_cell_xy,
                       u_face_xy, v_face_xy)
 from oracle.assemble import all_faces_dof, assemble, split_solution
 from oracle.direct import refined_solve, solve
@@ -337,3 +337,82 @@ def test_full_bj_couples_only_the_first_row_u_faces_to_the_top_cells():
     assert set(rows) == {L.u(i, 0) for i in range(1, L.nu_x + 1) if i <= p.nx - 1}
     assert set(cols) <= {L.q(i, p.ny_pm - 1) for i in range(p.nx)}
     assert np.allclose(np.asarray(d.tocsr().sum(axis=1)).ravel()[rows], 0.0, atol=1e-15)
+
+
+# ---- traction inflow and a porous block narrower than the free flow ----
+
+def _mms_errors_left_traction(n):
+    p, m = mms_problem(n, n // 2)
+    yc = p.y_gamma + (np.arange(p.ny) + 0.5) * p.dy
+    yv = p.y_gamma + np.arange(p.ny + 1) * p.dy
+    p.ff_left = "traction"
+    p.ff_left_n = m.flux_n(0.0, yc)          # n.(pI - tau)n, n = (-1, 0)
+    p.ff_left_t = -m.flux_t(0.0, yv)         # t.(pI - tau)n, n = (-1, 0)
+    a = assemble(p)
+    x = solve(a.A, a.b)
+    u, v, pp, q = split_solution(x, a.layout)
+    xu, yu = u_face_xy(p)
+    xv, yv2 = v_face_xy(p)
+    xc, yc2 = ff_cell_xy(p)
+    xq, yq = pm_cell_xy(p)
+    return np.array([np.abs(u - m.u(xu, yu)).max(), np.abs(v - m.v(xv, yv2)[:-1, :]).max(),
+                     np.abs(pp - m.p(xc, yc2)).max(), np.abs(q - m.P(xq, yq)).max()])
+
+
+def test_traction_on_both_sides_converges():
+    """Traction data on the left as well (every u face an unknown): the
+    manufactured solution converges at the stationary order."""
+    ns = [32, 64, 128]
+    errs = np.array([_mms_errors_left_traction(n) for n in ns])
+    assert np.all(np.diff(errs, axis=0) < 0)
+    slope = -np.polyfit(np.log2(ns), np.log2(errs), 1)[0]
+    assert np.all(slope >= 0.85), slope
+
+
+def test_narrow_block_tends_to_a_walled_channel():
+    """With K -> 0 the interface closes (no slip, no normal flux): the
+    channel over a narrow block tends to the same channel over a full-width
+    block, since BJS with K -> 0 is the no-slip wall closure used beside the
+    block."""
+    from sdinputs import BC_PRESSURE
+    n = 12
+    outs = []
+    for nx_pm, i0 in ((n, n), (3 * n, 0)):
+        p = paper_setup_problem(n, p_in=1.0, K=1e-16, dt=0.0)
+        p.nx_pm, p.pm_i0 = nx_pm, i0
+        p.K = np.full((n, nx_pm), 1e-16)
+        a = assemble(p)
+        x = refined_solve(a.A, a.b)
+        u, v, pp, q = split_solution(x, a.layout)
+        outs.append((u, v, pp))
+    for f0, f1 in zip(outs[0], outs[1]):
+        assert np.abs(f0 - f1).max() <= 1e-6 * np.abs(f1).max()
+
+
+def test_narrow_block_mass_balance():
+    n = 16
+    p = paper_setup_problem(n, p_in=1e-9, dt=0.0)
+    a = assemble(p)
+    x = refined_solve(a.A, a.b)
+    L = a.layout
+    u, v, pp, q = split_solution(x, L)
+    dx, dy = p.Lx / p.nx, p.H_ff / p.ny
+    vf = np.concatenate([v, np.zeros((1, p.nx))], axis=0)
+    div = (u[:, 1:] - u[:, :-1]) * dy + (vf[1:] - vf[:-1]) * dx
+    inflow = float(np.sum(u[:, 0]) * dy)
+    assert inflow > 0
+    assert np.abs(div).max() <= 1e-10 * abs(inflow)
+    # what enters on the left leaves on the right or through the block
+    outflow = float(np.sum(u[:, -1]) * dy)
+    into_block = float(-np.sum(v[0, L.i0:L.i0 + L.nx_pm]) * dx)
+    assert abs(inflow - outflow - into_block) <= 1e-10 * abs(inflow)
+    assert np.all(v[0, :L.i0] == 0.0) and np.all(v[0, L.i0 + L.nx_pm:] == 0.0)
+
+
+def test_dn_narrow_block_equals_monolithic():
+    p = paper_setup_problem(8, p_in=1e-9, dt=0.0)
+    a = assemble(p)
+    xs = refined_solve(a.A, a.b)
+    r = solve_dn(p, a, accel="iqn-ils", eps=1e-12)
+    assert r.converged
+    assert np.linalg.norm(r.x - xs) <= 1e-9 * np.linalg.norm(xs)
