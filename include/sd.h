@@ -78,6 +78,9 @@ typedef struct {
   double Lx, H_ff, H_pm;      /* extents; Gamma at y = H_pm                    */
   int nz;                     /* spanwise cells (z); 0 = the 2-D problem       */
   double Lz;                  /* spanwise extent (3-D only)                    */
+  int nx_pm;                  /* 2-D: porous columns (0 = nx), a block under   */
+  int pm_i0;                  /* free-flow columns pm_i0..pm_i0+nx_pm-1; the
+                                 free-flow bottom beside it is a no-slip wall  */
 } sd_grid;
 
 typedef struct {
@@ -94,11 +97,15 @@ typedef struct {
 typedef enum { SD_BC_VELOCITY = 0, SD_BC_TRACTION = 1, SD_BC_PRESSURE = 2,
                SD_BC_NOFLOW = 3 } sd_bc_type;
 
-/* Boundary conditions.  Free-flow left and top: SD_BC_VELOCITY; right:
- * SD_BC_VELOCITY or SD_BC_TRACTION; porous left/right/bottom (and back/front
- * in 3-D): SD_BC_PRESSURE or SD_BC_NOFLOW.  Data arrays may be NULL (zero).
+/* Boundary conditions.  Free-flow top: SD_BC_VELOCITY; left and right:
+ * SD_BC_VELOCITY or SD_BC_TRACTION (2-D; a pressure-driven inlet or outlet is
+ * a traction boundary whose normal datum is the pressure; 3-D: left
+ * SD_BC_VELOCITY); porous left/right/bottom (and back/front in 3-D):
+ * SD_BC_PRESSURE or SD_BC_NOFLOW.  Data arrays may be NULL (zero).  With a
+ * narrow porous block (nx_pm < nx) the porous arrays have nx_pm columns.
  * 2-D shapes:
- *   ff_left_n [ny] u at x=0;  ff_left_t [ny+1] v on the left wall at y_G + j dy
+ *   ff_left_n [ny] u (velocity) or n.(pI - tau)n (traction) at x = 0
+ *   ff_left_t [ny+1] v (velocity) or t.(pI - tau)n (traction), y_G + j dy
  *   ff_right_n [ny]  u (velocity) or n.(pI - tau)n (traction) at x = Lx
  *   ff_right_t [ny+1] v (velocity) or t.(pI - tau)n (traction), y_G + j dy
  *   ff_top_t [nx+1] u on the top wall at x = i dx; ff_top_n [nx] v on the top

@@ -229,8 +229,8 @@ static void step_rhs_impl(sd_solver* s, const double* d_b, const double* d_x, do
   if (!s->s->on_device) throw sd::Error(SD_E_INVALID, "solver has no device data");
   if (!d_x || !d_out) throw sd::Error(SD_E_INVALID, "NULL device vector");
   const sd::Layout& L = hp.L;
-  sd::launch_step_rhs(d_b ? d_b : s->s->b_dev, d_x, d_out, hp.mass, (int)L.N, L.nux, L.nx,
-                      (int)L.off_v, L.nx * L.nzc(), (int)L.off_w, (int)L.off_p, st);
+  sd::launch_step_rhs(d_b ? d_b : s->s->b_dev, d_x, d_out, hp.mass, (int)L.N, L.nux, L.i_first,
+                      L.nx, (int)L.off_v, (int)L.n_gamma(), (int)L.off_w, (int)L.off_p, st);
   SD_HIP(hipGetLastError());
 }
 

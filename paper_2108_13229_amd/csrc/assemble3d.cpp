@@ -44,6 +44,8 @@ void assemble_host_3d(const sd_grid* g, const sd_physics* ph, const sd_bcs* bcs,
   const int nx = g->nx, ny = g->ny, nyp = g->ny_pm, nz = g->nz;
   if (nx < 2 || ny < 2 || nyp < 1 || nz < 1)
     throw Error(SD_E_INVALID, "need nx >= 2, ny >= 2, ny_pm >= 1, nz >= 1");
+  if ((g->nx_pm != 0 && g->nx_pm != nx) || g->pm_i0 != 0)
+    throw Error(SD_E_INVALID, "3-D: the porous block spans the free flow (nx_pm = 0, pm_i0 = 0)");
   if (!finite_pos3(g->Lx) || !finite_pos3(g->H_ff) || !finite_pos3(g->H_pm) ||
       !finite_pos3(g->Lz))
     throw Error(SD_E_INVALID, "extents must be finite and positive");

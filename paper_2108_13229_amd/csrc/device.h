@@ -172,10 +172,11 @@ template <typename T>
 void launch_fill(T* a, T v, int n, hipStream_t s);
 
 // Backward-Euler right-hand side: out = b + m x on the velocity rows with a
-// time derivative (u rows r < off_v with r % nux + 1 <= nx - 1, v rows
-// off_v + v_skip <= r < off_w, w rows off_w <= r < off_p), b elsewhere; no
-// fused multiply-add.
+// time derivative (u rows r < off_v with 1 <= r % nux + ifirst <= nx - 1, v
+// rows off_v + v_skip <= r < off_w, w rows off_w <= r < off_p), b elsewhere;
+// no fused multiply-add.
 void launch_step_rhs(const double* b, const double* x, double* out, double m, int n, int nux,
-                     int nx, int off_v, int v_skip, int off_w, int off_p, hipStream_t s);
+                     int ifirst, int nx, int off_v, int v_skip, int off_w, int off_p,
+                     hipStream_t s);
 
 }  // namespace sd

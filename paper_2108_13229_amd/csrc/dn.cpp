@@ -115,8 +115,7 @@ void DNSolver::build(const HostProblem& P, const sd_solver_opts* o, const sd_all
                      hipStream_t s) {
   mono = &P;
   const Layout& L = P.L;
-  const int nzc = L.nzc();
-  nG = (int64_t)L.nx * nzc;
+  nG = L.n_gamma();
   g0 = L.off_v;
   off_q = L.off_q;
   N = L.N;
@@ -170,7 +169,7 @@ void DNSolver::build(const HostProblem& P, const sd_solver_opts* o, const sd_all
   pm.L.N = Npm;
   pm.A.n_rows = pm.A.n_cols = Npm;
   pm.A.rowptr.assign(1, 0);
-  pm_top = (int64_t)(L.nyp - 1) * nzc * L.nx;
+  pm_top = (int64_t)(L.nyp - 1) * nG;       // top porous layer, in interface order
   for (int64_t r = off_q; r < N; ++r) {
     for (int64_t k = P.A.rowptr[r]; k < P.A.rowptr[r + 1]; ++k) {
       const int64_t c = P.A.col[k];
@@ -191,8 +190,8 @@ void DNSolver::build(const HostProblem& P, const sd_solver_opts* o, const sd_all
     for (int64_t k = pm.A.rowptr[rr]; k < pm.A.rowptr[rr + 1]; ++k)
       if (pm.A.col[k] == rr) pm.A.val[k] = pm.A.val[k] + TB[(size_t)g];
   }
-  ff_p0 = ff.L.off_p;      // p(., 0) rows of the free-flow subsystem
-  ff_v1 = ff.L.off_v;      // v(., 1) rows
+  ff_p0 = ff.L.off_p + L.i0;   // p(., 0) over the block in the free-flow subsystem
+  ff_v1 = ff.L.off_v + L.i0;   // v(., 1) over the block
   // ---- sub-solvers and device buffers
   sd_solver_opts so = *o;
   if (so.schur == SD_SCHUR_CC) so.schur = SD_SCHUR_MASS;

@@ -1058,19 +1058,20 @@ __global__ __launch_bounds__(kBlock) void k_fill(T* __restrict__ a, T v, int n) 
 
 // Right-hand side of one backward-Euler step: out = b + m x on the rows whose
 // momentum balance has a time derivative (u faces i = 1..nx-1: rows
-// r < off_v with r % nux + 1 <= nx - 1; v faces off the interface: rows
+// r < off_v with 1 <= r % nux + ifirst <= nx - 1; v faces off the interface: rows
 // off_v + v_skip .. off_w - 1, v_skip = the interface faces; every w face:
 // rows off_w .. off_p - 1), b on the others.  One rounded product and one
 // rounded sum per row, never fused, so the result is reproducible bit for
 // bit.  out may alias b or x (each thread reads its row before writing it).
 __global__ __launch_bounds__(kBlock) void k_step_rhs(const double* b, const double* x,
                                                      double* out, double m, int n, int nux,
-                                                     int nx, int off_v, int v_skip, int off_w,
-                                                     int off_p) {
+                                                     int ifirst, int nx, int off_v, int v_skip,
+                                                     int off_w, int off_p) {
 #pragma clang fp contract(off)
   const int r = blockIdx.x * kBlock + threadIdx.x;
   if (r >= n) return;
-  const bool has = r < off_v   ? (r % nux) + 1 <= nx - 1
+  const int iu = r % nux + ifirst;   // face index of a u row
+  const bool has = r < off_v   ? (iu >= 1 && iu <= nx - 1)
                    : r < off_w ? r >= off_v + v_skip
                                : r < off_p;
   const double br = b[r];
@@ -1367,10 +1368,11 @@ void launch_fill(T* a, T v, int n, hipStream_t s) {
 }
 
 void launch_step_rhs(const double* b, const double* x, double* out, double m, int n, int nux,
-                     int nx, int off_v, int v_skip, int off_w, int off_p, hipStream_t s) {
+                     int ifirst, int nx, int off_v, int v_skip, int off_w, int off_p,
+                     hipStream_t s) {
   if (n <= 0) return;
-  k_step_rhs<<<blocks_for(n), kBlock, 0, s>>>(b, x, out, m, n, nux, nx, off_v, v_skip, off_w,
-                                              off_p);
+  k_step_rhs<<<blocks_for(n), kBlock, 0, s>>>(b, x, out, m, n, nux, ifirst, nx, off_v, v_skip,
+                                              off_w, off_p);
 }
 
 // ------------------------------------------------------- instantiations

@@ -29,20 +29,32 @@ struct HostCSR {
 // Unknown numbering of the pressure-velocity block form.
 // 2-D: u, v, p, q; 3-D (nz > 0): u, v, w, p, q with (row j, layer k,
 // column i) order, i fastest.  In 2-D off_w = off_p (no w block).
+// 2-D with a porous block of nx_pm columns under free-flow columns
+// i0..i0+nx_pm-1: the interface v faces come first in the v block, then rows
+// j = 1..ny-1; u faces start at i_first (0 with a traction left boundary).
 struct Layout {
   int nx = 0, ny = 0, nyp = 0, nux = 0, nz = 0;
+  int nx_pm = 0, i0 = 0, i_first = 1;
   int64_t off_v = 0, off_w = 0, off_p = 0, off_q = 0, N = 0;
   int nzc() const { return nz > 0 ? nz : 1; }
-  // rows with a time derivative: u faces i <= nx-1, v faces j >= 1, all w faces
+  // interface faces: the porous top layer under the free flow
+  int64_t n_gamma() const { return nz > 0 ? (int64_t)nx * nz : (int64_t)(nx_pm > 0 ? nx_pm : nx); }
+  // rows with a time derivative: interior u faces (1..nx-1), v faces off the
+  // interface, all w faces
   bool has_mass(int64_t r) const {
-    if (r < off_v) return (int)(r % nux) + 1 <= nx - 1;
-    if (r < off_w) return r >= off_v + (int64_t)nx * nzc();
+    if (r < off_v) {
+      const int i = (int)(r % nux) + i_first;
+      return i >= 1 && i <= nx - 1;
+    }
+    if (r < off_w) return r >= off_v + n_gamma();
     return r < off_p;
   }
-  int64_t u(int i, int j) const { return (int64_t)j * nux + (i - 1); }
-  int64_t v(int i, int j) const { return off_v + (int64_t)j * nx + i; }
+  int64_t u(int i, int j) const { return (int64_t)j * nux + (i - i_first); }
+  int64_t v(int i, int j) const {
+    return j == 0 ? off_v + (i - i0) : off_v + n_gamma() + (int64_t)(j - 1) * nx + i;
+  }
   int64_t p(int i, int j) const { return off_p + (int64_t)j * nx + i; }
-  int64_t q(int i, int k) const { return off_q + (int64_t)k * nx + i; }
+  int64_t q(int i, int k) const { return off_q + (int64_t)k * (nx_pm > 0 ? nx_pm : nx) + i; }
   int64_t u3(int i, int j, int k) const { return ((int64_t)j * nz + k) * nux + (i - 1); }
   int64_t v3(int i, int j, int k) const { return off_v + ((int64_t)j * nz + k) * nx + i; }
   int64_t w3(int i, int j, int k) const {

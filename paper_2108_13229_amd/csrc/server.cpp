@@ -329,11 +329,13 @@ int sd_submit(sd_server* sv, const sd_request* req, uint64_t* ticket) {
   r->bcs.ff_front_u = r->bcs.ff_front_v = r->bcs.ff_front_n = nullptr;
   r->bcs.pm_back_p = r->bcs.pm_front_p = nullptr;
   const int64_t nx = g.nx, ny = g.ny, nyp = g.ny_pm;
-  r->K.assign(req->K, req->K + nx * nyp);
+  const int64_t npm = g.nx_pm > 0 ? g.nx_pm : nx;
+  if (g.nx_pm < 0 || g.pm_i0 < 0 || g.pm_i0 + npm > nx) return SD_E_INVALID;
+  r->K.assign(req->K, req->K + npm * nyp);
   const double* src[9] = {req->bcs.ff_left_n, req->bcs.ff_left_t, req->bcs.ff_right_n,
                           req->bcs.ff_right_t, req->bcs.ff_top_t, req->bcs.ff_top_n,
                           req->bcs.pm_left_p, req->bcs.pm_right_p, req->bcs.pm_bottom_p};
-  const int64_t len[9] = {ny, ny + 1, ny, ny + 1, nx + 1, nx, nyp, nyp, nx};
+  const int64_t len[9] = {ny, ny + 1, ny, ny + 1, nx + 1, nx, nyp, nyp, npm};
   const double** dst[9] = {&r->bcs.ff_left_n, &r->bcs.ff_left_t, &r->bcs.ff_right_n,
                            &r->bcs.ff_right_t, &r->bcs.ff_top_t, &r->bcs.ff_top_n,
                            &r->bcs.pm_left_p, &r->bcs.pm_right_p, &r->bcs.pm_bottom_p};
@@ -347,7 +349,7 @@ int sd_submit(sd_server* sv, const sd_request* req, uint64_t* ticket) {
   }
   r->forcing.f_w = nullptr;
   const double* fs[3] = {req->forcing.f_u, req->forcing.f_v, req->forcing.q_pm};
-  const int64_t fl[3] = {ny * (nx + 1), (ny + 1) * nx, nyp * nx};
+  const int64_t fl[3] = {ny * (nx + 1), (ny + 1) * nx, nyp * npm};
   const double** fd[3] = {&r->forcing.f_u, &r->forcing.f_v, &r->forcing.q_pm};
   for (int k = 0; k < 3; ++k) {
     if (fs[k]) {

@@ -33,7 +33,7 @@ _dp = C.POINTER(C.c_double)
 class Grid(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("ny_pm", C.c_int),
                 ("Lx", C.c_double), ("H_ff", C.c_double), ("H_pm", C.c_double),
-                ("nz", C.c_int), ("Lz", C.c_double)]
+                ("nz", C.c_int), ("Lz", C.c_double), ("nx_pm", C.c_int), ("pm_i0", C.c_int)]
 
 
 class Physics(C.Structure):
@@ -203,7 +203,8 @@ def _ptr(a, keep):
 def _marshal(p, keep):
     nz = int(getattr(p, "nz", 0))
     g = Grid(int(p.nx), int(p.ny), int(p.ny_pm), float(p.Lx), float(p.H_ff), float(p.H_pm),
-             nz, float(getattr(p, "Lz", 1.0)))
+             nz, float(getattr(p, "Lz", 1.0)), int(getattr(p, "nx_pm", 0)),
+             int(getattr(p, "pm_i0", 0)))
     ph = Physics(float(p.mu), float(p.alpha_bj), float(getattr(p, "dt", 0.0)),
                  int(bool(getattr(p, "bj_full", False))))
     b = Bcs(BC[p.ff_left], BC[p.ff_right], BC[p.ff_top], BC[p.pm_left], BC[p.pm_right],

@@ -45,9 +45,20 @@ def _cases():
     p_vel_tr.dt = 3e-4
     p_bj = channel_problem(30, 14, 9, seed=6)
     p_bj.bj_full = True
+    from sdinputs import paper_setup_problem
+    p_paper = paper_setup_problem(6, p_in=1e-9)                   # narrow block, transient
+    p_lt = mms_problem(20, 10)[0]
+    p_lt.ff_left = "traction"
+    p_lt.ff_left_n = np.linspace(1.0, 2.0, 10)
+    p_lt.ff_left_t = np.linspace(-0.1, 0.1, 11)
+    p_narrow = channel_problem(24, 8, 6, seed=7)
+    p_narrow.nx_pm, p_narrow.pm_i0 = 10, 5
+    p_narrow.K = p_narrow.K[:, :10].copy()
+    p_narrow.pm_left, p_narrow.pm_left_p = "pressure", np.linspace(0.0, 1.0, 6)
+    p_narrow.bj_full = True
     return [mms_problem(32, 16)[0], mms_problem(24, 12, 9, K=3e-3, mu=0.5, alpha=0.7)[0],
             channel_problem(64, 32, seed=1), channel_problem(45, 22, 17, seed=5), p_vel, p_mixbc,
-            p_tr, p_vel_tr, mms_problem(20, 10, bj_full=True)[0], p_bj]
+            p_tr, p_vel_tr, mms_problem(20, 10, bj_full=True)[0], p_bj, p_paper, p_lt, p_narrow]
 
 
 @pytest.mark.parametrize("p", _cases())
@@ -64,7 +75,7 @@ def test_host_assembly_bit_exact(p):
 
 @pytest.mark.parametrize("amg_kind,mis", [("smoothed", 2), ("plain", 1), ("smoothed", 1),
                                           ("plain", 2)])
-@pytest.mark.parametrize("pi", [0, 2, 3, 6])
+@pytest.mark.parametrize("pi", [0, 2, 3, 6, 10, 12])
 def test_host_amg_bit_exact(amg_kind, mis, pi):
     p = _cases()[pi]
     P = sd.Problem(p, device=False)

@@ -104,3 +104,26 @@ def test_dn_c1_matches_monolithic_gpu_solve():
     off = P.block_off
     for lo, hi in ((off[0], off[2]), (off[2], off[3]), (off[3], off[4])):
         assert np.linalg.norm(x[lo:hi] - xm[lo:hi]) <= 1e-7 * np.linalg.norm(xm[lo:hi])
+
+
+def test_paper_geometry_monolithic_and_partitioned():
+    """The geometry of the paper's experiments (3 x 1 channel over a 1 x 1
+    block, pressure-driven): the monolithic GPU solve and the GPU coupling
+    iteration both reach the direct solution; the coupling takes the
+    oracle's number of IQN-ILS iterations."""
+    from sdinputs import paper_setup_problem
+    from oracle import krylov, precond
+    p = paper_setup_problem(16, p_in=1e-9, dt=2e5)
+    a = assemble(p)
+    xs = refined_solve(a.A, a.b)
+    P = sd.Problem(p, device=True)
+    S = sd.Solver(P, tol=1e-10, restart=60)
+    ref = krylov.fgmres(a.A, a.b, precond.build(p, a, "BGS"), tol=1e-10, m=60)
+    x, st, rc = S.solve()
+    assert rc == sd.SD_OK and abs(st["iters"] - ref.iters) <= 1
+    assert np.linalg.norm(_host(x) - xs) <= 1e-7 * np.linalg.norm(xs)
+    dn_ref = solve_dn(p, a, eps=1e-9, accel="iqn-ils")
+    D = sd.Partitioned(P, tol=1e-13, restart=60)
+    x, st, rc = D.solve(accel="iqn-ils", eps=1e-9)
+    assert rc == sd.SD_OK and abs(st["iters"] - dn_ref.iters) <= 2, (st, dn_ref.iters)
+    assert np.linalg.norm(_host(x) - xs) <= 1e-7 * np.linalg.norm(xs)

@@ -44,7 +44,13 @@ def _channel_tr():
     return p
 
 
-CASES = {"channel96_dt0.05": _channel_tr, "ragged_velocity_right": _channel_vel_right}
+def _paper_setup():
+    from sdinputs import paper_setup_problem
+    return paper_setup_problem(12, p_in=1e-9, dt=0.05)
+
+
+CASES = {"channel96_dt0.05": _channel_tr, "ragged_velocity_right": _channel_vel_right,
+         "paper_setup_traction_inflow": _paper_setup}
 
 
 @pytest.mark.parametrize("name", list(CASES))
