@@ -16,12 +16,13 @@ the C1 channel as a transient flow started from rest, 20 backward-Euler
 steps of dt = 0.1 with the hierarchies set up once and every step
 warm-started from the previous state (Cahouet-Chabard middle block); one
 step = one time step.  --config C4: the same on a 3-D channel of
-96 x 48 x 96 cells per subdomain (N = 2,207,232).  Inputs are
+96 x 48 x 96 cells per subdomain (N = 2,207,232).  --config P1: the setup of
+the paper's experiments replayed with the solvers built here.  Inputs are
 synthetic and seeded.  With the CPU leg on, the oracle also provides an FP64
 reference solution (its FGMRES to relative residual 1e-12) against which the
 per-block errors of every GPU solution are reported.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config C1|C2|T1|C4] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config C1|C2|T1|C4|P1] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -53,7 +54,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="C1", choices=["C1", "C2", "T1", "C4"])
+    ap.add_argument("--config", default="C1", choices=["C1", "C2", "T1", "C4", "P1"])
+    ap.add_argument("--paper-n", type=int, default=256,
+                    help="P1: cells per unit length of the paper's geometry")
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the CPU oracle leg (baseline timing and reference solution)")
     ap.add_argument("--no-mixed", action="store_true")
@@ -382,6 +385,76 @@ def variants(sd, args, p):
     print(json.dumps(out))
 
 
+def paper_replay(sd, args):
+    """The setup of the paper's experiments (Sec. 5): a 3 x 1 channel over a
+    1 x 1 porous block under its middle third, n x n cells per unit square,
+    K = 1e-6, alpha_BJ = 1, viscosity 1e-3, p = 0 under the block, the
+    channel driven by a half-cosine pressure difference rising to 1e-9 over
+    t_end = 5e6 s, 25 backward-Euler steps of 2e5 s.  Each solver of the
+    paper's comparison that is built here marches the 25 steps with its
+    set-up done once: monolithic FGMRES with P^pv_BGS (mu M_p^-1 middle
+    block) and with P^td_BGS(Uzawa, AMG), and the partitioned
+    Dirichlet-Neumann coupling with IQN-ILS (sub-solves to 1e-13, interface
+    tolerance 1e-8).  Reported: seconds for the 25 steps, iterations, and
+    the largest difference of each final state from the first solver's."""
+    import torch
+    from sdinputs import paper_inflow_pressure, paper_setup_problem
+    n = args.paper_n
+    dt, steps = 2e5, 25
+    P0 = sd.Problem(paper_setup_problem(n, 0.0, dt=dt), device=True)
+    P1 = sd.Problem(paper_setup_problem(n, 1.0, dt=dt), device=True)
+    b0 = torch.from_numpy(np.array(P0.csr()[3])).cuda()
+    db = torch.from_numpy(np.array(P1.csr()[3]) - np.array(P0.csr()[3])).cuda()
+    out = {"metric": "paper-setup replay: seconds for 25 backward-Euler steps",
+           "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"3x1 channel over 1x1 block, {n} cells per unit length "
+                                  f"(N={P0.N}), K=1e-6, half-cosine dp <= 1e-9, 25 steps of 2e5 s",
+                      "N": P0.N, "nnz": P0.nnz}, "solvers": {}}
+    finals = {}
+    runs = [("monolithic FGMRES + P^pv_BGS(AMG, mu Mp^-1, AMG)", "mono", dict(precond="BGS")),
+            ("monolithic FGMRES + P^td_BGS(Uzawa, AMG)", "mono", dict(precond="TD_BGS")),
+            ("partitioned DN + IQN-ILS", "dn", {})]
+    for name, kind, o in runs:
+        t0 = time.perf_counter()
+        if kind == "mono":
+            S = sd.Solver(P0, tol=1e-8, restart=args.restart, maxit=5000, **o)
+        else:
+            S = sd.Partitioned(P0, tol=1e-13, restart=args.restart)
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t0
+        x = torch.zeros(P0.N, dtype=torch.float64, device="cuda")
+        rhs = torch.empty_like(x)
+        its = []
+        helper = sd.Solver(P0, tol=1e-8, restart=1) if kind == "dn" else S
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(1, steps + 1):
+            bk = b0 + paper_inflow_pressure(k * dt) * db
+            helper.step_rhs(x, b_data=bk, out=rhs)
+            if kind == "mono":
+                x, st, rc = S.solve(b=rhs, x=x, use_x0=True)
+                its.append(st["iters"])
+            else:
+                x, st, rc = S.solve(accel="iqn-ils", eps=1e-8, maxit=1000, b=rhs, x=x)
+                its.append(st["iters"])
+            if rc != 0:
+                raise RuntimeError(f"{name}: step {k} failed ({rc})")
+        torch.cuda.synchronize()
+        span = time.perf_counter() - t0
+        finals[name] = x.cpu().numpy()
+        out["solvers"][name] = dict(seconds=span, ms_per_step=1e3 * span / steps,
+                                    setup_s=t_setup, iters_per_step=its)
+        S.close()
+        if kind == "dn":
+            helper.close()
+    ref = finals[runs[0][0]]
+    for name, x in finals.items():
+        out["solvers"][name]["max_diff_vs_first"] = float(np.abs(x - ref).max() / np.abs(ref).max())
+    out["value"] = out["solvers"][runs[0][0]]["seconds"]
+    print(json.dumps(out))
+
+
 def cpu_baseline(p, restart, timed=True):
     """The oracle's FP64 FGMRES with the same preconditioner, one solve,
     single-threaded (setup excluded; timed separately); then, with every
@@ -424,6 +497,9 @@ def main():
         sys.exit(1)
     if args.serving:
         serving(sd, args)
+        return
+    if args.config == "P1":
+        paper_replay(sd, args)
         return
     p = config_problem(args.config)
     if args.config in ("T1", "C4"):
