@@ -395,8 +395,12 @@ def paper_replay(sd, args):
     set-up done once: monolithic FGMRES with P^pv_BGS (mu M_p^-1 middle
     block) and with P^td_BGS(Uzawa, AMG), and the partitioned
     Dirichlet-Neumann coupling with IQN-ILS (sub-solves to 1e-13, interface
-    tolerance 1e-8).  Reported: seconds for the 25 steps, iterations, and
-    the largest difference of each final state from the first solver's."""
+    tolerance 1e-6: with K = 1e-6 the interface velocity is the small
+    difference q_top - sigma of two pressures, which the sub-solve accuracy
+    resolves to about 1e-7 at 256 cells per unit length).  Reported: seconds
+    for the 25 steps, iterations, steps whose solve did not meet its
+    tolerance, and the largest difference of each final state from the first
+    solver's."""
     import torch
     from sdinputs import paper_inflow_pressure, paper_setup_problem
     n = args.paper_n
@@ -427,6 +431,7 @@ def paper_replay(sd, args):
         # the march runs twice: the first pass captures the solver's graphs,
         # the second is timed
         for timed in (False, True):
+            failed = []
             x = torch.zeros(P0.N, dtype=torch.float64, device="cuda")
             rhs = torch.empty_like(x)
             its = []
@@ -438,15 +443,16 @@ def paper_replay(sd, args):
                 if kind == "mono":
                     x, st, rc = S.solve(b=rhs, x=x, use_x0=True)
                 else:
-                    x, st, rc = S.solve(accel="iqn-ils", eps=1e-8, maxit=1000, b=rhs, x=x)
+                    x, st, rc = S.solve(accel="iqn-ils", eps=1e-6, maxit=500, b=rhs, x=x)
                 its.append(st["iters"])
                 if rc != 0:
-                    raise RuntimeError(f"{name}: step {k} failed ({rc})")
+                    failed.append(k)
             torch.cuda.synchronize()
             span = time.perf_counter() - t0
         finals[name] = x.cpu().numpy()
         out["solvers"][name] = dict(seconds=span, ms_per_step=1e3 * span / steps,
-                                    setup_s=t_setup, iters_per_step=its)
+                                    setup_s=t_setup, iters_per_step=its,
+                                    steps_not_converged=failed)
         S.close()
         if kind == "dn":
             helper.close()
