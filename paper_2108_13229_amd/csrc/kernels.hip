@@ -36,15 +36,55 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <typename TM, typename TX>
+// M consecutive entries e, e + step, ... of a SELL row added to acc in
+// order; the M index/value loads and then the M gathers are all issued
+// before the first product.
+template <int M, typename TM, typename F>
+__device__ __forceinline__ void sell_chunk(const Sell<TM>& A, int e, int step, F f, TM& acc) {
+  int c[M];
+  TM v[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    c[i] = A.col[e + i * step];
+    v[i] = A.val[e + i * step];
+  }
+  TM x[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) x[i] = f(c[i]);
+#pragma unroll
+  for (int i = 0; i < M; ++i) acc += v[i] * x[i];
+}
+
+template <int M, typename TM, typename F>
+__device__ __forceinline__ void sell_tail(const Sell<TM>& A, int e, int cnt, int step, F f,
+                                          TM& acc) {
+  if constexpr (M > 0) {
+    if (cnt == M) sell_chunk<M>(A, e, step, f, acc);
+    else sell_tail<M - 1>(A, e, cnt, step, f, acc);
+  }
+}
+
+// The cnt entries e, e + step, ... of a SELL row, summed in that order: K at
+// a time, then one chunk of the cnt % K left, so a row of up to K entries
+// costs two dependent memory round trips (indices and values, then the
+// gathers) and no load is issued for an entry the row does not have.  cnt
+// is the same for all lanes of a slice, so the tail takes one branch.
+template <int K, typename TM, typename F>
+__device__ __forceinline__ TM sell_row(const Sell<TM>& A, int e, int cnt, int step, F f) {
+  TM acc = 0;
+  for (; cnt >= K; cnt -= K, e += K * step) sell_chunk<K>(A, e, step, f, acc);
+  sell_tail<K - 1>(A, e, cnt, step, f, acc);
+  return acc;
+}
+
+constexpr int kRowChunk = 6;   // entries of a SELL-64 row loaded at once
+
+template <int K = kRowChunk, typename TM, typename TX>
 __device__ __forceinline__ TM sell_dot(const Sell<TM>& A, const TX* __restrict__ x, int row) {
   const int s = row >> 6;
   const int beg = A.sptr[s] + (row & 63);
   const int end = A.sptr[s + 1];
-  TM acc = 0;
-#pragma unroll 4
-  for (int e = beg; e < end; e += 64) acc += A.val[e] * (TM)x[A.col[e]];
-  return acc;
+  return sell_row<K>(A, beg, (end - beg + 63) >> 6, 64, [&](int c) { return (TM)x[c]; });
 }
 
 __device__ __forceinline__ double scale_of(const double* s) { return s ? *s : 1.0; }
@@ -133,9 +173,8 @@ __device__ __forceinline__ TM row_sum(const Sell<TM>& A, int row, int sub, F f) 
     beg = A.sptr[sl];
     end = A.sptr[sl + 1];
   }
-  TM acc = 0;
-#pragma unroll 4
-  for (int e = beg + sub * C + r; e < end; e += 64) acc += A.val[e] * f(A.col[e]);
+  const int e0 = beg + sub * C + r;
+  TM acc = sell_row<LPR == 1 ? kRowChunk : 4>(A, e0, (end - e0 + 63) >> 6, 64, f);
 #pragma unroll
   for (int o = C; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
   return acc;
@@ -387,46 +426,22 @@ __global__ __launch_bounds__(kBlock) void k_add(const T* __restrict__ a, T* __re
 //            (the residual estimate trails the basis by one step).
 // In exact arithmetic a = 0 and the iterates are those of CGS2 FGMRES.  A
 // closing step (project without the product, update without row work)
-// completes the last column of a full cycle.  Layout: row-block x
-// vector-per-wavefront; a workgroup of 16 wavefronts owns a block of rows,
-// wavefront w handles basis vectors w, w+16, w+32, w+48 (one accumulator per
-// vector and lane), so every basis entry is read once, coalesced; row sums
-// across vectors go through LDS.
+// completes the last column of a full cycle.  Layout of the projection: a
+// workgroup of 8 wavefronts owns a block of rows; after the product (one
+// 64-row slice per wavefront and round, w and u_j kept in LDS) the basis
+// entries of the block are split evenly over the wavefronts as runs of
+// (vector, slice) units, so every basis entry is read once, coalesced, with
+// several loads in flight per wavefront.
 
-constexpr int kGsThreads = 1024;
+constexpr int kGsThreads = 512;
 constexpr int kGsWaves = kGsThreads / 64;
-constexpr int kGsVpw = kMaxBasis / kGsWaves;     // basis vectors per wavefront
-constexpr int kGsRound = 256;                     // rows per LDS round (4 per lane)
+constexpr int kProjChunk = 8;                     // basis slices loaded at once
+constexpr int kProjRowChunk = 6;                  // matrix entries per row loaded at once
+                                                  // (8 would spill at 64 VGPRs)
 constexpr int kSumStride = 2 * kMaxBasis + 4;
 
-// Rows ra and rb (slices of equal or different width) of a SELL-64 matrix
-// in one loop: two independent load chains per lane.
-template <typename TM, typename TX>
-__device__ __forceinline__ void sell_dot2(const Sell<TM>& A, const TX* __restrict__ x, int ra,
-                                          int rb, bool hb, TM& out_a, TM& out_b) {
-  int ea = A.sptr[ra >> 6] + (ra & 63);
-  const int enda = A.sptr[(ra >> 6) + 1];
-  int eb = 0, endb = 0;
-  if (hb) {
-    eb = A.sptr[rb >> 6] + (rb & 63);
-    endb = A.sptr[(rb >> 6) + 1];
-  }
-  TM aa = 0, ab = 0;
-#pragma unroll 2
-  for (; ea < enda && eb < endb; ea += 64, eb += 64) {
-    aa += A.val[ea] * (TM)x[A.col[ea]];
-    ab += A.val[eb] * (TM)x[A.col[eb]];
-  }
-#pragma unroll 4
-  for (; ea < enda; ea += 64) aa += A.val[ea] * (TM)x[A.col[ea]];
-#pragma unroll 4
-  for (; eb < endb; eb += 64) ab += A.val[eb] * (TM)x[A.col[eb]];
-  out_a = aa;
-  out_b = ab;
-}
-
 template <typename TM, typename TZ>
-__global__ __launch_bounds__(kGsThreads) void k_arn_project(Sell<TM> A, const TZ* __restrict__ z,
+__global__ __launch_bounds__(kGsThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_arn_project(Sell<TM> A, const TZ* __restrict__ z,
                                                             double* __restrict__ W,
                                                             const double* __restrict__ V,
                                                             int64_t ldv, int n, int j, int rpb,
@@ -437,7 +452,7 @@ __global__ __launch_bounds__(kGsThreads) void k_arn_project(Sell<TM> A, const TZ
   double* wt = sh;
   double* ut = sh + rpb;
   __shared__ double red3[kGsWaves][3];
-  __shared__ double red2[kGsWaves][2];
+  __shared__ double piece[2][kMaxBasis + kGsWaves];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r0 = blockIdx.x * rpb;
   const int ns = rpb / 64;                        // slices of the block (multiple of 16)
@@ -453,8 +468,8 @@ __global__ __launch_bounds__(kGsThreads) void k_arn_project(Sell<TM> A, const TZ
       ua = uj[ra];
       if (hb) ub = uj[rb];
       if (spmv) {
-        TM sa, sb;
-        sell_dot2(A, z, ra, rb, hb, sa, sb);
+        const TM sa = sell_dot<kProjRowChunk>(A, z, ra);
+        const TM sb = hb ? sell_dot<kProjRowChunk>(A, z, rb) : (TM)0;
         wa = (double)sa;
         W[ra] = wa;
         if (hb) {
@@ -474,75 +489,49 @@ __global__ __launch_bounds__(kGsThreads) void k_arn_project(Sell<TM> A, const TZ
     cww += wa * wa + wb * wb;
   }
   __syncthreads();
-  if (j >= kGsWaves) {
-    // wavefront w: basis vectors w, w+16, w+32, w+48 over all rows of the block
-    double aa[kGsVpw], ab[kGsVpw];
-#pragma unroll
-    for (int q = 0; q < kGsVpw; ++q) aa[q] = ab[q] = 0.0;
-    for (int base = 0; base < rpb; base += kGsRound) {
-#pragma unroll
-      for (int u4 = 0; u4 < kGsRound / 64; ++u4) {
-        const int lr = base + u4 * 64 + lane;
-        const int row = r0 + lr;
-        if (row < n) {
-          const double w = wt[lr], u = ut[lr];
-#pragma unroll
-          for (int q = 0; q < kGsVpw; ++q) {
-            const int k = wave + kGsWaves * q;
-            if (k < j) {
-              const double x = V[(size_t)k * ldv + row];
-              aa[q] += x * u;
-              ab[q] += x * w;
-            }
-          }
-        }
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < kGsVpw; ++q) {
-      const int k = wave + kGsWaves * q;
-      const double sa = wave_sum(aa[q]);
-      const double sb = wave_sum(ab[q]);
-      if (k < j && lane == 0) {
-        part[(size_t)(kGsRowA + k) * kGsMaxBlocks + blockIdx.x] = sa;
-        part[(size_t)(kGsRowB + k) * kGsMaxBlocks + blockIdx.x] = sb;
-      }
-    }
-  } else if (j > 0) {
-    // fewer vectors than wavefronts: g wavefronts per vector, each over every
-    // g-th slice; their sums are added in a fixed order
-    const int g = kGsWaves / j;
-    const int k = wave / g, p = wave - k * g;
-    double sa = 0.0, sb = 0.0;
-    if (k < j) {
+  if (j > 0) {
+    // The j x ns (vector, slice) units, vector-major, are cut into kGsWaves
+    // runs of equal length, one per wavefront, so every wavefront streams the
+    // same share of the basis whatever j is.  A run's sums over each vector
+    // it touches (a piece) go to LDS slot vector + wavefront, which no other
+    // piece shares; a vector's sum adds its pieces in wavefront order.
+    const int per = j * (ns / kGsWaves);
+    const int u0 = wave * per, u1 = u0 + per;
+    const int last = n - 1;
+    for (int k = u0 / ns; k * ns < u1; ++k) {
+      const int sb = max(u0 - k * ns, 0), se = min(u1 - k * ns, ns);
       const double* vk = V + (size_t)k * ldv;
-#pragma unroll 4
-      for (int sl = p; sl < ns; sl += g) {
-        const int lr = sl * 64 + lane;
-        const int row = r0 + lr;
-        if (row < n) {
-          const double x = vk[row];
-          sa += x * ut[lr];
-          sb += x * wt[lr];
+      double sa = 0.0, sw = 0.0;
+      for (int s = sb; s < se; s += kProjChunk) {
+        double x[kProjChunk];
+#pragma unroll
+        for (int i = 0; i < kProjChunk; ++i) {
+          const int si = min(s + i, se - 1);
+          x[i] = vk[min(r0 + si * 64 + lane, last)];   // rows past n: u, w are 0
+        }
+#pragma unroll
+        for (int i = 0; i < kProjChunk; ++i) {
+          const int li = min(s + i, se - 1) * 64 + lane;
+          const double ta = sa + x[i] * ut[li], tw = sw + x[i] * wt[li];
+          sa = s + i < se ? ta : sa;
+          sw = s + i < se ? tw : sw;
         }
       }
-    }
-    sa = wave_sum(sa);
-    sb = wave_sum(sb);
-    if (lane == 0) {
-      red2[wave][0] = sa;
-      red2[wave][1] = sb;
+      sa = wave_sum(sa);
+      sw = wave_sum(sw);
+      if (lane == 0) {
+        piece[0][k + wave] = sa;
+        piece[1][k + wave] = sw;
+      }
     }
     __syncthreads();
-    if ((int)threadIdx.x < j) {
-      const int kk = threadIdx.x;
-      double ta = 0.0, tb = 0.0;
-      for (int q = 0; q < g; ++q) {
-        ta += red2[kk * g + q][0];
-        tb += red2[kk * g + q][1];
-      }
-      part[(size_t)(kGsRowA + kk) * kGsMaxBlocks + blockIdx.x] = ta;
-      part[(size_t)(kGsRowB + kk) * kGsMaxBlocks + blockIdx.x] = tb;
+    if ((int)threadIdx.x < 2 * j) {
+      const int ab = (int)threadIdx.x >= j;
+      const int k = threadIdx.x - ab * j;
+      const int wf = (k * ns) / per, wl = ((k + 1) * ns - 1) / per;
+      double t = 0.0;
+      for (int w = wf; w <= wl; ++w) t += piece[ab][k + w];
+      part[(size_t)((ab ? kGsRowB : kGsRowA) + k) * kGsMaxBlocks + blockIdx.x] = t;
     }
   }
   cuu = wave_sum(cuu);
