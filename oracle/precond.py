@@ -27,6 +27,10 @@ block-Gauss-Seidel form with X = omega I, and P^td_BJ(P_A', P_D') =
 diag(P_A', P_D') keeps the v -> p coupling inside A' but drops the porous
 coupling C1' (y_pm = P_D' r_pm).
 
+Darcy sub-solve P_D': one AMG V-cycle on D~ (default), or the ILU(0)
+factorisation of D~ (forward and backward substitution, `oracle.ilu`), the
+Darcy preconditioner of Table 2's P^td(Uzawa, ILU(0)) rows.
+
 For the system of one backward-Euler step (mass |CV|/dt on the velocity
 diagonal) M_p / mu only describes the Schur complement of the viscous part:
 once sqrt(nu dt) is small against the domain, the mass term governs the
@@ -46,6 +50,7 @@ import numpy as np
 import scipy.sparse as sp
 
 from . import amg as amg_mod
+from . import ilu as ilu_mod
 from .assemble import Assembled
 
 SCHUR_IDENTITY = "identity"
@@ -53,6 +58,8 @@ SCHUR_MASS = "mass"
 SCHUR_CC = "cc"
 SCHUR_UZAWA = "uzawa"
 UZAWA_POWER_ITERS = 30
+DARCY_AMG = "amg"
+DARCY_ILU0 = "ilu0"
 
 
 @dataclasses.dataclass
@@ -60,20 +67,21 @@ class BlockPreconditioner:
     variant: str               # "BJ" or "BGS"
     schur: str
     hV: amg_mod.Hierarchy
-    hD: amg_mod.Hierarchy
+    hD: amg_mod.Hierarchy      # None when the Darcy block uses ILU(0)
     C: object                  # continuity rows x velocity columns
     C1: object                 # porous rows x velocity columns
     off: np.ndarray            # [0, off_v, off_p, off_q, N]
     xscale: float              # X = xscale * I (+ L_p^-1 with SCHUR_CC)
     dtype: type = np.float64
     hL: amg_mod.Hierarchy = None   # AMG hierarchy of L_p (SCHUR_CC only)
+    ilu: ilu_mod.ILU0 = None       # ILU(0) of D~ (DARCY_ILU0 only)
 
     def __post_init__(self):
         dt = self.dtype
         self._C = self.C.astype(dt)
         self._C1 = self.C1.astype(dt)
         self._mV = amg_mod.level_mats(self.hV, dt)
-        self._mD = amg_mod.level_mats(self.hD, dt)
+        self._mD = None if self.hD is None else amg_mod.level_mats(self.hD, dt)
         self._mL = None if self.hL is None else amg_mod.level_mats(self.hL, dt)
 
     def middle(self, t: np.ndarray) -> np.ndarray:
@@ -81,6 +89,11 @@ class BlockPreconditioner:
         if self.hL is not None:
             y = y + amg_mod.vcycle(self.hL, t, self.dtype, mats=self._mL)
         return y
+
+    def darcy(self, t: np.ndarray) -> np.ndarray:
+        if self.ilu is not None:
+            return self.ilu.solve(t).astype(self.dtype)
+        return amg_mod.vcycle(self.hD, t, self.dtype, mats=self._mD)
 
     def __call__(self, r: np.ndarray) -> np.ndarray:
         dt = self.dtype
@@ -90,13 +103,13 @@ class BlockPreconditioner:
         yv = amg_mod.vcycle(self.hV, rv, dt, mats=self._mV)
         if self.variant == "BJ":
             yp = self.middle(rp)
-            yq = amg_mod.vcycle(self.hD, rq, dt, mats=self._mD)
+            yq = self.darcy(rq)
         elif self.variant == "TD_BJ":
             yp = self.middle(rp - self._C @ yv)
-            yq = amg_mod.vcycle(self.hD, rq, dt, mats=self._mD)
+            yq = self.darcy(rq)
         elif self.variant in ("BGS", "TD_BGS"):
             yp = self.middle(rp - self._C @ yv)
-            yq = amg_mod.vcycle(self.hD, rq - self._C1 @ yv, dt, mats=self._mD)
+            yq = self.darcy(rq - self._C1 @ yv)
         else:
             raise ValueError(self.variant)
         return np.concatenate([yv, yp, yq])
@@ -171,12 +184,19 @@ def uzawa_relaxation(blk, hV, iters: int = UZAWA_POWER_ITERS) -> float:
 
 
 def build(p, a: Assembled, variant: str = "BGS", schur: str = SCHUR_MASS,
-          opts: amg_mod.AMGOptions | None = None, dtype=np.float64) -> BlockPreconditioner:
+          opts: amg_mod.AMGOptions | None = None, dtype=np.float64,
+          darcy: str = DARCY_AMG) -> BlockPreconditioner:
     opts = opts or amg_mod.AMGOptions()
     blk = a.blocks()
     hV = amg_mod.setup(blk["V"], velocity_components(a), False, opts)
     Dt = darcy_interface_block(blk)
-    hD = amg_mod.setup(Dt, np.zeros(Dt.shape[0], dtype=np.int32), False, opts)
+    hD, ilu = None, None
+    if darcy == DARCY_ILU0:
+        ilu = ilu_mod.ilu0(Dt)
+    elif darcy == DARCY_AMG:
+        hD = amg_mod.setup(Dt, np.zeros(Dt.shape[0], dtype=np.int32), False, opts)
+    else:
+        raise ValueError(darcy)
     vol = ((p.Lx / p.nx) * (p.H_ff / p.ny)) * p.dz     # dz = 1 in 2-D
     xscale = p.mu / vol if schur in (SCHUR_MASS, SCHUR_CC) else 1.0
     if variant in ("TD_BJ", "TD_BGS"):
@@ -188,7 +208,7 @@ def build(p, a: Assembled, variant: str = "BGS", schur: str = SCHUR_MASS,
         hL = amg_mod.setup(Lp, np.zeros(Lp.shape[0], dtype=np.int32), False, opts)
     return BlockPreconditioner(variant=variant, schur=schur, hV=hV, hD=hD,
                                C=blk["C"], C1=blk["C1"], off=a.layout.block_off,
-                               xscale=xscale, dtype=dtype, hL=hL)
+                               xscale=xscale, dtype=dtype, hL=hL, ilu=ilu)
 
 
 def exact_block_preconditioner(a: Assembled, variant: str, S_inv):
