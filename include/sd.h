@@ -194,6 +194,17 @@ enum { SD_SCHUR_IDENTITY = 0, SD_SCHUR_MASS = 1, SD_SCHUR_CC = 2 };
  * an FP32 product can support, and the FP64 restart residual refines. */
 enum { SD_PRECISION_FP64 = 0, SD_PRECISION_MIXED = 1, SD_PRECISION_MIXED32 = 2 };
 enum { SD_AMG_PLAIN = 0, SD_AMG_SMOOTHED = 1 };
+/* Darcy sub-solve P_D' of the block preconditioners: one AMG V-cycle on
+ * D~ (default), or ILU(0) of D~ (Meijerink & van der Vorst 1977), the Darcy
+ * preconditioner of the paper's P^td_BJ/BGS(Uzawa, ILU(0)) rows (Sec. 5
+ * solver setup, Table 2).  ILU(0) is factorised on the host at set-up
+ * (elimination in row order, entries outside the pattern of D~ dropped) and
+ * applied by level-scheduled forward and backward substitution in one
+ * workgroup.  Set-up fails with SD_E_INVALID if a row of D~ has more than 4
+ * entries on either side of its diagonal or a substitution has more than
+ * 4096 levels (a 2-D grid of nx x ny porous cells has nx + ny - 1), and
+ * with SD_E_BREAKDOWN on a zero pivot. */
+enum { SD_DARCY_AMG = 0, SD_DARCY_ILU0 = 1 };
 
 typedef struct {
   int krylov;        /* SD_KRYLOV_*                                            */
@@ -210,6 +221,7 @@ typedef struct {
   int nu_pre, nu_post; /* Jacobi sweeps, default 2 / 2                         */
   int coarse_max;    /* coarsest level size bound (dense inverse), default 2048 */
   int max_levels;    /* default 20                                             */
+  int darcy;         /* SD_DARCY_AMG (default) | SD_DARCY_ILU0                 */
 } sd_solver_opts;
 
 /* Fill opts with the defaults above. */
@@ -232,6 +244,16 @@ int sd_solver_level_csr(const sd_solver* s, int block, int level, int which,
                         const int32_t** col, const double** val);
 int sd_solver_level_agg(const sd_solver* s, int block, int level,
                         const int32_t** agg, int64_t* n);
+/* ILU(0) inspection (SD_DARCY_ILU0 only, SD_E_INVALID otherwise): the
+ * forward (lower != 0: the strict L part) or backward (the strict U part and
+ * diag = u_ii) substitution in level order.  lev[0..n_levels] are level
+ * pointers into the n positions; ord[q] is the Darcy-block row of position
+ * q; its off-diagonal entries occupy slots k = 0..3 at col[k*n + q],
+ * val[k*n + q] in ascending column order, padded with col -1 and val 0.
+ * Host views, valid until sd_solver_destroy; diag may be NULL. */
+int sd_solver_ilu(const sd_solver* s, int lower, int64_t* n, int* n_levels,
+                  const int32_t** lev, const int32_t** ord, const int32_t** col,
+                  const double** val, const double** diag);
 /* Dense row-major inverse of the coarsest operator of a block. */
 int sd_solver_coarse_inverse(const sd_solver* s, int block, const double** inv,
                              int64_t* n);

@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libsd.so")
 BUILD = os.path.join(HERE, "_build")
 
 HIP_SOURCES = ["kernels.hip"]
-CPP_SOURCES = ["assemble.cpp", "assemble3d.cpp", "amg_setup.cpp", "solver.cpp", "api.cpp", "dn.cpp", "server.cpp"]
+CPP_SOURCES = ["assemble.cpp", "assemble3d.cpp", "amg_setup.cpp", "ilu.cpp", "solver.cpp", "api.cpp", "dn.cpp", "server.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-I" + INCLUDE, "-I" + CSRC, "-Wall",
           "-Wno-unused-function"]

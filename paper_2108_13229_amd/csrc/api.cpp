@@ -78,6 +78,7 @@ void sd_solver_opts_default(sd_solver_opts* o) {
   o->nu_post = 2;
   o->coarse_max = 2048;
   o->max_levels = 20;
+  o->darcy = SD_DARCY_AMG;
 }
 
 static int assemble_impl(const sd_grid* grid, const sd_physics* phys, const sd_bcs* bcs,
@@ -187,6 +188,22 @@ int sd_solver_level_csr(const sd_solver* s, int block, int level, int which, int
   if (rowptr) *rowptr = M->rowptr.data();
   if (col) *col = M->col.data();
   if (val) *val = M->val.data();
+  return SD_OK;
+}
+
+int sd_solver_ilu(const sd_solver* s, int lower, int64_t* n, int* n_levels,
+                  const int32_t** lev, const int32_t** ord, const int32_t** col,
+                  const double** val, const double** diag) {
+  if (!s) return fail(SD_E_INVALID, "bad argument");
+  const sd::HostIlu& f = s->s->ilu;
+  if (f.n == 0) return fail(SD_E_INVALID, "the solver has no ILU(0) factors");
+  if (n) *n = f.n;
+  if (n_levels) *n_levels = (int)(lower ? f.lev_l.size() : f.lev_u.size()) - 1;
+  if (lev) *lev = lower ? f.lev_l.data() : f.lev_u.data();
+  if (ord) *ord = lower ? f.ord_l.data() : f.ord_u.data();
+  if (col) *col = lower ? f.col_l.data() : f.col_u.data();
+  if (val) *val = lower ? f.val_l.data() : f.val_u.data();
+  if (diag) *diag = lower ? nullptr : f.diag_u.data();
   return SD_OK;
 }
 

@@ -16,6 +16,8 @@ constexpr int kGsMaxBlocks = 1024;          // row blocks of the Gram-Schmidt ke
 // V^T u at kGsRowA, V^T w at kGsRowB, then u.u, u.w, w.w
 constexpr int kGsRowA = 0, kGsRowB = kMaxBasis, kGsRowC = 2 * kMaxBasis;
 constexpr int kGsPartRows = 2 * kMaxBasis + 3;
+constexpr int kIluWidth = 4;        // ILU(0): off-diagonal entries per triangle row
+constexpr int kIluMaxLevels = 4096; // ILU(0): levels per substitution
 
 // Sparse matrix on the device.  lpr == 1: sliced ELLPACK with 64-row slices
 // (one wavefront per slice); entry (r, k) of slice s lives at
@@ -31,6 +33,23 @@ struct Sell {
   int lpr = 1;
   int width = 0;   // > 0: every row padded to this width (SELL: slice s at
                    // 64 * width * s; CSR: row r at width * r), sptr not read
+};
+
+// ILU(0) factors in level order (see HostIlu): positions q of the forward
+// and the backward substitution, ELL slots k * n + q.
+template <typename T>
+struct IluDev {
+  int n = 0;
+  int nlev_l = 0, nlev_u = 0;
+  const int* lev_l = nullptr;
+  const int* lev_u = nullptr;
+  const int* ord_l = nullptr;
+  const int* ord_u = nullptr;
+  const int* col_l = nullptr;
+  const int* col_u = nullptr;
+  const T* val_l = nullptr;
+  const T* val_u = nullptr;
+  const T* diag_u = nullptr;
 };
 
 // Solver scalars resident in device memory.
@@ -99,6 +118,9 @@ template <typename T>
 void launch_prolong(const Sell<T>& P, const T* xc, T* x, const DevState* gate,
                     hipStream_t s);
 // xc = Ainv bc (FP64 dense)
+// z = U^-1 L^-1 r with the ILU(0) factors, one workgroup (z may not alias r)
+template <typename T>
+void launch_ilu0(const IluDev<T>& F, const T* r, T* z, const DevState* gate, hipStream_t s);
 template <typename T>
 void launch_coarse(const double* Ainv, int n, const T* bc, T* xc, const DevState* gate,
                    hipStream_t s);

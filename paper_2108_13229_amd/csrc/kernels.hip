@@ -347,6 +347,70 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Sell<T> P, const T* __restri
   if (rs.y == 0 && !stop) x[rs.x] += v;
 }
 
+constexpr int kIluThreads = 1024;
+
+// z = U^-1 L^-1 r with the ILU(0) factors of the Darcy block, in one
+// workgroup.  The rows of one level of a substitution depend only on rows of
+// earlier levels, so a level is one parallel step and a barrier orders the
+// levels (after it the workgroup sees its own global stores).  The forward
+// result y is kept in z and overwritten by the backward pass.  A position's
+// row index and slots are loaded at once, then the gathers; padded slots
+// (col -1) read z[0] and add nothing.
+template <typename T>
+__global__ __launch_bounds__(kIluThreads) void k_ilu0(IluDev<T> F, const T* __restrict__ r,
+                                                      T* z, const DevState* gate) {
+  __shared__ int lev[2][kIluMaxLevels + 1];
+  if (gate && gate->cycle_done) return;
+  const int t = threadIdx.x;
+  const size_t n = (size_t)F.n;
+  for (int l = t; l <= F.nlev_l; l += kIluThreads) lev[0][l] = F.lev_l[l];
+  for (int l = t; l <= F.nlev_u; l += kIluThreads) lev[1][l] = F.lev_u[l];
+  __syncthreads();
+  for (int lv = 0; lv < F.nlev_l; ++lv) {
+    const int q1 = lev[0][lv + 1];
+    for (int q = lev[0][lv] + t; q < q1; q += kIluThreads) {
+      const int i = F.ord_l[q];
+      int c[kIluWidth];
+      T v[kIluWidth];
+#pragma unroll
+      for (int k = 0; k < kIluWidth; ++k) {
+        c[k] = F.col_l[k * n + q];
+        v[k] = F.val_l[k * n + q];
+      }
+      T x[kIluWidth];
+#pragma unroll
+      for (int k = 0; k < kIluWidth; ++k) x[k] = z[max(c[k], 0)];
+      T acc = r[i];
+#pragma unroll
+      for (int k = 0; k < kIluWidth; ++k) acc = c[k] >= 0 ? acc - v[k] * x[k] : acc;
+      z[i] = acc;
+    }
+    __syncthreads();
+  }
+  for (int lv = 0; lv < F.nlev_u; ++lv) {
+    const int q1 = lev[1][lv + 1];
+    for (int q = lev[1][lv] + t; q < q1; q += kIluThreads) {
+      const int i = F.ord_u[q];
+      int c[kIluWidth];
+      T v[kIluWidth];
+#pragma unroll
+      for (int k = 0; k < kIluWidth; ++k) {
+        c[k] = F.col_u[k * n + q];
+        v[k] = F.val_u[k * n + q];
+      }
+      const T d = F.diag_u[q];
+      T x[kIluWidth];
+#pragma unroll
+      for (int k = 0; k < kIluWidth; ++k) x[k] = z[max(c[k], 0)];
+      T acc = z[i];
+#pragma unroll
+      for (int k = 0; k < kIluWidth; ++k) acc = c[k] >= 0 ? acc - v[k] * x[k] : acc;
+      z[i] = acc / d;
+    }
+    __syncthreads();
+  }
+}
+
 // xc = Ainv bc, FP64 dense inverse: one workgroup per row (the coarse rows
 // are few), each thread with up to eight loads in flight.
 template <typename T>
@@ -1201,6 +1265,12 @@ void launch_prolong(const Sell<T>& P, const T* xc, T* x, const DevState* gate, h
 }
 
 template <typename T>
+void launch_ilu0(const IluDev<T>& F, const T* r, T* z, const DevState* gate, hipStream_t s) {
+  if (F.n <= 0) return;
+  k_ilu0<T><<<1, kIluThreads, 0, s>>>(F, r, z, gate);
+}
+
+template <typename T>
 void launch_coarse(const double* Ainv, int n, const T* bc, T* xc, const DevState* gate,
                    hipStream_t s) {
   if (n <= 0) return;
@@ -1393,6 +1463,10 @@ template void launch_prolong<double>(const Sell<double>&, const double*, double*
                                      const DevState*, hipStream_t);
 template void launch_prolong<float>(const Sell<float>&, const float*, float*, const DevState*,
                                     hipStream_t);
+template void launch_ilu0<double>(const IluDev<double>&, const double*, double*,
+                                  const DevState*, hipStream_t);
+template void launch_ilu0<float>(const IluDev<float>&, const float*, float*, const DevState*,
+                                 hipStream_t);
 template void launch_coarse<double>(const double*, int, const double*, double*,
                                     const DevState*, hipStream_t);
 template void launch_coarse<float>(const double*, int, const float*, float*, const DevState*,

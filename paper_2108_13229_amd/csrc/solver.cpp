@@ -218,6 +218,7 @@ void Solver::setup_host(HostProblem* p, const sd_solver_opts* o) {
   if (so.krylov != SD_KRYLOV_FGMRES && so.krylov != SD_KRYLOV_BICGSTAB)
     throw Error(SD_E_INVALID, "krylov");
   if (so.amg != SD_AMG_PLAIN && so.amg != SD_AMG_SMOOTHED) throw Error(SD_E_INVALID, "amg");
+  if (so.darcy != SD_DARCY_AMG && so.darcy != SD_DARCY_ILU0) throw Error(SD_E_INVALID, "darcy");
   opts.amg.theta = so.theta;
   opts.amg.omega = so.omega;
   opts.amg.nu_pre = so.nu_pre;
@@ -247,8 +248,12 @@ void Solver::setup_host(HostProblem* p, const sd_solver_opts* o) {
   // porous block: its hierarchy then stays empty and its V-cycle is skipped
   hh[0] = HostHierarchy();
   hh[1] = HostHierarchy();
+  ilu = HostIlu();
   if (L.off_p > 0) amg_setup_host(Vb, compV, false, opts.amg, hh[0]);
-  if (L.N > L.off_q) amg_setup_host(Dt, compD, false, opts.amg, hh[1]);
+  if (L.N > L.off_q) {
+    if (so.darcy == SD_DARCY_ILU0) ilu0_host(Dt, ilu);
+    else amg_setup_host(Dt, compD, false, opts.amg, hh[1]);
+  }
   hh[2] = HostHierarchy();
   if (so.schur == SD_SCHUR_CC) {
     // L_p = B^T D^-1 B = (-C) diag(1/D) B, D = |CV|/dt on the velocity rows
@@ -462,10 +467,38 @@ void upload_hierarchy(const HostHierarchy& h, DevHierarchy<T>& d, double omega, 
   SD_HIP(hipStreamSynchronize(s));
 }
 
+template <typename T, typename S>
+static const T* upload_vec(const std::vector<S>& v, DeviceMem& mem, hipStream_t s) {
+  std::vector<T> h(v.begin(), v.end());
+  T* d = mem.array<T>(h.size());
+  SD_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  SD_HIP(hipStreamSynchronize(s));
+  return d;
+}
+
+template <typename T>
+IluDev<T> upload_ilu(const HostIlu& h, DeviceMem& mem, hipStream_t s) {
+  IluDev<T> d;
+  d.n = (int)h.n;
+  d.nlev_l = (int)h.lev_l.size() - 1;
+  d.nlev_u = (int)h.lev_u.size() - 1;
+  d.lev_l = upload_vec<int>(h.lev_l, mem, s);
+  d.lev_u = upload_vec<int>(h.lev_u, mem, s);
+  d.ord_l = upload_vec<int>(h.ord_l, mem, s);
+  d.ord_u = upload_vec<int>(h.ord_u, mem, s);
+  d.col_l = upload_vec<int>(h.col_l, mem, s);
+  d.col_u = upload_vec<int>(h.col_u, mem, s);
+  d.val_l = upload_vec<T>(h.val_l, mem, s);
+  d.val_u = upload_vec<T>(h.val_u, mem, s);
+  d.diag_u = upload_vec<T>(h.diag_u, mem, s);
+  return d;
+}
+
 template <typename T>
 class PrecImpl : public PrecBase {
  public:
   DevHierarchy<T> H[3];  // V, D~ and (Cahouet-Chabard middle block) L_p
+  IluDev<T> ilu;         // ILU(0) of D~ in place of its hierarchy (SD_DARCY_ILU0)
   Sell<T> Cf;
   Sell<float> A32;       // FP32 copy of A for the Arnoldi product (MIXED32 only)
   bool arn32 = false;
@@ -486,6 +519,7 @@ class PrecImpl : public PrecBase {
     for (int b = 0; b < 3; ++b)
       if (!S.hh[b].levels.empty())
         upload_hierarchy<T>(S.hh[b], H[b], S.opts.amg.omega, nu_pre, nu_post, mem, s);
+    if (S.ilu.n > 0) ilu = upload_ilu<T>(S.ilu, mem, s);
     if (cc) {
       tp = mem.array<T>((size_t)(S.off[3] - S.off[2]));
       yl = mem.array<T>((size_t)(S.off[3] - S.off[2]));
@@ -581,7 +615,11 @@ class PrecImpl : public PrecBase {
       vcycle<T>(2, 0, tp, nullptr, yl, gate, s);
       launch_add<T>(yl, z + o[2], n_p, gate, s);
     }
-    if (!H[1].lev.empty()) vcycle<T>(1, 0, tq, nullptr, z + o[3], gate, s);
+    if (ilu.n > 0) {
+      launch_ilu0<T>(ilu, tq, z + o[3], gate, s);
+    } else if (!H[1].lev.empty()) {
+      vcycle<T>(1, 0, tq, nullptr, z + o[3], gate, s);
+    }
   }
 
   void apply_precond(Solver& S, const double* r, double* z, hipStream_t s) override {

@@ -102,6 +102,33 @@ struct SolveRun {
   sd_stats out{};
 };
 
+// ILU(0) of a square matrix (Meijerink & van der Vorst 1977; the Darcy
+// preconditioner of the paper's P^td(Uzawa, ILU(0)) rows, Sec. 5 solver
+// setup and Table 2): elimination in row order, row i finished by
+//   l_ik = a_ik / u_kk for each k < i of its pattern, ascending, each
+//   followed by a_ij -= l_ik u_kj for the j > k of row k's pattern that are
+//   in row i's pattern, ascending;
+// every update outside the pattern is dropped.  For the device
+// substitution the rows are ordered by level: a row's forward level is one
+// more than the largest among the rows its L part references (0 without
+// any), its backward level likewise over its strict U part.  Positions
+// q = 0..n-1 run through the levels in order (rows ascending within a
+// level); the triangle entries of position q are stored as ELL with
+// kIluWidth slots, slot k at k * n + q, in ascending column order, padded
+// with col -1 and val 0.
+struct HostIlu {
+  int64_t n = 0;
+  std::vector<int32_t> lev_l, lev_u;   // level pointers into the positions
+  std::vector<int32_t> ord_l, ord_u;   // row of each position
+  std::vector<int32_t> col_l, col_u;   // kIluWidth * n
+  std::vector<double> val_l, val_u;    // l_ij, u_ij (j != i)
+  std::vector<double> diag_u;          // u_ii of each backward position
+};
+// Throws SD_E_INVALID (row without a diagonal entry, a triangle row wider
+// than kIluWidth, more than kIluMaxLevels levels) or SD_E_BREAKDOWN (zero
+// pivot).
+void ilu0_host(const HostCSR& A, HostIlu& out);
+
 // Precision-specific part: preconditioner operators and the Arnoldi matrix.
 class PrecBase {
  public:
@@ -125,6 +152,7 @@ class Solver {
   SolverOpts opts;
   HostHierarchy hh[3];              // 0: V, 1: Darcy block with interface correction,
                                     // 2: pressure operator L_p (SD_SCHUR_CC only)
+  HostIlu ilu;                      // ILU(0) of the Darcy block (SD_DARCY_ILU0; else n = 0)
   HostCSR Cf;                       // continuity and porous rows x velocity columns
   double xscale = 1.0;
   int64_t off[5] = {0, 0, 0, 0, 0};

@@ -25,6 +25,7 @@ PRECOND = {"BJ": 0, "BGS": 1, "TD_BJ": 2, "TD_BGS": 3}
 SCHUR = {"identity": 0, "mass": 1, "cc": 2}
 PRECISION = {"fp64": 0, "mixed": 1, "mixed32": 2}
 AMG = {"plain": 0, "smoothed": 1}
+DARCY = {"amg": 0, "ilu0": 1}
 REQ_STATE = {0: "pending", 1: "running", 2: "done", 3: "failed"}
 
 _dp = C.POINTER(C.c_double)
@@ -67,7 +68,8 @@ class SolverOpts(C.Structure):
                 ("tol", C.c_double), ("precond", C.c_int), ("schur", C.c_int),
                 ("precision", C.c_int), ("amg", C.c_int), ("mis", C.c_int),
                 ("theta", C.c_double), ("omega", C.c_double), ("nu_pre", C.c_int),
-                ("nu_post", C.c_int), ("coarse_max", C.c_int), ("max_levels", C.c_int)]
+                ("nu_post", C.c_int), ("coarse_max", C.c_int), ("max_levels", C.c_int),
+                ("darcy", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -132,6 +134,10 @@ SIGNATURES = {
     "sd_solver_level_csr": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int64),
                                       C.POINTER(C.c_int64), C.POINTER(C.POINTER(C.c_int64)),
                                       C.POINTER(C.POINTER(C.c_int32)), C.POINTER(_dp)]),
+    "sd_solver_ilu": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int),
+                                C.POINTER(C.POINTER(C.c_int32)), C.POINTER(C.POINTER(C.c_int32)),
+                                C.POINTER(C.POINTER(C.c_int32)), C.POINTER(_dp),
+                                C.POINTER(_dp)]),
     "sd_solver_level_agg": (C.c_int, [_P, C.c_int, C.c_int, C.POINTER(C.POINTER(C.c_int32)),
                                       C.POINTER(C.c_int64)]),
     "sd_solver_coarse_inverse": (C.c_int, [_P, C.c_int, C.POINTER(_dp), C.POINTER(C.c_int64)]),
@@ -226,7 +232,8 @@ def _marshal(p, keep):
 def solver_opts(**kw) -> SolverOpts:
     o = SolverOpts()
     lib().sd_solver_opts_default(C.byref(o))
-    maps = dict(krylov=KRYLOV, precond=PRECOND, schur=SCHUR, precision=PRECISION, amg=AMG)
+    maps = dict(krylov=KRYLOV, precond=PRECOND, schur=SCHUR, precision=PRECISION, amg=AMG,
+                darcy=DARCY)
     for k, v in kw.items():
         if k in maps and isinstance(v, str):
             v = maps[k][v]
@@ -319,6 +326,24 @@ class Solver:
         col = np.ctypeslib.as_array(ci, (max(nnz, 1),))[:nnz].copy()
         val = np.ctypeslib.as_array(va, (max(nnz, 1),))[:nnz].copy()
         return (nr.value, nc.value), rowptr, col, val
+
+    def ilu(self, lower: bool):
+        """ILU(0) factors of the Darcy block in level order (darcy="ilu0"):
+        dict(lev, ord, col, val, diag) with col/val of shape (4, n) (slot k
+        of position q at [k, q]) and diag None for the lower factor."""
+        n, nl = C.c_int64(), C.c_int()
+        lev, ordp, col = (C.POINTER(C.c_int32)() for _ in range(3))
+        val, dg = _dp(), _dp()
+        _check(lib().sd_solver_ilu(self.h, int(bool(lower)), C.byref(n), C.byref(nl),
+                                   C.byref(lev), C.byref(ordp), C.byref(col), C.byref(val),
+                                   C.byref(dg)))
+        n = n.value
+        out = dict(lev=np.ctypeslib.as_array(lev, (nl.value + 1,)).copy(),
+                   ord=np.ctypeslib.as_array(ordp, (n,)).copy(),
+                   col=np.ctypeslib.as_array(col, (4 * n,)).reshape(4, n).copy(),
+                   val=np.ctypeslib.as_array(val, (4 * n,)).reshape(4, n).copy(),
+                   diag=None if lower else np.ctypeslib.as_array(dg, (n,)).copy())
+        return out
 
     def level_agg(self, block: int, level: int) -> np.ndarray:
         a = C.POINTER(C.c_int32)()

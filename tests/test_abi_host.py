@@ -243,3 +243,59 @@ def test_two_domain_setup_on_host(variant):
     S = sd.Solver(P, device=False, precond=variant, coarse_max=64)
     assert S.n_levels(0) >= 2 and S.n_levels(1) >= 2
     assert S.middle_scale() == 1.0      # omega needs the device V-cycle
+
+
+def _ilu_cases():
+    from sdinputs import paper_setup_problem
+    return [("channel", lambda: channel_problem(24, 12, seed=2)),
+            ("ragged", lambda: channel_problem(45, 22, 17, seed=5)),
+            ("paper_geometry", lambda: paper_setup_problem(16, p_in=1e-9, dt=2e5)),
+            ("channel3d", lambda: __import__("sdinputs").channel3d_problem(8, 5, 6, seed=1))]
+
+
+@pytest.mark.parametrize("ci", range(4))
+def test_host_ilu0_bit_exact_and_level_schedule_valid(ci):
+    """The host ILU(0) factors of D~ equal the oracle's bit for bit, and each
+    substitution level references only rows of earlier levels."""
+    from oracle import precond
+    from oracle.assemble3d import assemble3d
+    from oracle.ilu import ilu0
+    name, make = _ilu_cases()[ci]
+    p = make()
+    a = assemble3d(p) if name == "channel3d" else assemble(p)
+    ref = ilu0(precond.darcy_interface_block(a.blocks()))
+    F, d = ref.F, ref.diag
+    P = sd.Problem(p, device=False)
+    S = sd.Solver(P, device=False, precond="TD_BGS", darcy="ilu0")
+    assert S.n_levels(1) == 0
+    n = F.shape[0]
+    for lower in (True, False):
+        f = S.ilu(lower)
+        lev, ordr = f["lev"], f["ord"]
+        assert lev[0] == 0 and lev[-1] == n and np.all(np.diff(lev) > 0)
+        assert np.array_equal(np.sort(ordr), np.arange(n))
+        level = np.empty(n, dtype=np.int64)
+        for lv in range(len(lev) - 1):
+            level[ordr[lev[lv]:lev[lv + 1]]] = lv
+        for q in range(n):
+            i = ordr[q]
+            e0, e1 = (F.indptr[i], d[i]) if lower else (d[i] + 1, F.indptr[i + 1])
+            cols, vals = F.indices[e0:e1], F.data[e0:e1]
+            k = len(cols)
+            assert np.array_equal(f["col"][:k, q], cols) and np.all(f["col"][k:, q] == -1)
+            assert np.array_equal(f["val"][:k, q], vals) and np.all(f["val"][k:, q] == 0.0)
+            assert np.all(level[cols] < level[i])
+            if not lower:
+                assert f["diag"][q] == F.data[d[i]]
+
+
+def test_ilu0_option_validation():
+    p = channel_problem(16, 8, seed=1)
+    P = sd.Problem(p, device=False)
+    for bad in (dict(darcy=2), dict(darcy=-1)):
+        with pytest.raises(sd.SDError) as e:
+            sd.Solver(P, device=False, **bad)
+        assert e.value.code == sd.SD_E_INVALID
+    S = sd.Solver(P, device=False)
+    with pytest.raises(sd.SDError):
+        S.ilu(True)                    # AMG Darcy block: no factors
