@@ -35,7 +35,11 @@ class DNResult:
     history: list
 
 
-def _subsolvers(p: Problem, a: Assembled):
+def subsolvers(p: Problem, a: Assembled):
+    """The two subdomain solution operators of the coupling (sparse LU of each
+    subdomain system, factorised here once) and the map back to the
+    monolithic ordering: S_ff(v) -> (sigma, x_ff), S_pm(sigma) -> (vt, q),
+    to_mono(x_ff, v, q)."""
     L = a.layout
     nx, nyp, npm, i0 = L.nx, L.ny_pm, L.nx_pm, L.i0
     A = a.A.tocsr()
@@ -89,13 +93,13 @@ def _subsolvers(p: Problem, a: Assembled):
 
 
 def solve_dn(p: Problem, a: Assembled, eps: float = 1e-10, maxit: int = 500,
-             omega0: float = 0.5, accel: str = "aitken") -> DNResult:
+             omega0: float = 0.5, accel: str = "aitken", subs=None) -> DNResult:
     """Dirichlet-Neumann fixed point with Aitken relaxation (accel="aitken")
     or IQN-ILS post-processing (accel="iqn-ils").  Iteration k maps the
     interface velocity v_k to sigma_k = S_ff(v_k) and vt_k = S_pm(sigma_k),
     r_k = vt_k - v_k, and stops once both relative measures of Sec. 3 hold:
     ||sigma_k - sigma_{k-1}|| < eps ||sigma_k|| and ||r_k|| < eps ||vt_k||."""
-    S_ff, S_pm, to_mono = _subsolvers(p, a)
+    S_ff, S_pm, to_mono = subs if subs is not None else subsolvers(p, a)
     nx = a.layout.n_gamma
     v = np.zeros(nx)
     sigma_old = None
@@ -153,7 +157,7 @@ def solve_interface_gmres(p: Problem, a: Assembled, tol: float = 1e-14) -> np.nd
     root is found here by dense Newton (one linear solve with the exactly
     assembled interface Jacobian), an alternative route to the same fixed
     point used as a cross-check of the Aitken iteration."""
-    S_ff, S_pm, to_mono = _subsolvers(p, a)
+    S_ff, S_pm, to_mono = subsolvers(p, a)
     nx = a.layout.n_gamma
 
     def R(v):

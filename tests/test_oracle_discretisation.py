@@ -229,8 +229,8 @@ def test_iqn_ils_reaches_the_monolithic_solution(nx, ny):
 
 
 def _interface_map(p, a):
-    from oracle.dn import _subsolvers
-    S_ff, S_pm, _ = _subsolvers(p, a)
+    from oracle.dn import subsolvers
+    S_ff, S_pm, _ = subsolvers(p, a)
     return lambda v: S_pm(S_ff(v)[0])[0]
 
 
