@@ -96,7 +96,7 @@ static int lanes_per_row(const HostCSR& A, bool allow_csr, int force_lpr) {
   if (force_lpr > 0) return force_lpr;
   if (!allow_csr || A.n_rows == 0) return 1;
   const double avg = (double)A.nnz() / (double)A.n_rows;
-  if (avg <= 12.0 && A.n_rows >= 65536) return 1;
+  if (avg <= 16.0 && A.n_rows >= 65536) return 1;
   return avg <= 16.0 ? 4 : (avg <= 48.0 ? 8 : (avg <= 96.0 ? 16 : (avg <= 192.0 ? 32 : 64)));
 }
 
