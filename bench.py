@@ -239,7 +239,42 @@ def serving(sd, args):
                                "lognormal K sigma U[0.5,2], inflow U[1e-3,1e-1], seed 7",
                    "restart": args.restart, "coarse_max": 1024},
     }
+    # dominant kernel on the largest request of the trace (mixed, as served)
+    big = max(probs, key=lambda q: q.nx * q.ny)
+    P = sd.Problem(big)
+    S = sd.Solver(P, **opts)
+    if args.roofline_solves > 0:
+        out["roofline"] = roofline(S, args.roofline_solves, "mixed", "serving")
+        out["roofline"]["request"] = f"{big.nx}x{big.ny} per subdomain (N={P.N})"
+    S.close()
+    P.close()
+    if not args.no_cpu:
+        out["cpu_baseline"] = serving_cpu_baseline(probs, args.restart)
     print(json.dumps(out))
+
+
+def serving_cpu_baseline(probs, restart, budget_s=20.0):
+    """The oracle serving the trace one request at a time on one thread:
+    assembly, AMG set-up (coarse levels up to 1024 rows, as served) and the
+    FP64 FGMRES solve of each request, in trace order, until budget_s has
+    been spent."""
+    from threadpoolctl import threadpool_limits
+    from oracle import amg, krylov, precond
+    from oracle.assemble import assemble
+    done = 0
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        for p in probs:
+            a = assemble(p)
+            M = precond.build(p, a, "BGS", opts=amg.AMGOptions(coarse_max=1024))
+            krylov.fgmres(a.A, a.b, M, tol=1e-8, m=restart)
+            done += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        span = time.perf_counter() - t0
+    return dict(value=done / span, unit="solves/s", cores=1, kind="oracle",
+                sample=f"the first {done} requests of the trace, each assembled, set up and "
+                       f"solved by the oracle one at a time ({span:.1f} s), 1 thread")
 
 
 WORKLOAD_T1 = ("512x256 free-flow + 512x256 porous cells (N=524288), lognormal K seed 1, "
