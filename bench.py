@@ -23,6 +23,7 @@ reference solution (its FGMRES to relative residual 1e-12) against which the
 per-block errors of every GPU solution are reported.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config C1|C2|T1|C4|P1] [--no-cpu]
+       python bench.py --partitioned | --variants | --serving N | --counter-run
 """
 from __future__ import annotations
 
