@@ -299,3 +299,14 @@ def test_ilu0_option_validation():
     S = sd.Solver(P, device=False)
     with pytest.raises(sd.SDError):
         S.ilu(True)                    # AMG Darcy block: no factors
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    """Without the built HIP library the binding raises; there is no CPU
+    fallback."""
+    monkeypatch.setattr(sd, "_lib", None)
+    monkeypatch.setattr(sd, "LIB_PATH", str(tmp_path / "libsd.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        sd.lib()
+    with pytest.raises(RuntimeError):
+        sd.Problem(channel_problem(8, 4, seed=1), device=False)
