@@ -571,7 +571,10 @@ __global__ __launch_bounds__(kGsThreads) __attribute__((amdgpu_waves_per_eu(8, 8
 #pragma unroll
         for (int i = 0; i < kProjChunk; ++i) {
           const int si = min(s + i, se - 1);
-          x[i] = vk[min(r0 + si * 64 + lane, last)];   // rows past n: u, w are 0
+          // rows past n: u, w are 0.  The basis is streamed: a
+          // non-temporal load keeps it from evicting the matrices and
+          // hierarchies, which the iteration re-reads, from the caches
+          x[i] = __builtin_nontemporal_load(&vk[min(r0 + si * 64 + lane, last)]);
         }
 #pragma unroll
         for (int i = 0; i < kProjChunk; ++i) {
@@ -699,21 +702,25 @@ __device__ __forceinline__ void arn_rows(const double* __restrict__ W, double* _
 #pragma unroll 4
     for (int k = 0; k < j; ++k) {
       const double* vk = V + (size_t)k * ldv;
-      const double xa = vk[ra];
-      const double xb = hb ? vk[rb] : 0.0;
+      // streamed basis: non-temporal, as in the projection
+      const double xa = __builtin_nontemporal_load(&vk[ra]);
+      const double xb = hb ? __builtin_nontemporal_load(&vk[rb]) : 0.0;
       const double ca = cf[k], cb = cf[kMaxBasis + k];
       p1a += ca * xa;
       p2a += cb * xa;
       p1b += ca * xb;
       p2b += cb * xb;
     }
-    const double ua = uj[ra];
-    uj[ra] = inv * ua - p1a;
-    un[ra] = W[ra] - p2a - tt * ua;
+    // u_j and w are read for the last time and v_j is next read as part of
+    // the streamed basis: all non-temporal; u_{j+1}, which the
+    // preconditioner reads next, is stored normally
+    const double ua = __builtin_nontemporal_load(&uj[ra]);
+    __builtin_nontemporal_store(inv * ua - p1a, &uj[ra]);
+    un[ra] = __builtin_nontemporal_load(&W[ra]) - p2a - tt * ua;
     if (hb) {
-      const double ub = uj[rb];
-      uj[rb] = inv * ub - p1b;
-      un[rb] = W[rb] - p2b - tt * ub;
+      const double ub = __builtin_nontemporal_load(&uj[rb]);
+      __builtin_nontemporal_store(inv * ub - p1b, &uj[rb]);
+      un[rb] = __builtin_nontemporal_load(&W[rb]) - p2b - tt * ub;
     }
   }
 }
