@@ -36,17 +36,26 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// A load that is cached normally, or (NT) non-temporally: data read once
+// per iteration should not evict what the iteration reads repeatedly.
+template <bool NT, typename T>
+__device__ __forceinline__ T load_hint(const T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
 // M consecutive entries e, e + step, ... of a SELL row added to acc in
 // order; the M index/value loads and then the M gathers are all issued
-// before the first product.
-template <int M, typename TM, typename F>
+// before the first product.  NT: the index and value loads are
+// non-temporal.
+template <int M, bool NT = false, typename TM, typename F>
 __device__ __forceinline__ void sell_chunk(const Sell<TM>& A, int e, int step, F f, TM& acc) {
   int c[M];
   TM v[M];
 #pragma unroll
   for (int i = 0; i < M; ++i) {
-    c[i] = A.col[e + i * step];
-    v[i] = A.val[e + i * step];
+    c[i] = load_hint<NT>(&A.col[e + i * step]);
+    v[i] = load_hint<NT>(&A.val[e + i * step]);
   }
   TM x[M];
 #pragma unroll
@@ -55,12 +64,12 @@ __device__ __forceinline__ void sell_chunk(const Sell<TM>& A, int e, int step, F
   for (int i = 0; i < M; ++i) acc += v[i] * x[i];
 }
 
-template <int M, typename TM, typename F>
+template <int M, bool NT, typename TM, typename F>
 __device__ __forceinline__ void sell_tail(const Sell<TM>& A, int e, int cnt, int step, F f,
                                           TM& acc) {
   if constexpr (M > 0) {
-    if (cnt == M) sell_chunk<M>(A, e, step, f, acc);
-    else sell_tail<M - 1>(A, e, cnt, step, f, acc);
+    if (cnt == M) sell_chunk<M, NT>(A, e, step, f, acc);
+    else sell_tail<M - 1, NT>(A, e, cnt, step, f, acc);
   }
 }
 
@@ -69,22 +78,22 @@ __device__ __forceinline__ void sell_tail(const Sell<TM>& A, int e, int cnt, int
 // costs two dependent memory round trips (indices and values, then the
 // gathers) and no load is issued for an entry the row does not have.  cnt
 // is the same for all lanes of a slice, so the tail takes one branch.
-template <int K, typename TM, typename F>
+template <int K, bool NT = false, typename TM, typename F>
 __device__ __forceinline__ TM sell_row(const Sell<TM>& A, int e, int cnt, int step, F f) {
   TM acc = 0;
-  for (; cnt >= K; cnt -= K, e += K * step) sell_chunk<K>(A, e, step, f, acc);
-  sell_tail<K - 1>(A, e, cnt, step, f, acc);
+  for (; cnt >= K; cnt -= K, e += K * step) sell_chunk<K, NT>(A, e, step, f, acc);
+  sell_tail<K - 1, NT>(A, e, cnt, step, f, acc);
   return acc;
 }
 
 constexpr int kRowChunk = 6;   // entries of a SELL-64 row loaded at once
 
-template <int K = kRowChunk, typename TM, typename TX>
+template <int K = kRowChunk, bool NT = false, typename TM, typename TX>
 __device__ __forceinline__ TM sell_dot(const Sell<TM>& A, const TX* __restrict__ x, int row) {
   const int s = row >> 6;
   const int beg = A.sptr[s] + (row & 63);
   const int end = A.sptr[s + 1];
-  return sell_row<K>(A, beg, (end - beg + 63) >> 6, 64, [&](int c) { return (TM)x[c]; });
+  return sell_row<K, NT>(A, beg, (end - beg + 63) >> 6, 64, [&](int c) { return (TM)x[c]; });
 }
 
 __device__ __forceinline__ double scale_of(const double* s) { return s ? *s : 1.0; }
@@ -532,8 +541,10 @@ __global__ __launch_bounds__(kGsThreads) __attribute__((amdgpu_waves_per_eu(8, 8
       ua = uj[ra];
       if (hb) ub = uj[rb];
       if (spmv) {
-        const TM sa = sell_dot<kProjRowChunk>(A, z, ra);
-        const TM sb = hb ? sell_dot<kProjRowChunk>(A, z, rb) : (TM)0;
+        // A is read once per iteration, the AMG hierarchies several times:
+        // its loads are non-temporal so that the hierarchies stay cached
+        const TM sa = sell_dot<kProjRowChunk, true>(A, z, ra);
+        const TM sb = hb ? sell_dot<kProjRowChunk, true>(A, z, rb) : (TM)0;
         wa = (double)sa;
         W[ra] = wa;
         if (hb) {
