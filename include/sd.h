@@ -348,7 +348,9 @@ int sd_solver_profile_read(const sd_solver* s, int64_t* launches, double* second
  * ||vt_k - v_k|| < eps ||vt_k|| (Sec. 3).  Both subdomain systems are solved
  * on the GPU by FGMRES with the block preconditioner (the missing block left
  * out), to the tolerance in the sub-solver options, each warm-started from
- * its previous state; SD_SCHUR_CC falls back to SD_SCHUR_MASS.  The
+ * its previous state.  With SD_SCHUR_CC on a backward-Euler problem the
+ * free-flow solver keeps the Cahouet-Chabard middle block (on a stationary
+ * problem, and for the porous solver, SD_SCHUR_MASS is used).  The
  * interface vectors (nx or nx nz values) are kept on the host. */
 typedef struct sd_dn sd_dn;
 enum { SD_DN_AITKEN = 0, SD_DN_IQN_ILS = 1 };

@@ -138,6 +138,7 @@ void DNSolver::build(const HostProblem& P, const sd_solver_opts* o, const sd_all
   ff.L.off_p = L.off_p - nG;
   ff.L.off_q = L.off_q - nG;
   ff.L.N = Nff;
+  ff.L.gamma_rows = false;
   ff.A.n_rows = ff.A.n_cols = Nff;
   ff.A.rowptr.assign(1, 0);
   AffG.n_rows = Nff;
@@ -193,13 +194,18 @@ void DNSolver::build(const HostProblem& P, const sd_solver_opts* o, const sd_all
   ff_p0 = ff.L.off_p + L.i0;   // p(., 0) over the block in the free-flow subsystem
   ff_v1 = ff.L.off_v + L.i0;   // v(., 1) over the block
   // ---- sub-solvers and device buffers
+  // the free-flow subsystem keeps the requested middle block (the
+  // Cahouet-Chabard one needs its backward-Euler mass); the porous
+  // subsystem has no pressure-velocity block, so it takes the default
   sd_solver_opts so = *o;
-  if (so.schur == SD_SCHUR_CC) so.schur = SD_SCHUR_MASS;
+  if (so.schur == SD_SCHUR_CC && !(ff.mass > 0.0)) so.schur = SD_SCHUR_MASS;
+  sd_solver_opts so_pm = so;
+  if (so_pm.schur == SD_SCHUR_CC) so_pm.schur = SD_SCHUR_MASS;
   sff.reset(new Solver());
   sff->setup_host(&ff, &so);
   sff->upload(alloc, s);
   spm.reset(new Solver());
-  spm->setup_host(&pm, &so);
+  spm->setup_host(&pm, &so_pm);
   spm->upload(alloc, s);
   mem.reset(new DeviceMem(alloc, s));
   AffG_dev = upload_sell<double>(AffG, *mem, s);

@@ -36,6 +36,9 @@ struct Layout {
   int nx = 0, ny = 0, nyp = 0, nux = 0, nz = 0;
   int nx_pm = 0, i0 = 0, i_first = 1;
   int64_t off_v = 0, off_w = 0, off_p = 0, off_q = 0, N = 0;
+  // the interface v faces lead the v block (false for the free-flow
+  // subsystem of the partitioned coupling, which has them removed)
+  bool gamma_rows = true;
   int nzc() const { return nz > 0 ? nz : 1; }
   // interface faces: the porous top layer under the free flow
   int64_t n_gamma() const { return nz > 0 ? (int64_t)nx * nz : (int64_t)(nx_pm > 0 ? nx_pm : nx); }
@@ -46,7 +49,7 @@ struct Layout {
       const int i = (int)(r % nux) + i_first;
       return i >= 1 && i <= nx - 1;
     }
-    if (r < off_w) return r >= off_v + n_gamma();
+    if (r < off_w) return !gamma_rows || r >= off_v + n_gamma();
     return r < off_p;
   }
   int64_t u(int i, int j) const { return (int64_t)j * nux + (i - i_first); }

@@ -127,3 +127,33 @@ def test_paper_geometry_monolithic_and_partitioned():
     x, st, rc = D.solve(accel="iqn-ils", eps=1e-9)
     assert rc == sd.SD_OK and abs(st["iters"] - dn_ref.iters) <= 2, (st, dn_ref.iters)
     assert np.linalg.norm(_host(x) - xs) <= 1e-7 * np.linalg.norm(xs)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_dn_backward_euler_step_keeps_cahouet_chabard_block(dim):
+    """One backward-Euler step system at dt = 0.1, where the viscous middle
+    block alone stalls: the coupling's free-flow sub-solve keeps the
+    Cahouet-Chabard block (its mass rows are those of the subsystem, whose
+    interface faces are removed), and the coupling reaches the direct
+    solution of the step system (in 2-D also in the oracle's number of
+    iterations; the oracle's coupling is 2-D only)."""
+    if dim == 2:
+        p = channel_problem(64, 32, seed=3)
+        asm = assemble
+    else:
+        p = channel3d_problem(12, 6, 8, seed=2)
+        asm = assemble3d
+    p.dt = 0.1
+    print("case dim", dim, flush=True)
+    a = asm(p)
+    xs = refined_solve(a.A, a.b)
+    P = sd.Problem(p, device=True)
+    D = sd.Partitioned(P, tol=1e-12, restart=60, schur="cc")
+    x, st, rc = D.solve(accel="iqn-ils", eps=1e-9, maxit=300)
+    assert rc == sd.SD_OK and st["converged"] == 1
+    if dim == 2:
+        ref = solve_dn(p, a, eps=1e-9, accel="iqn-ils")
+        assert ref.converged
+        assert abs(st["iters"] - ref.iters) <= 2, (st, ref.iters)
+    assert np.linalg.norm(_host(x) - xs) <= 1e-7 * np.linalg.norm(xs)
+    D.close()
