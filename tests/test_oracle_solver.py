@@ -515,3 +515,90 @@ def test_two_domain_variants_converge(variant):
     ident = krylov.fgmres(a.A, a.b, precond.build(p, a, "BGS", schur="identity"), tol=1e-10, m=60)
     if variant == "TD_BGS":
         assert r.iters < ident.iters
+
+
+# ---------------------------------------------------------------- PD-GMRES
+
+def test_pd_controller_lengths_on_a_fixed_history():
+    """The restart-length controller on a fixed residual history, worked by
+    hand: m_1 = m_init = 3; after r = 0.5: 3 + floor(-1.5) = 1 < m_min, so
+    m_init -> 8 and m = 8; after 0.3: 8 + floor(-1.8 - 3.5) = 2 -> m_init 13;
+    after 0.25: 13 + floor(-2.5 - 2.0833) = 8; after 0.24: 8 + floor(-2.88 -
+    0.6) = 4.  The cap m_max binds on a longer jump."""
+    length = krylov.pd_lengths(krylov.PDControl())
+    hist = [1.0, 0.5, 0.3, 0.25, 0.24]
+    got = [length(hist[:k + 1]) for k in range(len(hist))]
+    assert got == [3, 8, 13, 8, 4]
+    capped = krylov.pd_lengths(krylov.PDControl(m_max=10))
+    assert [capped(hist[:k + 1]) for k in range(3)] == [3, 8, 10]
+
+
+def _krylov_minimiser(A, M, x0, b, m):
+    """argmin of ||b - A x|| over x0 + M K_m(A M, r0), K_m spanned by an
+    orthonormalised power basis (independent of the Arnoldi process)."""
+    r = b - A @ x0
+    K = np.zeros((A.shape[0], m))
+    K[:, 0] = r / np.linalg.norm(r)
+    for i in range(1, m):
+        v = A @ M(K[:, i - 1])
+        K[:, i] = v / np.linalg.norm(v)
+    Q, _ = np.linalg.qr(K)
+    Z = np.column_stack([M(Q[:, i]) for i in range(m)])
+    return krylov.least_squares_iterate(A, b, Z, x0)
+
+
+def test_pd_gmres_cycles_are_least_squares_minimisers():
+    """Every PD-GMRES cycle of length m_c ends at the minimiser of the
+    residual over x_{c-1} + M K_{m_c}(A M, r_{c-1}), whatever lengths the
+    controller chose (the iterate after c cycles is the run stopped at the
+    cumulative iteration count)."""
+    p = channel_problem(12, 6, seed=2)
+    a = assemble(p)
+    M = precond.build(p, a, "BGS")
+    A = a.A.toarray()
+    res, lengths = krylov.pd_fgmres(a.A, a.b, M, tol=1e-300, maxit=40)
+    assert lengths[:2] == [3, 8] and max(lengths) > 3
+    x_prev = np.zeros(a.N)
+    done = 0
+    for c, m in enumerate(lengths[:4]):
+        done += m
+        xc, _ = krylov.pd_fgmres(a.A, a.b, M, tol=1e-300, maxit=done)
+        assert xc.iters == done and xc.restarts == c + 1
+        ref = _krylov_minimiser(A, M, x_prev, a.b, m)
+        assert np.linalg.norm(xc.x - ref) <= 1e-7 * np.linalg.norm(ref), c
+        x_prev = xc.x
+
+
+def test_pd_gmres_constant_length_is_restarted_gmres():
+    """With both gains zero the controller keeps m_init, and PD-GMRES is
+    restarted FGMRES(m_init): the same iterate after the same cycles, and
+    the solution SciPy's restarted GMRES reaches."""
+    p = channel_problem(16, 8, seed=1)
+    a = assemble(p)
+    M = precond.build(p, a, "BGS")
+    ctl = krylov.PDControl(m_init=7, m_min=1, alpha_p=0.0, alpha_d=0.0)
+    pd, lengths = krylov.pd_fgmres(a.A, a.b, M, tol=1e-10, ctl=ctl)
+    assert set(lengths) == {7}
+    fg = krylov.fgmres(a.A, a.b, M, tol=1e-10, m=7)
+    assert pd.iters == fg.iters and np.array_equal(pd.x, fg.x)
+    Mop = spla.LinearOperator(a.A.shape, matvec=M)
+    xg, info = spla.gmres(a.A, a.b, M=Mop, rtol=1e-12, restart=7, maxiter=500)
+    assert info == 0
+    xs = refined_solve(a.A, a.b)
+    assert np.linalg.norm(pd.x - xs) <= 1e-7 * np.linalg.norm(xs)
+    assert np.linalg.norm(xg - xs) <= 1e-7 * np.linalg.norm(xs)
+
+
+def test_pd_gmres_paper_setting_converges():
+    """The paper's setting (m_init = m_min = 3, m_step = 5) with the
+    block-Gauss-Seidel preconditioner reaches the direct solution; its
+    restart lengths cycle (shrinking, then back to a growing m_init)."""
+    p = channel_problem(128, 64, seed=1)
+    a = assemble(p)
+    M = precond.build(p, a, "BGS")
+    res, lengths = krylov.pd_fgmres(a.A, a.b, M, tol=1e-10)
+    assert res.converged and res.rel_res <= 1e-10
+    xs = refined_solve(a.A, a.b)
+    assert np.linalg.norm(res.x - xs) <= 1e-6 * np.linalg.norm(xs)
+    assert lengths[0] == 3 and any(l2 < l1 for l1, l2 in zip(lengths, lengths[1:]))
+    assert sum(lengths) >= res.iters
