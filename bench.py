@@ -1,29 +1,34 @@
 """Benchmark: coupled Stokes-Darcy solves/s on one MI355X.
 
-Workload C1 (default, the headline configuration): 512 x 256 cells in each
-subdomain (N = 524,288 unknowns), lognormal permeability
-ln K ~ N(ln 1e-4, 1) with an 8-cell Gaussian correlation (seed 1), viscosity
+Workload C2 (default, the headline configuration): 1024 x 512 cells in each
+subdomain (N = 2,097,152 unknowns), lognormal permeability
+ln K ~ N(ln 1e-4, 1) with an 8-cell Gaussian correlation (seed 2), viscosity
 1e-3, parabolic inflow of peak 1e-2, zero-traction outflow;
 block-Gauss-Seidel preconditioned FGMRES(60) with one smoothed-aggregation
 V-cycle per velocity and Darcy block and the viscosity-scaled pressure-mass
 Schur block, to relative residual 1e-8.  One step = one complete solve from
-x = 0 with the matrix and the AMG hierarchy resident in HBM.  FP64 is the
-headline; the mixed-precision solvers are reported beside it ("mixed": FP32
-preconditioner, FP64 Arnoldi product and outer residual; "mixed32": the
-Arnoldi product in FP32 too).  --config C2: the same physics at 1024 x 512
-(seed 2, N = 2,097,152), mixed precision as the headline.  --config T1:
-the C1 channel as a transient flow started from rest, 20 backward-Euler
-steps of dt = 0.1 with the hierarchies set up once and every step
-warm-started from the previous state (Cahouet-Chabard middle block); one
-step = one time step.  --config C4: the same on a 3-D channel of
-96 x 48 x 96 cells per subdomain (N = 2,207,232).  --config P1: the setup of
-the paper's experiments replayed with the solvers built here.  Inputs are
-synthetic and seeded.  With the CPU leg on, the oracle also provides an FP64
-reference solution (its FGMRES to relative residual 1e-12) against which the
-per-block errors of every GPU solution are reported.
+x = 0 with the matrix and the AMG hierarchy resident in HBM.  Mixed
+precision is the headline ("mixed": FP32 preconditioner, FP64 Arnoldi
+product, orthogonalisation and outer residual); FP64 and "mixed32" (the
+Arnoldi product in FP32 too) are reported beside it, and the same solvers on
+the 512 x 256 workload (C1, seed 1) under "c1".  --config C1: that workload
+as the headline (FP64).  --config T1: the C1 channel as a transient flow
+started from rest, 20 backward-Euler steps of dt = 0.1 with the hierarchies
+set up once and every step warm-started from the previous state
+(Cahouet-Chabard middle block); one step = one time step.  --config C4: the
+same on a 3-D channel of 96 x 48 x 96 cells per subdomain (N = 2,207,232).
+--config P1: the setup of the paper's experiments replayed with the solvers
+built here.  Inputs are synthetic and seeded.  The CPU leg times the oracle
+(its FGMRES with the same preconditioner, one thread and all threads, median
+of three; SuperLU on the 512 x 256 system) and provides an FP64 reference
+solution (its FGMRES to relative residual 1e-12) against which the
+per-block errors of every GPU solution are reported, beside their
+differences from the oracle's own iterate at the same tolerance.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config C1|C2|T1|C4|P1] [--no-cpu]
        python bench.py --partitioned | --variants | --serving N | --counter-run
+       python bench.py --summarize-counters FETCH_DIR WRITE_DIR --counter-out RUN_JSON
+                       --traffic-out OUT_JSON   (no GPU: counter CSVs -> traffic JSON)
 """
 from __future__ import annotations
 
@@ -47,7 +52,16 @@ ROOFLINE_KERNEL = {"fp64": "k_arn_project<double, double>",
                    "mixed32": "k_arn_project<float, float>"}
 WORKLOAD_C2 = ("1024x512 free-flow + 1024x512 porous cells (N=2097152), lognormal K seed 2, "
                "BGS(SA-AMG V-cycle, mu*Mp^-1, SA-AMG V-cycle) + FGMRES(m), rel. residual 1e-8")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_arnoldi_project_c1.json")
+
+
+def traffic_file(config):
+    return os.path.join(ROOT, "profiles", f"traffic_arnoldi_project_{config.lower()}.json")
+
+
+def kernels_sha():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2108_13229_amd", "csrc", "kernels.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()
 
 
 def parse():
@@ -55,7 +69,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="C1", choices=["C1", "C2", "T1", "C4", "P1"])
+    ap.add_argument("--config", default="C2", choices=["C1", "C2", "T1", "C4", "P1"])
     ap.add_argument("--paper-n", type=int, default=128,
                     help="P1: cells per unit length of the paper's geometry")
     ap.add_argument("--dn-sub-tol", type=float, default=1e-13,
@@ -77,8 +91,18 @@ def parse():
                     help="the monolithic preconditioner variants of the paper's Table 2 "
                          "(pv-BJ/BGS with AMG, td-BJ/BGS with Uzawa and AMG) on the workload")
     ap.add_argument("--counter-run", action="store_true",
-                    help="one FP64 solve with plain (non-graph) launches plus a 512 MiB "
-                         "device copy, for hardware-counter passes")
+                    help="one solve (headline precision) with plain (non-graph) launches plus "
+                         "a 512 MiB device copy, for hardware-counter passes")
+    ap.add_argument("--counter-out", default=None,
+                    help="--counter-run: where to write the run's launches and algorithmic "
+                         "bytes (JSON); --summarize-counters: where to read them")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="turn two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) of "
+                         "--counter-run into the dominant kernel's HBM traffic (no GPU)")
+    ap.add_argument("--traffic-out", default=None)
+    ap.add_argument("--cpu-repeats", type=int, default=3)
+    ap.add_argument("--no-c1", action="store_true",
+                    help="C2: leave out the 512 x 256 solves reported beside the headline")
     return ap.parse_args()
 
 
@@ -130,13 +154,10 @@ def roofline_from(r, precision, config):
     achieved = r["bytes"] / r["seconds"] / 1e9
     traffic = None
     try:
-        import hashlib
-        with open(TRAFFIC_FILE) as f:
+        with open(traffic_file(config)) as f:
             t = json.load(f)
-        src = os.path.join(ROOT, "paper_2108_13229_amd", "csrc", "kernels.hip")
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if (t.get("kernels_hip_sha256") == sha and t.get("kernel") == ROOFLINE_KERNEL[precision]
-                and config == "C1"):
+        if (t.get("kernels_hip_sha256") == kernels_sha()
+                and t.get("kernel") == ROOFLINE_KERNEL[precision]):
             traffic = t["hbm_bytes_per_launch"]
     except (OSError, ValueError, KeyError):
         traffic = None
@@ -147,21 +168,88 @@ def roofline_from(r, precision, config):
             "alg_bytes_per_launch": r["bytes"] / r["launches"]}
 
 
-def counter_run(sd, p, restart):
+def counter_run(sd, p, restart, precision, config, out_path):
     """Kernels launched one by one (no graph replay) so that per-dispatch
     counters attach to each kernel; then a plain 512 MiB device-to-device copy
-    whose FETCH_SIZE / WRITE_SIZE calibrate the counters (64 Mi doubles)."""
+    whose FETCH_SIZE / WRITE_SIZE calibrate the counters (64 Mi doubles).  The
+    solve's launches of the dominant kernel and their algorithmic bytes go to
+    out_path for --summarize-counters."""
     import torch
     P = sd.Problem(p, device=True)
-    S = sd.Solver(P, precond="BGS", schur="mass", tol=1e-8, restart=restart)
+    S = sd.Solver(P, precond="BGS", schur="mass", tol=1e-8, restart=restart,
+                  precision=precision)
     S.profile("arnoldi_spmv")
     x, st, rc = S.solve()
     torch.cuda.synchronize()
+    r = S.profile_read()
     a = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
     b.copy_(a)
     torch.cuda.synchronize()
-    print(json.dumps({"counter_run": True, "iters": st["iters"], "copy_bytes": a.numel() * 8}))
+    rec = {"counter_run": True, "config": config, "precision": precision,
+           "kernel": ROOFLINE_KERNEL[precision], "iters": st["iters"],
+           "launches": r["launches"], "alg_bytes_per_launch": r["bytes"] / r["launches"],
+           "copy_bytes": a.numel() * 8, "kernels_hip_sha256": kernels_sha()}
+    if out_path:
+        with open(out_path, "w") as f:
+            json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
+
+
+def _counter_rows(d, counter):
+    """(kernel name, value) per dispatch from a rocprofv3 --pmc CSV tree."""
+    import csv
+    import glob
+    files = sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True))
+    if not files:
+        raise SystemExit(f"no *counter_collection.csv under {d}")
+    rows = []
+    for fn in files:
+        with open(fn) as f:
+            for rec in csv.DictReader(f):
+                if rec.get("Counter_Name") == counter:
+                    rows.append((int(rec.get("Dispatch_Id") or 0), rec["Kernel_Name"],
+                                 float(rec["Counter_Value"])))
+    return [(n, v) for _, n, v in sorted(rows, key=lambda t: t[0])]
+
+
+def summarize_counters(fetch_dir, write_dir, run_json, out_json):
+    """HBM traffic per launch of the dominant kernel from two counter passes
+    of --counter-run (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each
+    scaled by the reading of the 512 MiB copy that ends the run.  Launches
+    that returned at once (enqueued ahead of the cycle's end: a reading below
+    1 % of the median) are left out, and of the others the first as many as
+    the run timed (columns j = 0 .. k-1 of the cycle; the launch that closes
+    the last column is not in the algorithmic bytes either)."""
+    with open(run_json) as f:
+        run = json.load(f)
+    kern = run["kernel"]
+    out = {"kernel": kern, "workload": f"{run['config']} {run['precision']} restart 60, "
+                                       f"one solve ({run['launches']} launches)"}
+    for counter, d, key in (("FETCH_SIZE", fetch_dir, "fetch"), ("WRITE_SIZE", write_dir,
+                                                                  "write")):
+        rows = _counter_rows(d, counter)
+        copy = [v for n, v in rows if "copyBuffer" in n]
+        vals = np.array([v for n, v in rows if kern in n])
+        if not copy or vals.size == 0:
+            raise SystemExit(f"{counter}: copy kernel or {kern} not found in {d}")
+        keep = vals[vals >= 0.01 * np.median(vals)][:run["launches"]]
+        scale = run["copy_bytes"] / (max(copy) * 1024.0)
+        out[f"{key}_size_kib_per_launch_raw"] = float(keep.mean())
+        out[f"{key}_launches_counted"] = int(keep.size)
+        out[f"{key}_scale"] = scale
+        out[f"{key}_copy_kib"] = max(copy)
+        out[f"{key}_bytes_per_launch"] = float(keep.mean()) * 1024.0 * scale
+    out["copy_bytes"] = run["copy_bytes"]
+    out["hbm_bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]
+    out["alg_bytes_per_launch"] = run["alg_bytes_per_launch"]
+    out["traffic_over_algorithmic"] = out["hbm_bytes_per_launch"] / run["alg_bytes_per_launch"]
+    out["kernels_hip_sha256"] = run["kernels_hip_sha256"]
+    if out["kernels_hip_sha256"] != kernels_sha():
+        print("warning: kernels.hip changed since the counter run", file=sys.stderr)
+    with open(out_json, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
 
 
 def replay(sd, probs, arrivals, slots, **opts):
@@ -495,7 +583,8 @@ def variants(sd, args, p):
     if roof is not None:
         roof["row"] = "pv-BGS(AMG,AMG), mu*Mp^-1 (default)"
     if not args.no_cpu:
-        base, _, _ = cpu_baseline(p, args.restart, timed=True, reference=False)
+        base, _, _, _ = cpu_baseline(p, args.restart, timed=True, reference=False,
+                                     repeats=args.cpu_repeats)
         base["row"] = "pv-BGS(AMG,AMG), mu*Mp^-1 (default)"
         out["cpu_baseline"] = base
     print(json.dumps(out))
@@ -618,37 +707,127 @@ def p1_cpu_baseline(n, dt, steps, restart):
                        f"same preconditioner, set-up excluded), 1 thread")
 
 
-def cpu_baseline(p, restart, timed=True, reference=True):
-    """The oracle's FP64 FGMRES with the same preconditioner, one solve,
-    single-threaded (setup excluded; timed separately); then, with every
-    host thread, the oracle's reference solution (FGMRES to relative
-    residual 1e-12) for the per-block errors of the GPU solutions."""
+def host_info():
+    """CPU model, logical CPUs and the CPUs this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = None
+    return {"cpu_model": model, "nproc": os.cpu_count(), "cpus_available": affinity}
+
+
+def _blas_threads():
+    from threadpoolctl import threadpool_info
+    n = [i.get("num_threads", 1) for i in threadpool_info()]
+    return max(n) if n else 1
+
+
+def cpu_baseline(p, restart, timed=True, reference=True, repeats=3):
+    """The oracle's FP64 FGMRES with the same preconditioner: set-up once on
+    one thread (assembly + AMG, timed separately), then `repeats` full solves
+    on one thread (median: the value) and `repeats` with every thread the
+    host allows (the oracle's sparse products are single-threaded in SciPy;
+    only its dense steps use more).  Also returns the oracle's iterate at the
+    same tolerance and, with reference, its FGMRES to relative residual 1e-12
+    for the per-block errors of the GPU solutions."""
     from threadpoolctl import threadpool_limits
     from oracle import krylov, precond
     from oracle.assemble import assemble
-    base = None
+    base, x_same = None, None
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         a = assemble(p)
         M = precond.build(p, a, "BGS")
         t_setup = time.perf_counter() - t0
         if timed:
+            ts = []
+            for _ in range(max(1, repeats)):
+                t0 = time.perf_counter()
+                r = krylov.fgmres(a.A, a.b, M, tol=1e-8, m=restart)
+                ts.append(time.perf_counter() - t0)
+            x_same = r.x
+            t1 = float(np.median(ts))
+            base = dict(value=1.0 / t1, unit="solves/s", cores=1, kind="oracle",
+                        sample=f"{len(ts)} full FP64 solves of the same workload (oracle FGMRES, "
+                               f"same preconditioner, {r.iters} iterations; median "
+                               f"{t1:.2f} s, all {', '.join(f'{t:.2f}' for t in ts)} s; "
+                               f"assembly + AMG setup {t_setup:.1f} s not included), 1 thread",
+                        median_s=t1, runs_s=ts, setup_s=t_setup, iters=r.iters, **host_info())
+    if timed:
+        ts = []
+        for _ in range(max(1, repeats)):
             t0 = time.perf_counter()
-            r = krylov.fgmres(a.A, a.b, M, tol=1e-8, m=restart)
-            t_solve = time.perf_counter() - t0
-            base = dict(value=1.0 / t_solve, unit="solves/s", cores=1, kind="oracle",
-                        sample=f"one full FP64 solve of the same workload (oracle FGMRES, "
-                               f"{r.iters} iterations, {t_solve:.1f} s; assembly+AMG setup "
-                               f"{t_setup:.1f} s not included), 1 thread")
+            krylov.fgmres(a.A, a.b, M, tol=1e-8, m=restart)
+            ts.append(time.perf_counter() - t0)
+        base["all_threads"] = dict(value=1.0 / float(np.median(ts)), unit="solves/s",
+                                   threads=_blas_threads(), median_s=float(np.median(ts)),
+                                   runs_s=ts)
     if not reference:
-        return base, None, None
+        return base, None, None, x_same
     ref = krylov.fgmres(a.A, a.b, M, tol=1e-12, m=restart, maxit=5000)
     rel = float(np.linalg.norm(a.b - a.A @ ref.x) / np.linalg.norm(a.b))
-    return base, ref.x, f"oracle FP64 FGMRES to relative residual {rel:.1e} ({ref.iters} iterations)"
+    return (base, ref.x,
+            f"oracle FP64 FGMRES to relative residual {rel:.1e} ({ref.iters} iterations)",
+            x_same)
+
+
+def direct_baseline(config="C1"):
+    """SciPy's SuperLU (sparse LU with COLAMD ordering; the analogue of the
+    paper's UMFPACK direct solver) on a workload, one factorisation and one
+    solve, on the threads the host allows."""
+    import scipy.sparse.linalg as spla
+    from oracle.assemble import assemble
+    from sdinputs import config_problem
+    a = assemble(config_problem(config))
+    A = a.A.tocsc()
+    t0 = time.perf_counter()
+    lu = spla.splu(A)
+    t1 = time.perf_counter()
+    x = lu.solve(a.b)
+    t2 = time.perf_counter()
+    rel = float(np.linalg.norm(a.b - a.A @ x) / np.linalg.norm(a.b))
+    return dict(kind="SciPy SuperLU", workload=config, N=int(a.N), nnz=int(A.nnz),
+                factor_s=t1 - t0, solve_s=t2 - t1, solves_per_s=1.0 / (t2 - t0),
+                nnz_LU=int(lu.L.nnz + lu.U.nnz), rel_res=rel)
+
+
+def headline_solves(sd, P, precs, args, roof_prec, config):
+    """args.warmup + args.steps solves per precision on one problem; the
+    dominant kernel's roofline for roof_prec."""
+    res, xs, roof = {}, {}, None
+    for prec in precs:
+        t0 = time.perf_counter()
+        S = sd.Solver(P, precond="BGS", schur="mass", tol=1e-8, restart=args.restart,
+                      precision=prec)
+        t_setup = time.perf_counter() - t0
+        lat, its, st, x = run_solves(S, args.steps, args.warmup)
+        xs[prec] = x
+        res[prec] = dict(solves_per_s=float(len(lat) / lat.sum()),
+                         ms_per_solve=float(1e3 * lat.mean()),
+                         p50_ms=float(1e3 * np.percentile(lat, 50)),
+                         p99_ms=float(1e3 * np.percentile(lat, 99)),
+                         iters=int(np.median(its)), restarts=st["restarts"],
+                         rel_res=st["rel_res"], setup_s=t_setup)
+        if prec == roof_prec and args.roofline_solves > 0:
+            roof = roofline(S, args.roofline_solves, prec, config)
+        S.close()
+    return res, xs, roof
 
 
 def main():
     args = parse()
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters, args.counter_out, args.traffic_out)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the solver has no multi-GPU path", file=sys.stderr)
@@ -676,34 +855,17 @@ def main():
     if args.variants:
         variants(sd, args, p)
         return
-    if args.counter_run:
-        counter_run(sd, p, args.restart)
-        return
     headline = args.precision or ("fp64" if args.config == "C1" else "mixed")
+    if args.counter_run:
+        counter_run(sd, p, args.restart, headline, args.config, args.counter_out)
+        return
     t0 = time.perf_counter()
     P = sd.Problem(p, device=True)
     t_asm = time.perf_counter() - t0
-    res, xs = {}, {}
-    roof = None
     precs = ["fp64"] if args.no_mixed else ["fp64", "mixed", "mixed32"]
     if headline not in precs:
         precs.append(headline)
-    for prec in precs:
-        t0 = time.perf_counter()
-        S = sd.Solver(P, precond="BGS", schur="mass", tol=1e-8, restart=args.restart,
-                      precision=prec)
-        t_setup = time.perf_counter() - t0
-        lat, its, st, x = run_solves(S, args.steps, args.warmup)
-        xs[prec] = x
-        res[prec] = dict(solves_per_s=float(len(lat) / lat.sum()),
-                         ms_per_solve=float(1e3 * lat.mean()),
-                         p50_ms=float(1e3 * np.percentile(lat, 50)),
-                         p99_ms=float(1e3 * np.percentile(lat, 99)),
-                         iters=int(np.median(its)), restarts=st["restarts"],
-                         rel_res=st["rel_res"], setup_s=t_setup)
-        if prec == headline and args.roofline_solves > 0:
-            roof = roofline(S, args.roofline_solves, prec, args.config)
-        S.close()
+    res, xs, roof = headline_solves(sd, P, precs, args, headline, args.config)
     head = res[headline]
     out = {
         "metric": "Stokes-Darcy solves/s to rel. residual 1e-8 (mixed vs FP64), p50/p99 latency",
@@ -728,9 +890,20 @@ def main():
         "mixed32": res.get("mixed32"),
         "roofline": roof,
     }
+    if args.config == "C2" and not args.no_c1:
+        # the 512 x 256 workload with the same solvers, beside the headline
+        from sdinputs import config_problem as cp
+        P1 = sd.Problem(cp("C1"), device=True)
+        r1, _, roof1 = headline_solves(sd, P1, ["fp64", "mixed"], args, "fp64", "C1")
+        out["c1"] = {"workload": WORKLOAD, "N": P1.N, "nnz": P1.nnz, **r1, "roofline": roof1}
+        P1.close()
     if not args.no_cpu:
-        base, ref, ref_kind = cpu_baseline(p, args.restart, timed=args.config in ("C1", "C2"))
+        base, ref, ref_kind, x_same = cpu_baseline(p, args.restart,
+                                                   timed=args.config in ("C1", "C2"),
+                                                   repeats=args.cpu_repeats)
         if base is not None:
+            if args.config == "C2":
+                base["direct"] = direct_baseline("C1")
             out["cpu_baseline"] = base
         off = P.block_off
         acc = {"reference": ref_kind, "blocks": ["velocity", "free-flow pressure",
@@ -738,6 +911,11 @@ def main():
         for prec, x in xs.items():
             acc[prec] = block_errors(x, ref, off)
         acc["mixed_vs_fp64"] = block_errors(xs.get("mixed", xs[headline]), xs["fp64"], off)
+        if x_same is not None:
+            # parity: each GPU iterate against the oracle's own FGMRES iterate at
+            # the same tolerance and restart
+            acc["vs_oracle_iterate_same_tol"] = {prec: block_errors(x, x_same, off)
+                                                 for prec, x in xs.items()}
         # tolerance at which the FP64 solve's error is <= 1e-8 in every block
         need = None
         for tol in (1e-9, 1e-10, 1e-11):

@@ -66,7 +66,11 @@ typedef struct sd_solver sd_solver;
 typedef struct sd_server sd_server;
 
 /* Device-memory callbacks (e.g. a framework's caching allocator).  NULL for
- * the library default (hipMalloc / hipFree).  alloc returns NULL on failure. */
+ * the library default (the stream-ordered pool: hipMallocAsync /
+ * hipFreeAsync).  alloc returns NULL on failure; the library takes memory in
+ * chunks of 32 MiB (larger arrays get their own) and returns each chunk with
+ * free, on the stream it was allocated on, once the handle that owns it is
+ * destroyed and its work has finished. */
 typedef struct {
   void* (*alloc)(size_t bytes, void* ctx, void* hip_stream);
   void (*free)(void* ptr, void* ctx, void* hip_stream);
@@ -166,7 +170,19 @@ int sd_problem_info(const sd_problem* pb, int64_t* N, int64_t block_off[5],
 int sd_problem_csr(const sd_problem* pb, const int64_t** rowptr,
                    const int32_t** col, const double** val, const double** b);
 
-enum { SD_KRYLOV_FGMRES = 0, SD_KRYLOV_BICGSTAB = 1 };
+/* Outer Krylov methods (the solvers of the Sec. 5 setup): flexible GMRES(m)
+ * with a fixed restart length; BiCGSTAB; PD-GMRES, the outer solver of every
+ * iterative row of the paper's Table 2 (Cuevas Nunez, Schaerer, Bhaya 2018),
+ * flexible GMRES whose restart length is set before each cycle from the
+ * true residual norms r_j at the restarts:
+ *   m_{j+1} = m_j + floor(alpha_p r_j/r_{j-1}
+ *                         + alpha_d (r_j - r_{j-2})/(2 r_{j-1}))
+ * (derivative term from the third restart on; the first cycle takes
+ * pd_m_init); when m_{j+1} < pd_m_min, pd_m_init grows by pd_m_step and
+ * m_{j+1} = pd_m_init; lengths are capped at restart (the basis capacity).
+ * The paper fixes m_init = m_min = 3, m_step = 5; the gains (defaults
+ * alpha_p = -3, alpha_d = 5) are this library's reading. */
+enum { SD_KRYLOV_FGMRES = 0, SD_KRYLOV_BICGSTAB = 1, SD_KRYLOV_PDGMRES = 2 };
 /* Block preconditioners (Sec. 4): the pressure-velocity block-Jacobi and
  * block-Gauss-Seidel forms P^pv_BJ / P^pv_BGS, and the two-domain forms
  * P^td_BJ / P^td_BGS whose free-flow block A' = [[V, B], [C, 0]] is
@@ -208,7 +224,8 @@ enum { SD_DARCY_AMG = 0, SD_DARCY_ILU0 = 1 };
 
 typedef struct {
   int krylov;        /* SD_KRYLOV_*                                            */
-  int restart;       /* FGMRES restart length m (1..63), default 30            */
+  int restart;       /* FGMRES restart length m (1..63), default 30; the
+                        largest PD-GMRES cycle                                 */
   int maxit;         /* total iteration cap, default 1000                      */
   double tol;        /* relative true FP64 residual ||b-Ax||/||b||             */
   int precond;       /* SD_PREC_BJ | SD_PREC_BGS | SD_PREC_TD_BJ | SD_PREC_TD_BGS */
@@ -222,14 +239,24 @@ typedef struct {
   int coarse_max;    /* coarsest level size bound (dense inverse), default 2048 */
   int max_levels;    /* default 20                                             */
   int darcy;         /* SD_DARCY_AMG (default) | SD_DARCY_ILU0                 */
+  int pd_m_init, pd_m_min, pd_m_step;   /* PD-GMRES: defaults 3, 3, 5          */
+  double pd_alpha_p, pd_alpha_d;        /* PD-GMRES gains: defaults -3, 5      */
 } sd_solver_opts;
 
 /* Fill opts with the defaults above. */
 void sd_solver_opts_default(sd_solver_opts* opts);
 
-/* Build the AMG hierarchies for V and for the Darcy block
- * D~ = D' - C1' diag(V)^-1 B1' (host, deterministic) and upload them with the
- * block preconditioner's operators and the Krylov workspace. */
+/* Set up the preconditioned Krylov solver of an assembled problem: the
+ * aggregation-AMG hierarchies of the Sec. 5 solver setup (one V-cycle per
+ * sub-solve) for the velocity block V and for the Darcy block
+ * D~ = D' - C1' diag(V)^-1 B1' (built on the host, deterministically), the
+ * operators of the Sec. 4 block preconditioner selected by opts (NULL = the
+ * defaults of sd_solver_opts_default) and the Krylov workspace, all uploaded
+ * to the problem's device through the allocator given to sd_assemble.  The
+ * handle keeps a pointer to pb, which must outlive it.  SD_E_INVALID for
+ * options out of range, a problem assembled by sd_assemble_host, or more
+ * than 16,777,216 unknowns (the row-block limit of the Gram-Schmidt
+ * kernels); SD_E_NOMEM when a device allocation fails. */
 int sd_setup(sd_problem* pb, const sd_solver_opts* opts, sd_solver** out);
 
 /* Host-only setup (no device work), for inspection. */
@@ -265,11 +292,16 @@ typedef struct {
   double t_setup, t_solve;   /* seconds                                     */
 } sd_stats;
 
-/* Solve A x = b.  d_b: device FP64 [N], or NULL for the assembled b.  d_x:
+/* Solve the coupled system A x = b of Sec. 2 with the Krylov method of the
+ * options (flexible GMRES(m) or BiCGSTAB, the solvers of the Sec. 5 setup),
+ * right-preconditioned by the block preconditioner of Sec. 4, to the
+ * relative true residual ||b - A x|| <= tol ||b|| (recomputed in FP64 at
+ * every restart).  d_b: device FP64 [N], or NULL for the assembled b.  d_x:
  * device FP64 [N], the initial guess when use_x0 != 0 (else overwritten from
- * zero) and the result.  Runs on hip_stream (NULL = default) and returns
+ * zero) and the result; both are owned by the caller and must not alias.
+ * Ordered after the work already on hip_stream (NULL = default); returns
  * after the solve has finished.  SD_E_NOCONV still writes the best iterate
- * and stats. */
+ * and stats; SD_E_BREAKDOWN on a non-finite value. */
 int sd_solve(sd_solver* s, const double* d_b, double* d_x, int use_x0,
              sd_stats* stats, void* hip_stream);
 
@@ -311,9 +343,16 @@ int sd_apply_matrix(sd_solver* s, const double* d_x, double* d_y, void* hip_stre
 int sd_apply_preconditioner(sd_solver* s, const double* d_r, double* d_z,
                             void* hip_stream);
 /* x = one V-cycle on block (0 = V, 1 = D~, 2 = L_p) for right-hand side b
- * (device FP64 vectors of the block's size): */
+ * (device FP64 vectors of n entries; n must equal the block's size, the
+ * row count of its finest level, else SD_E_INVALID): */
 int sd_apply_vcycle(sd_solver* s, int block, const double* d_b, double* d_x,
-                    void* hip_stream);
+                    int64_t n, void* hip_stream);
+
+/* Row blocking of the Gram-Schmidt projection kernel for n unknowns: rows
+ * per workgroup, workgroups, and dynamic LDS bytes per workgroup (the block's
+ * rows of w and u_j in FP64).  SD_E_INVALID for n < 1 or n above the limit
+ * that sd_setup enforces.  Host-only inspection. */
+int sd_arnoldi_layout(int64_t n, int* rows_per_block, int* blocks, size_t* lds_bytes);
 
 /* Measurement: bracket every launch of one kernel class with HIP events
  * during subsequent sd_solve calls (those solves then launch kernels one by
@@ -388,7 +427,13 @@ typedef struct {
   int device;          /* HIP device ordinal                                 */
 } sd_server_opts;
 
-int sd_server_create(const sd_server_opts* opts, sd_server** out);
+/* Start the request loop on opts->device (opts NULL = defaults).  allocator:
+ * device memory of every request's matrices, hierarchies and Krylov state
+ * (NULL = the stream-ordered pool, hipMallocAsync); its callbacks may be
+ * called from the server's threads, with the device current, and must be
+ * thread-safe.  It must stay valid until sd_server_destroy returns. */
+int sd_server_create(const sd_server_opts* opts, const sd_allocator* allocator,
+                     sd_server** out);
 
 typedef struct {
   sd_grid grid;
@@ -401,7 +446,8 @@ typedef struct {
 
 /* Queue a solve.  All host data is copied.  SD_E_NOMEM if the request can
  * never fit the budget; SD_E_INVALID for a 3-D grid (the request loop serves
- * 2-D problems) or a krylov other than FGMRES. */
+ * 2-D problems) or SD_KRYLOV_BICGSTAB (the loop drives the restarted GMRES
+ * forms). */
 int sd_submit(sd_server* sv, const sd_request* req, uint64_t* ticket);
 
 enum { SD_REQ_PENDING = 0, SD_REQ_RUNNING = 1, SD_REQ_DONE = 2, SD_REQ_FAILED = 3 };

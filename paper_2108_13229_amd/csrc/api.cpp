@@ -79,6 +79,11 @@ void sd_solver_opts_default(sd_solver_opts* o) {
   o->coarse_max = 2048;
   o->max_levels = 20;
   o->darcy = SD_DARCY_AMG;
+  o->pd_m_init = 3;
+  o->pd_m_min = 3;
+  o->pd_m_step = 5;
+  o->pd_alpha_p = -3.0;
+  o->pd_alpha_d = 5.0;
 }
 
 static int assemble_impl(const sd_grid* grid, const sd_physics* phys, const sd_bcs* bcs,
@@ -310,18 +315,34 @@ int sd_apply_preconditioner(sd_solver* s, const double* d_r, double* d_z, void* 
   });
 }
 
-int sd_apply_vcycle(sd_solver* s, int block, const double* d_b, double* d_x, void* hip_stream) {
+int sd_apply_vcycle(sd_solver* s, int block, const double* d_b, double* d_x, int64_t n,
+                    void* hip_stream) {
   return guarded([&] {
     if (!s || !d_b || !d_x || block < 0 || block > 2) return fail(SD_E_INVALID, "bad argument");
     if (s->s->hh[block].levels.empty())
-      return fail(SD_E_INVALID, "block 2 exists only with SD_SCHUR_CC");
+      return fail(SD_E_INVALID, "the block has no hierarchy (block 2 exists only with "
+                                "SD_SCHUR_CC, block 1 not with SD_DARCY_ILU0)");
     if (!s->s->on_device) return fail(SD_E_INVALID, "solver has no device data");
+    const int64_t nb = s->s->hh[block].levels[0].A.n_rows;
+    if (n != nb)
+      return fail(SD_E_INVALID, "vector length " + std::to_string(n) + " != block size " +
+                                    std::to_string(nb));
     hipStream_t st = (hipStream_t)hip_stream;
     s->s->prec->apply_vcycle(*s->s, block, d_b, d_x, st);
     SD_HIP(hipGetLastError());
     SD_HIP(hipStreamSynchronize(st));
     return (int)SD_OK;
   });
+}
+
+int sd_arnoldi_layout(int64_t n, int* rows_per_block, int* blocks, size_t* lds_bytes) {
+  if (n < 1 || n > sd::kMaxUnknowns)
+    return fail(SD_E_INVALID, "n must be in 1.." + std::to_string(sd::kMaxUnknowns));
+  const int rp = sd::gs_rows_per_block((int)n, sd::kGsProjectRows);
+  if (rows_per_block) *rows_per_block = rp;
+  if (blocks) *blocks = (int)((n + rp - 1) / rp);
+  if (lds_bytes) *lds_bytes = (size_t)2 * rp * sizeof(double);
+  return SD_OK;
 }
 
 int sd_solver_profile(sd_solver* s, int kernel_class) {

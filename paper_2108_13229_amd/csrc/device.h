@@ -11,7 +11,11 @@ constexpr int kMaxBasis = 64;       // FGMRES basis vectors (restart m <= 63)
 constexpr int kBlock = 256;         // threads per workgroup (4 wavefronts)
 constexpr int kDotBlocks = 512;     // workgroups of the fused reduction kernels
 constexpr int kPartStride = kMaxBasis + 4;   // partial-sum rows (k-major, kDotBlocks each)
-constexpr int kGsMaxBlocks = 1024;          // row blocks of the Gram-Schmidt kernels
+constexpr int kGsMaxBlocks = 4096;          // row blocks of the Gram-Schmidt kernels
+constexpr int kGsProjectRows = 1024;        // preferred rows per projection workgroup
+constexpr int kGsMaxRowsPerBlock = 4096;    // rows per projection workgroup (LDS: 16 B each)
+// largest system the Gram-Schmidt kernels take (sd_setup rejects more)
+constexpr int64_t kMaxUnknowns = (int64_t)kGsMaxBlocks * kGsMaxRowsPerBlock;
 // partial-sum rows of the Gram-Schmidt kernels (kGsMaxBlocks each):
 // V^T u at kGsRowA, V^T w at kGsRowB, then u.u, u.w, w.w
 constexpr int kGsRowA = 0, kGsRowB = kMaxBasis, kGsRowC = 2 * kMaxBasis;
@@ -73,6 +77,10 @@ struct DevState {
   double rho, alpha, omega, bbeta, dots[8];
   unsigned int counter[8];
 };
+
+// Rows per workgroup of the Gram-Schmidt kernels for n rows (base: the
+// preferred count); n <= kMaxUnknowns gives at most kGsMaxBlocks blocks.
+int gs_rows_per_block(int n, int base);
 
 // Optional per-slot host flags written by the device (mapped pinned memory).
 struct HostFlags {

@@ -1312,21 +1312,23 @@ void launch_add(const T* a, T* y, int n, const DevState* gate, hipStream_t s) {
 
 // Rows per workgroup: the projection kernel takes 1024 (two workgroups per
 // CU overlap one's latency-bound product phase with the other's streaming),
-// the update kernel 2048; both grow when the partial sums would exceed
-// kGsMaxBlocks workgroups.
+// the update kernel 2048; both double while a launch would have more than
+// 1024 workgroups, up to kGsMaxRowsPerBlock rows (64 KiB of LDS in the
+// projection), and beyond that the grid grows, up to kGsMaxBlocks workgroups
+// (the partial-sum capacity) at kMaxUnknowns rows.
 int gs_rows_per_block(int n, int base) {
   int rpb = base;
-  while ((n + rpb - 1) / rpb > kGsMaxBlocks) rpb *= 2;
+  while ((n + rpb - 1) / rpb > 1024 && rpb < kGsMaxRowsPerBlock) rpb *= 2;
   return rpb;
 }
-constexpr int kProjectRows = 1024, kUpdateRows = 2048;
+constexpr int kUpdateRows = 2048;
 
 template <typename TM, typename TZ>
 void launch_arnoldi_step(const Sell<TM>& A, const TZ* z, double* W, double* V, int64_t ldv, int j,
                          DevState* st, double* part, HostFlags* hf, hipStream_t s, int prof_class,
                          hipEvent_t* ev) {
   const int n = A.n_rows;
-  const int rp = gs_rows_per_block(n, kProjectRows), ru = gs_rows_per_block(n, kUpdateRows);
+  const int rp = gs_rows_per_block(n, kGsProjectRows), ru = gs_rows_per_block(n, kUpdateRows);
   const int np = (n + rp - 1) / rp, nu = (n + ru - 1) / ru;
   if (ev && prof_class == 1) (void)hipEventRecord(ev[0], s);
   k_arn_project<TM, TZ><<<np, kGsThreads, (size_t)2 * rp * sizeof(double), s>>>(
@@ -1340,7 +1342,7 @@ void launch_arnoldi_step(const Sell<TM>& A, const TZ* z, double* W, double* V, i
 
 void launch_arnoldi_close(int n, double* V, int64_t ldv, int j, DevState* st, double* part,
                           HostFlags* hf, hipStream_t s) {
-  const int rp = gs_rows_per_block(n, kProjectRows);
+  const int rp = gs_rows_per_block(n, kGsProjectRows);
   const int np = (n + rp - 1) / rp;
   k_arn_project<double, double><<<np, kGsThreads, (size_t)2 * rp * sizeof(double), s>>>(
       Sell<double>{}, nullptr, nullptr, V, ldv, n, j, rp, 0, st, part);

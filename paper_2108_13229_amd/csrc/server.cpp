@@ -89,6 +89,7 @@ double now_s() {
 
 struct sd_server {
   sd_server_opts opts{};
+  sd_allocator alloc{};            // device memory of the requests (alloc.alloc NULL: pool)
   size_t budget = 0;
   std::mutex mu;
   std::condition_variable cv_prep, cv_done, cv_sched;
@@ -155,7 +156,7 @@ void sd_server::prep_loop(hipStream_t prep_stream) {
       r->N = r->hp->L.N;
       r->solver.reset(new sd::Solver());
       r->solver->setup_host(r->hp.get(), &r->opts);
-      r->solver->upload(nullptr, prep_stream);
+      r->solver->upload(alloc.alloc ? &alloc : nullptr, prep_stream);
       r->d_x = r->solver->mem->array<double>((size_t)r->N);
     } catch (const sd::Error& e) {
       code = e.code;
@@ -279,9 +280,11 @@ void sd_server::sched_loop() {
 
 extern "C" {
 
-int sd_server_create(const sd_server_opts* opts, sd_server** out) {
+int sd_server_create(const sd_server_opts* opts, const sd_allocator* allocator,
+                     sd_server** out) {
   if (!out) return SD_E_INVALID;
   *out = nullptr;
+  if (allocator && (!allocator->alloc) != (!allocator->free)) return SD_E_INVALID;
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
     (void)hipGetLastError();
@@ -291,6 +294,7 @@ int sd_server_create(const sd_server_opts* opts, sd_server** out) {
   s->opts.hbm_budget = opts ? opts->hbm_budget : 0;
   s->opts.max_slots = (opts && opts->max_slots > 0) ? opts->max_slots : 8;
   s->opts.device = opts ? opts->device : 0;
+  if (allocator && allocator->alloc) s->alloc = *allocator;
   if (s->opts.device < 0 || s->opts.device >= n) return SD_E_INVALID;
   if (hipSetDevice(s->opts.device) != hipSuccess) return SD_E_DEVICE;
   size_t free_b = 0, total_b = 0;
@@ -318,7 +322,7 @@ int sd_submit(sd_server* sv, const sd_request* req, uint64_t* ticket) {
   const sd_grid& g = req->grid;
   if (g.nx < 2 || g.ny < 2 || g.ny_pm < 1) return SD_E_INVALID;
   if (g.nz != 0) return SD_E_INVALID;   // the request loop serves 2-D problems
-  if (req->opts.krylov != SD_KRYLOV_FGMRES) return SD_E_INVALID;  // resumable driver
+  if (req->opts.krylov == SD_KRYLOV_BICGSTAB) return SD_E_INVALID;  // resumable driver
   std::unique_ptr<Request> r(new Request());
   r->grid = g;
   r->phys = req->phys;

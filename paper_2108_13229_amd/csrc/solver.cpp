@@ -215,8 +215,14 @@ void Solver::setup_host(HostProblem* p, const sd_solver_opts* o) {
   if (so.precision != SD_PRECISION_FP64 && so.precision != SD_PRECISION_MIXED &&
       so.precision != SD_PRECISION_MIXED32)
     throw Error(SD_E_INVALID, "precision");
-  if (so.krylov != SD_KRYLOV_FGMRES && so.krylov != SD_KRYLOV_BICGSTAB)
+  if (so.krylov != SD_KRYLOV_FGMRES && so.krylov != SD_KRYLOV_BICGSTAB &&
+      so.krylov != SD_KRYLOV_PDGMRES)
     throw Error(SD_E_INVALID, "krylov");
+  if (so.krylov == SD_KRYLOV_PDGMRES &&
+      (so.pd_m_init < 1 || so.pd_m_min < 1 || so.pd_m_step < 0 ||
+       !std::isfinite(so.pd_alpha_p) || !std::isfinite(so.pd_alpha_d)))
+    throw Error(SD_E_INVALID, "PD-GMRES needs pd_m_init, pd_m_min >= 1, pd_m_step >= 0 and "
+                              "finite gains");
   if (so.amg != SD_AMG_PLAIN && so.amg != SD_AMG_SMOOTHED) throw Error(SD_E_INVALID, "amg");
   if (so.darcy != SD_DARCY_AMG && so.darcy != SD_DARCY_ILU0) throw Error(SD_E_INVALID, "darcy");
   opts.amg.theta = so.theta;
@@ -229,6 +235,9 @@ void Solver::setup_host(HostProblem* p, const sd_solver_opts* o) {
   opts.amg.mis = so.mis;
 
   const Layout& L = p->L;
+  if (L.N > kMaxUnknowns)
+    throw Error(SD_E_INVALID, "more than " + std::to_string(kMaxUnknowns) +
+                                  " unknowns: beyond the row blocking of the Gram-Schmidt kernels");
   off[0] = 0;
   off[1] = L.off_v;
   off[2] = L.off_p;
@@ -379,6 +388,28 @@ double Solver::uzawa_relaxation(hipStream_t s) {
     for (int64_t r = 0; r < np_; ++r) x[r] = y[r] / lam;
   }
   return 1.0 / lam;
+}
+
+int pd_next_length(const sd_solver_opts& o, SolveRun& R, int m_cap) {
+  const std::vector<double>& r = R.pd_res;
+  const size_t k = r.size();
+  int m;
+  if (R.pd_m == 0 || k < 2) {
+    m = R.pd_m_init;
+  } else {
+    const double rj = r[k - 1], rj1 = r[k - 2];
+    double d = o.pd_alpha_p * rj / rj1;
+    if (k >= 3) d += o.pd_alpha_d * (rj - r[k - 3]) / (2.0 * rj1);
+    const double step = std::floor(d);
+    m = R.pd_m + (std::isfinite(step) ? (int)std::max(-1e6, std::min(1e6, step)) : 0);
+    if (m < o.pd_m_min) {
+      R.pd_m_init += o.pd_m_step;
+      m = R.pd_m_init;
+    }
+  }
+  m = std::max(1, std::min(m, m_cap));
+  R.pd_m = m;
+  return m;
 }
 
 int Solver::solve(const double* b, double* x, int use_x0, sd_stats* stats, hipStream_t s) {
@@ -660,6 +691,9 @@ class PrecImpl : public PrecBase {
     R.status = SD_E_NOCONV;
     R.t0 = wall_time();
     R.out = sd_stats{};
+    R.pd_res.clear();
+    R.pd_m = 0;
+    R.pd_m_init = S.opts.o.pd_m_init;
   }
 
   static bool ready(hipEvent_t e, bool block) {
@@ -746,7 +780,12 @@ class PrecImpl : public PrecBase {
           S.hf->est[j] = 0.0;
         }
         R.ctarget = std::max(hs.target, drop * hs.beta);
-        R.m_cycle = std::min(m, std::max(1, o.maxit - hs.iters));
+        int len = m;
+        if (o.krylov == SD_KRYLOV_PDGMRES) {
+          R.pd_res.push_back(hs.beta);
+          len = pd_next_length(o, R, m);
+        }
+        R.m_cycle = std::min(len, std::max(1, o.maxit - hs.iters));
         launch_init_cycle(S, R.m_cycle, s);
         R.j_enq = 0;
         R.completed = -1;
@@ -841,9 +880,12 @@ class PrecImpl : public PrecBase {
     }
     SD_HIP(hipGraphLaunch(graphs[(size_t)j], s));
   }
+  // The preconditioner kernels are gated on the cycle-done flag: a column
+  // enqueued ahead of a cycle's end stores nothing (the ILU(0) substitution
+  // returns at once).
   void enqueue_iteration(Solver& S, int j, hipStream_t s) {
     T* zj = Z + (size_t)j * ldz;
-    apply(S, S.V + (size_t)j * S.ldv, &S.st->sigma[j], zj, nullptr, s);
+    apply(S, S.V + (size_t)j * S.ldv, &S.st->sigma[j], zj, S.st, s);
     arnoldi(S, zj, j, s, 0, nullptr);
   }
   // w = A z_j with the FP64 matrix, or the FP32 copy under MIXED32

@@ -100,7 +100,15 @@ struct SolveRun {
   int m_cycle = 0, j_enq = 0, completed = -1;
   double ctarget = 0.0, t0 = 0.0;
   sd_stats out{};
+  // PD-GMRES: true residual norms at the restarts (newest last), the last
+  // cycle length (0 before the first) and the current m_init
+  std::vector<double> pd_res;
+  int pd_m = 0, pd_m_init = 0;
 };
+
+// Restart length of the next PD-GMRES cycle (the controller documented at
+// SD_KRYLOV_PDGMRES in sd.h) from R.pd_res; updates R.pd_m and R.pd_m_init.
+int pd_next_length(const sd_solver_opts& o, SolveRun& R, int m_cap);
 
 // ILU(0) of a square matrix (Meijerink & van der Vorst 1977; the Darcy
 // preconditioner of the paper's P^td(Uzawa, ILU(0)) rows, Sec. 5 solver

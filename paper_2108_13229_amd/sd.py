@@ -2,7 +2,9 @@
 
 Argument marshalling only: every step of assembly, setup and solve runs in
 the native library (host C++ for assembly and AMG setup, HIP kernels for the
-iteration).  PyTorch provides device memory and the current HIP stream.
+iteration).  PyTorch provides the device memory (its caching allocator is
+registered as the library's sd_allocator for problems, solvers, the
+partitioned coupling and the request loop) and the current HIP stream.
 The library must have been built (``python -m paper_2108_13229_amd.build``);
 there is no fallback.
 """
@@ -10,6 +12,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import threading
 from typing import Optional
 
 import numpy as np
@@ -20,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libsd.so")
 SD_OK, SD_E_INVALID, SD_E_NOMEM, SD_E_DEVICE = 0, -1, -2, -3
 SD_E_NOCONV, SD_E_BREAKDOWN, SD_E_BUSY, SD_E_NOTFOUND = -4, -5, -6, -7
 BC = {"velocity": 0, "traction": 1, "pressure": 2, "noflow": 3}
-KRYLOV = {"fgmres": 0, "bicgstab": 1}
+KRYLOV = {"fgmres": 0, "bicgstab": 1, "pdgmres": 2}
 PRECOND = {"BJ": 0, "BGS": 1, "TD_BJ": 2, "TD_BGS": 3}
 SCHUR = {"identity": 0, "mass": 1, "cc": 2}
 PRECISION = {"fp64": 0, "mixed": 1, "mixed32": 2}
@@ -59,8 +62,57 @@ class Forcing(C.Structure):
     _fields_ = [("f_u", _dp), ("f_v", _dp), ("q_pm", _dp), ("f_w", _dp)]
 
 
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
 class Allocator(C.Structure):
-    _fields_ = [("alloc", C.c_void_p), ("free", C.c_void_p), ("ctx", C.c_void_p)]
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", C.c_void_p)]
+
+
+# torch's caching allocator behind the library's sd_allocator.  The callbacks
+# may run on the library's own threads (the request loop prepares requests in
+# parallel); ctypes takes the GIL for them.  ctx carries the device ordinal.
+_alloc_lock = threading.Lock()
+_alloc_live = {}
+ALLOC_STATS = {"allocs": 0, "frees": 0, "bytes_allocated": 0, "bytes_live": 0}
+
+
+def _torch_alloc(nbytes, ctx, stream):
+    try:
+        import torch
+        ptr = torch.cuda.caching_allocator_alloc(int(nbytes), device=int(ctx or 0),
+                                                 stream=int(stream or 0))
+    except Exception:       # noqa: BLE001 - reported to the library as NULL
+        return None
+    with _alloc_lock:
+        ALLOC_STATS["allocs"] += 1
+        ALLOC_STATS["bytes_allocated"] += int(nbytes)
+        ALLOC_STATS["bytes_live"] += int(nbytes)
+        _alloc_live[int(ptr)] = int(nbytes)
+    return ptr
+
+
+def _torch_free(ptr, ctx, stream):
+    if not ptr:
+        return
+    try:
+        import torch
+        torch.cuda.caching_allocator_delete(int(ptr))
+    except Exception:       # noqa: BLE001 - interpreter shutdown
+        return
+    with _alloc_lock:
+        ALLOC_STATS["frees"] += 1
+        ALLOC_STATS["bytes_live"] -= _alloc_live.pop(int(ptr), 0)
+
+
+_ALLOC_CB = _ALLOC_FN(_torch_alloc)
+_FREE_CB = _FREE_FN(_torch_free)
+
+
+def torch_allocator(device: int = 0) -> Allocator:
+    """The sd_allocator that hands the library torch caching-allocator blocks."""
+    return Allocator(_ALLOC_CB, _FREE_CB, C.c_void_p(int(device)))
 
 
 class SolverOpts(C.Structure):
@@ -69,7 +121,9 @@ class SolverOpts(C.Structure):
                 ("precision", C.c_int), ("amg", C.c_int), ("mis", C.c_int),
                 ("theta", C.c_double), ("omega", C.c_double), ("nu_pre", C.c_int),
                 ("nu_post", C.c_int), ("coarse_max", C.c_int), ("max_levels", C.c_int),
-                ("darcy", C.c_int)]
+                ("darcy", C.c_int), ("pd_m_init", C.c_int), ("pd_m_min", C.c_int),
+                ("pd_m_step", C.c_int), ("pd_alpha_p", C.c_double),
+                ("pd_alpha_d", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -150,12 +204,15 @@ SIGNATURES = {
     "sd_dn_solve": (C.c_int, [_P, C.POINTER(DNOpts), _P, _P, C.POINTER(DNStats), _P]),
     "sd_dn_destroy": (None, [_P]),
     "sd_apply_preconditioner": (C.c_int, [_P, _P, _P, _P]),
-    "sd_apply_vcycle": (C.c_int, [_P, C.c_int, _P, _P, _P]),
+    "sd_apply_vcycle": (C.c_int, [_P, C.c_int, _P, _P, C.c_int64, _P]),
+    "sd_arnoldi_layout": (C.c_int, [C.c_int64, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                    C.POINTER(C.c_size_t)]),
     "sd_solver_profile": (C.c_int, [_P, C.c_int]),
     "sd_solver_middle_scale": (C.c_int, [_P, C.POINTER(C.c_double)]),
     "sd_solver_profile_read": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                          C.POINTER(C.c_double)]),
-    "sd_server_create": (C.c_int, [C.POINTER(ServerOpts), C.POINTER(_P)]),
+    "sd_server_create": (C.c_int, [C.POINTER(ServerOpts), C.POINTER(Allocator),
+                                   C.POINTER(_P)]),
     "sd_submit": (C.c_int, [_P, C.POINTER(Request), C.POINTER(C.c_uint64)]),
     "sd_poll": (C.c_int, [_P, C.c_uint64, C.POINTER(Result)]),
     "sd_wait": (C.c_int, [_P, C.c_uint64, C.c_double, C.POINTER(Result)]),
@@ -256,8 +313,10 @@ class Problem:
         g, ph, b, f, K = _marshal(p, keep)
         h = C.c_void_p()
         if device:
+            import torch
+            self._alloc = torch_allocator(torch.cuda.current_device())
             _check(lib().sd_assemble(C.byref(g), C.byref(ph), C.byref(b), K, C.byref(f),
-                                     None, _stream(), C.byref(h)))
+                                     C.byref(self._alloc), _stream(), C.byref(h)))
         else:
             _check(lib().sd_assemble_host(C.byref(g), C.byref(ph), C.byref(b), K, C.byref(f),
                                           C.byref(h)))
@@ -420,11 +479,20 @@ class Solver:
                                              C.c_void_p(z.data_ptr()), _stream()))
         return z
 
+    def block_size(self, block: int) -> int:
+        """Rows of the finest level of a block's hierarchy (0 = V, 1 = D~, 2 = L_p)."""
+        nr = C.c_int64()
+        _check(lib().sd_solver_level_csr(self.h, block, 0, 0, C.byref(nr), None, None, None,
+                                         None))
+        return nr.value
+
     def apply_vcycle(self, block: int, b):
         import torch
+        n = self.block_size(block)
+        _require(b, n)
         x = torch.empty_like(b)
         _check(lib().sd_apply_vcycle(self.h, block, C.c_void_p(b.data_ptr()),
-                                     C.c_void_p(x.data_ptr()), _stream()))
+                                     C.c_void_p(x.data_ptr()), n, _stream()))
         return x
 
     def middle_scale(self) -> float:
@@ -497,8 +565,9 @@ class Server:
 
     def __init__(self, max_slots: int = 8, hbm_budget: int = 0, device: int = 0):
         o = ServerOpts(hbm_budget, max_slots, device)
+        self._alloc = torch_allocator(device)
         h = C.c_void_p()
-        _check(lib().sd_server_create(C.byref(o), C.byref(h)))
+        _check(lib().sd_server_create(C.byref(o), C.byref(self._alloc), C.byref(h)))
         self.h = h
 
     def submit(self, p, **opts) -> int:
@@ -548,6 +617,13 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def arnoldi_layout(n: int):
+    """(rows per workgroup, workgroups, LDS bytes) of the Gram-Schmidt projection."""
+    rp, nb, lds = C.c_int(), C.c_int(), C.c_size_t()
+    _check(lib().sd_arnoldi_layout(int(n), C.byref(rp), C.byref(nb), C.byref(lds)))
+    return rp.value, nb.value, lds.value
 
 
 def _require(t, n):

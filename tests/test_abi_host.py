@@ -310,3 +310,23 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
         sd.lib()
     with pytest.raises(RuntimeError):
         sd.Problem(channel_problem(8, 4, seed=1), device=False)
+
+
+def test_arnoldi_row_blocking_stays_within_lds_and_partials():
+    """The Gram-Schmidt projection keeps a block's rows of w and u_j in LDS
+    (16 B per row): for every admissible size the blocks cover the rows, the
+    LDS stays within 64 KiB and the grid within the 4096 partial-sum slots;
+    sizes beyond the limit are rejected (so sd_setup refuses them before the
+    host set-up)."""
+    limit = 4096 * 4096
+    for n in (1, 63, 1024, 1025, 524_288, 1_048_577, 2_097_152, 2_207_232, 4_194_305,
+              8_388_608, 8_388_609, limit - 1, limit):
+        rp, nb, lds = sd.arnoldi_layout(n)
+        assert rp % 1024 == 0 and rp <= 4096
+        assert nb * rp >= n and (nb - 1) * rp < n
+        assert nb <= 4096
+        assert lds == 16 * rp and lds <= 64 * 1024
+    assert sd.arnoldi_layout(2_097_152)[:2] == (2048, 1024)   # the 1024x512 workload
+    for bad in (0, -5, limit + 1):
+        with pytest.raises(sd.SDError):
+            sd.arnoldi_layout(bad)

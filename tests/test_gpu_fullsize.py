@@ -1,0 +1,152 @@
+"""GPU parity at the full benchmark sizes (512x256 and 1024x512 cells per
+subdomain), in the launch configuration bench.py times.  At these sizes the
+finest velocity level takes the unfused level kernels (separate Jacobi
+sweeps, residual, SELL restriction and prolongation) that the small parity
+cases never reach, so the V-cycle, the block preconditioner and the whole
+FGMRES iterate are compared with the oracle element by element or block by
+block here."""
+import numpy as np
+import pytest
+
+from sdinputs import config_problem
+from oracle import amg, krylov, precond
+from oracle.assemble import assemble
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+sd = pytest.importorskip("paper_2108_13229_amd.sd")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    sd.lib()
+
+
+_CACHE = {}
+
+
+def _oracle(cfg):
+    """Assembled system and the oracle's P^pv_BGS(AMG, mu Mp^-1, AMG), once per
+    workload."""
+    if cfg not in _CACHE:
+        p = config_problem(cfg)
+        a = assemble(p)
+        _CACHE[cfg] = (p, a, precond.build(p, a, "BGS"))
+    return _CACHE[cfg]
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _blocks(off):
+    return ((off[0], off[2]), (off[2], off[3]), (off[3], off[4]))
+
+
+@pytest.mark.parametrize("cfg", ["C1", "C2"])
+def test_vcycle_full_size(cfg):
+    """One V-cycle on the velocity block and on the Darcy block: the finest
+    level runs Jacobi from zero (two sweeps fused), the residual, the
+    restriction as a SELL product, then prolongation and separate
+    post-sweeps; every entry within 1e-11 of the largest."""
+    p, a, M = _oracle(cfg)
+    print("case vcycle", cfg, flush=True)
+    P = sd.Problem(p, device=True)
+    S = sd.Solver(P, precond="BGS", schur="mass", tol=1e-8, restart=60)
+    rng = np.random.default_rng(21)
+    for blk, h in [(0, M.hV), (1, M.hD)]:
+        n = h.levels[0].A.shape[0]
+        assert S.block_size(blk) == n
+        b = rng.standard_normal(n)
+        x = _host(S.apply_vcycle(blk, _dev(b)))
+        ref = amg.vcycle(h, b)
+        assert np.max(np.abs(x - ref)) <= 1e-11 * np.max(np.abs(ref)), blk
+        assert np.linalg.norm(x - ref) <= 1e-12 * np.linalg.norm(ref), blk
+    # a right-hand side of the wrong length is refused before any launch
+    with pytest.raises(ValueError):
+        S.apply_vcycle(0, _dev(np.ones(3)))
+    S.close()
+    P.close()
+
+
+@pytest.mark.parametrize("cfg", ["C1", "C2"])
+@pytest.mark.parametrize("precision,bound", [("fp64", 1e-12), ("mixed", 1e-5)])
+def test_block_preconditioner_full_size_per_block(cfg, precision, bound):
+    """One application of P^pv_BGS: velocity V-cycle, block sweep with the
+    mu Mp^-1 middle block, Darcy V-cycle on the interface-corrected block;
+    each block against the oracle's (FP64; the FP32 preconditioner of the
+    mixed solver within FP32 accuracy)."""
+    p, a, M = _oracle(cfg)
+    print("case precond", cfg, precision, flush=True)
+    P = sd.Problem(p, device=True)
+    S = sd.Solver(P, precond="BGS", schur="mass", tol=1e-8, restart=60, precision=precision)
+    r = np.random.default_rng(23).standard_normal(a.N)
+    z = _host(S.apply_preconditioner(_dev(r)))
+    ref = M(r)
+    for lo, hi in _blocks(a.layout.block_off):
+        assert np.linalg.norm(z[lo:hi] - ref[lo:hi]) <= bound * np.linalg.norm(ref[lo:hi])
+    S.close()
+    P.close()
+
+
+_ITER = {}
+
+
+def _oracle_iterate(cfg):
+    """The oracle's FGMRES(60) iterate at relative residual 1e-8."""
+    if cfg not in _ITER:
+        p, a, M = _oracle(cfg)
+        _ITER[cfg] = krylov.fgmres(a.A, a.b, M, tol=1e-8, m=60)
+    return _ITER[cfg]
+
+
+@pytest.mark.parametrize("cfg", ["C1", "C2"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fgmres_iterate_full_size(cfg, precision):
+    """The benchmark's solve (FGMRES(60), P^pv_BGS, tolerance 1e-8) against
+    the oracle's FGMRES with the same preconditioner, restart and tolerance:
+    the same iteration count (+-1), the true residual checked with the
+    oracle's matrix, and every block within 1e-8 of the oracle's iterate."""
+    p, a, M = _oracle(cfg)
+    ref = _oracle_iterate(cfg)
+    print("case fgmres", cfg, precision, "oracle iters", ref.iters, flush=True)
+    P = sd.Problem(p, device=True)
+    S = sd.Solver(P, precond="BGS", schur="mass", tol=1e-8, restart=60, precision=precision)
+    x, st, rc = S.solve()
+    x = _host(x)
+    assert rc == sd.SD_OK
+    assert abs(st["iters"] - ref.iters) <= 1
+    res = np.linalg.norm(a.b - a.A @ x) / np.linalg.norm(a.b)
+    assert res <= 1e-8
+    assert abs(st["rel_res"] - res) <= 1e-3 * res
+    for lo, hi in _blocks(a.layout.block_off):
+        assert np.linalg.norm(x[lo:hi] - ref.x[lo:hi]) <= 1e-8 * np.linalg.norm(ref.x[lo:hi])
+    S.close()
+    P.close()
+
+
+def test_pdgmres_full_size():
+    """PD-GMRES on the 512x256 workload (cycles capped at 60): the GPU takes
+    the oracle's cycles and reaches its iterate per block."""
+    p, a, M = _oracle("C1")
+    ref, lengths = krylov.pd_fgmres(a.A, a.b, M, tol=1e-8, ctl=krylov.PDControl(m_max=60))
+    print("case pdgmres C1, oracle", ref.iters, "iterations in cycles", lengths, flush=True)
+    P = sd.Problem(p, device=True)
+    S = sd.Solver(P, krylov="pdgmres", precond="BGS", schur="mass", tol=1e-8, restart=60)
+    x, st, rc = S.solve()
+    x = _host(x)
+    assert rc == sd.SD_OK
+    assert st["restarts"] == ref.restarts and abs(st["iters"] - ref.iters) <= 1
+    assert np.linalg.norm(a.b - a.A @ x) <= 1e-8 * np.linalg.norm(a.b)
+    for lo, hi in _blocks(a.layout.block_off):
+        assert np.linalg.norm(x[lo:hi] - ref.x[lo:hi]) <= 1e-8 * np.linalg.norm(ref.x[lo:hi])
+    S.close()
+    P.close()

@@ -110,7 +110,9 @@ def test_block_preconditioner_parity(name, variant, schur):
     r = np.random.default_rng(5).standard_normal(a.N)
     z = _host(S.apply_preconditioner(_dev(r)))
     ref = M(r)
-    assert np.linalg.norm(z - ref) <= 1e-12 * np.linalg.norm(ref)
+    o = a.layout.block_off
+    for lo, hi in ((o[0], o[2]), (o[2], o[3]), (o[3], o[4])):
+        assert np.linalg.norm(z[lo:hi] - ref[lo:hi]) <= 1e-12 * np.linalg.norm(ref[lo:hi])
 
 
 def test_mixed_preconditioner_close_to_fp64():
@@ -220,25 +222,35 @@ def _block_errors(x, ref, off):
 def test_c1_errors_against_oracle_reference():
     """512x256: the oracle's FGMRES to relative residual 1e-12 is the FP64
     reference (itself within 1e-10 of SuperLU per block at this size).  At
-    tolerance 1e-8 every precision's per-block error stays below 1e-7; at
-    1e-9 the FP64 and mixed solutions are within 1e-8 of the reference."""
+    tolerance 1e-8 the method itself leaves a per-block error of up to
+    about 4e-8 (the oracle's own FGMRES iterate at 1e-8 has it), so the GPU
+    solutions are held to the oracle iterate's error per block (FP64 and
+    mixed: within 1e-9 of it; mixed32, whose cycles end at FP32 accuracy,
+    within 2e-7); at tolerance 1e-9 the FP64 and mixed solutions are within
+    1e-8 of the reference in every block."""
     p = config_problem("C1")
     a = assemble(p)
     M = precond.build(p, a, "BGS")
     ref = krylov.fgmres(a.A, a.b, M, tol=1e-12, m=60, maxit=5000)
     assert np.linalg.norm(a.b - a.A @ ref.x) <= 1e-12 * np.linalg.norm(a.b)
     off = a.layout.block_off
+    e_or = {tol: _block_errors(krylov.fgmres(a.A, a.b, M, tol=tol, m=60).x, ref.x, off)
+            for tol in (1e-8, 1e-9)}
     P = sd.Problem(p, device=True)
     xs = {}
-    for prec, tol, bound in (("fp64", 1e-8, 1e-7), ("mixed", 1e-8, 1e-7), ("mixed32", 1e-8, 2e-7),
-                             ("fp64", 1e-9, 1e-8), ("mixed", 1e-9, 1e-8)):
+    for prec, tol in (("fp64", 1e-8), ("mixed", 1e-8), ("mixed32", 1e-8), ("fp64", 1e-9),
+                      ("mixed", 1e-9)):
         S = sd.Solver(P, precond="BGS", tol=tol, restart=60, precision=prec)
         x, st, rc = S.solve()
         x = _host(x)
         print("C1", prec, tol, st, flush=True)
         assert rc == sd.SD_OK
         assert np.linalg.norm(a.b - a.A @ x) <= tol * np.linalg.norm(a.b)
-        assert max(_block_errors(x, ref.x, off)) <= bound
+        e = _block_errors(x, ref.x, off)
+        slack = 2e-7 if prec == "mixed32" else 1e-9
+        assert all(ek <= eo + slack for ek, eo in zip(e, e_or[tol]))
+        if tol == 1e-9 and prec != "mixed32":
+            assert max(e) <= 1e-8
         xs[(prec, tol)] = x
         S.close()
     # the FP32 preconditioner changes the iterate only at rounding level
@@ -349,3 +361,42 @@ def test_full_beavers_joseph_solve():
     with pytest.raises(sd.SDError) as e:
         sd.Partitioned(P)
     assert e.value.code == sd.SD_E_INVALID
+
+
+@pytest.mark.parametrize("name", ["channel96", "channel_ragged", "mms32"])
+def test_pdgmres_matches_oracle(name):
+    """PD-GMRES (the paper's Sec. 5 setting m_init = m_min = 3, m_step = 5):
+    the GPU solve takes the oracle's cycles (same count, iterations within
+    one) and reaches its iterate per block."""
+    p = SMALL[name]()
+    print("case pdgmres", name, flush=True)
+    a = assemble(p)
+    M = precond.build(p, a, "BGS")
+    ref, lengths = krylov.pd_fgmres(a.A, a.b, M, tol=1e-10, ctl=krylov.PDControl(m_max=30))
+    assert ref.converged and len(lengths) >= 3
+    P, S = _setup(p, krylov="pdgmres", tol=1e-10, restart=30)
+    x, st, rc = S.solve()
+    x = _host(x)
+    assert rc == sd.SD_OK
+    assert st["restarts"] == ref.restarts and abs(st["iters"] - ref.iters) <= 1
+    assert np.linalg.norm(a.b - a.A @ x) <= 1e-10 * np.linalg.norm(a.b)
+    o = a.layout.block_off
+    for lo, hi in ((o[0], o[2]), (o[2], o[3]), (o[3], o[4])):
+        assert np.linalg.norm(x[lo:hi] - ref.x[lo:hi]) <= 1e-8 * np.linalg.norm(ref.x[lo:hi])
+    # mixed precision under the same controller
+    P, S = _setup(p, krylov="pdgmres", tol=1e-10, restart=30, precision="mixed")
+    xm, stm, rc = S.solve()
+    assert rc == sd.SD_OK
+    xm = _host(xm)
+    assert np.linalg.norm(a.b - a.A @ xm) <= 1e-10 * np.linalg.norm(a.b)
+    assert np.linalg.norm(xm - ref.x) <= 1e-7 * np.linalg.norm(ref.x)
+
+
+def test_pdgmres_options_validated():
+    p = SMALL["tiny"]()
+    P = sd.Problem(p, device=True)
+    for bad in (dict(pd_m_init=0), dict(pd_m_min=0), dict(pd_m_step=-1),
+                dict(pd_alpha_p=float("nan"))):
+        with pytest.raises(sd.SDError) as e:
+            sd.Solver(P, krylov="pdgmres", **bad)
+        assert e.value.code == sd.SD_E_INVALID

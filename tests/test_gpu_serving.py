@@ -140,3 +140,35 @@ def test_serving_trace_small():
     S.close()
     for t, r in zip(trace, res):
         assert r["status"] == sd.SD_OK, (t, r["status"])
+
+
+def test_device_memory_comes_from_torch_allocator():
+    """The binding registers torch's caching allocator as the library's
+    sd_allocator: a solver's matrices, hierarchies and Krylov state, and every
+    request of the loop, are torch blocks, all returned when the handles
+    close."""
+    torch.cuda.synchronize()
+    s0 = dict(sd.ALLOC_STATS)
+    m0 = torch.cuda.memory_allocated()
+    p = channel_problem(96, 48, seed=13)
+    P = sd.Problem(p)
+    S = sd.Solver(P, tol=1e-8, restart=40)
+    s1 = dict(sd.ALLOC_STATS)
+    got = s1["bytes_allocated"] - s0["bytes_allocated"]
+    assert s1["allocs"] > s0["allocs"] and got > 0
+    assert torch.cuda.memory_allocated() - m0 >= got
+    x, st, rc = S.solve()
+    assert rc == sd.SD_OK
+    del x
+    S.close()
+    P.close()
+    torch.cuda.synchronize()
+    assert sd.ALLOC_STATS["bytes_live"] == s0["bytes_live"]
+    # the request loop's requests
+    sv = sd.Server(max_slots=2)
+    res = _run(sv, _mix()[:2], tol=1e-8, restart=40)
+    assert all(r["status"] == sd.SD_OK for r in res)
+    s2 = dict(sd.ALLOC_STATS)
+    assert s2["allocs"] > s1["allocs"] + 1
+    sv.close()
+    assert sd.ALLOC_STATS["bytes_live"] == s0["bytes_live"]
