@@ -338,6 +338,14 @@ int sd_advance(sd_solver* s, const double* d_b_data, double* d_x, int n_steps,
  * ordering (FP64, length N), exposed for testing and composition.
  * y = A x with the assembled FP64 matrix: */
 int sd_apply_matrix(sd_solver* s, const double* d_x, double* d_y, void* hip_stream);
+/* r = b - A x with the assembled FP64 matrix (the true residual the solver
+ * recomputes at every restart) and its norms: d_norms[0..3] = ||r||_2 and
+ * the norms of its velocity, free-flow pressure and porous pressure blocks
+ * (device FP64, 4 entries).  d_b NULL = the assembled b; d_x NULL = zero;
+ * d_r and d_norms are required (device, caller-owned).  Enqueued on
+ * hip_stream; returns without waiting. */
+int sd_residual(sd_solver* s, const double* d_b, const double* d_x, double* d_r,
+                double* d_norms, void* hip_stream);
 /* z = P(r), one application of the configured block preconditioner (in FP32
  * inside when the solver is mixed; input and output are FP64): */
 int sd_apply_preconditioner(sd_solver* s, const double* d_r, double* d_z,

@@ -89,6 +89,7 @@ struct HostFlags {
 };
 
 // ---- launchers (stream-ordered, no synchronisation) ----
+
 template <typename TM, typename TX, typename TY>
 void launch_spmv(const Sell<TM>& A, const TX* x, TY* y, const DevState* gate,
                  hipStream_t s);
@@ -168,6 +169,10 @@ void launch_update_x(double* x, const TZ* Z, int64_t ldz, int n, DevState* st,
 void launch_restart_residual(const Sell<double>& A, const double* b, const double* x,
                              double* r, const int64_t* blk_off, DevState* st, double* part,
                              HostFlags* hf, hipStream_t s);
+// r = b - A x (x == nullptr: x = 0) and norms[0..3] = ||r||, ||r_v||, ||r_p||,
+// ||r_q|| (device); part holds 3 * kDotBlocks partial sums.
+void launch_residual_norms(const Sell<double>& A, const double* b, const double* x, double* r,
+                           const int64_t* blk_off, double* part, double* norms, hipStream_t s);
 // ||b||, sets target = tol ||b||.
 void launch_norm_b(const double* b, int n, double tol, DevState* st, double* part,
                    hipStream_t s);

@@ -21,6 +21,7 @@
 
 #include "device.h"
 
+
 namespace sd {
 
 namespace {
@@ -885,6 +886,17 @@ __global__ __launch_bounds__(kBlock) void k_restart_finish(const double* part, i
   }
 }
 
+// norms = (||r||, ||r_v||, ||r_p||, ||r_q||) from the block partials of
+// k_restart_residual, summed in a fixed order.
+__global__ __launch_bounds__(kBlock) void k_residual_norms(const double* part, int nb,
+                                                           double* norms) {
+  __shared__ double sums[3];
+  final_sums<3>(part, nb, 3, sums);
+  if (threadIdx.x != 0) return;
+  norms[0] = sqrt((sums[0] + sums[1]) + sums[2]);
+  for (int k = 0; k < 3; ++k) norms[k + 1] = sqrt(sums[k]);
+}
+
 __global__ __launch_bounds__(kBlock) void k_norm_b(const double* __restrict__ b, int n, int R,
                                                    double* part) {
   const int G = gridDim.x * kBlock;
@@ -1368,6 +1380,14 @@ void launch_restart_residual(const Sell<double>& A, const double* b, const doubl
   k_restart_finish<<<1, kBlock, 0, s>>>(part, nb, st, hf);
 }
 
+void launch_residual_norms(const Sell<double>& A, const double* b, const double* x, double* r,
+                           const int64_t* blk_off, double* part, double* norms, hipStream_t s) {
+  const int n = A.n_rows;
+  const int nb = dot_blocks(n);
+  const int R = (n + nb * kBlock - 1) / (nb * kBlock);
+  k_restart_residual<<<nb, kBlock, 0, s>>>(A, b, x, r, (int)blk_off[2], (int)blk_off[3], R, part);
+  k_residual_norms<<<1, kBlock, 0, s>>>(part, nb, norms);
+}
 void launch_norm_b(const double* b, int n, double tol, DevState* st, double* part,
                    hipStream_t s) {
   const int nb = dot_blocks(n);

@@ -204,6 +204,7 @@ SIGNATURES = {
     "sd_dn_solve": (C.c_int, [_P, C.POINTER(DNOpts), _P, _P, C.POINTER(DNStats), _P]),
     "sd_dn_destroy": (None, [_P]),
     "sd_apply_preconditioner": (C.c_int, [_P, _P, _P, _P]),
+    "sd_residual": (C.c_int, [_P, _P, _P, _P, _P, _P]),
     "sd_apply_vcycle": (C.c_int, [_P, C.c_int, _P, _P, C.c_int64, _P]),
     "sd_arnoldi_layout": (C.c_int, [C.c_int64, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                     C.POINTER(C.c_size_t)]),
@@ -470,6 +471,25 @@ class Solver:
         _check(lib().sd_apply_matrix(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
                                      _stream()))
         return y
+
+    def residual(self, x=None, b=None, r=None, norms=None):
+        """(r = b - A x, norms [||r||, ||r_v||, ||r_p||, ||r_q||]) on the device;
+        x None = zero, b None = the assembled b; r and norms may be given
+        (outputs)."""
+        import torch
+        N = self.problem.N
+        for t in (x, b):
+            if t is not None:
+                _require(t, N)
+        r = torch.empty(N, dtype=torch.float64, device="cuda") if r is None else r
+        norms = torch.empty(4, dtype=torch.float64, device="cuda") if norms is None else norms
+        _require(r, N)
+        _require(norms, 4)
+        _check(lib().sd_residual(self.h, C.c_void_p(b.data_ptr()) if b is not None else None,
+                                 C.c_void_p(x.data_ptr()) if x is not None else None,
+                                 C.c_void_p(r.data_ptr()), C.c_void_p(norms.data_ptr()),
+                                 _stream()))
+        return r, norms
 
     def apply_preconditioner(self, r):
         import torch

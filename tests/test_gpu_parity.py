@@ -400,3 +400,29 @@ def test_pdgmres_options_validated():
         with pytest.raises(sd.SDError) as e:
             sd.Solver(P, krylov="pdgmres", **bad)
         assert e.value.code == sd.SD_E_INVALID
+
+
+@pytest.mark.parametrize("name", ["mms_ragged", "channel_ragged", "tiny"])
+def test_true_residual_and_block_norms(name):
+    """sd_residual: r = b - A x with the FP64 matrix, element by element
+    within the rounding of a row's sum, and the norms of r and of its three
+    blocks; x = 0 gives r = b bit for bit."""
+    p = SMALL[name]()
+    print("case residual", name, flush=True)
+    a = assemble(p)
+    P, S = _setup(p)
+    rng = np.random.default_rng(29)
+    x = rng.standard_normal(a.N)
+    b = rng.standard_normal(a.N)
+    r, nrm = S.residual(x=_dev(x), b=_dev(b))
+    r, nrm = _host(r), _host(nrm)
+    ref = b - a.A @ x
+    bound = 16 * EPS * (np.abs(b) + abs(a.A) @ np.abs(x))
+    assert np.all(np.abs(r - ref) <= bound)
+    o = a.layout.block_off
+    want = [np.linalg.norm(ref)] + [np.linalg.norm(ref[lo:hi])
+                                    for lo, hi in ((o[0], o[2]), (o[2], o[3]), (o[3], o[4]))]
+    assert np.allclose(nrm, want, rtol=1e-12, atol=0.0)
+    r0, n0 = S.residual()
+    assert np.array_equal(_host(r0), a.b)
+    assert abs(_host(n0)[0] - np.linalg.norm(a.b)) <= 1e-13 * np.linalg.norm(a.b)
