@@ -346,6 +346,18 @@ int sd_apply_matrix(sd_solver* s, const double* d_x, double* d_y, void* hip_stre
  * hip_stream; returns without waiting. */
 int sd_residual(sd_solver* s, const double* d_b, const double* d_x, double* d_r,
                 double* d_norms, void* hip_stream);
+/* Allocation-free variant of sd_residual, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same kernels and results; the 3 x 512 block
+ * partials of the norms live in a static 12 KiB device array of the library
+ * (one per GPU, held until the process ends) instead of the solver's
+ * workspace, and the call allocates nothing.  Every call on one GPU shares
+ * that array: calls that overlap there (other streams or threads) race and
+ * must be serialised by the caller.  Nothing in it needs clearing (each
+ * partial is written before it is read).  Same arguments and errors as
+ * sd_residual; SD_E_INVALID beyond 16,777,216 unknowns. */
+int sd_residual_noalloc(sd_solver* s, const double* d_b, const double* d_x, double* d_r,
+                        double* d_norms, void* hip_stream);
 /* z = P(r), one application of the configured block preconditioner (in FP32
  * inside when the solver is mixed; input and output are FP64): */
 int sd_apply_preconditioner(sd_solver* s, const double* d_r, double* d_z,

@@ -317,6 +317,20 @@ int sd_residual(sd_solver* s, const double* d_b, const double* d_x, double* d_r,
   });
 }
 
+int sd_residual_noalloc(sd_solver* s, const double* d_b, const double* d_x, double* d_r,
+                        double* d_norms, void* hip_stream) {
+  return guarded([&] {
+    if (!s || !d_r || !d_norms) return fail(SD_E_INVALID, "NULL argument");
+    if (!s->s->on_device) return fail(SD_E_INVALID, "solver has no device data");
+    SD_HIP(hipSetDevice(s->pb->device_id));
+    sd::Solver& S = *s->s;
+    sd::launch_residual_norms_noalloc(S.A64, d_b ? d_b : S.b_dev, d_x, d_r, S.off, d_norms,
+                                      (hipStream_t)hip_stream);
+    SD_HIP(hipGetLastError());
+    return (int)SD_OK;
+  });
+}
+
 int sd_apply_preconditioner(sd_solver* s, const double* d_r, double* d_z, void* hip_stream) {
   return guarded([&] {
     if (!s || !d_r || !d_z) return fail(SD_E_INVALID, "NULL argument");

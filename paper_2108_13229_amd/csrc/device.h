@@ -173,6 +173,11 @@ void launch_restart_residual(const Sell<double>& A, const double* b, const doubl
 // ||r_q|| (device); part holds 3 * kDotBlocks partial sums.
 void launch_residual_norms(const Sell<double>& A, const double* b, const double* x, double* r,
                            const int64_t* blk_off, double* part, double* norms, hipStream_t s);
+// The same with the partials in the library's static device scratch (no
+// allocation; concurrent calls on one GPU race).  Throws sd::Error.
+void launch_residual_norms_noalloc(const Sell<double>& A, const double* b, const double* x,
+                                   double* r, const int64_t* blk_off, double* norms,
+                                   hipStream_t s);
 // ||b||, sets target = tol ||b||.
 void launch_norm_b(const double* b, int n, double tol, DevState* st, double* part,
                    hipStream_t s);

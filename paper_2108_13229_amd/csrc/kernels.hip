@@ -17,10 +17,19 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
+#include <string>
 #include <type_traits>
 
 #include "device.h"
+#include "sd_internal.h"
 
+// Device scratch of the allocation-free residual (sd_residual_noalloc): the
+// 3 x kDotBlocks block partials of its norms, 12 KiB, one copy per GPU that
+// the library runs on, held until the process ends.  Host code never uses
+// this name as an address: it takes each device's address once from
+// hipGetSymbolAddress (noalloc_scratch below).
+static __device__ __align__(256) double scratch[3 * sd::kDotBlocks];
 
 namespace sd {
 
@@ -1388,6 +1397,47 @@ void launch_residual_norms(const Sell<double>& A, const double* b, const double*
   k_restart_residual<<<nb, kBlock, 0, s>>>(A, b, x, r, (int)blk_off[2], (int)blk_off[3], R, part);
   k_residual_norms<<<1, kBlock, 0, s>>>(part, nb, norms);
 }
+namespace {
+constexpr int kScratchMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kScratchMaxDevices] = {};
+}  // namespace
+
+// Address of the current device's copy of `scratch`, looked up on the first
+// call on each device.
+static double* noalloc_scratch() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error(SD_E_DEVICE, "hipGetDevice failed");
+  }
+  if (dev < 0 || dev >= kScratchMaxDevices)
+    throw Error(SD_E_DEVICE, "device ordinal beyond the scratch table (64 devices)");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      throw Error(SD_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                   hipGetErrorString(e));
+    }
+    g_scratch[dev] = static_cast<double*>(p);
+  }
+  return g_scratch[dev];
+}
+
+void launch_residual_norms_noalloc(const Sell<double>& A, const double* b, const double* x,
+                                   double* r, const int64_t* blk_off, double* norms,
+                                   hipStream_t s) {
+  if ((int64_t)A.n_rows > kMaxUnknowns)
+    throw Error(SD_E_INVALID, "more unknowns than the allocation-free residual takes (" +
+                                  std::to_string(kMaxUnknowns) + ")");
+  if (dot_blocks(A.n_rows) * 3 > (int)(sizeof(scratch) / sizeof(double)))
+    throw Error(SD_E_INVALID, "residual partials exceed the static scratch");
+  launch_residual_norms(A, b, x, r, blk_off, noalloc_scratch(), norms, s);
+}
+
 void launch_norm_b(const double* b, int n, double tol, DevState* st, double* part,
                    hipStream_t s) {
   const int nb = dot_blocks(n);

@@ -205,6 +205,7 @@ SIGNATURES = {
     "sd_dn_destroy": (None, [_P]),
     "sd_apply_preconditioner": (C.c_int, [_P, _P, _P, _P]),
     "sd_residual": (C.c_int, [_P, _P, _P, _P, _P, _P]),
+    "sd_residual_noalloc": (C.c_int, [_P, _P, _P, _P, _P, _P]),
     "sd_apply_vcycle": (C.c_int, [_P, C.c_int, _P, _P, C.c_int64, _P]),
     "sd_arnoldi_layout": (C.c_int, [C.c_int64, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                     C.POINTER(C.c_size_t)]),
@@ -472,10 +473,10 @@ class Solver:
                                      _stream()))
         return y
 
-    def residual(self, x=None, b=None, r=None, norms=None):
+    def residual(self, x=None, b=None, r=None, norms=None, noalloc: bool = False):
         """(r = b - A x, norms [||r||, ||r_v||, ||r_p||, ||r_q||]) on the device;
         x None = zero, b None = the assembled b; r and norms may be given
-        (outputs)."""
+        (outputs).  noalloc: the allocation-free entry point."""
         import torch
         N = self.problem.N
         for t in (x, b):
@@ -485,10 +486,10 @@ class Solver:
         norms = torch.empty(4, dtype=torch.float64, device="cuda") if norms is None else norms
         _require(r, N)
         _require(norms, 4)
-        _check(lib().sd_residual(self.h, C.c_void_p(b.data_ptr()) if b is not None else None,
-                                 C.c_void_p(x.data_ptr()) if x is not None else None,
-                                 C.c_void_p(r.data_ptr()), C.c_void_p(norms.data_ptr()),
-                                 _stream()))
+        fn = lib().sd_residual_noalloc if noalloc else lib().sd_residual
+        _check(fn(self.h, C.c_void_p(b.data_ptr()) if b is not None else None,
+                  C.c_void_p(x.data_ptr()) if x is not None else None,
+                  C.c_void_p(r.data_ptr()), C.c_void_p(norms.data_ptr()), _stream()))
         return r, norms
 
     def apply_preconditioner(self, r):
