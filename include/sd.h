@@ -481,6 +481,17 @@ typedef struct {
   double t_submit, t_admit, t_done;   /* seconds on the server's clock      */
 } sd_result;
 
+/* Counters of the shared launches since sd_server_create: groups formed
+ * (requests whose iterations have the same kernel sequence share one), graph
+ * replays (each runs one Arnoldi column for every active member of a group
+ * in one batched launch per kernel), columns run by them (summed over the
+ * replays' members) and the most members a replay served. */
+typedef struct {
+  int64_t groups, replays, member_columns;
+  int max_members;
+} sd_batch_stats;
+int sd_server_batch_stats(sd_server* sv, sd_batch_stats* out);
+
 /* Non-blocking. */
 int sd_poll(sd_server* sv, uint64_t ticket, sd_result* out);
 /* Block until the ticket is DONE or FAILED (or timeout_s elapses: SD_E_BUSY). */

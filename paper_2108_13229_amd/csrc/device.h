@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 namespace sd {
 
@@ -76,6 +77,7 @@ struct DevState {
   // BiCGSTAB scalars
   double rho, alpha, omega, bbeta, dots[8];
   unsigned int counter[8];
+  int jstep;         // step of the column being replayed (request-loop graph)
 };
 
 // Rows per workgroup of the Gram-Schmidt kernels for n rows (base: the
@@ -89,6 +91,19 @@ struct HostFlags {
 };
 
 // ---- launchers (stream-ordered, no synchronisation) ----
+
+// A launch recorded instead of made: the batched form of the kernel (its
+// arguments in a per-slot table, see the request loop), the argument struct
+// and the launch shape of this solve.
+struct RecordedOp {
+  const void* fn = nullptr;
+  std::vector<char> args;
+  int nblocks = 0, threads = 0;
+  size_t lds = 0;
+};
+// While rec is set (non-null), the launchers below called on this thread
+// append to it instead of launching.
+void set_launch_recorder(std::vector<RecordedOp>* rec);
 
 template <typename TM, typename TX, typename TY>
 void launch_spmv(const Sell<TM>& A, const TX* x, TY* y, const DevState* gate,
@@ -158,6 +173,15 @@ template <typename TM, typename TZ>
 void launch_arnoldi_step(const Sell<TM>& A, const TZ* z, double* W, double* V, int64_t ldv,
                          int j, DevState* st, double* part, HostFlags* hf, hipStream_t s,
                          int prof_class = 0, hipEvent_t* ev = nullptr);
+// j < 0 in launch_arnoldi_step: the step index comes from st->jstep, written
+// by launch_copy_in, which copies u_j = V[j] (j = st->j) and sigma_j into the
+// fixed buffers rin and sig; launch_copy_out stores zfix into Z[j].  The
+// column kernels of such a step do nothing once the cycle is done or at
+// j >= st->m.  (The request loop replays one recorded column this way.)
+void launch_copy_in(const double* V, int64_t ldv, DevState* st, double* rin, double* sig, int n,
+                    hipStream_t s);
+template <typename T>
+void launch_copy_out(const T* zfix, T* Z, int64_t ldz, const DevState* st, int n, hipStream_t s);
 // Completes column j-1 = m-1 at the end of a full cycle of m = j columns.
 void launch_arnoldi_close(int n, double* V, int64_t ldv, int j, DevState* st, double* part,
                           HostFlags* hf, hipStream_t s);

@@ -208,10 +208,6 @@ __device__ __forceinline__ int2 row_of_thread(int block, int nblocks) {
   const int lane = gt & 63;
   return make_int2((gt >> 6) * C + lane % C, lane / C);
 }
-template <int LPR>
-__device__ __forceinline__ int2 row_of_thread() {
-  return row_of_thread<LPR>(blockIdx.x, gridDim.x);
-}
 
 // The cycle-done flag of the gated kernels, read with a vector load through
 // an opaque pointer so that it is in flight together with the kernel's first
@@ -225,146 +221,229 @@ __device__ __forceinline__ int gate_flag(const DevState* gate) {
 }
 
 
+// ---- V-cycle and block-sweep kernels.  Each is an Op: its arguments in a
+// struct and a body run(a, block, nblocks) for workgroup `block` of
+// `nblocks`.  A named kernel (k_spmv, k_jacobi, ...) runs one Op over its
+// grid; k_batch runs the same Op for every slot of a batch of solves (the
+// request loop's shared launches), each slot with its own arguments and
+// workgroup count, so a solve computes the same values in either form.
+
 template <int LPR, typename TM, typename TX, typename TY>
-__global__ __launch_bounds__(kBlock) void k_spmv(Sell<TM> A, const TX* __restrict__ x,
-                                                 TY* __restrict__ y, const DevState* gate) {
-  const int2 rs = row_of_thread<LPR>();
-  if (rs.x >= A.n_rows) return;
-  const int stop = gate_flag(gate);
-  const TM v = row_sum<LPR>(A, rs.x, rs.y, [&](int c) { return (TM)x[c]; });
-  if (rs.y == 0 && !stop) y[rs.x] = (TY)v;
-}
+struct SpmvOp {
+  struct Args {
+    Sell<TM> A;
+    const TX* x;
+    TY* y;
+    const DevState* gate;
+  };
+  static constexpr int kThreads = kBlock;
+  static __device__ __forceinline__ void run(const Args& a, int block, int nblocks) {
+    const int2 rs = row_of_thread<LPR>(block, nblocks);
+    if (rs.x >= a.A.n_rows) return;
+    const int stop = gate_flag(a.gate);
+    const TX* __restrict__ x = a.x;
+    const TM v = row_sum<LPR>(a.A, rs.x, rs.y, [&](int c) { return (TM)x[c]; });
+    if (rs.y == 0 && !stop) a.y[rs.x] = (TY)v;
+  }
+};
 
+// r = bscale * b - A x
 template <int LPR, typename T, typename TB>
-__global__ __launch_bounds__(kBlock) void k_residual(Sell<T> A, const TB* __restrict__ b,
-                                                     const double* bscale,
-                                                     const T* __restrict__ x,
-                                                     T* __restrict__ r, const DevState* gate) {
-  const int2 rs = row_of_thread<LPR>();
-  if (rs.x >= A.n_rows) return;
-  const int stop = gate_flag(gate);
-  const T ax = row_sum<LPR>(A, rs.x, rs.y, [&](int c) { return x[c]; });
-  if (rs.y == 0 && !stop) r[rs.x] = load_b<T>(b, scale_of(bscale), rs.x) - ax;
-}
+struct ResidualOp {
+  struct Args {
+    Sell<T> A;
+    const TB* b;
+    const double* bscale;
+    const T* x;
+    T* r;
+    const DevState* gate;
+  };
+  static constexpr int kThreads = kBlock;
+  static __device__ __forceinline__ void run(const Args& a, int block, int nblocks) {
+    const int2 rs = row_of_thread<LPR>(block, nblocks);
+    if (rs.x >= a.A.n_rows) return;
+    const int stop = gate_flag(a.gate);
+    const T* __restrict__ x = a.x;
+    const T ax = row_sum<LPR>(a.A, rs.x, rs.y, [&](int c) { return x[c]; });
+    if (rs.y == 0 && !stop) a.r[rs.x] = load_b<T>(a.b, scale_of(a.bscale), rs.x) - ax;
+  }
+};
 
-// x = w .* b (one sweep from zero) or two sweeps from zero fused: the first
-// sweep's values x1 = w .* b are recomputed at the neighbours.
 // bc = Q [bscale b; x] = R (bscale b - A x): residual and restriction in one
 // product over the coarse rows (columns >= n_fine address x).
 template <int LPR, typename T, typename TB>
-__global__ __launch_bounds__(kBlock) void k_restrict_residual(Sell<T> Q, const TB* __restrict__ b,
-                                                              const double* bscale,
-                                                              const T* __restrict__ x,
-                                                              int n_fine, T* __restrict__ bc,
-                                                              const DevState* gate) {
-  const int2 rs = row_of_thread<LPR>();
-  if (rs.x >= Q.n_rows) return;
-  const int stop = gate_flag(gate);
-  const double sc = scale_of(bscale);
-  const T v = row_sum<LPR>(Q, rs.x, rs.y, [&](int c) {
-    return c < n_fine ? load_b<T>(b, sc, c) : x[c - n_fine];
-  });
-  if (rs.y == 0 && !stop) bc[rs.x] = v;
-}
+struct RestrictResidualOp {
+  struct Args {
+    Sell<T> Q;
+    const TB* b;
+    const double* bscale;
+    const T* x;
+    int n_fine;
+    T* bc;
+    const DevState* gate;
+  };
+  static constexpr int kThreads = kBlock;
+  static __device__ __forceinline__ void run(const Args& a, int block, int nblocks) {
+    const int2 rs = row_of_thread<LPR>(block, nblocks);
+    if (rs.x >= a.Q.n_rows) return;
+    const int stop = gate_flag(a.gate);
+    const double sc = scale_of(a.bscale);
+    const TB* __restrict__ b = a.b;
+    const T* __restrict__ x = a.x;
+    const int n_fine = a.n_fine;
+    const T v = row_sum<LPR>(a.Q, rs.x, rs.y, [&](int c) {
+      return c < n_fine ? load_b<T>(b, sc, c) : x[c - n_fine];
+    });
+    if (rs.y == 0 && !stop) a.bc[rs.x] = v;
+  }
+};
 
 // Pre-smoothing and restriction in one launch, both from b alone: the first
 // nb_a workgroups run two damped-Jacobi sweeps from zero on the rows of A
 // (x = (2W - W A W) b, with A passed as A diag(w)), the others compute
 // bc = G b with G = R (I - A M2) (one wavefront per row: G's rows are long).
 template <int LA, typename T, typename TB>
-__global__ __launch_bounds__(kBlock) void k_presmooth_restrict(Sell<T> A, const T* __restrict__ wd,
-                                                               Sell<T> G, const TB* __restrict__ b,
-                                                               const double* bscale,
-                                                               T* __restrict__ x,
-                                                               T* __restrict__ bc, int nb_a,
-                                                               const DevState* gate) {
-  const int stop = gate_flag(gate);
-  const double s = scale_of(bscale);
-  if ((int)blockIdx.x < nb_a) {
-    const int2 rs = row_of_thread<LA>(blockIdx.x, nb_a);
-    const int row = rs.x, sub = rs.y;
-    if (row >= A.n_rows) return;
-    const T bi = load_b<T>(b, s, row);
-    const T acc = row_sum<LA>(A, row, sub, [&](int c) { return load_b<T>(b, s, c); });
-    if (sub == 0 && !stop) x[row] = wd[row] * bi + wd[row] * (bi - acc);
-  } else {
-    const int2 rs = row_of_thread<64>(blockIdx.x - nb_a, gridDim.x - nb_a);
-    const int row = rs.x, sub = rs.y;
-    if (row >= G.n_rows) return;
-    const T v = row_sum<64>(G, row, sub, [&](int c) { return load_b<T>(b, s, c); });
-    if (sub == 0 && !stop) bc[row] = v;
+struct PresmoothRestrictOp {
+  struct Args {
+    Sell<T> A;
+    const T* wd;
+    Sell<T> G;
+    const TB* b;
+    const double* bscale;
+    T* x;
+    T* bc;
+    int nb_a;
+    const DevState* gate;
+  };
+  static constexpr int kThreads = kBlock;
+  static __device__ __forceinline__ void run(const Args& a, int block, int nblocks) {
+    const int stop = gate_flag(a.gate);
+    const double s = scale_of(a.bscale);
+    const TB* __restrict__ b = a.b;
+    if (block < a.nb_a) {
+      const int2 rs = row_of_thread<LA>(block, a.nb_a);
+      const int row = rs.x, sub = rs.y;
+      if (row >= a.A.n_rows) return;
+      const T bi = load_b<T>(b, s, row);
+      const T acc = row_sum<LA>(a.A, row, sub, [&](int c) { return load_b<T>(b, s, c); });
+      if (sub == 0 && !stop) a.x[row] = a.wd[row] * bi + a.wd[row] * (bi - acc);
+    } else {
+      const int2 rs = row_of_thread<64>(block - a.nb_a, nblocks - a.nb_a);
+      const int row = rs.x, sub = rs.y;
+      if (row >= a.G.n_rows) return;
+      const T v = row_sum<64>(a.G, row, sub, [&](int c) { return load_b<T>(b, s, c); });
+      if (sub == 0 && !stop) a.bc[row] = v;
+    }
   }
-}
+};
 
 // Coarse correction and the first post-smoothing sweep in one pass:
 // xout = x + W (b - A x) + F xc with F = P - W A P (F stored with A's lanes).
 template <int LA, typename T, typename TB>
-__global__ __launch_bounds__(kBlock) void k_prolong_smooth(Sell<T> A, Sell<T> F,
-                                                           const T* __restrict__ wd,
-                                                           const TB* __restrict__ b,
-                                                           const double* bscale,
-                                                           const T* __restrict__ x,
-                                                           const T* __restrict__ xc,
-                                                           T* __restrict__ xout,
-                                                           const DevState* gate) {
-  const int2 rs = row_of_thread<LA>();
-  const int row = rs.x;
-  if (row >= A.n_rows) return;
-  const int stop = gate_flag(gate);
-  const T ax = row_sum<LA>(A, row, rs.y, [&](int c) { return x[c]; });
-  const T fx = row_sum<LA>(F, row, rs.y, [&](int c) { return xc[c]; });
-  if (rs.y == 0 && !stop)
-    xout[row] = x[row] + wd[row] * (load_b<T>(b, scale_of(bscale), row) - ax) + fx;
-}
-
-template <int LPR, typename T, typename TB>
-__global__ __launch_bounds__(kBlock) void k_jacobi_zero(Sell<T> A, const T* __restrict__ wd,
-                                                        const TB* __restrict__ b,
-                                                        const double* bscale,
-                                                        T* __restrict__ x, int two,
-                                                        const DevState* gate) {
-  const int2 rs = row_of_thread<LPR>();
-  const int row = rs.x;
-  if (row >= A.n_rows) return;
-  const int stop = gate_flag(gate);
-  const double s = scale_of(bscale);
-  const T bi = load_b<T>(b, s, row);
-  const T x1 = wd[row] * bi;
-  if (!two) {
-    if (rs.y == 0 && !stop) x[row] = x1;
-    return;
+struct ProlongSmoothOp {
+  struct Args {
+    Sell<T> A, F;
+    const T* wd;
+    const TB* b;
+    const double* bscale;
+    const T* x;
+    const T* xc;
+    T* xout;
+    const DevState* gate;
+  };
+  static constexpr int kThreads = kBlock;
+  static __device__ __forceinline__ void run(const Args& a, int block, int nblocks) {
+    const int2 rs = row_of_thread<LA>(block, nblocks);
+    const int row = rs.x;
+    if (row >= a.A.n_rows) return;
+    const int stop = gate_flag(a.gate);
+    const T* __restrict__ x = a.x;
+    const T* __restrict__ xc = a.xc;
+    const T ax = row_sum<LA>(a.A, row, rs.y, [&](int c) { return x[c]; });
+    const T fx = row_sum<LA>(a.F, row, rs.y, [&](int c) { return xc[c]; });
+    if (rs.y == 0 && !stop)
+      a.xout[row] = x[row] + a.wd[row] * (load_b<T>(a.b, scale_of(a.bscale), row) - ax) + fx;
   }
-  // A holds A diag(w) here, so the first sweep's values w_c b_c at the
-  // neighbours cost one gather each
-  const T acc = row_sum<LPR>(A, row, rs.y, [&](int c) { return load_b<T>(b, s, c); });
-  if (rs.y == 0 && !stop) x[row] = x1 + wd[row] * (bi - acc);
-}
+};
 
+// x = w .* b (one sweep from zero) or two sweeps from zero fused: the first
+// sweep's values x1 = w .* b are recomputed at the neighbours.
 template <int LPR, typename T, typename TB>
-__global__ __launch_bounds__(kBlock) void k_jacobi(Sell<T> A, const T* __restrict__ wd,
-                                                   const TB* __restrict__ b,
-                                                   const double* bscale,
-                                                   const T* __restrict__ xin,
-                                                   T* __restrict__ xout,
-                                                   const DevState* gate) {
-  const int2 rs = row_of_thread<LPR>();
-  const int row = rs.x;
-  if (row >= A.n_rows) return;
-  const int stop = gate_flag(gate);
-  const T ax = row_sum<LPR>(A, row, rs.y, [&](int c) { return xin[c]; });
-  if (rs.y == 0 && !stop)
-    xout[row] = xin[row] + wd[row] * (load_b<T>(b, scale_of(bscale), row) - ax);
-}
+struct JacobiZeroOp {
+  struct Args {
+    Sell<T> A;
+    const T* wd;
+    const TB* b;
+    const double* bscale;
+    T* x;
+    int two;
+    const DevState* gate;
+  };
+  static constexpr int kThreads = kBlock;
+  static __device__ __forceinline__ void run(const Args& a, int block, int nblocks) {
+    const int2 rs = row_of_thread<LPR>(block, nblocks);
+    const int row = rs.x;
+    if (row >= a.A.n_rows) return;
+    const int stop = gate_flag(a.gate);
+    const double s = scale_of(a.bscale);
+    const TB* __restrict__ b = a.b;
+    const T bi = load_b<T>(b, s, row);
+    const T x1 = a.wd[row] * bi;
+    if (!a.two) {
+      if (rs.y == 0 && !stop) a.x[row] = x1;
+      return;
+    }
+    // A holds A diag(w) here, so the first sweep's values w_c b_c at the
+    // neighbours cost one gather each
+    const T acc = row_sum<LPR>(a.A, row, rs.y, [&](int c) { return load_b<T>(b, s, c); });
+    if (rs.y == 0 && !stop) a.x[row] = x1 + a.wd[row] * (bi - acc);
+  }
+};
 
+// x_out = x_in + w .* (bscale b - A x_in)
+template <int LPR, typename T, typename TB>
+struct JacobiOp {
+  struct Args {
+    Sell<T> A;
+    const T* wd;
+    const TB* b;
+    const double* bscale;
+    const T* xin;
+    T* xout;
+    const DevState* gate;
+  };
+  static constexpr int kThreads = kBlock;
+  static __device__ __forceinline__ void run(const Args& a, int block, int nblocks) {
+    const int2 rs = row_of_thread<LPR>(block, nblocks);
+    const int row = rs.x;
+    if (row >= a.A.n_rows) return;
+    const int stop = gate_flag(a.gate);
+    const T* __restrict__ xin = a.xin;
+    const T ax = row_sum<LPR>(a.A, row, rs.y, [&](int c) { return xin[c]; });
+    if (rs.y == 0 && !stop)
+      a.xout[row] = xin[row] + a.wd[row] * (load_b<T>(a.b, scale_of(a.bscale), row) - ax);
+  }
+};
+
+// x += P xc
 template <int LPR, typename T>
-__global__ __launch_bounds__(kBlock) void k_prolong(Sell<T> P, const T* __restrict__ xc,
-                                                    T* __restrict__ x, const DevState* gate) {
-  const int2 rs = row_of_thread<LPR>();
-  if (rs.x >= P.n_rows) return;
-  const int stop = gate_flag(gate);
-  const T v = row_sum<LPR>(P, rs.x, rs.y, [&](int c) { return xc[c]; });
-  if (rs.y == 0 && !stop) x[rs.x] += v;
-}
+struct ProlongOp {
+  struct Args {
+    Sell<T> P;
+    const T* xc;
+    T* x;
+    const DevState* gate;
+  };
+  static constexpr int kThreads = kBlock;
+  static __device__ __forceinline__ void run(const Args& a, int block, int nblocks) {
+    const int2 rs = row_of_thread<LPR>(block, nblocks);
+    if (rs.x >= a.P.n_rows) return;
+    const int stop = gate_flag(a.gate);
+    const T* __restrict__ xc = a.xc;
+    const T v = row_sum<LPR>(a.P, rs.x, rs.y, [&](int c) { return xc[c]; });
+    if (rs.y == 0 && !stop) a.x[rs.x] += v;
+  }
+};
 
 constexpr int kIluThreads = 1024;
 
@@ -376,115 +455,267 @@ constexpr int kIluThreads = 1024;
 // row index and slots are loaded at once, then the gathers; padded slots
 // (col -1) read z[0] and add nothing.
 template <typename T>
-__global__ __launch_bounds__(kIluThreads) void k_ilu0(IluDev<T> F, const T* __restrict__ r,
-                                                      T* z, const DevState* gate) {
-  __shared__ int lev[2][kIluMaxLevels + 1];
-  if (gate && gate->cycle_done) return;
-  const int t = threadIdx.x;
-  const size_t n = (size_t)F.n;
-  for (int l = t; l <= F.nlev_l; l += kIluThreads) lev[0][l] = F.lev_l[l];
-  for (int l = t; l <= F.nlev_u; l += kIluThreads) lev[1][l] = F.lev_u[l];
-  __syncthreads();
-  for (int lv = 0; lv < F.nlev_l; ++lv) {
-    const int q1 = lev[0][lv + 1];
-    for (int q = lev[0][lv] + t; q < q1; q += kIluThreads) {
-      const int i = F.ord_l[q];
-      int c[kIluWidth];
-      T v[kIluWidth];
-#pragma unroll
-      for (int k = 0; k < kIluWidth; ++k) {
-        c[k] = F.col_l[k * n + q];
-        v[k] = F.val_l[k * n + q];
-      }
-      T x[kIluWidth];
-#pragma unroll
-      for (int k = 0; k < kIluWidth; ++k) x[k] = z[max(c[k], 0)];
-      T acc = r[i];
-#pragma unroll
-      for (int k = 0; k < kIluWidth; ++k) acc = c[k] >= 0 ? acc - v[k] * x[k] : acc;
-      z[i] = acc;
-    }
+struct Ilu0Op {
+  struct Args {
+    IluDev<T> F;
+    const T* r;
+    T* z;
+    const DevState* gate;
+  };
+  static constexpr int kThreads = kIluThreads;
+  static __device__ __forceinline__ void run(const Args& a, int, int) {
+    __shared__ int lev[2][kIluMaxLevels + 1];
+    if (a.gate && a.gate->cycle_done) return;
+    const IluDev<T>& F = a.F;
+    const T* __restrict__ r = a.r;
+    T* z = a.z;
+    const int t = threadIdx.x;
+    const size_t n = (size_t)F.n;
+    for (int l = t; l <= F.nlev_l; l += kIluThreads) lev[0][l] = F.lev_l[l];
+    for (int l = t; l <= F.nlev_u; l += kIluThreads) lev[1][l] = F.lev_u[l];
     __syncthreads();
-  }
-  for (int lv = 0; lv < F.nlev_u; ++lv) {
-    const int q1 = lev[1][lv + 1];
-    for (int q = lev[1][lv] + t; q < q1; q += kIluThreads) {
-      const int i = F.ord_u[q];
-      int c[kIluWidth];
-      T v[kIluWidth];
+    for (int lv = 0; lv < F.nlev_l; ++lv) {
+      const int q1 = lev[0][lv + 1];
+      for (int q = lev[0][lv] + t; q < q1; q += kIluThreads) {
+        const int i = F.ord_l[q];
+        int c[kIluWidth];
+        T v[kIluWidth];
 #pragma unroll
-      for (int k = 0; k < kIluWidth; ++k) {
-        c[k] = F.col_u[k * n + q];
-        v[k] = F.val_u[k * n + q];
+        for (int k = 0; k < kIluWidth; ++k) {
+          c[k] = F.col_l[k * n + q];
+          v[k] = F.val_l[k * n + q];
+        }
+        T x[kIluWidth];
+#pragma unroll
+        for (int k = 0; k < kIluWidth; ++k) x[k] = z[max(c[k], 0)];
+        T acc = r[i];
+#pragma unroll
+        for (int k = 0; k < kIluWidth; ++k) acc = c[k] >= 0 ? acc - v[k] * x[k] : acc;
+        z[i] = acc;
       }
-      const T d = F.diag_u[q];
-      T x[kIluWidth];
-#pragma unroll
-      for (int k = 0; k < kIluWidth; ++k) x[k] = z[max(c[k], 0)];
-      T acc = z[i];
-#pragma unroll
-      for (int k = 0; k < kIluWidth; ++k) acc = c[k] >= 0 ? acc - v[k] * x[k] : acc;
-      z[i] = acc / d;
+      __syncthreads();
     }
-    __syncthreads();
+    for (int lv = 0; lv < F.nlev_u; ++lv) {
+      const int q1 = lev[1][lv + 1];
+      for (int q = lev[1][lv] + t; q < q1; q += kIluThreads) {
+        const int i = F.ord_u[q];
+        int c[kIluWidth];
+        T v[kIluWidth];
+#pragma unroll
+        for (int k = 0; k < kIluWidth; ++k) {
+          c[k] = F.col_u[k * n + q];
+          v[k] = F.val_u[k * n + q];
+        }
+        const T d = F.diag_u[q];
+        T x[kIluWidth];
+#pragma unroll
+        for (int k = 0; k < kIluWidth; ++k) x[k] = z[max(c[k], 0)];
+        T acc = z[i];
+#pragma unroll
+        for (int k = 0; k < kIluWidth; ++k) acc = c[k] >= 0 ? acc - v[k] * x[k] : acc;
+        z[i] = acc / d;
+      }
+      __syncthreads();
+    }
   }
-}
+};
 
 // xc = Ainv bc, FP64 dense inverse: one workgroup per row (the coarse rows
 // are few), each thread with up to eight loads in flight.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_coarse(const double* __restrict__ Ainv, int n,
-                                                   const T* __restrict__ bc,
-                                                   T* __restrict__ xc, const DevState* gate) {
-  __shared__ double red[kBlock / 64];
-  const int stop = gate_flag(gate);
-  const double* a = Ainv + (size_t)blockIdx.x * n;
-  double sp[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int c0 = threadIdx.x; c0 < n; c0 += 8 * kBlock) {
+struct CoarseOp {
+  struct Args {
+    const double* Ainv;
+    int n;
+    const T* bc;
+    T* xc;
+    const DevState* gate;
+  };
+  static constexpr int kThreads = kBlock;
+  static __device__ __forceinline__ void run(const Args& a, int block, int) {
+    __shared__ double red[kBlock / 64];
+    const int stop = gate_flag(a.gate);
+    const int n = a.n;
+    const double* __restrict__ arow = a.Ainv + (size_t)block * n;
+    const T* __restrict__ bc = a.bc;
+    double sp[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c0 = threadIdx.x; c0 < n; c0 += 8 * kBlock) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int c = c0 + u * kBlock;
-      if (c < n) sp[u & 3] += a[c] * (double)bc[c];
+      for (int u = 0; u < 8; ++u) {
+        const int c = c0 + u * kBlock;
+        if (c < n) sp[u & 3] += arow[c] * (double)bc[c];
+      }
+    }
+    const double v = wave_sum((sp[0] + sp[1]) + (sp[2] + sp[3]));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0 && !stop) a.xc[block] = (T)(((red[0] + red[1]) + red[2]) + red[3]);
+  }
+};
+
+// Block sweep: rows of the continuity and porous blocks.
+template <typename T>
+struct BlockSweepOp {
+  struct Args {
+    Sell<T> Cf;
+    int n_p;
+    const double* r;
+    const double* bscale;
+    const T* yv;
+    double xscale;
+    T* zp;
+    T* tq;
+    T* tp;
+    const DevState* gate;
+  };
+  static constexpr int kThreads = kBlock;
+  static __device__ __forceinline__ void run(const Args& a, int block, int nblocks) {
+    const int row = xcd_block(block, nblocks) * kBlock + threadIdx.x;
+    if (row >= a.Cf.n_rows) return;
+    const int stop = gate_flag(a.gate);
+    const T t = load_b<T>(a.r, scale_of(a.bscale), row) - sell_dot(a.Cf, a.yv, row);
+    if (stop) return;
+    if (row < a.n_p) {
+      a.zp[row] = (T)a.xscale * t;
+      if (a.tp) a.tp[row] = t;     // right-hand side of the pressure-operator V-cycle
+    } else {
+      a.tq[row - a.n_p] = t;
     }
   }
-  const double v = wave_sum((sp[0] + sp[1]) + (sp[2] + sp[3]));
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  if (threadIdx.x == 0 && !stop) xc[blockIdx.x] = (T)(((red[0] + red[1]) + red[2]) + red[3]);
-}
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_block_sweep(Sell<T> Cf, int n_p,
-                                                        const double* __restrict__ r,
-                                                        const double* bscale,
-                                                        const T* __restrict__ yv, double xscale,
-                                                        T* __restrict__ zp, T* __restrict__ tq,
-                                                        T* __restrict__ tp,
-                                                        const DevState* gate) {
-  const int row = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  if (row >= Cf.n_rows) return;
-  const int stop = gate_flag(gate);
-  const T t = load_b<T>(r, scale_of(bscale), row) - sell_dot(Cf, yv, row);
-  if (stop) return;
-  if (row < n_p) {
-    zp[row] = (T)xscale * t;
-    if (tp) tp[row] = t;     // right-hand side of the pressure-operator V-cycle
-  } else {
-    tq[row - n_p] = t;
-  }
-}
+};
 
 // y += a (the pressure-operator V-cycle's share of the middle block).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_add(const T* __restrict__ a, T* __restrict__ y, int n,
-                                                const DevState* gate) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const int stop = gate_flag(gate);
-  const T v = a[i];
-  const T w = y[i];
-  if (stop) return;
-  y[i] = w + v;
+struct AddOp {
+  struct Args {
+    const T* a;
+    T* y;
+    int n;
+    const DevState* gate;
+  };
+  static constexpr int kThreads = kBlock;
+  static __device__ __forceinline__ void run(const Args& p, int block, int) {
+    const int i = block * kBlock + threadIdx.x;
+    if (i >= p.n) return;
+    const int stop = gate_flag(p.gate);
+    const T v = p.a[i];
+    const T w = p.y[i];
+    if (stop) return;
+    p.y[i] = w + v;
+  }
+};
+
+// out = (T)(bscale * b)
+template <typename TB, typename T>
+struct ScaleConvertOp {
+  struct Args {
+    const TB* b;
+    const double* bscale;
+    T* out;
+    int n;
+    const DevState* gate;
+  };
+  static constexpr int kThreads = kBlock;
+  static __device__ __forceinline__ void run(const Args& a, int block, int) {
+    const int i = block * kBlock + threadIdx.x;
+    if (i >= a.n) return;
+    const int stop = gate_flag(a.gate);
+    const T v = load_b<T>(a.b, scale_of(a.bscale), i);
+    if (!stop) a.out[i] = v;
+  }
+};
+
+template <typename TA, typename TB>
+struct ConvertOp {
+  struct Args {
+    const TA* a;
+    TB* b;
+    int n;
+  };
+  static constexpr int kThreads = kBlock;
+  static __device__ __forceinline__ void run(const Args& p, int block, int) {
+    const int i = block * kBlock + threadIdx.x;
+    if (i < p.n) p.b[i] = (TB)p.a[i];
+  }
+};
+
+template <typename T>
+struct FillOp {
+  struct Args {
+    T* a;
+    T v;
+    int n;
+  };
+  static constexpr int kThreads = kBlock;
+  static __device__ __forceinline__ void run(const Args& p, int block, int) {
+    const int i = block * kBlock + threadIdx.x;
+    if (i < p.n) p.a[i] = p.v;
+  }
+};
+
+// Named single launches of the Ops above.
+template <int LPR, typename TM, typename TX, typename TY>
+__global__ __launch_bounds__(kBlock) void k_spmv(typename SpmvOp<LPR, TM, TX, TY>::Args a) {
+  SpmvOp<LPR, TM, TX, TY>::run(a, blockIdx.x, gridDim.x);
+}
+template <int LPR, typename T, typename TB>
+__global__ __launch_bounds__(kBlock) void k_residual(typename ResidualOp<LPR, T, TB>::Args a) {
+  ResidualOp<LPR, T, TB>::run(a, blockIdx.x, gridDim.x);
+}
+template <int LPR, typename T, typename TB>
+__global__ __launch_bounds__(kBlock) void k_restrict_residual(
+    typename RestrictResidualOp<LPR, T, TB>::Args a) {
+  RestrictResidualOp<LPR, T, TB>::run(a, blockIdx.x, gridDim.x);
+}
+template <int LA, typename T, typename TB>
+__global__ __launch_bounds__(kBlock) void k_presmooth_restrict(
+    typename PresmoothRestrictOp<LA, T, TB>::Args a) {
+  PresmoothRestrictOp<LA, T, TB>::run(a, blockIdx.x, gridDim.x);
+}
+template <int LA, typename T, typename TB>
+__global__ __launch_bounds__(kBlock) void k_prolong_smooth(
+    typename ProlongSmoothOp<LA, T, TB>::Args a) {
+  ProlongSmoothOp<LA, T, TB>::run(a, blockIdx.x, gridDim.x);
+}
+template <int LPR, typename T, typename TB>
+__global__ __launch_bounds__(kBlock) void k_jacobi_zero(typename JacobiZeroOp<LPR, T, TB>::Args a) {
+  JacobiZeroOp<LPR, T, TB>::run(a, blockIdx.x, gridDim.x);
+}
+template <int LPR, typename T, typename TB>
+__global__ __launch_bounds__(kBlock) void k_jacobi(typename JacobiOp<LPR, T, TB>::Args a) {
+  JacobiOp<LPR, T, TB>::run(a, blockIdx.x, gridDim.x);
+}
+template <int LPR, typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong(typename ProlongOp<LPR, T>::Args a) {
+  ProlongOp<LPR, T>::run(a, blockIdx.x, gridDim.x);
+}
+template <typename T>
+__global__ __launch_bounds__(kIluThreads) void k_ilu0(typename Ilu0Op<T>::Args a) {
+  Ilu0Op<T>::run(a, blockIdx.x, gridDim.x);
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_coarse(typename CoarseOp<T>::Args a) {
+  CoarseOp<T>::run(a, blockIdx.x, gridDim.x);
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_block_sweep(typename BlockSweepOp<T>::Args a) {
+  BlockSweepOp<T>::run(a, blockIdx.x, gridDim.x);
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_add(typename AddOp<T>::Args a) {
+  AddOp<T>::run(a, blockIdx.x, gridDim.x);
+}
+template <typename TB, typename T>
+__global__ __launch_bounds__(kBlock) void k_scale_convert(typename ScaleConvertOp<TB, T>::Args a) {
+  ScaleConvertOp<TB, T>::run(a, blockIdx.x, gridDim.x);
+}
+template <typename TA, typename TB>
+__global__ __launch_bounds__(kBlock) void k_convert(typename ConvertOp<TA, TB>::Args a) {
+  ConvertOp<TA, TB>::run(a, blockIdx.x, gridDim.x);
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill(typename FillOp<T>::Args a) {
+  FillOp<T>::run(a, blockIdx.x, gridDim.x);
 }
 
 // ---- Arnoldi step j: classical Gram-Schmidt with one reorthogonalisation
@@ -523,21 +754,49 @@ constexpr int kProjRowChunk = 6;                  // matrix entries per row load
                                                   // (8 would spill at 64 VGPRs)
 constexpr int kSumStride = 2 * kMaxBasis + 4;
 
+// Step index of the Arnoldi kernels: the launch's j, or (j < 0: a launch
+// replayed for every column of the request loop's shared graph) the step the
+// column's copy-in recorded in st->jstep.
+__device__ __forceinline__ int step_of(int j, const DevState* st) {
+  return j >= 0 ? j : st->jstep;
+}
+
 template <typename TM, typename TZ>
-__global__ __launch_bounds__(kGsThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_arn_project(Sell<TM> A, const TZ* __restrict__ z,
-                                                            double* __restrict__ W,
-                                                            const double* __restrict__ V,
-                                                            int64_t ldv, int n, int j, int rpb,
-                                                            int spmv, const DevState* st,
-                                                            double* part) {
+struct ArnProjectOp {
+  struct Args {
+    Sell<TM> A;
+    const TZ* z;
+    double* W;
+    const double* V;
+    int64_t ldv;
+    int n, j, rpb, spmv;
+    const DevState* st;
+    double* part;
+  };
+  static constexpr int kThreads = kGsThreads;
+  static __device__ __forceinline__ void run(const Args& a, int block, int nblocks);
+};
+
+template <typename TM, typename TZ>
+__device__ __forceinline__ void ArnProjectOp<TM, TZ>::run(const Args& a, int block, int) {
+  const DevState* st = a.st;
   if (st->cycle_done) return;
+  const int j = step_of(a.j, st);
+  if (a.j < 0 && j >= st->m) return;     // no column beyond the cycle
+  const Sell<TM> A = a.A;
+  const TZ* __restrict__ z = a.z;
+  double* __restrict__ W = a.W;
+  const double* __restrict__ V = a.V;
+  const int64_t ldv = a.ldv;
+  const int n = a.n, rpb = a.rpb, spmv = a.spmv;
+  double* part = a.part;
   extern __shared__ double sh[];                  // w and u_j of the block's rows
   double* wt = sh;
   double* ut = sh + rpb;
   __shared__ double red3[kGsWaves][3];
   __shared__ double piece[2][kMaxBasis + kGsWaves];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int r0 = blockIdx.x * rpb;
+  const int r0 = block * rpb;
   const int ns = rpb / 64;                        // slices of the block (multiple of 16)
   const double* uj = V + (size_t)j * ldv;
   double cuu = 0.0, cuw = 0.0, cww = 0.0;
@@ -619,7 +878,7 @@ __global__ __launch_bounds__(kGsThreads) __attribute__((amdgpu_waves_per_eu(8, 8
       const int wf = (k * ns) / per, wl = ((k + 1) * ns - 1) / per;
       double t = 0.0;
       for (int w = wf; w <= wl; ++w) t += piece[ab][k + w];
-      part[(size_t)((ab ? kGsRowB : kGsRowA) + k) * kGsMaxBlocks + blockIdx.x] = t;
+      part[(size_t)((ab ? kGsRowB : kGsRowA) + k) * kGsMaxBlocks + block] = t;
     }
   }
   cuu = wave_sum(cuu);
@@ -635,8 +894,14 @@ __global__ __launch_bounds__(kGsThreads) __attribute__((amdgpu_waves_per_eu(8, 8
     double s = 0.0;
 #pragma unroll
     for (int w = 0; w < kGsWaves; ++w) s += red3[w][threadIdx.x];
-    part[(size_t)(kGsRowC + threadIdx.x) * kGsMaxBlocks + blockIdx.x] = s;
+    part[(size_t)(kGsRowC + threadIdx.x) * kGsMaxBlocks + block] = s;
   }
+}
+
+template <typename TM, typename TZ>
+__global__ __launch_bounds__(kGsThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void
+k_arn_project(typename ArnProjectOp<TM, TZ>::Args a) {
+  ArnProjectOp<TM, TZ>::run(a, blockIdx.x, gridDim.x);
 }
 
 // Scalar part of the update kernel: complete column jc = j - 1 (if any),
@@ -709,12 +974,12 @@ __device__ void arn_column(int j, int update, const double* sums, const double* 
 // per lane (two rows per thread in flight), the coefficients broadcast from
 // LDS, and each row's sums run over the basis in ascending order.
 __device__ __forceinline__ void arn_rows(const double* __restrict__ W, double* __restrict__ V,
-                                         int64_t ldv, int n, int j, int rpb, const double* cf,
-                                         double inv, double tt) {
+                                         int64_t ldv, int n, int j, int rpb, int block,
+                                         const double* cf, double inv, double tt) {
   const int t = threadIdx.x;
   double* uj = V + (size_t)j * ldv;
   double* un = V + (size_t)(j + 1) * ldv;
-  const int r0 = blockIdx.x * rpb;
+  const int r0 = block * rpb;
   const int r1 = min(r0 + rpb, n);
   for (int ra = r0 + t; ra < r1; ra += 2 * kGsThreads) {
     const int rb = ra + kGsThreads;
@@ -747,73 +1012,191 @@ __device__ __forceinline__ void arn_rows(const double* __restrict__ W, double* _
 }
 
 // One workgroup per partial-sum row (2j + 3 rows): the sum over the
-// projection workgroups, in a fixed order, into st->sums.
-__global__ __launch_bounds__(kBlock) void k_arn_sum_rows(const double* part, int nb, int j,
-                                                         DevState* st) {
-  const int stop = gate_flag(st);
-  __shared__ double red[kBlock / 64];
-  const int i = blockIdx.x;
-  const int row = i < j ? kGsRowA + i : (i < 2 * j ? kGsRowB + (i - j) : kGsRowC + (i - 2 * j));
-  const double* p = part + (size_t)row * kGsMaxBlocks;
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nb; b += kBlock) s += p[b];
-  s = wave_sum(s);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0 && !stop) st->sums[i] = ((red[0] + red[1]) + red[2]) + red[3];
+// projection workgroups, in a fixed order, into st->sums.  (A replayed
+// launch has 2m + 3 workgroups; those past the step's rows return.)
+struct ArnSumRowsOp {
+  struct Args {
+    const double* part;
+    int nb, j;
+    DevState* st;
+  };
+  static constexpr int kThreads = kBlock;
+  static __device__ __forceinline__ void run(const Args& a, int block, int) {
+    DevState* st = a.st;
+    const int stop = gate_flag(st);
+    const int j = step_of(a.j, st);
+    if (a.j < 0 && (j >= st->m || block >= 2 * j + 3)) return;
+    __shared__ double red[kBlock / 64];
+    const int i = block;
+    const int row = i < j ? kGsRowA + i : (i < 2 * j ? kGsRowB + (i - j) : kGsRowC + (i - 2 * j));
+    const double* p = a.part + (size_t)row * kGsMaxBlocks;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < a.nb; b += kBlock) s += p[b];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0 && !stop) st->sums[i] = ((red[0] + red[1]) + red[2]) + red[3];
+  }
+};
+
+__global__ __launch_bounds__(kBlock) void k_arn_sum_rows(ArnSumRowsOp::Args a) {
+  ArnSumRowsOp::run(a, blockIdx.x, gridDim.x);
 }
 
 // Update pass of Arnoldi step j: every workgroup derives the coefficients
 // from the 2j + 3 sums (same arithmetic in each), streams its rows, and the
 // last workgroup completes the Hessenberg column.  With update == 0 (closing
 // step, one workgroup) only the column is completed.
-__global__ __launch_bounds__(kGsThreads) void k_arn_update(const double* __restrict__ W,
-                                                           double* __restrict__ V, int64_t ldv,
-                                                           int n, int j, int rpb, int update,
-                                                           DevState* st, HostFlags* hf) {
-  __shared__ double scratch[4 * kMaxBasis];
-  __shared__ double sums[kSumStride];
-  __shared__ double cf[2 * kMaxBasis];
-  __shared__ double sc[8];
-  const int t = threadIdx.x;
-  const int nr = 2 * j + 3;
-  const int stop = st->cycle_done;
-  if (t < nr) sums[t] = st->sums[t];
-  __syncthreads();
-  if (stop) return;
-  if (t == 0) {
-    double aa = 0.0, ab = 0.0, bb = 0.0;
-    for (int k = 0; k < j; ++k) {
-      aa += sums[k] * sums[k];
-      ab += sums[k] * sums[j + k];
-      bb += sums[j + k] * sums[j + k];
-    }
-    const double uu = sums[2 * j], uw = sums[2 * j + 1], ww = sums[2 * j + 2];
-    const double nu2 = uu - aa;
-    const double nu = nu2 > 0.0 ? sqrt(nu2) : 0.0;
-    const double inv = nu > 0.0 ? 1.0 / nu : 0.0;
-    const double hjj = (uw - ab) * inv;
-    const double rest = ww - bb - hjj * hjj;
-    const double floor = 1e-16 * ww;
-    sc[0] = inv;
-    sc[1] = hjj * inv;
-    sc[2] = nu;
-    sc[3] = hjj;
-    sc[4] = ww > 0.0 ? 1.0 / sqrt(rest > floor ? rest : floor) : 1.0;
-  }
-  __syncthreads();
-  if (update) {
-    if (t < j) {
-      cf[t] = sc[0] * sums[t];
-      cf[kMaxBasis + t] = sums[j + t] - sc[1] * sums[t];
+struct ArnUpdateOp {
+  struct Args {
+    const double* W;
+    double* V;
+    int64_t ldv;
+    int n, j, rpb, update;
+    DevState* st;
+    HostFlags* hf;
+  };
+  static constexpr int kThreads = kGsThreads;
+  static __device__ __forceinline__ void run(const Args& a, int block, int nblocks) {
+    __shared__ double scratch[4 * kMaxBasis];
+    __shared__ double sums[kSumStride];
+    __shared__ double cf[2 * kMaxBasis];
+    __shared__ double sc[8];
+    DevState* st = a.st;
+    const int j = step_of(a.j, st);
+    if (a.j < 0 && j >= st->m) return;     // no column beyond the cycle
+    const int update = a.update;
+    const int t = threadIdx.x;
+    const int nr = 2 * j + 3;
+    const int stop = st->cycle_done;
+    if (t < nr) sums[t] = st->sums[t];
+    __syncthreads();
+    if (stop) return;
+    if (t == 0) {
+      double aa = 0.0, ab = 0.0, bb = 0.0;
+      for (int k = 0; k < j; ++k) {
+        aa += sums[k] * sums[k];
+        ab += sums[k] * sums[j + k];
+        bb += sums[j + k] * sums[j + k];
+      }
+      const double uu = sums[2 * j], uw = sums[2 * j + 1], ww = sums[2 * j + 2];
+      const double nu2 = uu - aa;
+      const double nu = nu2 > 0.0 ? sqrt(nu2) : 0.0;
+      const double inv = nu > 0.0 ? 1.0 / nu : 0.0;
+      const double hjj = (uw - ab) * inv;
+      const double rest = ww - bb - hjj * hjj;
+      const double floor = 1e-16 * ww;
+      sc[0] = inv;
+      sc[1] = hjj * inv;
+      sc[2] = nu;
+      sc[3] = hjj;
+      sc[4] = ww > 0.0 ? 1.0 / sqrt(rest > floor ? rest : floor) : 1.0;
     }
     __syncthreads();
-    arn_rows(W, V, ldv, n, j, rpb, cf, sc[0], sc[1]);
+    if (update) {
+      if (t < j) {
+        cf[t] = sc[0] * sums[t];
+        cf[kMaxBasis + t] = sums[j + t] - sc[1] * sums[t];
+      }
+      __syncthreads();
+      arn_rows(a.W, a.V, a.ldv, a.n, j, a.rpb, block, cf, sc[0], sc[1]);
+    }
+    if (block == nblocks - 1) {
+      __syncthreads();
+      arn_column(j, update, sums, sc, st, a.hf, scratch, scratch + 2 * kMaxBasis);
+    }
   }
-  if (blockIdx.x == gridDim.x - 1) {
-    __syncthreads();
-    arn_column(j, update, sums, sc, st, hf, scratch, scratch + 2 * kMaxBasis);
+};
+
+__global__ __launch_bounds__(kGsThreads) void k_arn_update(ArnUpdateOp::Args a) {
+  ArnUpdateOp::run(a, blockIdx.x, gridDim.x);
+}
+
+// Copy-in and copy-out of a column of the request loop's shared graph: the
+// graph is replayed for every column, so the preconditioner works on fixed
+// per-solve buffers.  Copy-in records the step j = st->j in st->jstep (read by
+// the later kernels of the column) and copies u_j = V[j] and sigma_j into
+// them; copy-out stores the preconditioned vector into Z[j].  Neither runs
+// once the cycle is done or past its last column.
+struct CopyInOp {
+  struct Args {
+    const double* V;
+    int64_t ldv;
+    DevState* st;
+    double* rin;
+    double* sig;
+    int n;
+  };
+  static constexpr int kThreads = kBlock;
+  static __device__ __forceinline__ void run(const Args& a, int block, int) {
+    DevState* st = a.st;
+    if (st->cycle_done) return;
+    const int j = st->j;
+    const int i = block * kBlock + threadIdx.x;
+    if (i == 0) {
+      st->jstep = j;
+      if (j < st->m) *a.sig = st->sigma[j];
+    }
+    if (j >= st->m || i >= a.n) return;
+    a.rin[i] = a.V[(size_t)j * a.ldv + i];
   }
+};
+
+template <typename T>
+struct CopyOutOp {
+  struct Args {
+    const T* zfix;
+    T* Z;
+    int64_t ldz;
+    const DevState* st;
+    int n;
+  };
+  static constexpr int kThreads = kBlock;
+  static __device__ __forceinline__ void run(const Args& a, int block, int) {
+    const DevState* st = a.st;
+    if (st->cycle_done) return;
+    const int j = st->jstep;
+    const int i = block * kBlock + threadIdx.x;
+    if (j >= st->m || i >= a.n) return;
+    a.Z[(size_t)j * a.ldz + i] = a.zfix[i];
+  }
+};
+
+__global__ __launch_bounds__(kBlock) void k_copy_in(CopyInOp::Args a) {
+  CopyInOp::run(a, blockIdx.x, gridDim.x);
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_copy_out(typename CopyOutOp<T>::Args a) {
+  CopyOutOp<T>::run(a, blockIdx.x, gridDim.x);
+}
+
+// Batched launch of an Op over the slots of the request loop's shared graph.
+// The slot table is one device array of `stride` bytes per slot; slot s
+// holds this Op's argument struct at base + s * stride + args_off and its
+// workgroup count at base + s * stride + nb_off (0: an empty slot).
+// Workgroup g serves slot g / cap as its local workgroup g % cap.
+template <typename Op>
+__device__ __forceinline__ void batch_slot(const char* __restrict__ base, int stride,
+                                           int args_off, int nb_off, int cap) {
+  const int slot = blockIdx.x / cap;
+  const int lb = blockIdx.x - slot * cap;
+  const char* reg = base + (size_t)slot * stride;
+  const int nb = *reinterpret_cast<const int*>(reg + nb_off);
+  if (lb >= nb) return;
+  Op::run(*reinterpret_cast<const typename Op::Args*>(reg + args_off), lb, nb);
+}
+
+template <typename Op>
+__global__ __launch_bounds__(Op::kThreads) void k_batch(const char* __restrict__ base, int stride,
+                                                        int args_off, int nb_off, int cap) {
+  batch_slot<Op>(base, stride, args_off, nb_off, cap);
+}
+
+// The projection keeps its occupancy hint in the batched form too.
+template <typename TM, typename TZ>
+__global__ __launch_bounds__(kGsThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void
+k_batch_project(const char* __restrict__ base, int stride, int args_off, int nb_off, int cap) {
+  batch_slot<ArnProjectOp<TM, TZ>>(base, stride, args_off, nb_off, cap);
 }
 
 // y = R^-1 g for the k x k upper triangle R of H (one wavefront): the
@@ -1123,31 +1506,6 @@ __global__ void k_set_cycle_length(DevState* st, int m) {
   if (threadIdx.x == 0 && blockIdx.x == 0) st->m = m;
 }
 
-template <typename TB, typename T>
-__global__ __launch_bounds__(kBlock) void k_scale_convert(const TB* __restrict__ b,
-                                                          const double* bscale,
-                                                          T* __restrict__ out, int n,
-                                                          const DevState* gate) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const int stop = gate_flag(gate);
-  const T v = load_b<T>(b, scale_of(bscale), i);
-  if (!stop) out[i] = v;
-}
-
-template <typename TA, typename TB>
-__global__ __launch_bounds__(kBlock) void k_convert(const TA* __restrict__ a, TB* __restrict__ b,
-                                                    int n) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) b[i] = (TB)a[i];
-}
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_fill(T* __restrict__ a, T v, int n) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) a[i] = v;
-}
-
 // Right-hand side of one backward-Euler step: out = b + m x on the rows whose
 // momentum balance has a time derivative (u faces i = 1..nx-1: rows
 // r < off_v with 1 <= r % nux + ifirst <= nx - 1; v faces off the interface: rows
@@ -1187,73 +1545,104 @@ inline int blocks_lpr(int n, int lpr) {
   return (int)((waves * 64 + kBlock - 1) / kBlock);
 }
 
+// Launches go through launch_op: normally a launch of the Op's named
+// kernel; while a recorder is installed on the calling thread (the request
+// loop building its shared graph) the launch is recorded instead, with the
+// Op's batched kernel, its arguments and its workgroup count.
+thread_local std::vector<RecordedOp>* g_recorder = nullptr;
+
+void set_launch_recorder(std::vector<RecordedOp>* rec) { g_recorder = rec; }
+
+template <typename Op, typename K, typename B>
+void launch_op(K kernel, B batched, const typename Op::Args& a, int nb, size_t lds,
+               hipStream_t s) {
+  if (nb <= 0) return;
+  if (g_recorder) {
+    RecordedOp r;
+    r.fn = reinterpret_cast<const void*>(batched);
+    r.args.assign(reinterpret_cast<const char*>(&a), reinterpret_cast<const char*>(&a) + sizeof(a));
+    r.nblocks = nb;
+    r.threads = Op::kThreads;
+    r.lds = lds;
+    g_recorder->push_back(std::move(r));
+    return;
+  }
+  kernel<<<nb, Op::kThreads, lds, s>>>(a);
+}
+
+// Calls f with the lanes-per-row count as a compile-time constant.
+template <typename F>
+void by_lpr(int lpr, F&& f) {
+  switch (lpr) {
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    case 16: f(std::integral_constant<int, 16>{}); break;
+    case 32: f(std::integral_constant<int, 32>{}); break;
+    case 64: f(std::integral_constant<int, 64>{}); break;
+    default: f(std::integral_constant<int, 1>{}); break;
+  }
+}
+
 template <typename TM, typename TX, typename TY>
 void launch_spmv(const Sell<TM>& A, const TX* x, TY* y, const DevState* gate, hipStream_t s) {
   if (A.n_rows <= 0) return;
-  switch (A.lpr) {
-    case 4: k_spmv<4, TM, TX, TY><<<blocks_lpr(A.n_rows, 4), kBlock, 0, s>>>(A, x, y, gate); break;
-    case 8: k_spmv<8, TM, TX, TY><<<blocks_lpr(A.n_rows, 8), kBlock, 0, s>>>(A, x, y, gate); break;
-    case 16: k_spmv<16, TM, TX, TY><<<blocks_lpr(A.n_rows, 16), kBlock, 0, s>>>(A, x, y, gate); break;
-    case 32: k_spmv<32, TM, TX, TY><<<blocks_lpr(A.n_rows, 32), kBlock, 0, s>>>(A, x, y, gate); break;
-    case 64: k_spmv<64, TM, TX, TY><<<blocks_lpr(A.n_rows, 64), kBlock, 0, s>>>(A, x, y, gate); break;
-    default: k_spmv<1, TM, TX, TY><<<blocks_lpr(A.n_rows, 1), kBlock, 0, s>>>(A, x, y, gate); break;
-  }
+  by_lpr(A.lpr, [&](auto L) {
+    constexpr int l = decltype(L)::value;
+    using Op = SpmvOp<l, TM, TX, TY>;
+    launch_op<Op>(k_spmv<l, TM, TX, TY>, k_batch<Op>, typename Op::Args{A, x, y, gate},
+                  blocks_lpr(A.n_rows, l), 0, s);
+  });
 }
 
 template <typename T, typename TB>
 void launch_residual(const Sell<T>& A, const TB* b, const double* bscale, const T* x, T* r,
                      const DevState* gate, hipStream_t s) {
   if (A.n_rows <= 0) return;
-  switch (A.lpr) {
-    case 4: k_residual<4, T, TB><<<blocks_lpr(A.n_rows, 4), kBlock, 0, s>>>(A, b, bscale, x, r, gate); break;
-    case 8: k_residual<8, T, TB><<<blocks_lpr(A.n_rows, 8), kBlock, 0, s>>>(A, b, bscale, x, r, gate); break;
-    case 16: k_residual<16, T, TB><<<blocks_lpr(A.n_rows, 16), kBlock, 0, s>>>(A, b, bscale, x, r, gate); break;
-    case 32: k_residual<32, T, TB><<<blocks_lpr(A.n_rows, 32), kBlock, 0, s>>>(A, b, bscale, x, r, gate); break;
-    case 64: k_residual<64, T, TB><<<blocks_lpr(A.n_rows, 64), kBlock, 0, s>>>(A, b, bscale, x, r, gate); break;
-    default: k_residual<1, T, TB><<<blocks_lpr(A.n_rows, 1), kBlock, 0, s>>>(A, b, bscale, x, r, gate); break;
-  }
+  by_lpr(A.lpr, [&](auto L) {
+    constexpr int l = decltype(L)::value;
+    using Op = ResidualOp<l, T, TB>;
+    launch_op<Op>(k_residual<l, T, TB>, k_batch<Op>, typename Op::Args{A, b, bscale, x, r, gate},
+                  blocks_lpr(A.n_rows, l), 0, s);
+  });
 }
 
 template <typename T, typename TB>
 void launch_jacobi_zero(const Sell<T>& A, const T* wd, const TB* b, const double* bscale, T* x,
                         int two, const DevState* gate, hipStream_t s) {
   if (A.n_rows <= 0) return;
-  switch (A.lpr) {
-    case 4: k_jacobi_zero<4, T, TB><<<blocks_lpr(A.n_rows, 4), kBlock, 0, s>>>(A, wd, b, bscale, x, two, gate); break;
-    case 8: k_jacobi_zero<8, T, TB><<<blocks_lpr(A.n_rows, 8), kBlock, 0, s>>>(A, wd, b, bscale, x, two, gate); break;
-    case 16: k_jacobi_zero<16, T, TB><<<blocks_lpr(A.n_rows, 16), kBlock, 0, s>>>(A, wd, b, bscale, x, two, gate); break;
-    case 32: k_jacobi_zero<32, T, TB><<<blocks_lpr(A.n_rows, 32), kBlock, 0, s>>>(A, wd, b, bscale, x, two, gate); break;
-    case 64: k_jacobi_zero<64, T, TB><<<blocks_lpr(A.n_rows, 64), kBlock, 0, s>>>(A, wd, b, bscale, x, two, gate); break;
-    default: k_jacobi_zero<1, T, TB><<<blocks_lpr(A.n_rows, 1), kBlock, 0, s>>>(A, wd, b, bscale, x, two, gate); break;
-  }
+  by_lpr(A.lpr, [&](auto L) {
+    constexpr int l = decltype(L)::value;
+    using Op = JacobiZeroOp<l, T, TB>;
+    launch_op<Op>(k_jacobi_zero<l, T, TB>, k_batch<Op>,
+                  typename Op::Args{A, wd, b, bscale, x, two, gate}, blocks_lpr(A.n_rows, l), 0,
+                  s);
+  });
 }
 
 template <typename T, typename TB>
 void launch_jacobi(const Sell<T>& A, const T* wd, const TB* b, const double* bscale,
                    const T* x_in, T* x_out, const DevState* gate, hipStream_t s) {
   if (A.n_rows <= 0) return;
-  switch (A.lpr) {
-    case 4: k_jacobi<4, T, TB><<<blocks_lpr(A.n_rows, 4), kBlock, 0, s>>>(A, wd, b, bscale, x_in, x_out, gate); break;
-    case 8: k_jacobi<8, T, TB><<<blocks_lpr(A.n_rows, 8), kBlock, 0, s>>>(A, wd, b, bscale, x_in, x_out, gate); break;
-    case 16: k_jacobi<16, T, TB><<<blocks_lpr(A.n_rows, 16), kBlock, 0, s>>>(A, wd, b, bscale, x_in, x_out, gate); break;
-    case 32: k_jacobi<32, T, TB><<<blocks_lpr(A.n_rows, 32), kBlock, 0, s>>>(A, wd, b, bscale, x_in, x_out, gate); break;
-    case 64: k_jacobi<64, T, TB><<<blocks_lpr(A.n_rows, 64), kBlock, 0, s>>>(A, wd, b, bscale, x_in, x_out, gate); break;
-    default: k_jacobi<1, T, TB><<<blocks_lpr(A.n_rows, 1), kBlock, 0, s>>>(A, wd, b, bscale, x_in, x_out, gate); break;
-  }
+  by_lpr(A.lpr, [&](auto L) {
+    constexpr int l = decltype(L)::value;
+    using Op = JacobiOp<l, T, TB>;
+    launch_op<Op>(k_jacobi<l, T, TB>, k_batch<Op>,
+                  typename Op::Args{A, wd, b, bscale, x_in, x_out, gate},
+                  blocks_lpr(A.n_rows, l), 0, s);
+  });
 }
 
 template <typename T, typename TB>
 void launch_restrict_residual(const Sell<T>& Q, const TB* b, const double* bscale, const T* x,
                               int n_fine, T* bc, const DevState* gate, hipStream_t s) {
   if (Q.n_rows <= 0) return;
-  switch (Q.lpr) {
-    case 4: k_restrict_residual<4, T, TB><<<blocks_lpr(Q.n_rows, 4), kBlock, 0, s>>>(Q, b, bscale, x, n_fine, bc, gate); break;
-    case 8: k_restrict_residual<8, T, TB><<<blocks_lpr(Q.n_rows, 8), kBlock, 0, s>>>(Q, b, bscale, x, n_fine, bc, gate); break;
-    case 16: k_restrict_residual<16, T, TB><<<blocks_lpr(Q.n_rows, 16), kBlock, 0, s>>>(Q, b, bscale, x, n_fine, bc, gate); break;
-    case 32: k_restrict_residual<32, T, TB><<<blocks_lpr(Q.n_rows, 32), kBlock, 0, s>>>(Q, b, bscale, x, n_fine, bc, gate); break;
-    case 64: k_restrict_residual<64, T, TB><<<blocks_lpr(Q.n_rows, 64), kBlock, 0, s>>>(Q, b, bscale, x, n_fine, bc, gate); break;
-    default: k_restrict_residual<1, T, TB><<<blocks_lpr(Q.n_rows, 1), kBlock, 0, s>>>(Q, b, bscale, x, n_fine, bc, gate); break;
-  }
+  by_lpr(Q.lpr, [&](auto L) {
+    constexpr int l = decltype(L)::value;
+    using Op = RestrictResidualOp<l, T, TB>;
+    launch_op<Op>(k_restrict_residual<l, T, TB>, k_batch<Op>,
+                  typename Op::Args{Q, b, bscale, x, n_fine, bc, gate}, blocks_lpr(Q.n_rows, l),
+                  0, s);
+  });
 }
 
 template <typename T, typename TB>
@@ -1264,14 +1653,12 @@ void launch_presmooth_restrict(const Sell<T>& A, const T* wd, const Sell<T>& G, 
   if (G.lpr != 64) throw_launch("presmooth_restrict: G must use 64 lanes per row");
   const int nb_a = blocks_lpr(A.n_rows, A.lpr);
   const int nb = nb_a + blocks_lpr(G.n_rows, 64);
-  switch (A.lpr) {
-    case 4: k_presmooth_restrict<4, T, TB><<<nb, kBlock, 0, s>>>(A, wd, G, b, bscale, x, bc, nb_a, gate); break;
-    case 8: k_presmooth_restrict<8, T, TB><<<nb, kBlock, 0, s>>>(A, wd, G, b, bscale, x, bc, nb_a, gate); break;
-    case 16: k_presmooth_restrict<16, T, TB><<<nb, kBlock, 0, s>>>(A, wd, G, b, bscale, x, bc, nb_a, gate); break;
-    case 32: k_presmooth_restrict<32, T, TB><<<nb, kBlock, 0, s>>>(A, wd, G, b, bscale, x, bc, nb_a, gate); break;
-    case 64: k_presmooth_restrict<64, T, TB><<<nb, kBlock, 0, s>>>(A, wd, G, b, bscale, x, bc, nb_a, gate); break;
-    default: k_presmooth_restrict<1, T, TB><<<nb, kBlock, 0, s>>>(A, wd, G, b, bscale, x, bc, nb_a, gate); break;
-  }
+  by_lpr(A.lpr, [&](auto L) {
+    constexpr int l = decltype(L)::value;
+    using Op = PresmoothRestrictOp<l, T, TB>;
+    launch_op<Op>(k_presmooth_restrict<l, T, TB>, k_batch<Op>,
+                  typename Op::Args{A, wd, G, b, bscale, x, bc, nb_a, gate}, nb, 0, s);
+  });
 }
 
 template <typename T, typename TB>
@@ -1280,40 +1667,39 @@ void launch_prolong_smooth(const Sell<T>& A, const Sell<T>& F, const T* wd, cons
                            const DevState* gate, hipStream_t s) {
   if (A.n_rows <= 0) return;
   if (F.lpr != A.lpr) throw_launch("prolong_smooth: F must use A's lanes per row");
-  switch (A.lpr) {
-    case 4: k_prolong_smooth<4, T, TB><<<blocks_lpr(A.n_rows, 4), kBlock, 0, s>>>(A, F, wd, b, bscale, x, xc, xout, gate); break;
-    case 8: k_prolong_smooth<8, T, TB><<<blocks_lpr(A.n_rows, 8), kBlock, 0, s>>>(A, F, wd, b, bscale, x, xc, xout, gate); break;
-    case 16: k_prolong_smooth<16, T, TB><<<blocks_lpr(A.n_rows, 16), kBlock, 0, s>>>(A, F, wd, b, bscale, x, xc, xout, gate); break;
-    case 32: k_prolong_smooth<32, T, TB><<<blocks_lpr(A.n_rows, 32), kBlock, 0, s>>>(A, F, wd, b, bscale, x, xc, xout, gate); break;
-    case 64: k_prolong_smooth<64, T, TB><<<blocks_lpr(A.n_rows, 64), kBlock, 0, s>>>(A, F, wd, b, bscale, x, xc, xout, gate); break;
-    default: k_prolong_smooth<1, T, TB><<<blocks_lpr(A.n_rows, 1), kBlock, 0, s>>>(A, F, wd, b, bscale, x, xc, xout, gate); break;
-  }
+  by_lpr(A.lpr, [&](auto L) {
+    constexpr int l = decltype(L)::value;
+    using Op = ProlongSmoothOp<l, T, TB>;
+    launch_op<Op>(k_prolong_smooth<l, T, TB>, k_batch<Op>,
+                  typename Op::Args{A, F, wd, b, bscale, x, xc, xout, gate},
+                  blocks_lpr(A.n_rows, l), 0, s);
+  });
 }
 
 template <typename T>
 void launch_prolong(const Sell<T>& P, const T* xc, T* x, const DevState* gate, hipStream_t s) {
   if (P.n_rows <= 0) return;
-  switch (P.lpr) {
-    case 4: k_prolong<4, T><<<blocks_lpr(P.n_rows, 4), kBlock, 0, s>>>(P, xc, x, gate); break;
-    case 8: k_prolong<8, T><<<blocks_lpr(P.n_rows, 8), kBlock, 0, s>>>(P, xc, x, gate); break;
-    case 16: k_prolong<16, T><<<blocks_lpr(P.n_rows, 16), kBlock, 0, s>>>(P, xc, x, gate); break;
-    case 32: k_prolong<32, T><<<blocks_lpr(P.n_rows, 32), kBlock, 0, s>>>(P, xc, x, gate); break;
-    case 64: k_prolong<64, T><<<blocks_lpr(P.n_rows, 64), kBlock, 0, s>>>(P, xc, x, gate); break;
-    default: k_prolong<1, T><<<blocks_lpr(P.n_rows, 1), kBlock, 0, s>>>(P, xc, x, gate); break;
-  }
+  by_lpr(P.lpr, [&](auto L) {
+    constexpr int l = decltype(L)::value;
+    using Op = ProlongOp<l, T>;
+    launch_op<Op>(k_prolong<l, T>, k_batch<Op>, typename Op::Args{P, xc, x, gate},
+                  blocks_lpr(P.n_rows, l), 0, s);
+  });
 }
 
 template <typename T>
 void launch_ilu0(const IluDev<T>& F, const T* r, T* z, const DevState* gate, hipStream_t s) {
   if (F.n <= 0) return;
-  k_ilu0<T><<<1, kIluThreads, 0, s>>>(F, r, z, gate);
+  using Op = Ilu0Op<T>;
+  launch_op<Op>(k_ilu0<T>, k_batch<Op>, typename Op::Args{F, r, z, gate}, 1, 0, s);
 }
 
 template <typename T>
 void launch_coarse(const double* Ainv, int n, const T* bc, T* xc, const DevState* gate,
                    hipStream_t s) {
   if (n <= 0) return;
-  k_coarse<T><<<n, kBlock, 0, s>>>(Ainv, n, bc, xc, gate);
+  using Op = CoarseOp<T>;
+  launch_op<Op>(k_coarse<T>, k_batch<Op>, typename Op::Args{Ainv, n, bc, xc, gate}, n, 0, s);
 }
 
 template <typename T>
@@ -1321,14 +1707,17 @@ void launch_block_sweep(const Sell<T>& Cf, int n_p, const double* r, const doubl
                         const T* yv, double xscale, T* zp, T* tq, T* tp, const DevState* gate,
                         hipStream_t s) {
   if (Cf.n_rows <= 0) return;
-  k_block_sweep<T><<<blocks_for(Cf.n_rows), kBlock, 0, s>>>(Cf, n_p, r, bscale, yv, xscale, zp,
-                                                            tq, tp, gate);
+  using Op = BlockSweepOp<T>;
+  launch_op<Op>(k_block_sweep<T>, k_batch<Op>,
+                typename Op::Args{Cf, n_p, r, bscale, yv, xscale, zp, tq, tp, gate},
+                blocks_for(Cf.n_rows), 0, s);
 }
 
 template <typename T>
 void launch_add(const T* a, T* y, int n, const DevState* gate, hipStream_t s) {
   if (n <= 0) return;
-  k_add<T><<<blocks_for(n), kBlock, 0, s>>>(a, y, n, gate);
+  using Op = AddOp<T>;
+  launch_op<Op>(k_add<T>, k_batch<Op>, typename Op::Args{a, y, n, gate}, blocks_for(n), 0, s);
 }
 
 // Rows per workgroup: the projection kernel takes 1024 (two workgroups per
@@ -1351,13 +1740,20 @@ void launch_arnoldi_step(const Sell<TM>& A, const TZ* z, double* W, double* V, i
   const int n = A.n_rows;
   const int rp = gs_rows_per_block(n, kGsProjectRows), ru = gs_rows_per_block(n, kUpdateRows);
   const int np = (n + rp - 1) / rp, nu = (n + ru - 1) / ru;
+  // j < 0: the step comes from st->jstep; the sums then get a workgroup per
+  // row of the largest step the basis holds
+  const int nsum = j >= 0 ? 2 * j + 3 : 2 * (kMaxBasis - 1) + 3;
+  using POp = ArnProjectOp<TM, TZ>;
   if (ev && prof_class == 1) (void)hipEventRecord(ev[0], s);
-  k_arn_project<TM, TZ><<<np, kGsThreads, (size_t)2 * rp * sizeof(double), s>>>(
-      A, z, W, V, ldv, n, j, rp, 1, st, part);
+  launch_op<POp>(k_arn_project<TM, TZ>, k_batch_project<TM, TZ>,
+                 typename POp::Args{A, z, W, V, ldv, n, j, rp, 1, st, part}, np,
+                 (size_t)2 * rp * sizeof(double), s);
   if (ev && prof_class == 1) (void)hipEventRecord(ev[1], s);
-  k_arn_sum_rows<<<2 * j + 3, kBlock, 0, s>>>(part, np, j, st);
+  launch_op<ArnSumRowsOp>(k_arn_sum_rows, k_batch<ArnSumRowsOp>,
+                          ArnSumRowsOp::Args{part, np, j, st}, nsum, 0, s);
   if (ev && prof_class == 2) (void)hipEventRecord(ev[0], s);
-  k_arn_update<<<nu, kGsThreads, 0, s>>>(W, V, ldv, n, j, ru, 1, st, hf);
+  launch_op<ArnUpdateOp>(k_arn_update, k_batch<ArnUpdateOp>,
+                         ArnUpdateOp::Args{W, V, ldv, n, j, ru, 1, st, hf}, nu, 0, s);
   if (ev && prof_class == 2) (void)hipEventRecord(ev[1], s);
 }
 
@@ -1365,10 +1761,24 @@ void launch_arnoldi_close(int n, double* V, int64_t ldv, int j, DevState* st, do
                           HostFlags* hf, hipStream_t s) {
   const int rp = gs_rows_per_block(n, kGsProjectRows);
   const int np = (n + rp - 1) / rp;
+  using POp = ArnProjectOp<double, double>;
   k_arn_project<double, double><<<np, kGsThreads, (size_t)2 * rp * sizeof(double), s>>>(
-      Sell<double>{}, nullptr, nullptr, V, ldv, n, j, rp, 0, st, part);
-  k_arn_sum_rows<<<2 * j + 3, kBlock, 0, s>>>(part, np, j, st);
-  k_arn_update<<<1, kGsThreads, 0, s>>>(nullptr, V, ldv, n, j, kUpdateRows, 0, st, hf);
+      POp::Args{Sell<double>{}, nullptr, nullptr, V, ldv, n, j, rp, 0, st, part});
+  k_arn_sum_rows<<<2 * j + 3, kBlock, 0, s>>>(ArnSumRowsOp::Args{part, np, j, st});
+  k_arn_update<<<1, kGsThreads, 0, s>>>(
+      ArnUpdateOp::Args{nullptr, V, ldv, n, j, kUpdateRows, 0, st, hf});
+}
+
+void launch_copy_in(const double* V, int64_t ldv, DevState* st, double* rin, double* sig, int n,
+                    hipStream_t s) {
+  launch_op<CopyInOp>(k_copy_in, k_batch<CopyInOp>,
+                      CopyInOp::Args{V, ldv, st, rin, sig, n}, blocks_for(n), 0, s);
+}
+
+template <typename T>
+void launch_copy_out(const T* zfix, T* Z, int64_t ldz, const DevState* st, int n, hipStream_t s) {
+  launch_op<CopyOutOp<T>>(k_copy_out<T>, k_batch<CopyOutOp<T>>,
+                          typename CopyOutOp<T>::Args{zfix, Z, ldz, st, n}, blocks_for(n), 0, s);
 }
 
 void launch_trisolve(DevState* st, hipStream_t s) { k_trisolve<<<1, 64, 0, s>>>(st); }
@@ -1500,20 +1910,21 @@ void launch_set_cycle_length(DevState* st, int m, hipStream_t s) {
 template <typename TB, typename T>
 void launch_scale_convert(const TB* b, const double* bscale, T* out, int n, const DevState* gate,
                           hipStream_t s) {
-  if (n <= 0) return;
-  k_scale_convert<TB, T><<<blocks_for(n), kBlock, 0, s>>>(b, bscale, out, n, gate);
+  using Op = ScaleConvertOp<TB, T>;
+  launch_op<Op>(k_scale_convert<TB, T>, k_batch<Op>, typename Op::Args{b, bscale, out, n, gate},
+                blocks_for(n), 0, s);
 }
 
 template <typename TA, typename TB>
 void launch_convert(const TA* a, TB* b, int n, hipStream_t s) {
-  if (n <= 0) return;
-  k_convert<TA, TB><<<blocks_for(n), kBlock, 0, s>>>(a, b, n);
+  using Op = ConvertOp<TA, TB>;
+  launch_op<Op>(k_convert<TA, TB>, k_batch<Op>, typename Op::Args{a, b, n}, blocks_for(n), 0, s);
 }
 
 template <typename T>
 void launch_fill(T* a, T v, int n, hipStream_t s) {
-  if (n <= 0) return;
-  k_fill<T><<<blocks_for(n), kBlock, 0, s>>>(a, v, n);
+  using Op = FillOp<T>;
+  launch_op<Op>(k_fill<T>, k_batch<Op>, typename Op::Args{a, v, n}, blocks_for(n), 0, s);
 }
 
 void launch_step_rhs(const double* b, const double* x, double* out, double m, int n, int nux,
@@ -1592,6 +2003,10 @@ template void launch_convert<float, float>(const float*, float*, int, hipStream_
 template void launch_convert<double, float>(const double*, float*, int, hipStream_t);
 template void launch_convert<float, double>(const float*, double*, int, hipStream_t);
 template void launch_convert<double, double>(const double*, double*, int, hipStream_t);
+template void launch_copy_out<double>(const double*, double*, int64_t, const DevState*, int,
+                                      hipStream_t);
+template void launch_copy_out<float>(const float*, float*, int64_t, const DevState*, int,
+                                     hipStream_t);
 template void launch_fill<double>(double*, double, int, hipStream_t);
 template void launch_fill<float>(float*, float, int, hipStream_t);
 

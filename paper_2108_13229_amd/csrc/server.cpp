@@ -6,18 +6,30 @@
 // system, builds the AMG hierarchies and uploads everything (matrices,
 // hierarchies and Krylov state stay resident until the request retires).
 // The scheduler advances every active solve through its resumable FGMRES
-// state machine on the request's own stream: each step enqueues one
-// hipGraph-captured Arnoldi column (or a restart) without blocking, so the
-// kernels of concurrent requests overlap on the device.  Requests join and
-// leave at iteration boundaries; a finished request's solution is copied to
-// the host and its device memory released at once.  Every request runs its
-// own deterministic kernels, so its result is bit-identical alone and in a mix.
+// state machine on the request's own stream (restart residuals, the
+// least-squares update at the end of a cycle), without blocking.
+//
+// The Arnoldi columns of concurrent solves run in shared launches: every
+// request records one column of its iteration once (copy-in of u_j, the
+// preconditioner's V-cycles and block sweep on fixed buffers, copy-out into
+// Z[j], the Gram-Schmidt step; the step j is read on the device), and
+// requests whose recorded columns have the same kernel sequence form a group.
+// A group keeps a device table with one region per slot (each member's
+// kernel arguments and workgroup counts) and one hipGraph with ONE batched
+// launch per kernel of the column, covering every slot; each replay advances
+// every member by one column, whatever column each is at.  Requests join a
+// group after their restart residual and leave it at the end of their cycle
+// (their table region's workgroup counts zeroed, their stream ordered after
+// the group's last replay).  A member computes exactly what its own kernels
+// would (same arithmetic per row and the same reduction order), so every
+// result is bit-identical alone, in a mix and to a direct sd_solve.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstring>
 #include <deque>
 #include <map>
 #include <memory>
@@ -56,7 +68,63 @@ struct Request {
   int64_t N = 0;
   sd_stats stats{};
   double t_submit = 0.0, t_admit = 0.0, t_done = 0.0;
+  // shared-launch state: the recorded column, its table region, the group
+  std::vector<sd::RecordedOp> rec;
+  std::vector<char> region;
+  struct Group* grp = nullptr;
+  int slot = -1;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
 };
+
+// Requests whose recorded columns have the same kernel sequence (launch
+// shapes aside) share a group; see the top of this file.
+constexpr int kGroupAhead = 2;        // replays enqueued beyond the completed ones
+
+struct GroupOp {
+  const void* fn = nullptr;
+  int threads = 0;
+  size_t lds = 0, args_size = 0;
+  int args_off = 0;                   // in a slot region
+  int cap = 0;                        // workgroups per slot in the graph
+};
+
+struct Member {
+  Request* r = nullptr;
+  uint64_t join_step = 0;             // the replay that runs its column 0
+  bool active = false;                // still in the table's workgroup counts
+};
+
+struct Group {
+  std::string key;
+  std::vector<GroupOp> ops;
+  int slots = 0;
+  int stride = 0, nb_off = 0;         // slot region bytes; workgroup counts at nb_off
+  char* table = nullptr;              // device, slots * stride bytes
+  std::vector<Member> mem;            // per slot
+  hipStream_t stream = nullptr;
+  hipGraphExec_t graph = nullptr;
+  bool dirty = true;                  // capture before the next replay
+  uint64_t enq = 0, done = 0;         // replays enqueued / completed
+  std::vector<hipEvent_t> ev;         // ring, one per replay in flight
+  int members() const {
+    int n = 0;
+    for (const Member& m : mem) n += m.r != nullptr;
+    return n;
+  }
+};
+
+// The group key of a recorded column: each kernel with its block size,
+// dynamic LDS and argument size.
+std::string group_key(const std::vector<sd::RecordedOp>& ops) {
+  std::string k;
+  for (const sd::RecordedOp& o : ops) {
+    const uintptr_t f = (uintptr_t)o.fn;
+    const uint64_t v[4] = {(uint64_t)f, (uint64_t)o.threads, (uint64_t)o.lds,
+                           (uint64_t)o.args.size()};
+    k.append(reinterpret_cast<const char*>(v), sizeof(v));
+  }
+  return k;
+}
 
 int64_t unknowns(const sd_grid& g, int ff_right) {
   const int64_t nux = ff_right == SD_BC_TRACTION ? g.nx : g.nx - 1;
@@ -77,6 +145,7 @@ size_t estimate_bytes(const sd_grid& g, int ff_right, const sd_solver_opts& o) {
   b += (o.schur == SD_SCHUR_CC ? 3.0 : 2.0) * nc * nc * 8.0;    // coarse inverses
   b += (o.restart + 2.0) * N * 8.0 + o.restart * N * tb;        // basis, Z, W
   b += 4.0 * N * 8.0 + (4 << 20);                               // b, x, misc
+  b += N * (8.0 + tb);                                          // replayed-column buffers
   return (size_t)b;
 }
 
@@ -106,11 +175,210 @@ struct sd_server {
   std::vector<std::thread> prep;
   std::vector<hipStream_t> prep_streams;
   double t0 = 0.0;
+  // groups of the shared launches (scheduler thread only)
+  std::map<std::string, std::unique_ptr<Group>> groups;
+  std::atomic<int64_t> n_groups{0}, n_replays{0}, n_member_columns{0};
+  std::atomic<int> max_members{0};
 
   void prep_loop(hipStream_t stream);
   void sched_loop();
   void retire(Request* r, int status, const std::string& err);
+  // shared launches (scheduler thread)
+  void join_group(Request* r);
+  void leave_group(Request* r, bool end_cycle, bool full);
+  bool step_group(Group& g);
+  void capture(Group& g);
+  void destroy_groups();
 };
+
+void sd_server::capture(Group& g) {
+  if (g.graph) {
+    SD_HIP(hipStreamSynchronize(g.stream));
+    SD_HIP(hipGraphExecDestroy(g.graph));
+    g.graph = nullptr;
+  }
+  hipGraph_t graph = nullptr;
+  SD_HIP(hipStreamBeginCapture(g.stream, hipStreamCaptureModeThreadLocal));
+  hipError_t err = hipSuccess;
+  for (size_t k = 0; k < g.ops.size() && err == hipSuccess; ++k) {
+    const GroupOp& o = g.ops[k];
+    const char* base = g.table;
+    int stride = g.stride, aoff = o.args_off, noff = g.nb_off + 4 * (int)k, cap = o.cap;
+    void* args[] = {&base, &stride, &aoff, &noff, &cap};
+    err = hipLaunchKernel(o.fn, dim3((unsigned)(g.slots * o.cap)), dim3((unsigned)o.threads), args,
+                          o.lds, g.stream);
+  }
+  const hipError_t e2 = hipStreamEndCapture(g.stream, &graph);
+  if (err != hipSuccess || e2 != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    throw sd::Error(SD_E_DEVICE, std::string("capturing the shared column graph: ") +
+                                     hipGetErrorString(err != hipSuccess ? err : e2));
+  }
+  SD_HIP(hipGraphInstantiate(&g.graph, graph, nullptr, nullptr, 0));
+  SD_HIP(hipGraphDestroy(graph));
+  g.dirty = false;
+}
+
+void sd_server::join_group(Request* r) {
+  sd::Solver& S = *r->solver;
+  if (r->rec.empty()) {
+    S.prec->record_column(S, r->rec);
+    if (r->rec.empty()) throw sd::Error(SD_E_INVALID, "empty recorded column");
+  }
+  const std::string key = group_key(r->rec);
+  auto it = groups.find(key);
+  Group* g = nullptr;
+  if (it != groups.end() && it->second->members() < it->second->slots) {
+    g = it->second.get();
+  } else if (it == groups.end()) {
+    std::unique_ptr<Group> ng(new Group());
+    ng->key = key;
+    ng->slots = opts.max_slots;
+    int off = 0;
+    for (const sd::RecordedOp& o : r->rec) {
+      GroupOp go;
+      go.fn = o.fn;
+      go.threads = o.threads;
+      go.lds = o.lds;
+      go.args_size = o.args.size();
+      go.args_off = off;
+      go.cap = 0;
+      off += (int)((o.args.size() + 15) / 16 * 16);
+      ng->ops.push_back(go);
+    }
+    ng->nb_off = off;
+    ng->stride = (int)((off + 4 * (int)r->rec.size() + 255) / 256 * 256);
+    ng->mem.resize((size_t)ng->slots);
+    SD_HIP(hipStreamCreateWithFlags(&ng->stream, hipStreamNonBlocking));
+    // the table (a few KiB per slot) comes from the stream-ordered pool
+    void* t = nullptr;
+    SD_HIP(hipMallocAsync(&t, (size_t)ng->slots * ng->stride, ng->stream));
+    ng->table = static_cast<char*>(t);
+    ng->ev.resize(kGroupAhead + 2);
+    for (auto& e : ng->ev) SD_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    // empty slots: zero workgroup counts
+    SD_HIP(hipMemsetAsync(ng->table, 0, (size_t)ng->slots * ng->stride, ng->stream));
+    g = ng.get();
+    groups[key] = std::move(ng);
+    n_groups.fetch_add(1);
+  } else {
+    return;   // the group is full: this request joins once a slot frees
+  }
+  int slot = -1;
+  for (int k = 0; k < g->slots; ++k)
+    if (!g->mem[(size_t)k].r) {
+      slot = k;
+      break;
+    }
+  // the slot's region: each kernel's arguments, then the workgroup counts
+  r->region.assign((size_t)g->stride, 0);
+  for (size_t k = 0; k < g->ops.size(); ++k) {
+    const sd::RecordedOp& o = r->rec[k];
+    std::memcpy(r->region.data() + g->ops[k].args_off, o.args.data(), o.args.size());
+    const int nb = o.nblocks;
+    std::memcpy(r->region.data() + g->nb_off + 4 * k, &nb, sizeof(int));
+    if (nb > g->ops[k].cap) {
+      g->ops[k].cap = nb + nb / 8;   // room for members with a few more rows
+      g->dirty = true;
+    }
+  }
+  if (!r->ev_in) SD_HIP(hipEventCreateWithFlags(&r->ev_in, hipEventDisableTiming));
+  if (!r->ev_out) SD_HIP(hipEventCreateWithFlags(&r->ev_out, hipEventDisableTiming));
+  // the replays start after the request's restart work
+  SD_HIP(hipEventRecord(r->ev_in, S.stream));
+  SD_HIP(hipStreamWaitEvent(g->stream, r->ev_in, 0));
+  SD_HIP(hipMemcpyAsync(g->table + (size_t)slot * g->stride, r->region.data(), (size_t)g->stride,
+                        hipMemcpyHostToDevice, g->stream));
+  g->mem[(size_t)slot] = Member{r, g->enq, true};
+  r->grp = g;
+  r->slot = slot;
+  r->run.batched = true;
+  r->run.j_enq = 0;
+  r->run.completed = -1;
+}
+
+void sd_server::leave_group(Request* r, bool end_cycle, bool full) {
+  Group* g = r->grp;
+  Member& m = g->mem[(size_t)r->slot];
+  if (m.active)
+    SD_HIP(hipMemsetAsync(g->table + (size_t)r->slot * g->stride + g->nb_off, 0,
+                          4 * g->ops.size(), g->stream));
+  // the request's stream continues after every replay that included it
+  SD_HIP(hipEventRecord(r->ev_out, g->stream));
+  SD_HIP(hipStreamWaitEvent(r->solver->stream, r->ev_out, 0));
+  m = Member{};
+  r->grp = nullptr;
+  r->slot = -1;
+  if (end_cycle) r->solver->prec->end_cycle(*r->solver, r->run, full, r->solver->stream);
+  r->run.batched = false;
+}
+
+// One scheduling round of a group: capture if needed, enqueue a replay while
+// fewer than kGroupAhead + 1 are in flight, retire completed replays, and let
+// members whose cycle has ended leave.  Returns whether anything happened.
+bool sd_server::step_group(Group& g) {
+  bool progress = false;
+  // completed replays
+  while (g.done < g.enq) {
+    const hipError_t q = hipEventQuery(g.ev[(size_t)(g.done % g.ev.size())]);
+    if (q == hipErrorNotReady) break;
+    SD_HIP(q);
+    ++g.done;
+    progress = true;
+  }
+  // members whose cycle ended: a completed column's flag, or every column
+  // of the cycle enqueued
+  for (Member& m : g.mem) {
+    if (!m.r) continue;
+    Request* r = m.r;
+    sd::SolveRun& R = r->run;
+    const int64_t c = std::min<int64_t>((int64_t)(g.done - std::min(g.done, m.join_step)),
+                                        R.j_enq);
+    bool done = false;
+    for (int q = 0; q < c && !done; ++q) done = r->solver->hf->cycle_done[q] != 0;
+    if (done || R.j_enq >= R.m_cycle) {
+      leave_group(r, true, !done);
+      progress = true;
+    }
+  }
+  bool any = false;
+  for (const Member& m : g.mem) any = any || (m.r && m.active);
+  if (!any || g.enq - g.done > (uint64_t)kGroupAhead) return progress;
+  if (g.dirty) capture(g);
+  SD_HIP(hipGraphLaunch(g.graph, g.stream));
+  SD_HIP(hipEventRecord(g.ev[(size_t)(g.enq % g.ev.size())], g.stream));
+  ++g.enq;
+  int n_in = 0;
+  for (const Member& m : g.mem) n_in += m.r && m.active;
+  n_replays.fetch_add(1);
+  n_member_columns.fetch_add(n_in);
+  if (n_in > max_members.load()) max_members.store(n_in);
+  for (Member& m : g.mem) {
+    if (!m.r || !m.active) continue;
+    if (++m.r->run.j_enq >= m.r->run.m_cycle) {
+      // every column of its cycle is enqueued: no further replay includes it
+      SD_HIP(hipMemsetAsync(g.table + (size_t)m.r->slot * g.stride + g.nb_off, 0,
+                            4 * g.ops.size(), g.stream));
+      m.active = false;
+    }
+  }
+  return true;
+}
+
+void sd_server::destroy_groups() {
+  for (auto& kv : groups) {
+    Group& g = *kv.second;
+    if (g.stream) (void)hipStreamSynchronize(g.stream);
+    if (g.graph) (void)hipGraphExecDestroy(g.graph);
+    for (auto e : g.ev) (void)hipEventDestroy(e);
+    if (g.table) (void)hipFreeAsync(g.table, g.stream);
+    if (g.stream) {
+      (void)hipStreamSynchronize(g.stream);
+      (void)hipStreamDestroy(g.stream);
+    }
+  }
+  groups.clear();
+}
 
 void sd_server::retire(Request* r, int status, const std::string& err) {
   // called by the scheduler thread without the lock held
@@ -125,6 +393,13 @@ void sd_server::retire(Request* r, int status, const std::string& err) {
   r->solver.reset();
   r->d_x = nullptr;
   r->hp.reset();
+  for (hipEvent_t* e : {&r->ev_in, &r->ev_out})
+    if (*e) {
+      (void)hipEventDestroy(*e);
+      *e = nullptr;
+    }
+  r->rec.clear();
+  r->region.clear();
   std::lock_guard<std::mutex> lk(mu);
   r->status = status;
   r->err = err;
@@ -158,6 +433,7 @@ void sd_server::prep_loop(hipStream_t prep_stream) {
       r->solver->setup_host(r->hp.get(), &r->opts);
       r->solver->upload(alloc.alloc ? &alloc : nullptr, prep_stream);
       r->d_x = r->solver->mem->array<double>((size_t)r->N);
+      r->solver->enable_column_replay();
     } catch (const sd::Error& e) {
       code = e.code;
       msg = e.what();
@@ -248,11 +524,17 @@ void sd_server::sched_loop() {
       bool finished = false;
       try {
         if (r->cancel) {
+          if (r->grp) leave_group(r, false, false);
           code = SD_E_INVALID;
           msg = "cancelled";
           finished = true;
         } else {
           progressed |= r->solver->prec->step(*r->solver, r->run, false);
+          // a cycle about to start joins the shared launches of its group
+          if (r->run.phase == sd::SolveRun::ITER && !r->run.batched && !r->grp) {
+            join_group(r);
+            progressed = true;
+          }
           if (r->run.phase == sd::SolveRun::DONE) {
             finished = true;
             code = r->run.status;
@@ -272,6 +554,23 @@ void sd_server::sched_loop() {
         progressed = true;
       } else {
         ++i;
+      }
+    }
+    for (auto& kv : groups) {
+      try {
+        progressed |= step_group(*kv.second);
+      } catch (const sd::Error& e) {
+        // a failed replay fails every member of the group
+        Group& g = *kv.second;
+        for (Member& m : g.mem) {
+          if (!m.r) continue;
+          Request* r = m.r;
+          m = Member{};
+          r->grp = nullptr;
+          r->slot = -1;
+          r->cancel = true;
+        }
+        (void)e;
       }
     }
     if (!progressed && !active.empty()) std::this_thread::sleep_for(std::chrono::microseconds(20));
@@ -314,6 +613,15 @@ int sd_server_create(const sd_server_opts* opts, const sd_allocator* allocator,
   for (hipStream_t ps : s->prep_streams) s->prep.emplace_back([raw, ps] { raw->prep_loop(ps); });
   s->sched = std::thread([raw] { raw->sched_loop(); });
   *out = s.release();
+  return SD_OK;
+}
+
+int sd_server_batch_stats(sd_server* sv, sd_batch_stats* out) {
+  if (!sv || !out) return SD_E_INVALID;
+  out->groups = sv->n_groups.load();
+  out->replays = sv->n_replays.load();
+  out->member_columns = sv->n_member_columns.load();
+  out->max_members = sv->max_members.load();
   return SD_OK;
 }
 
@@ -440,6 +748,8 @@ void sd_server_destroy(sd_server* sv) {
     if (t.joinable()) t.join();
   if (sv->sched.joinable()) sv->sched.join();
   (void)hipSetDevice(sv->opts.device);
+  // no replay may still read a request's memory when it is freed
+  sv->destroy_groups();
   for (Request* r : sv->active) {
     if (r->solver) (void)hipStreamSynchronize(r->solver->stream);
     r->solver.reset();
@@ -449,6 +759,9 @@ void sd_server_destroy(sd_server* sv) {
     r->solver.reset();
     r->d_x = nullptr;
   }
+  for (auto& kv : sv->reqs)
+    for (hipEvent_t e : {kv.second->ev_in, kv.second->ev_out})
+      if (e) (void)hipEventDestroy(e);
   for (hipStream_t ps : sv->prep_streams) (void)hipStreamDestroy(ps);
   delete sv;
 }

@@ -390,6 +390,15 @@ double Solver::uzawa_relaxation(hipStream_t s) {
   return 1.0 / lam;
 }
 
+void Solver::enable_column_replay() {
+  if (!on_device) throw Error(SD_E_INVALID, "solver was set up without a device");
+  if (rin) return;
+  const size_t tz = opts.o.precision == SD_PRECISION_FP64 ? sizeof(double) : sizeof(float);
+  rin = mem->array<double>((size_t)ldv);
+  sigfix = mem->array<double>(1);
+  zfix = mem->get((size_t)ldv * tz + 16);
+}
+
 int pd_next_length(const sd_solver_opts& o, SolveRun& R, int m_cap) {
   const std::vector<double>& r = R.pd_res;
   const size_t k = r.size();
@@ -793,6 +802,7 @@ class PrecImpl : public PrecBase {
         return true;
       }
       case SolveRun::ITER: {
+        if (R.batched) return false;   // the request loop drives the columns
         while (R.completed + 1 < R.j_enq && ready(S.events[(size_t)(R.completed + 1)], false))
           ++R.completed;
         bool done = false;
@@ -883,6 +893,32 @@ class PrecImpl : public PrecBase {
   // The preconditioner kernels are gated on the cycle-done flag: a column
   // enqueued ahead of a cycle's end stores nothing (the ILU(0) substitution
   // returns at once).
+  struct RecorderGuard {
+    explicit RecorderGuard(std::vector<RecordedOp>* r) { set_launch_recorder(r); }
+    ~RecorderGuard() { set_launch_recorder(nullptr); }
+  };
+
+  void record_column(Solver& S, std::vector<RecordedOp>& ops) override {
+    if (!S.rin) throw Error(SD_E_INVALID, "column replay not enabled on this solver");
+    if (S.prof_class != 0) throw Error(SD_E_INVALID, "column replay in measurement mode");
+    T* zf = static_cast<T*>(S.zfix);
+    ops.clear();
+    RecorderGuard g(&ops);
+    launch_copy_in(S.V, S.ldv, S.st, S.rin, S.sigfix, S.N, nullptr);
+    apply(S, S.rin, S.sigfix, zf, S.st, nullptr);
+    launch_copy_out<T>(zf, Z, ldz, S.st, S.N, nullptr);
+    arnoldi(S, zf, -1, nullptr, 0, nullptr);
+  }
+
+  void end_cycle(Solver& S, SolveRun& R, bool full, hipStream_t s) override {
+    if (full) launch_arnoldi_close(S.N, S.V, S.ldv, R.m_cycle, S.st, S.part, S.hf_dev, s);
+    launch_trisolve(S.st, s);
+    launch_update_x<T>(R.x, Z, ldz, S.N, S.st, s);
+    ++R.restarts;
+    R.batched = false;
+    R.phase = SolveRun::RESTART;
+  }
+
   void enqueue_iteration(Solver& S, int j, hipStream_t s) {
     T* zj = Z + (size_t)j * ldz;
     apply(S, S.V + (size_t)j * S.ldv, &S.st->sigma[j], zj, S.st, s);

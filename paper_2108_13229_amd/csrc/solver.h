@@ -104,6 +104,9 @@ struct SolveRun {
   // cycle length (0 before the first) and the current m_init
   std::vector<double> pd_res;
   int pd_m = 0, pd_m_init = 0;
+  // the request loop runs this solve's columns in its shared graph (ITER is
+  // then driven by the loop, see PrecBase::end_cycle)
+  bool batched = false;
 };
 
 // Restart length of the next PD-GMRES cycle (the controller documented at
@@ -149,6 +152,16 @@ class PrecBase {
   // returns whether it made progress (it never blocks unless block is set)
   virtual void start(Solver& S, SolveRun& run) = 0;
   virtual bool step(Solver& S, SolveRun& run, bool block) = 0;
+  // One Arnoldi column of this solve in the form the request loop replays
+  // for every column: copy-in of u_j and sigma_j (j read on the device),
+  // the preconditioner on the fixed buffers, copy-out into Z[j], the
+  // Arnoldi step with j from the device; recorded (RecordedOp) instead of
+  // launched.  Needs enable_column_replay().
+  virtual void record_column(Solver& S, std::vector<RecordedOp>& ops) = 0;
+  // End of a cycle whose columns the request loop ran: complete the last
+  // column if the cycle ran to its full length, solve for y, x += Z y; the
+  // run continues at RESTART.  Enqueued on s.
+  virtual void end_cycle(Solver& S, SolveRun& run, bool full, hipStream_t s) = 0;
   virtual void apply_precond(Solver& S, const double* r, double* z, hipStream_t s) = 0;
   virtual void apply_vcycle(Solver& S, int block, const double* b, double* x,
                             hipStream_t s) = 0;
@@ -192,12 +205,17 @@ class Solver {
   double prof_seconds = 0.0, prof_bytes = 0.0;
   std::vector<hipEvent_t> prof_ev;   // 2 per Arnoldi column
   int64_t nnz_A = 0, nnz_V0 = 0;
+  // fixed buffers of the request loop's replayed columns (enable_column_replay)
+  double* rin = nullptr;            // u_j
+  double* sigfix = nullptr;         // sigma_j
+  void* zfix = nullptr;             // preconditioned vector (preconditioner precision)
 
   ~Solver();
   void setup_host(HostProblem* p, const sd_solver_opts* o);
   void upload(const sd_allocator* alloc, hipStream_t s);
   size_t device_bytes() const { return mem ? mem->bytes() : 0; }
   int solve(const double* b, double* x, int use_x0, sd_stats* stats, hipStream_t s);
+  void enable_column_replay();
   double uzawa_relaxation(hipStream_t s);
 };
 

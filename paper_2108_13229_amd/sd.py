@@ -158,6 +158,11 @@ class ServerOpts(C.Structure):
     _fields_ = [("hbm_budget", C.c_size_t), ("max_slots", C.c_int), ("device", C.c_int)]
 
 
+class BatchStats(C.Structure):
+    _fields_ = [("groups", C.c_int64), ("replays", C.c_int64), ("member_columns", C.c_int64),
+                ("max_members", C.c_int)]
+
+
 class Request(C.Structure):
     _fields_ = [("grid", Grid), ("phys", Physics), ("bcs", Bcs), ("K", _dp),
                 ("forcing", Forcing), ("opts", SolverOpts)]
@@ -216,6 +221,7 @@ SIGNATURES = {
     "sd_server_create": (C.c_int, [C.POINTER(ServerOpts), C.POINTER(Allocator),
                                    C.POINTER(_P)]),
     "sd_submit": (C.c_int, [_P, C.POINTER(Request), C.POINTER(C.c_uint64)]),
+    "sd_server_batch_stats": (C.c_int, [_P, C.POINTER(BatchStats)]),
     "sd_poll": (C.c_int, [_P, C.c_uint64, C.POINTER(Result)]),
     "sd_wait": (C.c_int, [_P, C.c_uint64, C.c_double, C.POINTER(Result)]),
     "sd_result_release": (C.c_int, [_P, C.c_uint64]),
@@ -621,6 +627,12 @@ class Server:
         d = self._result(r, with_x)
         d["timed_out"] = rc == SD_E_BUSY
         return d
+
+    def batch_stats(self):
+        """Shared-launch counters: groups, replays, member_columns, max_members."""
+        st = BatchStats()
+        _check(lib().sd_server_batch_stats(self.h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in st._fields_}
 
     def release(self, ticket: int):
         _check(lib().sd_result_release(self.h, ticket))

@@ -172,3 +172,48 @@ def test_device_memory_comes_from_torch_allocator():
     assert s2["allocs"] > s1["allocs"] + 1
     sv.close()
     assert sd.ALLOC_STATS["bytes_live"] == s0["bytes_live"]
+
+
+def test_shared_launches_serve_every_member_bit_identically():
+    """Requests with the same kernel sequence (one grid and permeability
+    field, different inflow) form one group: each graph replay runs an
+    Arnoldi column for several of them in one batched launch per kernel, and
+    each result equals its direct sd_solve bit for bit."""
+    probs = [channel_problem(128, 64, seed=50, U=u) for u in (1e-3, 3e-3, 1e-2, 3e-2, 0.1, 0.3)]
+    S = sd.Server(max_slots=6)
+    res = _run(S, probs, tol=1e-8, restart=40)
+    st = S.batch_stats()
+    S.close()
+    print("batch stats", st, flush=True)
+    assert st["groups"] >= 1 and st["replays"] > 0
+    assert st["max_members"] >= 2
+    assert st["member_columns"] > st["replays"]
+    for p, r in zip(probs, res):
+        assert r["status"] == sd.SD_OK
+        P = sd.Problem(p)
+        Sv = sd.Solver(P, tol=1e-8, restart=40)
+        x, s1, rc = Sv.solve()
+        torch.cuda.synchronize()
+        assert np.array_equal(x.cpu().numpy(), r["x"]) and s1["iters"] == r["stats"]["iters"]
+        Sv.close()
+        P.close()
+
+
+@pytest.mark.parametrize("krylov", ["fgmres", "pdgmres"])
+def test_shared_launches_across_restarts(krylov):
+    """Short cycles (restart 8, and PD-GMRES's controlled lengths): members
+    leave the group at every cycle end, restart on their own stream and
+    join again; results still equal the direct solves bit for bit."""
+    probs = [channel_problem(64, 32, seed=60, U=u) for u in (1e-3, 1e-2, 0.1)]
+    S = sd.Server(max_slots=4)
+    res = _run(S, probs, tol=1e-8, restart=8, krylov=krylov)
+    S.close()
+    for p, r in zip(probs, res):
+        assert r["status"] == sd.SD_OK and r["stats"]["restarts"] >= 2
+        P = sd.Problem(p)
+        Sv = sd.Solver(P, tol=1e-8, restart=8, krylov=krylov)
+        x, s1, rc = Sv.solve()
+        torch.cuda.synchronize()
+        assert np.array_equal(x.cpu().numpy(), r["x"]) and s1["iters"] == r["stats"]["iters"]
+        Sv.close()
+        P.close()
