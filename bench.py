@@ -278,8 +278,9 @@ def replay(sd, probs, arrivals, slots, **opts):
         iters.append(r["stats"]["iters"])
         t_end = max(t_end, r["t_done"])
         S.release(t)
+    stats = S.batch_stats()
     S.close()
-    return np.array(lat), time.perf_counter() - t0, iters
+    return np.array(lat), time.perf_counter() - t0, iters, stats
 
 
 def serving(sd, args):
@@ -295,11 +296,11 @@ def serving(sd, args):
     # serving pays one AMG setup per solve: a smaller dense coarse level (1024
     # rows) halves the host setup of the largest grids for ~2 % more solve time
     opts = dict(tol=1e-8, restart=args.restart, precision="mixed", coarse_max=1024)
-    lat_sat, span_sat, _ = replay(sd, probs, [0.0] * n, args.slots, **opts)
+    lat_sat, span_sat, _, bst_sat = replay(sd, probs, [0.0] * n, args.slots, **opts)
     rate = 0.9 * n / span_sat
     trace = serving_trace(n, rate_per_s=rate, seed=7)
     arr = [t["t_arrival"] for t in trace]
-    lat, span, iters = replay(sd, probs, arr, args.slots, **opts)
+    lat, span, iters, bst = replay(sd, probs, arr, args.slots, **opts)
     # FP64 one request at a time (assembly, setup, solve), same arrivals
     t0 = time.perf_counter()
     lat1 = []
@@ -323,6 +324,12 @@ def serving(sd, args):
         "p50_ms": 1e3 * float(np.percentile(lat, 50)),
         "p99_ms": 1e3 * float(np.percentile(lat, 99)),
         "median_iters": float(np.median(iters)),
+        # shared launches: graph replays, each an Arnoldi column for every
+        # active member of a group of same-shape requests
+        "shared_launches": {"saturated": dict(bst_sat, columns_per_replay=bst_sat[
+                                "member_columns"] / max(1, bst_sat["replays"])),
+                            "at_rate": dict(bst, columns_per_replay=bst["member_columns"] /
+                                            max(1, bst["replays"]))},
         "fp64_one_at_a_time": {"solves_per_s": n / span1,
                                "p50_ms": 1e3 * float(np.percentile(lat1, 50)),
                                "p99_ms": 1e3 * float(np.percentile(lat1, 99))},
