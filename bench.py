@@ -171,6 +171,25 @@ def roofline_from(r, precision, config):
             "alg_bytes_per_launch": r["bytes"] / r["launches"]}
 
 
+def precond_roofline(S, n_solves):
+    """One whole preconditioner application (V-cycles and block sweep, every
+    kernel of it): HIP events around each application during n_solves solves
+    (launched one by one), against its algorithmic bytes (summed over its
+    kernels; each matrix value and index, padding excluded, and each vector
+    entry read or written once)."""
+    S.profile("precond")
+    for _ in range(n_solves):
+        S.solve()
+    r = S.profile_read()
+    S.profile("off")
+    b, launches = S.precond_cost()
+    t = r["seconds"] / max(1, r["launches"])
+    return {"alg_bytes_per_application": b, "launches_per_application": launches,
+            "applications": r["launches"], "avg_application_us": 1e6 * t,
+            "achieved": b / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": b / t / 1e9 / HBM_PEAK_GBS}
+
+
 def counter_run(sd, p, restart, precision, config, out_path):
     """Kernels launched one by one (no graph replay) so that per-dispatch
     counters attach to each kernel; then a plain 512 MiB device-to-device copy
@@ -197,6 +216,22 @@ def counter_run(sd, p, restart, precision, config, out_path):
         with open(out_path, "w") as f:
             json.dump(rec, f, indent=1)
     print(json.dumps(rec))
+
+
+def _counter_grid_rows(d, counter):
+    """(kernel name, grid size, value) per dispatch from a rocprofv3 --pmc CSV
+    tree, in dispatch order."""
+    import csv
+    import glob
+    rows = []
+    for fn in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
+        with open(fn) as f:
+            for rec in csv.DictReader(f):
+                if rec.get("Counter_Name") == counter:
+                    rows.append((int(rec.get("Dispatch_Id") or 0), rec["Kernel_Name"],
+                                 int(rec.get("Grid_Size") or rec.get("Grid_Size_X") or 0),
+                                 float(rec["Counter_Value"])))
+    return [(n, g, v) for _, n, g, v in sorted(rows, key=lambda t: t[0])]
 
 
 def _counter_rows(d, counter):
@@ -247,6 +282,25 @@ def summarize_counters(fetch_dir, write_dir, run_json, out_json):
     out["hbm_bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]
     out["alg_bytes_per_launch"] = run["alg_bytes_per_launch"]
     out["traffic_over_algorithmic"] = out["hbm_bytes_per_launch"] / run["alg_bytes_per_launch"]
+    # every kernel of the run by launch shape: mean HBM bytes per dispatch
+    # (both counters scaled as above), launches that did work only
+    per = {}
+    for counter, d, key in (("FETCH_SIZE", fetch_dir, "fetch"), ("WRITE_SIZE", write_dir,
+                                                                  "write")):
+        scale = out[f"{key}_scale"]
+        for name, grid, v in _counter_grid_rows(d, counter):
+            short = name.replace("sd::(anonymous namespace)::", "").replace("void ", "")
+            short = short.split("(")[0]
+            per.setdefault((short, grid), {"fetch": [], "write": []})[key].append(
+                v * 1024.0 * scale)
+    out["all_kernels"] = []
+    for (name, grid), d in sorted(per.items(), key=lambda kv: -sum(kv[1]["fetch"])):
+        f = np.array(d["fetch"])
+        w = np.array(d["write"]) if d["write"] else np.zeros(1)
+        keep = f >= 0.01 * np.median(f) if f.size else f
+        out["all_kernels"].append({"kernel": name, "grid": grid, "dispatches": int(f.size),
+                                   "hbm_bytes_per_dispatch": float(f[keep].mean() + w.mean())
+                                   if f.size else 0.0})
     out["kernels_hip_sha256"] = run["kernels_hip_sha256"]
     if out["kernels_hip_sha256"] != kernels_sha():
         print("warning: kernels.hip changed since the counter run", file=sys.stderr)
@@ -922,6 +976,7 @@ def headline_solves(sd, P, precs, args, roof_prec, config):
                          rel_res=st["rel_res"], setup_s=t_setup)
         if prec == roof_prec and args.roofline_solves > 0:
             roof = roofline(S, args.roofline_solves, prec, config)
+            res[prec]["preconditioner"] = precond_roofline(S, args.roofline_solves)
         S.close()
     return res, xs, roof
 

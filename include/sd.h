@@ -379,11 +379,18 @@ int sd_arnoldi_layout(int64_t n, int* rows_per_block, int* blocks, size_t* lds_b
  * one instead of replaying graphs).  kernel_class: 0 = off,
  * SD_PROF_ARNOLDI_SPMV (w = A z_j fused with the projection pass over the
  * basis), SD_PROF_ARNOLDI_UPDATE (the Gram-Schmidt update pass),
- * SD_PROF_JACOBI_V0 (damped-Jacobi sweep on the finest velocity level).
+ * SD_PROF_JACOBI_V0 (damped-Jacobi sweep on the finest velocity level),
+ * SD_PROF_PRECOND (one whole preconditioner application).
  * Resets the counters. */
 enum { SD_PROF_OFF = 0, SD_PROF_ARNOLDI_SPMV = 1, SD_PROF_ARNOLDI_UPDATE = 2,
-       SD_PROF_JACOBI_V0 = 3 };
+       SD_PROF_JACOBI_V0 = 3, SD_PROF_PRECOND = 4 };
 int sd_solver_profile(sd_solver* s, int kernel_class);
+/* One application of the block preconditioner (Sec. 4: the V-cycles of the
+ * Sec. 5 setup and the block sweep; SD_PROF_PRECOND brackets it): its
+ * algorithmic bytes (each matrix value and index, padding excluded, and each
+ * vector entry read or written once, summed over its kernels) and its kernel
+ * launches.  Host computation; no device work. */
+int sd_solver_precond_cost(sd_solver* s, double* bytes, int* launches);
 /* The scale X of the middle block's mu M_p^-1, identity or Uzawa term
  * (X = mu/(dx dy dz), 1, or omega). */
 int sd_solver_middle_scale(const sd_solver* s, double* x);

@@ -374,12 +374,21 @@ int sd_arnoldi_layout(int64_t n, int* rows_per_block, int* blocks, size_t* lds_b
 }
 
 int sd_solver_profile(sd_solver* s, int kernel_class) {
-  if (!s || kernel_class < 0 || kernel_class > 3) return fail(SD_E_INVALID, "bad argument");
+  if (!s || kernel_class < 0 || kernel_class > 4) return fail(SD_E_INVALID, "bad argument");
   s->s->prof_class = kernel_class;
   s->s->prof_launches = 0;
   s->s->prof_seconds = 0.0;
   s->s->prof_bytes = 0.0;
   return SD_OK;
+}
+
+int sd_solver_precond_cost(sd_solver* s, double* bytes, int* launches) {
+  return guarded([&] {
+    if (!s) return fail(SD_E_INVALID, "solver is NULL");
+    if (!s->s->on_device) return fail(SD_E_INVALID, "solver has no device data");
+    s->s->prec->precond_cost(*s->s, bytes, launches);
+    return (int)SD_OK;
+  });
 }
 
 int sd_solver_middle_scale(const sd_solver* s, double* x) {

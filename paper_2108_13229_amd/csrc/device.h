@@ -38,6 +38,7 @@ struct Sell {
   int lpr = 1;
   int width = 0;   // > 0: every row padded to this width (SELL: slice s at
                    // 64 * width * s; CSR: row r at width * r), sptr not read
+  int64_t nnz = 0; // stored entries without padding (algorithmic bytes only)
 };
 
 // ILU(0) factors in level order (see HostIlu): positions q of the forward
@@ -100,10 +101,15 @@ struct RecordedOp {
   std::vector<char> args;
   int nblocks = 0, threads = 0;
   size_t lds = 0;
+  double bytes = 0.0;   // algorithmic bytes: each matrix entry (value and
+                        // index, padding excluded) and each vector entry
+                        // read or written once
 };
 // While rec is set (non-null), the launchers below called on this thread
 // append to it instead of launching.
 void set_launch_recorder(std::vector<RecordedOp>* rec);
+// Whether launches on this thread are being recorded.
+bool launch_recording();
 
 template <typename TM, typename TX, typename TY>
 void launch_spmv(const Sell<TM>& A, const TX* x, TY* y, const DevState* gate,

@@ -1552,10 +1552,11 @@ inline int blocks_lpr(int n, int lpr) {
 thread_local std::vector<RecordedOp>* g_recorder = nullptr;
 
 void set_launch_recorder(std::vector<RecordedOp>* rec) { g_recorder = rec; }
+bool launch_recording() { return g_recorder != nullptr; }
 
 template <typename Op, typename K, typename B>
 void launch_op(K kernel, B batched, const typename Op::Args& a, int nb, size_t lds,
-               hipStream_t s) {
+               hipStream_t s, double bytes = 0.0) {
   if (nb <= 0) return;
   if (g_recorder) {
     RecordedOp r;
@@ -1564,10 +1565,17 @@ void launch_op(K kernel, B batched, const typename Op::Args& a, int nb, size_t l
     r.nblocks = nb;
     r.threads = Op::kThreads;
     r.lds = lds;
+    r.bytes = bytes;
     g_recorder->push_back(std::move(r));
     return;
   }
   kernel<<<nb, Op::kThreads, lds, s>>>(a);
+}
+
+// Algorithmic bytes of a sparse matrix pass: each stored value and index once.
+template <typename T>
+double mat_bytes(const Sell<T>& A) {
+  return (double)A.nnz * (double)(sizeof(T) + sizeof(int));
 }
 
 // Calls f with the lanes-per-row count as a compile-time constant.
@@ -1590,7 +1598,8 @@ void launch_spmv(const Sell<TM>& A, const TX* x, TY* y, const DevState* gate, hi
     constexpr int l = decltype(L)::value;
     using Op = SpmvOp<l, TM, TX, TY>;
     launch_op<Op>(k_spmv<l, TM, TX, TY>, k_batch<Op>, typename Op::Args{A, x, y, gate},
-                  blocks_lpr(A.n_rows, l), 0, s);
+                  blocks_lpr(A.n_rows, l), 0, s,
+                  mat_bytes(A) + (double)A.n_cols * sizeof(TX) + (double)A.n_rows * sizeof(TY));
   });
 }
 
@@ -1602,7 +1611,8 @@ void launch_residual(const Sell<T>& A, const TB* b, const double* bscale, const 
     constexpr int l = decltype(L)::value;
     using Op = ResidualOp<l, T, TB>;
     launch_op<Op>(k_residual<l, T, TB>, k_batch<Op>, typename Op::Args{A, b, bscale, x, r, gate},
-                  blocks_lpr(A.n_rows, l), 0, s);
+                  blocks_lpr(A.n_rows, l), 0, s,
+                  mat_bytes(A) + (double)A.n_rows * (sizeof(TB) + 2 * sizeof(T)));
   });
 }
 
@@ -1615,7 +1625,7 @@ void launch_jacobi_zero(const Sell<T>& A, const T* wd, const TB* b, const double
     using Op = JacobiZeroOp<l, T, TB>;
     launch_op<Op>(k_jacobi_zero<l, T, TB>, k_batch<Op>,
                   typename Op::Args{A, wd, b, bscale, x, two, gate}, blocks_lpr(A.n_rows, l), 0,
-                  s);
+                  s, (two ? mat_bytes(A) : 0.0) + (double)A.n_rows * (sizeof(TB) + 2 * sizeof(T)));
   });
 }
 
@@ -1628,7 +1638,8 @@ void launch_jacobi(const Sell<T>& A, const T* wd, const TB* b, const double* bsc
     using Op = JacobiOp<l, T, TB>;
     launch_op<Op>(k_jacobi<l, T, TB>, k_batch<Op>,
                   typename Op::Args{A, wd, b, bscale, x_in, x_out, gate},
-                  blocks_lpr(A.n_rows, l), 0, s);
+                  blocks_lpr(A.n_rows, l), 0, s,
+                  mat_bytes(A) + (double)A.n_rows * (sizeof(TB) + 3 * sizeof(T)));
   });
 }
 
@@ -1641,7 +1652,9 @@ void launch_restrict_residual(const Sell<T>& Q, const TB* b, const double* bscal
     using Op = RestrictResidualOp<l, T, TB>;
     launch_op<Op>(k_restrict_residual<l, T, TB>, k_batch<Op>,
                   typename Op::Args{Q, b, bscale, x, n_fine, bc, gate}, blocks_lpr(Q.n_rows, l),
-                  0, s);
+                  0, s,
+                  mat_bytes(Q) + (double)n_fine * (sizeof(TB) + sizeof(T)) +
+                      (double)Q.n_rows * sizeof(T));
   });
 }
 
@@ -1657,7 +1670,9 @@ void launch_presmooth_restrict(const Sell<T>& A, const T* wd, const Sell<T>& G, 
     constexpr int l = decltype(L)::value;
     using Op = PresmoothRestrictOp<l, T, TB>;
     launch_op<Op>(k_presmooth_restrict<l, T, TB>, k_batch<Op>,
-                  typename Op::Args{A, wd, G, b, bscale, x, bc, nb_a, gate}, nb, 0, s);
+                  typename Op::Args{A, wd, G, b, bscale, x, bc, nb_a, gate}, nb, 0, s,
+                  mat_bytes(A) + mat_bytes(G) + (double)A.n_rows * (sizeof(TB) + 2 * sizeof(T)) +
+                      (double)G.n_rows * sizeof(T));
   });
 }
 
@@ -1672,7 +1687,9 @@ void launch_prolong_smooth(const Sell<T>& A, const Sell<T>& F, const T* wd, cons
     using Op = ProlongSmoothOp<l, T, TB>;
     launch_op<Op>(k_prolong_smooth<l, T, TB>, k_batch<Op>,
                   typename Op::Args{A, F, wd, b, bscale, x, xc, xout, gate},
-                  blocks_lpr(A.n_rows, l), 0, s);
+                  blocks_lpr(A.n_rows, l), 0, s,
+                  mat_bytes(A) + mat_bytes(F) + (double)A.n_rows * (sizeof(TB) + 3 * sizeof(T)) +
+                      (double)F.n_cols * sizeof(T));
   });
 }
 
@@ -1683,7 +1700,8 @@ void launch_prolong(const Sell<T>& P, const T* xc, T* x, const DevState* gate, h
     constexpr int l = decltype(L)::value;
     using Op = ProlongOp<l, T>;
     launch_op<Op>(k_prolong<l, T>, k_batch<Op>, typename Op::Args{P, xc, x, gate},
-                  blocks_lpr(P.n_rows, l), 0, s);
+                  blocks_lpr(P.n_rows, l), 0, s,
+                  mat_bytes(P) + (double)P.n_cols * sizeof(T) + 2.0 * P.n_rows * sizeof(T));
   });
 }
 
@@ -1691,7 +1709,9 @@ template <typename T>
 void launch_ilu0(const IluDev<T>& F, const T* r, T* z, const DevState* gate, hipStream_t s) {
   if (F.n <= 0) return;
   using Op = Ilu0Op<T>;
-  launch_op<Op>(k_ilu0<T>, k_batch<Op>, typename Op::Args{F, r, z, gate}, 1, 0, s);
+  const double n = (double)F.n;
+  launch_op<Op>(k_ilu0<T>, k_batch<Op>, typename Op::Args{F, r, z, gate}, 1, 0, s,
+                n * (4 + 2 * kIluWidth * (4 + sizeof(T)) + sizeof(T)) + 3 * n * sizeof(T));
 }
 
 template <typename T>
@@ -1699,7 +1719,8 @@ void launch_coarse(const double* Ainv, int n, const T* bc, T* xc, const DevState
                    hipStream_t s) {
   if (n <= 0) return;
   using Op = CoarseOp<T>;
-  launch_op<Op>(k_coarse<T>, k_batch<Op>, typename Op::Args{Ainv, n, bc, xc, gate}, n, 0, s);
+  launch_op<Op>(k_coarse<T>, k_batch<Op>, typename Op::Args{Ainv, n, bc, xc, gate}, n, 0, s,
+                8.0 * n * n + 2.0 * n * sizeof(T));
 }
 
 template <typename T>
@@ -1710,14 +1731,17 @@ void launch_block_sweep(const Sell<T>& Cf, int n_p, const double* r, const doubl
   using Op = BlockSweepOp<T>;
   launch_op<Op>(k_block_sweep<T>, k_batch<Op>,
                 typename Op::Args{Cf, n_p, r, bscale, yv, xscale, zp, tq, tp, gate},
-                blocks_for(Cf.n_rows), 0, s);
+                blocks_for(Cf.n_rows), 0, s,
+                mat_bytes(Cf) + (double)Cf.n_rows * (8 + sizeof(T)) + (double)Cf.n_cols * sizeof(T) +
+                    (tp ? (double)n_p * sizeof(T) : 0.0));
 }
 
 template <typename T>
 void launch_add(const T* a, T* y, int n, const DevState* gate, hipStream_t s) {
   if (n <= 0) return;
   using Op = AddOp<T>;
-  launch_op<Op>(k_add<T>, k_batch<Op>, typename Op::Args{a, y, n, gate}, blocks_for(n), 0, s);
+  launch_op<Op>(k_add<T>, k_batch<Op>, typename Op::Args{a, y, n, gate}, blocks_for(n), 0, s,
+                3.0 * n * sizeof(T));
 }
 
 // Rows per workgroup: the projection kernel takes 1024 (two workgroups per
@@ -1912,19 +1936,21 @@ void launch_scale_convert(const TB* b, const double* bscale, T* out, int n, cons
                           hipStream_t s) {
   using Op = ScaleConvertOp<TB, T>;
   launch_op<Op>(k_scale_convert<TB, T>, k_batch<Op>, typename Op::Args{b, bscale, out, n, gate},
-                blocks_for(n), 0, s);
+                blocks_for(n), 0, s, (double)n * (sizeof(TB) + sizeof(T)));
 }
 
 template <typename TA, typename TB>
 void launch_convert(const TA* a, TB* b, int n, hipStream_t s) {
   using Op = ConvertOp<TA, TB>;
-  launch_op<Op>(k_convert<TA, TB>, k_batch<Op>, typename Op::Args{a, b, n}, blocks_for(n), 0, s);
+  launch_op<Op>(k_convert<TA, TB>, k_batch<Op>, typename Op::Args{a, b, n}, blocks_for(n), 0, s,
+                (double)n * (sizeof(TA) + sizeof(TB)));
 }
 
 template <typename T>
 void launch_fill(T* a, T v, int n, hipStream_t s) {
   using Op = FillOp<T>;
-  launch_op<Op>(k_fill<T>, k_batch<Op>, typename Op::Args{a, v, n}, blocks_for(n), 0, s);
+  launch_op<Op>(k_fill<T>, k_batch<Op>, typename Op::Args{a, v, n}, blocks_for(n), 0, s,
+                (double)n * sizeof(T));
 }
 
 void launch_step_rhs(const double* b, const double* x, double* out, double m, int n, int nux,

@@ -103,12 +103,13 @@ static int lanes_per_row(const HostCSR& A, bool allow_csr, int force_lpr) {
 template <typename T>
 static Sell<T> copy_sell(const std::vector<int>& ptr, const std::vector<int>& col,
                          const std::vector<T>& val, int64_t n, int64_t n_cols, int lpr, int width,
-                         DeviceMem& mem, hipStream_t s) {
+                         int64_t nnz, DeviceMem& mem, hipStream_t s) {
   Sell<T> d;
   d.n_rows = (int)n;
   d.n_cols = (int)n_cols;
   d.lpr = lpr;
   d.width = width;
+  d.nnz = nnz;
   int* dp = mem.array<int>(std::max<size_t>(ptr.size(), 1));
   int* dcol = mem.array<int>(std::max<size_t>(col.size(), 1));
   T* dval = mem.array<T>(std::max<size_t>(val.size(), 1));
@@ -183,7 +184,8 @@ Sell<T> upload_sell(const HostCSR& A, DeviceMem& mem, hipStream_t s, bool allow_
       }
     }
   });
-  return copy_sell<T>(sptr, col, val, n, A.n_cols, lpr, uniform ? (int)wmax : 0, mem, s);
+  return copy_sell<T>(sptr, col, val, n, A.n_cols, lpr, uniform ? (int)wmax : 0, A.nnz(), mem,
+                      s);
 }
 
 template Sell<double> upload_sell<double>(const HostCSR&, DeviceMem&, hipStream_t, bool, int);
@@ -308,6 +310,12 @@ Solver::~Solver() {
   if (ev_state) (void)hipEventDestroy(ev_state);
   pinned_release(hs, sizeof(HostState), false);
   if (stream) (void)hipStreamDestroy(stream);
+  if (stream2) {
+    (void)hipStreamSynchronize(stream2);
+    (void)hipStreamDestroy(stream2);
+  }
+  if (ev_fork) (void)hipEventDestroy(ev_fork);
+  if (ev_back) (void)hipEventDestroy(ev_back);
   pinned_release((void*)hf, sizeof(HostFlags), true);
 }
 
@@ -344,6 +352,11 @@ void Solver::upload(const sd_allocator* alloc, hipStream_t s) {
   nnz_A = pb->A.nnz();
   nnz_V0 = hh[0].levels.empty() ? 0 : hh[0].levels[0].A.nnz();
   SD_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+  if (opts.o.precond == SD_PREC_BJ) {
+    SD_HIP(hipStreamCreateWithFlags(&stream2, hipStreamNonBlocking));
+    SD_HIP(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+    SD_HIP(hipEventCreateWithFlags(&ev_back, hipEventDisableTiming));
+  }
   prec = opts.o.precision == SD_PRECISION_FP64 ? make_prec_fp64(*this, s) : make_prec_fp32(*this, s);
   SD_HIP(hipStreamSynchronize(s));
   if ((opts.o.precond == SD_PREC_TD_BJ || opts.o.precond == SD_PREC_TD_BGS) && off[2] > 0 &&
@@ -643,22 +656,36 @@ class PrecImpl : public PrecBase {
   }
   hipEvent_t* prof_jacobi_ev = nullptr;
 
-  // z = P(bs * r): block preconditioner on a basis vector (FP64 input).
+  // z = P(bs * r): block preconditioner on a basis vector (FP64 input).  In
+  // the block-Jacobi form nothing after the velocity V-cycle reads its
+  // result, so the rest runs on a second stream beside it (two parallel
+  // branches of the column graph); recorded columns stay in one sequence.
   void apply(Solver& S, const double* r, const double* bs, T* z, const DevState* gate,
              hipStream_t s) {
     const int64_t* o = S.off;
     const int n_p = (int)(o[3] - o[2]);
+    const bool fork = S.stream2 && !launch_recording();
+    hipStream_t s2 = s;
+    if (fork) {
+      SD_HIP(hipEventRecord(S.ev_fork, s));
+      SD_HIP(hipStreamWaitEvent(S.stream2, S.ev_fork, 0));
+      s2 = S.stream2;
+    }
     if (!H[0].lev.empty()) vcycle<double>(0, 0, r, bs, z, gate, s);
     launch_block_sweep<T>(Cf, n_p, r + o[2], bs, z, S.xscale, z + o[2], tq, cc ? tp : nullptr,
-                          gate, s);
+                          gate, s2);
     if (cc) {
-      vcycle<T>(2, 0, tp, nullptr, yl, gate, s);
-      launch_add<T>(yl, z + o[2], n_p, gate, s);
+      vcycle<T>(2, 0, tp, nullptr, yl, gate, s2);
+      launch_add<T>(yl, z + o[2], n_p, gate, s2);
     }
     if (ilu.n > 0) {
-      launch_ilu0<T>(ilu, tq, z + o[3], gate, s);
+      launch_ilu0<T>(ilu, tq, z + o[3], gate, s2);
     } else if (!H[1].lev.empty()) {
-      vcycle<T>(1, 0, tq, nullptr, z + o[3], gate, s);
+      vcycle<T>(1, 0, tq, nullptr, z + o[3], gate, s2);
+    }
+    if (fork) {
+      SD_HIP(hipEventRecord(S.ev_back, S.stream2));
+      SD_HIP(hipStreamWaitEvent(s, S.ev_back, 0));
     }
   }
 
@@ -871,6 +898,10 @@ class PrecImpl : public PrecBase {
       T* zj = Z + (size_t)j * ldz;
       if (S.prof_class == 3) {
         apply_profiled_jacobi(S, S.V + (size_t)j * S.ldv, &S.st->sigma[j], zj, s, ev);
+      } else if (S.prof_class == 4) {   // the whole preconditioner application
+        SD_HIP(hipEventRecord(ev[0], s));
+        apply(S, S.V + (size_t)j * S.ldv, &S.st->sigma[j], zj, nullptr, s);
+        SD_HIP(hipEventRecord(ev[1], s));
       } else {
         apply(S, S.V + (size_t)j * S.ldv, &S.st->sigma[j], zj, nullptr, s);
       }
@@ -908,6 +939,29 @@ class PrecImpl : public PrecBase {
     apply(S, S.rin, S.sigfix, zf, S.st, nullptr);
     launch_copy_out<T>(zf, Z, ldz, S.st, S.N, nullptr);
     arnoldi(S, zf, -1, nullptr, 0, nullptr);
+  }
+
+  // Algorithmic bytes and launches of one preconditioner application (from a
+  // recording of it; cached).
+  double pc_bytes = -1.0;
+  int pc_launches = 0;
+  double precond_bytes(Solver& S) {
+    if (pc_bytes < 0.0) {
+      std::vector<RecordedOp> ops;
+      {
+        RecorderGuard g(&ops);
+        apply(S, S.V, &S.st->sigma[0], Z, S.st, nullptr);
+      }
+      pc_bytes = 0.0;
+      for (const RecordedOp& o : ops) pc_bytes += o.bytes;
+      pc_launches = (int)ops.size();
+    }
+    return pc_bytes;
+  }
+  void precond_cost(Solver& S, double* bytes, int* launches) override {
+    const double b = precond_bytes(S);
+    if (bytes) *bytes = b;
+    if (launches) *launches = pc_launches;
   }
 
   void end_cycle(Solver& S, SolveRun& R, bool full, hipStream_t s) override {
@@ -960,6 +1014,8 @@ class PrecImpl : public PrecBase {
                         (j + 1) * 8.0 * n;
       else if (S.prof_class == 2)  // j basis vectors, u_j and w read; v_j, u_{j+1} written
         S.prof_bytes += (j + 4) * 8.0 * n;
+      else if (S.prof_class == 4)  // every launch of the application
+        S.prof_bytes += precond_bytes(S);
       else {  // V level 0: A_V (values + indices), x_in, b, w, x_out
         const double nv = (double)S.off[2];
         S.prof_bytes += (double)S.nnz_V0 * (tz + 4.0) + nv * (3.0 * tz + 8.0);

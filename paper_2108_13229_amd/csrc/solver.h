@@ -162,6 +162,10 @@ class PrecBase {
   // column if the cycle ran to its full length, solve for y, x += Z y; the
   // run continues at RESTART.  Enqueued on s.
   virtual void end_cycle(Solver& S, SolveRun& run, bool full, hipStream_t s) = 0;
+  // Algorithmic bytes (each matrix entry and vector entry read or written
+  // once, padding excluded) and kernel launches of one preconditioner
+  // application.
+  virtual void precond_cost(Solver& S, double* bytes, int* launches) = 0;
   virtual void apply_precond(Solver& S, const double* r, double* z, hipStream_t s) = 0;
   virtual void apply_vcycle(Solver& S, int block, const double* b, double* x,
                             hipStream_t s) = 0;
@@ -198,6 +202,11 @@ class Solver {
   hipEvent_t ev_state = nullptr;    // marks a finished state copy to hs
   HostState* hs = nullptr;          // pinned host copy of the solver scalars
   hipStream_t stream = nullptr;     // internal non-blocking stream (default priority)
+  // block-Jacobi forms: the Darcy (and middle) blocks of an application run
+  // on stream2 beside the velocity V-cycle (a parallel branch in a captured
+  // graph); ev_fork / ev_back order it into the application's stream
+  hipStream_t stream2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_back = nullptr;
   std::unique_ptr<PrecBase> prec;
   // measurement mode: events around one kernel class (0 = off)
   int prof_class = 0;

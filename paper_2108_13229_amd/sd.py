@@ -216,6 +216,7 @@ SIGNATURES = {
                                     C.POINTER(C.c_size_t)]),
     "sd_solver_profile": (C.c_int, [_P, C.c_int]),
     "sd_solver_middle_scale": (C.c_int, [_P, C.POINTER(C.c_double)]),
+    "sd_solver_precond_cost": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
     "sd_solver_profile_read": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                          C.POINTER(C.c_double)]),
     "sd_server_create": (C.c_int, [C.POINTER(ServerOpts), C.POINTER(Allocator),
@@ -527,7 +528,13 @@ class Solver:
         _check(lib().sd_solver_middle_scale(self.h, C.byref(x)))
         return x.value
 
-    PROFILE = {"off": 0, "arnoldi_spmv": 1, "arnoldi_update": 2, "jacobi_v0": 3}
+    PROFILE = {"off": 0, "arnoldi_spmv": 1, "arnoldi_update": 2, "jacobi_v0": 3, "precond": 4}
+
+    def precond_cost(self):
+        """(algorithmic bytes, kernel launches) of one preconditioner application."""
+        b, n = C.c_double(), C.c_int()
+        _check(lib().sd_solver_precond_cost(self.h, C.byref(b), C.byref(n)))
+        return b.value, n.value
 
     def profile(self, kernel_class: str):
         _check(lib().sd_solver_profile(self.h, self.PROFILE[kernel_class]))
