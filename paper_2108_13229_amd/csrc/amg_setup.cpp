@@ -545,12 +545,19 @@ HostCSR scaled_product(const HostCSR& X, const std::vector<double>& s, const Hos
   return spgemm(scale_cols(X, s), Y);
 }
 
-HostCSR presmoothed_restriction(const HostCSR& A, const HostCSR& R, double omega) {
+HostCSR sparse_product(const HostCSR& X, const HostCSR& Y) { return spgemm(X, Y); }
+
+HostCSR presmoothed_restriction(const HostCSR& A, const HostCSR& R, const HostCSR& RA,
+                                double omega) {
   const std::vector<double> w = jacobi_weights(A, omega);
   const HostCSR T = scale_cols(A, w);                 // A W
   // R (I - A M2) = R - 2 R A W + (R A W)(A W), the product with R first
-  const HostCSR RAW = scale_cols(spgemm(R, A), w);
+  const HostCSR RAW = scale_cols(RA, w);
   return add_scaled(add_scaled(R, RAW, -2.0), spgemm(RAW, T), 1.0);
+}
+
+HostCSR presmoothed_restriction(const HostCSR& A, const HostCSR& R, double omega) {
+  return presmoothed_restriction(A, R, spgemm(R, A), omega);
 }
 
 HostCSR smoothed_correction(const HostCSR& A, const HostCSR& P, const HostCSR& AP,
@@ -564,7 +571,10 @@ void parallel_ranges(int64_t r0, int64_t r1, const std::function<void(int64_t, i
 }
 
 HostCSR residual_restriction(const HostCSR& A, const HostCSR& R) {
-  const HostCSR RA = spgemm(R, A);
+  return residual_restriction(A, R, spgemm(R, A));
+}
+
+HostCSR residual_restriction(const HostCSR& A, const HostCSR& R, const HostCSR& RA) {
   HostCSR Q;
   Q.n_rows = R.n_rows;
   Q.n_cols = 2 * A.n_cols;

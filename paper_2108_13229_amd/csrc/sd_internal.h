@@ -130,7 +130,12 @@ void parallel_ranges(int64_t r0, int64_t r1, const std::function<void(int64_t, i
 
 // Q = [R | -R A] (n_c x 2n): the restricted residual R (b - A x) = Q [b; x]
 // in one sparse product, so that a V-cycle level needs no residual vector.
+// RA: the product R A when the caller has it (the same values as computed
+// here).
 HostCSR residual_restriction(const HostCSR& A, const HostCSR& R);
+HostCSR residual_restriction(const HostCSR& A, const HostCSR& R, const HostCSR& RA);
+// Z = X Y, each entry summed in ascending inner index.
+HostCSR sparse_product(const HostCSR& X, const HostCSR& Y);
 
 // (X diag(s)) Y: every entry of X scaled by s of its column, then the
 // product, each result entry summed in ascending inner index.
@@ -143,6 +148,8 @@ HostCSR scaled_product(const HostCSR& X, const std::vector<double>& s, const Hos
 //                      post-smoothing sweep: x + P xc followed by one sweep is
 //                      x + W (b - A x) + F xc.
 HostCSR presmoothed_restriction(const HostCSR& A, const HostCSR& R, double omega);
+HostCSR presmoothed_restriction(const HostCSR& A, const HostCSR& R, const HostCSR& RA,
+                                double omega);
 HostCSR smoothed_correction(const HostCSR& A, const HostCSR& P, const HostCSR& AP,
                             double omega);
 

@@ -482,15 +482,15 @@ void upload_hierarchy(const HostHierarchy& h, DevHierarchy<T>& d, double omega, 
         for (size_t k = 0; k < AW.val.size(); ++k) AW.val[k] = H.A.val[k] * w[AW.col[k]];
         D.AW = upload_sell<T>(AW, mem, s, true, D.A.lpr);
       }
-      D.P = upload_sell<T>(H.P, mem, s, true);
       const int64_t nnzA = H.A.nnz();
-      HostCSR G, Q, F;
-      if (l > 0) Q = residual_restriction(H.A, H.R);
+      HostCSR G, F, RA;
       D.fuse_pre = nu_pre == 2 && (l > 0 || H.A.n_rows < kFusePreRows) &&
                    nnzA <= kFuseMaxRowWidth * H.A.n_rows;
+      // R A serves both G and Q = [R | -R A] (nnz(Q) = nnz(R) + nnz(R A))
+      if (l > 0 || D.fuse_pre) RA = sparse_product(H.R, H.A);
       if (D.fuse_pre) {
-        G = presmoothed_restriction(H.A, H.R, omega);
-        const int64_t replaced = l > 0 ? Q.nnz() : H.R.nnz() + nnzA;
+        G = presmoothed_restriction(H.A, H.R, RA, omega);
+        const int64_t replaced = l > 0 ? H.R.nnz() + RA.nnz() : H.R.nnz() + nnzA;
         D.fuse_pre = (double)G.nnz() <= kFuseMaxGOverQ * (double)replaced;
       }
       D.fuse_post = nu_post >= 1 && (l > 0 || H.A.n_rows < kFusePostRows);
@@ -504,12 +504,10 @@ void upload_hierarchy(const HostHierarchy& h, DevHierarchy<T>& d, double omega, 
         D.R = upload_sell<T>(H.R, mem, s, true);
         D.r = mem.array<T>((size_t)D.n);
       } else {
-        D.Q = upload_sell<T>(Q, mem, s, true);
+        D.Q = upload_sell<T>(residual_restriction(H.A, H.R, RA), mem, s, true);
       }
-      if (D.fuse_post) {
-        D.F = upload_sell<T>(F, mem, s, true, D.A.lpr);
-        D.P = Sell<T>{};
-      }
+      if (D.fuse_post) D.F = upload_sell<T>(F, mem, s, true, D.A.lpr);
+      else D.P = upload_sell<T>(H.P, mem, s, true);
     }
     SD_HIP(hipStreamSynchronize(s));
   }
