@@ -118,10 +118,10 @@ void launch_spmv(const Sell<TM>& A, const TX* x, TY* y, const DevState* gate,
 template <typename T, typename TB>
 void launch_residual(const Sell<T>& A, const TB* b, const double* bscale, const T* x,
                      T* r, const DevState* gate, hipStream_t s);
-// x = w .* (bscale b) (one sweep from zero), or two sweeps from zero fused;
-// AW = A diag(w) (read only for two sweeps)
+// x = w .* (bscale b) (one sweep from zero), or two sweeps from zero fused
+// (A read only for two sweeps)
 template <typename T, typename TB>
-void launch_jacobi_zero(const Sell<T>& AW, const T* wd, const TB* b, const double* bscale,
+void launch_jacobi_zero(const Sell<T>& A, const T* wd, const TB* b, const double* bscale,
                         T* x, int two_sweeps, const DevState* gate, hipStream_t s);
 // x_out = x_in + w .* (bscale b - A x_in)
 template <typename T, typename TB>

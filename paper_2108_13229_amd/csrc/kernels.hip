@@ -367,7 +367,9 @@ struct ProlongSmoothOp {
 };
 
 // x = w .* b (one sweep from zero) or two sweeps from zero fused: the first
-// sweep's values x1 = w .* b are recomputed at the neighbours.
+// sweep's values x1 = w .* b are recomputed at the neighbours (a gather of b
+// and of w each), so the pass reads A, the matrix the residual and the
+// post-sweeps read next.
 template <int LPR, typename T, typename TB>
 struct JacobiZeroOp {
   struct Args {
@@ -393,9 +395,8 @@ struct JacobiZeroOp {
       if (rs.y == 0 && !stop) a.x[row] = x1;
       return;
     }
-    // A holds A diag(w) here, so the first sweep's values w_c b_c at the
-    // neighbours cost one gather each
-    const T acc = row_sum<LPR>(a.A, row, rs.y, [&](int c) { return load_b<T>(b, s, c); });
+    const T* __restrict__ wd = a.wd;
+    const T acc = row_sum<LPR>(a.A, row, rs.y, [&](int c) { return wd[c] * load_b<T>(b, s, c); });
     if (rs.y == 0 && !stop) a.x[row] = x1 + a.wd[row] * (bi - acc);
   }
 };

@@ -477,11 +477,6 @@ void upload_hierarchy(const HostHierarchy& h, DevHierarchy<T>& d, double omega, 
     D.x = mem.array<T>((size_t)D.n);
     D.b = mem.array<T>((size_t)D.n);
     if (l + 1 < h.levels.size()) {
-      if (nu_pre >= 2) {
-        HostCSR AW = H.A;
-        for (size_t k = 0; k < AW.val.size(); ++k) AW.val[k] = H.A.val[k] * w[AW.col[k]];
-        D.AW = upload_sell<T>(AW, mem, s, true, D.A.lpr);
-      }
       const int64_t nnzA = H.A.nnz();
       HostCSR G, F, RA;
       D.fuse_pre = nu_pre == 2 && (l > 0 || H.A.n_rows < kFusePreRows) &&
@@ -499,6 +494,10 @@ void upload_hierarchy(const HostHierarchy& h, DevHierarchy<T>& d, double omega, 
         D.fuse_post = l == 0 || (double)F.nnz() <= kFuseMaxFOverA * (double)nnzA;
       }
       if (D.fuse_pre) {
+        // the fused pre-smoothing reads A diag(w)
+        HostCSR AW = H.A;
+        for (size_t k = 0; k < AW.val.size(); ++k) AW.val[k] = H.A.val[k] * w[AW.col[k]];
+        D.AW = upload_sell<T>(AW, mem, s, true, D.A.lpr);
         D.G = upload_sell<T>(G, mem, s, true, 64);
       } else if (l == 0) {
         D.R = upload_sell<T>(H.R, mem, s, true);
@@ -611,8 +610,7 @@ class PrecImpl : public PrecBase {
       if (nu_pre == 0) {
         launch_fill<T>(cur, (T)0, L.n, s);
       } else {
-        launch_jacobi_zero<T, TB>(nu_pre >= 2 ? L.AW : L.A, L.wd, b, bs, cur, nu_pre >= 2 ? 1 : 0,
-                                  gate, s);
+        launch_jacobi_zero<T, TB>(L.A, L.wd, b, bs, cur, nu_pre >= 2 ? 1 : 0, gate, s);
         for (int k = 2; k < nu_pre; ++k) {
           launch_jacobi<T, TB>(L.A, L.wd, b, bs, cur, other, gate, s);
           std::swap(cur, other);

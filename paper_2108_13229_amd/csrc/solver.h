@@ -54,7 +54,7 @@ template <typename T>
 struct DevLevel {
   int n = 0;
   Sell<T> A, P;
-  Sell<T> AW;          // A diag(w): the fused first two sweeps gather b only
+  Sell<T> AW;          // A diag(w): the fused pre-smoothing + restriction reads it
   Sell<T> R;           // restriction (finest level)
   Sell<T> Q;           // [R | -R A]: restricted residual from [b; x] (coarser levels)
   Sell<T> G;           // R (I - A M2): restricted residual after pre-smoothing, from b
