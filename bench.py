@@ -104,6 +104,9 @@ def parse():
                          "--counter-run into the dominant kernel's HBM traffic (no GPU)")
     ap.add_argument("--traffic-out", default=None)
     ap.add_argument("--cpu-repeats", type=int, default=3)
+    ap.add_argument("--no-stencil", action="store_true",
+                    help="headline solvers read every column index (stencil_slices = 0); "
+                         "the results are the same, the time is not")
     ap.add_argument("--no-c1", action="store_true",
                     help="C2: leave out the 512 x 256 solves reported beside the headline")
     return ap.parse_args()
@@ -981,7 +984,7 @@ def headline_solves(sd, P, precs, args, roof_prec, config):
     for prec in precs:
         t0 = time.perf_counter()
         S = sd.Solver(P, precond="BGS", schur="mass", tol=1e-8, restart=args.restart,
-                      precision=prec)
+                      precision=prec, stencil_slices=0 if args.no_stencil else 1)
         t_setup = time.perf_counter() - t0
         lat, its, st, x = run_solves(S, args.steps, args.warmup)
         xs[prec] = x
@@ -1059,7 +1062,8 @@ def main():
         "dtype": "f64" if headline == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": WORKLOAD if args.config == "C1" else WORKLOAD_C2,
-                   "N": P.N, "nnz": P.nnz, "assembly_s": t_asm, "precision": headline},
+                   "N": P.N, "nnz": P.nnz, "assembly_s": t_asm, "precision": headline,
+                   "stencil_slices": 0 if args.no_stencil else 1},
         "p50_ms": head["p50_ms"],
         "p99_ms": head["p99_ms"],
         "restart": args.restart,

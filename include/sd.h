@@ -241,6 +241,11 @@ typedef struct {
   int darcy;         /* SD_DARCY_AMG (default) | SD_DARCY_ILU0                 */
   int pd_m_init, pd_m_min, pd_m_step;   /* PD-GMRES: defaults 3, 3, 5          */
   double pd_alpha_p, pd_alpha_d;        /* PD-GMRES gains: defaults -3, 5      */
+  int stencil_slices; /* 1 (default): 64-row slices of a one-lane-per-row
+                        matrix whose rows share one list of column offsets
+                        (a grid stencil) store those offsets once and read no
+                        column indices; 0: every slice reads its indices.
+                        Results are identical either way.                     */
 } sd_solver_opts;
 
 /* Fill opts with the defaults above. */
@@ -373,6 +378,40 @@ int sd_apply_vcycle(sd_solver* s, int block, const double* d_b, double* d_x,
  * rows of w and u_j in FP64).  SD_E_INVALID for n < 1 or n above the limit
  * that sd_setup enforces.  Host-only inspection. */
 int sd_arnoldi_layout(int64_t n, int* rows_per_block, int* blocks, size_t* lds_bytes);
+
+/* Sparse matrix layout of the device kernels, built on the host exactly as a
+ * solver uploads a matrix (host-only inspection).  Sliced ELLPACK: slices of
+ * C = 64 / lpr rows; entry k of row r of slice s at sptr[s] + C k + (r - C s)
+ * (with width > 0 every slice has that width and sptr[s] = C width s);
+ * padding has val 0.  lpr = 1 unless allow_csr lets a matrix with few or long
+ * rows take several lanes per row (the AMG hierarchy matrices).
+ * Stencil slices (stencil = 1, lpr = 1 only): a slice whose rows have their
+ * entries at columns row + o_k for one ascending offset list shared by the
+ * slice (a grid stencil) stores each row with an explicit zero at the offsets
+ * it lacks and doff[sptr[s] / 64 + k] = o_k (positions past the list repeat
+ * its last offset); the kernels then read no column indices for it.
+ * doff[sptr[s] / 64] = INT32_MIN marks a slice read through col, and one
+ * more INT32_MIN closes the array (a slice of width 0 has no entry); doff is
+ * NULL (n_doff = 0) when stencil slices hold less than half of the entries.
+ * col is complete for every slice.  idx counts the column indices or offsets
+ * a pass over the matrix reads.  Input: CSR with n_rows + 1 row pointers from
+ * 0 and columns in [0, n_cols); SD_E_INVALID otherwise or beyond 2^31 stored
+ * entries.  The views stay valid until sd_sell_destroy. */
+typedef struct sd_sell sd_sell;
+typedef struct {
+  int lpr, width;
+  int64_t n_rows, n_cols, nnz, idx;
+  int64_t n_ptr, n_entries, n_doff;   /* lengths of sptr, col / val, doff */
+  const int32_t* sptr;
+  const int32_t* col;
+  const double* val;
+  const int32_t* doff;
+} sd_sell_info;
+int sd_sell_build(int64_t n_rows, int64_t n_cols, const int64_t* rowptr,
+                  const int32_t* col, const double* val, int allow_csr,
+                  int stencil, sd_sell** out);
+int sd_sell_view(const sd_sell* m, sd_sell_info* info);
+void sd_sell_destroy(sd_sell* m);
 
 /* Measurement: bracket every launch of one kernel class with HIP events
  * during subsequent sd_solve calls (those solves then launch kernels one by

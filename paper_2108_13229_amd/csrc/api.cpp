@@ -84,6 +84,7 @@ void sd_solver_opts_default(sd_solver_opts* o) {
   o->pd_m_step = 5;
   o->pd_alpha_p = -3.0;
   o->pd_alpha_d = 5.0;
+  o->stencil_slices = 1;
 }
 
 static int assemble_impl(const sd_grid* grid, const sd_physics* phys, const sd_bcs* bcs,
@@ -372,6 +373,57 @@ int sd_arnoldi_layout(int64_t n, int* rows_per_block, int* blocks, size_t* lds_b
   if (lds_bytes) *lds_bytes = (size_t)2 * rp * sizeof(double);
   return SD_OK;
 }
+
+struct sd_sell {
+  sd::HostSell<double> h;
+};
+
+int sd_sell_build(int64_t n_rows, int64_t n_cols, const int64_t* rowptr, const int32_t* col,
+                  const double* val, int allow_csr, int stencil, sd_sell** out) {
+  return guarded([&] {
+    if (!out) return fail(SD_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (n_rows < 0 || n_cols < 0 || !rowptr || (n_rows > 0 && rowptr[n_rows] > 0 && (!col || !val)))
+      return fail(SD_E_INVALID, "bad CSR arguments");
+    if (rowptr[0] != 0) return fail(SD_E_INVALID, "rowptr[0] must be 0");
+    for (int64_t r = 0; r < n_rows; ++r)
+      if (rowptr[r + 1] < rowptr[r]) return fail(SD_E_INVALID, "rowptr must not decrease");
+    sd::HostCSR A;
+    A.n_rows = n_rows;
+    A.n_cols = n_cols;
+    A.rowptr.assign(rowptr, rowptr + n_rows + 1);
+    const int64_t nnz = rowptr[n_rows];
+    A.col.assign(col, col + nnz);
+    A.val.assign(val, val + nnz);
+    for (int32_t c : A.col)
+      if (c < 0 || c >= n_cols) return fail(SD_E_INVALID, "column outside [0, n_cols)");
+    std::unique_ptr<sd_sell> m(new sd_sell());
+    m->h = sd::build_sell<double>(A, allow_csr != 0, 0, stencil != 0);
+    *out = m.release();
+    return (int)SD_OK;
+  });
+}
+
+int sd_sell_view(const sd_sell* m, sd_sell_info* info) {
+  if (!m || !info) return fail(SD_E_INVALID, "NULL argument");
+  const sd::HostSell<double>& h = m->h;
+  info->lpr = h.lpr;
+  info->width = h.width;
+  info->n_rows = h.n_rows;
+  info->n_cols = h.n_cols;
+  info->nnz = h.nnz;
+  info->idx = h.idx;
+  info->n_ptr = (int64_t)h.sptr.size();
+  info->n_entries = (int64_t)h.col.size();
+  info->n_doff = (int64_t)h.doff.size();
+  info->sptr = h.sptr.data();
+  info->col = h.col.data();
+  info->val = h.val.data();
+  info->doff = h.doff.empty() ? nullptr : h.doff.data();
+  return SD_OK;
+}
+
+void sd_sell_destroy(sd_sell* m) { delete m; }
 
 int sd_solver_profile(sd_solver* s, int kernel_class) {
   if (!s || kernel_class < 0 || kernel_class > 4) return fail(SD_E_INVALID, "bad argument");

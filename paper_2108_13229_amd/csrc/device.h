@@ -28,17 +28,34 @@ constexpr int kIluMaxLevels = 4096; // ILU(0): levels per substitution
 // (one wavefront per slice); entry (r, k) of slice s lives at
 // sptr[s] + 64 k + (r - 64 s), padding has val = 0.  lpr > 1: CSR (sptr holds
 // the n_rows + 1 row pointers) read by lpr lanes per row.
+//
+// Stencil slices (lpr == 1 only): where every row of a slice has its entries
+// at columns row + o_k for one ascending list of offsets o_0 < o_1 < ...
+// shared by the slice (a grid stencil away from the grid's boundaries), the
+// rows are stored with an explicit zero at each offset they lack, and
+// doff[sptr[s] / 64 + k] = o_k.  A wavefront then takes column row + o_k
+// from one scalar load per entry position instead of a vector load of col.
+// doff[sptr[s] / 64] == kIrregularSlice marks a slice read through col (a
+// last kIrregularSlice closes the array; slices of width 0 have no entry).  col
+// stays complete for every slice (col = row + o_k in stencil slices).  A zero
+// added to a row sum started at +0 leaves it unchanged, so both forms give
+// the same sums.
+constexpr int kIrregularSlice = -2147483647 - 1;
+
 template <typename T>
 struct Sell {
   const int* sptr = nullptr;
   const int* col = nullptr;
   const T* val = nullptr;
+  const int* doff = nullptr;  // stencil offsets, or nullptr: every slice reads col
   int n_rows = 0;
   int n_cols = 0;
   int lpr = 1;
   int width = 0;   // > 0: every row padded to this width (SELL: slice s at
                    // 64 * width * s; CSR: row r at width * r), sptr not read
   int64_t nnz = 0; // stored entries without padding (algorithmic bytes only)
+  int64_t idx = 0; // column indices a pass reads: nnz without stencil slices,
+                   // else the irregular slices' unpadded entries + doff length
 };
 
 // ILU(0) factors in level order (see HostIlu): positions q of the forward

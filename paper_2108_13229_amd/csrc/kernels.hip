@@ -96,14 +96,67 @@ __device__ __forceinline__ TM sell_row(const Sell<TM>& A, int e, int cnt, int st
   return acc;
 }
 
+// The same sum over a stencil slice (see Sell): entry k of the row sits at
+// column row + o[k], o the slice's offsets (wavefront-uniform, so scalar
+// loads), and only the values are loaded per lane.  The entries are added
+// in the same order as by sell_row.
+template <int M, bool NT, typename TM, typename F>
+__device__ __forceinline__ void stencil_chunk(const Sell<TM>& A, int e, const int* o, int row,
+                                              F f, TM& acc) {
+  TM v[M];
+  int c[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    v[i] = load_hint<NT>(&A.val[e + i * 64]);
+    c[i] = row + o[i];
+  }
+  TM x[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) x[i] = f(c[i]);
+#pragma unroll
+  for (int i = 0; i < M; ++i) acc += v[i] * x[i];
+}
+
+template <int M, bool NT, typename TM, typename F>
+__device__ __forceinline__ void stencil_tail(const Sell<TM>& A, int e, int cnt, const int* o,
+                                             int row, F f, TM& acc) {
+  if constexpr (M > 0) {
+    if (cnt == M) stencil_chunk<M, NT>(A, e, o, row, f, acc);
+    else stencil_tail<M - 1, NT>(A, e, cnt, o, row, f, acc);
+  }
+}
+
+template <int K, bool NT = false, typename TM, typename F>
+__device__ __forceinline__ TM stencil_row(const Sell<TM>& A, int e, int cnt, const int* o,
+                                          int row, F f) {
+  TM acc = 0;
+  for (; cnt >= K; cnt -= K, e += K * 64, o += K) stencil_chunk<K, NT>(A, e, o, row, f, acc);
+  stencil_tail<K - 1, NT>(A, e, cnt, o, row, f, acc);
+  return acc;
+}
+
+// The offsets of the wavefront's slice whose first entry is at sbase (a
+// multiple of 64), or nullptr if the slice is read through col.  Callers
+// give every wavefront one slice, so sbase is uniform.
+template <typename TM>
+__device__ __forceinline__ const int* stencil_of(const Sell<TM>& A, int sbase) {
+  if (!A.doff) return nullptr;
+  const int* o = A.doff + (sbase >> 6);
+  return o[0] == kIrregularSlice ? nullptr : o;
+}
+
 constexpr int kRowChunk = 6;   // entries of a SELL-64 row loaded at once
 
+// Row `row` of a SELL-64 matrix times x.  The caller's wavefront holds the
+// 64 rows of one slice (64 consecutive rows from a multiple of 64).
 template <int K = kRowChunk, bool NT = false, typename TM, typename TX>
 __device__ __forceinline__ TM sell_dot(const Sell<TM>& A, const TX* __restrict__ x, int row) {
-  const int s = row >> 6;
-  const int beg = A.sptr[s] + (row & 63);
-  const int end = A.sptr[s + 1];
-  return sell_row<K, NT>(A, beg, (end - beg + 63) >> 6, 64, [&](int c) { return (TM)x[c]; });
+  const int s = __builtin_amdgcn_readfirstlane(row >> 6);
+  const int sbase = A.sptr[s];
+  const int cnt = (A.sptr[s + 1] - sbase) >> 6;
+  const auto f = [&](int c) { return (TM)x[c]; };
+  if (const int* o = stencil_of(A, sbase)) return stencil_row<K, NT>(A, sbase + (row & 63), cnt, o, row, f);
+  return sell_row<K, NT>(A, sbase + (row & 63), cnt, 64, f);
 }
 
 __device__ __forceinline__ double scale_of(const double* s) { return s ? *s : 1.0; }
@@ -183,7 +236,8 @@ inline int dot_blocks(int n) {
 template <int LPR, typename TM, typename F>
 __device__ __forceinline__ TM row_sum(const Sell<TM>& A, int row, int sub, F f) {
   constexpr int C = 64 / LPR;
-  const int sl = row / C, r = row - sl * C;
+  // row_of_thread gives each wavefront one slice
+  const int sl = __builtin_amdgcn_readfirstlane(row / C), r = row - sl * C;
   int beg, end;
   if (A.width) {
     beg = sl * (C * A.width);
@@ -191,6 +245,9 @@ __device__ __forceinline__ TM row_sum(const Sell<TM>& A, int row, int sub, F f) 
   } else {
     beg = A.sptr[sl];
     end = A.sptr[sl + 1];
+  }
+  if constexpr (LPR == 1) {
+    if (const int* o = stencil_of(A, beg)) return stencil_row<kRowChunk>(A, beg + r, (end - beg) >> 6, o, row, f);
   }
   const int e0 = beg + sub * C + r;
   TM acc = sell_row<LPR == 1 ? kRowChunk : 4>(A, e0, (end - e0 + 63) >> 6, 64, f);
@@ -1573,10 +1630,11 @@ void launch_op(K kernel, B batched, const typename Op::Args& a, int nb, size_t l
   kernel<<<nb, Op::kThreads, lds, s>>>(a);
 }
 
-// Algorithmic bytes of a sparse matrix pass: each stored value and index once.
+// Algorithmic bytes of a sparse matrix pass: each stored value once, and
+// each column index or stencil offset the pass reads once.
 template <typename T>
 double mat_bytes(const Sell<T>& A) {
-  return (double)A.nnz * (double)(sizeof(T) + sizeof(int));
+  return (double)A.nnz * (double)sizeof(T) + (double)A.idx * (double)sizeof(int);
 }
 
 // Calls f with the lanes-per-row count as a compile-time constant.

@@ -100,42 +100,38 @@ static int lanes_per_row(const HostCSR& A, bool allow_csr, int force_lpr) {
   return avg <= 16.0 ? 4 : (avg <= 48.0 ? 8 : (avg <= 96.0 ? 16 : (avg <= 192.0 ? 32 : 64)));
 }
 
-template <typename T>
-static Sell<T> copy_sell(const std::vector<int>& ptr, const std::vector<int>& col,
-                         const std::vector<T>& val, int64_t n, int64_t n_cols, int lpr, int width,
-                         int64_t nnz, DeviceMem& mem, hipStream_t s) {
-  Sell<T> d;
-  d.n_rows = (int)n;
-  d.n_cols = (int)n_cols;
-  d.lpr = lpr;
-  d.width = width;
-  d.nnz = nnz;
-  int* dp = mem.array<int>(std::max<size_t>(ptr.size(), 1));
-  int* dcol = mem.array<int>(std::max<size_t>(col.size(), 1));
-  T* dval = mem.array<T>(std::max<size_t>(val.size(), 1));
-  if (!ptr.empty())
-    SD_HIP(hipMemcpyAsync(dp, ptr.data(), ptr.size() * sizeof(int), hipMemcpyHostToDevice, s));
-  if (!col.empty())
-    SD_HIP(hipMemcpyAsync(dcol, col.data(), col.size() * sizeof(int), hipMemcpyHostToDevice, s));
-  if (!val.empty())
-    SD_HIP(hipMemcpyAsync(dval, val.data(), val.size() * sizeof(T), hipMemcpyHostToDevice, s));
-  SD_HIP(hipStreamSynchronize(s));
-  d.sptr = dp;
-  d.col = dcol;
-  d.val = dval;
-  return d;
+// Offsets of a stencil slice (see Sell): the ascending union of col - row
+// over the slice's rows, or an empty list when the slice is irregular (a row
+// with repeated columns, more offsets than the slice width w, or a column
+// row + o outside [0, n_cols) for one of its 64 rows, phantom rows past n
+// included).
+static std::vector<int> stencil_offsets(const HostCSR& A, int64_t sl, int64_t w) {
+  const int64_t n = A.n_rows, r0 = sl * 64, r1 = std::min(n, r0 + 64);
+  std::vector<int64_t> o;
+  for (int64_t r = r0; r < r1; ++r) {
+    for (int64_t e = A.rowptr[r]; e < A.rowptr[r + 1]; ++e) {
+      if (e > A.rowptr[r] && A.col[e] <= A.col[e - 1]) return {};
+      o.push_back((int64_t)A.col[e] - r);
+    }
+  }
+  std::sort(o.begin(), o.end());
+  o.erase(std::unique(o.begin(), o.end()), o.end());
+  if (o.empty() || (int64_t)o.size() > w) return {};
+  if (r0 + o.front() < 0 || r0 + 63 + o.back() >= A.n_cols) return {};
+  return std::vector<int>(o.begin(), o.end());
 }
 
-// Upload as SELL-C: slices of C = 64 / lpr rows, entry k of row r of slice s
-// at sptr[s] + k C + (r - s C), slice width = longest row of the slice rounded
-// up to a multiple of lpr (padding repeats the row's last column with value
-// 0).  lpr = 1 (SELL-64) unless allow_csr picks more lanes for matrices with
-// few or long rows.  Hierarchy matrices whose slices pad to one common width
-// at modest cost get that uniform width, which spares the kernels the slice
-// pointer load.
+// SELL-C layout on the host: slices of C = 64 / lpr rows, entry k of row r of
+// slice s at sptr[s] + C k + (r - C s).  A slice's width is its longest row
+// rounded up to a multiple of lpr; padding has val 0 and repeats the row's
+// last column (0 for an empty row).  lpr = 1 (SELL-64) unless allow_csr
+// picks more lanes for matrices with few or long rows.  Hierarchy matrices
+// whose slices pad to one common width at most 30 % larger get that width,
+// which spares the kernels the slice pointer load.  Stencil slices (lpr == 1,
+// see Sell) are used where they hold at least half of the entries.
 template <typename T>
-Sell<T> upload_sell(const HostCSR& A, DeviceMem& mem, hipStream_t s, bool allow_csr,
-                    int force_lpr) {
+HostSell<T> build_sell(const HostCSR& A, bool allow_csr, int force_lpr, bool stencil) {
+  HostSell<T> h;
   const int64_t n = A.n_rows;
   const int lpr = lanes_per_row(A, allow_csr, force_lpr);
   const int64_t C = 64 / lpr;
@@ -157,13 +153,70 @@ Sell<T> upload_sell(const HostCSR& A, DeviceMem& mem, hipStream_t s, bool allow_
     tot = C * ns * wmax;
   }
   if (tot >= ((int64_t)1 << 31)) throw Error(SD_E_INVALID, "matrix too large for int32 SELL");
-  std::vector<int> sptr((size_t)ns + 1, 0);
+  h.n_rows = n;
+  h.n_cols = A.n_cols;
+  h.lpr = lpr;
+  h.width = uniform ? (int)wmax : 0;
+  h.nnz = A.nnz();
+  std::vector<int>& sptr = h.sptr;
+  std::vector<int>& col = h.col;
+  std::vector<T>& val = h.val;
+  sptr.assign((size_t)ns + 1, 0);
   for (int64_t sl = 0; sl < ns; ++sl) sptr[sl + 1] = (int)(sptr[sl] + C * width[sl]);
-  std::vector<int> col((size_t)tot, 0);
-  std::vector<T> val((size_t)tot, (T)0);
+  col.assign((size_t)tot, 0);
+  val.assign((size_t)tot, (T)0);
+  std::vector<std::vector<int>> offs;
+  if (stencil && lpr == 1) {
+    offs.resize((size_t)ns);
+    parallel_ranges(0, ns, [&](int64_t s0, int64_t s1) {
+      for (int64_t sl = s0; sl < s1; ++sl) offs[sl] = stencil_offsets(A, sl, width[sl]);
+    });
+    int64_t covered = 0;
+    for (int64_t sl = 0; sl < ns; ++sl)
+      if (!offs[sl].empty()) covered += A.rowptr[std::min(n, sl * 64 + 64)] - A.rowptr[sl * 64];
+    if (covered == 0 || 2 * covered < A.nnz()) offs.clear();
+  }
+  std::vector<int>& doff = h.doff;
+  h.idx = A.nnz();
+  if (!offs.empty()) {
+    // one entry per slice position, and a closing kIrregularSlice: a slice
+    // of width 0 has no entry of its own, the kernels read the flag at its
+    // base (the next slice's first offset, or this one) and then nothing
+    doff.assign((size_t)(tot / 64 + 1), 0);
+    doff.back() = kIrregularSlice;
+    h.idx = (int64_t)doff.size();
+    for (int64_t sl = 0; sl < ns; ++sl) {
+      const int64_t b = sptr[sl] / 64, w = width[sl];
+      const std::vector<int>& o = offs[sl];
+      if (w == 0) continue;
+      if (o.empty()) {
+        doff[b] = kIrregularSlice;
+        h.idx += A.rowptr[std::min(n, sl * 64 + 64)] - A.rowptr[sl * 64];
+      } else {
+        // positions past the slice's offsets repeat the last one (zeros)
+        for (int64_t k = 0; k < w; ++k) doff[b + k] = o[std::min<int64_t>(k, (int64_t)o.size() - 1)];
+      }
+    }
+  }
   parallel_ranges(0, ns, [&](int64_t s0, int64_t s1) {
     for (int64_t sl = s0; sl < s1; ++sl) {
       const int64_t w = width[sl];
+      if (!offs.empty() && !offs[sl].empty()) {
+        const int* o = &doff[sptr[sl] / 64];
+        for (int64_t ri = 0; ri < 64; ++ri) {
+          const int64_t r = sl * 64 + ri;
+          int64_t e = r < n ? A.rowptr[r] : 0;
+          const int64_t end = r < n ? A.rowptr[r + 1] : 0;
+          for (int64_t k = 0; k < w; ++k) {
+            const int64_t p = sptr[sl] + 64 * k + ri;
+            col[p] = (int)(r + o[k]);
+            const bool here = e < end && (int64_t)A.col[e] - r == o[k] &&
+                              (k == 0 || o[k] != o[k - 1]);
+            val[p] = here ? (T)A.val[e++] : (T)0;
+          }
+        }
+        continue;
+      }
       for (int64_t ri = 0; ri < C; ++ri) {
         const int64_t r = sl * C + ri;
         int64_t len = 0, beg = 0;
@@ -184,12 +237,46 @@ Sell<T> upload_sell(const HostCSR& A, DeviceMem& mem, hipStream_t s, bool allow_
       }
     }
   });
-  return copy_sell<T>(sptr, col, val, n, A.n_cols, lpr, uniform ? (int)wmax : 0, A.nnz(), mem,
-                      s);
+  return h;
 }
 
-template Sell<double> upload_sell<double>(const HostCSR&, DeviceMem&, hipStream_t, bool, int);
-template Sell<float> upload_sell<float>(const HostCSR&, DeviceMem&, hipStream_t, bool, int);
+template HostSell<double> build_sell<double>(const HostCSR&, bool, int, bool);
+template HostSell<float> build_sell<float>(const HostCSR&, bool, int, bool);
+
+template <typename T>
+Sell<T> upload_sell(const HostCSR& A, DeviceMem& mem, hipStream_t s, bool allow_csr,
+                    int force_lpr, bool stencil) {
+  const HostSell<T> h = build_sell<T>(A, allow_csr, force_lpr, stencil);
+  Sell<T> d;
+  d.n_rows = (int)h.n_rows;
+  d.n_cols = (int)h.n_cols;
+  d.lpr = h.lpr;
+  d.width = h.width;
+  d.nnz = h.nnz;
+  d.idx = h.idx;
+  int* dp = mem.array<int>(std::max<size_t>(h.sptr.size(), 1));
+  int* dcol = mem.array<int>(std::max<size_t>(h.col.size(), 1));
+  T* dval = mem.array<T>(std::max<size_t>(h.val.size(), 1));
+  if (!h.sptr.empty())
+    SD_HIP(hipMemcpyAsync(dp, h.sptr.data(), h.sptr.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  if (!h.col.empty())
+    SD_HIP(hipMemcpyAsync(dcol, h.col.data(), h.col.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  if (!h.val.empty())
+    SD_HIP(hipMemcpyAsync(dval, h.val.data(), h.val.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  if (!h.doff.empty()) {
+    int* dd = mem.array<int>(h.doff.size());
+    SD_HIP(hipMemcpyAsync(dd, h.doff.data(), h.doff.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    d.doff = dd;
+  }
+  SD_HIP(hipStreamSynchronize(s));
+  d.sptr = dp;
+  d.col = dcol;
+  d.val = dval;
+  return d;
+}
+
+template Sell<double> upload_sell<double>(const HostCSR&, DeviceMem&, hipStream_t, bool, int, bool);
+template Sell<float> upload_sell<float>(const HostCSR&, DeviceMem&, hipStream_t, bool, int, bool);
 
 // ------------------------------------------------------------ host setup
 static double diag_at(const HostCSR& A, int64_t r) {
@@ -226,6 +313,8 @@ void Solver::setup_host(HostProblem* p, const sd_solver_opts* o) {
     throw Error(SD_E_INVALID, "PD-GMRES needs pd_m_init, pd_m_min >= 1, pd_m_step >= 0 and "
                               "finite gains");
   if (so.amg != SD_AMG_PLAIN && so.amg != SD_AMG_SMOOTHED) throw Error(SD_E_INVALID, "amg");
+  if (so.stencil_slices != 0 && so.stencil_slices != 1)
+    throw Error(SD_E_INVALID, "stencil_slices must be 0 or 1");
   if (so.darcy != SD_DARCY_AMG && so.darcy != SD_DARCY_ILU0) throw Error(SD_E_INVALID, "darcy");
   opts.amg.theta = so.theta;
   opts.amg.omega = so.omega;
@@ -322,7 +411,8 @@ Solver::~Solver() {
 void Solver::upload(const sd_allocator* alloc, hipStream_t s) {
   const double t0 = wall_time();
   mem.reset(new DeviceMem(alloc, s));
-  A64 = upload_sell<double>(pb->A, *mem, s);
+  const bool stencil = opts.o.stencil_slices != 0;
+  A64 = upload_sell<double>(pb->A, *mem, s, false, 0, stencil);
   b_dev = mem->array<double>((size_t)N);
   if (pb->mass > 0.0) step_b = mem->array<double>((size_t)N);
   SD_HIP(hipMemcpyAsync(b_dev, pb->b.data(), (size_t)N * sizeof(double), hipMemcpyHostToDevice, s));
@@ -460,13 +550,13 @@ constexpr int64_t kFuseMaxRowWidth = 64;
 
 template <typename T>
 void upload_hierarchy(const HostHierarchy& h, DevHierarchy<T>& d, double omega, int nu_pre,
-                      int nu_post, DeviceMem& mem, hipStream_t s) {
+                      int nu_post, bool stencil, DeviceMem& mem, hipStream_t s) {
   d.lev.resize(h.levels.size());
   for (size_t l = 0; l < h.levels.size(); ++l) {
     const HostLevel& H = h.levels[l];
     DevLevel<T>& D = d.lev[l];
     D.n = (int)H.A.n_rows;
-    D.A = upload_sell<T>(H.A, mem, s, true);
+    D.A = upload_sell<T>(H.A, mem, s, true, 0, stencil);
     std::vector<double> w((size_t)D.n);
     for (int i = 0; i < D.n; ++i) w[i] = omega / diag_at(H.A, i);
     std::vector<T> wd((size_t)D.n);
@@ -497,7 +587,7 @@ void upload_hierarchy(const HostHierarchy& h, DevHierarchy<T>& d, double omega, 
         // the fused pre-smoothing reads A diag(w)
         HostCSR AW = H.A;
         for (size_t k = 0; k < AW.val.size(); ++k) AW.val[k] = H.A.val[k] * w[AW.col[k]];
-        D.AW = upload_sell<T>(AW, mem, s, true, D.A.lpr);
+        D.AW = upload_sell<T>(AW, mem, s, true, D.A.lpr, stencil);
         D.G = upload_sell<T>(G, mem, s, true, 64);
       } else if (l == 0) {
         D.R = upload_sell<T>(H.R, mem, s, true);
@@ -568,15 +658,16 @@ class PrecImpl : public PrecBase {
     cc = !S.hh[2].levels.empty();
     for (int b = 0; b < 3; ++b)
       if (!S.hh[b].levels.empty())
-        upload_hierarchy<T>(S.hh[b], H[b], S.opts.amg.omega, nu_pre, nu_post, mem, s);
+        upload_hierarchy<T>(S.hh[b], H[b], S.opts.amg.omega, nu_pre, nu_post,
+                            S.opts.o.stencil_slices != 0, mem, s);
     if (S.ilu.n > 0) ilu = upload_ilu<T>(S.ilu, mem, s);
     if (cc) {
       tp = mem.array<T>((size_t)(S.off[3] - S.off[2]));
       yl = mem.array<T>((size_t)(S.off[3] - S.off[2]));
     }
-    Cf = upload_sell<T>(S.Cf, mem, s);
+    Cf = upload_sell<T>(S.Cf, mem, s, false, 0, S.opts.o.stencil_slices != 0);
     arn32 = S.opts.o.precision == SD_PRECISION_MIXED32;
-    if (arn32) A32 = upload_sell<float>(S.pb->A, mem, s);
+    if (arn32) A32 = upload_sell<float>(S.pb->A, mem, s, false, 0, S.opts.o.stencil_slices != 0);
     ldz = S.ldv;
     Z = mem.array<T>((size_t)S.opts.o.restart * ldz);
     tq = mem.array<T>((size_t)(S.N - S.off[3]) + 1);
@@ -1005,16 +1096,17 @@ class PrecImpl : public PrecBase {
       SD_HIP(hipEventElapsedTime(&ms, S.prof_ev[(size_t)2 * j], S.prof_ev[(size_t)2 * j + 1]));
       S.prof_seconds += 1e-3 * ms;
       S.prof_launches += 1;
-      if (S.prof_class == 1)  // A (values + indices), z, w, j+1 basis vectors
-        S.prof_bytes += (double)S.nnz_A * ((arn32 ? 4.0 : 8.0) + 4.0) + n * (tz + 8.0) +
-                        (j + 1) * 8.0 * n;
+      if (S.prof_class == 1)  // A (values + indices read), z, w, j+1 basis vectors
+        S.prof_bytes += (double)S.nnz_A * (arn32 ? 4.0 : 8.0) + 4.0 * (double)S.A64.idx +
+                        n * (tz + 8.0) + (j + 1) * 8.0 * n;
       else if (S.prof_class == 2)  // j basis vectors, u_j and w read; v_j, u_{j+1} written
         S.prof_bytes += (j + 4) * 8.0 * n;
       else if (S.prof_class == 4)  // every launch of the application
         S.prof_bytes += precond_bytes(S);
-      else {  // V level 0: A_V (values + indices), x_in, b, w, x_out
+      else {  // V level 0: A_V (values + indices read), x_in, b, w, x_out
         const double nv = (double)S.off[2];
-        S.prof_bytes += (double)S.nnz_V0 * (tz + 4.0) + nv * (3.0 * tz + 8.0);
+        const double idx = H[0].lev.empty() ? 0.0 : (double)H[0].lev[0].A.idx;
+        S.prof_bytes += (double)S.nnz_V0 * tz + 4.0 * idx + nv * (3.0 * tz + 8.0);
       }
     }
   }

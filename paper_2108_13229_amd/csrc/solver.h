@@ -230,10 +230,23 @@ class Solver {
 
 constexpr int kUzawaPowerIters = 30;
 
+// SELL layout of a matrix on the host, as upload_sell copies it to the
+// device (fields as in Sell; doff empty without stencil slices).
+template <typename T>
+struct HostSell {
+  int64_t n_rows = 0, n_cols = 0, nnz = 0, idx = 0;
+  int lpr = 1, width = 0;
+  std::vector<int> sptr, col, doff;
+  std::vector<T> val;
+};
+// stencil: use stencil slices (see Sell) where the layout is SELL-64.
+template <typename T>
+HostSell<T> build_sell(const HostCSR& A, bool allow_csr, int force_lpr, bool stencil);
+
 // SELL construction on the host and upload.
 template <typename T>
 Sell<T> upload_sell(const HostCSR& A, DeviceMem& mem, hipStream_t s, bool allow_csr = false,
-                    int force_lpr = 0);
+                    int force_lpr = 0, bool stencil = false);
 
 std::unique_ptr<PrecBase> make_prec_fp64(Solver& S, hipStream_t s);
 std::unique_ptr<PrecBase> make_prec_fp32(Solver& S, hipStream_t s);

@@ -123,7 +123,15 @@ class SolverOpts(C.Structure):
                 ("nu_post", C.c_int), ("coarse_max", C.c_int), ("max_levels", C.c_int),
                 ("darcy", C.c_int), ("pd_m_init", C.c_int), ("pd_m_min", C.c_int),
                 ("pd_m_step", C.c_int), ("pd_alpha_p", C.c_double),
-                ("pd_alpha_d", C.c_double)]
+                ("pd_alpha_d", C.c_double), ("stencil_slices", C.c_int)]
+
+
+class SellInfo(C.Structure):
+    _fields_ = [("lpr", C.c_int), ("width", C.c_int), ("n_rows", C.c_int64),
+                ("n_cols", C.c_int64), ("nnz", C.c_int64), ("idx", C.c_int64),
+                ("n_ptr", C.c_int64), ("n_entries", C.c_int64), ("n_doff", C.c_int64),
+                ("sptr", C.POINTER(C.c_int32)), ("col", C.POINTER(C.c_int32)),
+                ("val", C.POINTER(C.c_double)), ("doff", C.POINTER(C.c_int32))]
 
 
 class Stats(C.Structure):
@@ -214,6 +222,11 @@ SIGNATURES = {
     "sd_apply_vcycle": (C.c_int, [_P, C.c_int, _P, _P, C.c_int64, _P]),
     "sd_arnoldi_layout": (C.c_int, [C.c_int64, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                     C.POINTER(C.c_size_t)]),
+    "sd_sell_build": (C.c_int, [C.c_int64, C.c_int64, C.POINTER(C.c_int64),
+                                C.POINTER(C.c_int32), _dp, C.c_int, C.c_int,
+                                C.POINTER(_P)]),
+    "sd_sell_view": (C.c_int, [_P, C.POINTER(SellInfo)]),
+    "sd_sell_destroy": (None, [_P]),
     "sd_solver_profile": (C.c_int, [_P, C.c_int]),
     "sd_solver_middle_scale": (C.c_int, [_P, C.POINTER(C.c_double)]),
     "sd_solver_precond_cost": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
@@ -657,6 +670,33 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def sell_layout(rowptr, col, val, n_cols: int, allow_csr: bool = False, stencil: bool = True):
+    """The device layout of a CSR matrix (copies of the library's host arrays):
+    dict with lpr, width, nnz, idx and the arrays sptr, col, val, doff (None
+    without stencil slices)."""
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    val = np.ascontiguousarray(val, dtype=np.float64)
+    h = C.c_void_p()
+    _check(lib().sd_sell_build(len(rowptr) - 1, int(n_cols),
+                               rowptr.ctypes.data_as(C.POINTER(C.c_int64)),
+                               col.ctypes.data_as(C.POINTER(C.c_int32)),
+                               val.ctypes.data_as(C.POINTER(C.c_double)), int(allow_csr),
+                               int(stencil), C.byref(h)))
+    try:
+        info = SellInfo()
+        _check(lib().sd_sell_view(h, C.byref(info)))
+        def arr(ptr, n, dt):
+            return np.ctypeslib.as_array(ptr, (n,)).astype(dt, copy=True) if n else np.zeros(0, dt)
+        return dict(lpr=info.lpr, width=info.width, nnz=info.nnz, idx=info.idx,
+                    sptr=arr(info.sptr, info.n_ptr, np.int64),
+                    col=arr(info.col, info.n_entries, np.int64),
+                    val=arr(info.val, info.n_entries, np.float64),
+                    doff=arr(info.doff, info.n_doff, np.int64) if info.n_doff else None)
+    finally:
+        lib().sd_sell_destroy(h)
 
 
 def arnoldi_layout(n: int):
