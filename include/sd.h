@@ -385,21 +385,26 @@ int sd_arnoldi_layout(int64_t n, int* rows_per_block, int* blocks, size_t* lds_b
  * (with width > 0 every slice has that width and sptr[s] = C width s);
  * padding has val 0.  lpr = 1 unless allow_csr lets a matrix with few or long
  * rows take several lanes per row (the AMG hierarchy matrices).
- * Stencil slices (stencil = 1, lpr = 1 only): a slice whose rows have their
- * entries at columns row + o_k for one ascending offset list shared by the
- * slice (a grid stencil) stores each row with an explicit zero at the offsets
- * it lacks and doff[sptr[s] / 64 + k] = o_k (positions past the list repeat
- * its last offset); the kernels then read no column indices for it.
- * doff[sptr[s] / 64] = INT32_MIN marks a slice read through col, and one
- * more INT32_MIN closes the array (a slice of width 0 has no entry); doff is
- * NULL (n_doff = 0) when stencil slices hold less than half of the entries.
- * col is complete for every slice.  idx counts the column indices or offsets
- * a pass over the matrix reads.  Input: CSR with n_rows + 1 row pointers from
+ * Stencil slices (stencil = 1, lpr = 1 only): a slice stores its rows on the
+ * ascending union o_0 < o_1 < ... of their offsets col - row (a grid
+ * stencil), each row with an explicit zero at the offsets it lacks, and
+ * doff[sptr[s] / 64 + k] = o_k (positions past the union repeat its last
+ * offset); the kernels take column row + o_k, clamped into [0, n_cols)
+ * (where the clamp acts the value is 0), and read no column indices for it.
+ * A slice whose union is longer than its width is widened by up to 8
+ * positions when slices have their own widths (width = 0); otherwise, or
+ * when a row repeats a column, it is read through col.  info.stencil: 0 no
+ * stencil slices (doff NULL, n_doff = 0; also when they would hold less than
+ * half of the entries), 2 every slice, 1 some: doff[sptr[s] / 64] = INT32_MIN
+ * marks the others.  One more INT32_MIN closes doff (a slice of width 0 has
+ * no entry).  col is complete for every slice (the clamped row + o_k in
+ * stencil slices).  idx counts the column indices or offsets a pass over the
+ * matrix reads.  Input: CSR with n_rows + 1 row pointers from
  * 0 and columns in [0, n_cols); SD_E_INVALID otherwise or beyond 2^31 stored
  * entries.  The views stay valid until sd_sell_destroy. */
 typedef struct sd_sell sd_sell;
 typedef struct {
-  int lpr, width;
+  int lpr, width, stencil;
   int64_t n_rows, n_cols, nnz, idx;
   int64_t n_ptr, n_entries, n_doff;   /* lengths of sptr, col / val, doff */
   const int32_t* sptr;

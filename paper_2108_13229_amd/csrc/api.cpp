@@ -409,6 +409,7 @@ int sd_sell_view(const sd_sell* m, sd_sell_info* info) {
   const sd::HostSell<double>& h = m->h;
   info->lpr = h.lpr;
   info->width = h.width;
+  info->stencil = h.stencil;
   info->n_rows = h.n_rows;
   info->n_cols = h.n_cols;
   info->nnz = h.nnz;

@@ -29,17 +29,19 @@ constexpr int kIluMaxLevels = 4096; // ILU(0): levels per substitution
 // sptr[s] + 64 k + (r - 64 s), padding has val = 0.  lpr > 1: CSR (sptr holds
 // the n_rows + 1 row pointers) read by lpr lanes per row.
 //
-// Stencil slices (lpr == 1 only): where every row of a slice has its entries
-// at columns row + o_k for one ascending list of offsets o_0 < o_1 < ...
-// shared by the slice (a grid stencil away from the grid's boundaries), the
-// rows are stored with an explicit zero at each offset they lack, and
-// doff[sptr[s] / 64 + k] = o_k.  A wavefront then takes column row + o_k
-// from one scalar load per entry position instead of a vector load of col.
-// doff[sptr[s] / 64] == kIrregularSlice marks a slice read through col (a
-// last kIrregularSlice closes the array; slices of width 0 have no entry).  col
-// stays complete for every slice (col = row + o_k in stencil slices).  A zero
-// added to a row sum started at +0 leaves it unchanged, so both forms give
-// the same sums.
+// Stencil slices (lpr == 1 only): the rows of a slice are stored on the
+// ascending union o_0 < o_1 < ... of their offsets col - row (a grid stencil:
+// the same few offsets in every row), with an explicit zero at each offset a
+// row lacks, and doff[sptr[s] / 64 + k] = o_k (positions past the union
+// repeat its last offset).  A wavefront takes entry k's column as row + o_k,
+// clamped into [0, n_cols) (the positions that need the clamp hold zeros),
+// from one wavefront-uniform load per position instead of a per-lane load of
+// col.  stencil == 2: every slice is a stencil slice; stencil == 1:
+// doff[sptr[s] / 64] == kIrregularSlice marks the slices read through col (a
+// last kIrregularSlice closes the array; slices of width 0 have no entry).
+// col stays complete for every slice (the clamped row + o_k in stencil
+// slices).  A zero added to a row sum started at +0 leaves it unchanged, so
+// both forms give the same sums.
 constexpr int kIrregularSlice = -2147483647 - 1;
 
 template <typename T>
@@ -48,6 +50,7 @@ struct Sell {
   const int* col = nullptr;
   const T* val = nullptr;
   const int* doff = nullptr;  // stencil offsets, or nullptr: every slice reads col
+  int stencil = 0;            // 0: no stencil slices, 1: some, 2: all
   int n_rows = 0;
   int n_cols = 0;
   int lpr = 1;

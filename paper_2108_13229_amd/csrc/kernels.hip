@@ -96,19 +96,27 @@ __device__ __forceinline__ TM sell_row(const Sell<TM>& A, int e, int cnt, int st
   return acc;
 }
 
+// Read-only data that no kernel writes while it runs (slice pointers,
+// stencil offsets): read through the constant address space, a
+// wavefront-uniform address becomes a scalar load.
+typedef const __attribute__((address_space(4))) int* const_ints;
+
+__device__ __forceinline__ const_ints as_const(const int* p) { return (const_ints)p; }
+
 // The same sum over a stencil slice (see Sell): entry k of the row sits at
-// column row + o[k], o the slice's offsets (wavefront-uniform, so scalar
-// loads), and only the values are loaded per lane.  The entries are added
-// in the same order as by sell_row.
+// column row + o[k] clamped into [0, n_cols), o the slice's offsets (the
+// same address in every lane), and only the values are loaded per lane.
+// The entries are added in the same order as by sell_row.
 template <int M, bool NT, typename TM, typename F>
-__device__ __forceinline__ void stencil_chunk(const Sell<TM>& A, int e, const int* o, int row,
+__device__ __forceinline__ void stencil_chunk(const Sell<TM>& A, int e, const_ints o, int row,
                                               F f, TM& acc) {
   TM v[M];
   int c[M];
+  const int last = A.n_cols - 1;
 #pragma unroll
   for (int i = 0; i < M; ++i) {
     v[i] = load_hint<NT>(&A.val[e + i * 64]);
-    c[i] = row + o[i];
+    c[i] = min(max(row + o[i], 0), last);
   }
   TM x[M];
 #pragma unroll
@@ -118,7 +126,7 @@ __device__ __forceinline__ void stencil_chunk(const Sell<TM>& A, int e, const in
 }
 
 template <int M, bool NT, typename TM, typename F>
-__device__ __forceinline__ void stencil_tail(const Sell<TM>& A, int e, int cnt, const int* o,
+__device__ __forceinline__ void stencil_tail(const Sell<TM>& A, int e, int cnt, const_ints o,
                                              int row, F f, TM& acc) {
   if constexpr (M > 0) {
     if (cnt == M) stencil_chunk<M, NT>(A, e, o, row, f, acc);
@@ -127,7 +135,7 @@ __device__ __forceinline__ void stencil_tail(const Sell<TM>& A, int e, int cnt, 
 }
 
 template <int K, bool NT = false, typename TM, typename F>
-__device__ __forceinline__ TM stencil_row(const Sell<TM>& A, int e, int cnt, const int* o,
+__device__ __forceinline__ TM stencil_row(const Sell<TM>& A, int e, int cnt, const_ints o,
                                           int row, F f) {
   TM acc = 0;
   for (; cnt >= K; cnt -= K, e += K * 64, o += K) stencil_chunk<K, NT>(A, e, o, row, f, acc);
@@ -139,9 +147,10 @@ __device__ __forceinline__ TM stencil_row(const Sell<TM>& A, int e, int cnt, con
 // multiple of 64), or nullptr if the slice is read through col.  Callers
 // give every wavefront one slice, so sbase is uniform.
 template <typename TM>
-__device__ __forceinline__ const int* stencil_of(const Sell<TM>& A, int sbase) {
-  if (!A.doff) return nullptr;
-  const int* o = A.doff + (sbase >> 6);
+__device__ __forceinline__ const_ints stencil_of(const Sell<TM>& A, int sbase) {
+  if (!A.stencil) return nullptr;
+  const_ints o = as_const(A.doff) + (sbase >> 6);
+  if (A.stencil == 2) return o;
   return o[0] == kIrregularSlice ? nullptr : o;
 }
 
@@ -152,10 +161,10 @@ constexpr int kRowChunk = 6;   // entries of a SELL-64 row loaded at once
 template <int K = kRowChunk, bool NT = false, typename TM, typename TX>
 __device__ __forceinline__ TM sell_dot(const Sell<TM>& A, const TX* __restrict__ x, int row) {
   const int s = __builtin_amdgcn_readfirstlane(row >> 6);
-  const int sbase = A.sptr[s];
-  const int cnt = (A.sptr[s + 1] - sbase) >> 6;
+  const int sbase = as_const(A.sptr)[s];
+  const int cnt = (as_const(A.sptr)[s + 1] - sbase) >> 6;
   const auto f = [&](int c) { return (TM)x[c]; };
-  if (const int* o = stencil_of(A, sbase)) return stencil_row<K, NT>(A, sbase + (row & 63), cnt, o, row, f);
+  if (const_ints o = stencil_of(A, sbase)) return stencil_row<K, NT>(A, sbase + (row & 63), cnt, o, row, f);
   return sell_row<K, NT>(A, sbase + (row & 63), cnt, 64, f);
 }
 
@@ -243,11 +252,11 @@ __device__ __forceinline__ TM row_sum(const Sell<TM>& A, int row, int sub, F f) 
     beg = sl * (C * A.width);
     end = beg + C * A.width;
   } else {
-    beg = A.sptr[sl];
-    end = A.sptr[sl + 1];
+    beg = as_const(A.sptr)[sl];
+    end = as_const(A.sptr)[sl + 1];
   }
   if constexpr (LPR == 1) {
-    if (const int* o = stencil_of(A, beg)) return stencil_row<kRowChunk>(A, beg + r, (end - beg) >> 6, o, row, f);
+    if (const_ints o = stencil_of(A, beg)) return stencil_row<kRowChunk>(A, beg + r, (end - beg) >> 6, o, row, f);
   }
   const int e0 = beg + sub * C + r;
   TM acc = sell_row<LPR == 1 ? kRowChunk : 4>(A, e0, (end - e0 + 63) >> 6, 64, f);

@@ -101,11 +101,9 @@ static int lanes_per_row(const HostCSR& A, bool allow_csr, int force_lpr) {
 }
 
 // Offsets of a stencil slice (see Sell): the ascending union of col - row
-// over the slice's rows, or an empty list when the slice is irregular (a row
-// with repeated columns, more offsets than the slice width w, or a column
-// row + o outside [0, n_cols) for one of its 64 rows, phantom rows past n
-// included).
-static std::vector<int> stencil_offsets(const HostCSR& A, int64_t sl, int64_t w) {
+// over the slice's rows, or an empty list when a row repeats a column or the
+// slice has no entries.
+static std::vector<int> stencil_offsets(const HostCSR& A, int64_t sl) {
   const int64_t n = A.n_rows, r0 = sl * 64, r1 = std::min(n, r0 + 64);
   std::vector<int64_t> o;
   for (int64_t r = r0; r < r1; ++r) {
@@ -116,10 +114,13 @@ static std::vector<int> stencil_offsets(const HostCSR& A, int64_t sl, int64_t w)
   }
   std::sort(o.begin(), o.end());
   o.erase(std::unique(o.begin(), o.end()), o.end());
-  if (o.empty() || (int64_t)o.size() > w) return {};
-  if (r0 + o.front() < 0 || r0 + 63 + o.back() >= A.n_cols) return {};
   return std::vector<int>(o.begin(), o.end());
 }
+
+// A stencil slice may be widened beyond its longest row by this many
+// positions (zeros) when its rows' offsets differ (layouts with per-slice
+// widths only).
+constexpr int64_t kStencilWiden = 8;
 
 // SELL-C layout on the host: slices of C = 64 / lpr rows, entry k of row r of
 // slice s at sptr[s] + C k + (r - C s).  A slice's width is its longest row
@@ -128,7 +129,9 @@ static std::vector<int> stencil_offsets(const HostCSR& A, int64_t sl, int64_t w)
 // picks more lanes for matrices with few or long rows.  Hierarchy matrices
 // whose slices pad to one common width at most 30 % larger get that width,
 // which spares the kernels the slice pointer load.  Stencil slices (lpr == 1,
-// see Sell) are used where they hold at least half of the entries.
+// see Sell) are used where they hold at least half of the entries; with
+// per-slice widths a slice whose offsets outnumber its longest row by at most
+// kStencilWiden is widened to hold them.
 template <typename T>
 HostSell<T> build_sell(const HostCSR& A, bool allow_csr, int force_lpr, bool stencil) {
   HostSell<T> h;
@@ -152,6 +155,31 @@ HostSell<T> build_sell(const HostCSR& A, bool allow_csr, int force_lpr, bool ste
     for (auto& w : width) w = wmax;
     tot = C * ns * wmax;
   }
+  // stencil slices: offsets per slice (empty: the slice reads col)
+  std::vector<std::vector<int>> offs;
+  if (stencil && lpr == 1) {
+    offs.resize((size_t)ns);
+    parallel_ranges(0, ns, [&](int64_t s0, int64_t s1) {
+      for (int64_t sl = s0; sl < s1; ++sl) {
+        offs[sl] = stencil_offsets(A, sl);
+        const int64_t u = (int64_t)offs[sl].size();
+        const int64_t cap = uniform ? wmax : width[sl] + kStencilWiden;
+        if (u > cap) offs[sl].clear();
+      }
+    });
+    int64_t covered = 0;
+    for (int64_t sl = 0; sl < ns; ++sl)
+      if (!offs[sl].empty()) covered += A.rowptr[std::min(n, sl * 64 + 64)] - A.rowptr[sl * 64];
+    if (covered == 0 || 2 * covered < A.nnz()) {
+      offs.clear();
+    } else if (!uniform) {
+      tot = 0;
+      for (int64_t sl = 0; sl < ns; ++sl) {
+        width[sl] = std::max<int64_t>(width[sl], (int64_t)offs[sl].size());
+        tot += 64 * width[sl];
+      }
+    }
+  }
   if (tot >= ((int64_t)1 << 31)) throw Error(SD_E_INVALID, "matrix too large for int32 SELL");
   h.n_rows = n;
   h.n_cols = A.n_cols;
@@ -165,17 +193,6 @@ HostSell<T> build_sell(const HostCSR& A, bool allow_csr, int force_lpr, bool ste
   for (int64_t sl = 0; sl < ns; ++sl) sptr[sl + 1] = (int)(sptr[sl] + C * width[sl]);
   col.assign((size_t)tot, 0);
   val.assign((size_t)tot, (T)0);
-  std::vector<std::vector<int>> offs;
-  if (stencil && lpr == 1) {
-    offs.resize((size_t)ns);
-    parallel_ranges(0, ns, [&](int64_t s0, int64_t s1) {
-      for (int64_t sl = s0; sl < s1; ++sl) offs[sl] = stencil_offsets(A, sl, width[sl]);
-    });
-    int64_t covered = 0;
-    for (int64_t sl = 0; sl < ns; ++sl)
-      if (!offs[sl].empty()) covered += A.rowptr[std::min(n, sl * 64 + 64)] - A.rowptr[sl * 64];
-    if (covered == 0 || 2 * covered < A.nnz()) offs.clear();
-  }
   std::vector<int>& doff = h.doff;
   h.idx = A.nnz();
   if (!offs.empty()) {
@@ -185,12 +202,14 @@ HostSell<T> build_sell(const HostCSR& A, bool allow_csr, int force_lpr, bool ste
     doff.assign((size_t)(tot / 64 + 1), 0);
     doff.back() = kIrregularSlice;
     h.idx = (int64_t)doff.size();
+    h.stencil = 2;
     for (int64_t sl = 0; sl < ns; ++sl) {
       const int64_t b = sptr[sl] / 64, w = width[sl];
       const std::vector<int>& o = offs[sl];
       if (w == 0) continue;
       if (o.empty()) {
         doff[b] = kIrregularSlice;
+        h.stencil = 1;
         h.idx += A.rowptr[std::min(n, sl * 64 + 64)] - A.rowptr[sl * 64];
       } else {
         // positions past the slice's offsets repeat the last one (zeros)
@@ -209,7 +228,9 @@ HostSell<T> build_sell(const HostCSR& A, bool allow_csr, int force_lpr, bool ste
           const int64_t end = r < n ? A.rowptr[r + 1] : 0;
           for (int64_t k = 0; k < w; ++k) {
             const int64_t p = sptr[sl] + 64 * k + ri;
-            col[p] = (int)(r + o[k]);
+            // the kernels clamp the column into [0, n_cols): positions where
+            // row + o_k falls outside hold zeros
+            col[p] = (int)std::min<int64_t>(std::max<int64_t>(r + o[k], 0), A.n_cols - 1);
             const bool here = e < end && (int64_t)A.col[e] - r == o[k] &&
                               (k == 0 || o[k] != o[k - 1]);
             val[p] = here ? (T)A.val[e++] : (T)0;
@@ -254,6 +275,7 @@ Sell<T> upload_sell(const HostCSR& A, DeviceMem& mem, hipStream_t s, bool allow_
   d.width = h.width;
   d.nnz = h.nnz;
   d.idx = h.idx;
+  d.stencil = h.stencil;
   int* dp = mem.array<int>(std::max<size_t>(h.sptr.size(), 1));
   int* dcol = mem.array<int>(std::max<size_t>(h.col.size(), 1));
   T* dval = mem.array<T>(std::max<size_t>(h.val.size(), 1));

@@ -235,7 +235,7 @@ constexpr int kUzawaPowerIters = 30;
 template <typename T>
 struct HostSell {
   int64_t n_rows = 0, n_cols = 0, nnz = 0, idx = 0;
-  int lpr = 1, width = 0;
+  int lpr = 1, width = 0, stencil = 0;
   std::vector<int> sptr, col, doff;
   std::vector<T> val;
 };

@@ -127,7 +127,7 @@ class SolverOpts(C.Structure):
 
 
 class SellInfo(C.Structure):
-    _fields_ = [("lpr", C.c_int), ("width", C.c_int), ("n_rows", C.c_int64),
+    _fields_ = [("lpr", C.c_int), ("width", C.c_int), ("stencil", C.c_int), ("n_rows", C.c_int64),
                 ("n_cols", C.c_int64), ("nnz", C.c_int64), ("idx", C.c_int64),
                 ("n_ptr", C.c_int64), ("n_entries", C.c_int64), ("n_doff", C.c_int64),
                 ("sptr", C.POINTER(C.c_int32)), ("col", C.POINTER(C.c_int32)),
@@ -690,7 +690,8 @@ def sell_layout(rowptr, col, val, n_cols: int, allow_csr: bool = False, stencil:
         _check(lib().sd_sell_view(h, C.byref(info)))
         def arr(ptr, n, dt):
             return np.ctypeslib.as_array(ptr, (n,)).astype(dt, copy=True) if n else np.zeros(0, dt)
-        return dict(lpr=info.lpr, width=info.width, nnz=info.nnz, idx=info.idx,
+        return dict(lpr=info.lpr, width=info.width, stencil=info.stencil, nnz=info.nnz,
+                    idx=info.idx,
                     sptr=arr(info.sptr, info.n_ptr, np.int64),
                     col=arr(info.col, info.n_entries, np.int64),
                     val=arr(info.val, info.n_entries, np.float64),
