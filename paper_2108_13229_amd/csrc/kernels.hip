@@ -1038,8 +1038,11 @@ __device__ void arn_column(int j, int update, const double* sums, const double* 
 
 // Row work of the update kernel: v_j = inv u_j - V (inv a), u_{j+1} =
 // w - V (b - t a) - t u_j.  No dot products here, so the layout is one row
-// per lane (two rows per thread in flight), the coefficients broadcast from
-// LDS, and each row's sums run over the basis in ascending order.
+// per lane, four rows per thread (rows kGsThreads apart), the coefficients
+// broadcast from LDS, and each row's sums run over the basis in ascending
+// order.  The basis loads are unconditional (a row past the block reloads
+// the thread's first row, and its sums are dropped), so the four rows' loads
+// of four basis vectors are in flight together.
 __device__ __forceinline__ void arn_rows(const double* __restrict__ W, double* __restrict__ V,
                                          int64_t ldv, int n, int j, int rpb, int block,
                                          const double* cf, double inv, double tt) {
@@ -1048,32 +1051,40 @@ __device__ __forceinline__ void arn_rows(const double* __restrict__ W, double* _
   double* un = V + (size_t)(j + 1) * ldv;
   const int r0 = block * rpb;
   const int r1 = min(r0 + rpb, n);
-  for (int ra = r0 + t; ra < r1; ra += 2 * kGsThreads) {
-    const int rb = ra + kGsThreads;
-    const bool hb = rb < r1;
-    double p1a = 0.0, p2a = 0.0, p1b = 0.0, p2b = 0.0;
+  for (int r = r0 + t; r < r1; r += 4 * kGsThreads) {
+    int rr[4];
+    bool ok[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      ok[q] = r + q * kGsThreads < r1;
+      rr[q] = ok[q] ? r + q * kGsThreads : r;   // rows past the block reload row r
+    }
+    double p1[4] = {0.0, 0.0, 0.0, 0.0}, p2[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
     for (int k = 0; k < j; ++k) {
       const double* vk = V + (size_t)k * ldv;
       // streamed basis: non-temporal, as in the projection
-      const double xa = __builtin_nontemporal_load(&vk[ra]);
-      const double xb = hb ? __builtin_nontemporal_load(&vk[rb]) : 0.0;
+      double x[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x[q] = __builtin_nontemporal_load(&vk[rr[q]]);
       const double ca = cf[k], cb = cf[kMaxBasis + k];
-      p1a += ca * xa;
-      p2a += cb * xa;
-      p1b += ca * xb;
-      p2b += cb * xb;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        p1[q] += ca * x[q];
+        p2[q] += cb * x[q];
+      }
     }
     // u_j and w are read for the last time and v_j is next read as part of
     // the streamed basis: all non-temporal; u_{j+1}, which the
     // preconditioner reads next, is stored normally
-    const double ua = __builtin_nontemporal_load(&uj[ra]);
-    __builtin_nontemporal_store(inv * ua - p1a, &uj[ra]);
-    un[ra] = __builtin_nontemporal_load(&W[ra]) - p2a - tt * ua;
-    if (hb) {
-      const double ub = __builtin_nontemporal_load(&uj[rb]);
-      __builtin_nontemporal_store(inv * ub - p1b, &uj[rb]);
-      un[rb] = __builtin_nontemporal_load(&W[rb]) - p2b - tt * ub;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (ok[q]) {
+        const int rq = rr[q];
+        const double u = __builtin_nontemporal_load(&uj[rq]);
+        __builtin_nontemporal_store(inv * u - p1[q], &uj[rq]);
+        un[rq] = __builtin_nontemporal_load(&W[rq]) - p2[q] - tt * u;
+      }
     }
   }
 }

@@ -87,16 +87,17 @@ void pinned_release(void* p, size_t bytes, bool mapped) {
 }
 
 // -------------------------------------------------------------------- SELL
-// Device format choice: SELL-64 for long matrices with short rows; CSR with
-// 4, 8 or 16 lanes per row for short matrices or long rows (coarse AMG
-// levels and transfer operators), when the kernels that use it allow.
+// Device format choice: SELL-64 for long matrices (at least 65,536 rows)
+// with at most 32 entries per row on average; CSR with 4, 8 or 16 lanes per
+// row for short matrices or long rows (coarse AMG levels and transfer
+// operators), when the kernels that use it allow.
 [[noreturn]] void throw_launch(const char* what) { throw Error(SD_E_INVALID, what); }
 
 static int lanes_per_row(const HostCSR& A, bool allow_csr, int force_lpr) {
   if (force_lpr > 0) return force_lpr;
   if (!allow_csr || A.n_rows == 0) return 1;
   const double avg = (double)A.nnz() / (double)A.n_rows;
-  if (avg <= 16.0 && A.n_rows >= 65536) return 1;
+  if (avg <= 32.0 && A.n_rows >= 65536) return 1;
   return avg <= 16.0 ? 4 : (avg <= 48.0 ? 8 : (avg <= 96.0 ? 16 : (avg <= 192.0 ? 32 : 64)));
 }
 
