@@ -140,32 +140,43 @@ Graph symmetric_strength(const HostCSR& A, const std::vector<uint8_t>& m) {
   });
 }
 
-Graph square(const Graph& S) {
-  const int64_t n = (int64_t)S.ptr.size() - 1;
-  return build_graph(n, [&](int64_t i, std::vector<int32_t>& v) {
-    for (int64_t k = S.ptr[i]; k < S.ptr[i + 1]; ++k) {
-      const int32_t j = S.adj[k];
-      v.push_back(j);
-      for (int64_t l = S.ptr[j]; l < S.ptr[j + 1]; ++l) v.push_back(S.adj[l]);
-    }
-    std::sort(v.begin(), v.end());
-    v.erase(std::unique(v.begin(), v.end()), v.end());
-    v.erase(std::remove(v.begin(), v.end(), (int32_t)i), v.end());
-  });
-}
-
-std::vector<int8_t> luby_mis(const Graph& G, int level) {
+// Synchronous Luby rounds for a maximal set of nodes at pairwise distance
+// greater than dist (1 or 2) in the symmetric graph G: in a round every
+// undecided node whose key exceeds the keys of all undecided nodes within
+// dist becomes a root, then every undecided node within dist of a new root
+// leaves.  Every decision reads the state at the round's start, so the row
+// ranges of a phase run on threads.  For dist = 2 the two-hop neighbourhoods
+// are never formed: with top[v] the largest undecided key of v's closed
+// neighbourhood, node i (undecided) beats everything within two hops iff it
+// beats its undecided neighbours and top[j] <= key[i] for each neighbour j;
+// and i is within two hops of a new root iff a neighbour j is one or has one
+// as a neighbour.
+std::vector<int8_t> luby_mis(const Graph& G, int level, int dist) {
   const int64_t n = (int64_t)G.ptr.size() - 1;
   const uint32_t seed = (uint32_t)(0x9E3779B9ull * (uint64_t)(level + 1));
   std::vector<uint64_t> key((size_t)n);
   for (int64_t i = 0; i < n; ++i)
     key[i] = ((uint64_t)fmix32((uint32_t)i ^ seed) << 32) | (uint64_t)i;
   std::vector<int8_t> state((size_t)n, UND);
-  std::vector<uint8_t> new_root((size_t)n, 0);
+  std::vector<uint8_t> new_root((size_t)n, 0), near((size_t)n, 0);
+  std::vector<uint64_t> top(dist == 2 ? (size_t)n : 0, 0);
   int64_t undecided = n;
-  // synchronous rounds: every decision reads the state at the round's start,
-  // so the row ranges of a phase can run on threads
   while (undecided > 0) {
+    if (dist == 2) {
+      // top[v] = max undecided key over v and its neighbours (0: none; every
+      // key is positive: fmix32 maps only 0 to 0, and i ^ seed = 0 leaves the
+      // index i = seed > 0 in the low half)
+      parallel_rows(0, n, [&](int64_t r0, int64_t r1) {
+        for (int64_t v = r0; v < r1; ++v) {
+          uint64_t t = state[v] == UND ? key[v] : 0;
+          for (int64_t k = G.ptr[v]; k < G.ptr[v + 1]; ++k) {
+            const int32_t u = G.adj[k];
+            if (state[u] == UND && key[u] > t) t = key[u];
+          }
+          top[v] = t;
+        }
+      });
+    }
     parallel_rows(0, n, [&](int64_t r0, int64_t r1) {
       for (int64_t i = r0; i < r1; ++i) {
         new_root[i] = 0;
@@ -173,18 +184,28 @@ std::vector<int8_t> luby_mis(const Graph& G, int level) {
         bool lost = false;
         for (int64_t k = G.ptr[i]; k < G.ptr[i + 1] && !lost; ++k) {
           const int32_t j = G.adj[k];
-          if (state[j] == UND && key[j] > key[i]) lost = true;
+          if (dist == 2 ? top[j] > key[i] : (state[j] == UND && key[j] > key[i])) lost = true;
         }
         new_root[i] = !lost;
       }
     });
     for (int64_t i = 0; i < n; ++i)
       if (new_root[i]) state[i] = ROOT;
+    if (dist == 2) {
+      parallel_rows(0, n, [&](int64_t r0, int64_t r1) {
+        for (int64_t v = r0; v < r1; ++v) {
+          uint8_t f = new_root[v];
+          for (int64_t k = G.ptr[v]; k < G.ptr[v + 1] && !f; ++k) f = new_root[G.adj[k]];
+          near[v] = f;
+        }
+      });
+    }
+    const std::vector<uint8_t>& hit = dist == 2 ? near : new_root;
     parallel_rows(0, n, [&](int64_t r0, int64_t r1) {
       for (int64_t i = r0; i < r1; ++i) {
         if (state[i] != UND) continue;
         for (int64_t k = G.ptr[i]; k < G.ptr[i + 1]; ++k)
-          if (new_root[G.adj[k]]) {
+          if (hit[G.adj[k]]) {
             state[i] = NONROOT;
             break;
           }
@@ -621,7 +642,7 @@ void amg_setup_host(const HostCSR& A0, const std::vector<int32_t>& comp0, bool s
     for (int64_t i = 0; i < n; ++i) d[i] = diag_of(A, i);
     std::vector<uint8_t> strong = strong_mask(A, comp, d, theta);
     Graph S = symmetric_strength(A, strong);
-    std::vector<int8_t> state = o.mis == 1 ? luby_mis(S, lev) : luby_mis(square(S), lev);
+    std::vector<int8_t> state = luby_mis(S, lev, o.mis);
     std::vector<int32_t> agg((size_t)n, -1);
     std::vector<int32_t> roots;
     for (int64_t i = 0; i < n; ++i)

@@ -85,6 +85,7 @@ void sd_solver_opts_default(sd_solver_opts* o) {
   o->pd_alpha_p = -3.0;
   o->pd_alpha_d = 5.0;
   o->stencil_slices = 1;
+  o->fused_restriction = 1;
 }
 
 static int assemble_impl(const sd_grid* grid, const sd_physics* phys, const sd_bcs* bcs,

@@ -102,19 +102,22 @@ static int lanes_per_row(const HostCSR& A, bool allow_csr, int force_lpr) {
 }
 
 // Offsets of a stencil slice (see Sell): the ascending union of col - row
-// over the slice's rows, or an empty list when a row repeats a column or the
-// slice has no entries.
-static std::vector<int> stencil_offsets(const HostCSR& A, int64_t sl) {
+// over the slice's rows, or an empty list when a row repeats a column, the
+// slice has no entries or the union is longer than cap.
+static std::vector<int> stencil_offsets(const HostCSR& A, int64_t sl, int64_t cap) {
   const int64_t n = A.n_rows, r0 = sl * 64, r1 = std::min(n, r0 + 64);
-  std::vector<int64_t> o;
+  std::vector<int64_t> o;                 // distinct offsets, ascending
+  o.reserve((size_t)cap + 1);
   for (int64_t r = r0; r < r1; ++r) {
     for (int64_t e = A.rowptr[r]; e < A.rowptr[r + 1]; ++e) {
       if (e > A.rowptr[r] && A.col[e] <= A.col[e - 1]) return {};
-      o.push_back((int64_t)A.col[e] - r);
+      const int64_t d = (int64_t)A.col[e] - r;
+      auto it = std::lower_bound(o.begin(), o.end(), d);
+      if (it != o.end() && *it == d) continue;
+      if ((int64_t)o.size() == cap) return {};
+      o.insert(it, d);
     }
   }
-  std::sort(o.begin(), o.end());
-  o.erase(std::unique(o.begin(), o.end()), o.end());
   return std::vector<int>(o.begin(), o.end());
 }
 
@@ -161,12 +164,8 @@ HostSell<T> build_sell(const HostCSR& A, bool allow_csr, int force_lpr, bool ste
   if (stencil && lpr == 1) {
     offs.resize((size_t)ns);
     parallel_ranges(0, ns, [&](int64_t s0, int64_t s1) {
-      for (int64_t sl = s0; sl < s1; ++sl) {
-        offs[sl] = stencil_offsets(A, sl);
-        const int64_t u = (int64_t)offs[sl].size();
-        const int64_t cap = uniform ? wmax : width[sl] + kStencilWiden;
-        if (u > cap) offs[sl].clear();
-      }
+      for (int64_t sl = s0; sl < s1; ++sl)
+        offs[sl] = stencil_offsets(A, sl, uniform ? wmax : width[sl] + kStencilWiden);
     });
     int64_t covered = 0;
     for (int64_t sl = 0; sl < ns; ++sl)
@@ -338,6 +337,8 @@ void Solver::setup_host(HostProblem* p, const sd_solver_opts* o) {
   if (so.amg != SD_AMG_PLAIN && so.amg != SD_AMG_SMOOTHED) throw Error(SD_E_INVALID, "amg");
   if (so.stencil_slices != 0 && so.stencil_slices != 1)
     throw Error(SD_E_INVALID, "stencil_slices must be 0 or 1");
+  if (so.fused_restriction != 0 && so.fused_restriction != 1)
+    throw Error(SD_E_INVALID, "fused_restriction must be 0 or 1");
   if (so.darcy != SD_DARCY_AMG && so.darcy != SD_DARCY_ILU0) throw Error(SD_E_INVALID, "darcy");
   opts.amg.theta = so.theta;
   opts.amg.omega = so.omega;
@@ -573,7 +574,8 @@ constexpr int64_t kFuseMaxRowWidth = 64;
 
 template <typename T>
 void upload_hierarchy(const HostHierarchy& h, DevHierarchy<T>& d, double omega, int nu_pre,
-                      int nu_post, bool stencil, DeviceMem& mem, hipStream_t s) {
+                      int nu_post, bool stencil, bool fuse_restriction, DeviceMem& mem,
+                      hipStream_t s) {
   d.lev.resize(h.levels.size());
   for (size_t l = 0; l < h.levels.size(); ++l) {
     const HostLevel& H = h.levels[l];
@@ -592,7 +594,7 @@ void upload_hierarchy(const HostHierarchy& h, DevHierarchy<T>& d, double omega, 
     if (l + 1 < h.levels.size()) {
       const int64_t nnzA = H.A.nnz();
       HostCSR G, F, RA;
-      D.fuse_pre = nu_pre == 2 && (l > 0 || H.A.n_rows < kFusePreRows) &&
+      D.fuse_pre = fuse_restriction && nu_pre == 2 && (l > 0 || H.A.n_rows < kFusePreRows) &&
                    nnzA <= kFuseMaxRowWidth * H.A.n_rows;
       // R A serves both G and Q = [R | -R A] (nnz(Q) = nnz(R) + nnz(R A))
       if (l > 0 || D.fuse_pre) RA = sparse_product(H.R, H.A);
@@ -682,7 +684,8 @@ class PrecImpl : public PrecBase {
     for (int b = 0; b < 3; ++b)
       if (!S.hh[b].levels.empty())
         upload_hierarchy<T>(S.hh[b], H[b], S.opts.amg.omega, nu_pre, nu_post,
-                            S.opts.o.stencil_slices != 0, mem, s);
+                            S.opts.o.stencil_slices != 0, S.opts.o.fused_restriction != 0, mem,
+                            s);
     if (S.ilu.n > 0) ilu = upload_ilu<T>(S.ilu, mem, s);
     if (cc) {
       tp = mem.array<T>((size_t)(S.off[3] - S.off[2]));

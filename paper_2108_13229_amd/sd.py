@@ -123,7 +123,8 @@ class SolverOpts(C.Structure):
                 ("nu_post", C.c_int), ("coarse_max", C.c_int), ("max_levels", C.c_int),
                 ("darcy", C.c_int), ("pd_m_init", C.c_int), ("pd_m_min", C.c_int),
                 ("pd_m_step", C.c_int), ("pd_alpha_p", C.c_double),
-                ("pd_alpha_d", C.c_double), ("stencil_slices", C.c_int)]
+                ("pd_alpha_d", C.c_double), ("stencil_slices", C.c_int),
+                ("fused_restriction", C.c_int)]
 
 
 class SellInfo(C.Structure):

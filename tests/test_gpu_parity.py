@@ -100,6 +100,34 @@ def test_vcycle_parity_other_sweep_counts(nu_pre, nu_post):
 
 
 @pytest.mark.parametrize("name", ["mms32", "channel96", "channel_ragged"])
+def test_vcycle_parity_without_fused_restriction(name):
+    """fused_restriction = 0: the levels that would fuse the two
+    pre-sweeps with the restriction (G = R (I - A M2)) run them as separate
+    passes; the V-cycle and one FGMRES solve still match the oracle."""
+    p = SMALL[name]()
+    print("case unfused restriction", name, flush=True)
+    a = assemble(p)
+    M = precond.build(p, a, "BGS")
+    P, S = _setup(p, fused_restriction=0)
+    rng = np.random.default_rng(17)
+    for blk, h in [(0, M.hV), (1, M.hD)]:
+        n = h.levels[0].A.shape[0]
+        b = rng.standard_normal(n)
+        x = _host(S.apply_vcycle(blk, _dev(b)))
+        ref = amg.vcycle(h, b)
+        assert np.linalg.norm(x - ref) <= 1e-12 * np.linalg.norm(ref)
+        assert np.max(np.abs(x - ref)) <= 1e-11 * np.max(np.abs(ref))
+    ref = krylov.fgmres(a.A, a.b, M, tol=1e-10, m=30)
+    S2 = sd.Solver(P, precond="BGS", tol=1e-10, restart=30, fused_restriction=0)
+    x, st, rc = S2.solve()
+    x = _host(x)
+    assert rc == sd.SD_OK and abs(st["iters"] - ref.iters) <= 1
+    assert np.linalg.norm(x - ref.x) <= 1e-8 * np.linalg.norm(ref.x)
+    with pytest.raises(sd.SDError):
+        sd.Solver(P, fused_restriction=2)
+
+
+@pytest.mark.parametrize("name", ["mms32", "channel96", "channel_ragged"])
 @pytest.mark.parametrize("variant,schur", [("BGS", "mass"), ("BJ", "mass"), ("BGS", "identity")])
 def test_block_preconditioner_parity(name, variant, schur):
     p = SMALL[name]()
