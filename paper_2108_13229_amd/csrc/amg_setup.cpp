@@ -33,6 +33,8 @@ namespace sd {
 
 namespace {
 
+thread_local int tl_host_threads = 0;   // set_host_threads of this thread
+
 // Run f(begin, end) over [r0, r1) split into contiguous chunks on threads,
 // at least `grain` rows per thread (small ranges run inline: thread start-up
 // would cost more than the rows, and concurrent setups share the host).
@@ -40,7 +42,8 @@ template <typename F>
 void parallel_rows(int64_t r0, int64_t r1, F&& f, int64_t grain = 8192) {
   const int64_t cnt = r1 - r0;
   if (cnt <= 0) return;
-  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const unsigned cap = tl_host_threads > 0 ? (unsigned)tl_host_threads : 16u;
+  const unsigned hw = std::max(1u, std::min(cap, std::thread::hardware_concurrency()));
   const int64_t nt = std::min<int64_t>(hw, cnt / std::max<int64_t>(grain, 1));
   if (nt <= 1) {
     f(r0, r1);
@@ -590,6 +593,8 @@ HostCSR smoothed_correction(const HostCSR& A, const HostCSR& P, const HostCSR& A
 void parallel_ranges(int64_t r0, int64_t r1, const std::function<void(int64_t, int64_t)>& f) {
   parallel_rows(r0, r1, f);
 }
+
+void set_host_threads(int n) { tl_host_threads = std::max(0, n); }
 
 HostCSR residual_restriction(const HostCSR& A, const HostCSR& R) {
   return residual_restriction(A, R, spgemm(R, A));

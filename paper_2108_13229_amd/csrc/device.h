@@ -40,7 +40,8 @@ constexpr int kIluMaxLevels = 4096; // ILU(0): levels per substitution
 // doff[sptr[s] / 64] == kIrregularSlice marks the slices read through col (a
 // last kIrregularSlice closes the array; slices of width 0 have no entry).
 // col stays complete for every slice (the clamped row + o_k in stencil
-// slices).  A zero added to a row sum started at +0 leaves it unchanged, so
+// slices) except with stencil == 2, where nothing reads it and it is not
+// uploaded (col = nullptr).  A zero added to a row sum started at +0 leaves it unchanged, so
 // both forms give the same sums.
 constexpr int kIrregularSlice = -2147483647 - 1;
 

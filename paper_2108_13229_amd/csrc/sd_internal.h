@@ -125,8 +125,14 @@ struct HostHierarchy {
 void amg_setup_host(const HostCSR& A, const std::vector<int32_t>& comp,
                     bool singular, const AMGOpts& o, HostHierarchy& h);
 
-// f(a, b) over contiguous sub-ranges of [r0, r1) on up to 16 threads.
+// f(a, b) over contiguous sub-ranges of [r0, r1) on up to 16 threads (or
+// the calling thread's cap, below).
 void parallel_ranges(int64_t r0, int64_t r1, const std::function<void(int64_t, int64_t)>& f);
+
+// Cap on the threads the host set-up steps started from the calling thread
+// use (0: up to 16).  Threads that prepare several problems at once share
+// the host: each takes a share instead of 16.
+void set_host_threads(int n);
 
 // Q = [R | -R A] (n_c x 2n): the restricted residual R (b - A x) = Q [b; x]
 // in one sparse product, so that a V-cycle level needs no residual vector.

@@ -173,6 +173,7 @@ struct sd_server {
   bool stop = false;
   std::thread sched;
   std::vector<std::thread> prep;
+  int prep_threads = 0;   // host threads per preparation (set_host_threads)
   std::vector<hipStream_t> prep_streams;
   double t0 = 0.0;
   // groups of the shared launches (scheduler thread only)
@@ -413,6 +414,7 @@ void sd_server::retire(Request* r, int status, const std::string& err) {
 
 void sd_server::prep_loop(hipStream_t prep_stream) {
   (void)hipSetDevice(opts.device);
+  sd::set_host_threads(prep_threads);
   for (;;) {
     Request* r = nullptr;
     {
@@ -603,6 +605,10 @@ int sd_server_create(const sd_server_opts* opts, const sd_allocator* allocator,
   // requests runs in parallel
   const int hw = (int)std::max(2u, std::thread::hardware_concurrency());
   const int n_prep = std::max(1, std::min({8, s->opts.max_slots, hw / 2}));
+  // each preparation's set-up steps take a share of the (at most 16) host
+  // threads: eight set-ups on 16 threads each would spend a fifth of their
+  // CPU time starting and joining threads
+  s->prep_threads = std::max(1, std::min(16, hw) / n_prep);
   for (int k = 0; k < n_prep; ++k) {
     hipStream_t ps = nullptr;
     if (hipStreamCreateWithFlags(&ps, hipStreamNonBlocking) != hipSuccess) return SD_E_DEVICE;

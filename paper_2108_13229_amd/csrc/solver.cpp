@@ -277,11 +277,13 @@ Sell<T> upload_sell(const HostCSR& A, DeviceMem& mem, hipStream_t s, bool allow_
   d.idx = h.idx;
   d.stencil = h.stencil;
   int* dp = mem.array<int>(std::max<size_t>(h.sptr.size(), 1));
-  int* dcol = mem.array<int>(std::max<size_t>(h.col.size(), 1));
+  // an all-stencil matrix is never read through col: it stays on the host
+  const bool need_col = h.stencil != 2;
+  int* dcol = need_col ? mem.array<int>(std::max<size_t>(h.col.size(), 1)) : nullptr;
   T* dval = mem.array<T>(std::max<size_t>(h.val.size(), 1));
   if (!h.sptr.empty())
     SD_HIP(hipMemcpyAsync(dp, h.sptr.data(), h.sptr.size() * sizeof(int), hipMemcpyHostToDevice, s));
-  if (!h.col.empty())
+  if (need_col && !h.col.empty())
     SD_HIP(hipMemcpyAsync(dcol, h.col.data(), h.col.size() * sizeof(int), hipMemcpyHostToDevice, s));
   if (!h.val.empty())
     SD_HIP(hipMemcpyAsync(dval, h.val.data(), h.val.size() * sizeof(T), hipMemcpyHostToDevice, s));
