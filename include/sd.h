@@ -381,6 +381,13 @@ int sd_apply_preconditioner(sd_solver* s, const double* d_r, double* d_z,
 int sd_apply_vcycle(sd_solver* s, int block, const double* d_b, double* d_x,
                     int64_t n, void* hip_stream);
 
+/* Host threads that the set-up steps (assembly, AMG set-up, layout builds)
+ * started from the calling thread may use: n >= 1 caps them, 0 restores the
+ * default (up to 16).  Applies to the calling thread only; a caller running
+ * several set-ups at once gives each its share of the host.  Results do not
+ * depend on the thread count.  SD_E_INVALID for n < 0. */
+int sd_set_host_threads(int n);
+
 /* Row blocking of the Gram-Schmidt projection kernel for n unknowns: rows
  * per workgroup, workgroups, and dynamic LDS bytes per workgroup (the block's
  * rows of w and u_j in FP64).  SD_E_INVALID for n < 1 or n above the limit

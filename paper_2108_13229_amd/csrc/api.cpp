@@ -365,6 +365,12 @@ int sd_apply_vcycle(sd_solver* s, int block, const double* d_b, double* d_x, int
   });
 }
 
+int sd_set_host_threads(int n) {
+  if (n < 0) return fail(SD_E_INVALID, "n must be >= 0");
+  sd::set_host_threads(n);
+  return SD_OK;
+}
+
 int sd_arnoldi_layout(int64_t n, int* rows_per_block, int* blocks, size_t* lds_bytes) {
   if (n < 1 || n > sd::kMaxUnknowns)
     return fail(SD_E_INVALID, "n must be in 1.." + std::to_string(sd::kMaxUnknowns));

@@ -228,6 +228,7 @@ SIGNATURES = {
                                 C.POINTER(_P)]),
     "sd_sell_view": (C.c_int, [_P, C.POINTER(SellInfo)]),
     "sd_sell_destroy": (None, [_P]),
+    "sd_set_host_threads": (C.c_int, [C.c_int]),
     "sd_solver_profile": (C.c_int, [_P, C.c_int]),
     "sd_solver_middle_scale": (C.c_int, [_P, C.POINTER(C.c_double)]),
     "sd_solver_precond_cost": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
@@ -699,6 +700,12 @@ def sell_layout(rowptr, col, val, n_cols: int, allow_csr: bool = False, stencil:
                     doff=arr(info.doff, info.n_doff, np.int64) if info.n_doff else None)
     finally:
         lib().sd_sell_destroy(h)
+
+
+def set_host_threads(n: int):
+    """Cap the host threads of set-up steps started from the calling thread
+    (0: the default, up to 16)."""
+    _check(lib().sd_set_host_threads(int(n)))
 
 
 def arnoldi_layout(n: int):
