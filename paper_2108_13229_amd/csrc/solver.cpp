@@ -93,13 +93,19 @@ void pinned_release(void* p, size_t bytes, bool mapped) {
 // operators), when the kernels that use it allow.
 [[noreturn]] void throw_launch(const char* what) { throw Error(SD_E_INVALID, what); }
 
-static int lanes_per_row(const HostCSR& A, bool allow_csr, int force_lpr) {
+static int lanes_per_row(const HostCSR& A, bool allow_csr, int force_lpr, double sell_max = 32.0) {
   if (force_lpr > 0) return force_lpr;
   if (!allow_csr || A.n_rows == 0) return 1;
   const double avg = (double)A.nnz() / (double)A.n_rows;
-  if (avg <= 32.0 && A.n_rows >= 65536) return 1;
+  if (avg <= sell_max && A.n_rows >= 65536) return 1;
   return avg <= 16.0 ? 4 : (avg <= 48.0 ? 8 : (avg <= 96.0 ? 16 : (avg <= 192.0 ? 32 : 64)));
 }
+
+// Lanes per row of a grid-transfer operator (R, P, Q): their rows gather from
+// scattered aggregates, so SELL-64 pays only up to 16 entries per row (the
+// first coarse velocity restriction of 1024x512, 27 per row: 12.1 us with one
+// lane per row, 10.7 us with 8).
+static int transfer_lanes(const HostCSR& M) { return lanes_per_row(M, true, 0, 16.0); }
 
 // Offsets of a stencil slice (see Sell): the ascending union of col - row
 // over the slice's rows, or an empty list when a row repeats a column, the
@@ -617,13 +623,14 @@ void upload_hierarchy(const HostHierarchy& h, DevHierarchy<T>& d, double omega, 
         D.AW = upload_sell<T>(AW, mem, s, true, D.A.lpr, stencil);
         D.G = upload_sell<T>(G, mem, s, true, 64);
       } else if (l == 0) {
-        D.R = upload_sell<T>(H.R, mem, s, true);
+        D.R = upload_sell<T>(H.R, mem, s, true, transfer_lanes(H.R));
         D.r = mem.array<T>((size_t)D.n);
       } else {
-        D.Q = upload_sell<T>(residual_restriction(H.A, H.R, RA), mem, s, true);
+        const HostCSR Qh = residual_restriction(H.A, H.R, RA);
+        D.Q = upload_sell<T>(Qh, mem, s, true, transfer_lanes(Qh));
       }
       if (D.fuse_post) D.F = upload_sell<T>(F, mem, s, true, D.A.lpr);
-      else D.P = upload_sell<T>(H.P, mem, s, true);
+      else D.P = upload_sell<T>(H.P, mem, s, true, transfer_lanes(H.P));
     }
     SD_HIP(hipStreamSynchronize(s));
   }
