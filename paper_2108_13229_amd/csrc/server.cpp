@@ -551,6 +551,18 @@ void sd_server::sched_loop() {
         msg = e.what();
       }
       if (finished) {
+        // a member that fails leaves its group first: no later replay may
+        // read its buffers once retire frees them
+        if (r->grp) {
+          try {
+            leave_group(r, false, false);
+          } catch (const sd::Error&) {
+            // the device failed: at least no host step touches r again
+            r->grp->mem[(size_t)r->slot] = Member{};
+            r->grp = nullptr;
+            r->slot = -1;
+          }
+        }
         retire(r, code, msg);
         active.erase(active.begin() + (long)i);
         progressed = true;

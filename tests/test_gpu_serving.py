@@ -217,3 +217,40 @@ def test_shared_launches_across_restarts(krylov):
         assert np.array_equal(x.cpu().numpy(), r["x"]) and s1["iters"] == r["stats"]["iters"]
         Sv.close()
         P.close()
+
+
+def test_cancel_while_in_shared_launches():
+    """A request cancelled while its columns run in a group's shared launches
+    leaves the group (its workgroup counts cleared, its stream ordered after
+    the group's last replay) before its memory is freed; the other members
+    still equal their direct solves bit for bit."""
+    probs = [channel_problem(256, 128, seed=70, U=u) for u in (1e-3, 1e-2, 0.1, 0.3)]
+    S = sd.Server(max_slots=4)
+    tickets = [S.submit(p, tol=1e-10, restart=60) for p in probs]
+    victim = tickets[1]
+    t_end = time.time() + 60
+    while S.poll(victim)["state"] == "pending" and time.time() < t_end:
+        time.sleep(0.0005)
+    time.sleep(0.002)
+    S.cancel(victim)
+    res = [S.wait(t, timeout=120) for t in tickets]
+    st = S.batch_stats()
+    for t in tickets:
+        S.release(t)
+    S.close()
+    print("victim", res[1]["state"], res[1]["status"], "batch stats", st, flush=True)
+    assert res[1]["state"] in ("failed", "done")
+    if res[1]["state"] == "failed":
+        assert res[1]["status"] == sd.SD_E_INVALID
+    assert st["max_members"] >= 2
+    for k, (p, r) in enumerate(zip(probs, res)):
+        if k == 1:
+            continue
+        assert r["status"] == sd.SD_OK
+        P = sd.Problem(p)
+        Sv = sd.Solver(P, tol=1e-10, restart=60)
+        x, s1, rc = Sv.solve()
+        torch.cuda.synchronize()
+        assert np.array_equal(x.cpu().numpy(), r["x"]) and s1["iters"] == r["stats"]["iters"]
+        Sv.close()
+        P.close()
