@@ -246,11 +246,13 @@ typedef struct {
                         (a grid stencil) store those offsets once and read no
                         column indices; 0: every slice reads its indices.
                         Results are identical either way.                     */
-  int fused_restriction; /* 1 (default): on AMG levels below 196,608 rows
-                        the two pre-smoothing sweeps and the restriction of
-                        the residual are one pass through
-                        G = R (I - A M2) (M2: the two sweeps from zero),
-                        formed on the host at set-up; 0: separate passes and
+  int fused_restriction; /* 1 (default): on the coarser AMG levels, and on
+                        the finest one below 196,608 rows, the two
+                        pre-smoothing sweeps and the restriction of the
+                        residual are one pass through G = R (I - A M2)
+                        (M2: the two sweeps from zero), formed on the host at
+                        set-up and kept where G has at most 3x the nonzeros
+                        of the operators it replaces; 0: separate passes and
                         no G, a cheaper set-up (a serving request spends
                         about a fifth of its host preparation on G) for a
                         few more launches per V-cycle.                        */
