@@ -11,11 +11,14 @@ Modules
             conditions; block structure of the pv formulation)
   direct    sparse LU reference solve (the plain definition x* = A^-1 b)
   dn        partitioned Dirichlet-Neumann fixed point with Aitken relaxation
-            (Sec. 3, fixed-point problem and stopping rule)
+            or IQN-ILS (Sec. 3, fixed-point problem and stopping rule)
   amg       aggregation AMG setup and V-cycle (Sec. 5 solver setup)
   precond   pressure-velocity block-Jacobi / block-Gauss-Seidel (Sec. 4)
-  krylov    FGMRES(m) with classical Gram-Schmidt twice, BiCGSTAB, and the
-            mixed-precision iterative-refinement driver
+  krylov    FGMRES(m) with classical Gram-Schmidt twice, PD-GMRES (restart
+            lengths from a proportional-derivative controller), BiCGSTAB,
+            and the mixed-precision iterative-refinement driver
+  ilu       ILU(0) of the Darcy block and its triangular solves (Table 2's
+            ILU rows)
   hashing   the 32-bit integer finaliser used for aggregation priorities
   transient backward-Euler steps of the transient free flow (Sec. 2)
   assemble3d the same model and closures on a 3-D box grid
