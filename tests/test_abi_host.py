@@ -330,3 +330,16 @@ def test_arnoldi_row_blocking_stays_within_lds_and_partials():
     for bad in (0, -5, limit + 1):
         with pytest.raises(sd.SDError):
             sd.arnoldi_layout(bad)
+
+
+def test_setup_refuses_more_unknowns_than_the_row_blocking_covers():
+    """A channel of 4096 x 1025 cells per subdomain (16,789,504 unknowns,
+    just above 4096 x 4096): assembly accepts it, the solver set-up refuses
+    it with SD_E_INVALID before any AMG work."""
+    p = channel_problem(4096, 1025, seed=1)
+    P = sd.Problem(p, device=False)
+    assert P.N > 4096 * 4096
+    with pytest.raises(sd.SDError) as e:
+        sd.Solver(P, device=False)
+    assert e.value.code == sd.SD_E_INVALID
+    P.close()
