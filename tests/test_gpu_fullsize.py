@@ -202,3 +202,27 @@ def test_bicgstab_full_size():
         assert np.linalg.norm(x[lo:hi] - ref.x[lo:hi]) <= 1e-6 * np.linalg.norm(ref.x[lo:hi])
     S.close()
     P.close()
+
+
+def test_solve_at_the_size_limit():
+    """2048 x 2048 cells per subdomain: 16,777,216 unknowns, the largest
+    problem one solve takes (the Gram-Schmidt kernels' row blocking).  The
+    mixed solve converges, and its true relative residual, recomputed on the
+    host with the oracle's assembled matrix, meets 1e-8 and agrees with the
+    solver's own FP64 residual."""
+    from sdinputs import channel_problem
+    p = channel_problem(2048, 2048, seed=3)
+    a = assemble(p)
+    assert a.N == 4096 * 4096
+    print("case size limit, N =", a.N, flush=True)
+    P = sd.Problem(p, device=True)
+    S = sd.Solver(P, precond="BGS", schur="mass", tol=1e-8, restart=60, precision="mixed")
+    x, st, rc = S.solve()
+    x = _host(x)
+    print("size limit", st["iters"], st["rel_res"], flush=True)
+    assert rc == sd.SD_OK
+    res = np.linalg.norm(a.b - a.A @ x) / np.linalg.norm(a.b)
+    assert res <= 1e-8
+    assert abs(st["rel_res"] - res) <= 1e-3 * res
+    S.close()
+    P.close()
