@@ -47,7 +47,8 @@ def build(verbose: bool = False) -> str:
               "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     tmp = LIB + ".tmp"
-    _run(["hipcc", "-shared", "--offload-arch=gfx950", *objs, "-o", tmp, "-lpthread"])
+    _run(["hipcc", "-shared", "--offload-arch=gfx950", *objs, "-o", tmp, "-lpthread",
+          "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"])
     os.replace(tmp, LIB)
     if verbose:
         print("built", LIB)

@@ -5,9 +5,16 @@
 #include <memory>
 #include <string>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "handles.h"
 #include "sd.h"
 #include "solver.h"
+
+namespace sd {
+TraceRange::TraceRange(const char* name) { roctxRangePushA(name); }
+TraceRange::~TraceRange() { roctxRangePop(); }
+}  // namespace sd
 
 struct sd_solver {
   std::unique_ptr<sd::Solver> s;

@@ -63,6 +63,7 @@ void RowBuilder::finish() {
 
 void assemble_host(const sd_grid* g, const sd_physics* ph, const sd_bcs* bcs,
                    const double* K, const sd_forcing* f, HostProblem& P) {
+  TraceRange trace("sd: assembly");
   if (!g || !ph || !bcs || !K) throw Error(SD_E_INVALID, "null argument");
   if (g->nz < 0) throw Error(SD_E_INVALID, "nz must be >= 0 (0 = 2-D)");
   if (g->nz > 0) {

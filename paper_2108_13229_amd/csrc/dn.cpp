@@ -223,6 +223,7 @@ void DNSolver::build(const HostProblem& P, const sd_solver_opts* o, const sd_all
 
 int DNSolver::solve(const sd_dn_opts& d, const double* d_b, double* d_x, sd_dn_stats* out,
                     hipStream_t s) {
+  TraceRange trace("sd: partitioned coupling");
   const double t0 = wall_time();
   sd_dn_stats st{};
   // right-hand sides of the subsystems: the assembled ones or slices of d_b

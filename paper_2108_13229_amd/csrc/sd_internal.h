@@ -134,6 +134,18 @@ void parallel_ranges(int64_t r0, int64_t r1, const std::function<void(int64_t, i
 // the host: each takes a share instead of 16.
 void set_host_threads(int n);
 
+// A named host-side phase (assembly, set-up, upload, solve, a request's
+// preparation) as a ROCTx range, which rocprofv3 --marker-trace shows beside
+// the kernels; without a tracing tool attached it costs well under a
+// microsecond.  Pushed and popped on the constructing thread.
+class TraceRange {
+ public:
+  explicit TraceRange(const char* name);
+  ~TraceRange();
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
+
 // Q = [R | -R A] (n_c x 2n): the restricted residual R (b - A x) = Q [b; x]
 // in one sparse product, so that a V-cycle level needs no residual vector.
 // RA: the product R A when the caller has it (the same values as computed

@@ -427,6 +427,7 @@ void sd_server::prep_loop(hipStream_t prep_stream) {
     int code = SD_OK;
     std::string msg;
     try {
+      sd::TraceRange trace("sd: request preparation");
       if (r->cancel) throw sd::Error(SD_E_INVALID, "cancelled");
       r->hp.reset(new sd::HostProblem());
       sd::assemble_host(&r->grid, &r->phys, &r->bcs, r->K.data(), &r->forcing, *r->hp);

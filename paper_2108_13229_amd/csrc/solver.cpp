@@ -316,6 +316,7 @@ static double diag_at(const HostCSR& A, int64_t r) {
 }
 
 void Solver::setup_host(HostProblem* p, const sd_solver_opts* o) {
+  TraceRange trace("sd: set-up (host)");
   const double t0 = wall_time();
   pb = p;
   sd_solver_opts d;
@@ -381,8 +382,12 @@ void Solver::setup_host(HostProblem* p, const sd_solver_opts* o) {
   hh[0] = HostHierarchy();
   hh[1] = HostHierarchy();
   ilu = HostIlu();
-  if (L.off_p > 0) amg_setup_host(Vb, compV, false, opts.amg, hh[0]);
+  if (L.off_p > 0) {
+    TraceRange trace("sd: AMG set-up, velocity block");
+    amg_setup_host(Vb, compV, false, opts.amg, hh[0]);
+  }
   if (L.N > L.off_q) {
+    TraceRange trace("sd: Darcy block set-up");
     if (so.darcy == SD_DARCY_ILU0) ilu0_host(Dt, ilu);
     else amg_setup_host(Dt, compD, false, opts.amg, hh[1]);
   }
@@ -441,6 +446,7 @@ Solver::~Solver() {
 }
 
 void Solver::upload(const sd_allocator* alloc, hipStream_t s) {
+  TraceRange trace("sd: upload");
   const double t0 = wall_time();
   mem.reset(new DeviceMem(alloc, s));
   const bool stencil = opts.o.stencil_slices != 0;
@@ -557,6 +563,7 @@ int pd_next_length(const sd_solver_opts& o, SolveRun& R, int m_cap) {
 }
 
 int Solver::solve(const double* b, double* x, int use_x0, sd_stats* stats, hipStream_t s) {
+  TraceRange trace("sd: solve");
   if (!on_device) throw Error(SD_E_INVALID, "solver was set up without a device");
   if (!x) throw Error(SD_E_INVALID, "x must be a device pointer");
   if (!b) b = b_dev;
