@@ -354,7 +354,9 @@ HostCSR transpose(const HostCSR& P) {
 // then over Y's row k in ascending J.  Structural pattern, zeros kept.  Rows
 // are independent: contiguous row ranges run on threads, each row summed in
 // the same order as a serial loop, so the result does not depend on the
-// thread count.
+// thread count.  The rows per thread follow the work: products with few,
+// long rows (the Galerkin and fused-transfer products on coarse levels) get
+// small row ranges.
 HostCSR spgemm(const HostCSR& X, const HostCSR& Y) {
   struct Part {
     int64_t r0 = 0;
@@ -362,6 +364,11 @@ HostCSR spgemm(const HostCSR& X, const HostCSR& Y) {
     std::vector<int32_t> col;
     std::vector<double> val;
   };
+  int64_t products = 0;
+  for (int64_t k = 0; k < X.nnz(); ++k) products += Y.rowptr[X.col[k] + 1] - Y.rowptr[X.col[k]];
+  constexpr int64_t kProductsPerThread = 1 << 18;
+  const int64_t grain = std::max<int64_t>(
+      64, std::min<int64_t>(8192, X.n_rows * kProductsPerThread / std::max<int64_t>(products, 1)));
   std::vector<Part> parts;
   std::mutex mu;
   parallel_rows(0, X.n_rows, [&](int64_t r0, int64_t r1) {
@@ -396,7 +403,7 @@ HostCSR spgemm(const HostCSR& X, const HostCSR& Y) {
     }
     std::lock_guard<std::mutex> lk(mu);
     parts.push_back(std::move(pt));
-  });
+  }, grain);
   std::sort(parts.begin(), parts.end(), [](const Part& a, const Part& b) { return a.r0 < b.r0; });
   HostCSR Z;
   Z.n_rows = X.n_rows;

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <mutex>
 #include <map>
+#include <optional>
 #include <type_traits>
 
 namespace sd {
@@ -450,7 +451,10 @@ void Solver::upload(const sd_allocator* alloc, hipStream_t s) {
   const double t0 = wall_time();
   mem.reset(new DeviceMem(alloc, s));
   const bool stencil = opts.o.stencil_slices != 0;
-  A64 = upload_sell<double>(pb->A, *mem, s, false, 0, stencil);
+  {
+    TraceRange trace_a("sd: upload, coupled matrix");
+    A64 = upload_sell<double>(pb->A, *mem, s, false, 0, stencil);
+  }
   b_dev = mem->array<double>((size_t)N);
   if (pb->mass > 0.0) step_b = mem->array<double>((size_t)N);
   SD_HIP(hipMemcpyAsync(b_dev, pb->b.data(), (size_t)N * sizeof(double), hipMemcpyHostToDevice, s));
@@ -609,6 +613,8 @@ void upload_hierarchy(const HostHierarchy& h, DevHierarchy<T>& d, double omega, 
     if (l + 1 < h.levels.size()) {
       const int64_t nnzA = H.A.nnz();
       HostCSR G, F, RA;
+      std::optional<TraceRange> trace_f;
+      trace_f.emplace("sd: fused transfer operators (host)");
       D.fuse_pre = fuse_restriction && nu_pre == 2 && (l > 0 || H.A.n_rows < kFusePreRows) &&
                    nnzA <= kFuseMaxRowWidth * H.A.n_rows;
       // R A serves both G and Q = [R | -R A] (nnz(Q) = nnz(R) + nnz(R A))
@@ -623,6 +629,7 @@ void upload_hierarchy(const HostHierarchy& h, DevHierarchy<T>& d, double omega, 
         F = smoothed_correction(H.A, H.P, H.AP, omega);
         D.fuse_post = l == 0 || (double)F.nnz() <= kFuseMaxFOverA * (double)nnzA;
       }
+      trace_f.reset();
       if (D.fuse_pre) {
         // the fused pre-smoothing reads A diag(w)
         HostCSR AW = H.A;
@@ -697,11 +704,16 @@ class PrecImpl : public PrecBase {
     nu_pre = S.opts.amg.nu_pre;
     nu_post = S.opts.amg.nu_post;
     cc = !S.hh[2].levels.empty();
+    static const char* const kRange[3] = {"sd: upload, velocity hierarchy",
+                                          "sd: upload, Darcy hierarchy",
+                                          "sd: upload, pressure-operator hierarchy"};
     for (int b = 0; b < 3; ++b)
-      if (!S.hh[b].levels.empty())
+      if (!S.hh[b].levels.empty()) {
+        TraceRange trace(kRange[b]);
         upload_hierarchy<T>(S.hh[b], H[b], S.opts.amg.omega, nu_pre, nu_post,
                             S.opts.o.stencil_slices != 0, S.opts.o.fused_restriction != 0, mem,
                             s);
+      }
     if (S.ilu.n > 0) ilu = upload_ilu<T>(S.ilu, mem, s);
     if (cc) {
       tp = mem.array<T>((size_t)(S.off[3] - S.off[2]));
